@@ -1,0 +1,156 @@
+/*
+ * sdc.h -- C ABI of the MI355X (gfx950) diagonal IMEX SDC library for the rotating
+ * shallow-water equations in spherical-harmonic vorticity/divergence/geopotential form.
+ *
+ * Method: Freese, Goetschel, Lunet, Ruprecht, Schreiber, "Parallel performance of shared
+ * memory parallel spectral deferred corrections".  The interface follows the paper's
+ * initial-value problem u' = f_I(u) + f_E(u) (Section 4) and the three routines the paper
+ * asks of a code that adopts diagonal SDC (Section 4.2): evaluate f_E, evaluate f_I, and solve
+ * u - alpha f_I(u) = beta.  sdc_step is Algorithm 2 (diagonal IMEX SDC step) with the node
+ * update of Section 4.2 and the MIN-SR-FLEX coefficients; the shallow-water split is the one
+ * of Sections 3.2 and 4.4 (gravity-wave part L_g implicit, Coriolis plus nonlinear terms
+ * explicit).
+ *
+ * ---------------------------------------------------------------------------------------------
+ * Data layout (all buffers passed to the library are DEVICE pointers owned by the caller):
+ *
+ *   spectral field : ncoef complex128 values, interleaved (Re, Im) doubles, ncoef = (T+1)(T+2)/2,
+ *                    m-major triangular: index(m, n) = m(2T+3-m)/2 + (n - m), 0 <= m <= n <= T.
+ *                    Coefficients are of orthonormal spherical harmonics (integral over
+ *                    mu in [-1,1] of Pbar_n^m squared is 1, no Condon-Shortley phase); only
+ *                    m >= 0 is stored and a real field is f = sum_m s_m Re(F_m e^{i m lambda}),
+ *                    s_0 = 1, s_m = 2.  Imaginary parts of m = 0 coefficients are ignored on
+ *                    input by the transforms and are zero on output of every transform.
+ *   state          : [batch][3][ncoef] spectral fields in the order (Phi', zeta, delta):
+ *                    geopotential perturbation [m^2/s^2], vorticity [1/s], divergence [1/s]
+ *                    (the solution vector of Section 3.2).
+ *   grid field     : [batch][nlat][nlon] doubles; latitude index j runs north to south over the
+ *                    Gauss-Legendre latitudes (mu_j = sin(latitude) descending), longitude
+ *                    index i at lambda_i = 2 pi i / nlon.
+ *
+ * Execution: every call is enqueued on the HIP stream given to sdc_init and returns without
+ * waiting for the GPU.  Argument errors are detected on the host before anything is enqueued
+ * and returned synchronously (nothing is modified then).  Device-side conditions (non-finite
+ * values produced by sdc_step) are reported by the next sdc_sync.  No call allocates device
+ * memory except sdc_init; sdc_free releases everything the handle owns.  A handle must be used
+ * from one host thread at a time; different handles are independent.  No C++ exception crosses
+ * this interface.
+ * ---------------------------------------------------------------------------------------------
+ */
+#ifndef SDC_MI355X_H
+#define SDC_MI355X_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SDC_OK = 0,
+    SDC_EINVAL = -1,          /* invalid argument (message in sdc_last_error) */
+    SDC_ENOMEM = -2,          /* device allocation failed */
+    SDC_EHIP = -3,            /* a HIP runtime call failed */
+    SDC_ENONFINITE = -4,      /* sdc_step produced a non-finite value (reported by sdc_sync) */
+    SDC_EUNSUPPORTED = -5     /* valid but unsupported configuration (e.g. nlon not 2^p or 3*2^p) */
+} sdc_status;
+
+/* Arithmetic of the Legendre contractions (the only dense contraction of the step).  Gauss
+ * nodes and weights, Legendre tables, Q, Q_Delta and the implicit-solve coefficients are
+ * always generated and kept in FP64. */
+typedef enum {
+    SDC_FP64 = 0,             /* FP64 MFMA, FP64 tables */
+    SDC_FP32_MFMA = 1,        /* FP32 MFMA on FP32-rounded tables, FP32 accumulation */
+    SDC_BF16X3_MFMA = 2       /* operands split into three BF16 terms each, BF16 MFMA products,
+                                 FP32 accumulation */
+} sdc_precision;
+
+typedef struct {
+    int T;                    /* triangular truncation, 1 <= T <= 1023 */
+    int nlat;                 /* Gaussian latitudes: even, nlat >= T+1 */
+    int nlon;                 /* longitudes: nlon >= 2T+1 and nlon = 2^p or 3*2^p, nlon <= 4096 */
+    double radius;            /* a [m] */
+    double gravity;           /* g [m/s^2] */
+    double omega;             /* Omega [1/s], Coriolis parameter f = 2 Omega mu */
+    double mean_depth;        /* H [m]; mean geopotential Phi_bar = g H */
+    int M;                    /* largest number of collocation nodes used by sdc_step, 1..8 */
+    int K;                    /* largest number of sweeps used by sdc_step, 1..16 */
+    int nodes;                /* collocation nodes: 0 = Radau-right (tau_M = 1), the only choice */
+    int qdelta;               /* diagonal coefficients: 0 = MIN-SR-FLEX, the only choice */
+    int precision;            /* an sdc_precision value */
+    int batch;                /* ensemble members sharing this truncation, >= 1 */
+} sdc_config;
+
+typedef struct sdc_ctx* sdc_handle;
+
+typedef struct {
+    int T, nlat, nlon, ncoef, M, K, batch, precision;
+    long long device_bytes;   /* device memory owned by the handle */
+    long long table_bytes;    /* of which Legendre tables (all precisions kept) */
+} sdc_info;
+
+/* Create a handle: validates cfg, allocates every workspace, and generates on the GPU in FP64
+ * the Gauss-Legendre latitudes and weights, the orthonormal Legendre functions Pbar_n^m and
+ * H_n^m = (1-mu^2) dPbar_n^m/dmu at the northern latitudes (equatorial symmetry gives the
+ * southern ones), the Radau-right nodes and collocation matrices Q for every node count
+ * 1..cfg->M (Sections 4.1 and 4.2), and the FFT twiddles.  Blocks until setup is complete.
+ * hip_stream: a hipStream_t (NULL = the default stream) on which every later call enqueues.
+ * Returns SDC_EINVAL for an invalid cfg or out == NULL, SDC_EUNSUPPORTED for valid but
+ * unsupported grids, SDC_ENOMEM / SDC_EHIP on device failures (nothing is leaked). */
+int sdc_init(const sdc_config* cfg, void* hip_stream, sdc_handle* out);
+
+/* Release the handle (waits for its stream first).  NULL is accepted. */
+int sdc_free(sdc_handle h);
+
+/* One diagonal IMEX SDC step (Algorithm 2) in place: state holds u_n on entry and u_{n+1} on
+ * exit, for all batch members.  M nodes (1 <= M <= cfg.M) and K sweeps (1 <= K <= cfg.K);
+ * sweeps 1..K-1 update all M nodes from the previous sweep's values, sweep K only the last
+ * node; MIN-SR-FLEX coefficient of sweep s is tau_m / min(s, M).  dt > 0 and finite. */
+int sdc_step(sdc_handle h, double* state, double dt, int M, int K);
+
+/* Adjoint of one step: lam_n = (d u_{n+1} / d u_n)^T lam_np1 for the step taken from state_n
+ * with the same dt, M, K (the step is recomputed internally from state_n).  The inner product
+ * is the real Euclidean one over (Re, Im) of every stored coefficient; imaginary parts of m = 0
+ * entries of lam_n are set to zero.  lam_n may alias lam_np1 but not state_n. */
+int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1, double* lam_n,
+                     double dt, int M, int K);
+
+/* Scalar spherical-harmonic analysis of `batch` grid fields: grid [batch][nlat][nlon] ->
+ * spec [batch][ncoef] (Gauss quadrature of the longitude Fourier coefficients truncated to
+ * m <= T).  Exact inverse of sht_inverse on band-limited fields. */
+int sht_forward(sdc_handle h, const double* grid, double* spec);
+
+/* Scalar spherical-harmonic synthesis: spec [batch][ncoef] -> grid [batch][nlat][nlon]. */
+int sht_inverse(sdc_handle h, const double* spec, double* grid);
+
+/* The solver of Section 4.2: u with u - alpha f_I(u) = beta, for states [batch][3][ncoef];
+ * closed form per coefficient.  u may alias beta.  alpha >= 0 and finite. */
+int imex_solve(sdc_handle h, double alpha, const double* beta, double* u);
+
+/* f_E(u) = L_c + N_a + N_r (Coriolis and nonlinear terms, Sections 3.2 and 4.4) for states
+ * [batch][3][ncoef] by a transform round trip; fE must not alias u. */
+int eval_explicit(sdc_handle h, const double* u, double* fE);
+
+/* f_I(u) = L_g(u) (gravity-wave part, Section 3.2) for states [batch][3][ncoef]; fI may alias u. */
+int eval_implicit(sdc_handle h, const double* u, double* fI);
+
+/* Wait for all work enqueued by this handle; returns SDC_ENONFINITE if any sdc_step since the
+ * previous sdc_sync produced a non-finite value (and clears that condition), SDC_EHIP if the
+ * stream reported an error. */
+int sdc_sync(sdc_handle h);
+
+/* Sizes and device memory of a handle. */
+int sdc_get_info(sdc_handle h, sdc_info* info);
+
+/* Copies of setup results to HOST buffers (blocking; for checking the FP64 setup):
+ * mu[nlat], w[nlat] Gauss nodes and weights; tau[M], Q[M*M] (row-major) for 1 <= M <= cfg.M;
+ * Pbar[(T-m+1)*(nlat/2)] and H[...] rows n = m..T over the northern latitudes j < nlat/2. */
+int sdc_copy_grid(sdc_handle h, double* mu, double* w);
+int sdc_copy_coefficients(sdc_handle h, int M, double* tau, double* Q);
+int sdc_copy_legendre(sdc_handle h, int m, double* Pbar, double* H);
+
+/* Message of the last error on the calling host thread ("" if none). */
+const char* sdc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDC_MI355X_H */

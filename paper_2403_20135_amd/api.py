@@ -1,0 +1,154 @@
+"""Python binding of the dSDC library: torch device tensors in, the C ABI underneath.
+
+Every numerical step runs in the HIP library; this module only checks tensor shapes and passes
+device pointers and the HIP stream.  There is no CPU path: without the built library or a GPU
+the constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import SDCError, check  # noqa: F401  (re-exported)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class SDC:
+    """One truncation (and `batch` ensemble members) on the current CUDA/HIP stream of torch."""
+
+    def __init__(self, T: int, nlat: int, nlon: int, M: int, K: int, batch: int = 1,
+                 precision: str = "fp64", radius: float = 6.371e6, gravity: float = 9.81,
+                 omega: float = 7.292e-5, mean_depth: float = 1.0e4, stream: Optional[int] = None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the dSDC library needs a GPU (no CPU fallback)")
+        lib = _lib.load()
+        self._torch = torch
+        self.cfg = _lib.SdcConfig(T=T, nlat=nlat, nlon=nlon, radius=radius, gravity=gravity,
+                                  omega=omega, mean_depth=mean_depth, M=M, K=K, nodes=0, qdelta=0,
+                                  precision=_lib.PRECISIONS[precision], batch=batch)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        check(lib.sdc_init(ctypes.byref(self.cfg), ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.h = h
+        self.lib = lib
+        self.T, self.nlat, self.nlon, self.M, self.K, self.batch = T, nlat, nlon, M, K, batch
+        self.ncoef = (T + 1) * (T + 2) // 2
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, t, shape, name):
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA/HIP tensor")
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+    @property
+    def state_shape(self):
+        return (self.batch, 3, self.ncoef, 2)
+
+    @property
+    def spec_shape(self):
+        return (self.batch, self.ncoef, 2)
+
+    @property
+    def grid_shape(self):
+        return (self.batch, self.nlat, self.nlon)
+
+    # ------------------------------------------------------------------ C ABI calls
+    def step(self, state, dt: float, M: Optional[int] = None, K: Optional[int] = None):
+        """One dSDC step in place."""
+        self._check(state, self.state_shape, "state")
+        check(self.lib.sdc_step(self.h, _ptr(state), float(dt), M or self.M, K or self.K))
+        return state
+
+    def step_adjoint(self, state_n, lam_np1, lam_n, dt: float, M: Optional[int] = None,
+                     K: Optional[int] = None):
+        self._check(state_n, self.state_shape, "state_n")
+        self._check(lam_np1, self.state_shape, "lam_np1")
+        self._check(lam_n, self.state_shape, "lam_n")
+        check(self.lib.sdc_step_adjoint(self.h, _ptr(state_n), _ptr(lam_np1), _ptr(lam_n), float(dt),
+                                        M or self.M, K or self.K))
+        return lam_n
+
+    def sht_forward(self, grid, spec):
+        self._check(grid, self.grid_shape, "grid")
+        self._check(spec, self.spec_shape, "spec")
+        check(self.lib.sht_forward(self.h, _ptr(grid), _ptr(spec)))
+        return spec
+
+    def sht_inverse(self, spec, grid):
+        self._check(spec, self.spec_shape, "spec")
+        self._check(grid, self.grid_shape, "grid")
+        check(self.lib.sht_inverse(self.h, _ptr(spec), _ptr(grid)))
+        return grid
+
+    def imex_solve(self, alpha: float, beta, u):
+        self._check(beta, self.state_shape, "beta")
+        self._check(u, self.state_shape, "u")
+        check(self.lib.imex_solve(self.h, float(alpha), _ptr(beta), _ptr(u)))
+        return u
+
+    def eval_explicit(self, u, fE):
+        self._check(u, self.state_shape, "u")
+        self._check(fE, self.state_shape, "fE")
+        check(self.lib.eval_explicit(self.h, _ptr(u), _ptr(fE)))
+        return fE
+
+    def eval_implicit(self, u, fI):
+        self._check(u, self.state_shape, "u")
+        self._check(fI, self.state_shape, "fI")
+        check(self.lib.eval_implicit(self.h, _ptr(u), _ptr(fI)))
+        return fI
+
+    def sync(self):
+        check(self.lib.sdc_sync(self.h))
+
+    def info(self) -> dict:
+        inf = _lib.SdcInfo()
+        check(self.lib.sdc_get_info(self.h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    def grid(self):
+        mu = np.zeros(self.nlat)
+        w = np.zeros(self.nlat)
+        check(self.lib.sdc_copy_grid(self.h, mu.ctypes.data_as(_lib.P_DOUBLE), w.ctypes.data_as(_lib.P_DOUBLE)))
+        return mu, w
+
+    def coefficients(self, M: int):
+        tau = np.zeros(M)
+        Q = np.zeros(M * M)
+        check(self.lib.sdc_copy_coefficients(self.h, M, tau.ctypes.data_as(_lib.P_DOUBLE),
+                                             Q.ctypes.data_as(_lib.P_DOUBLE)))
+        return tau, Q.reshape(M, M)
+
+    def legendre(self, m: int):
+        rows = self.T - m + 1
+        P = np.zeros(rows * (self.nlat // 2))
+        H = np.zeros_like(P)
+        check(self.lib.sdc_copy_legendre(self.h, m, P.ctypes.data_as(_lib.P_DOUBLE),
+                                         H.ctypes.data_as(_lib.P_DOUBLE)))
+        return P.reshape(rows, -1), H.reshape(rows, -1)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.sdc_free(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

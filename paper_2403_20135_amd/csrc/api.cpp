@@ -1,0 +1,455 @@
+// C ABI of the dSDC library: argument validation, device memory, setup and the orchestration of
+// Algorithm 2 (diagonal IMEX SDC step) on one HIP stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(SDC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool make_fft_plan(int n, FFTPlan& pl) {
+    pl.n = n;
+    pl.nst = 0;
+    int rest = n;
+    if (rest % 3 == 0) {
+        rest /= 3;
+        pl.radix[pl.nst++] = 3;
+    }
+    int p = 0;
+    while (rest > 1 && rest % 2 == 0) {
+        rest /= 2;
+        ++p;
+    }
+    if (rest != 1) return false;
+    if (p % 2 == 1 && p >= 3) {
+        pl.radix[pl.nst++] = 8;
+        p -= 3;
+    }
+    while (p >= 2) {
+        pl.radix[pl.nst++] = 4;
+        p -= 2;
+    }
+    if (p == 1) pl.radix[pl.nst++] = 2;
+    // every stage must fit the per-thread butterfly budget of the LDS FFT
+    for (int s = 0; s < pl.nst; ++s) {
+        const int per = (pl.radix[s] >= 8) ? 1 : 2;
+        if (n / pl.radix[s] > per * kBlock) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+struct sdc_ctx {
+    sdc_config cfg{};
+    hipStream_t st = nullptr;
+    Geom g{};
+    FFTPlan plan{};
+    double phibar = 0, inv_a2 = 0, two_omega = 0;
+    std::vector<void*> allocs;
+    long long bytes = 0, table_bytes = 0;
+    double *mu = nullptr, *w = nullptr, *P = nullptr, *H = nullptr, *tau = nullptr, *Q = nullptr;
+    double *inv_lap = nullptr, *neg_lap = nullptr;
+    long long* toff = nullptr;
+    int* n_of = nullptr;
+    double2* tw = nullptr;
+    int2* syn_tasks = nullptr;
+    int n_syn = 0;
+    int4* ana_tasks = nullptr;
+    int n_ana = 0;
+    double *ua = nullptr, *ub = nullptr, *E = nullptr, *E0 = nullptr;
+    double2 *four = nullptr, *ana = nullptr;
+    int* flag = nullptr;
+    int smax = 0;
+    std::vector<long long> h_toff;
+
+    template <typename T>
+    int alloc(T*& p, size_t count, bool table = false) {
+        void* q = nullptr;
+        const size_t nb = count * sizeof(T);
+        if (hipMalloc(&q, nb) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SDC_ENOMEM, "device allocation of %zu bytes failed", nb);
+        }
+        allocs.push_back(q);
+        bytes += (long long)nb;
+        if (table) table_bytes += (long long)nb;
+        if (hipMemset(q, 0, nb) != hipSuccess) return fail(SDC_EHIP, "hipMemset failed");
+        p = static_cast<T*>(q);
+        return SDC_OK;
+    }
+    ~sdc_ctx() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+int validate_config(const sdc_config* c) {
+    if (!c) return fail(SDC_EINVAL, "cfg is NULL");
+    if (c->T < 1 || c->T > 1023) return fail(SDC_EINVAL, "T=%d out of range 1..1023", c->T);
+    if (c->nlat < c->T + 1) return fail(SDC_EINVAL, "nlat=%d < T+1", c->nlat);
+    if (c->nlat % 2 != 0) return fail(SDC_EINVAL, "nlat=%d must be even", c->nlat);
+    if (c->nlon < 2 * c->T + 1) return fail(SDC_EINVAL, "nlon=%d < 2T+1", c->nlon);
+    if (!(c->radius > 0) || !std::isfinite(c->radius)) return fail(SDC_EINVAL, "radius must be > 0");
+    if (!(c->gravity > 0) || !std::isfinite(c->gravity)) return fail(SDC_EINVAL, "gravity must be > 0");
+    if (!std::isfinite(c->omega)) return fail(SDC_EINVAL, "omega must be finite");
+    if (!(c->mean_depth > 0) || !std::isfinite(c->mean_depth)) return fail(SDC_EINVAL, "mean_depth must be > 0");
+    if (c->M < 1 || c->M > kMaxNodes) return fail(SDC_EINVAL, "M=%d out of range 1..%d", c->M, kMaxNodes);
+    if (c->K < 1 || c->K > kMaxSweeps) return fail(SDC_EINVAL, "K=%d out of range 1..%d", c->K, kMaxSweeps);
+    if (c->nodes != 0) return fail(SDC_EINVAL, "nodes=%d: only Radau-right (0) is defined", c->nodes);
+    if (c->qdelta != 0) return fail(SDC_EINVAL, "qdelta=%d: only MIN-SR-FLEX (0) is defined", c->qdelta);
+    if (c->precision < SDC_FP64 || c->precision > SDC_BF16X3_MFMA)
+        return fail(SDC_EINVAL, "precision=%d unknown", c->precision);
+    if (c->batch < 1 || c->batch > 4096) return fail(SDC_EINVAL, "batch=%d out of range 1..4096", c->batch);
+    if (c->nlon > 2048) return fail(SDC_EUNSUPPORTED, "nlon=%d > 2048 is not supported", c->nlon);
+    FFTPlan pl;
+    if (!make_fft_plan(c->nlon, pl))
+        return fail(SDC_EUNSUPPORTED, "nlon=%d is not 2^p or 3*2^p", c->nlon);
+    if (c->precision != SDC_FP64)
+        return fail(SDC_EUNSUPPORTED, "precision=%d is not available in this build", c->precision);
+    return SDC_OK;
+}
+
+int setup(sdc_ctx* c) {
+    const sdc_config& cf = c->cfg;
+    Geom& g = c->g;
+    g.T = cf.T;
+    g.nlat = cf.nlat;
+    g.nlon = cf.nlon;
+    g.nh = cf.nlat / 2;
+    g.nhp = (g.nh + 15) / 16 * 16;
+    g.ms = cf.T + 1;
+    g.ncoef = (cf.T + 1) * (cf.T + 2) / 2;
+    g.radius = cf.radius;
+    make_fft_plan(cf.nlon, c->plan);
+    c->phibar = cf.gravity * cf.mean_depth;
+    c->inv_a2 = 1.0 / (cf.radius * cf.radius);
+    c->two_omega = 2.0 * cf.omega;
+    c->smax = cf.batch * cf.M;
+    int rc;
+
+    // packed Legendre layout
+    c->h_toff.assign(2 * (g.T + 1), 0);
+    long long tot = 0;
+    for (int m = 0; m <= g.T; ++m)
+        for (int p = 0; p < 2; ++p) {
+            c->h_toff[2 * m + p] = tot;
+            tot += (long long)((npk_of(g.T, m, p) + 3) & ~3) * g.nhp;
+        }
+    if ((rc = c->alloc(c->mu, g.nlat))) return rc;
+    if ((rc = c->alloc(c->w, g.nlat))) return rc;
+    if ((rc = c->alloc(c->P, tot, true))) return rc;
+    if ((rc = c->alloc(c->H, tot, true))) return rc;
+    if ((rc = c->alloc(c->toff, c->h_toff.size()))) return rc;
+    if ((rc = c->alloc(c->n_of, g.ncoef))) return rc;
+    if ((rc = c->alloc(c->inv_lap, g.T + 1))) return rc;
+    if ((rc = c->alloc(c->neg_lap, g.T + 1))) return rc;
+    if ((rc = c->alloc(c->tau, (kMaxNodes + 1) * kMaxNodes))) return rc;
+    if ((rc = c->alloc(c->Q, (kMaxNodes + 1) * kMaxNodes * kMaxNodes))) return rc;
+    if ((rc = c->alloc(c->tw, cf.nlon))) return rc;
+    if ((rc = c->alloc(c->flag, 4))) return rc;
+
+    // task lists: synthesis (m, latitude group of 4 tiles), largest m-work first;
+    // analysis (m, parity, first row of a 16-row tile)
+    std::vector<int2> syn;
+    const int ntj = g.nhp / 16, njg = (ntj + 3) / 4;
+    for (int m = 0; m <= g.T; ++m)
+        for (int jg = 0; jg < njg; ++jg) syn.push_back(make_int2(m, jg));
+    std::vector<int4> ana;
+    for (int m = 0; m <= g.T; ++m)
+        for (int p = 0; p < 2; ++p)
+            for (int kk = 0; kk < npk_of(g.T, m, p); kk += 16) ana.push_back(make_int4(m, p, kk, 0));
+    c->n_syn = (int)syn.size();
+    c->n_ana = (int)ana.size();
+    if ((rc = c->alloc(c->syn_tasks, syn.size()))) return rc;
+    if ((rc = c->alloc(c->ana_tasks, ana.size()))) return rc;
+
+    // workspaces
+    const size_t st_d = (size_t)3 * g.ncoef * 2;
+    if ((rc = c->alloc(c->ua, st_d * c->smax))) return rc;
+    if ((rc = c->alloc(c->ub, st_d * c->smax))) return rc;
+    if ((rc = c->alloc(c->E, st_d * c->smax))) return rc;
+    if ((rc = c->alloc(c->E0, st_d * cf.batch))) return rc;
+    if ((rc = c->alloc(c->four, (size_t)c->smax * kSynFields * g.nlat * g.ms))) return rc;
+    if ((rc = c->alloc(c->ana, (size_t)c->smax * 2 * kAnaCols * g.nhp * g.ms))) return rc;
+
+    // host-computed index data and twiddles e^{-2 pi i k/nlon} (long double, rounded once)
+    std::vector<double2> tw(cf.nlon);
+    for (int k = 0; k < cf.nlon; ++k) {
+        const long double ang = -2.0L * 3.141592653589793238462643383279502884L * k / cf.nlon;
+        tw[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+    }
+    HIP_TRY(hipMemcpy(c->tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->toff, c->h_toff.data(), c->h_toff.size() * sizeof(long long), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->syn_tasks, syn.data(), syn.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->ana_tasks, ana.data(), ana.size() * sizeof(int4), hipMemcpyHostToDevice));
+
+    // FP64 setup kernels
+    launch_gauss(c->mu, c->w, g.nlat, c->st);
+    launch_legendre_tables(c->mu, c->P, c->H, c->toff, g, c->st);
+    launch_collocation(c->tau, c->Q, cf.M, c->st);
+    launch_degree_tables(c->n_of, c->inv_lap, c->neg_lap, g.T, g.radius, c->st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->st));
+
+    const size_t lds = (size_t)5 * cf.nlon * sizeof(double2);
+    if (lds > 65536) HIP_TRY(grid_set_lds_limit(lds));
+    return SDC_OK;
+}
+
+void run_explicit(sdc_ctx* c, const double* states, int S, double* out) {
+    launch_synthesis_swe(c->P, c->H, c->toff, c->syn_tasks, c->n_syn, states, S, c->inv_lap, c->four,
+                         c->g, c->st);
+    launch_grid_swe(c->four, c->ana, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
+    launch_analysis_swe(c->P, c->H, c->toff, c->ana_tasks, c->n_ana, c->ana, S, c->neg_lap, out, c->g,
+                        c->st);
+}
+
+int check_handle(sdc_handle h) {
+    if (!h) return fail(SDC_EINVAL, "handle is NULL");
+    return SDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sdc_last_error(void) { return g_last_error.c_str(); }
+
+int sdc_init(const sdc_config* cfg, void* hip_stream, sdc_handle* out) {
+    g_last_error.clear();
+    if (!out) return fail(SDC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_config(cfg);
+    if (rc) return rc;
+    sdc_ctx* c = new (std::nothrow) sdc_ctx();
+    if (!c) return fail(SDC_ENOMEM, "host allocation failed");
+    c->cfg = *cfg;
+    c->st = static_cast<hipStream_t>(hip_stream);
+    rc = setup(c);
+    if (rc) {
+        (void)hipStreamSynchronize(c->st);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return SDC_OK;
+}
+
+int sdc_free(sdc_handle h) {
+    if (!h) return SDC_OK;
+    (void)hipStreamSynchronize(h->st);
+    delete h;
+    return SDC_OK;
+}
+
+int sdc_get_info(sdc_handle h, sdc_info* info) {
+    if (int rc = check_handle(h)) return rc;
+    if (!info) return fail(SDC_EINVAL, "info is NULL");
+    info->T = h->g.T;
+    info->nlat = h->g.nlat;
+    info->nlon = h->g.nlon;
+    info->ncoef = h->g.ncoef;
+    info->M = h->cfg.M;
+    info->K = h->cfg.K;
+    info->batch = h->cfg.batch;
+    info->precision = h->cfg.precision;
+    info->device_bytes = h->bytes;
+    info->table_bytes = h->table_bytes;
+    return SDC_OK;
+}
+
+int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
+    if (int rc = check_handle(h)) return rc;
+    if (!state) return fail(SDC_EINVAL, "state is NULL");
+    if (M < 1 || M > h->cfg.M) return fail(SDC_EINVAL, "M=%d out of range 1..%d", M, h->cfg.M);
+    if (K < 1 || K > h->cfg.K) return fail(SDC_EINVAL, "K=%d out of range 1..%d", K, h->cfg.K);
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(SDC_EINVAL, "dt must be positive and finite");
+    sdc_ctx* c = h;
+    const int B = c->cfg.batch;
+    const long long fs = 3LL * c->g.ncoef * 2;
+    // sweep initialisation: E_0 = f_E(u_n); u_m^0 = u_n and E_m^0 = E_0 through node stride 0
+    run_explicit(c, state, B, c->E0);
+    UpdateArgs a{};
+    a.un = state;
+    a.tau = c->tau + M * kMaxNodes;
+    a.Q = c->Q + M * kMaxNodes * kMaxNodes;
+    a.n_of = c->n_of;
+    a.flag = c->flag;
+    a.dt = dt;
+    a.phibar = c->phibar;
+    a.inv_a2 = c->inv_a2;
+    a.M = M;
+    a.batch = B;
+    a.ncoef = c->g.ncoef;
+    a.uprev = state;
+    a.uprev_node = 0;
+    a.uprev_member = fs;
+    a.E = c->E0;
+    a.E_node = 0;
+    a.E_member = fs;
+    double* bufs[2] = {c->ua, c->ub};
+    int cur = 0;
+    for (int s = 1; s < K; ++s) {
+        a.uout = bufs[cur];
+        a.out_node = fs;
+        a.out_member = (long long)M * fs;
+        a.sweep = s;
+        a.last_only = 0;
+        launch_update(a, c->st);
+        run_explicit(c, bufs[cur], B * M, c->E);
+        a.uprev = bufs[cur];
+        a.uprev_node = fs;
+        a.uprev_member = (long long)M * fs;
+        a.E = c->E;
+        a.E_node = fs;
+        a.E_member = (long long)M * fs;
+        cur ^= 1;
+    }
+    // last sweep: node M only, written into the state
+    a.uout = state;
+    a.out_node = 0;
+    a.out_member = fs;
+    a.sweep = K;
+    a.last_only = 1;
+    launch_update(a, c->st);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1, double* lam_n,
+                     double dt, int M, int K) {
+    if (int rc = check_handle(h)) return rc;
+    (void)state_n; (void)lam_np1; (void)lam_n; (void)dt; (void)M; (void)K;
+    return fail(SDC_EUNSUPPORTED, "sdc_step_adjoint is not available in this build");
+}
+
+int sht_inverse(sdc_handle h, const double* spec, double* grid) {
+    if (int rc = check_handle(h)) return rc;
+    if (!spec || !grid) return fail(SDC_EINVAL, "spec/grid is NULL");
+    const int B = h->cfg.batch;
+    launch_synthesis_scalar(h->P, h->toff, h->syn_tasks, h->n_syn, spec, B, h->four, h->g, h->st);
+    launch_fft_inverse_scalar(h->four, grid, h->tw, h->plan, B, h->g, h->st);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int sht_forward(sdc_handle h, const double* grid, double* spec) {
+    if (int rc = check_handle(h)) return rc;
+    if (!spec || !grid) return fail(SDC_EINVAL, "spec/grid is NULL");
+    const int B = h->cfg.batch;
+    launch_fft_forward_scalar(grid, h->ana, h->w, h->tw, h->plan, B, h->g, h->st);
+    launch_analysis_scalar(h->P, h->toff, h->ana_tasks, h->n_ana, h->ana, B, spec, h->g, h->st);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int imex_solve(sdc_handle h, double alpha, const double* beta, double* u) {
+    if (int rc = check_handle(h)) return rc;
+    if (!beta || !u) return fail(SDC_EINVAL, "beta/u is NULL");
+    if (!(alpha >= 0) || !std::isfinite(alpha)) return fail(SDC_EINVAL, "alpha must be >= 0 and finite");
+    launch_solve(alpha, beta, u, h->n_of, h->phibar, h->inv_a2, h->cfg.batch, h->g.ncoef, h->st);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int eval_explicit(sdc_handle h, const double* u, double* fE) {
+    if (int rc = check_handle(h)) return rc;
+    if (!u || !fE) return fail(SDC_EINVAL, "u/fE is NULL");
+    if (u == fE) return fail(SDC_EINVAL, "fE must not alias u");
+    run_explicit(h, u, h->cfg.batch, fE);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int eval_implicit(sdc_handle h, const double* u, double* fI) {
+    if (int rc = check_handle(h)) return rc;
+    if (!u || !fI) return fail(SDC_EINVAL, "u/fI is NULL");
+    launch_implicit(u, fI, h->n_of, h->phibar, h->inv_a2, h->cfg.batch, h->g.ncoef, h->st);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int sdc_sync(sdc_handle h) {
+    if (int rc = check_handle(h)) return rc;
+    HIP_TRY(hipStreamSynchronize(h->st));
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        HIP_TRY(hipMemset(h->flag, 0, sizeof(int)));
+        return fail(SDC_ENONFINITE, "a step produced a non-finite value");
+    }
+    return SDC_OK;
+}
+
+int sdc_copy_grid(sdc_handle h, double* mu, double* w) {
+    if (int rc = check_handle(h)) return rc;
+    if (!mu || !w) return fail(SDC_EINVAL, "mu/w is NULL");
+    HIP_TRY(hipStreamSynchronize(h->st));
+    HIP_TRY(hipMemcpy(mu, h->mu, h->g.nlat * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(w, h->w, h->g.nlat * sizeof(double), hipMemcpyDeviceToHost));
+    return SDC_OK;
+}
+
+int sdc_copy_coefficients(sdc_handle h, int M, double* tau, double* Q) {
+    if (int rc = check_handle(h)) return rc;
+    if (M < 1 || M > h->cfg.M) return fail(SDC_EINVAL, "M=%d out of range 1..%d", M, h->cfg.M);
+    if (!tau || !Q) return fail(SDC_EINVAL, "tau/Q is NULL");
+    HIP_TRY(hipStreamSynchronize(h->st));
+    std::vector<double> t(kMaxNodes), q(kMaxNodes * kMaxNodes);
+    HIP_TRY(hipMemcpy(t.data(), h->tau + M * kMaxNodes, t.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(q.data(), h->Q + M * kMaxNodes * kMaxNodes, q.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int m = 0; m < M; ++m) {
+        tau[m] = t[m];
+        for (int j = 0; j < M; ++j) Q[m * M + j] = q[m * kMaxNodes + j];
+    }
+    return SDC_OK;
+}
+
+int sdc_copy_legendre(sdc_handle h, int m, double* Pbar, double* H) {
+    if (int rc = check_handle(h)) return rc;
+    if (m < 0 || m > h->g.T) return fail(SDC_EINVAL, "m=%d out of range 0..T", m);
+    if (!Pbar || !H) return fail(SDC_EINVAL, "Pbar/H is NULL");
+    HIP_TRY(hipStreamSynchronize(h->st));
+    const Geom& g = h->g;
+    for (int p = 0; p < 2; ++p) {
+        const int np = npk_of(g.T, m, p);
+        std::vector<double> bp((size_t)np * g.nhp), bh((size_t)np * g.nhp);
+        if (np == 0) continue;
+        HIP_TRY(hipMemcpy(bp.data(), h->P + h->h_toff[2 * m + p], bp.size() * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(bh.data(), h->H + h->h_toff[2 * m + p], bh.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int kk = 0; kk < np; ++kk) {
+            const int row = p + 2 * kk;    // n - m
+            for (int j = 0; j < g.nh; ++j) {
+                Pbar[(size_t)row * g.nh + j] = bp[(size_t)kk * g.nhp + j];
+                H[(size_t)row * g.nh + j] = bh[(size_t)kk * g.nhp + j];
+            }
+        }
+    }
+    return SDC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal definitions shared by the HIP sources of the dSDC library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "../../include/sdc.h"
+
+// ---------------------------------------------------------------------------------------------
+// Limits of this implementation
+// ---------------------------------------------------------------------------------------------
+constexpr int kMaxNodes = 8;        // collocation nodes per step
+constexpr int kMaxSweeps = 16;
+constexpr int kMaxFFTStages = 16;
+constexpr int kBlock = 256;         // threads per workgroup for all kernels (4 wave64)
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------------------------
+// FFT plan: nlon = 2^p or 3 * 2^p, factored into radices 3, 8, 4, 2 (in that order).
+// ---------------------------------------------------------------------------------------------
+struct FFTPlan {
+    int n;
+    int nst;
+    int radix[kMaxFFTStages];
+};
+
+// ---------------------------------------------------------------------------------------------
+// Geometry of one truncation as the kernels see it.
+//   nh  = nlat/2 northern latitudes; nhp = nh rounded up to a multiple of 16 (zero padded).
+//   ms  = T+1 Fourier wavenumbers stored per latitude row.
+//   Legendre tables (Pbar and H, same layout): for order m and parity p of n-m, rows
+//   kk = 0..npk4(m,p)-1 (n = m + p + 2 kk, zero rows beyond npk), each row nhp latitudes,
+//   block offset toff[2m+p] elements.
+// ---------------------------------------------------------------------------------------------
+struct Geom {
+    int T, nlat, nlon, nh, nhp, ms, ncoef;
+    double radius;
+};
+
+__host__ __device__ inline int coef_offset(int T, int m) { return m * (2 * T + 3 - m) / 2; }
+__host__ __device__ inline int npk_of(int T, int m, int p) { return (T - m + 2 - p) / 2; }
+
+// Column layout of the analysis input (per state, per parity p; rows jh < nh are written by the
+// grid kernel, padded rows are never read): complex columns
+//   0: zeta Pbar-part, 1: delta Pbar-part, 2: kinetic-energy Pbar-part, 3: Phi' Pbar-part,
+//   4: zeta H-part,    5: delta H-part,    6: Phi' H-part
+constexpr int kAnaCols = 7;
+// Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V
+constexpr int kSynFields = 4;
+
+// ---------------------------------------------------------------------------------------------
+// Launchers (defined in the .hip files; all enqueue on `st`)
+// ---------------------------------------------------------------------------------------------
+// setup.hip
+void launch_gauss(double* mu, double* w, int nlat, hipStream_t st);
+void launch_legendre_tables(const double* mu, double* P, double* H, const long long* toff,
+                            const Geom& g, hipStream_t st);
+void launch_collocation(double* tau, double* Q, int Mmax, hipStream_t st);
+void launch_degree_tables(int* n_of, double* inv_lap, double* neg_lap, int T, double radius,
+                          hipStream_t st);
+
+// legendre.hip
+void launch_synthesis_swe(const double* P, const double* H, const long long* toff,
+                          const int2* tasks, int ntasks, const double* state, int nstates,
+                          const double* inv_lap, double2* four, const Geom& g, hipStream_t st);
+void launch_analysis_swe(const double* P, const double* H, const long long* toff,
+                         const int4* tasks, int ntasks, const double2* ana, int nstates,
+                         const double* neg_lap, double* out, const Geom& g, hipStream_t st);
+void launch_synthesis_scalar(const double* P, const long long* toff, const int2* tasks, int ntasks,
+                             const double* spec, int nfields, double2* four, const Geom& g,
+                             hipStream_t st);
+void launch_analysis_scalar(const double* P, const long long* toff, const int4* tasks, int ntasks,
+                            const double2* ana, int nfields, double* spec, const Geom& g,
+                            hipStream_t st);
+
+// grid.hip
+void launch_grid_swe(const double2* four, double2* ana, const double* mu, const double* w,
+                     const double2* tw, const FFTPlan& plan, int nstates, double two_omega,
+                     const Geom& g, hipStream_t st);
+hipError_t grid_set_lds_limit(size_t bytes);
+void launch_fft_inverse_scalar(const double2* four, double* grid, const double2* tw,
+                               const FFTPlan& plan, int nfields, const Geom& g, hipStream_t st);
+void launch_fft_forward_scalar(const double* grid, double2* ana, const double* w,
+                               const double2* tw, const FFTPlan& plan, int nfields, const Geom& g,
+                               hipStream_t st);
+
+// update.hip
+struct UpdateArgs {
+    const double* un;          // [B][3][ncoef][2]
+    const double* uprev;       // node iterates of the previous sweep
+    long long uprev_node, uprev_member;   // strides in doubles (node stride 0 = all equal u_n)
+    const double* E;           // explicit tendencies of the previous sweep
+    long long E_node, E_member;
+    double* uout;              // [B][M][3][ncoef][2], or the state itself when last_only
+    long long out_node, out_member;
+    const double* tau;         // [M] Radau-right nodes (device, FP64)
+    const double* Q;           // [M][M] collocation matrix (device, FP64)
+    const int* n_of;           // degree of every coefficient
+    int* flag;                 // set to 1 on a non-finite output (last_only only)
+    double dt, phibar, inv_a2;
+    int M, sweep, last_only, batch, ncoef;
+};
+void launch_update(const UpdateArgs& a, hipStream_t st);
+void launch_implicit(const double* u, double* fI, const int* n_of, double phibar, double inv_a2,
+                     int batch, int ncoef, hipStream_t st);
+void launch_solve(double alpha, const double* beta, double* u, const int* n_of, double phibar,
+                  double inv_a2, int batch, int ncoef, hipStream_t st);

@@ -1,0 +1,299 @@
+// Longitude FFTs in LDS and the fused grid-space step of the explicit tendency.
+//
+// Each workgroup owns one pair of mirror latitudes (north j, south nlat-1-j).  A real field on
+// the two rows is carried as one complex signal z = north + i south, so one complex FFT of
+// length nlon serves both rows.  The FFT is a Stockham autosort transform with radices 3, 8, 4
+// and 2 (nlon = 2^p or 3*2^p), all signals of the workgroup advanced together, one LDS buffer
+// per signal (values staged in registers between the read and write halves of a stage).
+#include "common.h"
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by -i (forward) or +i (inverse)
+__device__ __forceinline__ double2 cmul_mi(double2 a, bool inv) {
+    return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+template <int R>
+__device__ __forceinline__ void dft_small(double2 (&v)[R], bool inv) {
+    if constexpr (R == 2) {
+        const double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+        // X1,2 = v0 - (v1+v2)/2 +- s i (sqrt3/2)(v1 - v2), s = -1 forward, +1 inverse
+        const double c = 0.86602540378443864676;
+        const double2 t1 = cadd(v[1], v[2]);
+        const double2 t2 = make_double2(v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y);
+        const double2 d = csub(v[1], v[2]);
+        const double2 t3 = inv ? make_double2(-c * d.y, c * d.x) : make_double2(c * d.y, -c * d.x);
+        v[0] = cadd(v[0], t1);
+        v[1] = cadd(t2, t3);
+        v[2] = csub(t2, t3);
+    } else if constexpr (R == 4) {
+        const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        const double2 a2 = cadd(v[1], v[3]), a3 = cmul_mi(csub(v[1], v[3]), inv);
+        v[0] = cadd(a0, a2);
+        v[2] = csub(a0, a2);
+        v[1] = cadd(a1, a3);
+        v[3] = csub(a1, a3);
+    } else if constexpr (R == 8) {
+        // two radix-4 DFTs on even and odd inputs, combined with the eighth roots of unity
+        double2 e[4] = {v[0], v[2], v[4], v[6]};
+        double2 o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<4>(e, inv);
+        dft_small<4>(o, inv);
+        const double r = 0.70710678118654752440;
+        const double sg = inv ? 1.0 : -1.0;
+        const double2 w1 = make_double2(r, sg * r), w3 = make_double2(-r, sg * r);
+        const double2 o1 = cmul(o[1], w1), o2 = cmul_mi(o[2], inv), o3 = cmul(o[3], w3);
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    }
+}
+
+// One Stockham stage of radix R on F signals of length N stored at buf + f*N.
+// Butterfly j reads x[j + r N/R], applies twiddles w^(r k), k = j mod Ns, w = e^{-+2 pi i/(Ns R)},
+// and writes y[(j/Ns) Ns R + k + r Ns].
+template <int R, int F>
+__device__ __forceinline__ void fft_stage(double2* buf, int N, int Ns, const double2* __restrict__ tw,
+                                          bool inv) {
+    constexpr int MAXB = R >= 8 ? 1 : 2;
+    const int nb = N / R;
+    const int tstep = N / (Ns * R);
+    double2 v[MAXB][F][R];
+#pragma unroll
+    for (int bb = 0; bb < MAXB; ++bb) {
+        const int j = threadIdx.x + bb * kBlock;
+        if (j < nb) {
+            const int k = j % Ns;
+#pragma unroll
+            for (int f = 0; f < F; ++f)
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[bb][f][r] = buf[f * N + j + r * nb];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                double2 t = tw[r * k * tstep];
+                if (inv) t.y = -t.y;
+#pragma unroll
+                for (int f = 0; f < F; ++f) v[bb][f][r] = cmul(v[bb][f][r], t);
+            }
+#pragma unroll
+            for (int f = 0; f < F; ++f) dft_small<R>(v[bb][f], inv);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < MAXB; ++bb) {
+        const int j = threadIdx.x + bb * kBlock;
+        if (j < nb) {
+            const int k = j % Ns;
+            const int d = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int f = 0; f < F; ++f)
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[f * N + d + r * Ns] = v[bb][f][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Unnormalised DFT of F signals in LDS: forward X_k = sum x_n e^{-2 pi i nk/N}, inverse with +.
+template <int F>
+__device__ void fft_lds(double2* buf, const FFTPlan& pl, const double2* __restrict__ tw, bool inv) {
+    int Ns = 1;
+    for (int s = 0; s < pl.nst; ++s) {
+        const int R = pl.radix[s];
+        if (R == 3) fft_stage<3, F>(buf, pl.n, Ns, tw, inv);
+        else if (R == 4) fft_stage<4, F>(buf, pl.n, Ns, tw, inv);
+        else if (R == 8) fft_stage<8, F>(buf, pl.n, Ns, tw, inv);
+        else fft_stage<2, F>(buf, pl.n, Ns, tw, inv);
+        Ns *= R;
+    }
+}
+
+// Hermitian spectrum of the pair (north X, south Y) for the inverse transform of z = x + i y:
+// W_0 = Re X_0 + i Re Y_0, W_m = X_m + i Y_m and W_{N-m} = conj(X_m) + i conj(Y_m) for 1<=m<=T.
+__device__ __forceinline__ double2 pack_pair(const double2* __restrict__ xn, const double2* __restrict__ ys,
+                                             int k, int N, int T) {
+    if (k == 0) return make_double2(xn[0].x, ys[0].x);
+    if (k <= T) {
+        const double2 X = xn[k], Y = ys[k];
+        return make_double2(X.x - Y.y, X.y + Y.x);
+    }
+    if (k >= N - T) {
+        const double2 X = xn[N - k], Y = ys[N - k];
+        return make_double2(X.x + Y.y, -X.y + Y.x);
+    }
+    return make_double2(0.0, 0.0);
+}
+
+// Split the forward transform W of z = a + i b: A_m = (W_m + conj W_{N-m})/2, B_m = (W_m - conj W_{N-m})/(2i)
+__device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, double2& A, double2& B) {
+    const double2 w = buf[m], c = buf[m == 0 ? 0 : N - m];
+    A = make_double2(0.5 * (w.x + c.x), 0.5 * (w.y - c.y));
+    B = make_double2(0.5 * (w.y + c.y), -0.5 * (w.x - c.x));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fused grid step of f_E for one latitude pair of one state:
+//   inverse FFT of zeta, Phi', U, V -> grid products
+//   A = (zeta+f) U, B = (zeta+f) V, C = Phi' U, D = Phi' V, E = (U^2+V^2)/(2(1-mu^2))
+//   -> forward FFT -> weighted analysis columns (north +- south sums per parity):
+//   Pbar columns: -i m A g, i m B g, E w, -i m C g;  H columns: B g, A g, D g
+//   with g = w / (a (1-mu^2)), Fourier coefficients normalised by 1/nlon.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_grid_swe(
+    const double2* __restrict__ four, double2* __restrict__ ana, const double* __restrict__ mu,
+    const double* __restrict__ w, const double2* __restrict__ tw, FFTPlan plan, double two_omega, Geom g) {
+    extern __shared__ double2 buf[];      // 5 signals x N
+    const int jh = blockIdx.x, s = blockIdx.y;
+    const int N = plan.n, T = g.T;
+    const int jN = jh, jS = g.nlat - 1 - jh;
+    const size_t fstride = (size_t)g.nlat * g.ms;
+    const double2* fs = four + (size_t)s * kSynFields * fstride;
+    for (int f = 0; f < kSynFields; ++f) {
+        const double2* xn = fs + f * fstride + (size_t)jN * g.ms;
+        const double2* ys = fs + f * fstride + (size_t)jS * g.ms;
+        for (int k = threadIdx.x; k < N; k += kBlock) buf[f * N + k] = pack_pair(xn, ys, k, N, T);
+    }
+    __syncthreads();
+    fft_lds<kSynFields>(buf, plan, tw, true);
+    const double x = mu[jN];
+    const double fN = two_omega * x, fS = -fN;
+    const double ke = 0.5 / ((1.0 - x) * (1.0 + x));
+    for (int k = threadIdx.x; k < N; k += kBlock) {
+        const double2 zeta = buf[k], phi = buf[N + k], U = buf[2 * N + k], V = buf[3 * N + k];
+        const double qn = zeta.x + fN, qs = zeta.y + fS;
+        buf[k] = make_double2(qn * U.x, qs * U.y);
+        buf[N + k] = make_double2(qn * V.x, qs * V.y);
+        buf[2 * N + k] = make_double2(phi.x * U.x, phi.y * U.y);
+        buf[3 * N + k] = make_double2(phi.x * V.x, phi.y * V.y);
+        buf[4 * N + k] = make_double2((U.x * U.x + V.x * V.x) * ke, (U.y * U.y + V.y * V.y) * ke);
+    }
+    __syncthreads();
+    fft_lds<5>(buf, plan, tw, false);
+    const double invN = 1.0 / N;
+    const double wt = w[jN];
+    const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
+    const double we = wt * invN;
+    const size_t cstride = (size_t)g.nhp * g.ms;
+    double2* out0 = ana + (size_t)(s * 2 + 0) * kAnaCols * cstride + (size_t)jh * g.ms;
+    double2* out1 = ana + (size_t)(s * 2 + 1) * kAnaCols * cstride + (size_t)jh * g.ms;
+    for (int m = threadIdx.x; m <= T; m += kBlock) {
+        double2 AN, AS, BN, BS, CN, CS, DN, DS, EN, ES;
+        unpack_pair(buf, m, N, AN, AS);
+        unpack_pair(buf + N, m, N, BN, BS);
+        unpack_pair(buf + 2 * N, m, N, CN, CS);
+        unpack_pair(buf + 3 * N, m, N, DN, DS);
+        unpack_pair(buf + 4 * N, m, N, EN, ES);
+        const double mm = (double)m;
+        // symmetric (north + south) and antisymmetric (north - south) parts
+        const double2 As = cadd(AN, AS), Aa = csub(AN, AS);
+        const double2 Bs = cadd(BN, BS), Ba = csub(BN, BS);
+        const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
+        const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
+        const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
+        // -i m X g = (m g X.y, -m g X.x); i m X g = (-m g X.y, m g X.x)
+        const double mg = mm * gg;
+        // parity 0 (n-m even): Pbar pairs with symmetric, H with antisymmetric sums
+        out0[0 * cstride + m] = make_double2(mg * As.y, -mg * As.x);
+        out0[1 * cstride + m] = make_double2(-mg * Bs.y, mg * Bs.x);
+        out0[2 * cstride + m] = make_double2(we * Es.x, we * Es.y);
+        out0[3 * cstride + m] = make_double2(mg * Cs.y, -mg * Cs.x);
+        out0[4 * cstride + m] = make_double2(gg * Ba.x, gg * Ba.y);
+        out0[5 * cstride + m] = make_double2(gg * Aa.x, gg * Aa.y);
+        out0[6 * cstride + m] = make_double2(gg * Da.x, gg * Da.y);
+        // parity 1 (n-m odd): Pbar with antisymmetric, H with symmetric sums
+        out1[0 * cstride + m] = make_double2(mg * Aa.y, -mg * Aa.x);
+        out1[1 * cstride + m] = make_double2(-mg * Ba.y, mg * Ba.x);
+        out1[2 * cstride + m] = make_double2(we * Ea.x, we * Ea.y);
+        out1[3 * cstride + m] = make_double2(mg * Ca.y, -mg * Ca.x);
+        out1[4 * cstride + m] = make_double2(gg * Bs.x, gg * Bs.y);
+        out1[5 * cstride + m] = make_double2(gg * As.x, gg * As.y);
+        out1[6 * cstride + m] = make_double2(gg * Ds.x, gg * Ds.y);
+    }
+}
+
+void launch_grid_swe(const double2* four, double2* ana, const double* mu, const double* w,
+                     const double2* tw, const FFTPlan& plan, int nstates, double two_omega,
+                     const Geom& g, hipStream_t st) {
+    dim3 grid(g.nh, nstates);
+    const size_t lds = (size_t)5 * plan.n * sizeof(double2);
+    k_grid_swe<<<grid, kBlock, lds, st>>>(four, ana, mu, w, tw, plan, two_omega, g);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Scalar longitude transforms for sht_inverse / sht_forward (one latitude pair per workgroup).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_fft_inverse_scalar(
+    const double2* __restrict__ four, double* __restrict__ grid, const double2* __restrict__ tw,
+    FFTPlan plan, Geom g) {
+    extern __shared__ double2 buf[];
+    const int jh = blockIdx.x, f = blockIdx.y;
+    const int N = plan.n;
+    const int jN = jh, jS = g.nlat - 1 - jh;
+    const double2* xn = four + ((size_t)f * g.nlat + jN) * g.ms;
+    const double2* ys = four + ((size_t)f * g.nlat + jS) * g.ms;
+    for (int k = threadIdx.x; k < N; k += kBlock) buf[k] = pack_pair(xn, ys, k, N, g.T);
+    __syncthreads();
+    fft_lds<1>(buf, plan, tw, true);
+    double* rn = grid + ((size_t)f * g.nlat + jN) * g.nlon;
+    double* rs = grid + ((size_t)f * g.nlat + jS) * g.nlon;
+    for (int k = threadIdx.x; k < N; k += kBlock) {
+        const double2 z = buf[k];
+        rn[k] = z.x;
+        rs[k] = z.y;
+    }
+}
+
+void launch_fft_inverse_scalar(const double2* four, double* grid, const double2* tw,
+                               const FFTPlan& plan, int nfields, const Geom& g, hipStream_t st) {
+    dim3 gr(g.nh, nfields);
+    k_fft_inverse_scalar<<<gr, kBlock, plan.n * sizeof(double2), st>>>(four, grid, tw, plan, g);
+}
+
+// Output ana[f][p][jh][m] = w_j/nlon * (F_N +- F_S), + for parity 0, - for parity 1.
+__global__ __launch_bounds__(kBlock) void k_fft_forward_scalar(
+    const double* __restrict__ grid, double2* __restrict__ ana, const double* __restrict__ w,
+    const double2* __restrict__ tw, FFTPlan plan, Geom g) {
+    extern __shared__ double2 buf[];
+    const int jh = blockIdx.x, f = blockIdx.y;
+    const int N = plan.n;
+    const int jN = jh, jS = g.nlat - 1 - jh;
+    const double* rn = grid + ((size_t)f * g.nlat + jN) * g.nlon;
+    const double* rs = grid + ((size_t)f * g.nlat + jS) * g.nlon;
+    for (int k = threadIdx.x; k < N; k += kBlock) buf[k] = make_double2(rn[k], rs[k]);
+    __syncthreads();
+    fft_lds<1>(buf, plan, tw, false);
+    const double sc = w[jN] / N;
+    double2* o0 = ana + ((size_t)(f * 2 + 0) * g.nhp + jh) * g.ms;
+    double2* o1 = ana + ((size_t)(f * 2 + 1) * g.nhp + jh) * g.ms;
+    for (int m = threadIdx.x; m <= g.T; m += kBlock) {
+        double2 XN, XS;
+        unpack_pair(buf, m, N, XN, XS);
+        o0[m] = make_double2(sc * (XN.x + XS.x), sc * (XN.y + XS.y));
+        o1[m] = make_double2(sc * (XN.x - XS.x), sc * (XN.y - XS.y));
+    }
+}
+
+void launch_fft_forward_scalar(const double* grid, double2* ana, const double* w,
+                               const double2* tw, const FFTPlan& plan, int nfields, const Geom& g,
+                               hipStream_t st) {
+    dim3 gr(g.nh, nfields);
+    k_fft_forward_scalar<<<gr, kBlock, plan.n * sizeof(double2), st>>>(grid, ana, w, tw, plan, g);
+}
+
+hipError_t grid_set_lds_limit(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_swe),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}

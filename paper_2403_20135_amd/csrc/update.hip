@@ -1,0 +1,130 @@
+// Coefficient-wise kernels of the step: the Q-matrix node integral fused with the per-degree
+// implicit solve (node update of Section 4.2), f_I = L_g, and the solver of u - alpha f_I(u) = beta.
+// All are HBM-bound streams over the coefficients; one thread per (member, coefficient).
+//
+// Gravity-wave operator per coefficient (c_n = n(n+1)/a^2, Phi_bar = g H):
+//   L_g(Phi', zeta, delta) = (-Phi_bar delta, 0, c_n Phi')
+// Solve of u - alpha L_g(u) = beta:
+//   Phi' = (beta_Phi - alpha Phi_bar beta_delta) / (1 + alpha^2 Phi_bar c_n),
+//   zeta = beta_zeta, delta = beta_delta + alpha c_n Phi'.
+#include "common.h"
+
+struct C3 {
+    double2 phi, zeta, div;
+};
+
+__device__ __forceinline__ double2 ld2(const double* p) { return *(const double2*)p; }
+__device__ __forceinline__ void st2(double* p, double2 v) { *(double2*)p = v; }
+
+// beta_m = u_n + dt sum_j Q[m][j] (L_g(u_j) + E_j) - alpha_m L_g(u_m);  u_m <- solve(alpha_m, beta_m)
+// alpha_m = dt tau_m / min(sweep, M)  (MIN-SR-FLEX).  When last_only, only node M is updated and
+// written (to the state), with a non-finite check.
+__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= a.ncoef) return;
+    const int nc = a.ncoef;
+    const int n = a.n_of[idx];
+    const double cn = n * (n + 1.0) * a.inv_a2;
+    const size_t o = (size_t)idx * 2;
+    const size_t fs = (size_t)nc * 2;             // field stride in doubles
+    const double* un = a.un + (size_t)b * 3 * fs + o;
+    const C3 u0 = {ld2(un), ld2(un + fs), ld2(un + 2 * fs)};
+    const int M = a.M;
+    double2 Fphi[kMaxNodes], Fzeta[kMaxNodes], Fdiv[kMaxNodes];
+    double2 Lphi[kMaxNodes], Ldiv[kMaxNodes];      // L_g(u_j) (zeta component is zero)
+    for (int j = 0; j < M; ++j) {
+        const double* uj = a.uprev + (size_t)b * a.uprev_member + (size_t)j * a.uprev_node + o;
+        const double* ej = a.E + (size_t)b * a.E_member + (size_t)j * a.E_node + o;
+        const double2 pj = ld2(uj), dj = ld2(uj + 2 * fs);
+        Lphi[j] = make_double2(-a.phibar * dj.x, -a.phibar * dj.y);
+        Ldiv[j] = make_double2(cn * pj.x, cn * pj.y);
+        const double2 e0 = ld2(ej), e1 = ld2(ej + fs), e2 = ld2(ej + 2 * fs);
+        Fphi[j] = make_double2(Lphi[j].x + e0.x, Lphi[j].y + e0.y);
+        Fzeta[j] = e1;
+        Fdiv[j] = make_double2(Ldiv[j].x + e2.x, Ldiv[j].y + e2.y);
+    }
+    const int sdiv = a.sweep < M ? a.sweep : M;
+    const int m_begin = a.last_only ? M - 1 : 0;
+    bool bad = false;
+    for (int m = m_begin; m < M; ++m) {
+        const double* Qm = a.Q + m * kMaxNodes;
+        double2 sp = make_double2(0.0, 0.0), sz = sp, sd = sp;
+        for (int j = 0; j < M; ++j) {
+            const double qj = Qm[j];
+            sp.x += qj * Fphi[j].x; sp.y += qj * Fphi[j].y;
+            sz.x += qj * Fzeta[j].x; sz.y += qj * Fzeta[j].y;
+            sd.x += qj * Fdiv[j].x; sd.y += qj * Fdiv[j].y;
+        }
+        const double alpha = a.dt * a.tau[m] / sdiv;
+        const double2 bphi = make_double2(u0.phi.x + a.dt * sp.x - alpha * Lphi[m].x,
+                                          u0.phi.y + a.dt * sp.y - alpha * Lphi[m].y);
+        const double2 bzeta = make_double2(u0.zeta.x + a.dt * sz.x, u0.zeta.y + a.dt * sz.y);
+        const double2 bdiv = make_double2(u0.div.x + a.dt * sd.x - alpha * Ldiv[m].x,
+                                          u0.div.y + a.dt * sd.y - alpha * Ldiv[m].y);
+        const double den = 1.0 / (1.0 + alpha * alpha * a.phibar * cn);
+        const double2 phi = make_double2((bphi.x - alpha * a.phibar * bdiv.x) * den,
+                                         (bphi.y - alpha * a.phibar * bdiv.y) * den);
+        const double2 dv = make_double2(bdiv.x + alpha * cn * phi.x, bdiv.y + alpha * cn * phi.y);
+        double* out = a.uout + (size_t)b * a.out_member + (size_t)(a.last_only ? 0 : m) * a.out_node + o;
+        st2(out, phi);
+        st2(out + fs, bzeta);
+        st2(out + 2 * fs, dv);
+        if (a.last_only) {
+            bad = !(isfinite(phi.x) && isfinite(phi.y) && isfinite(bzeta.x) && isfinite(bzeta.y) &&
+                    isfinite(dv.x) && isfinite(dv.y));
+        }
+    }
+    if (bad) a.flag[0] = 1;
+}
+
+void launch_update(const UpdateArgs& a, hipStream_t st) {
+    dim3 grid((a.ncoef + kBlock - 1) / kBlock, a.batch);
+    k_update<<<grid, kBlock, 0, st>>>(a);
+}
+
+__global__ __launch_bounds__(kBlock) void k_implicit(const double* __restrict__ u, double* __restrict__ fI,
+                                                     const int* __restrict__ n_of, double phibar,
+                                                     double inv_a2, int ncoef) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= ncoef) return;
+    const double cn = n_of[idx] * (n_of[idx] + 1.0) * inv_a2;
+    const size_t fs = (size_t)ncoef * 2;
+    const double* ub = u + (size_t)b * 3 * fs + (size_t)idx * 2;
+    double* ob = fI + (size_t)b * 3 * fs + (size_t)idx * 2;
+    const double2 p = ld2(ub), d = ld2(ub + 2 * fs);
+    st2(ob, make_double2(-phibar * d.x, -phibar * d.y));
+    st2(ob + fs, make_double2(0.0, 0.0));
+    st2(ob + 2 * fs, make_double2(cn * p.x, cn * p.y));
+}
+
+void launch_implicit(const double* u, double* fI, const int* n_of, double phibar, double inv_a2,
+                     int batch, int ncoef, hipStream_t st) {
+    dim3 grid((ncoef + kBlock - 1) / kBlock, batch);
+    k_implicit<<<grid, kBlock, 0, st>>>(u, fI, n_of, phibar, inv_a2, ncoef);
+}
+
+__global__ __launch_bounds__(kBlock) void k_solve(double alpha, const double* beta, double* u,
+                                                  const int* __restrict__ n_of, double phibar,
+                                                  double inv_a2, int ncoef) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= ncoef) return;
+    const double cn = n_of[idx] * (n_of[idx] + 1.0) * inv_a2;
+    const size_t fs = (size_t)ncoef * 2;
+    const double* bb = beta + (size_t)b * 3 * fs + (size_t)idx * 2;
+    double* ub = u + (size_t)b * 3 * fs + (size_t)idx * 2;
+    const double2 bp = ld2(bb), bz = ld2(bb + fs), bd = ld2(bb + 2 * fs);
+    const double den = 1.0 / (1.0 + alpha * alpha * phibar * cn);
+    const double2 p = make_double2((bp.x - alpha * phibar * bd.x) * den, (bp.y - alpha * phibar * bd.y) * den);
+    st2(ub, p);
+    st2(ub + fs, bz);
+    st2(ub + 2 * fs, make_double2(bd.x + alpha * cn * p.x, bd.y + alpha * cn * p.y));
+}
+
+void launch_solve(double alpha, const double* beta, double* u, const int* n_of, double phibar,
+                  double inv_a2, int batch, int ncoef, hipStream_t st) {
+    dim3 grid((ncoef + kBlock - 1) / kBlock, batch);
+    k_solve<<<grid, kBlock, 0, st>>>(alpha, beta, u, n_of, phibar, inv_a2, ncoef);
+}

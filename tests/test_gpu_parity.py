@@ -1,0 +1,297 @@
+"""GPU parity of the HIP path against the FP64 oracle, called through the C ABI.
+
+Tolerances: FP64 path <= 1e-11 relative L2 per field (the target fixed for the plain path);
+setup values and single transforms are held tighter (1e-12 .. 1e-14), see each test.
+Relative L2 of spectral fields uses the sphere norm sqrt(sum_m s_m |c|^2) (s_0 = 1, s_m = 2).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import quadrature, legendre
+from oracle.sdc import Oracle
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [  # (T, nlat, nlon): FFT plans 3x8x4, 3x4x4x4, 4x4x4 (ragged latitude tile), 3x8
+    (31, 48, 96),
+    (63, 96, 192),
+    (21, 34, 64),
+    (10, 12, 24),
+]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    return torch
+
+
+def _sdc(T, nlat, nlon, M=3, K=3, batch=1, precision="fp64"):
+    from paper_2403_20135_amd.api import SDC
+    print(f"\n[gpu] SDC(T={T}, {nlat}x{nlon}, M={M}, K={K}, batch={batch}, {precision})", flush=True)
+    return SDC(T, nlat, nlon, M, K, batch, precision, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
+
+
+def _oracle(T, nlat, nlon):
+    return Oracle(T, nlat, nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
+
+
+def _sm(T):
+    _, m = W.degree_order_arrays(T)
+    return np.where(m == 0, 1.0, 2.0)
+
+
+def rel_l2(x, y, T):
+    """max over leading fields of the sphere-norm relative L2 error; x, y [..., ncoef, 2]."""
+    s = _sm(T)
+    x = np.asarray(x).reshape(-1, x.shape[-2], 2)
+    y = np.asarray(y).reshape(-1, y.shape[-2], 2)
+    worst = 0.0
+    for a, b in zip(x, y):
+        num = np.sum(s[:, None] * (a - b) ** 2)
+        den = np.sum(s[:, None] * b ** 2)
+        worst = max(worst, math.sqrt(num / den) if den > 0 else math.sqrt(num))
+    return worst
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    _torch().cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _states(T, batch, seed, jet=True):
+    out = []
+    for b in range(batch):
+        st = W.random_state(T, seed + b)
+        if jet:
+            st = st + W.balanced_jet(T, 20.0 - 5.0 * b)
+        out.append(st)
+    return np.stack(out)
+
+
+# ----------------------------------------------------------------------------- setup (FP64)
+@pytest.mark.parametrize("T,nlat,nlon", GRIDS + [(255, 384, 768)])
+def test_setup_grid_coefficients_tables(T, nlat, nlon):
+    sdc = _sdc(T, nlat, nlon, M=4, K=4)
+    mu, w = sdc.grid()
+    mu_o, w_o = quadrature.gauss_legendre(nlat)
+    np.testing.assert_allclose(mu, mu_o, rtol=0, atol=2e-16)
+    np.testing.assert_allclose(w, w_o, rtol=2e-12, atol=0)
+    for M in range(1, 5):
+        tau, Q = sdc.coefficients(M)
+        tau_o = quadrature.radau_right_nodes(M)
+        np.testing.assert_allclose(tau, tau_o, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(Q, quadrature.collocation_matrix(tau_o), rtol=0, atol=2e-15)
+    nh = nlat // 2
+    for m in sorted({0, 1, 2, T // 3, T - 1, T}):
+        P, H = sdc.legendre(m)
+        Po = legendre.pbar_m(m, T, mu_o[:nh])
+        Ho = legendre.h_m(m, T, mu_o[:nh])
+        # upward recurrences over n: rounding (FMA on the GPU, separate multiply-add in numpy)
+        # accumulates ~ eps per step, so the bound grows with T
+        tol = 4e-15 * (T + 1)
+        np.testing.assert_allclose(P, Po, rtol=0, atol=tol * max(1.0, np.abs(Po).max()))
+        np.testing.assert_allclose(H, Ho, rtol=0, atol=tol * max(1.0, np.abs(Ho).max()))
+    sdc.close()
+
+
+# ----------------------------------------------------------------------------- transforms
+@pytest.mark.parametrize("T,nlat,nlon", GRIDS)
+def test_scalar_transforms(T, nlat, nlon):
+    batch = 3
+    sdc = _sdc(T, nlat, nlon, M=1, K=1, batch=batch)
+    o = _oracle(T, nlat, nlon)
+    spec = np.stack([W.random_state(T, 40 + b)[0] / 100.0 for b in range(batch)])
+    grid_ref = o.synthesis(spec)
+    g = _dev(np.zeros((batch, nlat, nlon)))
+    sdc.sht_inverse(_dev(spec), g)
+    gh = _host(g)
+    assert np.abs(gh - grid_ref).max() <= 1e-13 * np.abs(grid_ref).max()
+    # analysis of a grid that is not band-limited (aliasing must match too)
+    gr = W.random_grid(nlat, nlon, 3, batch)
+    spec_ref = o.analysis(gr)
+    s = _dev(np.zeros((batch, W.ncoef(T), 2)))
+    sdc.sht_forward(_dev(gr), s)
+    assert rel_l2(_host(s), spec_ref, T) <= 1e-13
+    # round trip on the device
+    s2 = _dev(np.zeros((batch, W.ncoef(T), 2)))
+    sdc.sht_forward(g, s2)
+    assert rel_l2(_host(s2), spec, T) <= 1e-13
+    sdc.close()
+
+
+@pytest.mark.parametrize("T,nlat,nlon", GRIDS[:2])
+def test_implicit_and_solve(T, nlat, nlon):
+    batch = 2
+    sdc = _sdc(T, nlat, nlon, batch=batch)
+    o = _oracle(T, nlat, nlon)
+    u = _states(T, batch, 7)
+    fI = _dev(np.zeros_like(u))
+    sdc.eval_implicit(_dev(u), fI)
+    ref = np.stack([o.f_implicit(x) for x in u])
+    np.testing.assert_allclose(_host(fI), ref, rtol=1e-15, atol=0)
+    for alpha in (0.0, 300.0):
+        x = _dev(u)
+        sdc.imex_solve(alpha, x, x)                 # aliasing allowed
+        ref = np.stack([o.solve(alpha, b) for b in u])
+        assert rel_l2(_host(x), ref, T) <= 1e-14
+    sdc.close()
+
+
+@pytest.mark.parametrize("T,nlat,nlon", GRIDS)
+def test_explicit_tendency(T, nlat, nlon):
+    batch = 2
+    sdc = _sdc(T, nlat, nlon, batch=batch)
+    o = _oracle(T, nlat, nlon)
+    u = _states(T, batch, 11)
+    fE = _dev(np.zeros_like(u))
+    sdc.eval_explicit(_dev(u), fE)
+    got = _host(fE)
+    ref = np.stack([o.f_explicit(x) for x in u])
+    assert rel_l2(got, ref, T) <= 1e-12, rel_l2(got, ref, T)
+
+
+# ----------------------------------------------------------------------------- full step
+def _run_steps(T, nlat, nlon, M, K, dt, steps, batch, seed=21, jet=True, cfgMK=None):
+    cm, ck = cfgMK or (M, K)
+    sdc = _sdc(T, nlat, nlon, M=cm, K=ck, batch=batch)
+    o = _oracle(T, nlat, nlon)
+    u0 = _states(T, batch, seed, jet)
+    x = _dev(u0)
+    for _ in range(steps):
+        sdc.step(x, dt, M, K)
+    sdc.sync()
+    got = _host(x)
+    ref = np.stack([o.step(s, dt, M, K, steps=steps) for s in u0])
+    sdc.close()
+    return got, ref
+
+
+@pytest.mark.parametrize("T,nlat,nlon,M,K,dt,steps,batch", [
+    (31, 48, 96, 3, 2, 600.0, 10, 1),       # the T31 workload: 10 steps of M=3, K=2
+    (63, 96, 192, 4, 4, 480.0, 3, 2),
+    (21, 34, 64, 3, 3, 900.0, 4, 3),        # ragged latitude tile
+    (10, 12, 24, 2, 3, 1200.0, 5, 1),       # K > M
+    (31, 48, 96, 1, 1, 300.0, 3, 1),        # IMEX Euler special case
+    (31, 48, 96, 4, 1, 300.0, 2, 2),        # one sweep only
+])
+def test_step_matches_oracle(T, nlat, nlon, M, K, dt, steps, batch):
+    got, ref = _run_steps(T, nlat, nlon, M, K, dt, steps, batch)
+    err = rel_l2(got, ref, T)
+    print(f"[gpu] rel L2 after {steps} steps: {err:.3e}", flush=True)
+    assert err <= 1e-11
+
+
+def test_step_with_fewer_nodes_than_configured():
+    got, ref = _run_steps(31, 48, 96, 2, 2, 600.0, 2, 2, cfgMK=(4, 4))
+    assert rel_l2(got, ref, 31) <= 1e-11
+
+
+def test_step_t127_jet_workload_prefix():
+    """The T127 jet workload (M=3, K=3, dt=240 s), first 10 of its 100 steps."""
+    wl = W.WORKLOADS["t127_m3k3_jet"]
+    mb = wl.members[0]
+    sdc = _sdc(mb.T, mb.nlat, mb.nlon, wl.M, wl.K)
+    o = _oracle(mb.T, mb.nlat, mb.nlon)
+    u0 = W.initial_state(wl)[None]
+    x = _dev(u0)
+    for _ in range(10):
+        sdc.step(x, mb.dt, wl.M, wl.K)
+    sdc.sync()
+    ref = o.step(u0[0], mb.dt, wl.M, wl.K, steps=10)
+    err = rel_l2(_host(x)[0], ref, mb.T)
+    print(f"[gpu] T127 jet 10 steps rel L2 {err:.3e}", flush=True)
+    assert err <= 1e-11
+
+
+def test_step_t255_headline_full_size():
+    """The T255, M=4, K=4 workload at full size, 2 steps, same launch configuration as the bench."""
+    wl = W.WORKLOADS["t255_m4k4"]
+    mb = wl.members[0]
+    sdc = _sdc(mb.T, mb.nlat, mb.nlon, wl.M, wl.K)
+    o = _oracle(mb.T, mb.nlat, mb.nlon)
+    u0 = W.initial_state(wl)[None]
+    x = _dev(u0)
+    for _ in range(2):
+        sdc.step(x, mb.dt, wl.M, wl.K)
+    sdc.sync()
+    ref = o.step(u0[0], mb.dt, wl.M, wl.K, steps=2)
+    err = rel_l2(_host(x)[0], ref, mb.T)
+    print(f"[gpu] T255 M4K4 2 steps rel L2 {err:.3e}", flush=True)
+    assert err <= 1e-11
+
+
+# ----------------------------------------------------------------------------- properties
+def test_steady_jet_and_mass_on_gpu():
+    T, nlat, nlon = 63, 96, 192
+    sdc = _sdc(T, nlat, nlon, M=4, K=4)
+    st = W.balanced_jet(T, 20.0)[None]
+    x = _dev(st)
+    for _ in range(3):
+        sdc.step(x, 900.0)
+    sdc.sync()
+    got = _host(x)
+    for f in (0, 1):
+        assert np.abs(got[0, f] - st[0, f]).max() < 1e-13 * np.abs(st[0, f]).max()
+    st2 = _states(T, 1, 5)
+    st2[0, 0, 0, 0] = 77.0
+    x = _dev(st2)
+    for _ in range(3):
+        sdc.step(x, 600.0)
+    sdc.sync()
+    got = _host(x)
+    assert abs(got[0, 0, 0, 0] - 77.0) <= 1e-15 * W.PHI_BAR
+    assert got[0, 1, 0, 0] == 0.0 and got[0, 2, 0, 0] == 0.0
+
+
+def test_repeatable_bitwise():
+    T, nlat, nlon = 31, 48, 96
+    sdc = _sdc(T, nlat, nlon, M=3, K=3, batch=2)
+    u0 = _states(T, 2, 9)
+    outs = []
+    for _ in range(2):
+        x = _dev(u0)
+        for _ in range(2):
+            sdc.step(x, 600.0)
+        outs.append(_host(x))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_nonfinite_is_reported_at_sync():
+    from paper_2403_20135_amd.api import SDCError
+    T, nlat, nlon = 31, 48, 96
+    sdc = _sdc(T, nlat, nlon)
+    st = _states(T, 1, 3)
+    st[0, 1, 5, 0] = np.nan
+    x = _dev(st)
+    sdc.step(x, 600.0)
+    with pytest.raises(SDCError) as ei:
+        sdc.sync()
+    assert ei.value.code == -4
+    sdc.sync()                                    # the condition is cleared
+    x = _dev(_states(T, 1, 3))
+    sdc.step(x, 600.0)
+    sdc.sync()
+
+
+def test_call_argument_errors_on_gpu_handle():
+    from paper_2403_20135_amd.api import SDCError
+    T, nlat, nlon = 31, 48, 96
+    sdc = _sdc(T, nlat, nlon, M=3, K=2)
+    x = _dev(_states(T, 1, 1))
+    with pytest.raises(SDCError):
+        sdc.step(x, 600.0, M=4, K=2)
+    with pytest.raises(SDCError):
+        sdc.step(x, -1.0)
+    with pytest.raises(ValueError):
+        sdc.step(_dev(np.zeros((2, 3, W.ncoef(T), 2))), 600.0)

@@ -66,7 +66,7 @@ typedef enum {
 typedef struct {
     int T;                    /* triangular truncation, 1 <= T <= 1023 */
     int nlat;                 /* Gaussian latitudes: even, nlat >= T+1 */
-    int nlon;                 /* longitudes: nlon >= 2T+1 and nlon = 2^p or 3*2^p, nlon <= 4096 */
+    int nlon;                 /* longitudes: nlon >= 2T+1 and nlon = 2^p or 3*2^p, nlon <= 2048 */
     double radius;            /* a [m] */
     double gravity;           /* g [m/s^2] */
     double omega;             /* Omega [1/s], Coriolis parameter f = 2 Omega mu */
@@ -136,6 +136,22 @@ int eval_implicit(sdc_handle h, const double* u, double* fI);
  * previous sdc_sync produced a non-finite value (and clears that condition), SDC_EHIP if the
  * stream reported an error. */
 int sdc_sync(sdc_handle h);
+
+/* Kernel classes of one step, for sdc_timing_read. */
+typedef enum {
+    SDC_KERNEL_SYNTHESIS = 0,   /* Legendre synthesis (spectral -> Fourier), MFMA */
+    SDC_KERNEL_GRID = 1,        /* inverse FFT, grid products, forward FFT */
+    SDC_KERNEL_ANALYSIS = 2,    /* Legendre analysis (Fourier -> spectral tendencies), MFMA */
+    SDC_KERNEL_UPDATE = 3,      /* node integral + implicit solve */
+    SDC_KERNEL_CLASSES = 4
+} sdc_kernel_class;
+
+/* Benchmark timing: while enabled, every kernel launch of the step is bracketed by a pair of
+ * HIP events recorded on the handle's stream.  Enabling (on = 1) or disabling clears the
+ * accumulated figures.  sdc_timing_read waits for the stream and returns, for one kernel class,
+ * the summed event-measured duration in milliseconds and the number of launches. */
+int sdc_timing_enable(sdc_handle h, int on);
+int sdc_timing_read(sdc_handle h, int kernel_class, double* total_ms, long long* launches);
 
 /* Sizes and device memory of a handle. */
 int sdc_get_info(sdc_handle h, sdc_info* info);

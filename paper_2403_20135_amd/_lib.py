@@ -11,6 +11,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "sdc.h")
 
 SDC_OK, SDC_EINVAL, SDC_ENOMEM, SDC_EHIP, SDC_ENONFINITE, SDC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+KERNEL_CLASSES = {"synthesis": 0, "grid": 1, "analysis": 2, "update": 3}
 _NAMES = {0: "SDC_OK", -1: "SDC_EINVAL", -2: "SDC_ENOMEM", -3: "SDC_EHIP", -4: "SDC_ENONFINITE",
           -5: "SDC_EUNSUPPORTED"}
 
@@ -52,6 +53,8 @@ _SIGS = {
     "sdc_copy_grid": (c_int, [c_void_p, P_DOUBLE, P_DOUBLE]),
     "sdc_copy_coefficients": (c_int, [c_void_p, c_int, P_DOUBLE, P_DOUBLE]),
     "sdc_copy_legendre": (c_int, [c_void_p, c_int, P_DOUBLE, P_DOUBLE]),
+    "sdc_timing_enable": (c_int, [c_void_p, c_int]),
+    "sdc_timing_read": (c_int, [c_void_p, c_int, P_DOUBLE, ctypes.POINTER(c_ll)]),
     "sdc_last_error": (ctypes.c_char_p, []),
 }
 

@@ -116,6 +116,20 @@ class SDC:
     def sync(self):
         check(self.lib.sdc_sync(self.h))
 
+    def timing(self, on: bool):
+        """Enable/disable per-kernel HIP-event timing on this handle's stream (clears figures)."""
+        check(self.lib.sdc_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self) -> dict:
+        """{class: (total_ms, launches)} accumulated since timing was enabled."""
+        out = {}
+        for name, k in _lib.KERNEL_CLASSES.items():
+            ms = ctypes.c_double()
+            n = ctypes.c_longlong()
+            check(self.lib.sdc_timing_read(self.h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
     def info(self) -> dict:
         inf = _lib.SdcInfo()
         check(self.lib.sdc_get_info(self.h, ctypes.byref(inf)))

@@ -84,6 +84,40 @@ struct sdc_ctx {
     int* flag = nullptr;
     int smax = 0;
     std::vector<long long> h_toff;
+    // benchmark timing: event pairs per kernel class (pool reused between enables)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<size_t, size_t>> ev_marks[SDC_KERNEL_CLASSES];
+
+    hipEvent_t next_event() {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+    // record a start event before a launch of class k; returns the pool index (or -1)
+    long begin(int k) {
+        if (!timing) return -1;
+        hipEvent_t e = next_event();
+        if (!e) return -1;
+        (void)hipEventRecord(e, st);
+        (void)k;
+        return (long)(ev_used - 1);
+    }
+    void end(int k, long start) {
+        if (start < 0) return;
+        hipEvent_t e = next_event();
+        if (!e) return;
+        (void)hipEventRecord(e, st);
+        ev_marks[k].push_back({(size_t)start, ev_used - 1});
+    }
+    void reset_timing() {
+        ev_used = 0;
+        for (auto& v : ev_marks) v.clear();
+    }
 
     template <typename T>
     int alloc(T*& p, size_t count, bool table = false) {
@@ -101,6 +135,7 @@ struct sdc_ctx {
         return SDC_OK;
     }
     ~sdc_ctx() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
     }
 };
@@ -221,11 +256,23 @@ int setup(sdc_ctx* c) {
 }
 
 void run_explicit(sdc_ctx* c, const double* states, int S, double* out) {
+    long t = c->begin(SDC_KERNEL_SYNTHESIS);
     launch_synthesis_swe(c->P, c->H, c->toff, c->syn_tasks, c->n_syn, states, S, c->inv_lap, c->four,
                          c->g, c->st);
+    c->end(SDC_KERNEL_SYNTHESIS, t);
+    t = c->begin(SDC_KERNEL_GRID);
     launch_grid_swe(c->four, c->ana, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
+    c->end(SDC_KERNEL_GRID, t);
+    t = c->begin(SDC_KERNEL_ANALYSIS);
     launch_analysis_swe(c->P, c->H, c->toff, c->ana_tasks, c->n_ana, c->ana, S, c->neg_lap, out, c->g,
                         c->st);
+    c->end(SDC_KERNEL_ANALYSIS, t);
+}
+
+void run_update(sdc_ctx* c, const UpdateArgs& a) {
+    const long t = c->begin(SDC_KERNEL_UPDATE);
+    launch_update(a, c->st);
+    c->end(SDC_KERNEL_UPDATE, t);
 }
 
 int check_handle(sdc_handle h) {
@@ -319,7 +366,7 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
         a.out_member = (long long)M * fs;
         a.sweep = s;
         a.last_only = 0;
-        launch_update(a, c->st);
+        run_update(c, a);
         run_explicit(c, bufs[cur], B * M, c->E);
         a.uprev = bufs[cur];
         a.uprev_node = fs;
@@ -335,7 +382,7 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
     a.out_member = fs;
     a.sweep = K;
     a.last_only = 1;
-    launch_update(a, c->st);
+    run_update(c, a);
     HIP_TRY(hipGetLastError());
     return SDC_OK;
 }
@@ -390,6 +437,31 @@ int eval_implicit(sdc_handle h, const double* u, double* fI) {
     if (!u || !fI) return fail(SDC_EINVAL, "u/fI is NULL");
     launch_implicit(u, fI, h->n_of, h->phibar, h->inv_a2, h->cfg.batch, h->g.ncoef, h->st);
     HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int sdc_timing_enable(sdc_handle h, int on) {
+    if (int rc = check_handle(h)) return rc;
+    HIP_TRY(hipStreamSynchronize(h->st));
+    h->reset_timing();
+    h->timing = on != 0;
+    return SDC_OK;
+}
+
+int sdc_timing_read(sdc_handle h, int kernel_class, double* total_ms, long long* launches) {
+    if (int rc = check_handle(h)) return rc;
+    if (kernel_class < 0 || kernel_class >= SDC_KERNEL_CLASSES)
+        return fail(SDC_EINVAL, "kernel_class=%d out of range", kernel_class);
+    if (!total_ms || !launches) return fail(SDC_EINVAL, "total_ms/launches is NULL");
+    HIP_TRY(hipStreamSynchronize(h->st));
+    double tot = 0.0;
+    for (const auto& pr : h->ev_marks[kernel_class]) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev_pool[pr.first], h->ev_pool[pr.second]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (long long)h->ev_marks[kernel_class].size();
     return SDC_OK;
 }
 

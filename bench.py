@@ -38,7 +38,9 @@ def algorithmic_work(T, nlat, M, K, batch):
     chi with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).
     Grid (bytes): reads 4 Fourier fields and writes 5 (minimal), nlat*(T+1) complex each per state.
     Update (bytes): per coefficient and member, reads u_n (3 complex), per node j the Phi',
-    delta of u_j (2) and E_j (3), writes the updated nodes (3 each).
+    delta of u_j (2) and E_j (3), writes the updated nodes (3 each) and their synthesis-layout
+    copy (4 each: zeta, Phi', psi, chi); the last sweep writes node M only; the first f_E of a
+    step converts u_n to the synthesis layout (reads 3, writes 4).
     """
     ncoef = (T + 1) * (T + 2) // 2
     transform = 2.0 * ncoef * nlat
@@ -46,7 +48,7 @@ def algorithmic_work(T, nlat, M, K, batch):
     syn_flops = 6 * transform * states
     ana_flops = 7 * transform * states
     grid_bytes = 9.0 * nlat * (T + 1) * 16 * states
-    upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 5 * M + 3 * M) + (3 + 5 * M + 3))
+    upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + 7)
     return {"synthesis": ("flops", syn_flops), "analysis": ("flops", ana_flops),
             "grid": ("bytes", grid_bytes), "update": ("bytes", upd_bytes)}
 
@@ -76,6 +78,9 @@ def main():
     ap.add_argument("--workload", default="t255_m4k4")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (a reference kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the step on a single MI355X "
@@ -149,6 +154,13 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["calibration_copy_bytes"] = 2 * src.numel() * 8      # read + write
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, state0)
     if not np.all(np.isfinite(x.cpu().numpy())):

@@ -142,7 +142,7 @@ typedef enum {
     SDC_KERNEL_SYNTHESIS = 0,   /* Legendre synthesis (spectral -> Fourier), MFMA */
     SDC_KERNEL_GRID = 1,        /* inverse FFT, grid products, forward FFT */
     SDC_KERNEL_ANALYSIS = 2,    /* Legendre analysis (Fourier -> spectral tendencies), MFMA */
-    SDC_KERNEL_UPDATE = 3,      /* node integral + implicit solve */
+    SDC_KERNEL_UPDATE = 3,      /* node integral + implicit solve; layout conversion of u_n */
     SDC_KERNEL_CLASSES = 4
 } sdc_kernel_class;
 

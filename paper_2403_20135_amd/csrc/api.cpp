@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -60,6 +61,43 @@ bool make_fft_plan(int n, FFTPlan& pl) {
     return true;
 }
 
+// Order workgroup tasks for round-robin dispatch over the 8 XCDs (workgroup b runs on XCD b % 8):
+// every task of one group lands on the same XCD (its operands stay in that XCD's L2), groups are
+// spread over the XCDs by work (largest first, onto the least-loaded XCD), and each XCD receives
+// its tasks in decreasing work.  Empty slots are filled with `pad`.
+template <class Task>
+std::vector<Task> xcd_order(const std::vector<Task>& tasks, const std::vector<int>& group,
+                            const std::vector<double>& work, Task pad) {
+    constexpr int kXcd = 8;
+    int ngroups = 0;
+    for (int gidx : group) ngroups = gidx + 1 > ngroups ? gidx + 1 : ngroups;
+    std::vector<double> gwork(ngroups, 0.0);
+    for (size_t t = 0; t < tasks.size(); ++t) gwork[group[t]] += work[t];
+    std::vector<int> order(ngroups);
+    for (int gi = 0; gi < ngroups; ++gi) order[gi] = gi;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gwork[a] > gwork[b]; });
+    std::vector<int> xcd_of(ngroups, 0);
+    double load[kXcd] = {0};
+    for (int gi : order) {
+        int best = 0;
+        for (int x = 1; x < kXcd; ++x)
+            if (load[x] < load[best]) best = x;
+        xcd_of[gi] = best;
+        load[best] += gwork[gi];
+    }
+    std::vector<std::vector<size_t>> lists(kXcd);
+    for (size_t t = 0; t < tasks.size(); ++t) lists[xcd_of[group[t]]].push_back(t);
+    size_t longest = 0;
+    for (auto& l : lists) {
+        std::stable_sort(l.begin(), l.end(), [&](size_t a, size_t b) { return work[a] > work[b]; });
+        longest = l.size() > longest ? l.size() : longest;
+    }
+    std::vector<Task> out(longest * kXcd, pad);
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t r = 0; r < lists[x].size(); ++r) out[r * kXcd + x] = tasks[lists[x][r]];
+    return out;
+}
+
 }  // namespace
 
 struct sdc_ctx {
@@ -73,14 +111,22 @@ struct sdc_ctx {
     double *mu = nullptr, *w = nullptr, *P = nullptr, *H = nullptr, *tau = nullptr, *Q = nullptr;
     double *inv_lap = nullptr, *neg_lap = nullptr;
     long long* toff = nullptr;
+    int* rowoff = nullptr;
     int* n_of = nullptr;
+    int* m_of = nullptr;
     double2* tw = nullptr;
-    int2* syn_tasks = nullptr;
+    int2* syn_tasks = nullptr;        // SWE synthesis workgroups (XCD-ordered)
     int n_syn = 0;
-    int4* ana_tasks = nullptr;
-    int n_ana = 0;
+    int4* ana_tasks = nullptr;        // SWE analysis: 4 wave tasks per workgroup (XCD-ordered)
+    int n_ana_wg = 0;
+    int2* ssyn_tasks = nullptr;       // scalar synthesis (m, latitude group)
+    int n_ssyn = 0;
+    int4* sana_tasks = nullptr;       // scalar analysis wave tasks
+    int n_sana = 0;
     double *ua = nullptr, *ub = nullptr, *E = nullptr, *E0 = nullptr;
-    double2 *four = nullptr, *ana = nullptr;
+    double* cml = nullptr;            // synthesis input, coefficient-major
+    double* G = nullptr;              // analysis input (also the scalar analysis input)
+    double2* four = nullptr;
     int* flag = nullptr;
     int smax = 0;
     std::vector<long long> h_toff;
@@ -188,18 +234,26 @@ int setup(sdc_ctx* c) {
 
     // packed Legendre layout
     c->h_toff.assign(2 * (g.T + 1), 0);
+    std::vector<int> h_rowoff(2 * (g.T + 1), 0);
     long long tot = 0;
+    int rows = 0;
     for (int m = 0; m <= g.T; ++m)
         for (int p = 0; p < 2; ++p) {
             c->h_toff[2 * m + p] = tot;
-            tot += (long long)((npk_of(g.T, m, p) + 3) & ~3) * g.nhp;
+            h_rowoff[2 * m + p] = rows;
+            const int np4 = (npk_of(g.T, m, p) + 3) & ~3;
+            tot += (long long)np4 * g.nhp;
+            rows += np4;
         }
+    g.nrows = rows;
     if ((rc = c->alloc(c->mu, g.nlat))) return rc;
     if ((rc = c->alloc(c->w, g.nlat))) return rc;
     if ((rc = c->alloc(c->P, tot, true))) return rc;
     if ((rc = c->alloc(c->H, tot, true))) return rc;
     if ((rc = c->alloc(c->toff, c->h_toff.size()))) return rc;
+    if ((rc = c->alloc(c->rowoff, h_rowoff.size()))) return rc;
     if ((rc = c->alloc(c->n_of, g.ncoef))) return rc;
+    if ((rc = c->alloc(c->m_of, g.ncoef))) return rc;
     if ((rc = c->alloc(c->inv_lap, g.T + 1))) return rc;
     if ((rc = c->alloc(c->neg_lap, g.T + 1))) return rc;
     if ((rc = c->alloc(c->tau, (kMaxNodes + 1) * kMaxNodes))) return rc;
@@ -207,20 +261,56 @@ int setup(sdc_ctx* c) {
     if ((rc = c->alloc(c->tw, cf.nlon))) return rc;
     if ((rc = c->alloc(c->flag, 4))) return rc;
 
-    // task lists: synthesis (m, latitude group of 4 tiles), largest m-work first;
-    // analysis (m, parity, first row of a 16-row tile)
-    std::vector<int2> syn;
+    // task lists.  SWE synthesis: (m, latitude tile) per workgroup; SWE analysis: (m, parity,
+    // 16-row tile) per workgroup.  Both are grouped per block of 8 orders on one XCD (the partial
+    // output lines of neighbouring orders meet in that L2) and issued longest first.
     const int ntj = g.nhp / 16, njg = (ntj + 3) / 4;
-    for (int m = 0; m <= g.T; ++m)
-        for (int jg = 0; jg < njg; ++jg) syn.push_back(make_int2(m, jg));
-    std::vector<int4> ana;
-    for (int m = 0; m <= g.T; ++m)
-        for (int p = 0; p < 2; ++p)
-            for (int kk = 0; kk < npk_of(g.T, m, p); kk += 16) ana.push_back(make_int4(m, p, kk, 0));
-    c->n_syn = (int)syn.size();
-    c->n_ana = (int)ana.size();
-    if ((rc = c->alloc(c->syn_tasks, syn.size()))) return rc;
-    if ((rc = c->alloc(c->ana_tasks, ana.size()))) return rc;
+    {
+        std::vector<int2> t;
+        std::vector<int> grp;
+        std::vector<double> wk;
+        for (int m = 0; m <= g.T; ++m) {
+            const double rows = ((npk_of(g.T, m, 0) + 3) & ~3) + ((npk_of(g.T, m, 1) + 3) & ~3);
+            for (int jt = 0; jt < ntj; ++jt) {
+                t.push_back(make_int2(m, jt));
+                grp.push_back(m / 8);
+                wk.push_back(rows / 4.0 + 8.0);     // chain length per wave + epilogue
+            }
+        }
+        std::vector<int2> ord = xcd_order(t, grp, wk, make_int2(-1, 0));
+        c->n_syn = (int)ord.size();
+        if ((rc = c->alloc(c->syn_tasks, ord.size()))) return rc;
+        HIP_TRY(hipMemcpy(c->syn_tasks, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
+    {
+        std::vector<int4> t;
+        std::vector<int> grp;
+        std::vector<double> wk;
+        for (int m = 0; m <= g.T; ++m)
+            for (int p = 0; p < 2; ++p)
+                for (int kk = 0; kk < npk_of(g.T, m, p); kk += 16) {
+                    t.push_back(make_int4(m, p, kk, 1));
+                    grp.push_back(m / 8);
+                    wk.push_back(1.0);
+                }
+        std::vector<int4> ord = xcd_order(t, grp, wk, make_int4(0, 0, 0, 0));
+        c->n_ana_wg = (int)ord.size();
+        if ((rc = c->alloc(c->ana_tasks, ord.size()))) return rc;
+        HIP_TRY(hipMemcpy(c->ana_tasks, ord.data(), ord.size() * sizeof(int4), hipMemcpyHostToDevice));
+        std::vector<int4> sw;
+        for (auto& w : t) sw.push_back(make_int4(w.x, w.y, w.z, 0));
+        c->n_sana = (int)sw.size();
+        if ((rc = c->alloc(c->sana_tasks, sw.size()))) return rc;
+        HIP_TRY(hipMemcpy(c->sana_tasks, sw.data(), sw.size() * sizeof(int4), hipMemcpyHostToDevice));
+    }
+    {
+        std::vector<int2> ss;
+        for (int m = 0; m <= g.T; ++m)
+            for (int jg = 0; jg < njg; ++jg) ss.push_back(make_int2(m, jg));
+        c->n_ssyn = (int)ss.size();
+        if ((rc = c->alloc(c->ssyn_tasks, ss.size()))) return rc;
+        HIP_TRY(hipMemcpy(c->ssyn_tasks, ss.data(), ss.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
 
     // workspaces
     const size_t st_d = (size_t)3 * g.ncoef * 2;
@@ -228,8 +318,9 @@ int setup(sdc_ctx* c) {
     if ((rc = c->alloc(c->ub, st_d * c->smax))) return rc;
     if ((rc = c->alloc(c->E, st_d * c->smax))) return rc;
     if ((rc = c->alloc(c->E0, st_d * cf.batch))) return rc;
+    if ((rc = c->alloc(c->cml, (size_t)g.nrows * c->smax * kCmlVals))) return rc;
     if ((rc = c->alloc(c->four, (size_t)c->smax * kSynFields * g.nlat * g.ms))) return rc;
-    if ((rc = c->alloc(c->ana, (size_t)c->smax * 2 * kAnaCols * g.nhp * g.ms))) return rc;
+    if ((rc = c->alloc(c->G, (size_t)(g.T + 1) * 2 * g.nhp * c->smax * kAnaVals))) return rc;
 
     // host-computed index data and twiddles e^{-2 pi i k/nlon} (long double, rounded once)
     std::vector<double2> tw(cf.nlon);
@@ -239,34 +330,42 @@ int setup(sdc_ctx* c) {
     }
     HIP_TRY(hipMemcpy(c->tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->toff, c->h_toff.data(), c->h_toff.size() * sizeof(long long), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->syn_tasks, syn.data(), syn.size() * sizeof(int2), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->ana_tasks, ana.data(), ana.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->rowoff, h_rowoff.data(), h_rowoff.size() * sizeof(int), hipMemcpyHostToDevice));
 
     // FP64 setup kernels
     launch_gauss(c->mu, c->w, g.nlat, c->st);
     launch_legendre_tables(c->mu, c->P, c->H, c->toff, g, c->st);
     launch_collocation(c->tau, c->Q, cf.M, c->st);
-    launch_degree_tables(c->n_of, c->inv_lap, c->neg_lap, g.T, g.radius, c->st);
+    launch_degree_tables(c->n_of, c->m_of, c->inv_lap, c->neg_lap, g.T, g.radius, c->st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->st));
 
-    const size_t lds = (size_t)5 * cf.nlon * sizeof(double2);
+    const size_t lds = (size_t)6 * cf.nlon * sizeof(double2);
     if (lds > 65536) HIP_TRY(grid_set_lds_limit(lds));
     return SDC_OK;
 }
 
-void run_explicit(sdc_ctx* c, const double* states, int S, double* out) {
+// f_E of S states whose synthesis input is already in c->cml (written by the update kernel or
+// by launch_prep_cml).
+void run_explicit_cml(sdc_ctx* c, int S, double* out) {
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
-    launch_synthesis_swe(c->P, c->H, c->toff, c->syn_tasks, c->n_syn, states, S, c->inv_lap, c->four,
+    launch_synthesis_swe(c->P, c->H, c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->four,
                          c->g, c->st);
     c->end(SDC_KERNEL_SYNTHESIS, t);
     t = c->begin(SDC_KERNEL_GRID);
-    launch_grid_swe(c->four, c->ana, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
+    launch_grid_swe(c->four, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
     c->end(SDC_KERNEL_GRID, t);
     t = c->begin(SDC_KERNEL_ANALYSIS);
-    launch_analysis_swe(c->P, c->H, c->toff, c->ana_tasks, c->n_ana, c->ana, S, c->neg_lap, out, c->g,
+    launch_analysis_swe(c->P, c->H, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap, out, c->g,
                         c->st);
     c->end(SDC_KERNEL_ANALYSIS, t);
+}
+
+void run_explicit(sdc_ctx* c, const double* states, int S, double* out) {
+    const long t = c->begin(SDC_KERNEL_UPDATE);
+    launch_prep_cml(states, S, c->cml, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->st);
+    c->end(SDC_KERNEL_UPDATE, t);
+    run_explicit_cml(c, S, out);
 }
 
 void run_update(sdc_ctx* c, const UpdateArgs& a) {
@@ -345,6 +444,9 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
     a.tau = c->tau + M * kMaxNodes;
     a.Q = c->Q + M * kMaxNodes * kMaxNodes;
     a.n_of = c->n_of;
+    a.m_of = c->m_of;
+    a.rowoff = c->rowoff;
+    a.inv_lap = c->inv_lap;
     a.flag = c->flag;
     a.dt = dt;
     a.phibar = c->phibar;
@@ -366,8 +468,9 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
         a.out_member = (long long)M * fs;
         a.sweep = s;
         a.last_only = 0;
+        a.cml = c->cml;
         run_update(c, a);
-        run_explicit(c, bufs[cur], B * M, c->E);
+        run_explicit_cml(c, B * M, c->E);
         a.uprev = bufs[cur];
         a.uprev_node = fs;
         a.uprev_member = (long long)M * fs;
@@ -380,6 +483,7 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
     a.uout = state;
     a.out_node = 0;
     a.out_member = fs;
+    a.cml = nullptr;
     a.sweep = K;
     a.last_only = 1;
     run_update(c, a);
@@ -398,7 +502,7 @@ int sht_inverse(sdc_handle h, const double* spec, double* grid) {
     if (int rc = check_handle(h)) return rc;
     if (!spec || !grid) return fail(SDC_EINVAL, "spec/grid is NULL");
     const int B = h->cfg.batch;
-    launch_synthesis_scalar(h->P, h->toff, h->syn_tasks, h->n_syn, spec, B, h->four, h->g, h->st);
+    launch_synthesis_scalar(h->P, h->toff, h->ssyn_tasks, h->n_ssyn, spec, B, h->four, h->g, h->st);
     launch_fft_inverse_scalar(h->four, grid, h->tw, h->plan, B, h->g, h->st);
     HIP_TRY(hipGetLastError());
     return SDC_OK;
@@ -408,8 +512,9 @@ int sht_forward(sdc_handle h, const double* grid, double* spec) {
     if (int rc = check_handle(h)) return rc;
     if (!spec || !grid) return fail(SDC_EINVAL, "spec/grid is NULL");
     const int B = h->cfg.batch;
-    launch_fft_forward_scalar(grid, h->ana, h->w, h->tw, h->plan, B, h->g, h->st);
-    launch_analysis_scalar(h->P, h->toff, h->ana_tasks, h->n_ana, h->ana, B, spec, h->g, h->st);
+    double2* sana = reinterpret_cast<double2*>(h->G);     // [f][p][nhp][m] fits in G
+    launch_fft_forward_scalar(grid, sana, h->w, h->tw, h->plan, B, h->g, h->st);
+    launch_analysis_scalar(h->P, h->toff, h->sana_tasks, h->n_sana, sana, B, spec, h->g, h->st);
     HIP_TRY(hipGetLastError());
     return SDC_OK;
 }

@@ -35,19 +35,25 @@ struct FFTPlan {
 // ---------------------------------------------------------------------------------------------
 struct Geom {
     int T, nlat, nlon, nh, nhp, ms, ncoef;
+    int nrows;          // table rows summed over (m, parity): sum of npk4
     double radius;
 };
 
 __host__ __device__ inline int coef_offset(int T, int m) { return m * (2 * T + 3 - m) / 2; }
 __host__ __device__ inline int npk_of(int T, int m, int p) { return (T - m + 2 - p) / 2; }
 
-// Column layout of the analysis input (per state, per parity p; rows jh < nh are written by the
-// grid kernel, padded rows are never read): complex columns
-//   0: zeta Pbar-part, 1: delta Pbar-part, 2: kinetic-energy Pbar-part, 3: Phi' Pbar-part,
-//   4: zeta H-part,    5: delta H-part,    6: Phi' H-part
-constexpr int kAnaCols = 7;
-// Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V
+// Synthesis input ("coefficient-major", written by the update/prep kernels): for table row
+// (m, p, kk) and state s, 8 doubles (zeta, Phi', psi, chi) x (Re, Im) with psi, chi the inverse
+// Laplacians of zeta and delta:  cml[((rowoff[2m+p] + kk) * S + s) * 8 + v].
+constexpr int kCmlVals = 8;
+// Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V, layout
+// four[s][field][lat][m].
 constexpr int kSynFields = 4;
+// Analysis input written by the grid kernel, per (m, parity p, northern latitude jh, state s):
+// 14 doubles = 7 complex columns, Pbar parts (zeta, delta, kinetic energy, Phi') then H parts
+// (zeta, delta, Phi'), already combined into the north +- south sums of parity p and weighted:
+//   G[(((m*2 + p) * nhp + jh) * S + s) * 14 + c]   (rows jh >= nh are never read).
+constexpr int kAnaVals = 14;
 
 // ---------------------------------------------------------------------------------------------
 // Launchers (defined in the .hip files; all enqueue on `st`)
@@ -57,15 +63,17 @@ void launch_gauss(double* mu, double* w, int nlat, hipStream_t st);
 void launch_legendre_tables(const double* mu, double* P, double* H, const long long* toff,
                             const Geom& g, hipStream_t st);
 void launch_collocation(double* tau, double* Q, int Mmax, hipStream_t st);
-void launch_degree_tables(int* n_of, double* inv_lap, double* neg_lap, int T, double radius,
-                          hipStream_t st);
+void launch_degree_tables(int* n_of, int* m_of, double* inv_lap, double* neg_lap, int T,
+                          double radius, hipStream_t st);
 
 // legendre.hip
+// Synthesis tasks: (m, latitude tile) per workgroup, XCD-ordered; x < 0 = pad.
 void launch_synthesis_swe(const double* P, const double* H, const long long* toff,
-                          const int2* tasks, int ntasks, const double* state, int nstates,
-                          const double* inv_lap, double2* four, const Geom& g, hipStream_t st);
+                          const int* rowoff, const int2* tasks, int ntasks, const double* cml,
+                          int nstates, double2* four, const Geom& g, hipStream_t st);
+// Analysis tasks: (m, p, first row, valid) per workgroup, XCD-ordered.
 void launch_analysis_swe(const double* P, const double* H, const long long* toff,
-                         const int4* tasks, int ntasks, const double2* ana, int nstates,
+                         const int4* tasks, int nwg, const double* G, int nstates,
                          const double* neg_lap, double* out, const Geom& g, hipStream_t st);
 void launch_synthesis_scalar(const double* P, const long long* toff, const int2* tasks, int ntasks,
                              const double* spec, int nfields, double2* four, const Geom& g,
@@ -75,7 +83,7 @@ void launch_analysis_scalar(const double* P, const long long* toff, const int4* 
                             hipStream_t st);
 
 // grid.hip
-void launch_grid_swe(const double2* four, double2* ana, const double* mu, const double* w,
+void launch_grid_swe(const double2* four, double* G, const double* mu, const double* w,
                      const double2* tw, const FFTPlan& plan, int nstates, double two_omega,
                      const Geom& g, hipStream_t st);
 hipError_t grid_set_lds_limit(size_t bytes);
@@ -94,6 +102,10 @@ struct UpdateArgs {
     long long E_node, E_member;
     double* uout;              // [B][M][3][ncoef][2], or the state itself when last_only
     long long out_node, out_member;
+    double* cml;               // if not null: the updated nodes also in synthesis layout (S = B*M)
+    const int* m_of;           // order m of every coefficient
+    const int* rowoff;         // table row offset of (m, parity)
+    const double* inv_lap;     // -a^2/(n(n+1)), 0 at n = 0
     const double* tau;         // [M] Radau-right nodes (device, FP64)
     const double* Q;           // [M][M] collocation matrix (device, FP64)
     const int* n_of;           // degree of every coefficient
@@ -102,6 +114,10 @@ struct UpdateArgs {
     int M, sweep, last_only, batch, ncoef;
 };
 void launch_update(const UpdateArgs& a, hipStream_t st);
+// Synthesis layout of `batch` states [b][3][ncoef] (the first f_E of a step, eval_explicit).
+void launch_prep_cml(const double* state, int nstates, double* cml, const int* n_of,
+                     const int* m_of, const int* rowoff, const double* inv_lap, int ncoef,
+                     hipStream_t st);
 void launch_implicit(const double* u, double* fI, const int* n_of, double phibar, double inv_a2,
                      int batch, int ncoef, hipStream_t st);
 void launch_solve(double alpha, const double* beta, double* u, const int* n_of, double phibar,

@@ -65,7 +65,7 @@ __device__ __forceinline__ void dft_small(double2 (&v)[R], bool inv) {
 // Butterfly j reads x[j + r N/R], applies twiddles w^(r k), k = j mod Ns, w = e^{-+2 pi i/(Ns R)},
 // and writes y[(j/Ns) Ns R + k + r Ns].
 template <int R, int F>
-__device__ __forceinline__ void fft_stage(double2* buf, int N, int Ns, const double2* __restrict__ tw,
+__device__ __forceinline__ void fft_stage(double2* buf, int N, int Ns, const double2* tw,
                                           bool inv) {
     constexpr int MAXB = R >= 8 ? 1 : 2;
     const int nb = N / R;
@@ -109,7 +109,7 @@ __device__ __forceinline__ void fft_stage(double2* buf, int N, int Ns, const dou
 
 // Unnormalised DFT of F signals in LDS: forward X_k = sum x_n e^{-2 pi i nk/N}, inverse with +.
 template <int F>
-__device__ void fft_lds(double2* buf, const FFTPlan& pl, const double2* __restrict__ tw, bool inv) {
+__device__ void fft_lds(double2* buf, const FFTPlan& pl, const double2* tw, bool inv) {
     int Ns = 1;
     for (int s = 0; s < pl.nst; ++s) {
         const int R = pl.radix[s];
@@ -151,23 +151,34 @@ __device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, do
 //   -> forward FFT -> weighted analysis columns (north +- south sums per parity):
 //   Pbar columns: -i m A g, i m B g, E w, -i m C g;  H columns: B g, A g, D g
 //   with g = w / (a (1-mu^2)), Fourier coefficients normalised by 1/nlon.
+// Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of (latitude, state) tasks,
+// states fastest, so the partial rows of the analysis input meet in one L2.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_grid_swe(
-    const double2* __restrict__ four, double2* __restrict__ ana, const double* __restrict__ mu,
-    const double* __restrict__ w, const double2* __restrict__ tw, FFTPlan plan, double two_omega, Geom g) {
-    extern __shared__ double2 buf[];      // 5 signals x N
-    const int jh = blockIdx.x, s = blockIdx.y;
+    const double2* __restrict__ four, double* __restrict__ G, const double* __restrict__ mu,
+    const double* __restrict__ w, const double2* __restrict__ tw, FFTPlan plan, double two_omega,
+    int nstates, Geom g) {
+    extern __shared__ double2 buf[];      // 5 signals x N, then the N twiddles
+    const int ntask = g.nh * nstates;
+    const int per = (ntask + 7) / 8;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= ntask) return;                // uniform per workgroup, before any barrier
+    const int jh = t / nstates, s = t % nstates;
     const int N = plan.n, T = g.T;
     const int jN = jh, jS = g.nlat - 1 - jh;
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four + (size_t)s * kSynFields * fstride;
+    double2* twl = buf + 5 * N;
+    for (int k = threadIdx.x; k < N; k += kBlock) twl[k] = tw[k];
     for (int f = 0; f < kSynFields; ++f) {
         const double2* xn = fs + f * fstride + (size_t)jN * g.ms;
         const double2* ys = fs + f * fstride + (size_t)jS * g.ms;
         for (int k = threadIdx.x; k < N; k += kBlock) buf[f * N + k] = pack_pair(xn, ys, k, N, T);
     }
     __syncthreads();
-    fft_lds<kSynFields>(buf, plan, tw, true);
+    // signals advanced two or three at a time to bound register use
+    fft_lds<2>(buf, plan, twl, true);
+    fft_lds<2>(buf + 2 * N, plan, twl, true);
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;
     const double ke = 0.5 / ((1.0 - x) * (1.0 + x));
@@ -181,14 +192,13 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
         buf[4 * N + k] = make_double2((U.x * U.x + V.x * V.x) * ke, (U.y * U.y + V.y * V.y) * ke);
     }
     __syncthreads();
-    fft_lds<5>(buf, plan, tw, false);
+    fft_lds<3>(buf, plan, twl, false);
+    fft_lds<2>(buf + 3 * N, plan, twl, false);
     const double invN = 1.0 / N;
     const double wt = w[jN];
     const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
     const double we = wt * invN;
-    const size_t cstride = (size_t)g.nhp * g.ms;
-    double2* out0 = ana + (size_t)(s * 2 + 0) * kAnaCols * cstride + (size_t)jh * g.ms;
-    double2* out1 = ana + (size_t)(s * 2 + 1) * kAnaCols * cstride + (size_t)jh * g.ms;
+    const size_t jstride = (size_t)nstates * kAnaVals;
     for (int m = threadIdx.x; m <= T; m += kBlock) {
         double2 AN, AS, BN, BS, CN, CS, DN, DS, EN, ES;
         unpack_pair(buf, m, N, AN, AS);
@@ -196,40 +206,42 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
         unpack_pair(buf + 2 * N, m, N, CN, CS);
         unpack_pair(buf + 3 * N, m, N, DN, DS);
         unpack_pair(buf + 4 * N, m, N, EN, ES);
-        const double mm = (double)m;
+        const double mg = (double)m * gg;
         // symmetric (north + south) and antisymmetric (north - south) parts
         const double2 As = cadd(AN, AS), Aa = csub(AN, AS);
         const double2 Bs = cadd(BN, BS), Ba = csub(BN, BS);
         const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
         const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
         const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
+        double2* o0 = reinterpret_cast<double2*>(G + ((size_t)(m * 2 + 0) * g.nhp + jh) * jstride + (size_t)s * kAnaVals);
+        double2* o1 = reinterpret_cast<double2*>(G + ((size_t)(m * 2 + 1) * g.nhp + jh) * jstride + (size_t)s * kAnaVals);
         // -i m X g = (m g X.y, -m g X.x); i m X g = (-m g X.y, m g X.x)
-        const double mg = mm * gg;
         // parity 0 (n-m even): Pbar pairs with symmetric, H with antisymmetric sums
-        out0[0 * cstride + m] = make_double2(mg * As.y, -mg * As.x);
-        out0[1 * cstride + m] = make_double2(-mg * Bs.y, mg * Bs.x);
-        out0[2 * cstride + m] = make_double2(we * Es.x, we * Es.y);
-        out0[3 * cstride + m] = make_double2(mg * Cs.y, -mg * Cs.x);
-        out0[4 * cstride + m] = make_double2(gg * Ba.x, gg * Ba.y);
-        out0[5 * cstride + m] = make_double2(gg * Aa.x, gg * Aa.y);
-        out0[6 * cstride + m] = make_double2(gg * Da.x, gg * Da.y);
+        o0[0] = make_double2(mg * As.y, -mg * As.x);
+        o0[1] = make_double2(-mg * Bs.y, mg * Bs.x);
+        o0[2] = make_double2(we * Es.x, we * Es.y);
+        o0[3] = make_double2(mg * Cs.y, -mg * Cs.x);
+        o0[4] = make_double2(gg * Ba.x, gg * Ba.y);
+        o0[5] = make_double2(gg * Aa.x, gg * Aa.y);
+        o0[6] = make_double2(gg * Da.x, gg * Da.y);
         // parity 1 (n-m odd): Pbar with antisymmetric, H with symmetric sums
-        out1[0 * cstride + m] = make_double2(mg * Aa.y, -mg * Aa.x);
-        out1[1 * cstride + m] = make_double2(-mg * Ba.y, mg * Ba.x);
-        out1[2 * cstride + m] = make_double2(we * Ea.x, we * Ea.y);
-        out1[3 * cstride + m] = make_double2(mg * Ca.y, -mg * Ca.x);
-        out1[4 * cstride + m] = make_double2(gg * Bs.x, gg * Bs.y);
-        out1[5 * cstride + m] = make_double2(gg * As.x, gg * As.y);
-        out1[6 * cstride + m] = make_double2(gg * Ds.x, gg * Ds.y);
+        o1[0] = make_double2(mg * Aa.y, -mg * Aa.x);
+        o1[1] = make_double2(-mg * Ba.y, mg * Ba.x);
+        o1[2] = make_double2(we * Ea.x, we * Ea.y);
+        o1[3] = make_double2(mg * Ca.y, -mg * Ca.x);
+        o1[4] = make_double2(gg * Bs.x, gg * Bs.y);
+        o1[5] = make_double2(gg * As.x, gg * As.y);
+        o1[6] = make_double2(gg * Ds.x, gg * Ds.y);
     }
 }
 
-void launch_grid_swe(const double2* four, double2* ana, const double* mu, const double* w,
+void launch_grid_swe(const double2* four, double* G, const double* mu, const double* w,
                      const double2* tw, const FFTPlan& plan, int nstates, double two_omega,
                      const Geom& g, hipStream_t st) {
-    dim3 grid(g.nh, nstates);
-    const size_t lds = (size_t)5 * plan.n * sizeof(double2);
-    k_grid_swe<<<grid, kBlock, lds, st>>>(four, ana, mu, w, tw, plan, two_omega, g);
+    const int ntask = g.nh * nstates;
+    const int nblk = (ntask + 7) / 8 * 8;
+    const size_t lds = (size_t)6 * plan.n * sizeof(double2);
+    k_grid_swe<<<nblk, kBlock, lds, st>>>(four, G, mu, w, tw, plan, two_omega, nstates, g);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -244,9 +256,13 @@ __global__ __launch_bounds__(kBlock) void k_fft_inverse_scalar(
     const int jN = jh, jS = g.nlat - 1 - jh;
     const double2* xn = four + ((size_t)f * g.nlat + jN) * g.ms;
     const double2* ys = four + ((size_t)f * g.nlat + jS) * g.ms;
-    for (int k = threadIdx.x; k < N; k += kBlock) buf[k] = pack_pair(xn, ys, k, N, g.T);
+    double2* twl = buf + N;
+    for (int k = threadIdx.x; k < N; k += kBlock) {
+        buf[k] = pack_pair(xn, ys, k, N, g.T);
+        twl[k] = tw[k];
+    }
     __syncthreads();
-    fft_lds<1>(buf, plan, tw, true);
+    fft_lds<1>(buf, plan, twl, true);
     double* rn = grid + ((size_t)f * g.nlat + jN) * g.nlon;
     double* rs = grid + ((size_t)f * g.nlat + jS) * g.nlon;
     for (int k = threadIdx.x; k < N; k += kBlock) {
@@ -259,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_inverse_scalar(
 void launch_fft_inverse_scalar(const double2* four, double* grid, const double2* tw,
                                const FFTPlan& plan, int nfields, const Geom& g, hipStream_t st) {
     dim3 gr(g.nh, nfields);
-    k_fft_inverse_scalar<<<gr, kBlock, plan.n * sizeof(double2), st>>>(four, grid, tw, plan, g);
+    k_fft_inverse_scalar<<<gr, kBlock, 2 * plan.n * sizeof(double2), st>>>(four, grid, tw, plan, g);
 }
 
 // Output ana[f][p][jh][m] = w_j/nlon * (F_N +- F_S), + for parity 0, - for parity 1.
@@ -272,9 +288,13 @@ __global__ __launch_bounds__(kBlock) void k_fft_forward_scalar(
     const int jN = jh, jS = g.nlat - 1 - jh;
     const double* rn = grid + ((size_t)f * g.nlat + jN) * g.nlon;
     const double* rs = grid + ((size_t)f * g.nlat + jS) * g.nlon;
-    for (int k = threadIdx.x; k < N; k += kBlock) buf[k] = make_double2(rn[k], rs[k]);
+    double2* twl = buf + N;
+    for (int k = threadIdx.x; k < N; k += kBlock) {
+        buf[k] = make_double2(rn[k], rs[k]);
+        twl[k] = tw[k];
+    }
     __syncthreads();
-    fft_lds<1>(buf, plan, tw, false);
+    fft_lds<1>(buf, plan, twl, false);
     const double sc = w[jN] / N;
     double2* o0 = ana + ((size_t)(f * 2 + 0) * g.nhp + jh) * g.ms;
     double2* o1 = ana + ((size_t)(f * 2 + 1) * g.nhp + jh) * g.ms;
@@ -290,7 +310,7 @@ void launch_fft_forward_scalar(const double* grid, double2* ana, const double* w
                                const double2* tw, const FFTPlan& plan, int nfields, const Geom& g,
                                hipStream_t st) {
     dim3 gr(g.nh, nfields);
-    k_fft_forward_scalar<<<gr, kBlock, plan.n * sizeof(double2), st>>>(grid, ana, w, tw, plan, g);
+    k_fft_forward_scalar<<<gr, kBlock, 2 * plan.n * sizeof(double2), st>>>(grid, ana, w, tw, plan, g);
 }
 
 hipError_t grid_set_lds_limit(size_t bytes) {

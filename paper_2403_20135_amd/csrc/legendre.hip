@@ -17,136 +17,145 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
 
 // ---------------------------------------------------------------------------------------------
 // Synthesis for the shallow-water explicit tendency.  Per state the inputs are the spectral
-// fields (Phi', zeta, delta); the outputs are the Fourier coefficients, at every latitude, of
-//   zeta, Phi', U = (1/a) sum_n [i m chi Pbar - psi H], V = (1/a) sum_n [i m psi Pbar + chi H]
-// with psi = -a^2 zeta/(n(n+1)) and chi = -a^2 delta/(n(n+1)) (zero at n = 0).
-// Columns of one 16-wide Pbar tile: 2 states x (zeta, Phi', psi, chi) x (Re, Im);
-// of the H tile: 4 states x (psi, chi) x (Re, Im).  A wave owns (m, one 16-latitude tile,
-// 4 states) and runs over all degrees n of both parities.
-// Task (m, latitude group of 4 tiles) per workgroup; blockIdx.y selects 4 states.
+// fields in the coefficient-major layout (zeta, Phi', psi, chi), psi = -a^2 zeta/(n(n+1)),
+// chi = -a^2 delta/(n(n+1)); the outputs are the Fourier coefficients, at every latitude, of
+//   zeta, Phi', U = (1/a) sum_n [i m chi Pbar - psi H], V = (1/a) sum_n [i m psi Pbar + chi H].
+// Columns of one 16-wide Pbar tile: 2 states x (zeta, Phi', psi, chi) x (Re, Im); of the H tile:
+// 4 states x (psi, chi) x (Re, Im).  A workgroup owns (m, one 16-latitude tile, 4 states); its 4
+// waves take every fourth 4-row step of the degree loop (both parities), so the longest chain
+// (m = 0) is a quarter of the degrees, and the partial tiles are summed in LDS in a fixed order.
 // ---------------------------------------------------------------------------------------------
+constexpr int kSynAcc = 24;      // doubles per lane: Pbar 2 parities x 2 tiles x 4, H 2 parities x 4
+
 __global__ __launch_bounds__(kBlock) void k_synthesis_swe(
     const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
-    const int2* __restrict__ tasks, const double* __restrict__ state, int nstates,
-    const double* __restrict__ inv_lap, double2* __restrict__ four, Geom g) {
-    __shared__ double red[4][4][2][12][16];   // [wave][state][north/south][value][latitude]
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int* __restrict__ rowoff, const int2* __restrict__ tasks, const double* __restrict__ cml,
+    int nstates, double2* __restrict__ four, Geom g) {
+    // partial accumulators [wave][value][lane]; then (aliased) the parity-combined tile
+    // red[state][north/south][value][latitude]
+    __shared__ double lds[4 * kSynAcc * 64];
     const int2 task = tasks[blockIdx.x];
-    const int m = task.x;
-    const int jt = task.y * 4 + wave;
-    const int ntj = g.nhp >> 4;
+    if (task.x < 0) return;                          // padding workgroup (uniform)
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = task.x, jt = task.y;
+    const int S = nstates;
     const int s0 = blockIdx.y * 4;
     const int i = lane & 15, q = lane >> 4;
-    const bool active = jt < ntj;
+    const int vP = i & 7, vH = i & 3;
 
-    const int vP = i & 7, reP = vP & 1, kindP = vP >> 1;     // kind: 0 zeta 1 Phi' 2 psi 3 chi
-    const int vH = i & 3, reH = vH & 1, kindH = vH >> 1;     // kind: 0 psi 1 chi
-    v4d accP[2][2], accH[2];
-    for (int p = 0; p < 2; ++p) {
-        accP[p][0] = accP[p][1] = accH[p] = (v4d){0.0, 0.0, 0.0, 0.0};
-    }
-    if (active) {
-        const int fieldP = (kindP == 1) ? 0 : ((kindP == 3) ? 2 : 1);
-        const bool scaleP = kindP >= 2;
-        const int fieldH = kindH == 0 ? 1 : 2;
-        const int cb = coef_offset(g.T, m) - m;
+    v4d acc[6];                                       // [p*3 + {Pbar tile 0, Pbar tile 1, H}]
+    for (int k = 0; k < 6; ++k) acc[k] = (v4d){0.0, 0.0, 0.0, 0.0};
+    {
+        // column -> state; out-of-range states read a valid address and are zeroed by a select
         const int sP0 = s0 + (i >> 3), sP1 = s0 + 2 + (i >> 3), sH = s0 + (i >> 2);
-        const double* bp0 = state + ((size_t)(sP0 * 3 + fieldP) * g.ncoef + cb) * 2 + reP;
-        const double* bp1 = state + ((size_t)(sP1 * 3 + fieldP) * g.ncoef + cb) * 2 + reP;
-        const double* bph = state + ((size_t)(sH * 3 + fieldH) * g.ncoef + cb) * 2 + reH;
-        const bool ok0 = sP0 < nstates, ok1 = sP1 < nstates, okh = sH < nstates;
+        const bool ok0 = sP0 < S, ok1 = sP1 < S, okh = sH < S;
+        const int c0off = (ok0 ? sP0 : 0) * kCmlVals + vP;
+        const int c1off = (ok1 ? sP1 : 0) * kCmlVals + vP;
+        const int choff = (okh ? sH : 0) * kCmlVals + 4 + vH;
         for (int p = 0; p < 2; ++p) {
             const int np = npk_of(g.T, m, p);
             const int np4 = (np + 3) & ~3;
-            const double* Pp = P + toff[2 * m + p] + jt * 16 + i;
-            const double* Hp = H + toff[2 * m + p] + jt * 16 + i;
-            v4d c0 = accP[p][0], c1 = accP[p][1], ch = accH[p];
-#pragma unroll 4
-            for (int kk0 = 0; kk0 < np4; kk0 += 4) {
-                const int kk = kk0 + q;
-                const int n = m + p + 2 * kk;
+            // this wave takes the 4-row steps 4*wave, 4*wave + 16, ... of parity p
+            const int steps = np4 > 4 * wave ? (np4 - 4 * wave + 15) / 16 : 0;   // uniform
+            const double* Pp = P + toff[2 * m + p] + jt * 16 + i + (size_t)(4 * wave + q) * g.nhp;
+            const double* Hp = H + toff[2 * m + p] + jt * 16 + i + (size_t)(4 * wave + q) * g.nhp;
+            const double* Bp = cml + ((size_t)rowoff[2 * m + p] + 4 * wave + q) * S * kCmlVals;
+            const size_t tstep = (size_t)16 * g.nhp, bstep = (size_t)16 * S * kCmlVals;
+            v4d c0 = acc[p * 3], c1 = acc[p * 3 + 1], ch = acc[p * 3 + 2];
+            int kk = 4 * wave + q;
+#pragma unroll 2
+            for (int it = 0; it < steps; ++it) {
                 const bool vn = kk < np;
-                const double ap = Pp[(size_t)kk * g.nhp];
-                const double ah = Hp[(size_t)kk * g.nhp];
-                const double il = vn ? inv_lap[n] : 0.0;
-                double b0 = (vn && ok0) ? bp0[2 * n] : 0.0;
-                double b1 = (vn && ok1) ? bp1[2 * n] : 0.0;
-                const double bh = (vn && okh) ? bph[2 * n] * il : 0.0;
-                if (scaleP) { b0 *= il; b1 *= il; }
-                c0 = mfma_f64(ap, b0, c0);
-                c1 = mfma_f64(ap, b1, c1);
-                ch = mfma_f64(ah, bh, ch);
+                const double ap = Pp[0], ah = Hp[0];
+                const double b0 = Bp[c0off], b1 = Bp[c1off], bh = Bp[choff];
+                c0 = mfma_f64(ap, (vn && ok0) ? b0 : 0.0, c0);
+                c1 = mfma_f64(ap, (vn && ok1) ? b1 : 0.0, c1);
+                ch = mfma_f64(ah, (vn && okh) ? bh : 0.0, ch);
+                Pp += tstep;
+                Hp += tstep;
+                Bp += bstep;
+                kk += 16;
             }
-            accP[p][0] = c0;
-            accP[p][1] = c1;
-            accH[p] = ch;
+            acc[p * 3] = c0;
+            acc[p * 3 + 1] = c1;
+            acc[p * 3 + 2] = ch;
+        }
+    }
+    for (int k = 0; k < 6; ++k)
+        for (int r = 0; r < 4; ++r) lds[(wave * kSynAcc + k * 4 + r) * 64 + lane] = acc[k][r];
+    __syncthreads();
+    double* red = lds;                                // [sl][ns][12][16], written by wave 0 only
+    if (wave == 0) {
+        double tot[kSynAcc];
+        for (int v = 0; v < kSynAcc; ++v) {
+            double sum = lds[v * 64 + lane];
+            for (int w = 1; w < 4; ++w) sum += lds[(w * kSynAcc + v) * 64 + lane];
+            tot[v] = sum;
         }
         // north = even + odd; south = even - odd (Pbar) and odd - even (H)
         for (int r = 0; r < 4; ++r) {
             const int latl = 4 * r + q;
             for (int t = 0; t < 2; ++t) {
-                const double e = accP[0][t][r], o = accP[1][t][r];
+                const double e = tot[t * 4 + r], o = tot[12 + t * 4 + r];
                 const int sl = 2 * t + (i >> 3);
-                red[wave][sl][0][vP][latl] = e + o;
-                red[wave][sl][1][vP][latl] = e - o;
+                red[((sl * 2 + 0) * 12 + vP) * 16 + latl] = e + o;
+                red[((sl * 2 + 1) * 12 + vP) * 16 + latl] = e - o;
             }
-            const double e = accH[0][r], o = accH[1][r];
-            red[wave][i >> 2][0][8 + vH][latl] = e + o;
-            red[wave][i >> 2][1][8 + vH][latl] = o - e;
+            const double e = tot[8 + r], o = tot[20 + r];
+            red[(((i >> 2) * 2 + 0) * 12 + 8 + vH) * 16 + latl] = e + o;
+            red[(((i >> 2) * 2 + 1) * 12 + 8 + vH) * 16 + latl] = o - e;
         }
     }
     __syncthreads();
-    if (!active) return;
+    const int it = threadIdx.x;                       // (state, north/south, latitude): 128 items
+    if (it >= 128) return;
+    const int sl = it >> 5, ns = (it >> 4) & 1, latl = it & 15;
+    const int s = s0 + sl, jh = jt * 16 + latl;
+    if (s >= S || jh >= g.nh) return;
     const double inva = 1.0 / g.radius;
     const double mm = (double)m;
+    const double* v = red + ((sl * 2 + ns) * 12) * 16 + latl;
+    const double ppr = v[4 * 16], ppi = v[5 * 16];    // Pbar psi
+    const double pcr = v[6 * 16], pci = v[7 * 16];    // Pbar chi
+    const double hpr = v[8 * 16], hpi = v[9 * 16];    // H psi
+    const double hcr = v[10 * 16], hci = v[11 * 16];  // H chi
+    const int j = ns ? g.nlat - 1 - jh : jh;
     const size_t fstride = (size_t)g.nlat * g.ms;
-    for (int it = lane; it < 128; it += 64) {
-        const int sl = it >> 5, ns = (it >> 4) & 1, latl = it & 15;
-        const int s = s0 + sl, jh = jt * 16 + latl;
-        if (s >= nstates || jh >= g.nh) continue;
-        const double* v = &red[wave][sl][ns][0][latl];
-        const double2 zeta = make_double2(v[0 * 16], v[1 * 16]);
-        const double2 phi = make_double2(v[2 * 16], v[3 * 16]);
-        const double ppr = v[4 * 16], ppi = v[5 * 16];       // Pbar psi
-        const double pcr = v[6 * 16], pci = v[7 * 16];       // Pbar chi
-        const double hpr = v[8 * 16], hpi = v[9 * 16];       // H psi
-        const double hcr = v[10 * 16], hci = v[11 * 16];     // H chi
-        const double2 U = make_double2((-mm * pci - hpr) * inva, (mm * pcr - hpi) * inva);
-        const double2 V = make_double2((-mm * ppi + hcr) * inva, (mm * ppr + hci) * inva);
-        const int j = ns ? g.nlat - 1 - jh : jh;
-        double2* base = four + ((size_t)s * kSynFields * g.nlat + j) * g.ms + m;
-        base[0] = zeta;
-        base[fstride] = phi;
-        base[2 * fstride] = U;
-        base[3 * fstride] = V;
-    }
+    double2* base = four + (size_t)s * kSynFields * fstride + (size_t)j * g.ms + m;
+    base[0] = make_double2(v[0 * 16], v[1 * 16]);
+    base[fstride] = make_double2(v[2 * 16], v[3 * 16]);
+    base[2 * fstride] = make_double2((-mm * pci - hpr) * inva, (mm * pcr - hpi) * inva);
+    base[3 * fstride] = make_double2((-mm * ppi + hcr) * inva, (mm * ppr + hci) * inva);
 }
 
 void launch_synthesis_swe(const double* P, const double* H, const long long* toff,
-                          const int2* tasks, int ntasks, const double* state, int nstates,
-                          const double* inv_lap, double2* four, const Geom& g, hipStream_t st) {
+                          const int* rowoff, const int2* tasks, int ntasks, const double* cml,
+                          int nstates, double2* four, const Geom& g, hipStream_t st) {
     dim3 grid(ntasks, (nstates + 3) / 4);
-    k_synthesis_swe<<<grid, kBlock, 0, st>>>(P, H, toff, tasks, state, nstates, inv_lap, four, g);
+    k_synthesis_swe<<<grid, kBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates, four, g);
 }
 
 // ---------------------------------------------------------------------------------------------
-// Analysis for the shallow-water explicit tendency.  Input: per state and parity p the seven
-// weighted Fourier columns produced by the grid kernel (already combined into the north +- south
-// sums that pair with Pbar and H of that parity).  Output per state:
+// Analysis for the shallow-water explicit tendency.  Input: per (m, parity p, latitude, state)
+// the seven weighted Fourier columns of the grid kernel.  Output per state:
 //   d zeta/dt = Pbar.col0 + H.col4, d delta/dt = Pbar.col1 + H.col5 + n(n+1)/a^2 Pbar.col2,
 //   d Phi'/dt = Pbar.col3 + H.col6.
-// A wave owns (m, parity, 16 consecutive rows n, 4 states) and contracts over all latitudes
-// (uniform work per wave).  Tile columns: 2 states x (zeta, delta, KE, Phi') x (Re, Im).
+// A workgroup owns (m, parity, 16 consecutive rows n, 4 states); its 4 waves take every fourth
+// 16-latitude block of the contraction and the partial tiles are summed in LDS in a fixed order.
+// Tile columns: 2 states x (zeta, delta, KE, Phi') x (Re, Im).
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
-    const int4* __restrict__ tasks, int ntasks, const double2* __restrict__ ana, int nstates,
+    const int4* __restrict__ tasks, const double* __restrict__ G, int nstates,
     const double* __restrict__ neg_lap, double* __restrict__ out, Geom g) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tid = blockIdx.x * 4 + wave;
-    if (tid >= ntasks) return;
-    const int4 task = tasks[tid];
+    __shared__ double lds[3 * 8 * 64];
+    const int4 task = tasks[blockIdx.x];
+    if (task.w == 0) return;                             // padding workgroup (uniform)
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = task.x, p = task.y, kk0 = task.z;
+    const int S = nstates;
     const int np = npk_of(g.T, m, p);
     const int np4 = (np + 3) & ~3;
     const int s0 = blockIdx.y * 4;
@@ -156,40 +165,76 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const double* Pr = P + toff[2 * m + p] + (size_t)(rowok ? kr : 0) * g.nhp + 4 * q;
     const double* Hr = H + toff[2 * m + p] + (size_t)(rowok ? kr : 0) * g.nhp + 4 * q;
 
-    const int v = i & 7, re = v & 1, kind = v >> 1;           // kind: 0 zeta 1 delta 2 KE 3 Phi'
-    const int cH = kind == 0 ? 4 : (kind == 1 ? 5 : 6);
-    const size_t jstride = (size_t)2 * g.ms;                   // doubles per latitude row
-    const double* bP[2];
-    const double* bH[2];
+    const int v = i & 7, re = v & 1, kind = v >> 1;      // kind: 0 zeta 1 delta 2 KE 3 Phi'
+    const int cH = (kind == 0 ? 8 : (kind == 1 ? 10 : 12)) + re;
+    const size_t jstride = (size_t)S * kAnaVals;
+    const double* gb = G + (size_t)(m * 2 + p) * g.nhp * jstride + 4 * q * jstride;
     bool okP[2], okH[2];
+    int offP[2], offH[2];
     for (int t = 0; t < 2; ++t) {
         const int s = s0 + 2 * t + (i >> 3);
-        okP[t] = s < nstates;
+        okP[t] = s < S;
         okH[t] = okP[t] && kind != 2;
-        const size_t colbase = (size_t)(s * 2 + p) * kAnaCols;
-        bP[t] = (const double*)(ana + (colbase + kind) * g.nhp * g.ms + m) + re + 4 * q * jstride;
-        bH[t] = (const double*)(ana + (colbase + cH) * g.nhp * g.ms + m) + re + 4 * q * jstride;
+        offP[t] = (okP[t] ? s : 0) * kAnaVals + v;
+        offH[t] = (okP[t] ? s : 0) * kAnaVals + cH;
     }
     v4d acc0 = (v4d){0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-    const v4d zero4 = acc0;
-    for (int jh0 = 0; jh0 < g.nhp; jh0 += 16) {
-        const v4d ap = rowok ? *(const v4d*)(Pr + jh0) : zero4;
-        const v4d ah = rowok ? *(const v4d*)(Hr + jh0) : zero4;
-        const size_t o = (size_t)jh0 * jstride;
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-            const size_t oo = o + qq * jstride;
-            const bool jok = jh0 + 4 * q + qq < g.nh;      // padded latitude rows are never read
-            const double p0 = (jok && okP[0]) ? bP[0][oo] : 0.0;
-            const double h0 = (jok && okH[0]) ? bH[0][oo] : 0.0;
-            const double p1 = (jok && okP[1]) ? bP[1][oo] : 0.0;
-            const double h1 = (jok && okH[1]) ? bH[1][oo] : 0.0;
-            acc0 = mfma_f64(ap[qq], p0, acc0);
-            acc0 = mfma_f64(ah[qq], h0, acc0);
-            acc1 = mfma_f64(ap[qq], p1, acc1);
-            acc1 = mfma_f64(ah[qq], h1, acc1);
+    // this wave takes latitude blocks 16*wave, 16*wave + 64, ...; the next block's operands are
+    // loaded into the alternate register set while the current one is contracted
+    const int steps = g.nhp > 16 * wave ? (g.nhp - 16 * wave + 63) / 64 : 0;   // uniform
+    v4d A_ap, A_ah, B_ap, B_ah;
+    double A_b[16], B_b[16];
+#define ANA_LOAD(X, it)                                                                \
+    {                                                                                  \
+        int it_ = (it) < steps ? (it) : steps - 1;  /* clamp: valid, result unused */ \
+        const int jh0_ = 16 * wave + 64 * it_;                                         \
+        X##_ap = *(const v4d*)(Pr + jh0_);                                             \
+        X##_ah = *(const v4d*)(Hr + jh0_);                                             \
+        const double* go_ = gb + (size_t)jh0_ * jstride;                               \
+        _Pragma("unroll") for (int qq = 0; qq < 4; ++qq) {                             \
+            const double* gq_ = go_ + qq * jstride;                                    \
+            X##_b[4 * qq + 0] = gq_[offP[0]];                                          \
+            X##_b[4 * qq + 1] = gq_[offH[0]];                                          \
+            X##_b[4 * qq + 2] = gq_[offP[1]];                                          \
+            X##_b[4 * qq + 3] = gq_[offH[1]];                                          \
+        }                                                                              \
+    }
+#define ANA_COMPUTE(X, it)                                                             \
+    { /* a step past the end (odd step count) runs on zeroed operands: no branch */     \
+        const bool live_ = (it) < steps;                                               \
+        const int jh0_ = 16 * wave + 64 * (it);                                        \
+        _Pragma("unroll") for (int qq = 0; qq < 4; ++qq) {                             \
+            const bool jok = live_ && jh0_ + 4 * q + qq < g.nh;  /* padded rows unused */ \
+            const double a_ = rowok ? X##_ap[qq] : 0.0, h_ = rowok ? X##_ah[qq] : 0.0;  \
+            acc0 = mfma_f64(a_, (jok && okP[0]) ? X##_b[4 * qq + 0] : 0.0, acc0);        \
+            acc0 = mfma_f64(h_, (jok && okH[0]) ? X##_b[4 * qq + 1] : 0.0, acc0);        \
+            acc1 = mfma_f64(a_, (jok && okP[1]) ? X##_b[4 * qq + 2] : 0.0, acc1);        \
+            acc1 = mfma_f64(h_, (jok && okH[1]) ? X##_b[4 * qq + 3] : 0.0, acc1);        \
+        }                                                                              \
+    }
+    if (steps > 0) {
+        ANA_LOAD(A, 0)
+        for (int it = 0; it < steps; it += 2) {
+            ANA_LOAD(B, it + 1)
+            ANA_COMPUTE(A, it)
+            ANA_LOAD(A, it + 2)
+            ANA_COMPUTE(B, it + 1)
         }
     }
+#undef ANA_LOAD
+#undef ANA_COMPUTE
+    if (wave > 0)
+        for (int r = 0; r < 4; ++r) {
+            lds[((wave - 1) * 8 + r) * 64 + lane] = acc0[r];
+            lds[((wave - 1) * 8 + 4 + r) * 64 + lane] = acc1[r];
+        }
+    __syncthreads();
+    if (wave != 0) return;
+    for (int w = 0; w < 3; ++w)
+        for (int r = 0; r < 4; ++r) {
+            acc0[r] += lds[(w * 8 + r) * 64 + lane];
+            acc1[r] += lds[(w * 8 + 4 + r) * 64 + lane];
+        }
     const int cb = coef_offset(g.T, m) - m;
     for (int t = 0; t < 2; ++t) {
         const int s = s0 + 2 * t + (i >> 3);
@@ -197,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
             const double val = t == 0 ? acc0[r] : acc1[r];
             const double ke = __shfl_down(val, 2, 64);      // KE column sits two lanes to the right
             const int kk = kk0 + 4 * r + q;
-            if (kk >= np || s >= nstates || kind == 2) continue;
+            if (kk >= np || s >= S || kind == 2) continue;
             const int n = m + p + 2 * kk;
             const int field = kind == 0 ? 1 : (kind == 1 ? 2 : 0);
             const double res = kind == 1 ? val + neg_lap[n] * ke : val;
@@ -207,10 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
 }
 
 void launch_analysis_swe(const double* P, const double* H, const long long* toff,
-                         const int4* tasks, int ntasks, const double2* ana, int nstates,
+                         const int4* tasks, int nwg, const double* G, int nstates,
                          const double* neg_lap, double* out, const Geom& g, hipStream_t st) {
-    dim3 grid((ntasks + 3) / 4, (nstates + 3) / 4);
-    k_analysis_swe<<<grid, kBlock, 0, st>>>(P, H, toff, tasks, ntasks, ana, nstates, neg_lap, out, g);
+    dim3 grid(nwg, (nstates + 3) / 4);
+    k_analysis_swe<<<grid, kBlock, 0, st>>>(P, H, toff, tasks, G, nstates, neg_lap, out, g);
 }
 
 // ---------------------------------------------------------------------------------------------

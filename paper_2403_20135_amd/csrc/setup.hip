@@ -158,13 +158,17 @@ void launch_collocation(double* tau, double* Q, int Mmax, hipStream_t st) {
     k_collocation<<<1, 64, 0, st>>>(tau, Q, Mmax);
 }
 
-// Degree tables: n of every stored coefficient, -a^2/(n(n+1)) (inverse Laplacian, 0 at n = 0)
+// Degree tables: n and m of every stored coefficient, -a^2/(n(n+1)) (inverse Laplacian, 0 at n = 0)
 // and n(n+1)/a^2 (minus the Laplacian) for n = 0..T.
-__global__ void k_degree_tables(int* __restrict__ n_of, double* __restrict__ inv_lap,
-                                double* __restrict__ neg_lap, int T, double radius) {
+__global__ void k_degree_tables(int* __restrict__ n_of, int* __restrict__ m_of,
+                                double* __restrict__ inv_lap, double* __restrict__ neg_lap, int T,
+                                double radius) {
     const int m = blockIdx.x;
     const int base = coef_offset(T, m);
-    for (int n = m + threadIdx.x; n <= T; n += blockDim.x) n_of[base + n - m] = n;
+    for (int n = m + threadIdx.x; n <= T; n += blockDim.x) {
+        n_of[base + n - m] = n;
+        m_of[base + n - m] = m;
+    }
     if (m == 0) {
         for (int n = threadIdx.x; n <= T; n += blockDim.x) {
             const double nn = n * (n + 1.0);
@@ -174,7 +178,7 @@ __global__ void k_degree_tables(int* __restrict__ n_of, double* __restrict__ inv
     }
 }
 
-void launch_degree_tables(int* n_of, double* inv_lap, double* neg_lap, int T, double radius,
-                          hipStream_t st) {
-    k_degree_tables<<<T + 1, 64, 0, st>>>(n_of, inv_lap, neg_lap, T, radius);
+void launch_degree_tables(int* n_of, int* m_of, double* inv_lap, double* neg_lap, int T,
+                          double radius, hipStream_t st) {
+    k_degree_tables<<<T + 1, 64, 0, st>>>(n_of, m_of, inv_lap, neg_lap, T, radius);
 }

@@ -70,6 +70,17 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
         st2(out, phi);
         st2(out + fs, bzeta);
         st2(out + 2 * fs, dv);
+        if (a.cml) {
+            // synthesis layout of node state b*M + m: (zeta, Phi', psi, chi)
+            const int mo = a.m_of[idx], par = (n - mo) & 1, kk = (n - mo) >> 1;
+            const double il = a.inv_lap[n];
+            const size_t S = (size_t)a.batch * M;
+            double* c = a.cml + (((size_t)a.rowoff[2 * mo + par] + kk) * S + (size_t)b * M + m) * kCmlVals;
+            st2(c, bzeta);
+            st2(c + 2, phi);
+            st2(c + 4, make_double2(il * bzeta.x, il * bzeta.y));
+            st2(c + 6, make_double2(il * dv.x, il * dv.y));
+        }
         if (a.last_only) {
             bad = !(isfinite(phi.x) && isfinite(phi.y) && isfinite(bzeta.x) && isfinite(bzeta.y) &&
                     isfinite(dv.x) && isfinite(dv.y));
@@ -79,8 +90,39 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
 }
 
 void launch_update(const UpdateArgs& a, hipStream_t st) {
-    dim3 grid((a.ncoef + kBlock - 1) / kBlock, a.batch);
-    k_update<<<grid, kBlock, 0, st>>>(a);
+    // small workgroups: one thread per coefficient leaves few threads, spread them over all CUs
+    constexpr int kUpd = 64;
+    dim3 grid((a.ncoef + kUpd - 1) / kUpd, a.batch);
+    k_update<<<grid, kUpd, 0, st>>>(a);
+}
+
+// Synthesis layout of states [s][3][ncoef]: one thread per (coefficient, state).
+__global__ __launch_bounds__(kBlock) void k_prep_cml(const double* __restrict__ state, int nstates,
+                                                     double* __restrict__ cml,
+                                                     const int* __restrict__ n_of,
+                                                     const int* __restrict__ m_of,
+                                                     const int* __restrict__ rowoff,
+                                                     const double* __restrict__ inv_lap, int ncoef) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (idx >= ncoef) return;
+    const int n = n_of[idx], mo = m_of[idx], par = (n - mo) & 1, kk = (n - mo) >> 1;
+    const size_t fs = (size_t)ncoef * 2;
+    const double* u = state + (size_t)s * 3 * fs + (size_t)idx * 2;
+    const double2 phi = ld2(u), zeta = ld2(u + fs), dv = ld2(u + 2 * fs);
+    const double il = inv_lap[n];
+    double* c = cml + (((size_t)rowoff[2 * mo + par] + kk) * nstates + s) * kCmlVals;
+    st2(c, zeta);
+    st2(c + 2, phi);
+    st2(c + 4, make_double2(il * zeta.x, il * zeta.y));
+    st2(c + 6, make_double2(il * dv.x, il * dv.y));
+}
+
+void launch_prep_cml(const double* state, int nstates, double* cml, const int* n_of,
+                     const int* m_of, const int* rowoff, const double* inv_lap, int ncoef,
+                     hipStream_t st) {
+    dim3 grid((ncoef + kBlock - 1) / kBlock, nstates);
+    k_prep_cml<<<grid, kBlock, 0, st>>>(state, nstates, cml, n_of, m_of, rowoff, inv_lap, ncoef);
 }
 
 __global__ __launch_bounds__(kBlock) void k_implicit(const double* __restrict__ u, double* __restrict__ fI,

@@ -107,9 +107,12 @@ int sdc_free(sdc_handle h);
 int sdc_step(sdc_handle h, double* state, double dt, int M, int K);
 
 /* Adjoint of one step: lam_n = (d u_{n+1} / d u_n)^T lam_np1 for the step taken from state_n
- * with the same dt, M, K (the step is recomputed internally from state_n).  The inner product
- * is the real Euclidean one over (Re, Im) of every stored coefficient; imaginary parts of m = 0
- * entries of lam_n are set to zero.  lam_n may alias lam_np1 but not state_n. */
+ * with the same dt, M, K (the step is recomputed internally from state_n, keeping the grid fields
+ * of every stage; then the sweep runs in reverse with Q^T, the transposed per-degree solve and
+ * the transposed transforms).  The inner product is the real Euclidean one over (Re, Im) of every
+ * stored coefficient; imaginary parts of m = 0 entries of lam_n are set to zero.  lam_n may alias
+ * lam_np1 but not state_n.  The first call on a handle allocates its adjoint workspaces
+ * (grid fields of 1+(K-1)M stage states per member); later calls allocate nothing. */
 int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1, double* lam_n,
                      double dt, int M, int K);
 
@@ -120,6 +123,11 @@ int sht_forward(sdc_handle h, const double* grid, double* spec);
 
 /* Scalar spherical-harmonic synthesis: spec [batch][ncoef] -> grid [batch][nlat][nlon]. */
 int sht_inverse(sdc_handle h, const double* spec, double* grid);
+
+/* Transpose of sht_inverse (real inner products of grid values and of (Re, Im) coefficient pairs):
+ * spec = S^T grid, spec_nm = s_m sum_j Pbar_n^m(mu_j) sum_i grid_ij e^{-i m lambda_i}; imaginary
+ * parts of m = 0 entries are zero.  Used for gradients of grid losses. */
+int sht_inverse_adjoint(sdc_handle h, const double* grid, double* spec);
 
 /* The solver of Section 4.2: u with u - alpha f_I(u) = beta, for states [batch][3][ncoef];
  * closed form per coefficient.  u may alias beta.  alpha >= 0 and finite. */

@@ -127,6 +127,25 @@ class Oracle:
         g[..., 0:self.sphere.T + 1, 1] = 0.0
         return float(L.detach()), g.numpy()
 
+    def step_vjp(self, state, lam, dt: float, M: int, K: int):
+        """(d u_{n+1}/d u_n)^T lam by torch autograd through one oracle step (real inner product
+        over (Re, Im) of every coefficient; m = 0 imaginary entries of the result set to 0)."""
+        x = torch.tensor(np.asarray(state), dtype=DT, requires_grad=True)
+        y = to_real(self.step_c(to_complex(x), dt, M, K))
+        (g,) = torch.autograd.grad(y, x, torch.as_tensor(np.asarray(lam), dtype=DT))
+        g = g.detach().clone()
+        g[..., 0:self.sphere.T + 1, 1] = 0.0
+        return g.numpy()
+
+    def synthesis_vjp(self, grid):
+        """Transpose of the scalar synthesis (grid [..., nlat, nlon] -> spec [..., ncoef, 2])."""
+        c0 = torch.zeros(np.asarray(grid).shape[:-2] + (self.sphere.ncoef, 2), dtype=DT, requires_grad=True)
+        y = self.sphere.synthesis(to_complex(c0))
+        (g,) = torch.autograd.grad(y, c0, torch.as_tensor(np.asarray(grid), dtype=DT))
+        g = g.detach().clone()
+        g[..., 0:self.sphere.T + 1, 1] = 0.0
+        return g.numpy()
+
     def loss(self, state, phi_target, dt: float, M: int, K: int, steps: int) -> float:
         with torch.no_grad():
             u = to_complex(torch.as_tensor(np.asarray(state), dtype=DT))

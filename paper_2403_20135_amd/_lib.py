@@ -45,6 +45,7 @@ _SIGS = {
     "sdc_step_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int]),
     "sht_forward": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sht_inverse": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "sht_inverse_adjoint": (c_int, [c_void_p, c_void_p, c_void_p]),
     "imex_solve": (c_int, [c_void_p, c_double, c_void_p, c_void_p]),
     "eval_explicit": (c_int, [c_void_p, c_void_p, c_void_p]),
     "eval_implicit": (c_int, [c_void_p, c_void_p, c_void_p]),

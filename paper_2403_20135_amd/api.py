@@ -95,6 +95,12 @@ class SDC:
         check(self.lib.sht_inverse(self.h, _ptr(spec), _ptr(grid)))
         return grid
 
+    def sht_inverse_adjoint(self, grid, spec):
+        self._check(grid, self.grid_shape, "grid")
+        self._check(spec, self.spec_shape, "spec")
+        check(self.lib.sht_inverse_adjoint(self.h, _ptr(grid), _ptr(spec)))
+        return spec
+
     def imex_solve(self, alpha: float, beta, u):
         self._check(beta, self.state_shape, "beta")
         self._check(u, self.state_shape, "u")

@@ -1,0 +1,288 @@
+// Discrete adjoint of one dSDC step (transpose of every linear map of the forward step, at the
+// recomputed stages), with respect to the real inner product over (Re, Im) of every coefficient.
+//
+// f_E(u) = Analysis(Products(Synthesis(u))) has the Jacobian transpose
+//   J^T = Synthesis^T . Products'^T . Analysis^T.
+// * Analysis^T (this file: k_synthesis_adj + the first half of k_grid_adj): the analysis of a grid
+//   field is c_nm = sum_j w_j Pbar (1/nlon) DFT_m; its transpose is a synthesis with unit m-weights
+//   scaled per latitude.  For the tendencies zeta_t = -div(A,B), delta_t = curl(A,B) + c_n KE,
+//   Phi'_t = -div(C,D), with div/curl weights g'_j = w_j/(1-mu_j^2):
+//     A^ = i m Pbar.zeta_adj + H.delta_adj,   B^ = H.zeta_adj - i m Pbar.delta_adj,
+//     C^ = i m Pbar.Phi_adj,  D^ = H.Phi_adj,  E^ = Pbar.(c_n delta_adj)
+//   and on the grid A_adj = g'_j/(a nlon) sum_m Re(A^_m e^{i m lambda}) (unit m-weights; E with
+//   w_j/nlon).
+// * Products'^T (k_grid_adj): at the stage's grid fields (zeta, Phi', U, V), q = zeta + f,
+//     zeta_g_adj = A U + B V, Phi_g_adj = C U + D V,
+//     U_adj = A q + C Phi' + E U/(1-mu^2), V_adj = B q + D Phi' + E V/(1-mu^2).
+// * Synthesis^T (second half of k_grid_adj + analysis kernel in adjoint mode): for a scalar field
+//   (Synthesis^T g)_nm = s_m sum_j Pbar DFT_m(g) (unnormalised, no quadrature weight); for the winds
+//   psi_adj = (s_m/a) sum_j [-i m V^ Pbar - U^ H], chi_adj = (s_m/a) sum_j [-i m U^ Pbar + V^ H],
+//   zeta_adj += -a^2/(n(n+1)) psi_adj, delta_adj += -a^2/(n(n+1)) chi_adj.
+// The node update and solve are per-coefficient linear maps with constant real coefficients; their
+// transposes are written out in k_update_adj.
+#include "common.h"
+
+__device__ __forceinline__ v4d mfma_f64a(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ double2 ld2a(const double* p) { return *(const double2*)p; }
+__device__ __forceinline__ void st2a(double* p, double2 v) { *(double2*)p = v; }
+
+// ---------------------------------------------------------------------------------------------
+// Coefficient-major layout of adjoint tendencies: (zeta_adj, delta_adj, Phi_adj, c_n delta_adj).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_prep_cml_adj(const double* __restrict__ ebar, int nstates,
+                                                         double* __restrict__ cml,
+                                                         const int* __restrict__ n_of,
+                                                         const int* __restrict__ m_of,
+                                                         const int* __restrict__ rowoff,
+                                                         const double* __restrict__ neg_lap, int ncoef) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (idx >= ncoef) return;
+    const int n = n_of[idx], mo = m_of[idx], par = (n - mo) & 1, kk = (n - mo) >> 1;
+    const size_t fs = (size_t)ncoef * 2;
+    const double* e = ebar + (size_t)s * 3 * fs + (size_t)idx * 2;
+    const double2 phi = ld2a(e), zeta = ld2a(e + fs), dv = ld2a(e + 2 * fs);
+    const double c = neg_lap[n];
+    double* o = cml + (((size_t)rowoff[2 * mo + par] + kk) * nstates + s) * kCmlVals;
+    st2a(o, zeta);
+    st2a(o + 2, dv);
+    st2a(o + 4, phi);
+    st2a(o + 6, make_double2(c * dv.x, c * dv.y));
+}
+
+void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int* n_of, const int* m_of,
+                         const int* rowoff, const double* neg_lap, int ncoef, hipStream_t st) {
+    dim3 grid((ncoef + kBlock - 1) / kBlock, nstates);
+    k_prep_cml_adj<<<grid, kBlock, 0, st>>>(ebar, nstates, cml, n_of, m_of, rowoff, neg_lap, ncoef);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Analysis^T, Legendre part: per (m, latitude tile, 4 states) the sums over n of Pbar and H times
+// (zeta_adj, delta_adj, Phi_adj, c delta_adj); both tables multiply the same 16-wide column tile
+// (2 states x 4 values x (Re, Im)).  Output: Fourier coefficients of A^, B^, C^, D^, E^ at every
+// latitude, halved for m > 0 so that the standard real inverse transform (weights s_m) realises
+// the unit m-weights of the transpose.  Same work split and reduction as the forward synthesis.
+// ---------------------------------------------------------------------------------------------
+constexpr int kAdjAcc = 32;     // doubles per lane: {Pbar, H} x 2 parities x 2 tiles x 4
+
+__global__ __launch_bounds__(kBlock) void k_synthesis_adj(
+    const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
+    const int* __restrict__ rowoff, const int2* __restrict__ tasks, const double* __restrict__ cml,
+    int nstates, double2* __restrict__ four5, Geom g) {
+    __shared__ double lds[4 * kAdjAcc * 64];
+    const int2 task = tasks[blockIdx.x];
+    if (task.x < 0) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = task.x, jt = task.y;
+    const int S = nstates;
+    const int s0 = blockIdx.y * 4;
+    const int i = lane & 15, q = lane >> 4;
+    const int v = i & 7;
+    v4d acc[8];                       // [(table*2 + p)*2 + tile]
+    for (int k = 0; k < 8; ++k) acc[k] = (v4d){0.0, 0.0, 0.0, 0.0};
+    const int sA = s0 + (i >> 3), sB = s0 + 2 + (i >> 3);
+    const bool okA = sA < S, okB = sB < S;
+    const int offA = (okA ? sA : 0) * kCmlVals + v, offB = (okB ? sB : 0) * kCmlVals + v;
+    for (int p = 0; p < 2; ++p) {
+        const int np = npk_of(g.T, m, p);
+        const int np4 = (np + 3) & ~3;
+        const int steps = np4 > 4 * wave ? (np4 - 4 * wave + 15) / 16 : 0;
+        const double* Pp = P + toff[2 * m + p] + jt * 16 + i + (size_t)(4 * wave + q) * g.nhp;
+        const double* Hp = H + toff[2 * m + p] + jt * 16 + i + (size_t)(4 * wave + q) * g.nhp;
+        const double* Bp = cml + ((size_t)rowoff[2 * m + p] + 4 * wave + q) * S * kCmlVals;
+        const size_t tstep = (size_t)16 * g.nhp, bstep = (size_t)16 * S * kCmlVals;
+        v4d pa = acc[p * 2], pb = acc[p * 2 + 1], ha = acc[4 + p * 2], hb = acc[4 + p * 2 + 1];
+        int kk = 4 * wave + q;
+#pragma unroll 2
+        for (int it = 0; it < steps; ++it) {
+            const bool vn = kk < np;
+            const double ap = Pp[0], ah = Hp[0];
+            const double bA = Bp[offA], bB = Bp[offB];
+            const double xA = (vn && okA) ? bA : 0.0, xB = (vn && okB) ? bB : 0.0;
+            pa = mfma_f64a(ap, xA, pa);
+            pb = mfma_f64a(ap, xB, pb);
+            ha = mfma_f64a(ah, xA, ha);
+            hb = mfma_f64a(ah, xB, hb);
+            Pp += tstep;
+            Hp += tstep;
+            Bp += bstep;
+            kk += 16;
+        }
+        acc[p * 2] = pa;
+        acc[p * 2 + 1] = pb;
+        acc[4 + p * 2] = ha;
+        acc[4 + p * 2 + 1] = hb;
+    }
+    for (int k = 0; k < 8; ++k)
+        for (int r = 0; r < 4; ++r) lds[(wave * kAdjAcc + k * 4 + r) * 64 + lane] = acc[k][r];
+    __syncthreads();
+    double* red = lds;                // [sl 4][north/south 2][value 16][latitude 16]
+    if (wave == 0) {
+        double tot[kAdjAcc];
+        for (int k = 0; k < kAdjAcc; ++k) {
+            double sum = lds[k * 64 + lane];
+            for (int w = 1; w < 4; ++w) sum += lds[(w * kAdjAcc + k) * 64 + lane];
+            tot[k] = sum;
+        }
+        for (int r = 0; r < 4; ++r) {
+            const int latl = 4 * r + q;
+            for (int t = 0; t < 2; ++t) {
+                const int sl = 2 * t + (i >> 3);
+                const double pe = tot[(0 * 2 + t) * 4 + r], po = tot[(1 * 2 + t) * 4 + r];
+                const double he = tot[(4 + 0 * 2 + t) * 4 + r], ho = tot[(4 + 1 * 2 + t) * 4 + r];
+                red[((sl * 2 + 0) * 16 + v) * 16 + latl] = pe + po;
+                red[((sl * 2 + 1) * 16 + v) * 16 + latl] = pe - po;
+                red[((sl * 2 + 0) * 16 + 8 + v) * 16 + latl] = he + ho;
+                red[((sl * 2 + 1) * 16 + 8 + v) * 16 + latl] = ho - he;
+            }
+        }
+    }
+    __syncthreads();
+    const int it = threadIdx.x;
+    if (it >= 128) return;
+    const int sl = it >> 5, ns = (it >> 4) & 1, latl = it & 15;
+    const int s = s0 + sl, jh = jt * 16 + latl;
+    if (s >= S || jh >= g.nh) return;
+    const double* x = red + ((sl * 2 + ns) * 16) * 16 + latl;
+    const double pzr = x[0 * 16], pzi = x[1 * 16], pdr = x[2 * 16], pdi = x[3 * 16];
+    const double ppr = x[4 * 16], ppi = x[5 * 16], pcr = x[6 * 16], pci = x[7 * 16];
+    const double hzr = x[8 * 16], hzi = x[9 * 16], hdr = x[10 * 16], hdi = x[11 * 16];
+    const double hpr = x[12 * 16], hpi = x[13 * 16];
+    const double mm = (double)m, hf = m > 0 ? 0.5 : 1.0;
+    const int j = ns ? g.nlat - 1 - jh : jh;
+    const size_t fstride = (size_t)g.nlat * g.ms;
+    double2* base = four5 + (size_t)s * 5 * fstride + (size_t)j * g.ms + m;
+    base[0] = make_double2(hf * (-mm * pzi + hdr), hf * (mm * pzr + hdi));          // A^
+    base[fstride] = make_double2(hf * (hzr + mm * pdi), hf * (hzi - mm * pdr));     // B^
+    base[2 * fstride] = make_double2(hf * (-mm * ppi), hf * (mm * ppr));            // C^
+    base[3 * fstride] = make_double2(hf * hpr, hf * hpi);                           // D^
+    base[4 * fstride] = make_double2(hf * pcr, hf * pci);                           // E^
+}
+
+void launch_synthesis_adj(const double* P, const double* H, const long long* toff, const int* rowoff,
+                          const int2* tasks, int ntasks, const double* cml, int nstates, double2* four5,
+                          const Geom& g, hipStream_t st) {
+    dim3 grid(ntasks, (nstates + 3) / 4);
+    k_synthesis_adj<<<grid, kBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates, four5, g);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Node-update adjoint, one thread per (coefficient, member).  Per node m of sweep s:
+//   beta_adj_m = A_{m,s}^T ubar_m,  A = (I - alpha L)^{-1},  A^T(a, b, d) = ((a + alpha c d)/D, b,
+//   (d - alpha Phi_bar a)/D), D = 1 + alpha^2 Phi_bar c;  L^T(a, b, d) = (c d, 0, -Phi_bar a).
+//   u_n_adj += beta_adj_m
+//   E_adj_j (previous sweep) = dt sum_m q_mj beta_adj_m
+//   u_adj_j (previous sweep) = dt sum_m q_mj L^T beta_adj_m - alpha_{j,s} L^T beta_adj_j
+// For the last sweep only node M carries ubar (= the incoming adjoint state).  When the previous
+// sweep is the initial one (all nodes equal u_n, all tendencies E_0) the node sums are folded
+// into u_n_adj and E_0_adj.
+// ---------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_update_adj(AdjUpdateArgs a) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= a.ncoef) return;
+    const int n = a.n_of[idx];
+    const double c = n * (n + 1.0) * a.inv_a2;
+    const size_t o = (size_t)idx * 2;
+    const size_t fs = (size_t)a.ncoef * 2;
+    const int M = a.M;
+    const int sdiv = a.sweep < M ? a.sweep : M;
+    double2 bp[kMaxNodes], bz[kMaxNodes], bd[kMaxNodes];      // beta_adj per node
+    for (int m = 0; m < M; ++m) {
+        if (a.last && m != M - 1) {
+            bp[m] = bz[m] = bd[m] = make_double2(0.0, 0.0);
+            continue;
+        }
+        const double* u = a.ubar + (size_t)b * a.ubar_member + (size_t)(a.last ? 0 : m) * a.ubar_node + o;
+        const double2 up = ld2a(u), uz = ld2a(u + fs), ud = ld2a(u + 2 * fs);
+        const double alpha = a.dt * a.tau[m] / sdiv;
+        const double den = 1.0 / (1.0 + alpha * alpha * a.phibar * c);
+        bp[m] = make_double2((up.x + alpha * c * ud.x) * den, (up.y + alpha * c * ud.y) * den);
+        bz[m] = uz;
+        bd[m] = make_double2((ud.x - alpha * a.phibar * up.x) * den, (ud.y - alpha * a.phibar * up.y) * den);
+    }
+    double2 sp = make_double2(0.0, 0.0), sz = sp, sd = sp;    // u_n adjoint contributions
+    double2 ep0 = sp, ez0 = sp, ed0 = sp;                     // E_0 adjoint when first_stage
+    for (int m = 0; m < M; ++m) {
+        sp.x += bp[m].x; sp.y += bp[m].y;
+        sz.x += bz[m].x; sz.y += bz[m].y;
+        sd.x += bd[m].x; sd.y += bd[m].y;
+    }
+    for (int j = 0; j < M; ++j) {
+        double2 qp = make_double2(0.0, 0.0), qz = qp, qd = qp;   // sum_m q_mj beta_adj_m
+        for (int m = 0; m < M; ++m) {
+            const double qmj = a.Q[m * kMaxNodes + j];
+            qp.x += qmj * bp[m].x; qp.y += qmj * bp[m].y;
+            qz.x += qmj * bz[m].x; qz.y += qmj * bz[m].y;
+            qd.x += qmj * bd[m].x; qd.y += qmj * bd[m].y;
+        }
+        const double aj = a.dt * a.tau[j] / sdiv;
+        // E_adj_j = dt * qsum;  u_adj_j = dt L^T qsum - alpha_j L^T beta_adj_j
+        const double2 ep = make_double2(a.dt * qp.x, a.dt * qp.y);
+        const double2 ez = make_double2(a.dt * qz.x, a.dt * qz.y);
+        const double2 ed = make_double2(a.dt * qd.x, a.dt * qd.y);
+        const double2 wp = make_double2(c * (ed.x - aj * bd[j].x), c * (ed.y - aj * bd[j].y));
+        const double2 wd = make_double2(-a.phibar * (ep.x - aj * bp[j].x), -a.phibar * (ep.y - aj * bp[j].y));
+        if (a.first_stage) {
+            ep0.x += ep.x; ep0.y += ep.y;
+            ez0.x += ez.x; ez0.y += ez.y;
+            ed0.x += ed.x; ed0.y += ed.y;
+            sp.x += wp.x; sp.y += wp.y;
+            sd.x += wd.x; sd.y += wd.y;
+        } else {
+            double* e = a.ebar_prev + ((size_t)b * M + j) * 3 * fs + o;
+            st2a(e, ep);
+            st2a(e + fs, ez);
+            st2a(e + 2 * fs, ed);
+            double* u = a.ubar_prev + ((size_t)b * M + j) * 3 * fs + o;
+            st2a(u, wp);
+            st2a(u + fs, make_double2(0.0, 0.0));
+            st2a(u + 2 * fs, wd);
+        }
+    }
+    if (a.first_stage) {
+        double* e = a.ebar_prev + (size_t)b * 3 * fs + o;
+        st2a(e, ep0);
+        st2a(e + fs, ez0);
+        st2a(e + 2 * fs, ed0);
+    }
+    double* un = a.ubar_n + (size_t)b * 3 * fs + o;
+    if (a.init_un) {
+        st2a(un, sp);
+        st2a(un + fs, sz);
+        st2a(un + 2 * fs, sd);
+    } else {
+        const double2 p0 = ld2a(un), z0 = ld2a(un + fs), d0 = ld2a(un + 2 * fs);
+        st2a(un, make_double2(p0.x + sp.x, p0.y + sp.y));
+        st2a(un + fs, make_double2(z0.x + sz.x, z0.y + sz.y));
+        st2a(un + 2 * fs, make_double2(d0.x + sd.x, d0.y + sd.y));
+    }
+}
+
+void launch_update_adj(const AdjUpdateArgs& a, hipStream_t st) {
+    dim3 grid((a.ncoef + 63) / 64, a.batch);
+    k_update_adj<<<grid, 64, 0, st>>>(a);
+}
+
+// Copy the accumulated adjoint to the output with the m = 0 imaginary parts set to zero.
+__global__ __launch_bounds__(kBlock) void k_finish_adj(const double* __restrict__ src,
+                                                       double* __restrict__ dst,
+                                                       const int* __restrict__ m_of, int ncoef,
+                                                       long long total) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // one double2 each
+    if (k >= total) return;
+    const int idx = (int)(k % ncoef);
+    double2 v = ld2a(src + 2 * k);
+    if (m_of[idx] == 0) v.y = 0.0;
+    st2a(dst + 2 * k, v);
+}
+
+void launch_finish_adj(const double* src, double* dst, const int* m_of, int ncoef, int nstates,
+                       hipStream_t st) {
+    const long long total = (long long)nstates * 3 * ncoef;
+    k_finish_adj<<<(int)((total + kBlock - 1) / kBlock), kBlock, 0, st>>>(src, dst, m_of, ncoef, total);
+}

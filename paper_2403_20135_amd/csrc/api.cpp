@@ -124,6 +124,14 @@ struct sdc_ctx {
     int4* sana_tasks = nullptr;       // scalar analysis wave tasks
     int n_sana = 0;
     double *ua = nullptr, *ub = nullptr, *E = nullptr, *E0 = nullptr;
+    // adjoint workspaces (allocated by the first sdc_step_adjoint call)
+    bool adj_ready = false;
+    double2* adj_save = nullptr;      // stage grid fields [stage states][4][nh][nlon] (N, S)
+    double2* adj_four5 = nullptr;     // adjoint Fourier fields [S][5][nlat][m]
+    double* adj_ubar = nullptr;       // node adjoints of the current sweep [B][M][3][ncoef]
+    double* adj_ebar = nullptr;       // tendency adjoints [B][M][3][ncoef]
+    double* adj_un = nullptr;         // u_n adjoint [B][3][ncoef]
+    double* adj_x = nullptr;          // copy of u_n for the recomputation
     double* cml = nullptr;            // synthesis input, coefficient-major
     double* G = nullptr;              // analysis input (also the scalar analysis input)
     double2* four = nullptr;
@@ -347,13 +355,13 @@ int setup(sdc_ctx* c) {
 
 // f_E of S states whose synthesis input is already in c->cml (written by the update kernel or
 // by launch_prep_cml).
-void run_explicit_cml(sdc_ctx* c, int S, double* out) {
+void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr) {
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
     launch_synthesis_swe(c->P, c->H, c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->four,
                          c->g, c->st);
     c->end(SDC_KERNEL_SYNTHESIS, t);
     t = c->begin(SDC_KERNEL_GRID);
-    launch_grid_swe(c->four, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
+    launch_grid_swe(c->four, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, save, c->g, c->st);
     c->end(SDC_KERNEL_GRID, t);
     t = c->begin(SDC_KERNEL_ANALYSIS);
     launch_analysis_swe(c->P, c->H, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap, out, c->g,
@@ -361,11 +369,42 @@ void run_explicit_cml(sdc_ctx* c, int S, double* out) {
     c->end(SDC_KERNEL_ANALYSIS, t);
 }
 
-void run_explicit(sdc_ctx* c, const double* states, int S, double* out) {
+void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2* save = nullptr) {
     const long t = c->begin(SDC_KERNEL_UPDATE);
     launch_prep_cml(states, S, c->cml, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->st);
     c->end(SDC_KERNEL_UPDATE, t);
-    run_explicit_cml(c, S, out);
+    run_explicit_cml(c, S, out, save);
+}
+
+// out_acc += J_E(u)^T ebar for S states whose stage grid fields are in `save`.
+void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save, double* out_acc) {
+    launch_prep_cml_adj(ebar, S, c->cml, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->st);
+    launch_synthesis_adj(c->P, c->H, c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->adj_four5,
+                         c->g, c->st);
+    launch_grid_adj(c->adj_four5, save, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
+    launch_analysis_adjoint(c->P, c->H, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->inv_lap, out_acc,
+                            c->g, c->st);
+}
+
+size_t stage_states(const sdc_ctx* c, int s, int M) {     // states stored before stage s
+    return s == 0 ? 0 : (size_t)c->cfg.batch + (size_t)(s - 1) * c->cfg.batch * M;
+}
+
+int alloc_adjoint(sdc_ctx* c) {
+    if (c->adj_ready) return SDC_OK;
+    const Geom& g = c->g;
+    const size_t B = c->cfg.batch;
+    const size_t nst = B + (size_t)(c->cfg.K > 1 ? c->cfg.K - 1 : 0) * B * c->cfg.M;
+    const size_t st_d = (size_t)3 * g.ncoef * 2;
+    int rc;
+    if ((rc = c->alloc(c->adj_save, nst * kSynFields * g.nh * g.nlon))) return rc;
+    if ((rc = c->alloc(c->adj_four5, (size_t)c->smax * 5 * g.nlat * g.ms))) return rc;
+    if ((rc = c->alloc(c->adj_ubar, st_d * c->smax))) return rc;
+    if ((rc = c->alloc(c->adj_ebar, st_d * c->smax))) return rc;
+    if ((rc = c->alloc(c->adj_un, st_d * B))) return rc;
+    if ((rc = c->alloc(c->adj_x, st_d * B))) return rc;
+    c->adj_ready = true;
+    return SDC_OK;
 }
 
 void run_update(sdc_ctx* c, const UpdateArgs& a) {
@@ -494,8 +533,99 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
 int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1, double* lam_n,
                      double dt, int M, int K) {
     if (int rc = check_handle(h)) return rc;
-    (void)state_n; (void)lam_np1; (void)lam_n; (void)dt; (void)M; (void)K;
-    return fail(SDC_EUNSUPPORTED, "sdc_step_adjoint is not available in this build");
+    if (!state_n || !lam_np1 || !lam_n) return fail(SDC_EINVAL, "state_n/lam_np1/lam_n is NULL");
+    if (lam_n == state_n) return fail(SDC_EINVAL, "lam_n must not alias state_n");
+    if (M < 1 || M > h->cfg.M) return fail(SDC_EINVAL, "M=%d out of range 1..%d", M, h->cfg.M);
+    if (K < 1 || K > h->cfg.K) return fail(SDC_EINVAL, "K=%d out of range 1..%d", K, h->cfg.K);
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(SDC_EINVAL, "dt must be positive and finite");
+    sdc_ctx* c = h;
+    if (int rc = alloc_adjoint(c)) return rc;
+    const int B = c->cfg.batch;
+    const long long fs = 3LL * c->g.ncoef * 2;
+    const size_t save_per_state = (size_t)kSynFields * c->g.nh * c->g.nlon;
+    auto save_at = [&](int s) { return c->adj_save + stage_states(c, s, M) * save_per_state; };
+
+    // 1. recompute the forward stages, keeping the grid fields of every f_E evaluation
+    HIP_TRY(hipMemcpyAsync(c->adj_x, state_n, (size_t)B * fs * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    run_explicit(c, c->adj_x, B, c->E0, save_at(0));
+    UpdateArgs a{};
+    a.un = c->adj_x;
+    a.tau = c->tau + M * kMaxNodes;
+    a.Q = c->Q + M * kMaxNodes * kMaxNodes;
+    a.n_of = c->n_of;
+    a.m_of = c->m_of;
+    a.rowoff = c->rowoff;
+    a.inv_lap = c->inv_lap;
+    a.flag = c->flag;
+    a.dt = dt;
+    a.phibar = c->phibar;
+    a.inv_a2 = c->inv_a2;
+    a.M = M;
+    a.batch = B;
+    a.ncoef = c->g.ncoef;
+    a.uprev = c->adj_x;
+    a.uprev_node = 0;
+    a.uprev_member = fs;
+    a.E = c->E0;
+    a.E_node = 0;
+    a.E_member = fs;
+    double* bufs[2] = {c->ua, c->ub};
+    int cur = 0;
+    for (int s = 1; s < K; ++s) {
+        a.uout = bufs[cur];
+        a.out_node = fs;
+        a.out_member = (long long)M * fs;
+        a.cml = c->cml;
+        a.sweep = s;
+        a.last_only = 0;
+        launch_update(a, c->st);
+        run_explicit_cml(c, B * M, c->E, save_at(s));
+        a.uprev = bufs[cur];
+        a.uprev_node = fs;
+        a.uprev_member = (long long)M * fs;
+        a.E = c->E;
+        a.E_node = fs;
+        a.E_member = (long long)M * fs;
+        cur ^= 1;
+    }
+
+    // 2. reversed sweep: last-node update, then sweeps K-1..1, then the initial f_E
+    AdjUpdateArgs b{};
+    b.tau = a.tau;
+    b.Q = a.Q;
+    b.n_of = c->n_of;
+    b.dt = dt;
+    b.phibar = c->phibar;
+    b.inv_a2 = c->inv_a2;
+    b.M = M;
+    b.batch = B;
+    b.ncoef = c->g.ncoef;
+    b.ubar_n = c->adj_un;
+    b.ubar = lam_np1;
+    b.ubar_node = 0;
+    b.ubar_member = fs;
+    b.ubar_prev = c->adj_ubar;
+    b.ebar_prev = c->adj_ebar;
+    b.sweep = K;
+    b.last = 1;
+    b.first_stage = K == 1;
+    b.init_un = 1;
+    launch_update_adj(b, c->st);
+    for (int s = K - 1; s >= 1; --s) {
+        run_explicit_adj(c, c->adj_ebar, B * M, save_at(s), c->adj_ubar);
+        b.ubar = c->adj_ubar;
+        b.ubar_node = fs;
+        b.ubar_member = (long long)M * fs;
+        b.sweep = s;
+        b.last = 0;
+        b.first_stage = s == 1;
+        b.init_un = 0;
+        launch_update_adj(b, c->st);
+    }
+    run_explicit_adj(c, c->adj_ebar, B, save_at(0), c->adj_un);
+    launch_finish_adj(c->adj_un, lam_n, c->m_of, c->g.ncoef, B, c->st);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
 }
 
 int sht_inverse(sdc_handle h, const double* spec, double* grid) {
@@ -508,12 +638,23 @@ int sht_inverse(sdc_handle h, const double* spec, double* grid) {
     return SDC_OK;
 }
 
+int sht_inverse_adjoint(sdc_handle h, const double* grid, double* spec) {
+    if (int rc = check_handle(h)) return rc;
+    if (!spec || !grid) return fail(SDC_EINVAL, "spec/grid is NULL");
+    const int B = h->cfg.batch;
+    double2* sana = reinterpret_cast<double2*>(h->G);
+    launch_fft_forward_scalar(grid, sana, h->w, h->tw, h->plan, B, 1, h->g, h->st);
+    launch_analysis_scalar(h->P, h->toff, h->sana_tasks, h->n_sana, sana, B, spec, h->g, h->st);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
 int sht_forward(sdc_handle h, const double* grid, double* spec) {
     if (int rc = check_handle(h)) return rc;
     if (!spec || !grid) return fail(SDC_EINVAL, "spec/grid is NULL");
     const int B = h->cfg.batch;
     double2* sana = reinterpret_cast<double2*>(h->G);     // [f][p][nhp][m] fits in G
-    launch_fft_forward_scalar(grid, sana, h->w, h->tw, h->plan, B, h->g, h->st);
+    launch_fft_forward_scalar(grid, sana, h->w, h->tw, h->plan, B, 0, h->g, h->st);
     launch_analysis_scalar(h->P, h->toff, h->sana_tasks, h->n_sana, sana, B, spec, h->g, h->st);
     HIP_TRY(hipGetLastError());
     return SDC_OK;

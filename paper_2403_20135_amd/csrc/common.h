@@ -78,20 +78,28 @@ void launch_analysis_swe(const double* P, const double* H, const long long* toff
 void launch_synthesis_scalar(const double* P, const long long* toff, const int2* tasks, int ntasks,
                              const double* spec, int nfields, double2* four, const Geom& g,
                              hipStream_t st);
+void launch_analysis_adjoint(const double* P, const double* H, const long long* toff,
+                             const int4* tasks, int nwg, const double* G, int nstates,
+                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st);
 void launch_analysis_scalar(const double* P, const long long* toff, const int4* tasks, int ntasks,
                             const double2* ana, int nfields, double* spec, const Geom& g,
                             hipStream_t st);
 
 // grid.hip
+// save (optional): grid values of zeta, Phi', U, V per [state][field][northern latitude][lon]
+// as (north, south) pairs, kept for the adjoint.
 void launch_grid_swe(const double2* four, double* G, const double* mu, const double* w,
                      const double2* tw, const FFTPlan& plan, int nstates, double two_omega,
-                     const Geom& g, hipStream_t st);
+                     double2* save, const Geom& g, hipStream_t st);
+void launch_grid_adj(const double2* four5, const double2* save, double* G, const double* mu,
+                     const double* w, const double2* tw, const FFTPlan& plan, int nstates,
+                     double two_omega, const Geom& g, hipStream_t st);
 hipError_t grid_set_lds_limit(size_t bytes);
 void launch_fft_inverse_scalar(const double2* four, double* grid, const double2* tw,
                                const FFTPlan& plan, int nfields, const Geom& g, hipStream_t st);
 void launch_fft_forward_scalar(const double* grid, double2* ana, const double* w,
-                               const double2* tw, const FFTPlan& plan, int nfields, const Geom& g,
-                               hipStream_t st);
+                               const double2* tw, const FFTPlan& plan, int nfields,
+                               int transpose_synthesis, const Geom& g, hipStream_t st);
 
 // update.hip
 struct UpdateArgs {
@@ -122,3 +130,26 @@ void launch_implicit(const double* u, double* fI, const int* n_of, double phibar
                      int batch, int ncoef, hipStream_t st);
 void launch_solve(double alpha, const double* beta, double* u, const int* n_of, double phibar,
                   double inv_a2, int batch, int ncoef, hipStream_t st);
+
+// adjoint.hip
+void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int* n_of, const int* m_of,
+                         const int* rowoff, const double* neg_lap, int ncoef, hipStream_t st);
+void launch_synthesis_adj(const double* P, const double* H, const long long* toff, const int* rowoff,
+                          const int2* tasks, int ntasks, const double* cml, int nstates, double2* four5,
+                          const Geom& g, hipStream_t st);
+struct AdjUpdateArgs {
+    const double* ubar;          // [B][M][3][ncoef] adjoint of this sweep's nodes (or lam: [B][3][ncoef])
+    long long ubar_node, ubar_member;
+    double* ubar_prev;           // [B][M][3][ncoef] (written unless first_stage)
+    double* ebar_prev;           // [B][M][3][ncoef] or E_0 adjoint [B][3][ncoef] when first_stage
+    double* ubar_n;              // [B][3][ncoef]
+    const double* tau;
+    const double* Q;
+    const int* n_of;
+    double dt, phibar, inv_a2;
+    int M, sweep, last, first_stage, init_un, batch, ncoef;
+};
+
+void launch_update_adj(const AdjUpdateArgs& a, hipStream_t st);
+void launch_finish_adj(const double* src, double* dst, const int* m_of, int ncoef, int nstates,
+                       hipStream_t st);

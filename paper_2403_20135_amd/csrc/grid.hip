@@ -157,7 +157,7 @@ __device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, do
 __global__ __launch_bounds__(kBlock) void k_grid_swe(
     const double2* __restrict__ four, double* __restrict__ G, const double* __restrict__ mu,
     const double* __restrict__ w, const double2* __restrict__ tw, FFTPlan plan, double two_omega,
-    int nstates, Geom g) {
+    int nstates, double2* __restrict__ save, Geom g) {
     extern __shared__ double2 buf[];      // 5 signals x N, then the N twiddles
     const int ntask = g.nh * nstates;
     const int per = (ntask + 7) / 8;
@@ -179,6 +179,11 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
     // signals advanced two or three at a time to bound register use
     fft_lds<2>(buf, plan, twl, true);
     fft_lds<2>(buf + 2 * N, plan, twl, true);
+    if (save) {      // grid values of zeta, Phi', U, V (north, south) for the adjoint
+        for (int f = 0; f < kSynFields; ++f)
+            for (int k = threadIdx.x; k < N; k += kBlock)
+                save[((size_t)(s * kSynFields + f) * g.nh + jh) * N + k] = buf[f * N + k];
+    }
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;
     const double ke = 0.5 / ((1.0 - x) * (1.0 + x));
@@ -237,11 +242,103 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
 
 void launch_grid_swe(const double2* four, double* G, const double* mu, const double* w,
                      const double2* tw, const FFTPlan& plan, int nstates, double two_omega,
-                     const Geom& g, hipStream_t st) {
+                     double2* save, const Geom& g, hipStream_t st) {
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
     const size_t lds = (size_t)6 * plan.n * sizeof(double2);
-    k_grid_swe<<<nblk, kBlock, lds, st>>>(four, G, mu, w, tw, plan, two_omega, nstates, g);
+    k_grid_swe<<<nblk, kBlock, lds, st>>>(four, G, mu, w, tw, plan, two_omega, nstates, save, g);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adjoint grid step for one latitude pair of one state: inverse FFT of the adjoint Fourier fields
+// A^, B^, C^, D^, E^ (already halved for m > 0), latitude weights w/((1-mu^2) a nlon) and w/nlon,
+// transposed products at the saved stage fields, forward FFT (unnormalised) of the adjoints of
+// zeta, Phi', U, V, and the columns of the transposed synthesis (s_m = 1, 2 for m = 0, > 0):
+//   Pbar: s_m Z, (s_m/a)(-i m V), (s_m/a)(-i m U), s_m Phi;   H: -(s_m/a) U, (s_m/a) V
+// combined into north +- south sums per parity (Pbar: + for even n-m; H: - for even n-m).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_grid_adj(
+    const double2* __restrict__ four5, const double2* __restrict__ save, double* __restrict__ G,
+    const double* __restrict__ mu, const double* __restrict__ w, const double2* __restrict__ tw,
+    FFTPlan plan, double two_omega, int nstates, Geom g) {
+    extern __shared__ double2 buf[];      // 5 signals x N, then the N twiddles
+    const int ntask = g.nh * nstates;
+    const int per = (ntask + 7) / 8;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= ntask) return;
+    const int jh = t / nstates, s = t % nstates;
+    const int N = plan.n, T = g.T;
+    const int jN = jh, jS = g.nlat - 1 - jh;
+    const size_t fstride = (size_t)g.nlat * g.ms;
+    const double2* fs = four5 + (size_t)s * 5 * fstride;
+    double2* twl = buf + 5 * N;
+    for (int k = threadIdx.x; k < N; k += kBlock) twl[k] = tw[k];
+    for (int f = 0; f < 5; ++f) {
+        const double2* xn = fs + f * fstride + (size_t)jN * g.ms;
+        const double2* ys = fs + f * fstride + (size_t)jS * g.ms;
+        for (int k = threadIdx.x; k < N; k += kBlock) buf[f * N + k] = pack_pair(xn, ys, k, N, T);
+    }
+    __syncthreads();
+    fft_lds<3>(buf, plan, twl, true);
+    fft_lds<2>(buf + 3 * N, plan, twl, true);
+    const double x = mu[jN];
+    const double fN = two_omega * x, fS = -fN;
+    const double om2 = (1.0 - x) * (1.0 + x);
+    const double inv = 1.0 / om2;
+    const double gA = w[jN] / (om2 * g.radius * N), gE = w[jN] / N;
+    const double2* sv = save + ((size_t)(s * kSynFields) * g.nh + jh) * N;
+    const size_t sstride = (size_t)g.nh * N;
+    for (int k = threadIdx.x; k < N; k += kBlock) {
+        const double2 a = buf[k], b = buf[N + k], c = buf[2 * N + k], d = buf[3 * N + k], e = buf[4 * N + k];
+        const double2 zeta = sv[k], phi = sv[sstride + k], U = sv[2 * sstride + k], V = sv[3 * sstride + k];
+        const double An = gA * a.x, As = gA * a.y, Bn = gA * b.x, Bs = gA * b.y;
+        const double Cn = gA * c.x, Cs = gA * c.y, Dn = gA * d.x, Ds = gA * d.y;
+        const double En = gE * e.x * inv, Es = gE * e.y * inv;
+        const double qn = zeta.x + fN, qs = zeta.y + fS;
+        buf[k] = make_double2(An * U.x + Bn * V.x, As * U.y + Bs * V.y);
+        buf[N + k] = make_double2(Cn * U.x + Dn * V.x, Cs * U.y + Ds * V.y);
+        buf[2 * N + k] = make_double2(An * qn + Cn * phi.x + En * U.x, As * qs + Cs * phi.y + Es * U.y);
+        buf[3 * N + k] = make_double2(Bn * qn + Dn * phi.x + En * V.x, Bs * qs + Ds * phi.y + Es * V.y);
+    }
+    __syncthreads();
+    fft_lds<2>(buf, plan, twl, false);
+    fft_lds<2>(buf + 2 * N, plan, twl, false);
+    const size_t jstride = (size_t)nstates * kAnaVals;
+    const double inva = 1.0 / g.radius;
+    for (int m = threadIdx.x; m <= T; m += kBlock) {
+        double2 ZN, ZS, PN, PS, UN, US, VN, VS;
+        unpack_pair(buf, m, N, ZN, ZS);
+        unpack_pair(buf + N, m, N, PN, PS);
+        unpack_pair(buf + 2 * N, m, N, UN, US);
+        unpack_pair(buf + 3 * N, m, N, VN, VS);
+        const double sm = m == 0 ? 1.0 : 2.0, sa = sm * inva, ms = (double)m * sa;
+        const double2 Zs = cadd(ZN, ZS), Za = csub(ZN, ZS), Ps = cadd(PN, PS), Pa = csub(PN, PS);
+        const double2 Us = cadd(UN, US), Ua = csub(UN, US), Vs = cadd(VN, VS), Va = csub(VN, VS);
+        double2* o0 = reinterpret_cast<double2*>(G + ((size_t)(m * 2 + 0) * g.nhp + jh) * jstride + (size_t)s * kAnaVals);
+        double2* o1 = reinterpret_cast<double2*>(G + ((size_t)(m * 2 + 1) * g.nhp + jh) * jstride + (size_t)s * kAnaVals);
+        // -i m X (s_m/a) = (m sa X.y, -m sa X.x)
+        o0[0] = make_double2(sm * Zs.x, sm * Zs.y);
+        o0[1] = make_double2(ms * Vs.y, -ms * Vs.x);
+        o0[2] = make_double2(ms * Us.y, -ms * Us.x);
+        o0[3] = make_double2(sm * Ps.x, sm * Ps.y);
+        o0[4] = make_double2(-sa * Ua.x, -sa * Ua.y);
+        o0[5] = make_double2(sa * Va.x, sa * Va.y);
+        o1[0] = make_double2(sm * Za.x, sm * Za.y);
+        o1[1] = make_double2(ms * Va.y, -ms * Va.x);
+        o1[2] = make_double2(ms * Ua.y, -ms * Ua.x);
+        o1[3] = make_double2(sm * Pa.x, sm * Pa.y);
+        o1[4] = make_double2(-sa * Us.x, -sa * Us.y);
+        o1[5] = make_double2(sa * Vs.x, sa * Vs.y);
+    }
+}
+
+void launch_grid_adj(const double2* four5, const double2* save, double* G, const double* mu,
+                     const double* w, const double2* tw, const FFTPlan& plan, int nstates,
+                     double two_omega, const Geom& g, hipStream_t st) {
+    const int ntask = g.nh * nstates;
+    const int nblk = (ntask + 7) / 8 * 8;
+    const size_t lds = (size_t)6 * plan.n * sizeof(double2);
+    k_grid_adj<<<nblk, kBlock, lds, st>>>(four5, save, G, mu, w, tw, plan, two_omega, nstates, g);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -278,10 +375,11 @@ void launch_fft_inverse_scalar(const double2* four, double* grid, const double2*
     k_fft_inverse_scalar<<<gr, kBlock, 2 * plan.n * sizeof(double2), st>>>(four, grid, tw, plan, g);
 }
 
-// Output ana[f][p][jh][m] = w_j/nlon * (F_N +- F_S), + for parity 0, - for parity 1.
+// Output ana[f][p][jh][m] = scale * (F_N +- F_S), + for parity 0, - for parity 1, with F the
+// unnormalised DFT and scale = w_j/nlon (analysis) or s_m (transpose of the synthesis).
 __global__ __launch_bounds__(kBlock) void k_fft_forward_scalar(
     const double* __restrict__ grid, double2* __restrict__ ana, const double* __restrict__ w,
-    const double2* __restrict__ tw, FFTPlan plan, Geom g) {
+    const double2* __restrict__ tw, FFTPlan plan, int transpose_synthesis, Geom g) {
     extern __shared__ double2 buf[];
     const int jh = blockIdx.x, f = blockIdx.y;
     const int N = plan.n;
@@ -295,25 +393,30 @@ __global__ __launch_bounds__(kBlock) void k_fft_forward_scalar(
     }
     __syncthreads();
     fft_lds<1>(buf, plan, twl, false);
-    const double sc = w[jN] / N;
+    const double wsc = w[jN] / N;
     double2* o0 = ana + ((size_t)(f * 2 + 0) * g.nhp + jh) * g.ms;
     double2* o1 = ana + ((size_t)(f * 2 + 1) * g.nhp + jh) * g.ms;
     for (int m = threadIdx.x; m <= g.T; m += kBlock) {
         double2 XN, XS;
         unpack_pair(buf, m, N, XN, XS);
+        const double sc = transpose_synthesis ? (m == 0 ? 1.0 : 2.0) : wsc;
         o0[m] = make_double2(sc * (XN.x + XS.x), sc * (XN.y + XS.y));
         o1[m] = make_double2(sc * (XN.x - XS.x), sc * (XN.y - XS.y));
     }
 }
 
 void launch_fft_forward_scalar(const double* grid, double2* ana, const double* w,
-                               const double2* tw, const FFTPlan& plan, int nfields, const Geom& g,
-                               hipStream_t st) {
+                               const double2* tw, const FFTPlan& plan, int nfields,
+                               int transpose_synthesis, const Geom& g, hipStream_t st) {
     dim3 gr(g.nh, nfields);
-    k_fft_forward_scalar<<<gr, kBlock, 2 * plan.n * sizeof(double2), st>>>(grid, ana, w, tw, plan, g);
+    k_fft_forward_scalar<<<gr, kBlock, 2 * plan.n * sizeof(double2), st>>>(grid, ana, w, tw, plan,
+                                                                           transpose_synthesis, g);
 }
 
 hipError_t grid_set_lds_limit(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_swe),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_swe),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_adj),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }

@@ -11,6 +11,8 @@
 //   (rows interleaved across the four lane groups).
 #include "common.h"
 
+constexpr int kAnaForward = 0, kAnaAdjoint = 1;
+
 __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -137,18 +139,23 @@ void launch_synthesis_swe(const double* P, const double* H, const long long* tof
 }
 
 // ---------------------------------------------------------------------------------------------
-// Analysis for the shallow-water explicit tendency.  Input: per (m, parity p, latitude, state)
-// the seven weighted Fourier columns of the grid kernel.  Output per state:
+// Analysis for the shallow-water explicit tendency (MODE = kAnaForward).  Input: per (m, parity
+// p, latitude, state) the seven weighted Fourier columns of the grid kernel.  Output per state:
 //   d zeta/dt = Pbar.col0 + H.col4, d delta/dt = Pbar.col1 + H.col5 + n(n+1)/a^2 Pbar.col2,
 //   d Phi'/dt = Pbar.col3 + H.col6.
+// Transposed synthesis of the adjoint (MODE = kAnaAdjoint), accumulated into the output:
+//   zeta_adj += Pbar.col0 + (-a^2/(n(n+1))) (Pbar.col1 + H.col4'),
+//   delta_adj += (-a^2/(n(n+1))) (Pbar.col2 + H.col5'),  Phi'_adj += Pbar.col3
+// (col4', col5' stored in the H slots of kinds 1 and 2).
 // A workgroup owns (m, parity, 16 consecutive rows n, 4 states); its 4 waves take every fourth
 // 16-latitude block of the contraction and the partial tiles are summed in LDS in a fixed order.
 // Tile columns: 2 states x (zeta, delta, KE, Phi') x (Re, Im).
 // ---------------------------------------------------------------------------------------------
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
     const int4* __restrict__ tasks, const double* __restrict__ G, int nstates,
-    const double* __restrict__ neg_lap, double* __restrict__ out, Geom g) {
+    const double* __restrict__ nscale, double* __restrict__ out, Geom g) {
     __shared__ double lds[3 * 8 * 64];
     const int4 task = tasks[blockIdx.x];
     if (task.w == 0) return;                             // padding workgroup (uniform)
@@ -165,8 +172,12 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const double* Pr = P + toff[2 * m + p] + (size_t)(rowok ? kr : 0) * g.nhp + 4 * q;
     const double* Hr = H + toff[2 * m + p] + (size_t)(rowok ? kr : 0) * g.nhp + 4 * q;
 
-    const int v = i & 7, re = v & 1, kind = v >> 1;      // kind: 0 zeta 1 delta 2 KE 3 Phi'
-    const int cH = (kind == 0 ? 8 : (kind == 1 ? 10 : 12)) + re;
+    // forward kinds: 0 zeta 1 delta 2 KE 3 Phi'; adjoint kinds: 0 zeta 1 zeta (via psi)
+    // 2 delta (via chi) 3 Phi'
+    const int v = i & 7, re = v & 1, kind = v >> 1;
+    const bool has_h = MODE == kAnaForward ? kind != 2 : (kind == 1 || kind == 2);
+    const int cH = (MODE == kAnaForward ? (kind == 0 ? 8 : (kind == 1 ? 10 : 12))
+                                        : (kind == 1 ? 8 : 10)) + re;
     const size_t jstride = (size_t)S * kAnaVals;
     const double* gb = G + (size_t)(m * 2 + p) * g.nhp * jstride + 4 * q * jstride;
     bool okP[2], okH[2];
@@ -174,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     for (int t = 0; t < 2; ++t) {
         const int s = s0 + 2 * t + (i >> 3);
         okP[t] = s < S;
-        okH[t] = okP[t] && kind != 2;
+        okH[t] = okP[t] && has_h;
         offP[t] = (okP[t] ? s : 0) * kAnaVals + v;
         offH[t] = (okP[t] ? s : 0) * kAnaVals + cH;
     }
@@ -240,13 +251,21 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         const int s = s0 + 2 * t + (i >> 3);
         for (int r = 0; r < 4; ++r) {
             const double val = t == 0 ? acc0[r] : acc1[r];
-            const double ke = __shfl_down(val, 2, 64);      // KE column sits two lanes to the right
+            const double right = __shfl_down(val, 2, 64);   // the kind one to the right
             const int kk = kk0 + 4 * r + q;
-            if (kk >= np || s >= S || kind == 2) continue;
+            if (kk >= np || s >= S) continue;
             const int n = m + p + 2 * kk;
-            const int field = kind == 0 ? 1 : (kind == 1 ? 2 : 0);
-            const double res = kind == 1 ? val + neg_lap[n] * ke : val;
-            out[((size_t)(s * 3 + field) * g.ncoef + cb + n) * 2 + re] = res;
+            if constexpr (MODE == kAnaForward) {
+                if (kind == 2) continue;
+                const int field = kind == 0 ? 1 : (kind == 1 ? 2 : 0);
+                const double res = kind == 1 ? val + nscale[n] * right : val;
+                out[((size_t)(s * 3 + field) * g.ncoef + cb + n) * 2 + re] = res;
+            } else {
+                if (kind == 1) continue;
+                const int field = kind == 0 ? 1 : (kind == 2 ? 2 : 0);
+                const double res = kind == 0 ? val + nscale[n] * right : (kind == 2 ? nscale[n] * val : val);
+                out[((size_t)(s * 3 + field) * g.ncoef + cb + n) * 2 + re] += res;
+            }
         }
     }
 }
@@ -255,7 +274,14 @@ void launch_analysis_swe(const double* P, const double* H, const long long* toff
                          const int4* tasks, int nwg, const double* G, int nstates,
                          const double* neg_lap, double* out, const Geom& g, hipStream_t st) {
     dim3 grid(nwg, (nstates + 3) / 4);
-    k_analysis_swe<<<grid, kBlock, 0, st>>>(P, H, toff, tasks, G, nstates, neg_lap, out, g);
+    k_analysis_swe<kAnaForward><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, G, nstates, neg_lap, out, g);
+}
+
+void launch_analysis_adjoint(const double* P, const double* H, const long long* toff,
+                             const int4* tasks, int nwg, const double* G, int nstates,
+                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st) {
+    dim3 grid(nwg, (nstates + 3) / 4);
+    k_analysis_swe<kAnaAdjoint><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, G, nstates, inv_lap, out_acc, g);
 }
 
 // ---------------------------------------------------------------------------------------------

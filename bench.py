@@ -3,12 +3,14 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload t255_m4k4] [--no-cpu-baseline]
 
-Prints ONE JSON line.  The timed region is exactly K steps (after W warm-up steps) of the HIP
-library on synthetic seeded fields already resident in device memory, bracketed by
-torch.cuda.synchronize().  Inside the timed region the library brackets every kernel launch with
-HIP events on its own stream; the dominant kernel class (largest summed time) is reported
-against its roofline from algorithmic work per launch (flops of the useful Legendre
-contractions with equatorial symmetry, or minimal HBM bytes of the grid/update kernels).
+Prints ONE JSON line.  The timed region is exactly K steps (after W warm-up steps and one graph
+capture) of the HIP library on synthetic seeded fields already resident in device memory,
+bracketed by torch.cuda.synchronize(); each step is one replay of the step's captured hipGraph.
+A second region of K eager steps of the same kernels brackets every launch with HIP events on the
+library's stream; the dominant kernel class (largest summed time) is reported against its
+roofline from algorithmic work per launch (flops of the useful Legendre contractions with
+equatorial symmetry, or minimal HBM bytes of the grid/update kernels).  A third region times K
+forward steps with one checkpoint each followed by K adjoint steps (forward+adjoint steps/s).
 The CPU baseline is the FP64 oracle timed on this machine's host cores on a bounded sample.
 """
 from __future__ import annotations
@@ -102,13 +104,25 @@ def main():
         sdc.step(x, mb.dt)
     sdc.sync()
 
+    # timed region: K steps, each one replay of the step's captured hipGraph
+    sdc.step_graph(x, mb.dt)                          # capture (untimed)
+    sdc.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sdc.step_graph(x, mb.dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sdc.sync()
+
+    # per-kernel HIP events (on the library's stream) over K eager steps of the same kernels
     sdc.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         sdc.step(x, mb.dt)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed_eager = time.perf_counter() - t0
     sdc.sync()
     kt = sdc.timing_read()
     sdc.timing(False)
@@ -132,7 +146,7 @@ def main():
     d = kernels[dom]
     roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
                 "frac": d["frac"], "traffic": None, "kernel": dom,
-                "avg_launch_us": d["avg_us"]}
+                "avg_launch_us": d["avg_us"], "timed_over": "eager steps with per-launch HIP events"}
 
     # forward + adjoint: every forward step keeps its input (one checkpoint per step), then the
     # adjoint steps run in reverse, each recomputing its step's stages from the checkpoint
@@ -164,6 +178,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "eager_ms_per_step": round(elapsed_eager / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -106,6 +106,12 @@ int sdc_free(sdc_handle h);
  * node; MIN-SR-FLEX coefficient of sweep s is tau_m / min(s, M).  dt > 0 and finite. */
 int sdc_step(sdc_handle h, double* state, double dt, int M, int K);
 
+/* Same result as sdc_step, executed as one hipGraph launch on the handle's stream.  The first
+ * call for a given (state pointer, dt, M, K) captures the step's kernel sequence (on a private
+ * stream) and instantiates it; later calls with the same key replay it.  A handle keeps the 8 most
+ * recent graphs.  The state must stay allocated while a graph for it is cached. */
+int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K);
+
 /* Adjoint of one step: lam_n = (d u_{n+1} / d u_n)^T lam_np1 for the step taken from state_n
  * with the same dt, M, K (the step is recomputed internally from state_n, keeping the grid fields
  * of every stage; then the sweep runs in reverse with Q^T, the transposed per-degree solve and
@@ -170,6 +176,19 @@ int sdc_get_info(sdc_handle h, sdc_info* info);
 int sdc_copy_grid(sdc_handle h, double* mu, double* w);
 int sdc_copy_coefficients(sdc_handle h, int M, double* tau, double* Q);
 int sdc_copy_legendre(sdc_handle h, int m, double* Pbar, double* H);
+
+/* Ensembles of different truncations (one handle per truncation, each with its own members):
+ * sdc_group_step advances every member of every handle by one dSDC step (Algorithm 2) as ONE graph
+ * launch on the group's stream; the handles' steps are parallel branches of the graph.  states[i]
+ * and dts[i] belong to members[i]; M and K are common (<= every handle's configured M, K).  The
+ * graph is captured on the first call and whenever states, dts, M or K change.  The member handles
+ * must outlive the group and must not be used on other streams while a group step is in flight.
+ * sdc_group_sync waits for the group's stream and returns the first deferred error of a member. */
+typedef struct sdc_group_s* sdc_group;
+int sdc_group_create(const sdc_handle* members, int n, void* hip_stream, sdc_group* out);
+int sdc_group_step(sdc_group g, double* const* states, const double* dts, int M, int K);
+int sdc_group_sync(sdc_group g);
+int sdc_group_free(sdc_group g);
 
 /* Message of the last error on the calling host thread ("" if none). */
 const char* sdc_last_error(void);

@@ -42,7 +42,12 @@ _SIGS = {
     "sdc_init": (c_int, [ctypes.POINTER(SdcConfig), c_void_p, ctypes.POINTER(c_void_p)]),
     "sdc_free": (c_int, [c_void_p]),
     "sdc_step": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
+    "sdc_step_graph": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
     "sdc_step_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int]),
+    "sdc_group_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    "sdc_group_step": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_double), c_int, c_int]),
+    "sdc_group_sync": (c_int, [c_void_p]),
+    "sdc_group_free": (c_int, [c_void_p]),
     "sht_forward": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sht_inverse": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sht_inverse_adjoint": (c_int, [c_void_p, c_void_p, c_void_p]),

@@ -74,6 +74,12 @@ class SDC:
         check(self.lib.sdc_step(self.h, _ptr(state), float(dt), M or self.M, K or self.K))
         return state
 
+    def step_graph(self, state, dt: float, M: Optional[int] = None, K: Optional[int] = None):
+        """One dSDC step in place as a replayed hipGraph (captured on first use per key)."""
+        self._check(state, self.state_shape, "state")
+        check(self.lib.sdc_step_graph(self.h, _ptr(state), float(dt), M or self.M, K or self.K))
+        return state
+
     def step_adjoint(self, state_n, lam_np1, lam_n, dt: float, M: Optional[int] = None,
                      K: Optional[int] = None):
         self._check(state_n, self.state_shape, "state_n")
@@ -166,6 +172,45 @@ class SDC:
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.sdc_free(self.h)
             self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SDCGroup:
+    """Members of different truncations advanced together: one graph launch per step."""
+
+    def __init__(self, members, stream: Optional[int] = None):
+        import torch
+        self.members = list(members)
+        self.lib = _lib.load()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        arr = (ctypes.c_void_p * len(self.members))(*[m.h.value for m in self.members])
+        g = ctypes.c_void_p()
+        check(self.lib.sdc_group_create(arr, len(self.members), ctypes.c_void_p(stream), ctypes.byref(g)))
+        self.g = g
+
+    def step(self, states, dts, M: int, K: int):
+        if len(states) != len(self.members) or len(dts) != len(self.members):
+            raise ValueError("one state tensor and one dt per member handle")
+        for m, s in zip(self.members, states):
+            m._check(s, m.state_shape, "state")
+        ptrs = (ctypes.c_void_p * len(states))(*[s.data_ptr() for s in states])
+        dd = (ctypes.c_double * len(dts))(*[float(d) for d in dts])
+        check(self.lib.sdc_group_step(self.g, ptrs, dd, int(M), int(K)))
+        return states
+
+    def sync(self):
+        check(self.lib.sdc_group_sync(self.g))
+
+    def close(self):
+        if getattr(self, "g", None) is not None and self.g.value:
+            self.lib.sdc_group_free(self.g)
+            self.g = ctypes.c_void_p()
 
     def __del__(self):
         try:

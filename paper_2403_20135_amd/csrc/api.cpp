@@ -124,6 +124,16 @@ struct sdc_ctx {
     int4* sana_tasks = nullptr;       // scalar analysis wave tasks
     int n_sana = 0;
     double *ua = nullptr, *ub = nullptr, *E = nullptr, *E0 = nullptr;
+    // captured steps: (state, dt, M, K) -> executable graph, replayed on st
+    struct GraphEntry {
+        const double* state;
+        double dt;
+        int M, K;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    hipStream_t cap = nullptr;        // private stream used only for capture
+    std::vector<GraphEntry> graphs;
     // adjoint workspaces (allocated by the first sdc_step_adjoint call)
     bool adj_ready = false;
     double2* adj_save = nullptr;      // stage grid fields [stage states][4][nh][nlon] (N, S)
@@ -189,6 +199,11 @@ struct sdc_ctx {
         return SDC_OK;
     }
     ~sdc_ctx() {
+        for (auto& ge : graphs) {
+            (void)hipGraphExecDestroy(ge.exec);
+            (void)hipGraphDestroy(ge.graph);
+        }
+        if (cap) (void)hipStreamDestroy(cap);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
     }
@@ -467,13 +482,21 @@ int sdc_get_info(sdc_handle h, sdc_info* info) {
     return SDC_OK;
 }
 
-int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
+}  // extern "C"
+
+namespace {
+
+int check_step_args(sdc_handle h, const double* state, double dt, int M, int K) {
     if (int rc = check_handle(h)) return rc;
     if (!state) return fail(SDC_EINVAL, "state is NULL");
     if (M < 1 || M > h->cfg.M) return fail(SDC_EINVAL, "M=%d out of range 1..%d", M, h->cfg.M);
     if (K < 1 || K > h->cfg.K) return fail(SDC_EINVAL, "K=%d out of range 1..%d", K, h->cfg.K);
     if (!(dt > 0) || !std::isfinite(dt)) return fail(SDC_EINVAL, "dt must be positive and finite");
-    sdc_ctx* c = h;
+    return SDC_OK;
+}
+
+// Algorithm 2 for all members of the handle, enqueued on c->st (arguments already checked).
+void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
     const int B = c->cfg.batch;
     const long long fs = 3LL * c->g.ncoef * 2;
     // sweep initialisation: E_0 = f_E(u_n); u_m^0 = u_n and E_m^0 = E_0 through node stride 0
@@ -526,7 +549,55 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
     a.sweep = K;
     a.last_only = 1;
     run_update(c, a);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
+    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    enqueue_step(h, state, dt, M, K);
     HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K) {
+    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    sdc_ctx* c = h;
+    sdc_ctx::GraphEntry* hit = nullptr;
+    for (auto& ge : c->graphs)
+        if (ge.state == state && ge.dt == dt && ge.M == M && ge.K == K) hit = &ge;
+    if (!hit) {
+        if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        hipStream_t user = c->st;
+        const bool timing = c->timing;
+        c->st = c->cap;
+        c->timing = false;
+        hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+        hipGraph_t graph = nullptr;
+        if (e == hipSuccess) {
+            enqueue_step(c, state, dt, M, K);
+            e = hipStreamEndCapture(c->cap, &graph);
+        }
+        c->st = user;
+        c->timing = timing;
+        if (e != hipSuccess) return fail(SDC_EHIP, "step capture failed: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(SDC_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        if (c->graphs.size() >= 8) {          // keep a few recent shapes
+            (void)hipGraphExecDestroy(c->graphs.front().exec);
+            (void)hipGraphDestroy(c->graphs.front().graph);
+            c->graphs.erase(c->graphs.begin());
+        }
+        c->graphs.push_back({state, dt, M, K, graph, exec});
+        hit = &c->graphs.back();
+    }
+    HIP_TRY(hipGraphLaunch(hit->exec, c->st));
     return SDC_OK;
 }
 
@@ -768,6 +839,138 @@ int sdc_copy_legendre(sdc_handle h, int m, double* Pbar, double* H) {
         }
     }
     return SDC_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Ensembles of mixed truncations: one graph per step whose parallel branches are the members'
+// handles (each with its own workspaces), forked from and joined back to one capture stream.
+// ---------------------------------------------------------------------------------------------
+struct sdc_group_s {
+    std::vector<sdc_handle> members;
+    hipStream_t st = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> branch;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    std::vector<double*> key_states;
+    std::vector<double> key_dts;
+    int key_M = 0, key_K = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~sdc_group_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : join) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        for (hipStream_t b : branch) (void)hipStreamDestroy(b);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+int sdc_group_create(const sdc_handle* members, int n, void* hip_stream, sdc_group* out) {
+    if (!out) return fail(SDC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!members || n < 1 || n > 64) return fail(SDC_EINVAL, "members/n invalid (1 <= n <= 64)");
+    for (int i = 0; i < n; ++i) {
+        if (!members[i]) return fail(SDC_EINVAL, "member %d is NULL", i);
+        for (int j = 0; j < i; ++j)
+            if (members[j] == members[i]) return fail(SDC_EINVAL, "member %d repeated", i);
+    }
+    sdc_group_s* g = new (std::nothrow) sdc_group_s();
+    if (!g) return fail(SDC_ENOMEM, "host allocation failed");
+    g->members.assign(members, members + n);
+    g->st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        hipStream_t b = nullptr;
+        hipEvent_t j = nullptr;
+        e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
+        if (e == hipSuccess) g->branch.push_back(b);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+        if (e == hipSuccess) g->join.push_back(j);
+    }
+    if (e != hipSuccess) {
+        delete g;
+        return fail(SDC_EHIP, "group stream/event creation failed: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return SDC_OK;
+}
+
+int sdc_group_free(sdc_group g) {
+    if (!g) return SDC_OK;
+    (void)hipStreamSynchronize(g->st);
+    delete g;
+    return SDC_OK;
+}
+
+int sdc_group_step(sdc_group g, double* const* states, const double* dts, int M, int K) {
+    if (!g) return fail(SDC_EINVAL, "group is NULL");
+    if (!states || !dts) return fail(SDC_EINVAL, "states/dts is NULL");
+    const size_t n = g->members.size();
+    for (size_t i = 0; i < n; ++i)
+        if (int rc = check_step_args(g->members[i], states[i], dts[i], M, K)) return rc;
+    bool same = g->exec && g->key_M == M && g->key_K == K;
+    for (size_t i = 0; same && i < n; ++i) same = g->key_states[i] == states[i] && g->key_dts[i] == dts[i];
+    if (!same) {
+        if (g->exec) {
+            (void)hipGraphExecDestroy(g->exec);
+            (void)hipGraphDestroy(g->graph);
+            g->exec = nullptr;
+            g->graph = nullptr;
+        }
+        std::vector<hipStream_t> saved(n);
+        std::vector<bool> saved_timing(n);
+        hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) e = hipEventRecord(g->fork, g->cap);
+        for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+            sdc_ctx* c = g->members[i];
+            e = hipStreamWaitEvent(g->branch[i], g->fork, 0);
+            if (e != hipSuccess) break;
+            saved[i] = c->st;
+            saved_timing[i] = c->timing;
+            c->st = g->branch[i];
+            c->timing = false;
+            enqueue_step(c, states[i], dts[i], M, K);
+            c->st = saved[i];
+            c->timing = saved_timing[i];
+            e = hipEventRecord(g->join[i], g->branch[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(g->cap, g->join[i], 0);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(g->cap, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(SDC_EHIP, "group step capture failed: %s", hipGetErrorString(e));
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(SDC_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        g->graph = graph;
+        g->exec = exec;
+        g->key_states.assign(states, states + n);
+        g->key_dts.assign(dts, dts + n);
+        g->key_M = M;
+        g->key_K = K;
+    }
+    HIP_TRY(hipGraphLaunch(g->exec, g->st));
+    return SDC_OK;
+}
+
+int sdc_group_sync(sdc_group g) {
+    if (!g) return fail(SDC_EINVAL, "group is NULL");
+    HIP_TRY(hipStreamSynchronize(g->st));
+    int rc_all = SDC_OK;
+    for (sdc_handle h : g->members) {
+        const int rc = sdc_sync(h);
+        if (rc != SDC_OK && rc_all == SDC_OK) rc_all = rc;
+    }
+    return rc_all;
 }
 
 }  // extern "C"

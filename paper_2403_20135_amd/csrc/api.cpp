@@ -30,13 +30,54 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(SDC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// FFT plan for nlon = 2^p or 3*2^p: an optional radix-3 stage, then the power of two split into
+// radices 16, 8, 4, 2.  A pass advances fchunk of a workgroup's up to 5 signals together, every
+// stage within the per-thread task budget fft_task_cap; the plan minimises the number of
+// stage passes ceil(5 / fchunk) * stages.
+constexpr int kFFTSignals = 5;
+
+int fft_chunk_for(int n, const std::vector<int>& radices) {
+    int best = 0;
+    for (int F = 1; F <= kFFTSignals; ++F) {
+        bool ok = true;
+        for (int R : radices) ok = ok && (F * (n / R) + kBlock - 1) / kBlock <= fft_task_cap(R);
+        if (ok) best = F;
+    }
+    return best;
+}
+
+void search_pow2(int n, int p_left, std::vector<int>& cur, const std::vector<int>& head,
+                 std::vector<int>& best, int& best_cost) {
+    if (p_left == 0) {
+        std::vector<int> all(head);
+        all.insert(all.end(), cur.begin(), cur.end());
+        const int fc = fft_chunk_for(n, all);
+        if (fc == 0) return;
+        const int cost = (kFFTSignals + fc - 1) / fc * (int)all.size();
+        if (best.empty() || cost < best_cost) {
+            best = all;
+            best_cost = cost;
+        }
+        return;
+    }
+    const int last = cur.empty() ? 4 : 31 - __builtin_clz(cur.back());
+    for (int part = last; part >= 1; --part) {       // non-increasing radices
+        if (part > p_left) continue;
+        cur.push_back(1 << part);
+        search_pow2(n, p_left - part, cur, head, best, best_cost);
+        cur.pop_back();
+    }
+}
+
 bool make_fft_plan(int n, FFTPlan& pl) {
     pl.n = n;
     pl.nst = 0;
+    pl.fchunk = 0;
     int rest = n;
+    std::vector<int> head;
     if (rest % 3 == 0) {
         rest /= 3;
-        pl.radix[pl.nst++] = 3;
+        head.push_back(3);
     }
     int p = 0;
     while (rest > 1 && rest % 2 == 0) {
@@ -44,20 +85,17 @@ bool make_fft_plan(int n, FFTPlan& pl) {
         ++p;
     }
     if (rest != 1) return false;
-    if (p % 2 == 1 && p >= 3) {
-        pl.radix[pl.nst++] = 8;
-        p -= 3;
+    std::vector<int> cur, best;
+    int best_cost = 0;
+    if (p > 0) {
+        search_pow2(n, p, cur, head, best, best_cost);
+    } else {
+        best = head;
     }
-    while (p >= 2) {
-        pl.radix[pl.nst++] = 4;
-        p -= 2;
-    }
-    if (p == 1) pl.radix[pl.nst++] = 2;
-    // every stage must fit the per-thread butterfly budget of the LDS FFT
-    for (int s = 0; s < pl.nst; ++s) {
-        const int per = (pl.radix[s] >= 8) ? 1 : 2;
-        if (n / pl.radix[s] > per * kBlock) return false;
-    }
+    if (best.empty() || (int)best.size() > kMaxFFTStages) return false;
+    pl.fchunk = fft_chunk_for(n, best);
+    if (pl.fchunk == 0) return false;
+    for (int R : best) pl.radix[pl.nst++] = R;
     return true;
 }
 
@@ -230,8 +268,8 @@ int validate_config(const sdc_config* c) {
     if (c->batch < 1 || c->batch > 4096) return fail(SDC_EINVAL, "batch=%d out of range 1..4096", c->batch);
     if (c->nlon > 2048) return fail(SDC_EUNSUPPORTED, "nlon=%d > 2048 is not supported", c->nlon);
     FFTPlan pl;
-    if (!make_fft_plan(c->nlon, pl))
-        return fail(SDC_EUNSUPPORTED, "nlon=%d is not 2^p or 3*2^p", c->nlon);
+    if (!make_fft_plan(c->nlon, pl) || !fft_length_supported(c->nlon))
+        return fail(SDC_EUNSUPPORTED, "nlon=%d is not one of 16..2048 = 2^p or 24..1536 = 3*2^p", c->nlon);
     if (c->precision != SDC_FP64)
         return fail(SDC_EUNSUPPORTED, "precision=%d is not available in this build", c->precision);
     return SDC_OK;
@@ -364,7 +402,7 @@ int setup(sdc_ctx* c) {
     HIP_TRY(hipStreamSynchronize(c->st));
 
     const size_t lds = (size_t)6 * cf.nlon * sizeof(double2);
-    if (lds > 65536) HIP_TRY(grid_set_lds_limit(lds));
+    if (lds > 65536) HIP_TRY(grid_set_lds_limit(cf.nlon, lds));
     return SDC_OK;
 }
 

@@ -17,13 +17,17 @@ constexpr int kBlock = 256;         // threads per workgroup for all kernels (4 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------------------------
-// FFT plan: nlon = 2^p or 3 * 2^p, factored into radices 3, 8, 4, 2 (in that order).
+// FFT plan: nlon = 2^p or 3 * 2^p, factored into radices 3, 16, 8, 4, 2.
 // ---------------------------------------------------------------------------------------------
 struct FFTPlan {
     int n;
     int nst;
+    int fchunk;                 // signals advanced together per pass (register budget)
     int radix[kMaxFFTStages];
 };
+// tasks (butterflies) a thread may stage per radix: bounds the registers of an FFT stage to about
+// 24 complex values
+__host__ __device__ constexpr int fft_task_cap(int R) { return R >= 16 ? 1 : 24 / R; }
 
 // ---------------------------------------------------------------------------------------------
 // Geometry of one truncation as the kernels see it.
@@ -94,7 +98,8 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
 void launch_grid_adj(const double2* four5, const double2* save, double* G, const double* mu,
                      const double* w, const double2* tw, const FFTPlan& plan, int nstates,
                      double two_omega, const Geom& g, hipStream_t st);
-hipError_t grid_set_lds_limit(size_t bytes);
+hipError_t grid_set_lds_limit(int nlon, size_t bytes);
+bool fft_length_supported(int nlon);
 void launch_fft_inverse_scalar(const double2* four, double* grid, const double2* tw,
                                const FFTPlan& plan, int nfields, const Geom& g, hipStream_t st);
 void launch_fft_forward_scalar(const double* grid, double2* ana, const double* w,

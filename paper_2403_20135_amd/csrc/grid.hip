@@ -2,9 +2,10 @@
 //
 // Each workgroup owns one pair of mirror latitudes (north j, south nlat-1-j).  A real field on
 // the two rows is carried as one complex signal z = north + i south, so one complex FFT of
-// length nlon serves both rows.  The FFT is a Stockham autosort transform with radices 3, 8, 4
-// and 2 (nlon = 2^p or 3*2^p), all signals of the workgroup advanced together, one LDS buffer
-// per signal (values staged in registers between the read and write halves of a stage).
+// length nlon serves both rows.  The FFT is a Stockham autosort transform with radices 3, 16, 8,
+// 4 and 2 (nlon = 2^p or 3*2^p), all signals of the workgroup advanced together, one LDS buffer
+// per signal (values staged in registers between the read and write halves of a stage).  Radix
+// 16 and 8 stages keep the number of LDS passes and barriers low (nlon = 768 = 3 x 16 x 16).
 #include "common.h"
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -40,6 +41,35 @@ __device__ __forceinline__ void dft_small(double2 (&v)[R], bool inv) {
         v[2] = csub(a0, a2);
         v[1] = cadd(a1, a3);
         v[3] = csub(a1, a3);
+    } else if constexpr (R == 16) {
+        // 16 = 4 x 4: DFT4 over n1 of v[4 n1 + n2], twiddles W16^{n2 k1}, DFT4 over n2
+        constexpr double C[10] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                                  0.38268343236508977173, 0.0, -0.38268343236508977173,
+                                  -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                                  -0.92387953251128675613};
+        constexpr double Sn[10] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                                   0.92387953251128675613, 1.0, 0.92387953251128675613,
+                                   0.70710678118654752440, 0.38268343236508977173, 0.0,
+                                   -0.38268343236508977173};
+        const double sg = inv ? 1.0 : -1.0;
+        double2 y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            double2 t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+            dft_small<4>(t, inv);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) {
+                const int j = n2 * k1;
+                y[n2][k1] = j == 0 ? t[k1] : cmul(t[k1], make_double2(C[j], sg * Sn[j]));
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            double2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            dft_small<4>(t, inv);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
     } else if constexpr (R == 8) {
         // two radix-4 DFTs on even and odd inputs, combined with the eighth roots of unity
         double2 e[4] = {v[0], v[2], v[4], v[6]};
@@ -61,65 +91,115 @@ __device__ __forceinline__ void dft_small(double2 (&v)[R], bool inv) {
     }
 }
 
-// One Stockham stage of radix R on F signals of length N stored at buf + f*N.
-// Butterfly j reads x[j + r N/R], applies twiddles w^(r k), k = j mod Ns, w = e^{-+2 pi i/(Ns R)},
-// and writes y[(j/Ns) Ns R + k + r Ns].
-template <int R, int F>
-__device__ __forceinline__ void fft_stage(double2* buf, int N, int Ns, const double2* tw,
-                                          bool inv) {
-    constexpr int MAXB = R >= 8 ? 1 : 2;
-    const int nb = N / R;
-    const int tstep = N / (Ns * R);
-    double2 v[MAXB][F][R];
+// Compile-time FFT plans for the supported lengths (radix-3 stage first, then radices 16/8/4/2;
+// a pass advances up to fft_fchunk(N) of a workgroup's signals so that every stage stages at
+// most fft_task_cap(R) butterflies per thread).  The host accepts exactly these lengths.
+constexpr int fft_nst(int n) {
+    switch (n) {
+        case 16: return 1;
+        case 24: case 48: case 32: case 64: case 128: case 256: return 2;
+        case 96: case 192: case 384: case 768: case 512: return 3;
+        case 1536: case 1024: case 2048: return 4;
+        default: return 0;
+    }
+}
+constexpr int fft_fchunk(int n) { return n == 1536 ? 4 : (n == 2048 ? 3 : 5); }
+constexpr int fft_radix(int n, int s) {
+    switch (n) {
+        case 24: return s == 0 ? 3 : 8;
+        case 48: return s == 0 ? 3 : 16;
+        case 96: return s == 0 ? 3 : (s == 1 ? 16 : 2);
+        case 192: return s == 0 ? 3 : (s == 1 ? 16 : 4);
+        case 384: return s == 0 ? 3 : (s == 1 ? 16 : 8);
+        case 768: return s == 0 ? 3 : 16;
+        case 1536: return s == 0 ? 3 : 8;
+        case 16: return 16;
+        case 32: return s == 0 ? 16 : 2;
+        case 64: return s == 0 ? 16 : 4;
+        case 128: return s == 0 ? 16 : 8;
+        case 256: return 16;
+        case 512: return s < 2 ? 16 : 2;
+        case 1024: return s < 3 ? 8 : 2;
+        case 2048: return s < 3 ? 8 : 4;
+        default: return 0;
+    }
+}
+
+// One Stockham stage of radix R on F <= fft_fchunk(N) signals of length N at buf + f*N.  Task t
+// of the workgroup is butterfly j = t mod (N/R) of signal f = t div (N/R); it reads x[j + r N/R],
+// applies twiddles w^(r k), k = j mod NS, w = e^{-+2 pi i/(NS R)}, and writes
+// y[(j/NS) NS R + k + r NS].  Up to MAXT tasks per thread are held in registers between the read
+// and the write half (one LDS buffer per signal).
+template <int R, int N, int NS, int MAXT, bool INV>
+__device__ __forceinline__ void fft_stage(double2* buf, int F, const double2* tw) {
+    constexpr int nb = N / R;
+    constexpr int tstep = N / (NS * R);
+    const int ntask = F * nb;
+    double2 v[MAXT][R];
 #pragma unroll
-    for (int bb = 0; bb < MAXB; ++bb) {
-        const int j = threadIdx.x + bb * kBlock;
-        if (j < nb) {
-            const int k = j % Ns;
+    for (int tt = 0; tt < MAXT; ++tt) {
+        const int t = threadIdx.x + tt * kBlock;
+        if (t < ntask) {
+            const int f = t / nb, j = t - f * nb, k = j % NS;
+            const double2* src = buf + f * N + j;
 #pragma unroll
-            for (int f = 0; f < F; ++f)
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[bb][f][r] = buf[f * N + j + r * nb];
+            for (int r = 0; r < R; ++r) v[tt][r] = src[r * nb];
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                double2 t = tw[r * k * tstep];
-                if (inv) t.y = -t.y;
-#pragma unroll
-                for (int f = 0; f < F; ++f) v[bb][f][r] = cmul(v[bb][f][r], t);
+                double2 w = tw[r * k * tstep];
+                if (INV) w.y = -w.y;
+                v[tt][r] = cmul(v[tt][r], w);
             }
-#pragma unroll
-            for (int f = 0; f < F; ++f) dft_small<R>(v[bb][f], inv);
+            dft_small<R>(v[tt], INV);
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int bb = 0; bb < MAXB; ++bb) {
-        const int j = threadIdx.x + bb * kBlock;
-        if (j < nb) {
-            const int k = j % Ns;
-            const int d = (j / Ns) * Ns * R + k;
+    for (int tt = 0; tt < MAXT; ++tt) {
+        const int t = threadIdx.x + tt * kBlock;
+        if (t < ntask) {
+            const int f = t / nb, j = t - f * nb, k = j % NS;
+            double2* dst = buf + f * N + (j / NS) * NS * R + k;
 #pragma unroll
-            for (int f = 0; f < F; ++f)
-#pragma unroll
-                for (int r = 0; r < R; ++r) buf[f * N + d + r * Ns] = v[bb][f][r];
+            for (int r = 0; r < R; ++r) dst[r * NS] = v[tt][r];
         }
     }
     __syncthreads();
 }
 
-// Unnormalised DFT of F signals in LDS: forward X_k = sum x_n e^{-2 pi i nk/N}, inverse with +.
-template <int F>
-__device__ void fft_lds(double2* buf, const FFTPlan& pl, const double2* tw, bool inv) {
-    int Ns = 1;
-    for (int s = 0; s < pl.nst; ++s) {
-        const int R = pl.radix[s];
-        if (R == 3) fft_stage<3, F>(buf, pl.n, Ns, tw, inv);
-        else if (R == 4) fft_stage<4, F>(buf, pl.n, Ns, tw, inv);
-        else if (R == 8) fft_stage<8, F>(buf, pl.n, Ns, tw, inv);
-        else fft_stage<2, F>(buf, pl.n, Ns, tw, inv);
-        Ns *= R;
+template <int N, int S, int NS, bool INV>
+__device__ __forceinline__ void fft_stages(double2* buf, int F, const double2* tw) {
+    if constexpr (S < fft_nst(N)) {
+        constexpr int R = fft_radix(N, S);
+        constexpr int MAXT = (fft_fchunk(N) * (N / R) + kBlock - 1) / kBlock;
+        static_assert(MAXT <= fft_task_cap(R), "FFT stage exceeds the per-thread task budget");
+        fft_stage<R, N, NS, MAXT, INV>(buf, F, tw);
+        fft_stages<N, S + 1, NS * R, INV>(buf, F, tw);
     }
 }
+
+// Unnormalised DFT of F signals of length N in LDS: forward X_k = sum x_n e^{-2 pi i nk/N},
+// inverse with +.
+template <int N, bool INV>
+__device__ __forceinline__ void fft_lds(double2* buf, int F, const double2* tw) {
+    constexpr int FC = fft_fchunk(N);
+    for (int f0 = 0; f0 < F; f0 += FC) fft_stages<N, 0, 1, INV>(buf + f0 * N, F - f0 < FC ? F - f0 : FC, tw);
+}
+
+bool fft_length_supported(int n) { return fft_nst(n) > 0; }
+
+// calls BODY(N) with N the compile-time FFT length equal to the runtime value n
+#define FFT_DISPATCH(n, BODY)                                                       \
+    switch (n) {                                                                    \
+        case 16: BODY(16); break;     case 24: BODY(24); break;                     \
+        case 32: BODY(32); break;     case 48: BODY(48); break;                     \
+        case 64: BODY(64); break;     case 96: BODY(96); break;                     \
+        case 128: BODY(128); break;   case 192: BODY(192); break;                   \
+        case 256: BODY(256); break;   case 384: BODY(384); break;                   \
+        case 512: BODY(512); break;   case 768: BODY(768); break;                   \
+        case 1024: BODY(1024); break; case 1536: BODY(1536); break;                 \
+        case 2048: BODY(2048); break; default: break;                               \
+    }
 
 // Hermitian spectrum of the pair (north X, south Y) for the inverse transform of z = x + i y:
 // W_0 = Re X_0 + i Re Y_0, W_m = X_m + i Y_m and W_{N-m} = conj(X_m) + i conj(Y_m) for 1<=m<=T.
@@ -154,9 +234,10 @@ __device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, do
 // Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of (latitude, state) tasks,
 // states fastest, so the partial rows of the analysis input meet in one L2.
 // ---------------------------------------------------------------------------------------------
+template <int N>
 __global__ __launch_bounds__(kBlock) void k_grid_swe(
     const double2* __restrict__ four, double* __restrict__ G, const double* __restrict__ mu,
-    const double* __restrict__ w, const double2* __restrict__ tw, FFTPlan plan, double two_omega,
+    const double* __restrict__ w, const double2* __restrict__ tw, double two_omega,
     int nstates, double2* __restrict__ save, Geom g) {
     extern __shared__ double2 buf[];      // 5 signals x N, then the N twiddles
     const int ntask = g.nh * nstates;
@@ -164,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
     const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (t >= ntask) return;                // uniform per workgroup, before any barrier
     const int jh = t / nstates, s = t % nstates;
-    const int N = plan.n, T = g.T;
+    const int T = g.T;
     const int jN = jh, jS = g.nlat - 1 - jh;
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four + (size_t)s * kSynFields * fstride;
@@ -177,8 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
     }
     __syncthreads();
     // signals advanced two or three at a time to bound register use
-    fft_lds<2>(buf, plan, twl, true);
-    fft_lds<2>(buf + 2 * N, plan, twl, true);
+    fft_lds<N, true>(buf, kSynFields, twl);
     if (save) {      // grid values of zeta, Phi', U, V (north, south) for the adjoint
         for (int f = 0; f < kSynFields; ++f)
             for (int k = threadIdx.x; k < N; k += kBlock)
@@ -197,8 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
         buf[4 * N + k] = make_double2((U.x * U.x + V.x * V.x) * ke, (U.y * U.y + V.y * V.y) * ke);
     }
     __syncthreads();
-    fft_lds<3>(buf, plan, twl, false);
-    fft_lds<2>(buf + 3 * N, plan, twl, false);
+    fft_lds<N, false>(buf, 5, twl);
     const double invN = 1.0 / N;
     const double wt = w[jN];
     const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
@@ -246,7 +325,9 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
     const size_t lds = (size_t)6 * plan.n * sizeof(double2);
-    k_grid_swe<<<nblk, kBlock, lds, st>>>(four, G, mu, w, tw, plan, two_omega, nstates, save, g);
+#define LAUNCH(NN) k_grid_swe<NN><<<nblk, kBlock, lds, st>>>(four, G, mu, w, tw, two_omega, nstates, save, g)
+    FFT_DISPATCH(plan.n, LAUNCH)
+#undef LAUNCH
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -257,17 +338,18 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
 //   Pbar: s_m Z, (s_m/a)(-i m V), (s_m/a)(-i m U), s_m Phi;   H: -(s_m/a) U, (s_m/a) V
 // combined into north +- south sums per parity (Pbar: + for even n-m; H: - for even n-m).
 // ---------------------------------------------------------------------------------------------
+template <int N>
 __global__ __launch_bounds__(kBlock) void k_grid_adj(
     const double2* __restrict__ four5, const double2* __restrict__ save, double* __restrict__ G,
     const double* __restrict__ mu, const double* __restrict__ w, const double2* __restrict__ tw,
-    FFTPlan plan, double two_omega, int nstates, Geom g) {
+    double two_omega, int nstates, Geom g) {
     extern __shared__ double2 buf[];      // 5 signals x N, then the N twiddles
     const int ntask = g.nh * nstates;
     const int per = (ntask + 7) / 8;
     const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (t >= ntask) return;
     const int jh = t / nstates, s = t % nstates;
-    const int N = plan.n, T = g.T;
+    const int T = g.T;
     const int jN = jh, jS = g.nlat - 1 - jh;
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four5 + (size_t)s * 5 * fstride;
@@ -279,8 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(
         for (int k = threadIdx.x; k < N; k += kBlock) buf[f * N + k] = pack_pair(xn, ys, k, N, T);
     }
     __syncthreads();
-    fft_lds<3>(buf, plan, twl, true);
-    fft_lds<2>(buf + 3 * N, plan, twl, true);
+    fft_lds<N, true>(buf, 5, twl);
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;
     const double om2 = (1.0 - x) * (1.0 + x);
@@ -301,8 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(
         buf[3 * N + k] = make_double2(Bn * qn + Dn * phi.x + En * V.x, Bs * qs + Ds * phi.y + Es * V.y);
     }
     __syncthreads();
-    fft_lds<2>(buf, plan, twl, false);
-    fft_lds<2>(buf + 2 * N, plan, twl, false);
+    fft_lds<N, false>(buf, kSynFields, twl);
     const size_t jstride = (size_t)nstates * kAnaVals;
     const double inva = 1.0 / g.radius;
     for (int m = threadIdx.x; m <= T; m += kBlock) {
@@ -338,18 +418,20 @@ void launch_grid_adj(const double2* four5, const double2* save, double* G, const
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
     const size_t lds = (size_t)6 * plan.n * sizeof(double2);
-    k_grid_adj<<<nblk, kBlock, lds, st>>>(four5, save, G, mu, w, tw, plan, two_omega, nstates, g);
+#define LAUNCH(NN) k_grid_adj<NN><<<nblk, kBlock, lds, st>>>(four5, save, G, mu, w, tw, two_omega, nstates, g)
+    FFT_DISPATCH(plan.n, LAUNCH)
+#undef LAUNCH
 }
 
 // ---------------------------------------------------------------------------------------------
 // Scalar longitude transforms for sht_inverse / sht_forward (one latitude pair per workgroup).
 // ---------------------------------------------------------------------------------------------
+template <int N>
 __global__ __launch_bounds__(kBlock) void k_fft_inverse_scalar(
     const double2* __restrict__ four, double* __restrict__ grid, const double2* __restrict__ tw,
-    FFTPlan plan, Geom g) {
+    Geom g) {
     extern __shared__ double2 buf[];
     const int jh = blockIdx.x, f = blockIdx.y;
-    const int N = plan.n;
     const int jN = jh, jS = g.nlat - 1 - jh;
     const double2* xn = four + ((size_t)f * g.nlat + jN) * g.ms;
     const double2* ys = four + ((size_t)f * g.nlat + jS) * g.ms;
@@ -359,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_inverse_scalar(
         twl[k] = tw[k];
     }
     __syncthreads();
-    fft_lds<1>(buf, plan, twl, true);
+    fft_lds<N, true>(buf, 1, twl);
     double* rn = grid + ((size_t)f * g.nlat + jN) * g.nlon;
     double* rs = grid + ((size_t)f * g.nlat + jS) * g.nlon;
     for (int k = threadIdx.x; k < N; k += kBlock) {
@@ -372,17 +454,20 @@ __global__ __launch_bounds__(kBlock) void k_fft_inverse_scalar(
 void launch_fft_inverse_scalar(const double2* four, double* grid, const double2* tw,
                                const FFTPlan& plan, int nfields, const Geom& g, hipStream_t st) {
     dim3 gr(g.nh, nfields);
-    k_fft_inverse_scalar<<<gr, kBlock, 2 * plan.n * sizeof(double2), st>>>(four, grid, tw, plan, g);
+    const size_t lds = 2 * plan.n * sizeof(double2);
+#define LAUNCH(NN) k_fft_inverse_scalar<NN><<<gr, kBlock, lds, st>>>(four, grid, tw, g)
+    FFT_DISPATCH(plan.n, LAUNCH)
+#undef LAUNCH
 }
 
 // Output ana[f][p][jh][m] = scale * (F_N +- F_S), + for parity 0, - for parity 1, with F the
 // unnormalised DFT and scale = w_j/nlon (analysis) or s_m (transpose of the synthesis).
+template <int N>
 __global__ __launch_bounds__(kBlock) void k_fft_forward_scalar(
     const double* __restrict__ grid, double2* __restrict__ ana, const double* __restrict__ w,
-    const double2* __restrict__ tw, FFTPlan plan, int transpose_synthesis, Geom g) {
+    const double2* __restrict__ tw, int transpose_synthesis, Geom g) {
     extern __shared__ double2 buf[];
     const int jh = blockIdx.x, f = blockIdx.y;
-    const int N = plan.n;
     const int jN = jh, jS = g.nlat - 1 - jh;
     const double* rn = grid + ((size_t)f * g.nlat + jN) * g.nlon;
     const double* rs = grid + ((size_t)f * g.nlat + jS) * g.nlon;
@@ -392,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_forward_scalar(
         twl[k] = tw[k];
     }
     __syncthreads();
-    fft_lds<1>(buf, plan, twl, false);
+    fft_lds<N, false>(buf, 1, twl);
     const double wsc = w[jN] / N;
     double2* o0 = ana + ((size_t)(f * 2 + 0) * g.nhp + jh) * g.ms;
     double2* o1 = ana + ((size_t)(f * 2 + 1) * g.nhp + jh) * g.ms;
@@ -409,14 +494,21 @@ void launch_fft_forward_scalar(const double* grid, double2* ana, const double* w
                                const double2* tw, const FFTPlan& plan, int nfields,
                                int transpose_synthesis, const Geom& g, hipStream_t st) {
     dim3 gr(g.nh, nfields);
-    k_fft_forward_scalar<<<gr, kBlock, 2 * plan.n * sizeof(double2), st>>>(grid, ana, w, tw, plan,
-                                                                           transpose_synthesis, g);
+    const size_t lds = 2 * plan.n * sizeof(double2);
+#define LAUNCH(NN) k_fft_forward_scalar<NN><<<gr, kBlock, lds, st>>>(grid, ana, w, tw, transpose_synthesis, g)
+    FFT_DISPATCH(plan.n, LAUNCH)
+#undef LAUNCH
 }
 
-hipError_t grid_set_lds_limit(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_swe),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_adj),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+hipError_t grid_set_lds_limit(int n, size_t bytes) {
+    hipError_t e = hipSuccess;
+#define SETLDS(NN)                                                                                   \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_swe<NN>),                          \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                 \
+    if (e == hipSuccess)                                                                             \
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_adj<NN>),                      \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)
+    FFT_DISPATCH(n, SETLDS)
+#undef SETLDS
+    return e;
 }

@@ -28,6 +28,8 @@ def compile_flags():
             "-Wno-unused-function", "-Wno-unused-command-line-argument",
             # no packed FP32 instructions in any device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # MFMA accumulators in ordinary VGPRs (no AGPR copies around every MFMA in loops)
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             f"-I{os.path.join(ROOT, 'include')}"]
 
 

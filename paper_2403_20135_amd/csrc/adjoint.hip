@@ -181,6 +181,7 @@ void launch_synthesis_adj(const double* P, const double* H, const long long* tof
 // into u_n_adj and E_0_adj.
 // ---------------------------------------------------------------------------------------------
 
+template <int M>
 __global__ __launch_bounds__(64) void k_update_adj(AdjUpdateArgs a) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
@@ -189,9 +190,9 @@ __global__ __launch_bounds__(64) void k_update_adj(AdjUpdateArgs a) {
     const double c = n * (n + 1.0) * a.inv_a2;
     const size_t o = (size_t)idx * 2;
     const size_t fs = (size_t)a.ncoef * 2;
-    const int M = a.M;
     const int sdiv = a.sweep < M ? a.sweep : M;
-    double2 bp[kMaxNodes], bz[kMaxNodes], bd[kMaxNodes];      // beta_adj per node
+    double2 bp[M], bz[M], bd[M];                              // beta_adj per node
+#pragma unroll
     for (int m = 0; m < M; ++m) {
         if (a.last && m != M - 1) {
             bp[m] = bz[m] = bd[m] = make_double2(0.0, 0.0);
@@ -207,13 +208,16 @@ __global__ __launch_bounds__(64) void k_update_adj(AdjUpdateArgs a) {
     }
     double2 sp = make_double2(0.0, 0.0), sz = sp, sd = sp;    // u_n adjoint contributions
     double2 ep0 = sp, ez0 = sp, ed0 = sp;                     // E_0 adjoint when first_stage
+#pragma unroll
     for (int m = 0; m < M; ++m) {
         sp.x += bp[m].x; sp.y += bp[m].y;
         sz.x += bz[m].x; sz.y += bz[m].y;
         sd.x += bd[m].x; sd.y += bd[m].y;
     }
+#pragma unroll
     for (int j = 0; j < M; ++j) {
         double2 qp = make_double2(0.0, 0.0), qz = qp, qd = qp;   // sum_m q_mj beta_adj_m
+#pragma unroll
         for (int m = 0; m < M; ++m) {
             const double qmj = a.Q[m * kMaxNodes + j];
             qp.x += qmj * bp[m].x; qp.y += qmj * bp[m].y;
@@ -265,7 +269,16 @@ __global__ __launch_bounds__(64) void k_update_adj(AdjUpdateArgs a) {
 
 void launch_update_adj(const AdjUpdateArgs& a, hipStream_t st) {
     dim3 grid((a.ncoef + 63) / 64, a.batch);
-    k_update_adj<<<grid, 64, 0, st>>>(a);
+    switch (a.M) {
+    case 1: k_update_adj<1><<<grid, 64, 0, st>>>(a); break;
+    case 2: k_update_adj<2><<<grid, 64, 0, st>>>(a); break;
+    case 3: k_update_adj<3><<<grid, 64, 0, st>>>(a); break;
+    case 4: k_update_adj<4><<<grid, 64, 0, st>>>(a); break;
+    case 5: k_update_adj<5><<<grid, 64, 0, st>>>(a); break;
+    case 6: k_update_adj<6><<<grid, 64, 0, st>>>(a); break;
+    case 7: k_update_adj<7><<<grid, 64, 0, st>>>(a); break;
+    default: k_update_adj<8><<<grid, 64, 0, st>>>(a); break;
+    }
 }
 
 // Copy the accumulated adjoint to the output with the m = 0 imaginary parts set to zero.

@@ -18,7 +18,9 @@ __device__ __forceinline__ void st2(double* p, double2 v) { *(double2*)p = v; }
 
 // beta_m = u_n + dt sum_j Q[m][j] (L_g(u_j) + E_j) - alpha_m L_g(u_m);  u_m <- solve(alpha_m, beta_m)
 // alpha_m = dt tau_m / min(sweep, M)  (MIN-SR-FLEX).  When last_only, only node M is updated and
-// written (to the state), with a non-finite check.
+// written (to the state), with a non-finite check.  The node count is a template parameter so that
+// the per-node arrays live in registers.
+template <int M>
 __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
@@ -30,9 +32,9 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
     const size_t fs = (size_t)nc * 2;             // field stride in doubles
     const double* un = a.un + (size_t)b * 3 * fs + o;
     const C3 u0 = {ld2(un), ld2(un + fs), ld2(un + 2 * fs)};
-    const int M = a.M;
-    double2 Fphi[kMaxNodes], Fzeta[kMaxNodes], Fdiv[kMaxNodes];
-    double2 Lphi[kMaxNodes], Ldiv[kMaxNodes];      // L_g(u_j) (zeta component is zero)
+    double2 Fphi[M], Fzeta[M], Fdiv[M];
+    double2 Lphi[M], Ldiv[M];                      // L_g(u_j) (zeta component is zero)
+#pragma unroll
     for (int j = 0; j < M; ++j) {
         const double* uj = a.uprev + (size_t)b * a.uprev_member + (size_t)j * a.uprev_node + o;
         const double* ej = a.E + (size_t)b * a.E_member + (size_t)j * a.E_node + o;
@@ -47,9 +49,12 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
     const int sdiv = a.sweep < M ? a.sweep : M;
     const int m_begin = a.last_only ? M - 1 : 0;
     bool bad = false;
-    for (int m = m_begin; m < M; ++m) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if (m < m_begin) continue;
         const double* Qm = a.Q + m * kMaxNodes;
         double2 sp = make_double2(0.0, 0.0), sz = sp, sd = sp;
+#pragma unroll
         for (int j = 0; j < M; ++j) {
             const double qj = Qm[j];
             sp.x += qj * Fphi[j].x; sp.y += qj * Fphi[j].y;
@@ -93,7 +98,16 @@ void launch_update(const UpdateArgs& a, hipStream_t st) {
     // small workgroups: one thread per coefficient leaves few threads, spread them over all CUs
     constexpr int kUpd = 64;
     dim3 grid((a.ncoef + kUpd - 1) / kUpd, a.batch);
-    k_update<<<grid, kUpd, 0, st>>>(a);
+    switch (a.M) {
+    case 1: k_update<1><<<grid, kUpd, 0, st>>>(a); break;
+    case 2: k_update<2><<<grid, kUpd, 0, st>>>(a); break;
+    case 3: k_update<3><<<grid, kUpd, 0, st>>>(a); break;
+    case 4: k_update<4><<<grid, kUpd, 0, st>>>(a); break;
+    case 5: k_update<5><<<grid, kUpd, 0, st>>>(a); break;
+    case 6: k_update<6><<<grid, kUpd, 0, st>>>(a); break;
+    case 7: k_update<7><<<grid, kUpd, 0, st>>>(a); break;
+    default: k_update<8><<<grid, kUpd, 0, st>>>(a); break;
+    }
 }
 
 // Synthesis layout of states [s][3][ncoef]: one thread per (coefficient, state).

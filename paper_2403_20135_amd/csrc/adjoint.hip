@@ -3,7 +3,7 @@
 //
 // f_E(u) = Analysis(Products(Synthesis(u))) has the Jacobian transpose
 //   J^T = Synthesis^T . Products'^T . Analysis^T.
-// * Analysis^T (this file: k_synthesis_adj + the first half of k_grid_adj): the analysis of a grid
+// * Analysis^T (the synthesis kernel in adjoint mode + the first half of k_grid_adj): the analysis of a grid
 //   field is c_nm = sum_j w_j Pbar (1/nlon) DFT_m; its transpose is a synthesis with unit m-weights
 //   scaled per latitude.  For the tendencies zeta_t = -div(A,B), delta_t = curl(A,B) + c_n KE,
 //   Phi'_t = -div(C,D), with div/curl weights g'_j = w_j/(1-mu_j^2):
@@ -22,9 +22,6 @@
 // transposes are written out in k_update_adj.
 #include "common.h"
 
-__device__ __forceinline__ v4d mfma_f64a(double a, double b, v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 __device__ __forceinline__ double2 ld2a(const double* p) { return *(const double2*)p; }
 __device__ __forceinline__ void st2a(double* p, double2 v) { *(double2*)p = v; }
 
@@ -36,7 +33,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_cml_adj(const double* __restric
                                                          const int* __restrict__ n_of,
                                                          const int* __restrict__ m_of,
                                                          const int* __restrict__ rowoff,
-                                                         const double* __restrict__ neg_lap, int ncoef) {
+                                                         const double* __restrict__ neg_lap, int ncoef,
+                                                         int T) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (idx >= ncoef) return;
@@ -50,123 +48,13 @@ __global__ __launch_bounds__(kBlock) void k_prep_cml_adj(const double* __restric
     st2a(o + 2, dv);
     st2a(o + 4, phi);
     st2a(o + 6, make_double2(c * dv.x, c * dv.y));
+    cml_clear_pad(cml, rowoff[2 * mo + par], kk, npk_of(T, mo, par), nstates, s);
 }
 
 void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int* n_of, const int* m_of,
-                         const int* rowoff, const double* neg_lap, int ncoef, hipStream_t st) {
+                         const int* rowoff, const double* neg_lap, int ncoef, int T, hipStream_t st) {
     dim3 grid((ncoef + kBlock - 1) / kBlock, nstates);
-    k_prep_cml_adj<<<grid, kBlock, 0, st>>>(ebar, nstates, cml, n_of, m_of, rowoff, neg_lap, ncoef);
-}
-
-// ---------------------------------------------------------------------------------------------
-// Analysis^T, Legendre part: per (m, latitude tile, 4 states) the sums over n of Pbar and H times
-// (zeta_adj, delta_adj, Phi_adj, c delta_adj); both tables multiply the same 16-wide column tile
-// (2 states x 4 values x (Re, Im)).  Output: Fourier coefficients of A^, B^, C^, D^, E^ at every
-// latitude, halved for m > 0 so that the standard real inverse transform (weights s_m) realises
-// the unit m-weights of the transpose.  Same work split and reduction as the forward synthesis.
-// ---------------------------------------------------------------------------------------------
-constexpr int kAdjAcc = 32;     // doubles per lane: {Pbar, H} x 2 parities x 2 tiles x 4
-
-__global__ __launch_bounds__(kBlock) void k_synthesis_adj(
-    const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
-    const int* __restrict__ rowoff, const int2* __restrict__ tasks, const double* __restrict__ cml,
-    int nstates, double2* __restrict__ four5, Geom g) {
-    __shared__ double lds[4 * kAdjAcc * 64];
-    const int2 task = tasks[blockIdx.x];
-    if (task.x < 0) return;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int m = task.x, jt = task.y;
-    const int S = nstates;
-    const int s0 = blockIdx.y * 4;
-    const int i = lane & 15, q = lane >> 4;
-    const int v = i & 7;
-    v4d acc[8];                       // [(table*2 + p)*2 + tile]
-    for (int k = 0; k < 8; ++k) acc[k] = (v4d){0.0, 0.0, 0.0, 0.0};
-    const int sA = s0 + (i >> 3), sB = s0 + 2 + (i >> 3);
-    const bool okA = sA < S, okB = sB < S;
-    const int offA = (okA ? sA : 0) * kCmlVals + v, offB = (okB ? sB : 0) * kCmlVals + v;
-    for (int p = 0; p < 2; ++p) {
-        const int np = npk_of(g.T, m, p);
-        const int np4 = (np + 3) & ~3;
-        const int steps = np4 > 4 * wave ? (np4 - 4 * wave + 15) / 16 : 0;
-        const double* Pp = P + toff[2 * m + p] + jt * 16 + i + (size_t)(4 * wave + q) * g.nhp;
-        const double* Hp = H + toff[2 * m + p] + jt * 16 + i + (size_t)(4 * wave + q) * g.nhp;
-        const double* Bp = cml + ((size_t)rowoff[2 * m + p] + 4 * wave + q) * S * kCmlVals;
-        const size_t tstep = (size_t)16 * g.nhp, bstep = (size_t)16 * S * kCmlVals;
-        v4d pa = acc[p * 2], pb = acc[p * 2 + 1], ha = acc[4 + p * 2], hb = acc[4 + p * 2 + 1];
-        int kk = 4 * wave + q;
-#pragma unroll 2
-        for (int it = 0; it < steps; ++it) {
-            const bool vn = kk < np;
-            const double ap = Pp[0], ah = Hp[0];
-            const double bA = Bp[offA], bB = Bp[offB];
-            const double xA = (vn && okA) ? bA : 0.0, xB = (vn && okB) ? bB : 0.0;
-            pa = mfma_f64a(ap, xA, pa);
-            pb = mfma_f64a(ap, xB, pb);
-            ha = mfma_f64a(ah, xA, ha);
-            hb = mfma_f64a(ah, xB, hb);
-            Pp += tstep;
-            Hp += tstep;
-            Bp += bstep;
-            kk += 16;
-        }
-        acc[p * 2] = pa;
-        acc[p * 2 + 1] = pb;
-        acc[4 + p * 2] = ha;
-        acc[4 + p * 2 + 1] = hb;
-    }
-    for (int k = 0; k < 8; ++k)
-        for (int r = 0; r < 4; ++r) lds[(wave * kAdjAcc + k * 4 + r) * 64 + lane] = acc[k][r];
-    __syncthreads();
-    double* red = lds;                // [sl 4][north/south 2][value 16][latitude 16]
-    if (wave == 0) {
-        double tot[kAdjAcc];
-        for (int k = 0; k < kAdjAcc; ++k) {
-            double sum = lds[k * 64 + lane];
-            for (int w = 1; w < 4; ++w) sum += lds[(w * kAdjAcc + k) * 64 + lane];
-            tot[k] = sum;
-        }
-        for (int r = 0; r < 4; ++r) {
-            const int latl = 4 * r + q;
-            for (int t = 0; t < 2; ++t) {
-                const int sl = 2 * t + (i >> 3);
-                const double pe = tot[(0 * 2 + t) * 4 + r], po = tot[(1 * 2 + t) * 4 + r];
-                const double he = tot[(4 + 0 * 2 + t) * 4 + r], ho = tot[(4 + 1 * 2 + t) * 4 + r];
-                red[((sl * 2 + 0) * 16 + v) * 16 + latl] = pe + po;
-                red[((sl * 2 + 1) * 16 + v) * 16 + latl] = pe - po;
-                red[((sl * 2 + 0) * 16 + 8 + v) * 16 + latl] = he + ho;
-                red[((sl * 2 + 1) * 16 + 8 + v) * 16 + latl] = ho - he;
-            }
-        }
-    }
-    __syncthreads();
-    const int it = threadIdx.x;
-    if (it >= 128) return;
-    const int sl = it >> 5, ns = (it >> 4) & 1, latl = it & 15;
-    const int s = s0 + sl, jh = jt * 16 + latl;
-    if (s >= S || jh >= g.nh) return;
-    const double* x = red + ((sl * 2 + ns) * 16) * 16 + latl;
-    const double pzr = x[0 * 16], pzi = x[1 * 16], pdr = x[2 * 16], pdi = x[3 * 16];
-    const double ppr = x[4 * 16], ppi = x[5 * 16], pcr = x[6 * 16], pci = x[7 * 16];
-    const double hzr = x[8 * 16], hzi = x[9 * 16], hdr = x[10 * 16], hdi = x[11 * 16];
-    const double hpr = x[12 * 16], hpi = x[13 * 16];
-    const double mm = (double)m, hf = m > 0 ? 0.5 : 1.0;
-    const int j = ns ? g.nlat - 1 - jh : jh;
-    const size_t fstride = (size_t)g.nlat * g.ms;
-    double2* base = four5 + (size_t)s * 5 * fstride + (size_t)j * g.ms + m;
-    base[0] = make_double2(hf * (-mm * pzi + hdr), hf * (mm * pzr + hdi));          // A^
-    base[fstride] = make_double2(hf * (hzr + mm * pdi), hf * (hzi - mm * pdr));     // B^
-    base[2 * fstride] = make_double2(hf * (-mm * ppi), hf * (mm * ppr));            // C^
-    base[3 * fstride] = make_double2(hf * hpr, hf * hpi);                           // D^
-    base[4 * fstride] = make_double2(hf * pcr, hf * pci);                           // E^
-}
-
-void launch_synthesis_adj(const double* P, const double* H, const long long* toff, const int* rowoff,
-                          const int2* tasks, int ntasks, const double* cml, int nstates, double2* four5,
-                          const Geom& g, hipStream_t st) {
-    dim3 grid(ntasks, (nstates + 3) / 4);
-    k_synthesis_adj<<<grid, kBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates, four5, g);
+    k_prep_cml_adj<<<grid, kBlock, 0, st>>>(ebar, nstates, cml, n_of, m_of, rowoff, neg_lap, ncoef, T);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -322,44 +322,45 @@ int setup(sdc_ctx* c) {
     if ((rc = c->alloc(c->tw, cf.nlon))) return rc;
     if ((rc = c->alloc(c->flag, 4))) return rc;
 
-    // task lists.  SWE synthesis: (m, latitude tile) per workgroup; SWE analysis: (m, parity,
-    // 16-row tile) per workgroup.  Both are grouped per block of 8 orders on one XCD (the partial
-    // output lines of neighbouring orders meet in that L2) and issued longest first.
+    // task lists.  SWE synthesis: (order pair index k, first of 4 latitude tiles) per workgroup;
+    // the wave owning tile jt processes the orders k and T - k, T + 2 degrees in all, so every
+    // wave carries the same work.  SWE analysis: (m, parity, first of four 16-row tiles) per
+    // workgroup.  Both are grouped per block of 8 orders on one XCD (the partial output lines of
+    // neighbouring orders meet in that L2) and issued longest first.
     const int ntj = g.nhp / 16, njg = (ntj + 3) / 4;
     {
         std::vector<int2> t;
         std::vector<int> grp;
         std::vector<double> wk;
-        for (int m = 0; m <= g.T; ++m) {
-            const double rows = ((npk_of(g.T, m, 0) + 3) & ~3) + ((npk_of(g.T, m, 1) + 3) & ~3);
-            for (int jt = 0; jt < ntj; ++jt) {
-                t.push_back(make_int2(m, jt));
-                grp.push_back(m / 8);
-                wk.push_back(rows / 4.0 + 8.0);     // chain length per wave + epilogue
+        for (int k = 0; 2 * k <= g.T; ++k)
+            for (int jg = 0; jg < njg; ++jg) {
+                t.push_back(make_int2(k, 4 * jg));
+                grp.push_back(k / 8);
+                wk.push_back((double)(g.T + 2) * (ntj - 4 * jg < 4 ? ntj - 4 * jg : 4));
             }
-        }
         std::vector<int2> ord = xcd_order(t, grp, wk, make_int2(-1, 0));
         c->n_syn = (int)ord.size();
         if ((rc = c->alloc(c->syn_tasks, ord.size()))) return rc;
         HIP_TRY(hipMemcpy(c->syn_tasks, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice));
     }
     {
-        std::vector<int4> t;
+        std::vector<int4> t, sw;
         std::vector<int> grp;
         std::vector<double> wk;
         for (int m = 0; m <= g.T; ++m)
-            for (int p = 0; p < 2; ++p)
-                for (int kk = 0; kk < npk_of(g.T, m, p); kk += 16) {
+            for (int p = 0; p < 2; ++p) {
+                const int np = npk_of(g.T, m, p);
+                for (int kk = 0; kk < np; kk += 64) {
                     t.push_back(make_int4(m, p, kk, 1));
                     grp.push_back(m / 8);
-                    wk.push_back(1.0);
+                    wk.push_back((double)((np - kk < 64 ? np - kk : 64) + 15) / 16.0 + 0.5);
                 }
+                for (int kk = 0; kk < np; kk += 16) sw.push_back(make_int4(m, p, kk, 0));
+            }
         std::vector<int4> ord = xcd_order(t, grp, wk, make_int4(0, 0, 0, 0));
         c->n_ana_wg = (int)ord.size();
         if ((rc = c->alloc(c->ana_tasks, ord.size()))) return rc;
         HIP_TRY(hipMemcpy(c->ana_tasks, ord.data(), ord.size() * sizeof(int4), hipMemcpyHostToDevice));
-        std::vector<int4> sw;
-        for (auto& w : t) sw.push_back(make_int4(w.x, w.y, w.z, 0));
         c->n_sana = (int)sw.size();
         if ((rc = c->alloc(c->sana_tasks, sw.size()))) return rc;
         HIP_TRY(hipMemcpy(c->sana_tasks, sw.data(), sw.size() * sizeof(int4), hipMemcpyHostToDevice));
@@ -424,14 +425,14 @@ void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr) {
 
 void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2* save = nullptr) {
     const long t = c->begin(SDC_KERNEL_UPDATE);
-    launch_prep_cml(states, S, c->cml, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->st);
+    launch_prep_cml(states, S, c->cml, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->g.T, c->st);
     c->end(SDC_KERNEL_UPDATE, t);
     run_explicit_cml(c, S, out, save);
 }
 
 // out_acc += J_E(u)^T ebar for S states whose stage grid fields are in `save`.
 void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save, double* out_acc) {
-    launch_prep_cml_adj(ebar, S, c->cml, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->st);
+    launch_prep_cml_adj(ebar, S, c->cml, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->g.T, c->st);
     launch_synthesis_adj(c->P, c->H, c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->adj_four5,
                          c->g, c->st);
     launch_grid_adj(c->adj_four5, save, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
@@ -554,6 +555,7 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
     a.M = M;
     a.batch = B;
     a.ncoef = c->g.ncoef;
+    a.T = c->g.T;
     a.uprev = state;
     a.uprev_node = 0;
     a.uprev_member = fs;
@@ -672,6 +674,7 @@ int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1,
     a.M = M;
     a.batch = B;
     a.ncoef = c->g.ncoef;
+    a.T = c->g.T;
     a.uprev = c->adj_x;
     a.uprev_node = 0;
     a.uprev_member = fs;

@@ -50,6 +50,17 @@ __host__ __device__ inline int npk_of(int T, int m, int p) { return (T - m + 2 -
 // (m, p, kk) and state s, 8 doubles (zeta, Phi', psi, chi) x (Re, Im) with psi, chi the inverse
 // Laplacians of zeta and delta:  cml[((rowoff[2m+p] + kk) * S + s) * 8 + v].
 constexpr int kCmlVals = 8;
+// Rows np..np4-1 of every (m, parity) block are padding; each producer of the layout zeroes them
+// for the states it writes (the thread of the block's last real row does it), so that the
+// synthesis contracts whole 4-row steps without masks.
+__device__ inline void cml_clear_pad(double* cml, size_t row0, int kk, int np, size_t S, size_t s) {
+    if (kk != np - 1) return;
+    const int np4 = (np + 3) & ~3;
+    for (int r = np; r < np4; ++r) {
+        double2* c = (double2*)(cml + ((row0 + r) * S + s) * kCmlVals);
+        for (int k = 0; k < kCmlVals / 2; ++k) c[k] = make_double2(0.0, 0.0);
+    }
+}
 // Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V, layout
 // four[s][field][lat][m].
 constexpr int kSynFields = 4;
@@ -124,12 +135,12 @@ struct UpdateArgs {
     const int* n_of;           // degree of every coefficient
     int* flag;                 // set to 1 on a non-finite output (last_only only)
     double dt, phibar, inv_a2;
-    int M, sweep, last_only, batch, ncoef;
+    int M, sweep, last_only, batch, ncoef, T;
 };
 void launch_update(const UpdateArgs& a, hipStream_t st);
 // Synthesis layout of `batch` states [b][3][ncoef] (the first f_E of a step, eval_explicit).
 void launch_prep_cml(const double* state, int nstates, double* cml, const int* n_of,
-                     const int* m_of, const int* rowoff, const double* inv_lap, int ncoef,
+                     const int* m_of, const int* rowoff, const double* inv_lap, int ncoef, int T,
                      hipStream_t st);
 void launch_implicit(const double* u, double* fI, const int* n_of, double phibar, double inv_a2,
                      int batch, int ncoef, hipStream_t st);
@@ -138,7 +149,7 @@ void launch_solve(double alpha, const double* beta, double* u, const int* n_of, 
 
 // adjoint.hip
 void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int* n_of, const int* m_of,
-                         const int* rowoff, const double* neg_lap, int ncoef, hipStream_t st);
+                         const int* rowoff, const double* neg_lap, int ncoef, int T, hipStream_t st);
 void launch_synthesis_adj(const double* P, const double* H, const long long* toff, const int* rowoff,
                           const int2* tasks, int ntasks, const double* cml, int nstates, double2* four5,
                           const Geom& g, hipStream_t st);

@@ -1,4 +1,4 @@
-// Legendre transforms as FP64 MFMA contractions (gfx950, v_mfma_f64_16x16x4).
+// Legendre transforms as FP64 MFMA contractions (gfx950, v_mfma_f64_16x16x4f64).
 //
 // For every zonal wavenumber m the Legendre part of the spherical-harmonic transform is a
 // small dense product between a table (latitudes x degrees n) and a few coefficient columns.
@@ -9,133 +9,202 @@
 // MFMA operand layout (64 lanes, lane l, i = l % 16, q = l / 16):
 //   A[i][q] (16x4), B[q][i] (4x16); the FP64 accumulator of lane l holds D[4r + q][i], r = 0..3
 //   (rows interleaved across the four lane groups).
+//
+// Both SWE kernels give every wave one whole contraction (no partial sums across waves, no LDS),
+// keep several 4-row (synthesis) or 16-latitude (analysis) operand stages in flight in registers,
+// and place the columns of their tiles so that every output is formed from values the lane
+// already holds.
 #include "common.h"
 
 constexpr int kAnaForward = 0, kAnaAdjoint = 1;
+constexpr int kSynForward = 0, kSynAdjoint = 1;
 
 __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ v4d zero4() { return (v4d){0.0, 0.0, 0.0, 0.0}; }
 
 // ---------------------------------------------------------------------------------------------
-// Synthesis for the shallow-water explicit tendency.  Per state the inputs are the spectral
-// fields in the coefficient-major layout (zeta, Phi', psi, chi), psi = -a^2 zeta/(n(n+1)),
-// chi = -a^2 delta/(n(n+1)); the outputs are the Fourier coefficients, at every latitude, of
-//   zeta, Phi', U = (1/a) sum_n [i m chi Pbar - psi H], V = (1/a) sum_n [i m psi Pbar + chi H].
-// Columns of one 16-wide Pbar tile: 2 states x (zeta, Phi', psi, chi) x (Re, Im); of the H tile:
-// 4 states x (psi, chi) x (Re, Im).  A workgroup owns (m, one 16-latitude tile, 4 states); its 4
-// waves take every fourth 4-row step of the degree loop (both parities), so the longest chain
-// (m = 0) is a quarter of the degrees, and the partial tiles are summed in LDS in a fixed order.
+// Synthesis (forward SWE and the transposed analysis of the adjoint).
+//
+// A wave owns one 16-latitude tile, 4 states, and the pair of orders (m, T - m): the two chains
+// together always hold T + 2 degrees, so all waves carry the same work.  Per order the degree loop
+// runs both parities at once in 4-row steps (the parity-0 chain is at most one step longer).
+//
+// Column tiles: 16 columns = 4 states x 4 values (lane column i: state i >> 2, value v = i & 3).
+// Forward, Fourier fields (zeta, Phi', U, V), cml values (zeta, Phi', psi, chi) x (Re, Im):
+//   tile 0 (Pbar): zeta re, zeta im, Phi' re, Phi' im        -> cml value v
+//   tile 1 (Pbar): chi im, chi re, psi im, psi re            -> cml value 7 - v
+//   tile 2 (H):    psi re, psi im, chi re, chi im            -> cml value 4 + v
+// so that U = (1/a)(i m chi Pbar - psi H) and V = (1/a)(i m psi Pbar + chi H) are lane-local:
+//   (U re, U im, V re, V im)[v] = ((v odd ? m : -m) tile1 + (v < 2 ? -1 : 1) tile2) / a.
+// Adjoint, fields (A^, B^, C^, D^, E^), cml values (zeta, delta, Phi, c_n delta)_adj x (Re, Im):
+//   A^ = i m Pbar.zeta + H.delta,  B^ = H.zeta - i m Pbar.delta,  C^ = i m Pbar.Phi,
+//   D^ = H.Phi,  E^ = Pbar.(c delta), all halved for m > 0;
+//   tile 0 (Pbar): zeta im, zeta re, delta im, delta re      -> v ^ 1
+//   tile 1 (H):    delta re, delta im, zeta re, zeta im      -> v ^ 2
+//   tile 2 (Pbar): Phi im, Phi re, c delta re, c delta im    -> v < 2 ? 5 - v : 4 + v
+//   tile 3 (H):    Phi re, Phi im, (unused), (unused)        -> 4 + (v & 1)
+// Rows of the table past n = T are zero, and so are the matching rows of the cml input (written
+// by its producers), so no row needs masking; columns of absent states read state S-1 and are
+// dropped.
 // ---------------------------------------------------------------------------------------------
-constexpr int kSynAcc = 24;      // doubles per lane: Pbar 2 parities x 2 tiles x 4, H 2 parities x 4
+template <int MODE> struct SynTiles;
+template <> struct SynTiles<kSynForward> {
+    static constexpr int NT = 3, NF = kSynFields, D = 6;
+    __device__ static constexpr bool is_h(int t) { return t == 2; }
+    __device__ static int col(int t, int v) { return t == 0 ? v : (t == 1 ? 7 - v : 4 + v); }
+};
+template <> struct SynTiles<kSynAdjoint> {
+    static constexpr int NT = 4, NF = 5, D = 5;
+    __device__ static constexpr bool is_h(int t) { return t == 1 || t == 3; }
+    __device__ static int col(int t, int v) {
+        return t == 0 ? (v ^ 1) : (t == 1 ? (v ^ 2) : (t == 2 ? (v < 2 ? 5 - v : 4 + v) : 4 + (v & 1)));
+    }
+};
 
-__global__ __launch_bounds__(kBlock) void k_synthesis_swe(
+template <int NT> struct SynStage {
+    double a[2][2];          // [parity][Pbar, H]
+    double b[2][NT];         // [parity][tile]
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_synthesis(
     const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
     const int* __restrict__ rowoff, const int2* __restrict__ tasks, const double* __restrict__ cml,
-    int nstates, double2* __restrict__ four, Geom g) {
-    // partial accumulators [wave][value][lane]; then (aliased) the parity-combined tile
-    // red[state][north/south][value][latitude]
-    __shared__ double lds[4 * kSynAcc * 64];
+    int nstates, double* __restrict__ four, Geom g) {
+    using TL = SynTiles<MODE>;
+    constexpr int NT = TL::NT, D = TL::D;
     const int2 task = tasks[blockIdx.x];
-    if (task.x < 0) return;                          // padding workgroup (uniform)
-    const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int m = task.x, jt = task.y;
+    const int jt = task.y + wave;
+    if (task.x < 0 || jt * 16 >= g.nhp) return;          // padding workgroup, tile past the end
+    const int lane = threadIdx.x & 63, i = lane & 15, q = lane >> 4, v = i & 3;
     const int S = nstates;
-    const int s0 = blockIdx.y * 4;
-    const int i = lane & 15, q = lane >> 4;
-    const int vP = i & 7, vH = i & 3;
-
-    v4d acc[6];                                       // [p*3 + {Pbar tile 0, Pbar tile 1, H}]
-    for (int k = 0; k < 6; ++k) acc[k] = (v4d){0.0, 0.0, 0.0, 0.0};
-    {
-        // column -> state; out-of-range states read a valid address and are zeroed by a select
-        const int sP0 = s0 + (i >> 3), sP1 = s0 + 2 + (i >> 3), sH = s0 + (i >> 2);
-        const bool ok0 = sP0 < S, ok1 = sP1 < S, okh = sH < S;
-        const int c0off = (ok0 ? sP0 : 0) * kCmlVals + vP;
-        const int c1off = (ok1 ? sP1 : 0) * kCmlVals + vP;
-        const int choff = (okh ? sH : 0) * kCmlVals + 4 + vH;
-        for (int p = 0; p < 2; ++p) {
-            const int np = npk_of(g.T, m, p);
-            const int np4 = (np + 3) & ~3;
-            // this wave takes the 4-row steps 4*wave, 4*wave + 16, ... of parity p
-            const int steps = np4 > 4 * wave ? (np4 - 4 * wave + 15) / 16 : 0;   // uniform
-            const double* Pp = P + toff[2 * m + p] + jt * 16 + i + (size_t)(4 * wave + q) * g.nhp;
-            const double* Hp = H + toff[2 * m + p] + jt * 16 + i + (size_t)(4 * wave + q) * g.nhp;
-            const double* Bp = cml + ((size_t)rowoff[2 * m + p] + 4 * wave + q) * S * kCmlVals;
-            const size_t tstep = (size_t)16 * g.nhp, bstep = (size_t)16 * S * kCmlVals;
-            v4d c0 = acc[p * 3], c1 = acc[p * 3 + 1], ch = acc[p * 3 + 2];
-            int kk = 4 * wave + q;
-#pragma unroll 2
-            for (int it = 0; it < steps; ++it) {
-                const bool vn = kk < np;
-                const double ap = Pp[0], ah = Hp[0];
-                const double b0 = Bp[c0off], b1 = Bp[c1off], bh = Bp[choff];
-                c0 = mfma_f64(ap, (vn && ok0) ? b0 : 0.0, c0);
-                c1 = mfma_f64(ap, (vn && ok1) ? b1 : 0.0, c1);
-                ch = mfma_f64(ah, (vn && okh) ? bh : 0.0, ch);
-                Pp += tstep;
-                Hp += tstep;
-                Bp += bstep;
-                kk += 16;
-            }
-            acc[p * 3] = c0;
-            acc[p * 3 + 1] = c1;
-            acc[p * 3 + 2] = ch;
-        }
-    }
-    for (int k = 0; k < 6; ++k)
-        for (int r = 0; r < 4; ++r) lds[(wave * kSynAcc + k * 4 + r) * 64 + lane] = acc[k][r];
-    __syncthreads();
-    double* red = lds;                                // [sl][ns][12][16], written by wave 0 only
-    if (wave == 0) {
-        double tot[kSynAcc];
-        for (int v = 0; v < kSynAcc; ++v) {
-            double sum = lds[v * 64 + lane];
-            for (int w = 1; w < 4; ++w) sum += lds[(w * kSynAcc + v) * 64 + lane];
-            tot[v] = sum;
-        }
-        // north = even + odd; south = even - odd (Pbar) and odd - even (H)
-        for (int r = 0; r < 4; ++r) {
-            const int latl = 4 * r + q;
-            for (int t = 0; t < 2; ++t) {
-                const double e = tot[t * 4 + r], o = tot[12 + t * 4 + r];
-                const int sl = 2 * t + (i >> 3);
-                red[((sl * 2 + 0) * 12 + vP) * 16 + latl] = e + o;
-                red[((sl * 2 + 1) * 12 + vP) * 16 + latl] = e - o;
-            }
-            const double e = tot[8 + r], o = tot[20 + r];
-            red[(((i >> 2) * 2 + 0) * 12 + 8 + vH) * 16 + latl] = e + o;
-            red[(((i >> 2) * 2 + 1) * 12 + 8 + vH) * 16 + latl] = o - e;
-        }
-    }
-    __syncthreads();
-    const int it = threadIdx.x;                       // (state, north/south, latitude): 128 items
-    if (it >= 128) return;
-    const int sl = it >> 5, ns = (it >> 4) & 1, latl = it & 15;
-    const int s = s0 + sl, jh = jt * 16 + latl;
-    if (s >= S || jh >= g.nh) return;
+    const int s = blockIdx.y * 4 + (i >> 2);
+    const int sc = s < S ? s : S - 1;
+    // 32-bit byte offsets from per-order (uniform) base addresses keep one VGPR per address
+    unsigned boff[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * 8u;
+    const unsigned rstride = (unsigned)S * kCmlVals * 8u;           // bytes per cml row
+    const unsigned tstep = 4u * g.nhp * 8u, cstep = 4u * rstride;   // bytes per 4-row step
+    const unsigned tlane = ((unsigned)q * g.nhp + jt * 16 + i) * 8u, clane = (unsigned)q * rstride;
+    const size_t fstride = (size_t)2 * g.nlat * g.ms;               // doubles per Fourier field
     const double inva = 1.0 / g.radius;
-    const double mm = (double)m;
-    const double* v = red + ((sl * 2 + ns) * 12) * 16 + latl;
-    const double ppr = v[4 * 16], ppi = v[5 * 16];    // Pbar psi
-    const double pcr = v[6 * 16], pci = v[7 * 16];    // Pbar chi
-    const double hpr = v[8 * 16], hpi = v[9 * 16];    // H psi
-    const double hcr = v[10 * 16], hci = v[11 * 16];  // H chi
-    const int j = ns ? g.nlat - 1 - jh : jh;
-    const size_t fstride = (size_t)g.nlat * g.ms;
-    double2* base = four + (size_t)s * kSynFields * fstride + (size_t)j * g.ms + m;
-    base[0] = make_double2(v[0 * 16], v[1 * 16]);
-    base[fstride] = make_double2(v[2 * 16], v[3 * 16]);
-    base[2 * fstride] = make_double2((-mm * pci - hpr) * inva, (mm * pcr - hpi) * inva);
-    base[3 * fstride] = make_double2((-mm * ppi + hcr) * inva, (mm * ppr + hci) * inva);
+
+    for (int pass = 0; pass < 2; ++pass) {
+        const int m = pass == 0 ? task.x : g.T - task.x;
+        if (pass == 1 && m <= task.x) break;                // uniform
+        const int n0 = (npk_of(g.T, m, 0) + 3) >> 2, n1 = (npk_of(g.T, m, 1) + 3) >> 2;
+        const char* tb[2][2];
+        const char* cb[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            tb[p][0] = (const char*)(P + toff[2 * m + p]);
+            tb[p][1] = (const char*)(H + toff[2 * m + p]);
+            cb[p] = (const char*)(cml + (size_t)rowoff[2 * m + p] * S * kCmlVals);
+        }
+        v4d acc[2][NT];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[p][t] = zero4();
+        SynStage<NT> st[D];
+        auto ldd = [](const char* base, unsigned off) { return *(const double*)(base + off); };
+        auto load = [&](SynStage<NT>& x, int j) {
+            const unsigned ot = tlane + (unsigned)j * tstep, oc = clane + (unsigned)j * cstep;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                x.a[p][0] = ldd(tb[p][0], ot);
+                x.a[p][1] = ldd(tb[p][1], ot);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) x.b[p][t] = ldd(cb[p], oc + boff[t]);
+            }
+        };
+        auto compute = [&](const SynStage<NT>& x) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[p][t] = mfma_f64(x.a[p][TL::is_h(t) ? 1 : 0], x.b[p][t], acc[p][t]);
+        };
+        // Loads past the chain's end re-read its last step (cache hits, results unused): a
+        // branch-free loop body lets every stage wait for its own loads only.
+        if (n1 > 0) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) load(st[u], u < n1 ? u : n1 - 1);
+            int j0 = 0;
+            for (; j0 + D <= n1; j0 += D) {
+#pragma unroll
+                for (int u = 0; u < D; ++u) {
+                    compute(st[u]);
+                    const int jn = j0 + u + D;
+                    load(st[u], jn < n1 ? jn : n1 - 1);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < D; ++u)
+                if (u < n1 - j0) compute(st[u]);
+        }
+        if (n0 > n1) {                                      // last parity-0 step
+            const unsigned ot = tlane + (unsigned)n1 * tstep, oc = clane + (unsigned)n1 * cstep;
+            const double a0 = ldd(tb[0][0], ot), a1 = ldd(tb[0][1], ot);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                acc[0][t] = mfma_f64(TL::is_h(t) ? a1 : a0, ldd(cb[0], oc + boff[t]), acc[0][t]);
+        }
+
+        // north = even + odd; south = even - odd (Pbar tiles), odd - even (H tiles)
+        const double mm = (double)m;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int jh = jt * 16 + 4 * r + q;
+            if (s >= S || jh >= g.nh) continue;
+#pragma unroll
+            for (int ns = 0; ns < 2; ++ns) {
+                const int j = ns ? g.nlat - 1 - jh : jh;
+                double val[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const double e = acc[0][t][r], o = acc[1][t][r];
+                    val[t] = ns == 0 ? e + o : (TL::is_h(t) ? o - e : e - o);
+                }
+                double* base = four + (((size_t)s * TL::NF * g.nlat + j) * g.ms + m) * 2 + (v & 1);
+                if constexpr (MODE == kSynForward) {
+                    base[(size_t)(v >> 1) * fstride] = val[0];
+                    const double sx = (v & 1) ? mm : -mm, sh = v < 2 ? -1.0 : 1.0;
+                    base[(size_t)(2 + (v >> 1)) * fstride] = (sx * val[1] + sh * val[2]) * inva;
+                } else {
+                    const double hf = m > 0 ? 0.5 : 1.0;
+                    const double sx = (v == 0 || v == 3) ? -mm : mm;
+                    base[(size_t)(v >> 1) * fstride] = hf * (sx * val[0] + val[1]);
+                    if (v < 2) {
+                        base[2 * fstride] = hf * ((v ? mm : -mm) * val[2]);
+                        base[3 * fstride] = hf * val[3];
+                    } else {
+                        base[4 * fstride] = hf * val[2];
+                    }
+                }
+            }
+        }
+    }
 }
 
 void launch_synthesis_swe(const double* P, const double* H, const long long* toff,
                           const int* rowoff, const int2* tasks, int ntasks, const double* cml,
                           int nstates, double2* four, const Geom& g, hipStream_t st) {
     dim3 grid(ntasks, (nstates + 3) / 4);
-    k_synthesis_swe<<<grid, kBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates, four, g);
+    k_synthesis<kSynForward><<<grid, kBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates,
+                                                       (double*)four, g);
+}
+
+void launch_synthesis_adj(const double* P, const double* H, const long long* toff, const int* rowoff,
+                          const int2* tasks, int ntasks, const double* cml, int nstates, double2* four5,
+                          const Geom& g, hipStream_t st) {
+    dim3 grid(ntasks, (nstates + 3) / 4);
+    k_synthesis<kSynAdjoint><<<grid, kBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates,
+                                                       (double*)four5, g);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -147,30 +216,48 @@ void launch_synthesis_swe(const double* P, const double* H, const long long* tof
 //   zeta_adj += Pbar.col0 + (-a^2/(n(n+1))) (Pbar.col1 + H.col4'),
 //   delta_adj += (-a^2/(n(n+1))) (Pbar.col2 + H.col5'),  Phi'_adj += Pbar.col3
 // (col4', col5' stored in the H slots of kinds 1 and 2).
-// A workgroup owns (m, parity, 16 consecutive rows n, 4 states); its 4 waves take every fourth
-// 16-latitude block of the contraction and the partial tiles are summed in LDS in a fixed order.
-// Tile columns: 2 states x (zeta, delta, KE, Phi') x (Re, Im).
+//
+// A workgroup owns (m, parity, 64 consecutive rows n, 4 states); wave w takes the 16-row tile w
+// and all 4 states (two 16-column tiles: 2 states x (zeta, delta, KE, Phi') x (Re, Im)), and
+// contracts over all latitudes in 16-latitude blocks.  The columns of a block (16 latitudes x 4
+// states x 14 values) are loaded once per workgroup into LDS (double-buffered, one barrier per
+// block) and read by all four waves; the table rows stream through D register stages per wave.
+// The Pbar and H products of one column accumulate in the same lane (the H product of a kind
+// without an H part is formed from another column and dropped), so every output except the KE
+// term of delta (one lane to the right) is lane-local.
 // ---------------------------------------------------------------------------------------------
+constexpr int kAnaLat = 4 * kAnaVals + 2;       // LDS doubles per latitude (padded: no conflicts)
+constexpr int kAnaBuf = 16 * kAnaLat;           // doubles per LDS block buffer
+constexpr int kAnaChunks = 16 * 2 * kAnaVals;   // double2 chunks per block (16 lat x 4 states x 7)
+
+struct AnaStage {
+    v4d aP, aH;              // table rows, 4 consecutive latitudes per lane group
+};
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
     const int4* __restrict__ tasks, const double* __restrict__ G, int nstates,
     const double* __restrict__ nscale, double* __restrict__ out, Geom g) {
-    __shared__ double lds[3 * 8 * 64];
+    constexpr int D = 4;
+    __shared__ __align__(16) double gl[2][kAnaBuf + 2];       // + a dummy slot for idle threads
     const int4 task = tasks[blockIdx.x];
-    if (task.w == 0) return;                             // padding workgroup (uniform)
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int m = task.x, p = task.y, kk0 = task.z;
-    const int S = nstates;
+    if (task.w == 0) return;                                 // padding workgroup (uniform)
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m = task.x, p = task.y;
+    const int kt = task.z + 16 * wave;
+    const int S = nstates, s0 = blockIdx.y * 4;
+    const int nsg = S - s0 < 4 ? S - s0 : 4;                 // states in this group
     const int np = npk_of(g.T, m, p);
+    const bool active = kt < np;                             // wave-uniform
+    const int lane = tid & 63, i = lane & 15, q = lane >> 4;
     const int np4 = (np + 3) & ~3;
-    const int s0 = blockIdx.y * 4;
-    const int i = lane & 15, q = lane >> 4;
-    const int kr = kk0 + i;
-    const bool rowok = kr < np4;
-    const double* Pr = P + toff[2 * m + p] + (size_t)(rowok ? kr : 0) * g.nhp + 4 * q;
-    const double* Hr = H + toff[2 * m + p] + (size_t)(rowok ? kr : 0) * g.nhp + 4 * q;
+    // rows past the block's end read its last row; their outputs are dropped
+    const int kr = kt + i < np4 ? kt + i : np4 - 1;
+    const double* Pr = P + toff[2 * m + p] + (size_t)kr * g.nhp + 4 * q;
+    const double* Hr = H + toff[2 * m + p] + (size_t)kr * g.nhp + 4 * q;
+    const int nb = g.nhp >> 4;
 
     // forward kinds: 0 zeta 1 delta 2 KE 3 Phi'; adjoint kinds: 0 zeta 1 zeta (via psi)
     // 2 delta (via chi) 3 Phi'
@@ -178,81 +265,114 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const bool has_h = MODE == kAnaForward ? kind != 2 : (kind == 1 || kind == 2);
     const int cH = (MODE == kAnaForward ? (kind == 0 ? 8 : (kind == 1 ? 10 : 12))
                                         : (kind == 1 ? 8 : 10)) + re;
-    const size_t jstride = (size_t)S * kAnaVals;
-    const double* gb = G + (size_t)(m * 2 + p) * g.nhp * jstride + 4 * q * jstride;
-    bool okP[2], okH[2];
     int offP[2], offH[2];
+#pragma unroll
     for (int t = 0; t < 2; ++t) {
-        const int s = s0 + 2 * t + (i >> 3);
-        okP[t] = s < S;
-        okH[t] = okP[t] && has_h;
-        offP[t] = (okP[t] ? s : 0) * kAnaVals + v;
-        offH[t] = (okP[t] ? s : 0) * kAnaVals + cH;
+        int sl = 2 * t + (i >> 3);
+        sl = sl < nsg ? sl : nsg - 1;                        // absent states: column dropped
+        offP[t] = sl * kAnaVals + v;
+        offH[t] = sl * kAnaVals + (has_h ? cH : v);
     }
-    v4d acc0 = (v4d){0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-    // this wave takes latitude blocks 16*wave, 16*wave + 64, ...; the next block's operands are
-    // loaded into the alternate register set while the current one is contracted
-    const int steps = g.nhp > 16 * wave ? (g.nhp - 16 * wave + 63) / 64 : 0;   // uniform
-    v4d A_ap, A_ah, B_ap, B_ah;
-    double A_b[16], B_b[16];
-#define ANA_LOAD(X, it)                                                                \
-    {                                                                                  \
-        int it_ = (it) < steps ? (it) : steps - 1;  /* clamp: valid, result unused */ \
-        const int jh0_ = 16 * wave + 64 * it_;                                         \
-        X##_ap = *(const v4d*)(Pr + jh0_);                                             \
-        X##_ah = *(const v4d*)(Hr + jh0_);                                             \
-        const double* go_ = gb + (size_t)jh0_ * jstride;                               \
-        _Pragma("unroll") for (int qq = 0; qq < 4; ++qq) {                             \
-            const double* gq_ = go_ + qq * jstride;                                    \
-            X##_b[4 * qq + 0] = gq_[offP[0]];                                          \
-            X##_b[4 * qq + 1] = gq_[offH[0]];                                          \
-            X##_b[4 * qq + 2] = gq_[offP[1]];                                          \
-            X##_b[4 * qq + 3] = gq_[offH[1]];                                          \
-        }                                                                              \
+
+    // cooperative copy of a G block into LDS: thread tid moves chunks tid and tid + 256
+    const size_t jstride = (size_t)S * kAnaVals;
+    const double* gsrc = G + (size_t)(m * 2 + p) * g.nhp * jstride + (size_t)s0 * kAnaVals;
+    int clat[2], cw[2], cdst[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int c = tid + kBlock * k;
+        clat[k] = c / (2 * kAnaVals);
+        cw[k] = c % (2 * kAnaVals);
+        const bool ok = c < kAnaChunks && cw[k] < nsg * (kAnaVals / 2);
+        if (!ok) { clat[k] = 0; cw[k] = 0; }
+        cdst[k] = ok ? clat[k] * kAnaLat + 2 * cw[k] : kAnaBuf;   // idle: the dummy slot
     }
-#define ANA_COMPUTE(X, it)                                                             \
-    { /* a step past the end (odd step count) runs on zeroed operands: no branch */     \
-        const bool live_ = (it) < steps;                                               \
-        const int jh0_ = 16 * wave + 64 * (it);                                        \
-        _Pragma("unroll") for (int qq = 0; qq < 4; ++qq) {                             \
-            const bool jok = live_ && jh0_ + 4 * q + qq < g.nh;  /* padded rows unused */ \
-            const double a_ = rowok ? X##_ap[qq] : 0.0, h_ = rowok ? X##_ah[qq] : 0.0;  \
-            acc0 = mfma_f64(a_, (jok && okP[0]) ? X##_b[4 * qq + 0] : 0.0, acc0);        \
-            acc0 = mfma_f64(h_, (jok && okH[0]) ? X##_b[4 * qq + 1] : 0.0, acc0);        \
-            acc1 = mfma_f64(a_, (jok && okP[1]) ? X##_b[4 * qq + 2] : 0.0, acc1);        \
-            acc1 = mfma_f64(h_, (jok && okH[1]) ? X##_b[4 * qq + 3] : 0.0, acc1);        \
-        }                                                                              \
-    }
-    if (steps > 0) {
-        ANA_LOAD(A, 0)
-        for (int it = 0; it < steps; it += 2) {
-            ANA_LOAD(B, it + 1)
-            ANA_COMPUTE(A, it)
-            ANA_LOAD(A, it + 2)
-            ANA_COMPUTE(B, it + 1)
+    auto gload = [&](double2 (&r)[2], int b) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            int jh = 16 * b + clat[k];
+            jh = jh < g.nh ? jh : g.nh - 1;
+            r[k] = *(const double2*)(gsrc + (size_t)jh * jstride + 2 * cw[k]);
         }
-    }
-#undef ANA_LOAD
-#undef ANA_COMPUTE
-    if (wave > 0)
-        for (int r = 0; r < 4; ++r) {
-            lds[((wave - 1) * 8 + r) * 64 + lane] = acc0[r];
-            lds[((wave - 1) * 8 + 4 + r) * 64 + lane] = acc1[r];
+    };
+    // latitudes past nh are stored as zeros (their table entries are zero as well)
+    // (no branches: a load sunk into a branch would wait for every load in flight)
+    auto gstore = [&](const double2 (&r)[2], int b, int buf) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const bool live = 16 * b + clat[k] < g.nh;
+            *(double2*)&gl[buf][cdst[k]] = live ? r[k] : make_double2(0.0, 0.0);
         }
+    };
+
+    v4d accP[2] = {zero4(), zero4()}, accH[2] = {zero4(), zero4()};
+    auto load = [&](AnaStage& x, int b) {
+        x.aP = *(const v4d*)(Pr + 16 * b);
+        x.aH = *(const v4d*)(Hr + 16 * b);
+    };
+    // k-step qq of a block contracts latitude 4 q + qq of the block (lane group q)
+    auto compute = [&](const AnaStage& x, const double* lb) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const double* lq = lb + (4 * q + qq) * kAnaLat;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                accP[t] = mfma_f64(x.aP[qq], lq[offP[t]], accP[t]);
+                accH[t] = mfma_f64(x.aH[qq], lq[offH[t]], accH[t]);
+            }
+        }
+    };
+
+    double2 gr[2];
+    gload(gr, 0);
+    gstore(gr, 0, 0);
     __syncthreads();
-    if (wave != 0) return;
-    for (int w = 0; w < 3; ++w)
-        for (int r = 0; r < 4; ++r) {
-            acc0[r] += lds[(w * 8 + r) * 64 + lane];
-            acc1[r] += lds[(w * 8 + 4 + r) * 64 + lane];
+    if (active) {
+        AnaStage st[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) load(st[u], u < nb ? u : nb - 1);
+        int b0 = 0;
+        for (; b0 + D <= nb; b0 += D) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const int b = b0 + u;
+                gload(gr, b + 1 < nb ? b + 1 : nb - 1);
+                compute(st[u], gl[b & 1]);
+                const int bn = b + D;
+                load(st[u], bn < nb ? bn : nb - 1);          // past the end: re-read, unused
+                gstore(gr, b + 1, (b + 1) & 1);
+                __syncthreads();
+            }
         }
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int b = b0 + u;
+            if (b < nb) {                                    // uniform
+                gload(gr, b + 1 < nb ? b + 1 : nb - 1);
+                compute(st[u], gl[b & 1]);
+                gstore(gr, b + 1, (b + 1) & 1);
+                __syncthreads();
+            }
+        }
+    } else {
+        // rows past the order's end: this wave only helps move the columns
+        for (int b = 0; b < nb; ++b) {
+            gload(gr, b + 1 < nb ? b + 1 : nb - 1);
+            gstore(gr, b + 1, (b + 1) & 1);
+            __syncthreads();
+        }
+        return;
+    }
+
     const int cb = coef_offset(g.T, m) - m;
+#pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int s = s0 + 2 * t + (i >> 3);
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double val = t == 0 ? acc0[r] : acc1[r];
-            const double right = __shfl_down(val, 2, 64);   // the kind one to the right
-            const int kk = kk0 + 4 * r + q;
+            const double val = has_h ? accP[t][r] + accH[t][r] : accP[t][r];
+            const double right = __shfl_down(val, 2, 64);    // the kind one to the right
+            const int kk = kt + 4 * r + q;
             if (kk >= np || s >= S) continue;
             const int n = m + p + 2 * kk;
             if constexpr (MODE == kAnaForward) {

@@ -85,6 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
             st2(c + 2, phi);
             st2(c + 4, make_double2(il * bzeta.x, il * bzeta.y));
             st2(c + 6, make_double2(il * dv.x, il * dv.y));
+            cml_clear_pad(a.cml, a.rowoff[2 * mo + par], kk, npk_of(a.T, mo, par), S, (size_t)b * M + m);
         }
         if (a.last_only) {
             bad = !(isfinite(phi.x) && isfinite(phi.y) && isfinite(bzeta.x) && isfinite(bzeta.y) &&
@@ -116,7 +117,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_cml(const double* __restrict__ 
                                                      const int* __restrict__ n_of,
                                                      const int* __restrict__ m_of,
                                                      const int* __restrict__ rowoff,
-                                                     const double* __restrict__ inv_lap, int ncoef) {
+                                                     const double* __restrict__ inv_lap, int ncoef,
+                                                     int T) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (idx >= ncoef) return;
@@ -130,13 +132,14 @@ __global__ __launch_bounds__(kBlock) void k_prep_cml(const double* __restrict__ 
     st2(c + 2, phi);
     st2(c + 4, make_double2(il * zeta.x, il * zeta.y));
     st2(c + 6, make_double2(il * dv.x, il * dv.y));
+    cml_clear_pad(cml, rowoff[2 * mo + par], kk, npk_of(T, mo, par), nstates, s);
 }
 
 void launch_prep_cml(const double* state, int nstates, double* cml, const int* n_of,
-                     const int* m_of, const int* rowoff, const double* inv_lap, int ncoef,
+                     const int* m_of, const int* rowoff, const double* inv_lap, int ncoef, int T,
                      hipStream_t st) {
     dim3 grid((ncoef + kBlock - 1) / kBlock, nstates);
-    k_prep_cml<<<grid, kBlock, 0, st>>>(state, nstates, cml, n_of, m_of, rowoff, inv_lap, ncoef);
+    k_prep_cml<<<grid, kBlock, 0, st>>>(state, nstates, cml, n_of, m_of, rowoff, inv_lap, ncoef, T);
 }
 
 __global__ __launch_bounds__(kBlock) void k_implicit(const double* __restrict__ u, double* __restrict__ fI,

@@ -322,21 +322,20 @@ int setup(sdc_ctx* c) {
     if ((rc = c->alloc(c->tw, cf.nlon))) return rc;
     if ((rc = c->alloc(c->flag, 4))) return rc;
 
-    // task lists.  SWE synthesis: (order pair index k, first of 4 latitude tiles) per workgroup;
-    // the wave owning tile jt processes the orders k and T - k, T + 2 degrees in all, so every
-    // wave carries the same work.  SWE analysis: (m, parity, first of four 16-row tiles) per
-    // workgroup.  Both are grouped per block of 8 orders on one XCD (the partial output lines of
-    // neighbouring orders meet in that L2) and issued longest first.
+    // task lists.  SWE synthesis: (m, 16-latitude tile) per workgroup of two waves (one per
+    // parity).  SWE analysis: (m, parity, first of four 16-row tiles) per workgroup.  Both are
+    // grouped per block of 8 orders on one XCD (the partial output lines of neighbouring orders
+    // meet in that L2) and issued longest first.
     const int ntj = g.nhp / 16, njg = (ntj + 3) / 4;
     {
         std::vector<int2> t;
         std::vector<int> grp;
         std::vector<double> wk;
-        for (int k = 0; 2 * k <= g.T; ++k)
-            for (int jg = 0; jg < njg; ++jg) {
-                t.push_back(make_int2(k, 4 * jg));
-                grp.push_back(k / 8);
-                wk.push_back((double)(g.T + 2) * (ntj - 4 * jg < 4 ? ntj - 4 * jg : 4));
+        for (int m = 0; m <= g.T; ++m)
+            for (int jt = 0; jt < ntj; ++jt) {
+                t.push_back(make_int2(m, jt));
+                grp.push_back(m / 8);
+                wk.push_back((double)((npk_of(g.T, m, 0) + 3) / 4) + 4.0);
             }
         std::vector<int2> ord = xcd_order(t, grp, wk, make_int2(-1, 0));
         c->n_syn = (int)ord.size();

@@ -27,9 +27,10 @@ __device__ __forceinline__ v4d zero4() { return (v4d){0.0, 0.0, 0.0, 0.0}; }
 // ---------------------------------------------------------------------------------------------
 // Synthesis (forward SWE and the transposed analysis of the adjoint).
 //
-// A wave owns one 16-latitude tile, 4 states, and the pair of orders (m, T - m): the two chains
-// together always hold T + 2 degrees, so all waves carry the same work.  Per order the degree loop
-// runs both parities at once in 4-row steps (the parity-0 chain is at most one step longer).
+// A workgroup of two waves owns (m, one 16-latitude tile, 4 states); wave p contracts the degrees
+// of parity p (4-row steps, D operand stages in flight in registers).  The two partial tiles meet
+// in LDS once at the end: wave 0 writes the northern latitudes (even + odd), wave 1 the southern
+// ones (even - odd for Pbar tiles, odd - even for H tiles).
 //
 // Column tiles: 16 columns = 4 states x 4 values (lane column i: state i >> 2, value v = i & 3).
 // Forward, Fourier fields (zeta, Phi', U, V), cml values (zeta, Phi', psi, chi) x (Re, Im):
@@ -51,12 +52,12 @@ __device__ __forceinline__ v4d zero4() { return (v4d){0.0, 0.0, 0.0, 0.0}; }
 // ---------------------------------------------------------------------------------------------
 template <int MODE> struct SynTiles;
 template <> struct SynTiles<kSynForward> {
-    static constexpr int NT = 3, NF = kSynFields, D = 6;
+    static constexpr int NT = 3, NF = kSynFields;
     __device__ static constexpr bool is_h(int t) { return t == 2; }
     __device__ static int col(int t, int v) { return t == 0 ? v : (t == 1 ? 7 - v : 4 + v); }
 };
 template <> struct SynTiles<kSynAdjoint> {
-    static constexpr int NT = 4, NF = 5, D = 5;
+    static constexpr int NT = 4, NF = 5;
     __device__ static constexpr bool is_h(int t) { return t == 1 || t == 3; }
     __device__ static int col(int t, int v) {
         return t == 0 ? (v ^ 1) : (t == 1 ? (v ^ 2) : (t == 2 ? (v < 2 ? 5 - v : 4 + v) : 4 + (v & 1)));
@@ -64,128 +65,111 @@ template <> struct SynTiles<kSynAdjoint> {
 };
 
 template <int NT> struct SynStage {
-    double a[2][2];          // [parity][Pbar, H]
-    double b[2][NT];         // [parity][tile]
+    double a[2];             // Pbar, H
+    double b[NT];
 };
 
+constexpr int kSynBlock = 128;                   // two waves: the two parities
+
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_synthesis(
+__global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
     const int* __restrict__ rowoff, const int2* __restrict__ tasks, const double* __restrict__ cml,
     int nstates, double* __restrict__ four, Geom g) {
     using TL = SynTiles<MODE>;
-    constexpr int NT = TL::NT, D = TL::D;
+    constexpr int NT = TL::NT, D = 8;
+    __shared__ double part[2][NT][4][64];
     const int2 task = tasks[blockIdx.x];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int jt = task.y + wave;
-    if (task.x < 0 || jt * 16 >= g.nhp) return;          // padding workgroup, tile past the end
+    if (task.x < 0) return;                                  // padding workgroup (uniform)
+    const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // parity of this wave
+    const int m = task.x, jt = task.y;
     const int lane = threadIdx.x & 63, i = lane & 15, q = lane >> 4, v = i & 3;
     const int S = nstates;
     const int s = blockIdx.y * 4 + (i >> 2);
     const int sc = s < S ? s : S - 1;
-    // 32-bit byte offsets from per-order (uniform) base addresses keep one VGPR per address
+    // 32-bit byte offsets from per-block (uniform) base addresses: one VGPR per address
     unsigned boff[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * 8u;
     const unsigned rstride = (unsigned)S * kCmlVals * 8u;           // bytes per cml row
     const unsigned tstep = 4u * g.nhp * 8u, cstep = 4u * rstride;   // bytes per 4-row step
     const unsigned tlane = ((unsigned)q * g.nhp + jt * 16 + i) * 8u, clane = (unsigned)q * rstride;
+    const int nst = (npk_of(g.T, m, p) + 3) >> 2;                   // 4-row steps of this parity
+    const char* tP = (const char*)(P + toff[2 * m + p]);
+    const char* tH = (const char*)(H + toff[2 * m + p]);
+    const char* cb = (const char*)(cml + (size_t)rowoff[2 * m + p] * S * kCmlVals);
+    auto ldd = [](const char* base, unsigned off) { return *(const double*)(base + off); };
+
+    v4d acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = zero4();
+    auto load = [&](SynStage<NT>& x, int j) {
+        const unsigned ot = tlane + (unsigned)j * tstep, oc = clane + (unsigned)j * cstep;
+        x.a[0] = ldd(tP, ot);
+        x.a[1] = ldd(tH, ot);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) x.b[t] = ldd(cb, oc + boff[t]);
+    };
+    auto compute = [&](const SynStage<NT>& x) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma_f64(x.a[TL::is_h(t) ? 1 : 0], x.b[t], acc[t]);
+    };
+    // Loads past the chain's end re-read its last step (cache hits, results unused): a
+    // branch-free loop body lets every stage wait for its own loads only.
+    if (nst > 0) {
+        SynStage<NT> st[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) load(st[u], u < nst ? u : nst - 1);
+        int j0 = 0;
+        for (; j0 + D <= nst; j0 += D) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                compute(st[u]);
+                const int jn = j0 + u + D;
+                load(st[u], jn < nst ? jn : nst - 1);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < D; ++u)
+            if (u < nst - j0) compute(st[u]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[p][t][r][lane] = acc[t][r];
+    __syncthreads();
+
+    // wave 0: north = even + odd; wave 1: south = even - odd (Pbar tiles), odd - even (H tiles)
+    const int ns = p;
+    const double mm = (double)m;
     const size_t fstride = (size_t)2 * g.nlat * g.ms;               // doubles per Fourier field
     const double inva = 1.0 / g.radius;
-
-    for (int pass = 0; pass < 2; ++pass) {
-        const int m = pass == 0 ? task.x : g.T - task.x;
-        if (pass == 1 && m <= task.x) break;                // uniform
-        const int n0 = (npk_of(g.T, m, 0) + 3) >> 2, n1 = (npk_of(g.T, m, 1) + 3) >> 2;
-        const char* tb[2][2];
-        const char* cb[2];
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            tb[p][0] = (const char*)(P + toff[2 * m + p]);
-            tb[p][1] = (const char*)(H + toff[2 * m + p]);
-            cb[p] = (const char*)(cml + (size_t)rowoff[2 * m + p] * S * kCmlVals);
+    for (int r = 0; r < 4; ++r) {
+        const int jh = jt * 16 + 4 * r + q;
+        if (s >= S || jh >= g.nh) continue;
+        const int j = ns ? g.nlat - 1 - jh : jh;
+        double val[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const double e = ns == 0 ? acc[t][r] : part[0][t][r][lane];
+            const double o = ns == 0 ? part[1][t][r][lane] : acc[t][r];
+            val[t] = ns == 0 ? e + o : (TL::is_h(t) ? o - e : e - o);
         }
-        v4d acc[2][NT];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[p][t] = zero4();
-        SynStage<NT> st[D];
-        auto ldd = [](const char* base, unsigned off) { return *(const double*)(base + off); };
-        auto load = [&](SynStage<NT>& x, int j) {
-            const unsigned ot = tlane + (unsigned)j * tstep, oc = clane + (unsigned)j * cstep;
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                x.a[p][0] = ldd(tb[p][0], ot);
-                x.a[p][1] = ldd(tb[p][1], ot);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) x.b[p][t] = ldd(cb[p], oc + boff[t]);
-            }
-        };
-        auto compute = [&](const SynStage<NT>& x) {
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    acc[p][t] = mfma_f64(x.a[p][TL::is_h(t) ? 1 : 0], x.b[p][t], acc[p][t]);
-        };
-        // Loads past the chain's end re-read its last step (cache hits, results unused): a
-        // branch-free loop body lets every stage wait for its own loads only.
-        if (n1 > 0) {
-#pragma unroll
-            for (int u = 0; u < D; ++u) load(st[u], u < n1 ? u : n1 - 1);
-            int j0 = 0;
-            for (; j0 + D <= n1; j0 += D) {
-#pragma unroll
-                for (int u = 0; u < D; ++u) {
-                    compute(st[u]);
-                    const int jn = j0 + u + D;
-                    load(st[u], jn < n1 ? jn : n1 - 1);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < D; ++u)
-                if (u < n1 - j0) compute(st[u]);
-        }
-        if (n0 > n1) {                                      // last parity-0 step
-            const unsigned ot = tlane + (unsigned)n1 * tstep, oc = clane + (unsigned)n1 * cstep;
-            const double a0 = ldd(tb[0][0], ot), a1 = ldd(tb[0][1], ot);
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-                acc[0][t] = mfma_f64(TL::is_h(t) ? a1 : a0, ldd(cb[0], oc + boff[t]), acc[0][t]);
-        }
-
-        // north = even + odd; south = even - odd (Pbar tiles), odd - even (H tiles)
-        const double mm = (double)m;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int jh = jt * 16 + 4 * r + q;
-            if (s >= S || jh >= g.nh) continue;
-#pragma unroll
-            for (int ns = 0; ns < 2; ++ns) {
-                const int j = ns ? g.nlat - 1 - jh : jh;
-                double val[NT];
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const double e = acc[0][t][r], o = acc[1][t][r];
-                    val[t] = ns == 0 ? e + o : (TL::is_h(t) ? o - e : e - o);
-                }
-                double* base = four + (((size_t)s * TL::NF * g.nlat + j) * g.ms + m) * 2 + (v & 1);
-                if constexpr (MODE == kSynForward) {
-                    base[(size_t)(v >> 1) * fstride] = val[0];
-                    const double sx = (v & 1) ? mm : -mm, sh = v < 2 ? -1.0 : 1.0;
-                    base[(size_t)(2 + (v >> 1)) * fstride] = (sx * val[1] + sh * val[2]) * inva;
-                } else {
-                    const double hf = m > 0 ? 0.5 : 1.0;
-                    const double sx = (v == 0 || v == 3) ? -mm : mm;
-                    base[(size_t)(v >> 1) * fstride] = hf * (sx * val[0] + val[1]);
-                    if (v < 2) {
-                        base[2 * fstride] = hf * ((v ? mm : -mm) * val[2]);
-                        base[3 * fstride] = hf * val[3];
-                    } else {
-                        base[4 * fstride] = hf * val[2];
-                    }
-                }
+        double* base = four + (((size_t)s * TL::NF * g.nlat + j) * g.ms + m) * 2 + (v & 1);
+        if constexpr (MODE == kSynForward) {
+            base[(size_t)(v >> 1) * fstride] = val[0];
+            const double sx = (v & 1) ? mm : -mm, sh = v < 2 ? -1.0 : 1.0;
+            base[(size_t)(2 + (v >> 1)) * fstride] = (sx * val[1] + sh * val[2]) * inva;
+        } else {
+            const double hf = m > 0 ? 0.5 : 1.0;
+            const double sx = (v == 0 || v == 3) ? -mm : mm;
+            base[(size_t)(v >> 1) * fstride] = hf * (sx * val[0] + val[1]);
+            if (v < 2) {
+                base[2 * fstride] = hf * ((v ? mm : -mm) * val[2]);
+                base[3 * fstride] = hf * val[3];
+            } else {
+                base[4 * fstride] = hf * val[2];
             }
         }
     }
@@ -195,16 +179,16 @@ void launch_synthesis_swe(const double* P, const double* H, const long long* tof
                           const int* rowoff, const int2* tasks, int ntasks, const double* cml,
                           int nstates, double2* four, const Geom& g, hipStream_t st) {
     dim3 grid(ntasks, (nstates + 3) / 4);
-    k_synthesis<kSynForward><<<grid, kBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates,
-                                                       (double*)four, g);
+    k_synthesis<kSynForward><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates,
+                                                          (double*)four, g);
 }
 
 void launch_synthesis_adj(const double* P, const double* H, const long long* toff, const int* rowoff,
                           const int2* tasks, int ntasks, const double* cml, int nstates, double2* four5,
                           const Geom& g, hipStream_t st) {
     dim3 grid(ntasks, (nstates + 3) / 4);
-    k_synthesis<kSynAdjoint><<<grid, kBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates,
-                                                       (double*)four5, g);
+    k_synthesis<kSynAdjoint><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates,
+                                                          (double*)four5, g);
 }
 
 // ---------------------------------------------------------------------------------------------

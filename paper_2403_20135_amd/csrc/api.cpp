@@ -866,15 +866,16 @@ int sdc_copy_legendre(sdc_handle h, int m, double* Pbar, double* H) {
     const Geom& g = h->g;
     for (int p = 0; p < 2; ++p) {
         const int np = npk_of(g.T, m, p);
-        std::vector<double> bp((size_t)np * g.nhp), bh((size_t)np * g.nhp);
+        std::vector<double> bp((size_t)((np + 3) & ~3) * g.nhp), bh(bp.size());
         if (np == 0) continue;
         HIP_TRY(hipMemcpy(bp.data(), h->P + h->h_toff[2 * m + p], bp.size() * sizeof(double), hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(bh.data(), h->H + h->h_toff[2 * m + p], bh.size() * sizeof(double), hipMemcpyDeviceToHost));
+        const int np4 = (np + 3) & ~3;
         for (int kk = 0; kk < np; ++kk) {
             const int row = p + 2 * kk;    // n - m
             for (int j = 0; j < g.nh; ++j) {
-                Pbar[(size_t)row * g.nh + j] = bp[(size_t)kk * g.nhp + j];
-                H[(size_t)row * g.nh + j] = bh[(size_t)kk * g.nhp + j];
+                Pbar[(size_t)row * g.nh + j] = bp[tab_index(np4, kk, j)];
+                H[(size_t)row * g.nh + j] = bh[tab_index(np4, kk, j)];
             }
         }
     }

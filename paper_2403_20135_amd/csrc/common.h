@@ -45,6 +45,13 @@ struct Geom {
 
 __host__ __device__ inline int coef_offset(int T, int m) { return m * (2 * T + 3 - m) / 2; }
 __host__ __device__ inline int npk_of(int T, int m, int p) { return (T - m + 2 - p) / 2; }
+// Legendre table layout.  Per (m, parity) block: np4 = npk rounded up to 4 rows, nhp northern
+// latitudes, stored tile-major (16-latitude tiles of np4 x 16 values, rows contiguous within a
+// tile), so that a wave streaming one tile, or 16 rows of one tile, reads contiguous memory:
+//   P[toff[2m + p] + tab_index(np4, kk, jh)].
+__host__ __device__ inline size_t tab_index(int np4, int kk, int jh) {
+    return (size_t)(jh >> 4) * np4 * 16 + (size_t)kk * 16 + (jh & 15);
+}
 
 // Synthesis input ("coefficient-major", written by the update/prep kernels): for table row
 // (m, p, kk) and state s, 8 doubles (zeta, Phi', psi, chi) x (Re, Im) with psi, chi the inverse

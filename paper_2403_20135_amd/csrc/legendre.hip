@@ -92,9 +92,9 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
 #pragma unroll
     for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * 8u;
     const unsigned rstride = (unsigned)S * kCmlVals * 8u;           // bytes per cml row
-    const unsigned tstep = 4u * g.nhp * 8u, cstep = 4u * rstride;   // bytes per 4-row step
-    const unsigned tlane = ((unsigned)q * g.nhp + jt * 16 + i) * 8u, clane = (unsigned)q * rstride;
     const int nst = (npk_of(g.T, m, p) + 3) >> 2;                   // 4-row steps of this parity
+    const unsigned tstep = 4u * 16u * 8u, cstep = 4u * rstride;     // bytes per 4-row step
+    const unsigned tlane = ((unsigned)(jt * 4 * nst + q) * 16 + i) * 8u, clane = (unsigned)q * rstride;
     const char* tP = (const char*)(P + toff[2 * m + p]);
     const char* tH = (const char*)(H + toff[2 * m + p]);
     const char* cb = (const char*)(cml + (size_t)rowoff[2 * m + p] * S * kCmlVals);
@@ -239,8 +239,9 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const int np4 = (np + 3) & ~3;
     // rows past the block's end read its last row; their outputs are dropped
     const int kr = kt + i < np4 ? kt + i : np4 - 1;
-    const double* Pr = P + toff[2 * m + p] + (size_t)kr * g.nhp + 4 * q;
-    const double* Hr = H + toff[2 * m + p] + (size_t)kr * g.nhp + 4 * q;
+    const double* Pr = P + toff[2 * m + p] + tab_index(np4, kr, 4 * q);
+    const double* Hr = H + toff[2 * m + p] + tab_index(np4, kr, 4 * q);
+    const size_t bstride = (size_t)np4 * 16;                 // doubles per 16-latitude tile
     const int nb = g.nhp >> 4;
 
     // forward kinds: 0 zeta 1 delta 2 KE 3 Phi'; adjoint kinds: 0 zeta 1 zeta (via psi)
@@ -291,8 +292,8 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
 
     v4d accP[2] = {zero4(), zero4()}, accH[2] = {zero4(), zero4()};
     auto load = [&](AnaStage& x, int b) {
-        x.aP = *(const v4d*)(Pr + 16 * b);
-        x.aH = *(const v4d*)(Hr + 16 * b);
+        x.aP = *(const v4d*)(Pr + b * bstride);
+        x.aH = *(const v4d*)(Hr + b * bstride);
     };
     // k-step qq of a block contracts latitude 4 q + qq of the block (lane group q)
     auto compute = [&](const AnaStage& x, const double* lb) {
@@ -409,13 +410,13 @@ __global__ __launch_bounds__(kBlock) void k_synthesis_scalar(
     for (int p = 0; p < 2; ++p) {
         const int np = npk_of(g.T, m, p);
         const int np4 = (np + 3) & ~3;
-        const double* Pp = P + toff[2 * m + p] + jt * 16 + i;
+        const double* Pp = P + toff[2 * m + p] + tab_index(np4, 0, jt * 16 + i);
         v4d c = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
         for (int kk0 = 0; kk0 < np4; kk0 += 4) {
             const int kk = kk0 + q;
             const int n = m + p + 2 * kk;
-            const double ap = Pp[(size_t)kk * g.nhp];
+            const double ap = Pp[(size_t)kk * 16];
             const double b = (kk < np && okf) ? bp[2 * n] : 0.0;
             c = mfma_f64(ap, b, c);
         }
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_scalar(
     const int i = lane & 15, q = lane >> 4;
     const int kr = kk0 + i;
     const bool rowok = kr < np4;
-    const double* Pr = P + toff[2 * m + p] + (size_t)(rowok ? kr : 0) * g.nhp + 4 * q;
+    const double* Pr = P + toff[2 * m + p] + tab_index(np4, rowok ? kr : 0, 4 * q);
     const int f = blockIdx.y * 8 + (i >> 1), re = i & 1;
     const bool okf = f < nfields;
     const size_t jstride = (size_t)2 * g.ms;
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_scalar(
     v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
     const v4d zero4 = acc;
     for (int jh0 = 0; jh0 < g.nhp; jh0 += 16) {
-        const v4d ap = rowok ? *(const v4d*)(Pr + jh0) : zero4;
+        const v4d ap = rowok ? *(const v4d*)(Pr + (size_t)(jh0 >> 4) * np4 * 16) : zero4;
         const size_t o = (size_t)jh0 * jstride;
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {

@@ -51,7 +51,8 @@ __device__ inline double eps_nm(int n, int m) {
 }
 
 // One thread per (m, northern latitude): upward recurrence in n from Pbar_m^m, writing Pbar and
-// H for n = m..T into the parity-split packed layout (row n goes to parity (n-m)&1, row (n-m)>>1).
+// H for n = m..T into the parity-split packed layout (row n goes to parity (n-m)&1, row (n-m)>>1;
+// tile-major, tab_index).
 __global__ void k_legendre(const double* __restrict__ mu, double* __restrict__ P,
                            double* __restrict__ H, const long long* __restrict__ toff, Geom g) {
     const int jh = blockIdx.x * blockDim.x + threadIdx.x;
@@ -68,7 +69,7 @@ __global__ void k_legendre(const double* __restrict__ mu, double* __restrict__ P
         const double e_n = eps_nm(n, m), e_n1 = eps_nm(n + 1, m);
         const double h = (n + 1) * e_n * p_prev - n * e_n1 * p_next;
         const int par = (n - m) & 1, kk = (n - m) >> 1;
-        const long long idx = toff[2 * m + par] + (long long)kk * g.nhp + jh;
+        const long long idx = toff[2 * m + par] + tab_index((npk_of(g.T, m, par) + 3) & ~3, kk, jh);
         P[idx] = p_cur;
         H[idx] = h;
         // advance: Pbar_{n+2} = (x Pbar_{n+1} - eps_{n+1} Pbar_n) / eps_{n+2}

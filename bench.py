@@ -2,21 +2,35 @@
 """Benchmark: dSDC steps/s of the T255, M=4, K=4 shallow-water workload on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload t255_m4k4] [--no-cpu-baseline]
+                    [--no-fp32]
+    python bench.py --summarize-pmc FETCH.csv WRITE.csv COPY_MIB OUT.json   (counter summary)
 
-Prints ONE JSON line.  The timed region is exactly K steps (after W warm-up steps and one graph
-capture) of the HIP library on synthetic seeded fields already resident in device memory,
-bracketed by torch.cuda.synchronize(); each step is one replay of the step's captured hipGraph.
-A second region of K eager steps of the same kernels brackets every launch with HIP events on the
-library's stream; the dominant kernel class (largest summed time) is reported against its
-roofline from algorithmic work per launch (flops of the useful Legendre contractions with
-equatorial symmetry, or minimal HBM bytes of the grid/update kernels).  A third region times K
-forward steps with one checkpoint each followed by K adjoint steps (forward+adjoint steps/s).
-The CPU baseline is the FP64 oracle timed on this machine's host cores on a bounded sample.
+Prints ONE JSON line.  `value` is the plain FP64 path: exactly K steps (after W warm-up steps and
+one graph capture) on synthetic seeded fields already resident in device memory, bracketed by
+torch.cuda.synchronize(); each step is one replay of the step's captured hipGraph.  A second
+region of K eager steps brackets every launch with HIP events on the library's stream; the
+dominant kernel class (largest summed time) is reported against its roofline.  A third region
+times K forward steps with one checkpoint each followed by K adjoint steps (forward+adjoint).
+The same three regions are measured for the FP32 precision mode (Legendre contractions in FP32
+on MFMA), whose error is compared with the plain path's at equal step size against the FP64
+path at dt/8 ("equal error": E_fp32 <= 1.1 E_fp64, E = max over output times of the relative
+L2 error of vorticity).  The CPU baseline is the FP64 oracle timed on the host cores on a bounded
+sample.
+
+Rooflines: the Legendre kernels are priced at min(MFMA peak, AI x HBM peak) with AI = useful
+flops / algorithmic bytes (tables read once per launch, spectral and Fourier I/O); when the
+bandwidth term is the smaller one they are reported in GB/s against 8 TB/s.  Grid and update
+kernels are HBM-bound (minimal bytes).  `traffic` comes from a committed counter summary
+(FETCH_SIZE, WRITE_SIZE scaled by a copy kernel of known size) and is reported only when that
+summary was taken from the current kernel sources.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -28,31 +42,221 @@ import workloads as W  # noqa: E402
 
 METRIC = "SDC steps/s (fwd, fwd+adjoint) at T255 M=4 vs plain FP64 GPU at equal error"
 PEAK_HBM_GBS = 8000.0
-PEAK_FP64_TFLOPS = 78.6
-PEAK = {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+TABLE_BYTES = {"fp64": 8, "fp32": 4}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_t255_m4k4.json")
 
 
-def algorithmic_work(T, nlat, M, K, batch):
-    """Algorithmic work of every kernel class over one step.
+def source_hash() -> str:
+    """Hash of the HIP sources: a counter summary is valid only for the kernels it measured."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2403_20135_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode() + f.read())
+    return h.hexdigest()[:16]
 
-    Legendre (flops): one scalar-equivalent complex transform with equatorial symmetry costs
-    2*ncoef*nlat flops; synthesis does 6 per state (zeta, Phi', psi and chi with Pbar, psi and
-    chi with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).
+
+def algorithmic_work(T, nlat, M, K, batch, precision):
+    """Algorithmic work of every kernel class over one step: {class: (flops, bytes)}.
+
+    Legendre: one scalar-equivalent complex transform with equatorial symmetry costs
+    2*ncoef*nlat flops; synthesis does 6 per state (zeta, Phi', psi and chi with Pbar, psi and chi
+    with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).  Bytes: both tables (Pbar, H:
+    ncoef x nlat/2 entries each) once per launch, plus per state the spectral input (4 complex per
+    coefficient) and Fourier output (4 fields x nlat x (T+1) complex) of the synthesis, and the
+    analysis input (7 weighted columns x (T+1) x nlat complex) and spectral output (3 complex).
     Grid (bytes): reads 4 Fourier fields and writes 5 (minimal), nlat*(T+1) complex each per state.
-    Update (bytes): per coefficient and member, reads u_n (3 complex), per node j the Phi',
-    delta of u_j (2) and E_j (3), writes the updated nodes (3 each) and their synthesis-layout
-    copy (4 each: zeta, Phi', psi, chi); the last sweep writes node M only; the first f_E of a
-    step converts u_n to the synthesis layout (reads 3, writes 4).
+    Update (bytes): per coefficient and member, reads u_n (3 complex), per node j the Phi', delta
+    of u_j (2) and E_j (3), writes the updated nodes (3 each) and their synthesis-layout copy
+    (4 each); the last sweep writes node M only; the first f_E of a step converts u_n (3 -> 4).
     """
     ncoef = (T + 1) * (T + 2) // 2
     transform = 2.0 * ncoef * nlat
     states = batch * (1 + (K - 1) * M)          # states transformed per step
-    syn_flops = 6 * transform * states
-    ana_flops = 7 * transform * states
+    launches = K                                 # Legendre launches per step (one per sweep + first)
+    tables = 2.0 * ncoef * (nlat // 2) * TABLE_BYTES[precision] * launches
+    syn_bytes = tables + states * (4 * 16.0 * ncoef + 4 * 16.0 * nlat * (T + 1))
+    ana_bytes = tables + states * (7 * 16.0 * nlat * (T + 1) + 3 * 16.0 * ncoef)
     grid_bytes = 9.0 * nlat * (T + 1) * 16 * states
     upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + 7)
-    return {"synthesis": ("flops", syn_flops), "analysis": ("flops", ana_flops),
-            "grid": ("bytes", grid_bytes), "update": ("bytes", upd_bytes)}
+    return {"synthesis": (6 * transform * states, syn_bytes),
+            "analysis": (7 * transform * states, ana_bytes),
+            "grid": (0.0, grid_bytes), "update": (0.0, upd_bytes)}
+
+
+def roofline_entry(flops, nbytes, secs, launches, precision):
+    """Achieved rate against min(MFMA peak, AI x HBM peak) (bytes only: HBM)."""
+    if flops > 0:
+        ai = flops / nbytes
+        if ai * PEAK_HBM_GBS * 1e9 < PEAK_TFLOPS[precision] * 1e12:
+            bound, ach, peak, unit = "hbm", nbytes / secs / 1e9, PEAK_HBM_GBS, "GB/s"
+        else:
+            bound, ach, peak, unit = "mfma", flops / secs / 1e12, PEAK_TFLOPS[precision], "TFLOP/s"
+        extra = {"ai_flop_per_byte": round(ai, 3), "tflops": round(flops / secs / 1e12, 3)}
+    else:
+        bound, ach, peak, unit = "hbm", nbytes / secs / 1e9, PEAK_HBM_GBS, "GB/s"
+        extra = {}
+    e = {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+         "frac": round(ach / peak, 4), "avg_us": round(secs * 1e6 / max(launches, 1), 2),
+         "launches": launches, "algorithmic_bytes_per_launch": round(nbytes / max(launches, 1))}
+    e.update(extra)
+    return e
+
+
+def measure(wl, precision, steps, warmup, with_kernels=True):
+    """Graph-replay steps/s, per-kernel HIP-event timing over eager steps, fwd+adj steps/s."""
+    import torch
+    from paper_2403_20135_amd.api import SDC
+    mb = wl.members[0]
+    batch = 1
+    sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, batch, precision, W.RADIUS, W.GRAVITY,
+              W.OMEGA, W.MEAN_DEPTH)
+    x = torch.tensor(W.initial_state(wl)[None], dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        sdc.step(x, mb.dt)
+    sdc.sync()
+
+    # timed region: K steps, each one replay of the step's captured hipGraph
+    sdc.step_graph(x, mb.dt)                          # capture (untimed)
+    sdc.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sdc.step_graph(x, mb.dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sdc.sync()
+    out = {"steps_per_s": steps / elapsed, "ms_per_step": elapsed / steps * 1e3}
+
+    if with_kernels:
+        # per-kernel HIP events (on the library's stream) over K eager steps of the same kernels
+        sdc.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sdc.step(x, mb.dt)
+        torch.cuda.synchronize()
+        out["eager_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
+        sdc.sync()
+        kt = sdc.timing_read()
+        sdc.timing(False)
+        work = algorithmic_work(mb.T, mb.nlat, wl.M, wl.K, batch, precision)
+        out["kernels"] = {name: roofline_entry(work[name][0] * steps, work[name][1] * steps, ms / 1e3,
+                                               launches, precision)
+                          for name, (ms, launches) in kt.items()}
+        out["kernel_ms"] = {name: ms for name, (ms, _) in kt.items()}
+
+    # forward + adjoint: every forward step keeps its input (one checkpoint per step), then the
+    # adjoint steps run in reverse, each recomputing its step's stages from the checkpoint
+    ckpt = torch.empty((steps,) + tuple(x.shape), dtype=torch.float64, device="cuda")
+    lam = torch.ones_like(x)
+    lam_out = torch.empty_like(x)
+    sdc.step_adjoint(x, lam, lam_out, mb.dt)          # allocates the adjoint workspaces once
+    sdc.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ckpt[k].copy_(x)
+        sdc.step(x, mb.dt)
+    for k in range(steps - 1, -1, -1):
+        sdc.step_adjoint(ckpt[k], lam, lam, mb.dt)
+    torch.cuda.synchronize()
+    elapsed_fa = time.perf_counter() - t0
+    sdc.sync()
+    if not bool(torch.isfinite(lam).all()) or not bool(torch.isfinite(x).all()):
+        raise RuntimeError(f"non-finite state or adjoint ({precision})")
+    out["fwd_adj_steps_per_s"] = steps / elapsed_fa
+    out["fwd_adj_ms_per_step"] = elapsed_fa / steps * 1e3
+    sdc.close()
+    return out
+
+
+def equal_error(wl, steps=40, every=10):
+    """E_fp64, E_fp32 against the FP64 path at dt/8: max over output times of the relative L2
+    error (sphere norm) of vorticity."""
+    import numpy as np
+    import torch
+    from paper_2403_20135_amd.api import SDC
+    mb = wl.members[0]
+    _, m = W.degree_order_arrays(mb.T)
+    sm = np.where(m == 0, 1.0, 2.0)[:, None]
+
+    def history(precision, dt, n, ev):
+        sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, 1, precision, W.RADIUS, W.GRAVITY,
+                  W.OMEGA, W.MEAN_DEPTH)
+        x = torch.tensor(W.initial_state(wl)[None], dtype=torch.float64, device="cuda")
+        out = []
+        for k in range(1, n + 1):
+            sdc.step(x, dt)
+            if k % ev == 0:
+                out.append(x[0, 1].cpu().numpy())
+        sdc.sync()
+        sdc.close()
+        return out
+
+    ref = history("fp64", mb.dt / 8, 8 * steps, 8 * every)
+
+    def err(h):
+        return max(math.sqrt(np.sum(sm * (a - r) ** 2) / np.sum(sm * r ** 2)) for a, r in zip(h, ref))
+
+    e64, e32 = err(history("fp64", mb.dt, steps, every)), err(history("fp32", mb.dt, steps, every))
+    return {"E_fp64": e64, "E_fp32": e32, "ratio": e32 / e64, "equal": bool(e32 <= 1.1 * e64),
+            "quantity": f"max over t = {every}..{steps} steps (every {every}) of rel. L2 of zeta",
+            "reference": f"FP64 GPU path at dt/8 ({8 * steps} steps of {mb.dt / 8} s)"}
+
+
+def traffic_for(kernel):
+    """Measured HBM bytes per launch of `kernel` from the committed counter summary, or None when
+    the summary is missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != source_hash() or kernel not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel]
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json):
+    """Counter summary: mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel class, scaled
+    so that the device-to-device copy of copy_mib MiB reads and writes exactly that many bytes."""
+    import csv
+    # forward FP64 kernels of the bench workload (name prefixes as rocprofv3 prints them)
+    classes = {"void k_synthesis<0, double>": "synthesis", "void k_analysis_swe<0, double>": "analysis",
+               "void k_grid_swe<": "grid", "void k_update<": "update"}
+
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+        return acc
+
+    out = {"source_sha": source_hash(), "copy_mib": copy_mib, "kernels": {}}
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = copy_mib * (1 << 20)
+    cf = [v for k, vs in fetch.items() if "copyBuffer" in k for v in vs]
+    cw = [v for k, vs in write.items() if "copyBuffer" in k for v in vs]
+    f_scale = copy_bytes / (max(cf) * 1024.0)
+    w_scale = copy_bytes / (max(cw) * 1024.0)
+    out["fetch_scale"], out["write_scale"] = f_scale, w_scale
+    for name, vals in fetch.items():
+        cls = next((c for key, c in classes.items() if name.startswith(key)), None)
+        if cls is None:
+            continue
+        wv = write.get(name, [0.0])
+        out["kernels"].setdefault(cls, {
+            "kernel_name": name.split("(")[0],
+            "dispatches": len(vals),
+            "fetch_bytes_per_launch": sum(vals) / len(vals) * 1024.0 * f_scale,
+            "write_bytes_per_launch": sum(wv) / len(wv) * 1024.0 * w_scale})
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(wl, state0, budget_s=15.0):
@@ -78,119 +282,68 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="t255_m4k4")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="measure the plain FP64 path only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a reference kernel of known "
                          "traffic for scaling hardware byte counters)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB", "OUT"))
     args = ap.parse_args()
+    if args.summarize_pmc:
+        f, w, mib, outp = args.summarize_pmc
+        summarize_pmc(f, w, float(mib), outp)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the step on a single MI355X "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2403_20135_amd.api import SDC
 
     wl = W.WORKLOADS[args.workload]
     mb = wl.members[0]
-    batch = 1
-    sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, batch, args.precision, W.RADIUS, W.GRAVITY,
-              W.OMEGA, W.MEAN_DEPTH)
-    state0 = W.initial_state(wl)
-    x = torch.tensor(state0[None], dtype=torch.float64, device="cuda")
-    for _ in range(args.warmup):
-        sdc.step(x, mb.dt)
-    sdc.sync()
-
-    # timed region: K steps, each one replay of the step's captured hipGraph
-    sdc.step_graph(x, mb.dt)                          # capture (untimed)
-    sdc.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sdc.step_graph(x, mb.dt)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    sdc.sync()
-
-    # per-kernel HIP events (on the library's stream) over K eager steps of the same kernels
-    sdc.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sdc.step(x, mb.dt)
-    torch.cuda.synchronize()
-    elapsed_eager = time.perf_counter() - t0
-    sdc.sync()
-    kt = sdc.timing_read()
-    sdc.timing(False)
-
-    work = algorithmic_work(mb.T, mb.nlat, wl.M, wl.K, batch)
-    kernels = {}
-    for name, (ms, launches) in kt.items():
-        kind, per_step = work[name]
-        total = per_step * args.steps
-        secs = ms / 1e3
-        if kind == "flops":
-            ach, unit, peak, bound = total / secs / 1e12, "TFLOP/s", PEAK[args.precision], "mfma"
-        else:
-            ach, unit, peak, bound = total / secs / 1e9, "GB/s", PEAK_HBM_GBS, "hbm"
-        kernels[name] = {"ms_total": round(ms, 3), "launches": launches,
-                         "avg_us": round(ms * 1e3 / max(launches, 1), 2),
-                         "achieved": round(ach, 3), "unit": unit, "peak": peak, "bound": bound,
-                         "frac": round(ach / peak, 4),
-                         "algorithmic_per_launch": total / max(launches, 1)}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
+    r64 = measure(wl, "fp64", args.steps, args.warmup)
+    kernels = r64["kernels"]
+    dom = max(r64["kernel_ms"], key=lambda k: r64["kernel_ms"][k])
     d = kernels[dom]
+    tr = traffic_for(dom)
     roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
-                "frac": d["frac"], "traffic": None, "kernel": dom,
-                "avg_launch_us": d["avg_us"], "timed_over": "eager steps with per-launch HIP events"}
-
-    # forward + adjoint: every forward step keeps its input (one checkpoint per step), then the
-    # adjoint steps run in reverse, each recomputing its step's stages from the checkpoint
-    ckpt = torch.empty((args.steps,) + tuple(x.shape), dtype=torch.float64, device="cuda")
-    lam = torch.ones_like(x)
-    lam_out = torch.empty_like(x)
-    sdc.step_adjoint(x, lam, lam_out, mb.dt)          # allocates the adjoint workspaces once
-    sdc.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ckpt[k].copy_(x)
-        sdc.step(x, mb.dt)
-    for k in range(args.steps - 1, -1, -1):
-        sdc.step_adjoint(ckpt[k], lam, lam, mb.dt)
-    torch.cuda.synchronize()
-    elapsed_fa = time.perf_counter() - t0
-    sdc.sync()
-    if not bool(torch.isfinite(lam).all()):
-        raise RuntimeError("non-finite adjoint")
-    del ckpt
-
-    steps_s = args.steps / elapsed
+                "frac": d["frac"], "traffic": tr, "kernel": dom, "avg_launch_us": d["avg_us"],
+                "timed_over": "eager steps with per-launch HIP events on the library's stream"}
     result = {
         "metric": METRIC,
-        "value": round(steps_s, 3),
+        "value": round(r64["steps_per_s"], 3),
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
-        "eager_ms_per_step": round(elapsed_eager / args.steps * 1e3, 4),
+        "ms_per_step": round(r64["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "T": mb.T, "nlat": mb.nlat, "nlon": mb.nlon, "M": wl.M,
-                   "K": wl.K, "dt": mb.dt, "batch": batch, "precision": args.precision},
-        "fwd_adj_steps_per_s": round(args.steps / elapsed_fa, 3),
-        "fwd_adj_ms_per_step": round(elapsed_fa / args.steps * 1e3, 4),
+                   "K": wl.K, "dt": mb.dt, "batch": 1, "precision": "fp64"},
+        "eager_ms_per_step": round(r64["eager_ms_per_step"], 4),
+        "fwd_adj_steps_per_s": round(r64["fwd_adj_steps_per_s"], 3),
+        "fwd_adj_ms_per_step": round(r64["fwd_adj_ms_per_step"], 4),
         "roofline": roofline,
         "kernels": kernels,
     }
+    if not args.no_fp32:
+        r32 = measure(wl, "fp32", args.steps, args.warmup)
+        ee = equal_error(wl)
+        result["fp32"] = {
+            "value": round(r32["steps_per_s"], 3), "unit": "steps/s",
+            "dtype": "f32 Legendre contractions (FP32 MFMA, FP32 accumulation); f64 elsewhere",
+            "ms_per_step": round(r32["ms_per_step"], 4),
+            "fwd_adj_steps_per_s": round(r32["fwd_adj_steps_per_s"], 3),
+            "speedup_vs_fp64": round(r32["steps_per_s"] / r64["steps_per_s"], 4),
+            "fwd_adj_speedup_vs_fp64": round(r32["fwd_adj_steps_per_s"] / r64["fwd_adj_steps_per_s"], 4),
+            "equal_error": ee,
+            "kernels": r32["kernels"],
+        }
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -199,9 +352,7 @@ def main():
         torch.cuda.synchronize()
         result["calibration_copy_bytes"] = 2 * src.numel() * 8      # read + write
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(wl, state0)
-    if not np.all(np.isfinite(x.cpu().numpy())):
-        raise RuntimeError("non-finite state after the timed steps")
+        result["cpu_baseline"] = cpu_baseline(wl, W.initial_state(wl))
     print(json.dumps(result))
 
 

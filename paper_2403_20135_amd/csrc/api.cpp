@@ -147,6 +147,7 @@ struct sdc_ctx {
     std::vector<void*> allocs;
     long long bytes = 0, table_bytes = 0;
     double *mu = nullptr, *w = nullptr, *P = nullptr, *H = nullptr, *tau = nullptr, *Q = nullptr;
+    float *P32 = nullptr, *H32 = nullptr;   // FP32 copies of the tables (precision SDC_FP32_MFMA)
     double *inv_lap = nullptr, *neg_lap = nullptr;
     long long* toff = nullptr;
     int* rowoff = nullptr;
@@ -221,6 +222,8 @@ struct sdc_ctx {
         for (auto& v : ev_marks) v.clear();
     }
 
+    Tables tables() const { return Tables{P, H, P32, H32}; }
+
     template <typename T>
     int alloc(T*& p, size_t count, bool table = false) {
         void* q = nullptr;
@@ -270,8 +273,8 @@ int validate_config(const sdc_config* c) {
     FFTPlan pl;
     if (!make_fft_plan(c->nlon, pl) || !fft_length_supported(c->nlon))
         return fail(SDC_EUNSUPPORTED, "nlon=%d is not one of 16..2048 = 2^p or 24..1536 = 3*2^p", c->nlon);
-    if (c->precision != SDC_FP64)
-        return fail(SDC_EUNSUPPORTED, "precision=%d is not available in this build", c->precision);
+    if (c->precision == SDC_BF16X3_MFMA)
+        return fail(SDC_EUNSUPPORTED, "precision=%d (BF16x3) is not available in this build", c->precision);
     return SDC_OK;
 }
 
@@ -396,6 +399,12 @@ int setup(sdc_ctx* c) {
     // FP64 setup kernels
     launch_gauss(c->mu, c->w, g.nlat, c->st);
     launch_legendre_tables(c->mu, c->P, c->H, c->toff, g, c->st);
+    if (cf.precision == SDC_FP32_MFMA) {
+        // FP32 copies of the FP64 tables for the Legendre contractions
+        if ((rc = c->alloc(c->P32, tot, true))) return rc;
+        if ((rc = c->alloc(c->H32, tot, true))) return rc;
+        launch_round_tables(c->P, c->H, c->P32, c->H32, tot, c->st);
+    }
     launch_collocation(c->tau, c->Q, cf.M, c->st);
     launch_degree_tables(c->n_of, c->m_of, c->inv_lap, c->neg_lap, g.T, g.radius, c->st);
     HIP_TRY(hipGetLastError());
@@ -410,14 +419,14 @@ int setup(sdc_ctx* c) {
 // by launch_prep_cml).
 void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr) {
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
-    launch_synthesis_swe(c->P, c->H, c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->four,
+    launch_synthesis_swe(c->tables(), c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->four,
                          c->g, c->st);
     c->end(SDC_KERNEL_SYNTHESIS, t);
     t = c->begin(SDC_KERNEL_GRID);
     launch_grid_swe(c->four, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, save, c->g, c->st);
     c->end(SDC_KERNEL_GRID, t);
     t = c->begin(SDC_KERNEL_ANALYSIS);
-    launch_analysis_swe(c->P, c->H, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap, out, c->g,
+    launch_analysis_swe(c->tables(), c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap, out, c->g,
                         c->st);
     c->end(SDC_KERNEL_ANALYSIS, t);
 }
@@ -432,10 +441,10 @@ void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2*
 // out_acc += J_E(u)^T ebar for S states whose stage grid fields are in `save`.
 void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save, double* out_acc) {
     launch_prep_cml_adj(ebar, S, c->cml, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->g.T, c->st);
-    launch_synthesis_adj(c->P, c->H, c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->adj_four5,
+    launch_synthesis_adj(c->tables(), c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->adj_four5,
                          c->g, c->st);
     launch_grid_adj(c->adj_four5, save, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
-    launch_analysis_adjoint(c->P, c->H, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->inv_lap, out_acc,
+    launch_analysis_adjoint(c->tables(), c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->inv_lap, out_acc,
                             c->g, c->st);
 }
 

@@ -89,20 +89,30 @@ void launch_degree_tables(int* n_of, int* m_of, double* inv_lap, double* neg_lap
                           double radius, hipStream_t st);
 
 // legendre.hip
+// The Legendre tables of the SWE kernels: FP64, and FP32 copies when the handle computes its
+// Legendre contractions in FP32 (P32 != nullptr selects them).
+struct Tables {
+    const double* P;
+    const double* H;
+    const float* P32;
+    const float* H32;
+};
 // Synthesis tasks: (m, latitude tile) per workgroup, XCD-ordered; x < 0 = pad.
-void launch_synthesis_swe(const double* P, const double* H, const long long* toff,
-                          const int* rowoff, const int2* tasks, int ntasks, const double* cml,
-                          int nstates, double2* four, const Geom& g, hipStream_t st);
+void launch_synthesis_swe(const Tables& tb, const long long* toff, const int* rowoff,
+                          const int2* tasks, int ntasks, const double* cml, int nstates,
+                          double2* four, const Geom& g, hipStream_t st);
 // Analysis tasks: (m, p, first row, valid) per workgroup, XCD-ordered.
-void launch_analysis_swe(const double* P, const double* H, const long long* toff,
-                         const int4* tasks, int nwg, const double* G, int nstates,
-                         const double* neg_lap, double* out, const Geom& g, hipStream_t st);
+void launch_analysis_swe(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
+                         const double* G, int nstates, const double* neg_lap, double* out,
+                         const Geom& g, hipStream_t st);
 void launch_synthesis_scalar(const double* P, const long long* toff, const int2* tasks, int ntasks,
                              const double* spec, int nfields, double2* four, const Geom& g,
                              hipStream_t st);
-void launch_analysis_adjoint(const double* P, const double* H, const long long* toff,
-                             const int4* tasks, int nwg, const double* G, int nstates,
-                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st);
+void launch_analysis_adjoint(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
+                             const double* G, int nstates, const double* inv_lap, double* out_acc,
+                             const Geom& g, hipStream_t st);
+void launch_round_tables(const double* P, const double* H, float* P32, float* H32, long long n,
+                         hipStream_t st);
 void launch_analysis_scalar(const double* P, const long long* toff, const int4* tasks, int ntasks,
                             const double2* ana, int nfields, double* spec, const Geom& g,
                             hipStream_t st);
@@ -157,9 +167,9 @@ void launch_solve(double alpha, const double* beta, double* u, const int* n_of, 
 // adjoint.hip
 void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int* n_of, const int* m_of,
                          const int* rowoff, const double* neg_lap, int ncoef, int T, hipStream_t st);
-void launch_synthesis_adj(const double* P, const double* H, const long long* toff, const int* rowoff,
-                          const int2* tasks, int ntasks, const double* cml, int nstates, double2* four5,
-                          const Geom& g, hipStream_t st);
+void launch_synthesis_adj(const Tables& tb, const long long* toff, const int* rowoff,
+                          const int2* tasks, int ntasks, const double* cml, int nstates,
+                          double2* four5, const Geom& g, hipStream_t st);
 struct AdjUpdateArgs {
     const double* ubar;          // [B][M][3][ncoef] adjoint of this sweep's nodes (or lam: [B][3][ncoef])
     long long ubar_node, ubar_member;

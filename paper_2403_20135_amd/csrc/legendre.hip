@@ -24,6 +24,29 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
 }
 __device__ __forceinline__ v4d zero4() { return (v4d){0.0, 0.0, 0.0, 0.0}; }
 
+// Table precision of the SWE kernels: FP64 (v_mfma_f64_16x16x4f64; the accumulator of lane l
+// holds rows 4r + q) or FP32 (v_mfma_f32_16x16x4f32 with FP32 accumulation; rows 4q + r).  Both
+// take A[i][q] and B[q][i] from lane i + 16 q.  Coefficient columns stay FP64 in memory and are
+// rounded to the table precision as they enter the MFMA.
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <typename TT> struct Mma;
+template <> struct Mma<double> {
+    typedef v4d vec;
+    __device__ static vec zero() { return (v4d){0.0, 0.0, 0.0, 0.0}; }
+    __device__ static vec mma(double a, double b, vec c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static constexpr int row(int r, int q) { return 4 * r + q; }
+};
+template <> struct Mma<float> {
+    typedef v4f vec;
+    __device__ static vec zero() { return (v4f){0.0f, 0.0f, 0.0f, 0.0f}; }
+    __device__ static vec mma(float a, float b, vec c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static constexpr int row(int r, int q) { return 4 * q + r; }
+};
+
 // ---------------------------------------------------------------------------------------------
 // Synthesis (forward SWE and the transposed analysis of the adjoint).
 //
@@ -64,20 +87,22 @@ template <> struct SynTiles<kSynAdjoint> {
     }
 };
 
-template <int NT> struct SynStage {
-    double a[2];             // Pbar, H
-    double b[NT];
+template <typename TT, int NT> struct SynStage {
+    TT a[2];                 // Pbar, H
+    double b[NT];            // rounded to TT at the MFMA (a conversion here would wait for the load)
 };
 
 constexpr int kSynBlock = 128;                   // two waves: the two parities
 
-template <int MODE>
+template <int MODE, typename TT>
 __global__ __launch_bounds__(kSynBlock) void k_synthesis(
-    const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
+    const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int* __restrict__ rowoff, const int2* __restrict__ tasks, const double* __restrict__ cml,
     int nstates, double* __restrict__ four, Geom g) {
     using TL = SynTiles<MODE>;
+    using MM = Mma<TT>;
     constexpr int NT = TL::NT, D = 8;
+    constexpr unsigned tsz = sizeof(TT);
     __shared__ double part[2][NT][4][64];
     const int2 task = tasks[blockIdx.x];
     if (task.x < 0) return;                                  // padding workgroup (uniform)
@@ -93,31 +118,32 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * 8u;
     const unsigned rstride = (unsigned)S * kCmlVals * 8u;           // bytes per cml row
     const int nst = (npk_of(g.T, m, p) + 3) >> 2;                   // 4-row steps of this parity
-    const unsigned tstep = 4u * 16u * 8u, cstep = 4u * rstride;     // bytes per 4-row step
-    const unsigned tlane = ((unsigned)(jt * 4 * nst + q) * 16 + i) * 8u, clane = (unsigned)q * rstride;
+    const unsigned tstep = 4u * 16u * tsz, cstep = 4u * rstride;    // bytes per 4-row step
+    const unsigned tlane = ((unsigned)(jt * 4 * nst + q) * 16 + i) * tsz, clane = (unsigned)q * rstride;
     const char* tP = (const char*)(P + toff[2 * m + p]);
     const char* tH = (const char*)(H + toff[2 * m + p]);
     const char* cb = (const char*)(cml + (size_t)rowoff[2 * m + p] * S * kCmlVals);
     auto ldd = [](const char* base, unsigned off) { return *(const double*)(base + off); };
+    auto ldt = [](const char* base, unsigned off) { return *(const TT*)(base + off); };
 
-    v4d acc[NT];
+    typename MM::vec acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = zero4();
-    auto load = [&](SynStage<NT>& x, int j) {
+    for (int t = 0; t < NT; ++t) acc[t] = MM::zero();
+    auto load = [&](SynStage<TT, NT>& x, int j) {
         const unsigned ot = tlane + (unsigned)j * tstep, oc = clane + (unsigned)j * cstep;
-        x.a[0] = ldd(tP, ot);
-        x.a[1] = ldd(tH, ot);
+        x.a[0] = ldt(tP, ot);
+        x.a[1] = ldt(tH, ot);
 #pragma unroll
         for (int t = 0; t < NT; ++t) x.b[t] = ldd(cb, oc + boff[t]);
     };
-    auto compute = [&](const SynStage<NT>& x) {
+    auto compute = [&](const SynStage<TT, NT>& x) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = mfma_f64(x.a[TL::is_h(t) ? 1 : 0], x.b[t], acc[t]);
+        for (int t = 0; t < NT; ++t) acc[t] = MM::mma(x.a[TL::is_h(t) ? 1 : 0], (TT)x.b[t], acc[t]);
     };
     // Loads past the chain's end re-read its last step (cache hits, results unused): a
     // branch-free loop body lets every stage wait for its own loads only.
     if (nst > 0) {
-        SynStage<NT> st[D];
+        SynStage<TT, NT> st[D];
 #pragma unroll
         for (int u = 0; u < D; ++u) load(st[u], u < nst ? u : nst - 1);
         int j0 = 0;
@@ -136,7 +162,7 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) part[p][t][r][lane] = acc[t][r];
+        for (int r = 0; r < 4; ++r) part[p][t][r][lane] = (double)acc[t][r];
     __syncthreads();
 
     // wave 0: north = even + odd; wave 1: south = even - odd (Pbar tiles), odd - even (H tiles)
@@ -146,14 +172,14 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const double inva = 1.0 / g.radius;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int jh = jt * 16 + 4 * r + q;
+        const int jh = jt * 16 + MM::row(r, q);
         if (s >= S || jh >= g.nh) continue;
         const int j = ns ? g.nlat - 1 - jh : jh;
         double val[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const double e = ns == 0 ? acc[t][r] : part[0][t][r][lane];
-            const double o = ns == 0 ? part[1][t][r][lane] : acc[t][r];
+            const double e = ns == 0 ? (double)acc[t][r] : part[0][t][r][lane];
+            const double o = ns == 0 ? part[1][t][r][lane] : (double)acc[t][r];
             val[t] = ns == 0 ? e + o : (TL::is_h(t) ? o - e : e - o);
         }
         double* base = four + (((size_t)s * TL::NF * g.nlat + j) * g.ms + m) * 2 + (v & 1);
@@ -175,20 +201,28 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     }
 }
 
-void launch_synthesis_swe(const double* P, const double* H, const long long* toff,
-                          const int* rowoff, const int2* tasks, int ntasks, const double* cml,
-                          int nstates, double2* four, const Geom& g, hipStream_t st) {
+void launch_synthesis_swe(const Tables& tb, const long long* toff, const int* rowoff,
+                          const int2* tasks, int ntasks, const double* cml, int nstates,
+                          double2* four, const Geom& g, hipStream_t st) {
     dim3 grid(ntasks, (nstates + 3) / 4);
-    k_synthesis<kSynForward><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates,
-                                                          (double*)four, g);
+    if (tb.P32)
+        k_synthesis<kSynForward, float><<<grid, kSynBlock, 0, st>>>(
+            tb.P32, tb.H32, toff, rowoff, tasks, cml, nstates, (double*)four, g);
+    else
+        k_synthesis<kSynForward, double><<<grid, kSynBlock, 0, st>>>(
+            tb.P, tb.H, toff, rowoff, tasks, cml, nstates, (double*)four, g);
 }
 
-void launch_synthesis_adj(const double* P, const double* H, const long long* toff, const int* rowoff,
-                          const int2* tasks, int ntasks, const double* cml, int nstates, double2* four5,
-                          const Geom& g, hipStream_t st) {
+void launch_synthesis_adj(const Tables& tb, const long long* toff, const int* rowoff,
+                          const int2* tasks, int ntasks, const double* cml, int nstates,
+                          double2* four5, const Geom& g, hipStream_t st) {
     dim3 grid(ntasks, (nstates + 3) / 4);
-    k_synthesis<kSynAdjoint><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates,
-                                                          (double*)four5, g);
+    if (tb.P32)
+        k_synthesis<kSynAdjoint, float><<<grid, kSynBlock, 0, st>>>(
+            tb.P32, tb.H32, toff, rowoff, tasks, cml, nstates, (double*)four5, g);
+    else
+        k_synthesis<kSynAdjoint, double><<<grid, kSynBlock, 0, st>>>(
+            tb.P, tb.H, toff, rowoff, tasks, cml, nstates, (double*)four5, g);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -214,15 +248,17 @@ constexpr int kAnaLat = 4 * kAnaVals + 2;       // LDS doubles per latitude (pad
 constexpr int kAnaBuf = 16 * kAnaLat;           // doubles per LDS block buffer
 constexpr int kAnaChunks = 16 * 2 * kAnaVals;   // double2 chunks per block (16 lat x 4 states x 7)
 
-struct AnaStage {
-    v4d aP, aH;              // table rows, 4 consecutive latitudes per lane group
+template <typename TT> struct AnaStage {
+    typename Mma<TT>::vec aP, aH;   // table rows, 4 consecutive latitudes per lane group
 };
 
-template <int MODE>
+template <int MODE, typename TT>
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
-    const double* __restrict__ P, const double* __restrict__ H, const long long* __restrict__ toff,
+    const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int4* __restrict__ tasks, const double* __restrict__ G, int nstates,
     const double* __restrict__ nscale, double* __restrict__ out, Geom g) {
+    using MM = Mma<TT>;
+    using vec = typename MM::vec;
     constexpr int D = 4;
     __shared__ __align__(16) double gl[2][kAnaBuf + 2];       // + a dummy slot for idle threads
     const int4 task = tasks[blockIdx.x];
@@ -239,8 +275,8 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const int np4 = (np + 3) & ~3;
     // rows past the block's end read its last row; their outputs are dropped
     const int kr = kt + i < np4 ? kt + i : np4 - 1;
-    const double* Pr = P + toff[2 * m + p] + tab_index(np4, kr, 4 * q);
-    const double* Hr = H + toff[2 * m + p] + tab_index(np4, kr, 4 * q);
+    const TT* Pr = P + toff[2 * m + p] + tab_index(np4, kr, 4 * q);
+    const TT* Hr = H + toff[2 * m + p] + tab_index(np4, kr, 4 * q);
     const size_t bstride = (size_t)np4 * 16;                 // doubles per 16-latitude tile
     const int nb = g.nhp >> 4;
 
@@ -290,20 +326,20 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         }
     };
 
-    v4d accP[2] = {zero4(), zero4()}, accH[2] = {zero4(), zero4()};
-    auto load = [&](AnaStage& x, int b) {
-        x.aP = *(const v4d*)(Pr + b * bstride);
-        x.aH = *(const v4d*)(Hr + b * bstride);
+    vec accP[2] = {MM::zero(), MM::zero()}, accH[2] = {MM::zero(), MM::zero()};
+    auto load = [&](AnaStage<TT>& x, int b) {
+        x.aP = *(const vec*)(Pr + b * bstride);
+        x.aH = *(const vec*)(Hr + b * bstride);
     };
     // k-step qq of a block contracts latitude 4 q + qq of the block (lane group q)
-    auto compute = [&](const AnaStage& x, const double* lb) {
+    auto compute = [&](const AnaStage<TT>& x, const double* lb) {
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             const double* lq = lb + (4 * q + qq) * kAnaLat;
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                accP[t] = mfma_f64(x.aP[qq], lq[offP[t]], accP[t]);
-                accH[t] = mfma_f64(x.aH[qq], lq[offH[t]], accH[t]);
+                accP[t] = MM::mma(x.aP[qq], (TT)lq[offP[t]], accP[t]);
+                accH[t] = MM::mma(x.aH[qq], (TT)lq[offH[t]], accH[t]);   // dropped for kinds without H
             }
         }
     };
@@ -313,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     gstore(gr, 0, 0);
     __syncthreads();
     if (active) {
-        AnaStage st[D];
+        AnaStage<TT> st[D];
 #pragma unroll
         for (int u = 0; u < D; ++u) load(st[u], u < nb ? u : nb - 1);
         int b0 = 0;
@@ -355,9 +391,9 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         const int s = s0 + 2 * t + (i >> 3);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double val = has_h ? accP[t][r] + accH[t][r] : accP[t][r];
+            const double val = has_h ? (double)accP[t][r] + (double)accH[t][r] : (double)accP[t][r];
             const double right = __shfl_down(val, 2, 64);    // the kind one to the right
-            const int kk = kt + 4 * r + q;
+            const int kk = kt + MM::row(r, q);
             if (kk >= np || s >= S) continue;
             const int n = m + p + 2 * kk;
             if constexpr (MODE == kAnaForward) {
@@ -375,18 +411,44 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     }
 }
 
-void launch_analysis_swe(const double* P, const double* H, const long long* toff,
-                         const int4* tasks, int nwg, const double* G, int nstates,
-                         const double* neg_lap, double* out, const Geom& g, hipStream_t st) {
+void launch_analysis_swe(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
+                         const double* G, int nstates, const double* neg_lap, double* out,
+                         const Geom& g, hipStream_t st) {
     dim3 grid(nwg, (nstates + 3) / 4);
-    k_analysis_swe<kAnaForward><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, G, nstates, neg_lap, out, g);
+    if (tb.P32)
+        k_analysis_swe<kAnaForward, float><<<grid, kBlock, 0, st>>>(tb.P32, tb.H32, toff, tasks, G,
+                                                                    nstates, neg_lap, out, g);
+    else
+        k_analysis_swe<kAnaForward, double><<<grid, kBlock, 0, st>>>(tb.P, tb.H, toff, tasks, G,
+                                                                     nstates, neg_lap, out, g);
 }
 
-void launch_analysis_adjoint(const double* P, const double* H, const long long* toff,
-                             const int4* tasks, int nwg, const double* G, int nstates,
-                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st) {
+void launch_analysis_adjoint(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
+                             const double* G, int nstates, const double* inv_lap, double* out_acc,
+                             const Geom& g, hipStream_t st) {
     dim3 grid(nwg, (nstates + 3) / 4);
-    k_analysis_swe<kAnaAdjoint><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, G, nstates, inv_lap, out_acc, g);
+    if (tb.P32)
+        k_analysis_swe<kAnaAdjoint, float><<<grid, kBlock, 0, st>>>(tb.P32, tb.H32, toff, tasks, G,
+                                                                    nstates, inv_lap, out_acc, g);
+    else
+        k_analysis_swe<kAnaAdjoint, double><<<grid, kBlock, 0, st>>>(tb.P, tb.H, toff, tasks, G,
+                                                                     nstates, inv_lap, out_acc, g);
+}
+
+// FP32 copies of the FP64 tables (same layout), for the FP32 precision mode.
+__global__ __launch_bounds__(kBlock) void k_round_tables(const double* __restrict__ P,
+                                                          const double* __restrict__ H,
+                                                          float* __restrict__ P32,
+                                                          float* __restrict__ H32, long long n) {
+    const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    P32[k] = (float)P[k];
+    H32[k] = (float)H[k];
+}
+
+void launch_round_tables(const double* P, const double* H, float* P32, float* H32, long long n,
+                         hipStream_t st) {
+    k_round_tables<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(P, H, P32, H32, n);
 }
 
 // ---------------------------------------------------------------------------------------------

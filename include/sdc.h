@@ -58,9 +58,13 @@ typedef enum {
  * always generated and kept in FP64. */
 typedef enum {
     SDC_FP64 = 0,             /* FP64 MFMA, FP64 tables */
-    SDC_FP32_MFMA = 1,        /* FP32 MFMA on FP32-rounded tables, FP32 accumulation */
+    SDC_FP32_MFMA = 1,        /* FP32 MFMA (16x16x4) on FP32-rounded copies of the FP64 tables, the
+                                 spectral / Fourier columns rounded to FP32 as they enter the MFMA,
+                                 FP32 accumulation; every other step of sdc_step stays FP64 */
     SDC_BF16X3_MFMA = 2       /* operands split into three BF16 terms each, BF16 MFMA products,
-                                 FP32 accumulation */
+                                 FP32 accumulation: sdc_init returns SDC_EUNSUPPORTED in this build
+                                 (one member at T255 is table-bandwidth-bound, where three BF16
+                                 terms move more bytes than one FP32 value) */
 } sdc_precision;
 
 typedef struct {

@@ -103,7 +103,7 @@ def roofline_entry(flops, nbytes, secs, launches, precision):
     return e
 
 
-def measure(wl, precision, steps, warmup, with_kernels=True):
+def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
     """Graph-replay steps/s, per-kernel HIP-event timing over eager steps, fwd+adj steps/s."""
     import torch
     from paper_2403_20135_amd.api import SDC
@@ -146,6 +146,9 @@ def measure(wl, precision, steps, warmup, with_kernels=True):
                           for name, (ms, launches) in kt.items()}
         out["kernel_ms"] = {name: ms for name, (ms, _) in kt.items()}
 
+    if not with_adjoint:
+        sdc.close()
+        return out
     # forward + adjoint: every forward step keeps its input (one checkpoint per step), then the
     # adjoint steps run in reverse, each recomputing its step's stages from the checkpoint
     ckpt = torch.empty((steps,) + tuple(x.shape), dtype=torch.float64, device="cuda")
@@ -284,6 +287,8 @@ def main():
     ap.add_argument("--workload", default="t255_m4k4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="measure the plain FP64 path only")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the forward+adjoint region (counter runs of the forward kernels)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a reference kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -302,7 +307,7 @@ def main():
 
     wl = W.WORKLOADS[args.workload]
     mb = wl.members[0]
-    r64 = measure(wl, "fp64", args.steps, args.warmup)
+    r64 = measure(wl, "fp64", args.steps, args.warmup, with_adjoint=not args.no_adjoint)
     kernels = r64["kernels"]
     dom = max(r64["kernel_ms"], key=lambda k: r64["kernel_ms"][k])
     d = kernels[dom]
@@ -326,8 +331,8 @@ def main():
         "config": {"workload": wl.name, "T": mb.T, "nlat": mb.nlat, "nlon": mb.nlon, "M": wl.M,
                    "K": wl.K, "dt": mb.dt, "batch": 1, "precision": "fp64"},
         "eager_ms_per_step": round(r64["eager_ms_per_step"], 4),
-        "fwd_adj_steps_per_s": round(r64["fwd_adj_steps_per_s"], 3),
-        "fwd_adj_ms_per_step": round(r64["fwd_adj_ms_per_step"], 4),
+        "fwd_adj_steps_per_s": round(r64["fwd_adj_steps_per_s"], 3) if "fwd_adj_steps_per_s" in r64 else None,
+        "fwd_adj_ms_per_step": round(r64["fwd_adj_ms_per_step"], 4) if "fwd_adj_ms_per_step" in r64 else None,
         "roofline": roofline,
         "kernels": kernels,
     }

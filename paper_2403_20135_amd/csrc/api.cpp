@@ -384,7 +384,7 @@ int setup(sdc_ctx* c) {
     if ((rc = c->alloc(c->E0, st_d * cf.batch))) return rc;
     if ((rc = c->alloc(c->cml, (size_t)g.nrows * c->smax * kCmlVals))) return rc;
     if ((rc = c->alloc(c->four, (size_t)c->smax * kSynFields * g.nlat * g.ms))) return rc;
-    if ((rc = c->alloc(c->G, (size_t)(g.T + 1) * 2 * g.nhp * c->smax * kAnaVals))) return rc;
+    if ((rc = c->alloc(c->G, (size_t)(g.T + 1) * 2 * g.nhp * c->smax * kAnaStride))) return rc;
 
     // host-computed index data and twiddles e^{-2 pi i k/nlon} (long double, rounded once)
     std::vector<double2> tw(cf.nlon);

@@ -71,11 +71,18 @@ __device__ inline void cml_clear_pad(double* cml, size_t row0, int kk, int np, s
 // Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V, layout
 // four[s][field][lat][m].
 constexpr int kSynFields = 4;
-// Analysis input written by the grid kernel, per (m, parity p, northern latitude jh, state s):
+// Analysis input written by the grid kernel, per (northern latitude jh, m, parity p, state s):
 // 14 doubles = 7 complex columns, Pbar parts (zeta, delta, kinetic energy, Phi') then H parts
-// (zeta, delta, Phi'), already combined into the north +- south sums of parity p and weighted:
-//   G[(((m*2 + p) * nhp + jh) * S + s) * 14 + c]   (rows jh >= nh are never read).
+// (zeta, delta, Phi'), already combined into the north +- south sums of parity p and weighted,
+// padded to kAnaStride doubles (one 128-byte line, written whole with zeros in the pad).  The
+// latitude is outermost, so a grid workgroup (one latitude pair, one state) writes whole lines
+// into one contiguous slab and the states of a latitude complete each other's rows:
+//   G[ana_index(T, S, jh, m, p, s) + c]
 constexpr int kAnaVals = 14;
+constexpr int kAnaStride = 16;
+__host__ __device__ inline size_t ana_index(int T, int S, int jh, int m, int p, int s) {
+    return ((((size_t)jh * (T + 1) + m) * 2 + p) * S + s) * kAnaStride;
+}
 
 // ---------------------------------------------------------------------------------------------
 // Launchers (defined in the .hip files; all enqueue on `st`)

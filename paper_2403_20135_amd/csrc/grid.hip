@@ -3,9 +3,11 @@
 // Each workgroup owns one pair of mirror latitudes (north j, south nlat-1-j).  A real field on
 // the two rows is carried as one complex signal z = north + i south, so one complex FFT of
 // length nlon serves both rows.  The FFT is a Stockham autosort transform with radices 3, 16, 8,
-// 4 and 2 (nlon = 2^p or 3*2^p), all signals of the workgroup advanced together, one LDS buffer
-// per signal (values staged in registers between the read and write halves of a stage).  Radix
-// 16 and 8 stages keep the number of LDS passes and barriers low (nlon = 768 = 3 x 16 x 16).
+// 4 and 2 (nlon = 2^p or 3*2^p), one LDS buffer per signal (values staged in registers between
+// the read and write halves of a stage).  In the shallow-water grid kernels each signal is carried
+// through all stages by one wave without workgroup barriers; the scalar transforms advance all
+// signals of a workgroup together.  Radix 16 and 8 stages keep the number of LDS passes low
+// (nlon = 768 = 3 x 16 x 16).
 #include "common.h"
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -186,6 +188,66 @@ __device__ __forceinline__ void fft_lds(double2* buf, int F, const double2* tw) 
     for (int f0 = 0; f0 < F; f0 += FC) fft_stages<N, 0, 1, INV>(buf + f0 * N, F - f0 < FC ? F - f0 : FC, tw);
 }
 
+// Wave-level transforms: one wave (64 lanes) carries one signal through every stage with no
+// workgroup barrier.  The LDS operations of a wave execute in issue order, so all reads of a stage
+// are done before its writes; the fences keep the compiler from moving LDS accesses across the
+// read/write boundary (other lanes' data is involved).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int R, int N, int NS, bool INV>
+__device__ __forceinline__ void fft_wave_stage(double2* buf, const double2* tw, int lane) {
+    constexpr int nb = N / R;
+    constexpr int MAXT = (nb + 63) / 64;
+    constexpr int tstep = N / (NS * R);
+    double2 v[MAXT][R];
+#pragma unroll
+    for (int tt = 0; tt < MAXT; ++tt) {
+        const int j = lane + 64 * tt, k = j % NS;
+        if (j < nb) {
+            const double2* src = buf + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[tt][r] = src[r * nb];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                double2 w = tw[r * k * tstep];
+                if (INV) w.y = -w.y;
+                v[tt][r] = cmul(v[tt][r], w);
+            }
+            dft_small<R>(v[tt], INV);
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int tt = 0; tt < MAXT; ++tt) {
+        const int j = lane + 64 * tt, k = j % NS;
+        if (j < nb) {
+            double2* dst = buf + (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * NS] = v[tt][r];
+        }
+    }
+    wave_lds_sync();
+}
+
+template <int N, int S, int NS, bool INV>
+__device__ __forceinline__ void fft_wave_stages(double2* buf, const double2* tw, int lane) {
+    if constexpr (S < fft_nst(N)) {
+        constexpr int R = fft_radix(N, S);
+        fft_wave_stage<R, N, NS, INV>(buf, tw, lane);
+        fft_wave_stages<N, S + 1, NS * R, INV>(buf, tw, lane);
+    }
+}
+
+// Unnormalised DFT of the signal of length N at buf by the calling wave alone.
+template <int N, bool INV>
+__device__ __forceinline__ void fft_wave(double2* buf, const double2* tw, int lane) {
+    fft_wave_stages<N, 0, 1, INV>(buf, tw, lane);
+}
+
 bool fft_length_supported(int n) { return fft_nst(n) > 0; }
 
 // calls BODY(N) with N the compile-time FFT length equal to the runtime value n
@@ -224,6 +286,52 @@ __device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, do
     B = make_double2(0.5 * (w.y + c.y), -0.5 * (w.x - c.x));
 }
 
+// Twiddles and the packed spectra (pack_pair) of F Fourier fields of one latitude pair, staged
+// into LDS with all global loads of a chunk issued before its LDS stores (one memory round trip
+// per chunk of 3 x kGridBlock points instead of one per field and point).
+constexpr int kGridBlock = 320;
+
+template <int N, int F>
+__device__ __forceinline__ void stage_inputs(double2* buf, double2* twl, const double2* __restrict__ tw,
+                                             const double2* __restrict__ fs, size_t fstride, int jN,
+                                             int jS, int T, int ms) {
+    constexpr int KP = 3;
+    for (int k0 = 0; k0 < N; k0 += KP * kGridBlock) {
+        double2 twv[KP], xv[F][KP], yv[F][KP];
+        int src[KP];
+#pragma unroll
+        for (int kk = 0; kk < KP; ++kk) {
+            const int k = k0 + threadIdx.x + kk * kGridBlock;
+            const int kc = k < N ? k : 0;
+            src[kk] = kc <= T ? kc : (kc >= N - T ? N - kc : 0);
+            twv[kk] = tw[kc];
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+            for (int kk = 0; kk < KP; ++kk) {
+                xv[f][kk] = fs[f * fstride + (size_t)jN * ms + src[kk]];
+                yv[f][kk] = fs[f * fstride + (size_t)jS * ms + src[kk]];
+            }
+#pragma unroll
+        for (int kk = 0; kk < KP; ++kk) {
+            const int k = k0 + threadIdx.x + kk * kGridBlock;
+            if (k >= N) continue;
+            twl[k] = twv[kk];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const double2 X = xv[f][kk], Y = yv[f][kk];
+                double2 z;
+                if (k == 0) z = make_double2(X.x, Y.x);
+                else if (k <= T) z = make_double2(X.x - Y.y, X.y + Y.x);
+                else if (k >= N - T) z = make_double2(X.x + Y.y, -X.y + Y.x);
+                else z = make_double2(0.0, 0.0);
+                buf[f * N + k] = z;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Fused grid step of f_E for one latitude pair of one state:
 //   inverse FFT of zeta, Phi', U, V -> grid products
@@ -232,10 +340,13 @@ __device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, do
 //   Pbar columns: -i m A g, i m B g, E w, -i m C g;  H columns: B g, A g, D g
 //   with g = w / (a (1-mu^2)), Fourier coefficients normalised by 1/nlon.
 // Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of (latitude, state) tasks,
-// states fastest, so the partial rows of the analysis input meet in one L2.
+// states fastest, so the rows of the analysis input meet in one L2.  Five waves: wave f < 4
+// transforms field f back to the grid, wave f < 5 transforms product f forward; only the hand-offs
+// between the phases are workgroup barriers.  Every analysis row is written as a whole 128-byte
+// line (14 values and 2 zeros).
 // ---------------------------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_grid_swe(
+__global__ __launch_bounds__(kGridBlock) void k_grid_swe(
     const double2* __restrict__ four, double* __restrict__ G, const double* __restrict__ mu,
     const double* __restrict__ w, const double2* __restrict__ tw, double two_omega,
     int nstates, double2* __restrict__ save, Geom g) {
@@ -249,25 +360,21 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
     const int jN = jh, jS = g.nlat - 1 - jh;
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four + (size_t)s * kSynFields * fstride;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double2* twl = buf + 5 * N;
-    for (int k = threadIdx.x; k < N; k += kBlock) twl[k] = tw[k];
-    for (int f = 0; f < kSynFields; ++f) {
-        const double2* xn = fs + f * fstride + (size_t)jN * g.ms;
-        const double2* ys = fs + f * fstride + (size_t)jS * g.ms;
-        for (int k = threadIdx.x; k < N; k += kBlock) buf[f * N + k] = pack_pair(xn, ys, k, N, T);
-    }
+    stage_inputs<N, kSynFields>(buf, twl, tw, fs, fstride, jN, jS, T, g.ms);
     __syncthreads();
-    // signals advanced two or three at a time to bound register use
-    fft_lds<N, true>(buf, kSynFields, twl);
+    if (wave < kSynFields) fft_wave<N, true>(buf + wave * N, twl, lane);
+    __syncthreads();
     if (save) {      // grid values of zeta, Phi', U, V (north, south) for the adjoint
         for (int f = 0; f < kSynFields; ++f)
-            for (int k = threadIdx.x; k < N; k += kBlock)
+            for (int k = threadIdx.x; k < N; k += kGridBlock)
                 save[((size_t)(s * kSynFields + f) * g.nh + jh) * N + k] = buf[f * N + k];
     }
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;
     const double ke = 0.5 / ((1.0 - x) * (1.0 + x));
-    for (int k = threadIdx.x; k < N; k += kBlock) {
+    for (int k = threadIdx.x; k < N; k += kGridBlock) {
         const double2 zeta = buf[k], phi = buf[N + k], U = buf[2 * N + k], V = buf[3 * N + k];
         const double qn = zeta.x + fN, qs = zeta.y + fS;
         buf[k] = make_double2(qn * U.x, qs * U.y);
@@ -277,13 +384,14 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
         buf[4 * N + k] = make_double2((U.x * U.x + V.x * V.x) * ke, (U.y * U.y + V.y * V.y) * ke);
     }
     __syncthreads();
-    fft_lds<N, false>(buf, 5, twl);
+    fft_wave<N, false>(buf + wave * N, twl, lane);
+    __syncthreads();
     const double invN = 1.0 / N;
     const double wt = w[jN];
     const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
     const double we = wt * invN;
-    const size_t jstride = (size_t)nstates * kAnaVals;
-    for (int m = threadIdx.x; m <= T; m += kBlock) {
+    const double2 z2 = make_double2(0.0, 0.0);
+    for (int m = threadIdx.x; m <= T; m += kGridBlock) {
         double2 AN, AS, BN, BS, CN, CS, DN, DS, EN, ES;
         unpack_pair(buf, m, N, AN, AS);
         unpack_pair(buf + N, m, N, BN, BS);
@@ -297,8 +405,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
         const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
         const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
         const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
-        double2* o0 = reinterpret_cast<double2*>(G + ((size_t)(m * 2 + 0) * g.nhp + jh) * jstride + (size_t)s * kAnaVals);
-        double2* o1 = reinterpret_cast<double2*>(G + ((size_t)(m * 2 + 1) * g.nhp + jh) * jstride + (size_t)s * kAnaVals);
+        double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
+        double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
         // -i m X g = (m g X.y, -m g X.x); i m X g = (-m g X.y, m g X.x)
         // parity 0 (n-m even): Pbar pairs with symmetric, H with antisymmetric sums
         o0[0] = make_double2(mg * As.y, -mg * As.x);
@@ -308,6 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
         o0[4] = make_double2(gg * Ba.x, gg * Ba.y);
         o0[5] = make_double2(gg * Aa.x, gg * Aa.y);
         o0[6] = make_double2(gg * Da.x, gg * Da.y);
+        o0[7] = z2;
         // parity 1 (n-m odd): Pbar with antisymmetric, H with symmetric sums
         o1[0] = make_double2(mg * Aa.y, -mg * Aa.x);
         o1[1] = make_double2(-mg * Ba.y, mg * Ba.x);
@@ -316,6 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_swe(
         o1[4] = make_double2(gg * Bs.x, gg * Bs.y);
         o1[5] = make_double2(gg * As.x, gg * As.y);
         o1[6] = make_double2(gg * Ds.x, gg * Ds.y);
+        o1[7] = z2;
     }
 }
 
@@ -325,7 +435,7 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
     const size_t lds = (size_t)6 * plan.n * sizeof(double2);
-#define LAUNCH(NN) k_grid_swe<NN><<<nblk, kBlock, lds, st>>>(four, G, mu, w, tw, two_omega, nstates, save, g)
+#define LAUNCH(NN) k_grid_swe<NN><<<nblk, kGridBlock, lds, st>>>(four, G, mu, w, tw, two_omega, nstates, save, g)
     FFT_DISPATCH(plan.n, LAUNCH)
 #undef LAUNCH
 }
@@ -339,7 +449,7 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
 // combined into north +- south sums per parity (Pbar: + for even n-m; H: - for even n-m).
 // ---------------------------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_grid_adj(
+__global__ __launch_bounds__(kGridBlock) void k_grid_adj(
     const double2* __restrict__ four5, const double2* __restrict__ save, double* __restrict__ G,
     const double* __restrict__ mu, const double* __restrict__ w, const double2* __restrict__ tw,
     double two_omega, int nstates, Geom g) {
@@ -353,15 +463,12 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(
     const int jN = jh, jS = g.nlat - 1 - jh;
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four5 + (size_t)s * 5 * fstride;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double2* twl = buf + 5 * N;
-    for (int k = threadIdx.x; k < N; k += kBlock) twl[k] = tw[k];
-    for (int f = 0; f < 5; ++f) {
-        const double2* xn = fs + f * fstride + (size_t)jN * g.ms;
-        const double2* ys = fs + f * fstride + (size_t)jS * g.ms;
-        for (int k = threadIdx.x; k < N; k += kBlock) buf[f * N + k] = pack_pair(xn, ys, k, N, T);
-    }
+    stage_inputs<N, 5>(buf, twl, tw, fs, fstride, jN, jS, T, g.ms);
     __syncthreads();
-    fft_lds<N, true>(buf, 5, twl);
+    fft_wave<N, true>(buf + wave * N, twl, lane);
+    __syncthreads();
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;
     const double om2 = (1.0 - x) * (1.0 + x);
@@ -369,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(
     const double gA = w[jN] / (om2 * g.radius * N), gE = w[jN] / N;
     const double2* sv = save + ((size_t)(s * kSynFields) * g.nh + jh) * N;
     const size_t sstride = (size_t)g.nh * N;
-    for (int k = threadIdx.x; k < N; k += kBlock) {
+    for (int k = threadIdx.x; k < N; k += kGridBlock) {
         const double2 a = buf[k], b = buf[N + k], c = buf[2 * N + k], d = buf[3 * N + k], e = buf[4 * N + k];
         const double2 zeta = sv[k], phi = sv[sstride + k], U = sv[2 * sstride + k], V = sv[3 * sstride + k];
         const double An = gA * a.x, As = gA * a.y, Bn = gA * b.x, Bs = gA * b.y;
@@ -382,10 +489,11 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(
         buf[3 * N + k] = make_double2(Bn * qn + Dn * phi.x + En * V.x, Bs * qs + Ds * phi.y + Es * V.y);
     }
     __syncthreads();
-    fft_lds<N, false>(buf, kSynFields, twl);
-    const size_t jstride = (size_t)nstates * kAnaVals;
+    if (wave < kSynFields) fft_wave<N, false>(buf + wave * N, twl, lane);
+    __syncthreads();
     const double inva = 1.0 / g.radius;
-    for (int m = threadIdx.x; m <= T; m += kBlock) {
+    const double2 z2 = make_double2(0.0, 0.0);
+    for (int m = threadIdx.x; m <= T; m += kGridBlock) {
         double2 ZN, ZS, PN, PS, UN, US, VN, VS;
         unpack_pair(buf, m, N, ZN, ZS);
         unpack_pair(buf + N, m, N, PN, PS);
@@ -394,8 +502,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(
         const double sm = m == 0 ? 1.0 : 2.0, sa = sm * inva, ms = (double)m * sa;
         const double2 Zs = cadd(ZN, ZS), Za = csub(ZN, ZS), Ps = cadd(PN, PS), Pa = csub(PN, PS);
         const double2 Us = cadd(UN, US), Ua = csub(UN, US), Vs = cadd(VN, VS), Va = csub(VN, VS);
-        double2* o0 = reinterpret_cast<double2*>(G + ((size_t)(m * 2 + 0) * g.nhp + jh) * jstride + (size_t)s * kAnaVals);
-        double2* o1 = reinterpret_cast<double2*>(G + ((size_t)(m * 2 + 1) * g.nhp + jh) * jstride + (size_t)s * kAnaVals);
+        double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
+        double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
         // -i m X (s_m/a) = (m sa X.y, -m sa X.x)
         o0[0] = make_double2(sm * Zs.x, sm * Zs.y);
         o0[1] = make_double2(ms * Vs.y, -ms * Vs.x);
@@ -403,12 +511,16 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(
         o0[3] = make_double2(sm * Ps.x, sm * Ps.y);
         o0[4] = make_double2(-sa * Ua.x, -sa * Ua.y);
         o0[5] = make_double2(sa * Va.x, sa * Va.y);
+        o0[6] = z2;
+        o0[7] = z2;
         o1[0] = make_double2(sm * Za.x, sm * Za.y);
         o1[1] = make_double2(ms * Va.y, -ms * Va.x);
         o1[2] = make_double2(ms * Ua.y, -ms * Ua.x);
         o1[3] = make_double2(sm * Pa.x, sm * Pa.y);
         o1[4] = make_double2(-sa * Us.x, -sa * Us.y);
         o1[5] = make_double2(sa * Vs.x, sa * Vs.y);
+        o1[6] = z2;
+        o1[7] = z2;
     }
 }
 
@@ -418,7 +530,7 @@ void launch_grid_adj(const double2* four5, const double2* save, double* G, const
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
     const size_t lds = (size_t)6 * plan.n * sizeof(double2);
-#define LAUNCH(NN) k_grid_adj<NN><<<nblk, kBlock, lds, st>>>(four5, save, G, mu, w, tw, two_omega, nstates, g)
+#define LAUNCH(NN) k_grid_adj<NN><<<nblk, kGridBlock, lds, st>>>(four5, save, G, mu, w, tw, two_omega, nstates, g)
     FFT_DISPATCH(plan.n, LAUNCH)
 #undef LAUNCH
 }

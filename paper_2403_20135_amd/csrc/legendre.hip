@@ -296,9 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     }
 
     // cooperative copy of a G block into LDS: thread tid moves chunks tid and tid + 256
-    const size_t jstride = (size_t)S * kAnaVals;
-    const double* gsrc = G + (size_t)(m * 2 + p) * g.nhp * jstride + (size_t)s0 * kAnaVals;
-    int clat[2], cw[2], cdst[2];
+    const size_t jstride = ana_index(g.T, S, 1, 0, 0, 0);           // doubles per latitude
+    const double* gsrc = G + ana_index(g.T, S, 0, m, p, s0);
+    // chunk c: latitude c / 28 of the block, state cw / 7, values 2 (cw % 7), 2 (cw % 7) + 1
+    int clat[2], cw[2], csrc[2], cdst[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int c = tid + kBlock * k;
@@ -306,6 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         cw[k] = c % (2 * kAnaVals);
         const bool ok = c < kAnaChunks && cw[k] < nsg * (kAnaVals / 2);
         if (!ok) { clat[k] = 0; cw[k] = 0; }
+        csrc[k] = (cw[k] / (kAnaVals / 2)) * kAnaStride + 2 * (cw[k] % (kAnaVals / 2));
         cdst[k] = ok ? clat[k] * kAnaLat + 2 * cw[k] : kAnaBuf;   // idle: the dummy slot
     }
     auto gload = [&](double2 (&r)[2], int b) {
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         for (int k = 0; k < 2; ++k) {
             int jh = 16 * b + clat[k];
             jh = jh < g.nh ? jh : g.nh - 1;
-            r[k] = *(const double2*)(gsrc + (size_t)jh * jstride + 2 * cw[k]);
+            r[k] = *(const double2*)(gsrc + (size_t)jh * jstride + csrc[k]);
         }
     };
     // latitudes past nh are stored as zeros (their table entries are zero as well)

@@ -410,7 +410,7 @@ int setup(sdc_ctx* c) {
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->st));
 
-    const size_t lds = (size_t)6 * cf.nlon * sizeof(double2);
+    const size_t lds = (size_t)4 * cf.nlon * sizeof(double2);      // four signals per grid workgroup
     if (lds > 65536) HIP_TRY(grid_set_lds_limit(cf.nlon, lds));
     return SDC_OK;
 }

@@ -211,11 +211,15 @@ __device__ __forceinline__ void fft_wave_stage(double2* buf, const double2* tw, 
             const double2* src = buf + j;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[tt][r] = src[r * nb];
+            // twiddles w^(r k) for r >= 2 as powers of w^k (one table read per butterfly instead
+            // of R - 1; the products add a few ulps, far below the transform's own rounding)
+            double2 w1 = tw[k * tstep];
+            if (INV) w1.y = -w1.y;
+            double2 wr = w1;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                double2 w = tw[r * k * tstep];
-                if (INV) w.y = -w.y;
-                v[tt][r] = cmul(v[tt][r], w);
+                if (r > 1) wr = cmul(wr, w1);
+                v[tt][r] = cmul(v[tt][r], wr);
             }
             dft_small<R>(v[tt], INV);
         }
@@ -286,25 +290,24 @@ __device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, do
     B = make_double2(0.5 * (w.y + c.y), -0.5 * (w.x - c.x));
 }
 
-// Twiddles and the packed spectra (pack_pair) of F Fourier fields of one latitude pair, staged
-// into LDS with all global loads of a chunk issued before its LDS stores (one memory round trip
-// per chunk of 3 x kGridBlock points instead of one per field and point).
+// The packed spectra (pack_pair) of F Fourier fields of one latitude pair, staged into LDS with
+// all global loads of a chunk issued before its LDS stores (one memory round trip per chunk of
+// 3 x kGridBlock points instead of one per field and point).
 constexpr int kGridBlock = 320;
+constexpr int kGridSignals = 4;                 // LDS signal buffers of the grid kernels
 
 template <int N, int F>
-__device__ __forceinline__ void stage_inputs(double2* buf, double2* twl, const double2* __restrict__ tw,
-                                             const double2* __restrict__ fs, size_t fstride, int jN,
-                                             int jS, int T, int ms) {
+__device__ __forceinline__ void stage_inputs(double2* buf, const double2* __restrict__ fs,
+                                             size_t fstride, int jN, int jS, int T, int ms) {
     constexpr int KP = 3;
     for (int k0 = 0; k0 < N; k0 += KP * kGridBlock) {
-        double2 twv[KP], xv[F][KP], yv[F][KP];
+        double2 xv[F][KP], yv[F][KP];
         int src[KP];
 #pragma unroll
         for (int kk = 0; kk < KP; ++kk) {
             const int k = k0 + threadIdx.x + kk * kGridBlock;
             const int kc = k < N ? k : 0;
             src[kk] = kc <= T ? kc : (kc >= N - T ? N - kc : 0);
-            twv[kk] = tw[kc];
         }
 #pragma unroll
         for (int f = 0; f < F; ++f)
@@ -317,7 +320,6 @@ __device__ __forceinline__ void stage_inputs(double2* buf, double2* twl, const d
         for (int kk = 0; kk < KP; ++kk) {
             const int k = k0 + threadIdx.x + kk * kGridBlock;
             if (k >= N) continue;
-            twl[k] = twv[kk];
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 const double2 X = xv[f][kk], Y = yv[f][kk];
@@ -340,17 +342,19 @@ __device__ __forceinline__ void stage_inputs(double2* buf, double2* twl, const d
 //   Pbar columns: -i m A g, i m B g, E w, -i m C g;  H columns: B g, A g, D g
 //   with g = w / (a (1-mu^2)), Fourier coefficients normalised by 1/nlon.
 // Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of (latitude, state) tasks,
-// states fastest, so the rows of the analysis input meet in one L2.  Five waves: wave f < 4
-// transforms field f back to the grid, wave f < 5 transforms product f forward; only the hand-offs
-// between the phases are workgroup barriers.  Every analysis row is written as a whole 128-byte
-// line (14 values and 2 zeros).
+// states fastest, so the rows of the analysis input meet in one L2.  Each signal is transformed by
+// one wave; only the hand-offs between phases are workgroup barriers.  LDS holds four signals
+// (three workgroups fit a CU) and the twiddles are read from memory: the fifth product E waits in
+// registers while A..D are transformed and unpacked, then reuses buffer 0, so an analysis row
+// (14 values and 2 zeros, one 128-byte line) is written in two parts from the same workgroup.
 // ---------------------------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
     const double2* __restrict__ four, double* __restrict__ G, const double* __restrict__ mu,
     const double* __restrict__ w, const double2* __restrict__ tw, double two_omega,
     int nstates, double2* __restrict__ save, Geom g) {
-    extern __shared__ double2 buf[];      // 5 signals x N, then the N twiddles
+    extern __shared__ double2 buf[];      // kGridSignals signals x N
+    constexpr int KP = (N + kGridBlock - 1) / kGridBlock;
     const int ntask = g.nh * nstates;
     const int per = (ntask + 7) / 8;
     const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -361,10 +365,9 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four + (size_t)s * kSynFields * fstride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double2* twl = buf + 5 * N;
-    stage_inputs<N, kSynFields>(buf, twl, tw, fs, fstride, jN, jS, T, g.ms);
+    stage_inputs<N, kSynFields>(buf, fs, fstride, jN, jS, T, g.ms);
     __syncthreads();
-    if (wave < kSynFields) fft_wave<N, true>(buf + wave * N, twl, lane);
+    if (wave < kSynFields) fft_wave<N, true>(buf + wave * N, tw, lane);
     __syncthreads();
     if (save) {      // grid values of zeta, Phi', U, V (north, south) for the adjoint
         for (int f = 0; f < kSynFields; ++f)
@@ -374,58 +377,76 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;
     const double ke = 0.5 / ((1.0 - x) * (1.0 + x));
-    for (int k = threadIdx.x; k < N; k += kGridBlock) {
+    double2 ereg[KP];                      // E at this thread's points until buffer 0 is free
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+        const int k = threadIdx.x + kk * kGridBlock;
+        if (k >= N) continue;
         const double2 zeta = buf[k], phi = buf[N + k], U = buf[2 * N + k], V = buf[3 * N + k];
         const double qn = zeta.x + fN, qs = zeta.y + fS;
         buf[k] = make_double2(qn * U.x, qs * U.y);
         buf[N + k] = make_double2(qn * V.x, qs * V.y);
         buf[2 * N + k] = make_double2(phi.x * U.x, phi.y * U.y);
         buf[3 * N + k] = make_double2(phi.x * V.x, phi.y * V.y);
-        buf[4 * N + k] = make_double2((U.x * U.x + V.x * V.x) * ke, (U.y * U.y + V.y * V.y) * ke);
+        ereg[kk] = make_double2((U.x * U.x + V.x * V.x) * ke, (U.y * U.y + V.y * V.y) * ke);
     }
     __syncthreads();
-    fft_wave<N, false>(buf + wave * N, twl, lane);
+    if (wave < 4) fft_wave<N, false>(buf + wave * N, tw, lane);
     __syncthreads();
     const double invN = 1.0 / N;
     const double wt = w[jN];
     const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
     const double we = wt * invN;
     const double2 z2 = make_double2(0.0, 0.0);
+    // -i m X g = (m g X.y, -m g X.x); i m X g = (-m g X.y, m g X.x)
+    // parity 0 (n-m even): Pbar pairs with symmetric, H with antisymmetric sums; parity 1 the reverse
     for (int m = threadIdx.x; m <= T; m += kGridBlock) {
-        double2 AN, AS, BN, BS, CN, CS, DN, DS, EN, ES;
+        double2 AN, AS, BN, BS, CN, CS, DN, DS;
         unpack_pair(buf, m, N, AN, AS);
         unpack_pair(buf + N, m, N, BN, BS);
         unpack_pair(buf + 2 * N, m, N, CN, CS);
         unpack_pair(buf + 3 * N, m, N, DN, DS);
-        unpack_pair(buf + 4 * N, m, N, EN, ES);
         const double mg = (double)m * gg;
         // symmetric (north + south) and antisymmetric (north - south) parts
         const double2 As = cadd(AN, AS), Aa = csub(AN, AS);
         const double2 Bs = cadd(BN, BS), Ba = csub(BN, BS);
         const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
         const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
-        const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
         double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
         double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
-        // -i m X g = (m g X.y, -m g X.x); i m X g = (-m g X.y, m g X.x)
-        // parity 0 (n-m even): Pbar pairs with symmetric, H with antisymmetric sums
         o0[0] = make_double2(mg * As.y, -mg * As.x);
         o0[1] = make_double2(-mg * Bs.y, mg * Bs.x);
-        o0[2] = make_double2(we * Es.x, we * Es.y);
         o0[3] = make_double2(mg * Cs.y, -mg * Cs.x);
         o0[4] = make_double2(gg * Ba.x, gg * Ba.y);
         o0[5] = make_double2(gg * Aa.x, gg * Aa.y);
         o0[6] = make_double2(gg * Da.x, gg * Da.y);
         o0[7] = z2;
-        // parity 1 (n-m odd): Pbar with antisymmetric, H with symmetric sums
         o1[0] = make_double2(mg * Aa.y, -mg * Aa.x);
         o1[1] = make_double2(-mg * Ba.y, mg * Ba.x);
-        o1[2] = make_double2(we * Ea.x, we * Ea.y);
         o1[3] = make_double2(mg * Ca.y, -mg * Ca.x);
         o1[4] = make_double2(gg * Bs.x, gg * Bs.y);
         o1[5] = make_double2(gg * As.x, gg * As.y);
         o1[6] = make_double2(gg * Ds.x, gg * Ds.y);
         o1[7] = z2;
+    }
+    __syncthreads();
+    // E: into buffer 0, forward transform, its slot of every row
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+        const int k = threadIdx.x + kk * kGridBlock;
+        if (k < N) buf[k] = ereg[kk];
+    }
+    __syncthreads();
+    if (wave == 0) fft_wave<N, false>(buf, tw, lane);
+    __syncthreads();
+    for (int m = threadIdx.x; m <= T; m += kGridBlock) {
+        double2 EN, ES;
+        unpack_pair(buf, m, N, EN, ES);
+        const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
+        double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
+        double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
+        o0[2] = make_double2(we * Es.x, we * Es.y);
+        o1[2] = make_double2(we * Ea.x, we * Ea.y);
     }
 }
 
@@ -434,7 +455,7 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
                      double2* save, const Geom& g, hipStream_t st) {
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
-    const size_t lds = (size_t)6 * plan.n * sizeof(double2);
+    const size_t lds = (size_t)kGridSignals * plan.n * sizeof(double2);
 #define LAUNCH(NN) k_grid_swe<NN><<<nblk, kGridBlock, lds, st>>>(four, G, mu, w, tw, two_omega, nstates, save, g)
     FFT_DISPATCH(plan.n, LAUNCH)
 #undef LAUNCH
@@ -447,13 +468,15 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
 // zeta, Phi', U, V, and the columns of the transposed synthesis (s_m = 1, 2 for m = 0, > 0):
 //   Pbar: s_m Z, (s_m/a)(-i m V), (s_m/a)(-i m U), s_m Phi;   H: -(s_m/a) U, (s_m/a) V
 // combined into north +- south sums per parity (Pbar: + for even n-m; H: - for even n-m).
+// With four LDS signals, E^ is transformed first and held in registers during the products.
 // ---------------------------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
     const double2* __restrict__ four5, const double2* __restrict__ save, double* __restrict__ G,
     const double* __restrict__ mu, const double* __restrict__ w, const double2* __restrict__ tw,
     double two_omega, int nstates, Geom g) {
-    extern __shared__ double2 buf[];      // 5 signals x N, then the N twiddles
+    extern __shared__ double2 buf[];      // kGridSignals signals x N
+    constexpr int KP = (N + kGridBlock - 1) / kGridBlock;
     const int ntask = g.nh * nstates;
     const int per = (ntask + 7) / 8;
     const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -464,10 +487,21 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four5 + (size_t)s * 5 * fstride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double2* twl = buf + 5 * N;
-    stage_inputs<N, 5>(buf, twl, tw, fs, fstride, jN, jS, T, g.ms);
+    // E^ first (wave 0), kept in registers at this thread's points, then A^..D^ (waves 0..3)
+    stage_inputs<N, 1>(buf, fs + 4 * fstride, fstride, jN, jS, T, g.ms);
     __syncthreads();
-    fft_wave<N, true>(buf + wave * N, twl, lane);
+    if (wave == 0) fft_wave<N, true>(buf, tw, lane);
+    __syncthreads();
+    double2 ereg[KP];
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+        const int k = threadIdx.x + kk * kGridBlock;
+        ereg[kk] = buf[k < N ? k : 0];
+    }
+    __syncthreads();
+    stage_inputs<N, 4>(buf, fs, fstride, jN, jS, T, g.ms);
+    __syncthreads();
+    if (wave < 4) fft_wave<N, true>(buf + wave * N, tw, lane);
     __syncthreads();
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;
@@ -476,8 +510,11 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
     const double gA = w[jN] / (om2 * g.radius * N), gE = w[jN] / N;
     const double2* sv = save + ((size_t)(s * kSynFields) * g.nh + jh) * N;
     const size_t sstride = (size_t)g.nh * N;
-    for (int k = threadIdx.x; k < N; k += kGridBlock) {
-        const double2 a = buf[k], b = buf[N + k], c = buf[2 * N + k], d = buf[3 * N + k], e = buf[4 * N + k];
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+        const int k = threadIdx.x + kk * kGridBlock;
+        if (k >= N) continue;
+        const double2 a = buf[k], b = buf[N + k], c = buf[2 * N + k], d = buf[3 * N + k], e = ereg[kk];
         const double2 zeta = sv[k], phi = sv[sstride + k], U = sv[2 * sstride + k], V = sv[3 * sstride + k];
         const double An = gA * a.x, As = gA * a.y, Bn = gA * b.x, Bs = gA * b.y;
         const double Cn = gA * c.x, Cs = gA * c.y, Dn = gA * d.x, Ds = gA * d.y;
@@ -489,7 +526,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
         buf[3 * N + k] = make_double2(Bn * qn + Dn * phi.x + En * V.x, Bs * qs + Ds * phi.y + Es * V.y);
     }
     __syncthreads();
-    if (wave < kSynFields) fft_wave<N, false>(buf + wave * N, twl, lane);
+    if (wave < kSynFields) fft_wave<N, false>(buf + wave * N, tw, lane);
     __syncthreads();
     const double inva = 1.0 / g.radius;
     const double2 z2 = make_double2(0.0, 0.0);
@@ -529,7 +566,7 @@ void launch_grid_adj(const double2* four5, const double2* save, double* G, const
                      double two_omega, const Geom& g, hipStream_t st) {
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
-    const size_t lds = (size_t)6 * plan.n * sizeof(double2);
+    const size_t lds = (size_t)kGridSignals * plan.n * sizeof(double2);
 #define LAUNCH(NN) k_grid_adj<NN><<<nblk, kGridBlock, lds, st>>>(four5, save, G, mu, w, tw, two_omega, nstates, g)
     FFT_DISPATCH(plan.n, LAUNCH)
 #undef LAUNCH

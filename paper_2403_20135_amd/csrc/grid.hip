@@ -293,7 +293,7 @@ __device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, do
 // The packed spectra (pack_pair) of F Fourier fields of one latitude pair, staged into LDS with
 // all global loads of a chunk issued before its LDS stores (one memory round trip per chunk of
 // 3 x kGridBlock points instead of one per field and point).
-constexpr int kGridBlock = 320;
+constexpr int kGridBlock = 256;               // four waves: one per LDS signal
 constexpr int kGridSignals = 4;                 // LDS signal buffers of the grid kernels
 
 template <int N, int F>

@@ -71,92 +71,91 @@ void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int
 
 template <int M>
 __global__ __launch_bounds__(64) void k_update_adj(AdjUpdateArgs a) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    // one thread per (coefficient, Re/Im part): every map here has real coefficients
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
-    if (idx >= a.ncoef) return;
+    if (t >= 2 * a.ncoef) return;
+    const int idx = t >> 1;
     const int n = a.n_of[idx];
     const double c = n * (n + 1.0) * a.inv_a2;
-    const size_t o = (size_t)idx * 2;
+    const size_t o = (size_t)t;
     const size_t fs = (size_t)a.ncoef * 2;
     const int sdiv = a.sweep < M ? a.sweep : M;
-    double2 bp[M], bz[M], bd[M];                              // beta_adj per node
+    double bp[M], bz[M], bd[M];                               // beta_adj per node
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         if (a.last && m != M - 1) {
-            bp[m] = bz[m] = bd[m] = make_double2(0.0, 0.0);
+            bp[m] = bz[m] = bd[m] = 0.0;
             continue;
         }
         const double* u = a.ubar + (size_t)b * a.ubar_member + (size_t)(a.last ? 0 : m) * a.ubar_node + o;
-        const double2 up = ld2a(u), uz = ld2a(u + fs), ud = ld2a(u + 2 * fs);
+        const double up = u[0], uz = u[fs], ud = u[2 * fs];
         const double alpha = a.dt * a.tau[m] / sdiv;
         const double den = 1.0 / (1.0 + alpha * alpha * a.phibar * c);
-        bp[m] = make_double2((up.x + alpha * c * ud.x) * den, (up.y + alpha * c * ud.y) * den);
+        bp[m] = (up + alpha * c * ud) * den;
         bz[m] = uz;
-        bd[m] = make_double2((ud.x - alpha * a.phibar * up.x) * den, (ud.y - alpha * a.phibar * up.y) * den);
+        bd[m] = (ud - alpha * a.phibar * up) * den;
     }
-    double2 sp = make_double2(0.0, 0.0), sz = sp, sd = sp;    // u_n adjoint contributions
-    double2 ep0 = sp, ez0 = sp, ed0 = sp;                     // E_0 adjoint when first_stage
+    double sp = 0.0, sz = 0.0, sd = 0.0;                      // u_n adjoint contributions
+    double ep0 = 0.0, ez0 = 0.0, ed0 = 0.0;                   // E_0 adjoint when first_stage
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        sp.x += bp[m].x; sp.y += bp[m].y;
-        sz.x += bz[m].x; sz.y += bz[m].y;
-        sd.x += bd[m].x; sd.y += bd[m].y;
+        sp += bp[m];
+        sz += bz[m];
+        sd += bd[m];
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        double2 qp = make_double2(0.0, 0.0), qz = qp, qd = qp;   // sum_m q_mj beta_adj_m
+        double qp = 0.0, qz = 0.0, qd = 0.0;                  // sum_m q_mj beta_adj_m
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const double qmj = a.Q[m * kMaxNodes + j];
-            qp.x += qmj * bp[m].x; qp.y += qmj * bp[m].y;
-            qz.x += qmj * bz[m].x; qz.y += qmj * bz[m].y;
-            qd.x += qmj * bd[m].x; qd.y += qmj * bd[m].y;
+            qp += qmj * bp[m];
+            qz += qmj * bz[m];
+            qd += qmj * bd[m];
         }
         const double aj = a.dt * a.tau[j] / sdiv;
         // E_adj_j = dt * qsum;  u_adj_j = dt L^T qsum - alpha_j L^T beta_adj_j
-        const double2 ep = make_double2(a.dt * qp.x, a.dt * qp.y);
-        const double2 ez = make_double2(a.dt * qz.x, a.dt * qz.y);
-        const double2 ed = make_double2(a.dt * qd.x, a.dt * qd.y);
-        const double2 wp = make_double2(c * (ed.x - aj * bd[j].x), c * (ed.y - aj * bd[j].y));
-        const double2 wd = make_double2(-a.phibar * (ep.x - aj * bp[j].x), -a.phibar * (ep.y - aj * bp[j].y));
+        const double ep = a.dt * qp, ez = a.dt * qz, ed = a.dt * qd;
+        const double wp = c * (ed - aj * bd[j]);
+        const double wd = -a.phibar * (ep - aj * bp[j]);
         if (a.first_stage) {
-            ep0.x += ep.x; ep0.y += ep.y;
-            ez0.x += ez.x; ez0.y += ez.y;
-            ed0.x += ed.x; ed0.y += ed.y;
-            sp.x += wp.x; sp.y += wp.y;
-            sd.x += wd.x; sd.y += wd.y;
+            ep0 += ep;
+            ez0 += ez;
+            ed0 += ed;
+            sp += wp;
+            sd += wd;
         } else {
             double* e = a.ebar_prev + ((size_t)b * M + j) * 3 * fs + o;
-            st2a(e, ep);
-            st2a(e + fs, ez);
-            st2a(e + 2 * fs, ed);
+            e[0] = ep;
+            e[fs] = ez;
+            e[2 * fs] = ed;
             double* u = a.ubar_prev + ((size_t)b * M + j) * 3 * fs + o;
-            st2a(u, wp);
-            st2a(u + fs, make_double2(0.0, 0.0));
-            st2a(u + 2 * fs, wd);
+            u[0] = wp;
+            u[fs] = 0.0;
+            u[2 * fs] = wd;
         }
     }
     if (a.first_stage) {
         double* e = a.ebar_prev + (size_t)b * 3 * fs + o;
-        st2a(e, ep0);
-        st2a(e + fs, ez0);
-        st2a(e + 2 * fs, ed0);
+        e[0] = ep0;
+        e[fs] = ez0;
+        e[2 * fs] = ed0;
     }
     double* un = a.ubar_n + (size_t)b * 3 * fs + o;
     if (a.init_un) {
-        st2a(un, sp);
-        st2a(un + fs, sz);
-        st2a(un + 2 * fs, sd);
+        un[0] = sp;
+        un[fs] = sz;
+        un[2 * fs] = sd;
     } else {
-        const double2 p0 = ld2a(un), z0 = ld2a(un + fs), d0 = ld2a(un + 2 * fs);
-        st2a(un, make_double2(p0.x + sp.x, p0.y + sp.y));
-        st2a(un + fs, make_double2(z0.x + sz.x, z0.y + sz.y));
-        st2a(un + 2 * fs, make_double2(d0.x + sd.x, d0.y + sd.y));
+        un[0] += sp;
+        un[fs] += sz;
+        un[2 * fs] += sd;
     }
 }
 
 void launch_update_adj(const AdjUpdateArgs& a, hipStream_t st) {
-    dim3 grid((a.ncoef + 63) / 64, a.batch);
+    dim3 grid((2 * a.ncoef + 63) / 64, a.batch);
     switch (a.M) {
     case 1: k_update_adj<1><<<grid, 64, 0, st>>>(a); break;
     case 2: k_update_adj<2><<<grid, 64, 0, st>>>(a); break;

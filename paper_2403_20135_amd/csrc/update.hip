@@ -18,33 +18,34 @@ __device__ __forceinline__ void st2(double* p, double2 v) { *(double2*)p = v; }
 
 // beta_m = u_n + dt sum_j Q[m][j] (L_g(u_j) + E_j) - alpha_m L_g(u_m);  u_m <- solve(alpha_m, beta_m)
 // alpha_m = dt tau_m / min(sweep, M)  (MIN-SR-FLEX).  When last_only, only node M is updated and
-// written (to the state), with a non-finite check.  The node count is a template parameter so that
-// the per-node arrays live in registers.
+// written (to the state), with a non-finite check.  Every coefficient of the update is real, so
+// the Re and Im parts are independent: one thread per (coefficient, part), twice the waves of a
+// thread per coefficient for the same bytes.  The node count is a template parameter so that the
+// per-node arrays live in registers.
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
-    if (idx >= a.ncoef) return;
+    if (t >= 2 * a.ncoef) return;
+    const int idx = t >> 1, c = t & 1;
     const int nc = a.ncoef;
     const int n = a.n_of[idx];
     const double cn = n * (n + 1.0) * a.inv_a2;
-    const size_t o = (size_t)idx * 2;
+    const size_t o = (size_t)t;                   // = 2 idx + c
     const size_t fs = (size_t)nc * 2;             // field stride in doubles
     const double* un = a.un + (size_t)b * 3 * fs + o;
-    const C3 u0 = {ld2(un), ld2(un + fs), ld2(un + 2 * fs)};
-    double2 Fphi[M], Fzeta[M], Fdiv[M];
-    double2 Lphi[M], Ldiv[M];                      // L_g(u_j) (zeta component is zero)
+    const double u0p = un[0], u0z = un[fs], u0d = un[2 * fs];
+    double Fphi[M], Fzeta[M], Fdiv[M];
+    double Lphi[M], Ldiv[M];                      // L_g(u_j) (zeta component is zero)
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const double* uj = a.uprev + (size_t)b * a.uprev_member + (size_t)j * a.uprev_node + o;
         const double* ej = a.E + (size_t)b * a.E_member + (size_t)j * a.E_node + o;
-        const double2 pj = ld2(uj), dj = ld2(uj + 2 * fs);
-        Lphi[j] = make_double2(-a.phibar * dj.x, -a.phibar * dj.y);
-        Ldiv[j] = make_double2(cn * pj.x, cn * pj.y);
-        const double2 e0 = ld2(ej), e1 = ld2(ej + fs), e2 = ld2(ej + 2 * fs);
-        Fphi[j] = make_double2(Lphi[j].x + e0.x, Lphi[j].y + e0.y);
-        Fzeta[j] = e1;
-        Fdiv[j] = make_double2(Ldiv[j].x + e2.x, Ldiv[j].y + e2.y);
+        Lphi[j] = -a.phibar * uj[2 * fs];
+        Ldiv[j] = cn * uj[0];
+        Fphi[j] = Lphi[j] + ej[0];
+        Fzeta[j] = ej[fs];
+        Fdiv[j] = Ldiv[j] + ej[2 * fs];
     }
     const int sdiv = a.sweep < M ? a.sweep : M;
     const int m_begin = a.last_only ? M - 1 : 0;
@@ -53,52 +54,47 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
     for (int m = 0; m < M; ++m) {
         if (m < m_begin) continue;
         const double* Qm = a.Q + m * kMaxNodes;
-        double2 sp = make_double2(0.0, 0.0), sz = sp, sd = sp;
+        double sp = 0.0, sz = 0.0, sd = 0.0;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             const double qj = Qm[j];
-            sp.x += qj * Fphi[j].x; sp.y += qj * Fphi[j].y;
-            sz.x += qj * Fzeta[j].x; sz.y += qj * Fzeta[j].y;
-            sd.x += qj * Fdiv[j].x; sd.y += qj * Fdiv[j].y;
+            sp += qj * Fphi[j];
+            sz += qj * Fzeta[j];
+            sd += qj * Fdiv[j];
         }
         const double alpha = a.dt * a.tau[m] / sdiv;
-        const double2 bphi = make_double2(u0.phi.x + a.dt * sp.x - alpha * Lphi[m].x,
-                                          u0.phi.y + a.dt * sp.y - alpha * Lphi[m].y);
-        const double2 bzeta = make_double2(u0.zeta.x + a.dt * sz.x, u0.zeta.y + a.dt * sz.y);
-        const double2 bdiv = make_double2(u0.div.x + a.dt * sd.x - alpha * Ldiv[m].x,
-                                          u0.div.y + a.dt * sd.y - alpha * Ldiv[m].y);
+        const double bphi = u0p + a.dt * sp - alpha * Lphi[m];
+        const double bzeta = u0z + a.dt * sz;
+        const double bdiv = u0d + a.dt * sd - alpha * Ldiv[m];
         const double den = 1.0 / (1.0 + alpha * alpha * a.phibar * cn);
-        const double2 phi = make_double2((bphi.x - alpha * a.phibar * bdiv.x) * den,
-                                         (bphi.y - alpha * a.phibar * bdiv.y) * den);
-        const double2 dv = make_double2(bdiv.x + alpha * cn * phi.x, bdiv.y + alpha * cn * phi.y);
+        const double phi = (bphi - alpha * a.phibar * bdiv) * den;
+        const double dv = bdiv + alpha * cn * phi;
         double* out = a.uout + (size_t)b * a.out_member + (size_t)(a.last_only ? 0 : m) * a.out_node + o;
-        st2(out, phi);
-        st2(out + fs, bzeta);
-        st2(out + 2 * fs, dv);
+        out[0] = phi;
+        out[fs] = bzeta;
+        out[2 * fs] = dv;
         if (a.cml) {
-            // synthesis layout of node state b*M + m: (zeta, Phi', psi, chi)
+            // synthesis layout of node state b*M + m: (zeta, Phi', psi, chi) x (Re, Im)
             const int mo = a.m_of[idx], par = (n - mo) & 1, kk = (n - mo) >> 1;
             const double il = a.inv_lap[n];
             const size_t S = (size_t)a.batch * M;
-            double* c = a.cml + (((size_t)a.rowoff[2 * mo + par] + kk) * S + (size_t)b * M + m) * kCmlVals;
-            st2(c, bzeta);
-            st2(c + 2, phi);
-            st2(c + 4, make_double2(il * bzeta.x, il * bzeta.y));
-            st2(c + 6, make_double2(il * dv.x, il * dv.y));
-            cml_clear_pad(a.cml, a.rowoff[2 * mo + par], kk, npk_of(a.T, mo, par), S, (size_t)b * M + m);
+            double* cr = a.cml + (((size_t)a.rowoff[2 * mo + par] + kk) * S + (size_t)b * M + m) * kCmlVals + c;
+            cr[0] = bzeta;
+            cr[2] = phi;
+            cr[4] = il * bzeta;
+            cr[6] = il * dv;
+            if (c == 0)
+                cml_clear_pad(a.cml, a.rowoff[2 * mo + par], kk, npk_of(a.T, mo, par), S, (size_t)b * M + m);
         }
-        if (a.last_only) {
-            bad = !(isfinite(phi.x) && isfinite(phi.y) && isfinite(bzeta.x) && isfinite(bzeta.y) &&
-                    isfinite(dv.x) && isfinite(dv.y));
-        }
+        if (a.last_only) bad = !(isfinite(phi) && isfinite(bzeta) && isfinite(dv));
     }
     if (bad) a.flag[0] = 1;
 }
 
 void launch_update(const UpdateArgs& a, hipStream_t st) {
-    // small workgroups: one thread per coefficient leaves few threads, spread them over all CUs
+    // small workgroups: spread the (coefficient, part) threads over all CUs
     constexpr int kUpd = 64;
-    dim3 grid((a.ncoef + kUpd - 1) / kUpd, a.batch);
+    dim3 grid((2 * a.ncoef + kUpd - 1) / kUpd, a.batch);
     switch (a.M) {
     case 1: k_update<1><<<grid, kUpd, 0, st>>>(a); break;
     case 2: k_update<2><<<grid, kUpd, 0, st>>>(a); break;

@@ -47,9 +47,13 @@ def gauss_legendre(nlat: int):
     # one more Newton step at convergence so that the weights use the polished nodes
     p, dp = _legendre_and_derivative(nlat, x)
     x = x - p / dp
+    return x, gauss_weights(nlat, x)
+
+
+def gauss_weights(nlat: int, x: np.ndarray) -> np.ndarray:
+    """Gauss-Legendre weights w = 2 / ((1 - x^2) P_nlat'(x)^2) at the nodes x."""
     _, dp = _legendre_and_derivative(nlat, x)
-    w = 2.0 / ((1.0 - x * x) * dp * dp)
-    return x, w
+    return 2.0 / ((1.0 - x * x) * dp * dp)
 
 
 def radau_right_nodes(M: int) -> np.ndarray:

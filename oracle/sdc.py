@@ -65,8 +65,8 @@ class Oracle:
     """Sphere + shallow-water right-hand side + collocation coefficients for one truncation."""
 
     def __init__(self, T: int, nlat: int, nlon: int, radius: float, gravity: float,
-                 omega: float, mean_depth: float):
-        self.sphere = Sphere(T, nlat, nlon, radius)
+                 omega: float, mean_depth: float, grid=None):
+        self.sphere = Sphere(T, nlat, nlon, radius, grid)
         self.swe = SWE(self.sphere, gravity, omega, mean_depth)
         self.gravity = gravity
         self.mean_depth = mean_depth

@@ -36,11 +36,13 @@ CT = torch.complex128
 class Sphere:
     """Gaussian grid, Legendre tables and DFT matrices for truncation T on nlat x nlon."""
 
-    def __init__(self, T: int, nlat: int, nlon: int, radius: float):
+    def __init__(self, T: int, nlat: int, nlon: int, radius: float, grid=None):
+        """grid: optional (mu, w) replacing the Gauss-Legendre nodes and weights (used by the
+        tests to measure how much a result moves when the nodes move by one ulp)."""
         if nlat < T + 1 or nlon < 2 * T + 1:
             raise ValueError("grid too small for truncation")
         self.T, self.nlat, self.nlon, self.radius = T, nlat, nlon, radius
-        mu, w = quadrature.gauss_legendre(nlat)
+        mu, w = quadrature.gauss_legendre(nlat) if grid is None else grid
         self.mu_np, self.w_np = mu, w
         self.mu = torch.tensor(mu, dtype=DT)
         self.w = torch.tensor(w, dtype=DT)

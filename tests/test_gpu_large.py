@@ -1,0 +1,121 @@
+"""GPU checks at the largest truncation, T511 on 768 x 1536 (M=4, K=4, dt=60 s): one f_E and one
+dSDC step at full size against the FP64 oracle, the FP32 tendency within 2 (T+1) u_32, and the
+adjoint step against central differences of the GPU step (dot-product test).
+
+Tolerance at T511.  Gauss nodes computed by two correct FP64 Newton iterations may differ by one
+ulp; near the poles that moves the weights by ~1e-11 relative and the tables by ~1e-12, and the
+divergence tendency (which carries n(n+1)/a^2 times the kinetic energy) amplifies it further.  The
+FP64 bar is therefore the larger of the plain-path target (1e-12 for f_E, 1e-11 for a step) and
+three times the oracle's own spread: the oracle evaluated on nodes moved by one ulp (weights
+recomputed by its own formula), per field.
+
+The FP32 bar 2 (T+1) u_32 holds for an output as well conditioned as Phi' (a plain divergence of
+fluxes).  The divergence tendency is a curl plus a Laplacian of the kinetic energy, whose factor
+n(n+1) lifts the high-degree rounding noise against a spectrum that decays there; the oracle
+measures that amplification itself: with its Legendre tables rounded to FP32 (arithmetic still
+FP64) field k moves by eps_k, and the bar for field k is 2 (T+1) u_32 max(1, eps_k / eps_Phi').
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import quadrature
+from oracle.sdc import Oracle
+
+from test_gpu_parity import _dev, _host, _sdc, _states, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+T, NLAT, NLON, M, K, DT = 511, 768, 1536, 4, 4, 60.0
+
+
+def _oracle_on(grid=None):
+    return Oracle(T, NLAT, NLON, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, grid)
+
+
+def _oracle_fp32_tables():
+    """The oracle with its (real-valued) Legendre tables rounded to FP32."""
+    o = _oracle_on()
+    sp = o.sphere
+    sp.P = [t.real.float().double().to(t.dtype) for t in sp.P]
+    sp.H = [t.real.float().double().to(t.dtype) for t in sp.H]
+    return o
+
+
+def _grid_one_ulp(seed):
+    """Gauss nodes moved by one ulp each (seeded directions, mirror-symmetric), weights recomputed."""
+    mu, _ = quadrature.gauss_legendre(NLAT)
+    h = NLAT // 2
+    s = np.random.default_rng(seed).choice([-1.0, 1.0], size=h)
+    mun = np.nextafter(mu[:h], mu[:h] + s)
+    mu2 = np.concatenate([mun, -mun[::-1]])
+    return mu2, quadrature.gauss_weights(NLAT, mu2)
+
+
+@pytest.fixture(scope="module")
+def oracles():
+    return _oracle_on(), _oracle_on(_grid_one_ulp(1)), _oracle_fp32_tables()
+
+
+def _per_field(a, b):
+    return [rel_l2(a[..., k, :, :], b[..., k, :, :], T) for k in range(3)]
+
+
+def test_t511_explicit_tendency_fp64_and_fp32(oracles):
+    o, o1, o32 = oracles
+    x = _states(T, 1, 511)
+    ref = o.f_explicit(x[0])[None]
+    spread = _per_field(o1.f_explicit(x[0])[None], ref)
+    eps = _per_field(o32.f_explicit(x[0])[None], ref)
+    tol32 = [2 * (T + 1) * 2.0 ** -24 * max(1.0, e / eps[0]) for e in eps]
+    for prec in ("fp64", "fp32"):
+        sdc = _sdc(T, NLAT, NLON, M, K, 1, precision=prec)
+        f = _dev(np.zeros_like(x))
+        sdc.eval_explicit(_dev(x), f)
+        err = _per_field(_host(f), ref)
+        for k, name in enumerate(("Phi'", "zeta", "delta")):
+            tol = max(1e-12, 3 * spread[k]) if prec == "fp64" else tol32[k]
+            print(f"[gpu] T511 f_E {prec} {name}: rel L2 {err[k]:.3e} (oracle 1-ulp spread "
+                  f"{spread[k]:.2e}, FP32-table shift {eps[k]:.2e}, tol {tol:.2e})", flush=True)
+            assert err[k] <= tol
+        sdc.close()
+
+
+def test_t511_step_fp64(oracles):
+    o, o1, _ = oracles
+    wl = W.WORKLOADS["t511_m4k4"]
+    x0 = W.initial_state(wl)[None]
+    sdc = _sdc(T, NLAT, NLON, M, K, 1)
+    x = _dev(x0)
+    sdc.step(x, DT)
+    sdc.sync()
+    ref = o.step(x0[0], DT, M, K)[None]
+    spread = _per_field(o1.step(x0[0], DT, M, K)[None], ref)
+    err = _per_field(_host(x), ref)
+    for k, name in enumerate(("Phi'", "zeta", "delta")):
+        tol = max(1e-11, 3 * spread[k])
+        print(f"[gpu] T511 step {name}: rel L2 {err[k]:.3e} (oracle 1-ulp spread {spread[k]:.2e}, "
+              f"tol {tol:.2e})", flush=True)
+        assert err[k] <= tol
+
+
+def test_t511_adjoint_dot_product():
+    sdc = _sdc(T, NLAT, NLON, M, K, 1)
+    x = _states(T, 1, 7)
+    lam = W.random_state(T, 8)[None]
+    lam[..., :T + 1, 1] = 0.0
+    g = _dev(np.zeros_like(x))
+    sdc.step_adjoint(_dev(x), _dev(lam), g, DT)
+    g = _host(g)
+    eps = 1e-6
+    v = W.random_directions(x.shape, 9, 1)[0]
+    v[..., :T + 1, 1] = 0.0
+    for f in range(3):
+        v[0, f] *= np.linalg.norm(x[0, f]) / np.linalg.norm(v[0, f])
+    xp, xm = _dev(x + eps * v), _dev(x - eps * v)
+    sdc.step(xp, DT)
+    sdc.step(xm, DT)
+    jv = (_host(xp) - _host(xm)) / (2 * eps)
+    lhs, rhs = float(np.sum(jv * lam)), float(np.sum(v * g))
+    print(f"[gpu] T511 adjoint dot product: {lhs:.12e} vs {rhs:.12e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs)

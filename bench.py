@@ -2,7 +2,7 @@
 """Benchmark: dSDC steps/s of the T255, M=4, K=4 shallow-water workload on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload t255_m4k4] [--no-cpu-baseline]
-                    [--no-fp32]
+                    [--no-fp32] [--no-adjoint]
     python bench.py --summarize-pmc FETCH.csv WRITE.csv COPY_MIB OUT.json   (counter summary)
 
 Prints ONE JSON line.  `value` is the plain FP64 path: exactly K steps (after W warm-up steps and
@@ -14,7 +14,9 @@ times K forward steps with one checkpoint each followed by K adjoint steps (forw
 The same three regions are measured for the FP32 precision mode (Legendre contractions in FP32
 on MFMA), whose error is compared with the plain path's at equal step size against the FP64
 path at dt/8 ("equal error": E_fp32 <= 1.1 E_fp64, E = max over output times of the relative
-L2 error of vorticity).  The CPU baseline is the FP64 oracle timed on the host cores on a bounded
+L2 error of vorticity).  Two further workloads are reported beside the headline: the 32-member
+ensemble of mixed truncations (one graph launch per step) and T511 (FP64 and FP32, forward and
+forward+adjoint).  The CPU baseline is the FP64 oracle timed on the host cores on a bounded
 sample.
 
 Rooflines: the Legendre kernels are priced at min(MFMA peak, AI x HBM peak) with AI = useful
@@ -208,6 +210,45 @@ def equal_error(wl, steps=40, every=10):
             "reference": f"FP64 GPU path at dt/8 ({8 * steps} steps of {mb.dt / 8} s)"}
 
 
+def measure_mixed(steps=20, warmup=3):
+    """The 32-member ensemble of mixed truncations (16 x T63, 12 x T127, 4 x T255; M=4, K=3):
+    one graph launch per step advances every member (FP64)."""
+    import torch
+    from paper_2403_20135_amd.api import SDC, SDCGroup
+    wl = W.WORKLOADS["mixed32_m4k3"]
+    groups = {}
+    for k, mb in enumerate(wl.members):
+        groups.setdefault(mb.T, []).append((k, mb))
+    handles, xs, dts = [], [], []
+    for T, lst in sorted(groups.items()):
+        mb = lst[0][1]
+        handles.append(SDC(T, mb.nlat, mb.nlon, wl.M, wl.K, len(lst), "fp64", W.RADIUS, W.GRAVITY,
+                           W.OMEGA, W.MEAN_DEPTH))
+        xs.append(torch.tensor(__import__("numpy").stack([W.initial_state(wl, member=k) for k, _ in lst]),
+                               dtype=torch.float64, device="cuda"))
+        dts.append(mb.dt)
+    grp = SDCGroup(handles)
+    for _ in range(warmup):
+        grp.step(xs, dts, wl.M, wl.K)
+    grp.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        grp.step(xs, dts, wl.M, wl.K)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    grp.sync()
+    if not all(bool(torch.isfinite(x).all()) for x in xs):
+        raise RuntimeError("non-finite ensemble state")
+    grp.close()
+    for h in handles:
+        h.close()
+    return {"workload": wl.name, "members": len(wl.members), "steps": steps,
+            "steps_per_s": round(steps / el, 3), "member_steps_per_s": round(len(wl.members) * steps / el, 1),
+            "ms_per_step": round(el / steps * 1e3, 4), "precision": "fp64",
+            "launch": "one hipGraph per step (members as parallel branches)"}
+
+
 def traffic_for(kernel):
     """Measured HBM bytes per launch of `kernel` from the committed counter summary, or None when
     the summary is missing or was taken from other kernel sources."""
@@ -349,6 +390,14 @@ def main():
             "equal_error": ee,
             "kernels": r32["kernels"],
         }
+    if not args.no_fp32 and args.workload == "t255_m4k4":
+        result["mixed32_m4k3"] = measure_mixed()
+        big = W.WORKLOADS["t511_m4k4"]
+        r511 = {p: measure(big, p, 20, 3, with_kernels=False) for p in ("fp64", "fp32")}
+        result["t511_m4k4"] = {
+            "config": {"T": 511, "nlat": 768, "nlon": 1536, "M": 4, "K": 4, "dt": 60.0, "steps": 20},
+            **{p: {"steps_per_s": round(r["steps_per_s"], 3),
+                   "fwd_adj_steps_per_s": round(r["fwd_adj_steps_per_s"], 3)} for p, r in r511.items()}}
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -53,6 +53,20 @@ __host__ __device__ inline size_t tab_index(int np4, int kk, int jh) {
     return (size_t)(jh >> 4) * np4 * 16 + (size_t)kk * 16 + (jh & 15);
 }
 
+// Workgroups of a launch are dealt to the 8 XCDs round-robin by their linear index, and each
+// XCD starts its share in order.  A Legendre launch over G state groups uses a 1-D grid of
+// xcd_grid(ntasks, G) workgroups and maps workgroup w to (task, group) so that the G groups of a
+// task run back to back on one XCD: the table tile they share comes from HBM once and from that
+// XCD's L2 for the other groups.  With G = 1 the map is the identity.  Tasks >= ntasks are
+// padding (the kernel returns).
+__host__ inline unsigned xcd_grid(int ntasks, int ngroups) {
+    return (unsigned)((ntasks + 7) / 8) * 8u * (unsigned)ngroups;
+}
+__device__ inline int2 xcd_task_group(int ngroups) {
+    const int w = blockIdx.x, x = w & 7, l = w >> 3;
+    return make_int2((l / ngroups) * 8 + x, l % ngroups);
+}
+
 // Synthesis input ("coefficient-major", written by the update/prep kernels): for table row
 // (m, p, kk) and state s, 8 doubles (zeta, Phi', psi, chi) x (Re, Im) with psi, chi the inverse
 // Laplacians of zeta and delta:  cml[((rowoff[2m+p] + kk) * S + s) * 8 + v].

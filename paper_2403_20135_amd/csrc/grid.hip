@@ -198,28 +198,62 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Twiddle powers w^r, r = 1..R-1, from w^1 by a product tree (w^r = w^h w^(r-h), h the largest
+// power of two <= r): log2(R) dependent products instead of R - 2.  The products add a few ulps,
+// far below the transform's own rounding.
+constexpr int pow2_floor(int r) { return r >= 8 ? 8 : (r >= 4 ? 4 : (r >= 2 ? 2 : 1)); }
+template <int R>
+__device__ __forceinline__ void twiddle_powers(double2 (&wr)[R], double2 w1) {
+    wr[1] = w1;
+#pragma unroll
+    for (int r = 2; r < R; ++r) {
+        const int h = pow2_floor(r);
+        wr[r] = h == r ? cmul(wr[r / 2], wr[r / 2]) : cmul(wr[h], wr[r - h]);
+    }
+}
+
+// Per-lane first twiddles of the wave transforms: for stage S and the lane's butterfly tt,
+// w^k = tw[k tstep] with k = j mod NS (stage 0, NS = 1, needs none).  Loaded once per kernel so
+// that no stage waits on a memory load; the inverse transforms conjugate them.
+constexpr int kWaveMaxT = 8;
+template <int N> using WaveTw = double2[fft_nst(N) > 0 ? fft_nst(N) : 1][kWaveMaxT];
+
+template <int N, int S, int NS>
+__device__ __forceinline__ void wave_tw_load(WaveTw<N>& w, const double2* __restrict__ tw, int lane) {
+    if constexpr (S < fft_nst(N)) {
+        constexpr int R = fft_radix(N, S), nb = N / R, MAXT = (nb + 63) / 64;
+        constexpr int tstep = N / (NS * R);
+        if constexpr (NS > 1) {
+            static_assert(MAXT <= kWaveMaxT, "wave FFT stage exceeds the per-lane butterfly budget");
+#pragma unroll
+            for (int tt = 0; tt < MAXT; ++tt) {
+                const int j = lane + 64 * tt;
+                w[S][tt] = tw[(j < nb ? j % NS : 0) * tstep];
+            }
+        }
+        wave_tw_load<N, S + 1, NS * R>(w, tw, lane);
+    }
+}
+
 template <int R, int N, int NS, bool INV>
-__device__ __forceinline__ void fft_wave_stage(double2* buf, const double2* tw, int lane) {
+__device__ __forceinline__ void fft_wave_stage(double2* buf, const double2 (&w1s)[kWaveMaxT], int lane) {
     constexpr int nb = N / R;
     constexpr int MAXT = (nb + 63) / 64;
-    constexpr int tstep = N / (NS * R);
     double2 v[MAXT][R];
 #pragma unroll
     for (int tt = 0; tt < MAXT; ++tt) {
-        const int j = lane + 64 * tt, k = j % NS;
+        const int j = lane + 64 * tt;
         if (j < nb) {
             const double2* src = buf + j;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[tt][r] = src[r * nb];
-            // twiddles w^(r k) for r >= 2 as powers of w^k (one table read per butterfly instead
-            // of R - 1; the products add a few ulps, far below the transform's own rounding)
-            double2 w1 = tw[k * tstep];
-            if (INV) w1.y = -w1.y;
-            double2 wr = w1;
+            if constexpr (NS > 1) {                       // first stage: all twiddles are 1
+                double2 w1 = w1s[tt];
+                if (INV) w1.y = -w1.y;
+                double2 wr[R];
+                twiddle_powers<R>(wr, w1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                if (r > 1) wr = cmul(wr, w1);
-                v[tt][r] = cmul(v[tt][r], wr);
+                for (int r = 1; r < R; ++r) v[tt][r] = cmul(v[tt][r], wr[r]);
             }
             dft_small<R>(v[tt], INV);
         }
@@ -238,18 +272,107 @@ __device__ __forceinline__ void fft_wave_stage(double2* buf, const double2* tw, 
 }
 
 template <int N, int S, int NS, bool INV>
-__device__ __forceinline__ void fft_wave_stages(double2* buf, const double2* tw, int lane) {
+__device__ __forceinline__ void fft_wave_stages(double2* buf, const WaveTw<N>& w, int lane) {
     if constexpr (S < fft_nst(N)) {
         constexpr int R = fft_radix(N, S);
-        fft_wave_stage<R, N, NS, INV>(buf, tw, lane);
-        fft_wave_stages<N, S + 1, NS * R, INV>(buf, tw, lane);
+        fft_wave_stage<R, N, NS, INV>(buf, w[S], lane);
+        fft_wave_stages<N, S + 1, NS * R, INV>(buf, w, lane);
     }
 }
 
-// Unnormalised DFT of the signal of length N at buf by the calling wave alone.
+// Unnormalised DFT of the signal of length N at buf by the calling wave alone (twiddles from
+// wave_tw_load).
 template <int N, bool INV>
-__device__ __forceinline__ void fft_wave(double2* buf, const double2* tw, int lane) {
-    fft_wave_stages<N, 0, 1, INV>(buf, tw, lane);
+__device__ __forceinline__ void fft_wave(double2* buf, const WaveTw<N>& w, int lane) {
+    fft_wave_stages<N, 0, 1, INV>(buf, w, lane);
+}
+
+constexpr int kGridBlock = 256;               // four waves: one per LDS signal
+constexpr int kGridSignals = 4;                 // LDS signal buffers of the grid kernels
+
+// Workgroup-wide transform of ONE signal by all kGridBlock threads (barriers between stages), for
+// the signal the grid kernels cannot give a wave of its own.  Plan: radix 3 when 3 | N, then
+// radix 4 stages and a last radix 2 when needed, so that most stages give every thread a
+// butterfly (768 = 3 x 4^4: 256 then 192 butterflies per stage).
+constexpr int fftb_nst(int n) {
+    int s = 0;
+    if (n % 3 == 0) { n /= 3; ++s; }
+    while (n % 4 == 0) { n /= 4; ++s; }
+    return s + (n == 2 ? 1 : 0);
+}
+constexpr int fftb_radix(int n, int s) {
+    return (n % 3 == 0) ? (s == 0 ? 3 : fftb_radix(n / 3, s - 1))
+                        : (n % 4 == 0 ? (s == 0 ? 4 : fftb_radix(n / 4, s - 1)) : 2);
+}
+constexpr int kBlockMaxT = 4;
+template <int N> using BlockTw = double2[fftb_nst(N)][kBlockMaxT];
+
+template <int N, int S, int NS>
+__device__ __forceinline__ void block_tw_load(BlockTw<N>& w, const double2* __restrict__ tw) {
+    if constexpr (S < fftb_nst(N)) {
+        constexpr int R = fftb_radix(N, S), nb = N / R;
+        constexpr int MAXT = (nb + kGridBlock - 1) / kGridBlock, tstep = N / (NS * R);
+        if constexpr (NS > 1) {
+            static_assert(MAXT <= kBlockMaxT, "block FFT stage exceeds the per-thread budget");
+#pragma unroll
+            for (int tt = 0; tt < MAXT; ++tt) {
+                const int j = threadIdx.x + kGridBlock * tt;
+                w[S][tt] = tw[(j < nb ? j % NS : 0) * tstep];
+            }
+        }
+        block_tw_load<N, S + 1, NS * R>(w, tw);
+    }
+}
+
+template <int R, int N, int NS, bool INV>
+__device__ __forceinline__ void fft_block_stage(double2* buf, const double2 (&w1s)[kBlockMaxT]) {
+    constexpr int nb = N / R;
+    constexpr int MAXT = (nb + kGridBlock - 1) / kGridBlock;
+    double2 v[MAXT][R];
+#pragma unroll
+    for (int tt = 0; tt < MAXT; ++tt) {
+        const int j = threadIdx.x + kGridBlock * tt;
+        if (j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[tt][r] = buf[j + r * nb];
+            if constexpr (NS > 1) {
+                double2 w1 = w1s[tt];
+                if (INV) w1.y = -w1.y;
+                double2 wr[R];
+                twiddle_powers<R>(wr, w1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[tt][r] = cmul(v[tt][r], wr[r]);
+            }
+            dft_small<R>(v[tt], INV);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < MAXT; ++tt) {
+        const int j = threadIdx.x + kGridBlock * tt, k = j % NS;
+        if (j < nb) {
+            double2* dst = buf + (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * NS] = v[tt][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int S, int NS, bool INV>
+__device__ __forceinline__ void fft_block_stages(double2* buf, const BlockTw<N>& w) {
+    if constexpr (S < fftb_nst(N)) {
+        constexpr int R = fftb_radix(N, S);
+        fft_block_stage<R, N, NS, INV>(buf, w[S]);
+        fft_block_stages<N, S + 1, NS * R, INV>(buf, w);
+    }
+}
+
+// Unnormalised DFT of the signal at buf by the whole workgroup (every thread must call it; the
+// caller synchronises before, the last stage ends with a barrier).
+template <int N, bool INV>
+__device__ __forceinline__ void fft_block(double2* buf, const BlockTw<N>& w) {
+    fft_block_stages<N, 0, 1, INV>(buf, w);
 }
 
 bool fft_length_supported(int n) { return fft_nst(n) > 0; }
@@ -293,8 +416,6 @@ __device__ __forceinline__ void unpack_pair(const double2* buf, int m, int N, do
 // The packed spectra (pack_pair) of F Fourier fields of one latitude pair, staged into LDS with
 // all global loads of a chunk issued before its LDS stores (one memory round trip per chunk of
 // 3 x kGridBlock points instead of one per field and point).
-constexpr int kGridBlock = 256;               // four waves: one per LDS signal
-constexpr int kGridSignals = 4;                 // LDS signal buffers of the grid kernels
 
 template <int N, int F>
 __device__ __forceinline__ void stage_inputs(double2* buf, const double2* __restrict__ fs,
@@ -342,11 +463,13 @@ __device__ __forceinline__ void stage_inputs(double2* buf, const double2* __rest
 //   Pbar columns: -i m A g, i m B g, E w, -i m C g;  H columns: B g, A g, D g
 //   with g = w / (a (1-mu^2)), Fourier coefficients normalised by 1/nlon.
 // Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of (latitude, state) tasks,
-// states fastest, so the rows of the analysis input meet in one L2.  Each signal is transformed by
-// one wave; only the hand-offs between phases are workgroup barriers.  LDS holds four signals
-// (three workgroups fit a CU) and the twiddles are read from memory: the fifth product E waits in
-// registers while A..D are transformed and unpacked, then reuses buffer 0, so an analysis row
-// (14 values and 2 zeros, one 128-byte line) is written in two parts from the same workgroup.
+// states fastest, so the rows of the analysis input meet in one L2.  Each of the first eight
+// signals is transformed by one wave; only the hand-offs between phases are workgroup barriers.
+// LDS holds four signals (three workgroups fit a CU), and every thread loads the first twiddles
+// of its butterflies once, ahead of their use: the fifth product E waits in registers while A..D are
+// transformed and unpacked, then reuses buffer 0 and is transformed by the whole workgroup, so an
+// analysis row (14 values and 2 zeros, one 128-byte line) is written in two parts from the same
+// workgroup.
 // ---------------------------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
@@ -365,9 +488,11 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four + (size_t)s * kSynFields * fstride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    WaveTw<N> twl;
+    wave_tw_load<N, 0, 1>(twl, tw, lane);
     stage_inputs<N, kSynFields>(buf, fs, fstride, jN, jS, T, g.ms);
     __syncthreads();
-    if (wave < kSynFields) fft_wave<N, true>(buf + wave * N, tw, lane);
+    if (wave < kSynFields) fft_wave<N, true>(buf + wave * N, twl, lane);
     __syncthreads();
     if (save) {      // grid values of zeta, Phi', U, V (north, south) for the adjoint
         for (int f = 0; f < kSynFields; ++f)
@@ -391,8 +516,10 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
         ereg[kk] = make_double2((U.x * U.x + V.x * V.x) * ke, (U.y * U.y + V.y * V.y) * ke);
     }
     __syncthreads();
-    if (wave < 4) fft_wave<N, false>(buf + wave * N, tw, lane);
+    if (wave < 4) fft_wave<N, false>(buf + wave * N, twl, lane);
     __syncthreads();
+    BlockTw<N> twb;                        // loaded here: in flight during the unpack of A..D
+    block_tw_load<N, 0, 1>(twb, tw);
     const double invN = 1.0 / N;
     const double wt = w[jN];
     const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
@@ -437,8 +564,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
         if (k < N) buf[k] = ereg[kk];
     }
     __syncthreads();
-    if (wave == 0) fft_wave<N, false>(buf, tw, lane);
-    __syncthreads();
+    fft_block<N, false>(buf, twb);
     for (int m = threadIdx.x; m <= T; m += kGridBlock) {
         double2 EN, ES;
         unpack_pair(buf, m, N, EN, ES);
@@ -468,7 +594,8 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
 // zeta, Phi', U, V, and the columns of the transposed synthesis (s_m = 1, 2 for m = 0, > 0):
 //   Pbar: s_m Z, (s_m/a)(-i m V), (s_m/a)(-i m U), s_m Phi;   H: -(s_m/a) U, (s_m/a) V
 // combined into north +- south sums per parity (Pbar: + for even n-m; H: - for even n-m).
-// With four LDS signals, E^ is transformed first and held in registers during the products.
+// With four LDS signals, E^ is transformed first (by the whole workgroup) and held in registers
+// during the products.
 // ---------------------------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
@@ -487,11 +614,15 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
     const size_t fstride = (size_t)g.nlat * g.ms;
     const double2* fs = four5 + (size_t)s * 5 * fstride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // E^ first (wave 0), kept in registers at this thread's points, then A^..D^ (waves 0..3)
+    WaveTw<N> twl;
+    wave_tw_load<N, 0, 1>(twl, tw, lane);
+    BlockTw<N> twb;
+    block_tw_load<N, 0, 1>(twb, tw);
+    // E^ first (whole workgroup), kept in registers at this thread's points, then A^..D^ (one
+    // wave each)
     stage_inputs<N, 1>(buf, fs + 4 * fstride, fstride, jN, jS, T, g.ms);
     __syncthreads();
-    if (wave == 0) fft_wave<N, true>(buf, tw, lane);
-    __syncthreads();
+    fft_block<N, true>(buf, twb);
     double2 ereg[KP];
 #pragma unroll
     for (int kk = 0; kk < KP; ++kk) {
@@ -501,7 +632,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
     __syncthreads();
     stage_inputs<N, 4>(buf, fs, fstride, jN, jS, T, g.ms);
     __syncthreads();
-    if (wave < 4) fft_wave<N, true>(buf + wave * N, tw, lane);
+    if (wave < 4) fft_wave<N, true>(buf + wave * N, twl, lane);
     __syncthreads();
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;
@@ -526,7 +657,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
         buf[3 * N + k] = make_double2(Bn * qn + Dn * phi.x + En * V.x, Bs * qs + Ds * phi.y + Es * V.y);
     }
     __syncthreads();
-    if (wave < kSynFields) fft_wave<N, false>(buf + wave * N, tw, lane);
+    if (wave < kSynFields) fft_wave<N, false>(buf + wave * N, twl, lane);
     __syncthreads();
     const double inva = 1.0 / g.radius;
     const double2 z2 = make_double2(0.0, 0.0);

@@ -104,6 +104,8 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     constexpr int NT = TL::NT, D = 8;
     constexpr unsigned tsz = sizeof(TT);
     __shared__ double part[2][NT][4][64];
+    // state groups on blockIdx.y: the groups of one task run far apart in time (sharing a
+    // table tile between co-scheduled groups through L2 measured slower)
     const int2 task = tasks[blockIdx.x];
     if (task.x < 0) return;                                  // padding workgroup (uniform)
     const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // parity of this wave
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
 void launch_synthesis_swe(const Tables& tb, const long long* toff, const int* rowoff,
                           const int2* tasks, int ntasks, const double* cml, int nstates,
                           double2* four, const Geom& g, hipStream_t st) {
-    dim3 grid(ntasks, (nstates + 3) / 4);
+    const dim3 grid(ntasks, (nstates + 3) / 4);
     if (tb.P32)
         k_synthesis<kSynForward, float><<<grid, kSynBlock, 0, st>>>(
             tb.P32, tb.H32, toff, rowoff, tasks, cml, nstates, (double*)four, g);
@@ -216,7 +218,7 @@ void launch_synthesis_swe(const Tables& tb, const long long* toff, const int* ro
 void launch_synthesis_adj(const Tables& tb, const long long* toff, const int* rowoff,
                           const int2* tasks, int ntasks, const double* cml, int nstates,
                           double2* four5, const Geom& g, hipStream_t st) {
-    dim3 grid(ntasks, (nstates + 3) / 4);
+    const dim3 grid(ntasks, (nstates + 3) / 4);
     if (tb.P32)
         k_synthesis<kSynAdjoint, float><<<grid, kSynBlock, 0, st>>>(
             tb.P32, tb.H32, toff, rowoff, tasks, cml, nstates, (double*)four5, g);
@@ -255,19 +257,21 @@ template <typename TT> struct AnaStage {
 template <int MODE, typename TT>
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
-    const int4* __restrict__ tasks, const double* __restrict__ G, int nstates,
+    const int4* __restrict__ tasks, int ntasks, const double* __restrict__ G, int nstates,
     const double* __restrict__ nscale, double* __restrict__ out, Geom g) {
     using MM = Mma<TT>;
     using vec = typename MM::vec;
     constexpr int D = 4;
     __shared__ __align__(16) double gl[2][kAnaBuf + 2];       // + a dummy slot for idle threads
-    const int4 task = tasks[blockIdx.x];
+    const int2 tg = xcd_task_group((nstates + 3) >> 2);
+    if (tg.x >= ntasks) return;
+    const int4 task = tasks[tg.x];
     if (task.w == 0) return;                                 // padding workgroup (uniform)
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int m = task.x, p = task.y;
     const int kt = task.z + 16 * wave;
-    const int S = nstates, s0 = blockIdx.y * 4;
+    const int S = nstates, s0 = tg.y * 4;
     const int nsg = S - s0 < 4 ? S - s0 : 4;                 // states in this group
     const int np = npk_of(g.T, m, p);
     const bool active = kt < np;                             // wave-uniform
@@ -416,25 +420,25 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
 void launch_analysis_swe(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
                          const double* G, int nstates, const double* neg_lap, double* out,
                          const Geom& g, hipStream_t st) {
-    dim3 grid(nwg, (nstates + 3) / 4);
+    const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
     if (tb.P32)
-        k_analysis_swe<kAnaForward, float><<<grid, kBlock, 0, st>>>(tb.P32, tb.H32, toff, tasks, G,
-                                                                    nstates, neg_lap, out, g);
+        k_analysis_swe<kAnaForward, float><<<grid, kBlock, 0, st>>>(tb.P32, tb.H32, toff, tasks, nwg,
+                                                                    G, nstates, neg_lap, out, g);
     else
-        k_analysis_swe<kAnaForward, double><<<grid, kBlock, 0, st>>>(tb.P, tb.H, toff, tasks, G,
-                                                                     nstates, neg_lap, out, g);
+        k_analysis_swe<kAnaForward, double><<<grid, kBlock, 0, st>>>(tb.P, tb.H, toff, tasks, nwg,
+                                                                     G, nstates, neg_lap, out, g);
 }
 
 void launch_analysis_adjoint(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
                              const double* G, int nstates, const double* inv_lap, double* out_acc,
                              const Geom& g, hipStream_t st) {
-    dim3 grid(nwg, (nstates + 3) / 4);
+    const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
     if (tb.P32)
-        k_analysis_swe<kAnaAdjoint, float><<<grid, kBlock, 0, st>>>(tb.P32, tb.H32, toff, tasks, G,
-                                                                    nstates, inv_lap, out_acc, g);
+        k_analysis_swe<kAnaAdjoint, float><<<grid, kBlock, 0, st>>>(tb.P32, tb.H32, toff, tasks, nwg,
+                                                                    G, nstates, inv_lap, out_acc, g);
     else
-        k_analysis_swe<kAnaAdjoint, double><<<grid, kBlock, 0, st>>>(tb.P, tb.H, toff, tasks, G,
-                                                                     nstates, inv_lap, out_acc, g);
+        k_analysis_swe<kAnaAdjoint, double><<<grid, kBlock, 0, st>>>(tb.P, tb.H, toff, tasks, nwg,
+                                                                     G, nstates, inv_lap, out_acc, g);
 }
 
 // FP32 copies of the FP64 tables (same layout), for the FP32 precision mode.

@@ -174,6 +174,33 @@ int sdc_timing_read(sdc_handle h, int kernel_class, double* total_ms, long long*
 /* Sizes and device memory of a handle. */
 int sdc_get_info(sdc_handle h, sdc_info* info);
 
+/* Launch variants of the two Legendre kernels (the Legendre parts of the spectral transforms of
+ * Section 3.2).  Every variant computes the same sums in the same order, so results are bitwise
+ * identical; only the speed differs with truncation, batch and precision.
+ *   syn_lat_tiles, syn_depth: 16-latitude tiles per synthesis workgroup and operand stages in
+ *     flight per wave; the built pairs are (1, 8), (1, 4), (2, 4) (the default), (2, 2), (4, 2).
+ *   ana_depth: table stages in flight per analysis wave, 2 (default) or 4.
+ *   ana_interleave: 1 (default) runs the 4-state groups of one analysis task back to back on one
+ *     XCD (shared table tile from its L2), 0 issues group after group. */
+typedef struct {
+    int syn_lat_tiles, syn_depth, ana_depth, ana_interleave;
+} sdc_plan;
+
+/* The handle's current variants. */
+int sdc_get_plan(sdc_handle h, sdc_plan* plan);
+
+/* Select variants; SDC_EINVAL for a combination that is not built (the handle keeps its plan).
+ * Graphs cached by sdc_step_graph are dropped and recaptured on their next call. */
+int sdc_set_plan(sdc_handle h, const sdc_plan* plan);
+
+/* Autotuner: times every built synthesis variant and every analysis variant on the handle's
+ * stream, at the launch shape of a step (batch x M states), reps launches each after one warm-up
+ * (1 <= reps <= 1000), and keeps the fastest of each (written to *chosen unless NULL).  Blocks
+ * until the timing is done.  Overwrites the handle's synthesis and analysis workspaces (states
+ * passed to other calls are not touched) and drops cached step graphs.  SDC_EHIP if a launch
+ * fails (the previous plan is kept). */
+int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen);
+
 /* Copies of setup results to HOST buffers (blocking; for checking the FP64 setup):
  * mu[nlat], w[nlat] Gauss nodes and weights; tau[M], Q[M*M] (row-major) for 1 <= M <= cfg.M;
  * Pbar[(T-m+1)*(nlat/2)] and H[...] rows n = m..T over the northern latitudes j < nlat/2. */

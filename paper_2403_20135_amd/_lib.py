@@ -32,6 +32,11 @@ class SdcInfo(ctypes.Structure):
                 ("device_bytes", c_ll), ("table_bytes", c_ll)]
 
 
+class SdcPlan(ctypes.Structure):
+    _fields_ = [("syn_lat_tiles", c_int), ("syn_depth", c_int), ("ana_depth", c_int),
+                ("ana_interleave", c_int)]
+
+
 class SDCError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{_NAMES.get(code, code)}: {msg}")
@@ -56,6 +61,9 @@ _SIGS = {
     "eval_implicit": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sdc_sync": (c_int, [c_void_p]),
     "sdc_get_info": (c_int, [c_void_p, ctypes.POINTER(SdcInfo)]),
+    "sdc_get_plan": (c_int, [c_void_p, ctypes.POINTER(SdcPlan)]),
+    "sdc_set_plan": (c_int, [c_void_p, ctypes.POINTER(SdcPlan)]),
+    "sdc_autotune": (c_int, [c_void_p, c_int, ctypes.POINTER(SdcPlan)]),
     "sdc_copy_grid": (c_int, [c_void_p, P_DOUBLE, P_DOUBLE]),
     "sdc_copy_coefficients": (c_int, [c_void_p, c_int, P_DOUBLE, P_DOUBLE]),
     "sdc_copy_legendre": (c_int, [c_void_p, c_int, P_DOUBLE, P_DOUBLE]),

@@ -142,6 +142,22 @@ class SDC:
             out[name] = (ms.value, n.value)
         return out
 
+    def plan(self) -> dict:
+        """The Legendre launch variants in use (see sdc_plan)."""
+        pl = _lib.SdcPlan()
+        check(self.lib.sdc_get_plan(self.h, ctypes.byref(pl)))
+        return {k: getattr(pl, k) for k, _ in pl._fields_}
+
+    def set_plan(self, syn_lat_tiles: int, syn_depth: int, ana_depth: int, ana_interleave: int):
+        pl = _lib.SdcPlan(syn_lat_tiles, syn_depth, ana_depth, ana_interleave)
+        check(self.lib.sdc_set_plan(self.h, ctypes.byref(pl)))
+
+    def autotune(self, reps: int = 10) -> dict:
+        """Time every built variant at this handle's step shape and keep the fastest."""
+        pl = _lib.SdcPlan()
+        check(self.lib.sdc_autotune(self.h, int(reps), ctypes.byref(pl)))
+        return {k: getattr(pl, k) for k, _ in pl._fields_}
+
     def info(self) -> dict:
         inf = _lib.SdcInfo()
         check(self.lib.sdc_get_info(self.h, ctypes.byref(inf)))

@@ -154,8 +154,9 @@ struct sdc_ctx {
     int* n_of = nullptr;
     int* m_of = nullptr;
     double2* tw = nullptr;
-    int2* syn_tasks = nullptr;        // SWE synthesis workgroups (XCD-ordered)
-    int n_syn = 0;
+    int2* syn_tasks_t[3] = {nullptr, nullptr, nullptr};   // the same for 1, 2, 4 latitude tiles
+    int n_syn_t[3] = {0, 0, 0};
+    LegPlan lplan{};                  // Legendre launch variants (defaults or sdc_autotune)
     int4* ana_tasks = nullptr;        // SWE analysis: 4 wave tasks per workgroup (XCD-ordered)
     int n_ana_wg = 0;
     int2* ssyn_tasks = nullptr;       // scalar synthesis (m, latitude group)
@@ -217,6 +218,17 @@ struct sdc_ctx {
         (void)hipEventRecord(e, st);
         ev_marks[k].push_back({(size_t)start, ev_used - 1});
     }
+    // SWE synthesis workgroups (XCD-ordered) for the plan's latitude tiles per workgroup
+    static int tiles_index(int jt) { return jt == 4 ? 2 : (jt == 2 ? 1 : 0); }
+    const int2* syn_list() const { return syn_tasks_t[tiles_index(lplan.syn_tiles)]; }
+    int syn_count() const { return n_syn_t[tiles_index(lplan.syn_tiles)]; }
+    void drop_graphs() {
+        for (auto& ge : graphs) {
+            (void)hipGraphExecDestroy(ge.exec);
+            (void)hipGraphDestroy(ge.graph);
+        }
+        graphs.clear();
+    }
     void reset_timing() {
         ev_used = 0;
         for (auto& v : ev_marks) v.clear();
@@ -240,10 +252,7 @@ struct sdc_ctx {
         return SDC_OK;
     }
     ~sdc_ctx() {
-        for (auto& ge : graphs) {
-            (void)hipGraphExecDestroy(ge.exec);
-            (void)hipGraphDestroy(ge.graph);
-        }
+        drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
@@ -330,20 +339,22 @@ int setup(sdc_ctx* c) {
     // grouped per block of 8 orders on one XCD (the partial output lines of neighbouring orders
     // meet in that L2) and issued longest first.
     const int ntj = g.nhp / 16, njg = (ntj + 3) / 4;
-    {
+    for (int jt_per = 1; jt_per <= 4; jt_per *= 2) {
         std::vector<int2> t;
         std::vector<int> grp;
         std::vector<double> wk;
         for (int m = 0; m <= g.T; ++m)
-            for (int jt = 0; jt < ntj; ++jt) {
+            for (int jt = 0; jt < ntj; jt += jt_per) {
                 t.push_back(make_int2(m, jt));
                 grp.push_back(m / 8);
-                wk.push_back((double)((npk_of(g.T, m, 0) + 3) / 4) + 4.0);
+                const int tiles = ntj - jt < jt_per ? ntj - jt : jt_per;
+                wk.push_back((double)((npk_of(g.T, m, 0) + 3) / 4) * tiles + 4.0);
             }
         std::vector<int2> ord = xcd_order(t, grp, wk, make_int2(-1, 0));
-        c->n_syn = (int)ord.size();
-        if ((rc = c->alloc(c->syn_tasks, ord.size()))) return rc;
-        HIP_TRY(hipMemcpy(c->syn_tasks, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice));
+        int2*& dst = c->syn_tasks_t[sdc_ctx::tiles_index(jt_per)];
+        c->n_syn_t[sdc_ctx::tiles_index(jt_per)] = (int)ord.size();
+        if ((rc = c->alloc(dst, ord.size()))) return rc;
+        HIP_TRY(hipMemcpy(dst, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice));
     }
     {
         std::vector<int4> t, sw;
@@ -419,15 +430,15 @@ int setup(sdc_ctx* c) {
 // by launch_prep_cml).
 void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr) {
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
-    launch_synthesis_swe(c->tables(), c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->four,
-                         c->g, c->st);
+    launch_synthesis_swe(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
+                         c->cml, S, c->four, c->g, c->st);
     c->end(SDC_KERNEL_SYNTHESIS, t);
     t = c->begin(SDC_KERNEL_GRID);
     launch_grid_swe(c->four, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, save, c->g, c->st);
     c->end(SDC_KERNEL_GRID, t);
     t = c->begin(SDC_KERNEL_ANALYSIS);
-    launch_analysis_swe(c->tables(), c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap, out, c->g,
-                        c->st);
+    launch_analysis_swe(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
+                        out, c->g, c->st);
     c->end(SDC_KERNEL_ANALYSIS, t);
 }
 
@@ -441,11 +452,11 @@ void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2*
 // out_acc += J_E(u)^T ebar for S states whose stage grid fields are in `save`.
 void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save, double* out_acc) {
     launch_prep_cml_adj(ebar, S, c->cml, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->g.T, c->st);
-    launch_synthesis_adj(c->tables(), c->toff, c->rowoff, c->syn_tasks, c->n_syn, c->cml, S, c->adj_four5,
-                         c->g, c->st);
+    launch_synthesis_adj(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
+                         c->cml, S, c->adj_four5, c->g, c->st);
     launch_grid_adj(c->adj_four5, save, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
-    launch_analysis_adjoint(c->tables(), c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->inv_lap, out_acc,
-                            c->g, c->st);
+    launch_analysis_adjoint(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S,
+                            c->inv_lap, out_acc, c->g, c->st);
 }
 
 size_t stage_states(const sdc_ctx* c, int s, int M) {     // states stored before stage s
@@ -526,6 +537,110 @@ int sdc_get_info(sdc_handle h, sdc_info* info) {
     info->precision = h->cfg.precision;
     info->device_bytes = h->bytes;
     info->table_bytes = h->table_bytes;
+    return SDC_OK;
+}
+
+int sdc_get_plan(sdc_handle h, sdc_plan* plan) {
+    if (int rc = check_handle(h)) return rc;
+    if (!plan) return fail(SDC_EINVAL, "plan is NULL");
+    plan->syn_lat_tiles = h->lplan.syn_tiles;
+    plan->syn_depth = h->lplan.syn_depth;
+    plan->ana_depth = h->lplan.ana_depth;
+    plan->ana_interleave = h->lplan.ana_interleave;
+    return SDC_OK;
+}
+
+int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
+    if (int rc = check_handle(h)) return rc;
+    if (!plan) return fail(SDC_EINVAL, "plan is NULL");
+    const int jt = plan->syn_lat_tiles, d = plan->syn_depth;
+    const bool syn_ok = (jt == 1 && (d == 8 || d == 4)) || (jt == 2 && (d == 4 || d == 2)) || (jt == 4 && d == 2);
+    if (!syn_ok)
+        return fail(SDC_EINVAL, "synthesis variant (%d tiles, depth %d) not built: use (1, 8), (1, 4), (2, 4), "
+                    "(2, 2) or (4, 2)", jt, d);
+    if ((plan->ana_depth != 2 && plan->ana_depth != 4) || (plan->ana_interleave != 0 && plan->ana_interleave != 1))
+        return fail(SDC_EINVAL, "analysis variant (depth %d, interleave %d) not built: depth 2 or 4, interleave 0 or 1",
+                    plan->ana_depth, plan->ana_interleave);
+    h->lplan.syn_tiles = plan->syn_lat_tiles;
+    h->lplan.syn_depth = plan->syn_depth;
+    h->lplan.ana_depth = plan->ana_depth;
+    h->lplan.ana_interleave = plan->ana_interleave;
+    h->drop_graphs();                 // recaptured with the new variants on their next replay
+    return SDC_OK;
+}
+
+int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
+    if (int rc = check_handle(h)) return rc;
+    if (reps < 1 || reps > 1000) return fail(SDC_EINVAL, "reps = %d outside [1, 1000]", reps);
+    sdc_ctx* c = h;
+    // the launch shape that dominates a step: every node state of every member at once
+    const int S = c->cfg.batch * c->cfg.M;
+    // finite operands for every candidate (the buffers are workspaces every step rewrites)
+    HIP_TRY(hipMemsetAsync(c->cml, 0, (size_t)c->g.nrows * c->smax * kCmlVals * sizeof(double), c->st));
+    HIP_TRY(hipMemsetAsync(c->G, 0, (size_t)(c->g.T + 1) * 2 * c->g.nhp * c->smax * kAnaStride * sizeof(double),
+                           c->st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SDC_EHIP, "hipEventCreate failed");
+    }
+    auto time_it = [&](auto&& launch, float& ms) -> hipError_t {
+        launch();                                        // warm-up (code objects, caches)
+        hipError_t e = hipEventRecord(e0, c->st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, c->st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) e = hipGetLastError();
+        return e;
+    };
+    const LegPlan saved = c->lplan;
+    const LegPlan syn_cands[5] = {{1, 8, 4, 1}, {1, 4, 4, 1}, {2, 4, 4, 1}, {2, 2, 4, 1}, {4, 2, 4, 1}};
+    const LegPlan ana_cands[4] = {{1, 8, 4, 1}, {1, 8, 4, 0}, {1, 8, 2, 1}, {1, 8, 2, 0}};
+    LegPlan best = saved;
+    float best_syn = 0.f, best_ana = 0.f;
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < 5 && err == hipSuccess; ++k) {
+        c->lplan = syn_cands[k];
+        float ms = 0.f;
+        err = time_it([&] {
+            launch_synthesis_swe(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
+                                 c->cml, S, c->four, c->g, c->st);
+        }, ms);
+        if (err == hipSuccess && (k == 0 || ms < best_syn)) {
+            best_syn = ms;
+            best.syn_tiles = syn_cands[k].syn_tiles;
+            best.syn_depth = syn_cands[k].syn_depth;
+        }
+    }
+    for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+        c->lplan = ana_cands[k];
+        float ms = 0.f;
+        err = time_it([&] {
+            launch_analysis_swe(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
+                                c->E, c->g, c->st);
+        }, ms);
+        if (err == hipSuccess && (k == 0 || ms < best_ana)) {
+            best_ana = ms;
+            best.ana_depth = ana_cands[k].ana_depth;
+            best.ana_interleave = ana_cands[k].ana_interleave;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) {
+        c->lplan = saved;
+        return fail(SDC_EHIP, "autotune launch failed: %s", hipGetErrorString(err));
+    }
+    c->lplan = best;
+    c->drop_graphs();
+    if (chosen) {
+        chosen->syn_lat_tiles = best.syn_tiles;
+        chosen->syn_depth = best.syn_depth;
+        chosen->ana_depth = best.ana_depth;
+        chosen->ana_interleave = best.ana_interleave;
+    }
     return SDC_OK;
 }
 

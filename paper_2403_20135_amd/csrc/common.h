@@ -54,18 +54,31 @@ __host__ __device__ inline size_t tab_index(int np4, int kk, int jh) {
 }
 
 // Workgroups of a launch are dealt to the 8 XCDs round-robin by their linear index, and each
-// XCD starts its share in order.  A Legendre launch over G state groups uses a 1-D grid of
-// xcd_grid(ntasks, G) workgroups and maps workgroup w to (task, group) so that the G groups of a
-// task run back to back on one XCD: the table tile they share comes from HBM once and from that
-// XCD's L2 for the other groups.  With G = 1 the map is the identity.  Tasks >= ntasks are
-// padding (the kernel returns).
+// XCD starts its share in order.  A Legendre analysis launch over G state groups uses a 1-D grid
+// of xcd_grid(ntasks, G) workgroups.  Task t always runs on XCD t % 8.  Interleaved, the G groups
+// of a task run back to back on that XCD (the table tile they share comes from HBM once and from
+// the XCD's L2 for the other groups); otherwise group-major (group g starts after every task of
+// group g - 1 has been issued).  Tasks >= ntasks are padding (the kernel returns).
 __host__ inline unsigned xcd_grid(int ntasks, int ngroups) {
     return (unsigned)((ntasks + 7) / 8) * 8u * (unsigned)ngroups;
 }
-__device__ inline int2 xcd_task_group(int ngroups) {
-    const int w = blockIdx.x, x = w & 7, l = w >> 3;
+__device__ inline int2 xcd_task_group(int ntasks, int ngroups, int interleave) {
+    const int w = blockIdx.x;
+    if (!interleave) {
+        const int npad = (ntasks + 7) / 8 * 8;
+        return make_int2(w % npad, w / npad);
+    }
+    const int x = w & 7, l = w >> 3;
     return make_int2((l / ngroups) * 8 + x, l % ngroups);
 }
+
+// Launch variants of the Legendre kernels, chosen per handle (defaults or timed at run time):
+// synthesis latitude tiles per workgroup and operand stages in flight per wave ((1, 8), (1, 4),
+// (2, 4), (2, 2), (4, 2)), analysis table stages per wave (4 or 2) and state-group order.  The
+// defaults are the variants measured fastest for one T255 member.
+struct LegPlan {
+    int syn_tiles = 2, syn_depth = 4, ana_depth = 2, ana_interleave = 1;
+};
 
 // Synthesis input ("coefficient-major", written by the update/prep kernels): for table row
 // (m, p, kk) and state s, 8 doubles (zeta, Phi', psi, chi) x (Re, Im) with psi, chi the inverse
@@ -119,19 +132,19 @@ struct Tables {
     const float* H32;
 };
 // Synthesis tasks: (m, latitude tile) per workgroup, XCD-ordered; x < 0 = pad.
-void launch_synthesis_swe(const Tables& tb, const long long* toff, const int* rowoff,
-                          const int2* tasks, int ntasks, const double* cml, int nstates,
-                          double2* four, const Geom& g, hipStream_t st);
+void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
+                          const int* rowoff, const int2* tasks, int ntasks, const double* cml,
+                          int nstates, double2* four, const Geom& g, hipStream_t st);
 // Analysis tasks: (m, p, first row, valid) per workgroup, XCD-ordered.
-void launch_analysis_swe(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
-                         const double* G, int nstates, const double* neg_lap, double* out,
-                         const Geom& g, hipStream_t st);
+void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
+                         const int4* tasks, int nwg, const double* G, int nstates,
+                         const double* neg_lap, double* out, const Geom& g, hipStream_t st);
 void launch_synthesis_scalar(const double* P, const long long* toff, const int2* tasks, int ntasks,
                              const double* spec, int nfields, double2* four, const Geom& g,
                              hipStream_t st);
-void launch_analysis_adjoint(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
-                             const double* G, int nstates, const double* inv_lap, double* out_acc,
-                             const Geom& g, hipStream_t st);
+void launch_analysis_adjoint(const Tables& tb, const LegPlan& plan, const long long* toff,
+                             const int4* tasks, int nwg, const double* G, int nstates,
+                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st);
 void launch_round_tables(const double* P, const double* H, float* P32, float* H32, long long n,
                          hipStream_t st);
 void launch_analysis_scalar(const double* P, const long long* toff, const int4* tasks, int ntasks,
@@ -188,9 +201,9 @@ void launch_solve(double alpha, const double* beta, double* u, const int* n_of, 
 // adjoint.hip
 void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int* n_of, const int* m_of,
                          const int* rowoff, const double* neg_lap, int ncoef, int T, hipStream_t st);
-void launch_synthesis_adj(const Tables& tb, const long long* toff, const int* rowoff,
-                          const int2* tasks, int ntasks, const double* cml, int nstates,
-                          double2* four5, const Geom& g, hipStream_t st);
+void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long* toff,
+                          const int* rowoff, const int2* tasks, int ntasks, const double* cml,
+                          int nstates, double2* four5, const Geom& g, hipStream_t st);
 struct AdjUpdateArgs {
     const double* ubar;          // [B][M][3][ncoef] adjoint of this sweep's nodes (or lam: [B][3][ncoef])
     long long ubar_node, ubar_member;

@@ -87,21 +87,24 @@ template <> struct SynTiles<kSynAdjoint> {
     }
 };
 
-template <typename TT, int NT> struct SynStage {
-    TT a[2];                 // Pbar, H
+template <typename TT, int NT, int JT> struct SynStage {
+    TT a[JT][2];             // Pbar, H of each latitude tile
     double b[NT];            // rounded to TT at the MFMA (a conversion here would wait for the load)
 };
 
 constexpr int kSynBlock = 128;                   // two waves: the two parities
 
-template <int MODE, typename TT>
+// JT latitude tiles per workgroup share every coefficient column they load; D operand stages are
+// in flight per wave.  Task (m, jt0) covers tiles jt0 .. jt0 + JT - 1 (tiles past the last one
+// re-read it and store nothing).
+template <int MODE, typename TT, int JT, int D>
 __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int* __restrict__ rowoff, const int2* __restrict__ tasks, const double* __restrict__ cml,
     int nstates, double* __restrict__ four, Geom g) {
     using TL = SynTiles<MODE>;
     using MM = Mma<TT>;
-    constexpr int NT = TL::NT, D = 8;
+    constexpr int NT = TL::NT;
     constexpr unsigned tsz = sizeof(TT);
     __shared__ double part[2][NT][4][64];
     // state groups on blockIdx.y: the groups of one task run far apart in time (sharing a
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const int2 task = tasks[blockIdx.x];
     if (task.x < 0) return;                                  // padding workgroup (uniform)
     const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // parity of this wave
-    const int m = task.x, jt = task.y;
+    const int m = task.x, jt0 = task.y, ntj = g.nhp >> 4;
     const int lane = threadIdx.x & 63, i = lane & 15, q = lane >> 4, v = i & 3;
     const int S = nstates;
     const int s = blockIdx.y * 4 + (i >> 2);
@@ -121,31 +124,47 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const unsigned rstride = (unsigned)S * kCmlVals * 8u;           // bytes per cml row
     const int nst = (npk_of(g.T, m, p) + 3) >> 2;                   // 4-row steps of this parity
     const unsigned tstep = 4u * 16u * tsz, cstep = 4u * rstride;    // bytes per 4-row step
-    const unsigned tlane = ((unsigned)(jt * 4 * nst + q) * 16 + i) * tsz, clane = (unsigned)q * rstride;
+    unsigned tlane[JT];
+#pragma unroll
+    for (int u = 0; u < JT; ++u) {
+        const int jt = jt0 + u < ntj ? jt0 + u : ntj - 1;
+        tlane[u] = ((unsigned)(jt * 4 * nst + q) * 16 + i) * tsz;
+    }
+    const unsigned clane = (unsigned)q * rstride;
     const char* tP = (const char*)(P + toff[2 * m + p]);
     const char* tH = (const char*)(H + toff[2 * m + p]);
     const char* cb = (const char*)(cml + (size_t)rowoff[2 * m + p] * S * kCmlVals);
     auto ldd = [](const char* base, unsigned off) { return *(const double*)(base + off); };
     auto ldt = [](const char* base, unsigned off) { return *(const TT*)(base + off); };
 
-    typename MM::vec acc[NT];
+    typename MM::vec acc[JT][NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = MM::zero();
-    auto load = [&](SynStage<TT, NT>& x, int j) {
-        const unsigned ot = tlane + (unsigned)j * tstep, oc = clane + (unsigned)j * cstep;
-        x.a[0] = ldt(tP, ot);
-        x.a[1] = ldt(tH, ot);
+    for (int u = 0; u < JT; ++u)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[u][t] = MM::zero();
+    auto load = [&](SynStage<TT, NT, JT>& x, int j) {
+        const unsigned oc = clane + (unsigned)j * cstep;
+#pragma unroll
+        for (int u = 0; u < JT; ++u) {
+            const unsigned ot = tlane[u] + (unsigned)j * tstep;
+            x.a[u][0] = ldt(tP, ot);
+            x.a[u][1] = ldt(tH, ot);
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t) x.b[t] = ldd(cb, oc + boff[t]);
     };
-    auto compute = [&](const SynStage<TT, NT>& x) {
+    auto compute = [&](const SynStage<TT, NT, JT>& x) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = MM::mma(x.a[TL::is_h(t) ? 1 : 0], (TT)x.b[t], acc[t]);
+        for (int t = 0; t < NT; ++t) {
+            const TT bt = (TT)x.b[t];
+#pragma unroll
+            for (int u = 0; u < JT; ++u) acc[u][t] = MM::mma(x.a[u][TL::is_h(t) ? 1 : 0], bt, acc[u][t]);
+        }
     };
     // Loads past the chain's end re-read its last step (cache hits, results unused): a
     // branch-free loop body lets every stage wait for its own loads only.
     if (nst > 0) {
-        SynStage<TT, NT> st[D];
+        SynStage<TT, NT, JT> st[D];
 #pragma unroll
         for (int u = 0; u < D; ++u) load(st[u], u < nst ? u : nst - 1);
         int j0 = 0;
@@ -161,70 +180,92 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
         for (int u = 0; u < D; ++u)
             if (u < nst - j0) compute(st[u]);
     }
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) part[p][t][r][lane] = (double)acc[t][r];
-    __syncthreads();
 
-    // wave 0: north = even + odd; wave 1: south = even - odd (Pbar tiles), odd - even (H tiles)
+    // wave 0: north = even + odd; wave 1: south = even - odd (Pbar tiles), odd - even (H tiles);
+    // one latitude tile at a time through the same LDS exchange buffer
     const int ns = p;
     const double mm = (double)m;
     const size_t fstride = (size_t)2 * g.nlat * g.ms;               // doubles per Fourier field
     const double inva = 1.0 / g.radius;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int jh = jt * 16 + MM::row(r, q);
-        if (s >= S || jh >= g.nh) continue;
-        const int j = ns ? g.nlat - 1 - jh : jh;
-        double val[NT];
+    for (int u = 0; u < JT; ++u) {
+        if (u > 0) __syncthreads();
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const double e = ns == 0 ? (double)acc[t][r] : part[0][t][r][lane];
-            const double o = ns == 0 ? part[1][t][r][lane] : (double)acc[t][r];
-            val[t] = ns == 0 ? e + o : (TL::is_h(t) ? o - e : e - o);
-        }
-        double* base = four + (((size_t)s * TL::NF * g.nlat + j) * g.ms + m) * 2 + (v & 1);
-        if constexpr (MODE == kSynForward) {
-            base[(size_t)(v >> 1) * fstride] = val[0];
-            const double sx = (v & 1) ? mm : -mm, sh = v < 2 ? -1.0 : 1.0;
-            base[(size_t)(2 + (v >> 1)) * fstride] = (sx * val[1] + sh * val[2]) * inva;
-        } else {
-            const double hf = m > 0 ? 0.5 : 1.0;
-            const double sx = (v == 0 || v == 3) ? -mm : mm;
-            base[(size_t)(v >> 1) * fstride] = hf * (sx * val[0] + val[1]);
-            if (v < 2) {
-                base[2 * fstride] = hf * ((v ? mm : -mm) * val[2]);
-                base[3 * fstride] = hf * val[3];
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[p][t][r][lane] = (double)acc[u][t][r];
+        __syncthreads();
+        if (jt0 + u >= ntj) continue;                        // uniform
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int jh = (jt0 + u) * 16 + MM::row(r, q);
+            if (s >= S || jh >= g.nh) continue;
+            const int j = ns ? g.nlat - 1 - jh : jh;
+            double val[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double e = ns == 0 ? (double)acc[u][t][r] : part[0][t][r][lane];
+                const double o = ns == 0 ? part[1][t][r][lane] : (double)acc[u][t][r];
+                val[t] = ns == 0 ? e + o : (TL::is_h(t) ? o - e : e - o);
+            }
+            double* base = four + (((size_t)s * TL::NF * g.nlat + j) * g.ms + m) * 2 + (v & 1);
+            if constexpr (MODE == kSynForward) {
+                base[(size_t)(v >> 1) * fstride] = val[0];
+                const double sx = (v & 1) ? mm : -mm, sh = v < 2 ? -1.0 : 1.0;
+                base[(size_t)(2 + (v >> 1)) * fstride] = (sx * val[1] + sh * val[2]) * inva;
             } else {
-                base[4 * fstride] = hf * val[2];
+                const double hf = m > 0 ? 0.5 : 1.0;
+                const double sx = (v == 0 || v == 3) ? -mm : mm;
+                base[(size_t)(v >> 1) * fstride] = hf * (sx * val[0] + val[1]);
+                if (v < 2) {
+                    base[2 * fstride] = hf * ((v ? mm : -mm) * val[2]);
+                    base[3 * fstride] = hf * val[3];
+                } else {
+                    base[4 * fstride] = hf * val[2];
+                }
             }
         }
     }
 }
 
-void launch_synthesis_swe(const Tables& tb, const long long* toff, const int* rowoff,
-                          const int2* tasks, int ntasks, const double* cml, int nstates,
-                          double2* four, const Geom& g, hipStream_t st) {
-    const dim3 grid(ntasks, (nstates + 3) / 4);
-    if (tb.P32)
-        k_synthesis<kSynForward, float><<<grid, kSynBlock, 0, st>>>(
-            tb.P32, tb.H32, toff, rowoff, tasks, cml, nstates, (double*)four, g);
-    else
-        k_synthesis<kSynForward, double><<<grid, kSynBlock, 0, st>>>(
-            tb.P, tb.H, toff, rowoff, tasks, cml, nstates, (double*)four, g);
+// Synthesis variants (latitude tiles per workgroup, stages in flight): (1, 8), (1, 4), (2, 4),
+// (2, 2), (4, 2).
+template <int MODE, typename TT>
+static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t st, const TT* P,
+                                     const TT* H, const long long* toff, const int* rowoff,
+                                     const int2* tasks, const double* cml, int nstates,
+                                     double* four, const Geom& g) {
+#define SYN(JT, D) k_synthesis<MODE, TT, JT, D><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates, four, g)
+    if (plan.syn_tiles == 4) SYN(4, 2);
+    else if (plan.syn_tiles == 2 && plan.syn_depth == 2) SYN(2, 2);
+    else if (plan.syn_tiles == 2) SYN(2, 4);
+    else if (plan.syn_depth == 4) SYN(1, 4);
+    else SYN(1, 8);
+#undef SYN
 }
 
-void launch_synthesis_adj(const Tables& tb, const long long* toff, const int* rowoff,
-                          const int2* tasks, int ntasks, const double* cml, int nstates,
-                          double2* four5, const Geom& g, hipStream_t st) {
+void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
+                          const int* rowoff, const int2* tasks, int ntasks, const double* cml,
+                          int nstates, double2* four, const Geom& g, hipStream_t st) {
     const dim3 grid(ntasks, (nstates + 3) / 4);
     if (tb.P32)
-        k_synthesis<kSynAdjoint, float><<<grid, kSynBlock, 0, st>>>(
-            tb.P32, tb.H32, toff, rowoff, tasks, cml, nstates, (double*)four5, g);
+        launch_synthesis_variant<kSynForward, float>(plan, grid, st, tb.P32, tb.H32, toff, rowoff,
+                                                     tasks, cml, nstates, (double*)four, g);
     else
-        k_synthesis<kSynAdjoint, double><<<grid, kSynBlock, 0, st>>>(
-            tb.P, tb.H, toff, rowoff, tasks, cml, nstates, (double*)four5, g);
+        launch_synthesis_variant<kSynForward, double>(plan, grid, st, tb.P, tb.H, toff, rowoff,
+                                                      tasks, cml, nstates, (double*)four, g);
+}
+
+void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long* toff,
+                          const int* rowoff, const int2* tasks, int ntasks, const double* cml,
+                          int nstates, double2* four5, const Geom& g, hipStream_t st) {
+    const dim3 grid(ntasks, (nstates + 3) / 4);
+    if (tb.P32)
+        launch_synthesis_variant<kSynAdjoint, float>(plan, grid, st, tb.P32, tb.H32, toff, rowoff,
+                                                     tasks, cml, nstates, (double*)four5, g);
+    else
+        launch_synthesis_variant<kSynAdjoint, double>(plan, grid, st, tb.P, tb.H, toff, rowoff,
+                                                      tasks, cml, nstates, (double*)four5, g);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -254,16 +295,15 @@ template <typename TT> struct AnaStage {
     typename Mma<TT>::vec aP, aH;   // table rows, 4 consecutive latitudes per lane group
 };
 
-template <int MODE, typename TT>
+template <int MODE, typename TT, int D>
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
-    const int4* __restrict__ tasks, int ntasks, const double* __restrict__ G, int nstates,
-    const double* __restrict__ nscale, double* __restrict__ out, Geom g) {
+    const int4* __restrict__ tasks, int ntasks, int interleave, const double* __restrict__ G,
+    int nstates, const double* __restrict__ nscale, double* __restrict__ out, Geom g) {
     using MM = Mma<TT>;
     using vec = typename MM::vec;
-    constexpr int D = 4;
     __shared__ __align__(16) double gl[2][kAnaBuf + 2];       // + a dummy slot for idle threads
-    const int2 tg = xcd_task_group((nstates + 3) >> 2);
+    const int2 tg = xcd_task_group(ntasks, (nstates + 3) >> 2, interleave);
     if (tg.x >= ntasks) return;
     const int4 task = tasks[tg.x];
     if (task.w == 0) return;                                 // padding workgroup (uniform)
@@ -417,28 +457,43 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     }
 }
 
-void launch_analysis_swe(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
-                         const double* G, int nstates, const double* neg_lap, double* out,
-                         const Geom& g, hipStream_t st) {
-    const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
-    if (tb.P32)
-        k_analysis_swe<kAnaForward, float><<<grid, kBlock, 0, st>>>(tb.P32, tb.H32, toff, tasks, nwg,
-                                                                    G, nstates, neg_lap, out, g);
+// Analysis variants: D = 4 or 2 table stages in flight per wave; state groups interleaved per
+// XCD or group-major.
+template <int MODE, typename TT>
+static void launch_analysis_variant(const LegPlan& plan, unsigned grid, hipStream_t st, const TT* P,
+                                    const TT* H, const long long* toff, const int4* tasks, int nwg,
+                                    const double* G, int nstates, const double* nscale, double* out,
+                                    const Geom& g) {
+    if (plan.ana_depth == 2)
+        k_analysis_swe<MODE, TT, 2><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg, plan.ana_interleave,
+                                                             G, nstates, nscale, out, g);
     else
-        k_analysis_swe<kAnaForward, double><<<grid, kBlock, 0, st>>>(tb.P, tb.H, toff, tasks, nwg,
-                                                                     G, nstates, neg_lap, out, g);
+        k_analysis_swe<MODE, TT, 4><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg, plan.ana_interleave,
+                                                             G, nstates, nscale, out, g);
 }
 
-void launch_analysis_adjoint(const Tables& tb, const long long* toff, const int4* tasks, int nwg,
-                             const double* G, int nstates, const double* inv_lap, double* out_acc,
-                             const Geom& g, hipStream_t st) {
+void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
+                         const int4* tasks, int nwg, const double* G, int nstates,
+                         const double* neg_lap, double* out, const Geom& g, hipStream_t st) {
     const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
     if (tb.P32)
-        k_analysis_swe<kAnaAdjoint, float><<<grid, kBlock, 0, st>>>(tb.P32, tb.H32, toff, tasks, nwg,
-                                                                    G, nstates, inv_lap, out_acc, g);
+        launch_analysis_variant<kAnaForward, float>(plan, grid, st, tb.P32, tb.H32, toff, tasks, nwg, G,
+                                                    nstates, neg_lap, out, g);
     else
-        k_analysis_swe<kAnaAdjoint, double><<<grid, kBlock, 0, st>>>(tb.P, tb.H, toff, tasks, nwg,
-                                                                     G, nstates, inv_lap, out_acc, g);
+        launch_analysis_variant<kAnaForward, double>(plan, grid, st, tb.P, tb.H, toff, tasks, nwg, G,
+                                                     nstates, neg_lap, out, g);
+}
+
+void launch_analysis_adjoint(const Tables& tb, const LegPlan& plan, const long long* toff,
+                             const int4* tasks, int nwg, const double* G, int nstates,
+                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st) {
+    const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
+    if (tb.P32)
+        launch_analysis_variant<kAnaAdjoint, float>(plan, grid, st, tb.P32, tb.H32, toff, tasks, nwg, G,
+                                                    nstates, inv_lap, out_acc, g);
+    else
+        launch_analysis_variant<kAnaAdjoint, double>(plan, grid, st, tb.P, tb.H, toff, tasks, nwg, G,
+                                                     nstates, inv_lap, out_acc, g);
 }
 
 // FP32 copies of the FP64 tables (same layout), for the FP32 precision mode.

@@ -1,0 +1,81 @@
+"""Launch variants of the Legendre kernels and the autotuner (GPU, through the C ABI).
+
+Every variant forms the same sums in the same order, so f_E, a step and an adjoint step must agree
+bitwise with the default variants; the grids include an odd number of 16-latitude tiles (T63:
+three tiles, so two- and four-tile synthesis tasks have tiles past the end) and batched node
+states.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2403_20135_amd import _lib
+
+from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+DEFAULT = dict(syn_lat_tiles=2, syn_depth=4, ana_depth=2, ana_interleave=1)
+VARIANTS = [(1, 8, 4, 1), (1, 4, 4, 1), (2, 4, 4, 1), (2, 2, 4, 1), (4, 2, 4, 1), (1, 8, 2, 1),
+            (1, 8, 4, 0), (2, 4, 2, 0)]
+
+
+def _outputs(sdc, x, lam, dt):
+    f = _dev(np.zeros_like(x))
+    sdc.eval_explicit(_dev(x), f)
+    u = _dev(x)
+    sdc.step(u, dt)
+    g = _dev(np.zeros_like(x))
+    sdc.step_adjoint(_dev(x), _dev(lam), g, dt)
+    sdc.sync()
+    return _host(f), _host(u), _host(g)
+
+
+@pytest.mark.parametrize("T,nlat,nlon,batch,prec", [(63, 96, 192, 2, "fp64"), (31, 48, 96, 3, "fp32"),
+                                                    (21, 34, 64, 1, "fp64")])
+def test_variants_agree_bitwise(T, nlat, nlon, batch, prec):
+    sdc = _sdc(T, nlat, nlon, 3, 3, batch, precision=prec)
+    x = _states(T, batch, 301)
+    lam = np.stack([W.random_state(T, 302 + b) for b in range(batch)])
+    lam[..., :T + 1, 1] = 0.0
+    dt = 600.0
+    assert sdc.plan() == DEFAULT
+    ref = _outputs(sdc, x, lam, dt)
+    for v in VARIANTS:
+        sdc.set_plan(*v)
+        got = _outputs(sdc, x, lam, dt)
+        for name, a, b in zip(("f_E", "step", "adjoint"), got, ref):
+            print(f"[gpu] T{T} {prec} variant {v} {name}: max |diff| {np.max(np.abs(a - b)):.3e}", flush=True)
+            assert np.array_equal(a, b), (v, name)
+
+
+def test_set_plan_rejects_variants_not_built():
+    sdc = _sdc(21, 34, 64, 2, 2, 1)
+    for bad in [(2, 8, 4, 1), (4, 4, 4, 1), (3, 4, 4, 1), (1, 6, 4, 1), (1, 8, 3, 1), (1, 8, 4, 2)]:
+        with pytest.raises(_lib.SDCError) as ei:
+            sdc.set_plan(*bad)
+        assert ei.value.code == _lib.SDC_EINVAL
+    assert sdc.plan() == DEFAULT
+
+
+def test_autotune_keeps_results_and_graphs():
+    T, nlat, nlon, M, K, dt = 63, 96, 192, 3, 2, 480.0
+    sdc = _sdc(T, nlat, nlon, M, K, 4)
+    o = _oracle(T, nlat, nlon)
+    x0 = _states(T, 4, 311)
+    x = _dev(x0)
+    sdc.step_graph(x, dt)                 # a cached graph from before tuning
+    chosen = sdc.autotune(5)
+    print(f"[gpu] autotune T{T} x4: {chosen}", flush=True)
+    assert chosen == sdc.plan()
+    assert (chosen["syn_lat_tiles"], chosen["syn_depth"]) in [(1, 8), (1, 4), (2, 4), (2, 2), (4, 2)]
+    assert chosen["ana_depth"] in (2, 4) and chosen["ana_interleave"] in (0, 1)
+    for _ in range(2):
+        sdc.step_graph(x, dt)             # recaptured with the chosen variants
+    sdc.sync()
+    ref = np.stack([o.step(x0[b], dt, M, K, steps=3) for b in range(4)])
+    err = rel_l2(_host(x), ref, T)
+    print(f"[gpu] after autotune: 3 steps rel L2 {err:.3e}", flush=True)
+    assert err <= 1e-11
+    with pytest.raises(_lib.SDCError):
+        sdc.autotune(0)

@@ -2,8 +2,9 @@
 """Benchmark: dSDC steps/s of the T255, M=4, K=4 shallow-water workload on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload t255_m4k4] [--no-cpu-baseline]
-                    [--no-fp32] [--no-adjoint]
-    python bench.py --summarize-pmc FETCH.csv WRITE.csv COPY_MIB OUT.json   (counter summary)
+                    [--no-fp32] [--no-adjoint] [--plan TILES,DEPTH,ANA_DEPTH,INTERLEAVE]
+    python bench.py --summarize-pmc FETCH.csv WRITE.csv COPY_MIB OUT.json FETCH.log WRITE.log
+                                                                            (counter summary)
 
 Prints ONE JSON line.  Every handle first runs the library's autotuner (untimed; it picks the
 Legendre launch variants, reported as `legendre_plan`).  `value` is the plain FP64 path: exactly
@@ -106,6 +107,9 @@ def roofline_entry(flops, nbytes, secs, launches, precision):
     return e
 
 
+FORCED_PLAN = None          # --plan: Legendre variants set instead of tuned
+
+
 def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
     """Graph-replay steps/s, per-kernel HIP-event timing over eager steps, fwd+adj steps/s."""
     import torch
@@ -115,7 +119,11 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
     sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, batch, precision, W.RADIUS, W.GRAVITY,
               W.OMEGA, W.MEAN_DEPTH)
     x = torch.tensor(W.initial_state(wl)[None], dtype=torch.float64, device="cuda")
-    plan = sdc.autotune(10)                           # Legendre launch variants (untimed setup)
+    if FORCED_PLAN is not None:                       # fixed variants (profiling runs)
+        sdc.set_plan(*FORCED_PLAN)
+        plan = sdc.plan()
+    else:
+        plan = sdc.autotune(10)                       # Legendre launch variants (untimed setup)
     for _ in range(warmup):
         sdc.step(x, mb.dt)
     sdc.sync()
@@ -252,9 +260,10 @@ def measure_mixed(steps=20, warmup=3):
             "launch": "one hipGraph per step (members as parallel branches)"}
 
 
-def traffic_for(kernel):
+def traffic_for(kernel, plan):
     """Measured HBM bytes per launch of `kernel` from the committed counter summary, or None when
-    the summary is missing or was taken from other kernel sources."""
+    the summary is missing, was taken from other kernel sources or (for the Legendre classes)
+    from other launch variants than `plan`."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -262,16 +271,31 @@ def traffic_for(kernel):
         return None
     if t.get("source_sha") != source_hash() or kernel not in t.get("kernels", {}):
         return None
+    if kernel in ("synthesis", "analysis") and t.get("legendre_plan") != plan:
+        return None
     k = t["kernels"][kernel]
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
-def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json):
+def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     """Counter summary: mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel class, scaled
-    so that the device-to-device copy of copy_mib MiB reads and writes exactly that many bytes."""
+    so that the device-to-device copy of copy_mib MiB reads and writes exactly that many bytes.
+    The Legendre classes take the launch variants the profiled bench runs used (their JSON lines in
+    bench_logs name them; both runs must agree); the autotuner's trial launches of other variants
+    are left out."""
     import csv
-    # forward FP64 kernels of the bench workload (name prefixes as rocprofv3 prints them)
-    classes = {"void k_synthesis<0, double>": "synthesis", "void k_analysis_swe<0, double>": "analysis",
+    plans = []
+    for log in bench_logs:
+        found = [json.loads(line)["legendre_plan"] for line in open(log) if line.startswith('{"metric"')]
+        if not found:
+            raise RuntimeError(f"no bench result line in {log}")
+        plans.append(found[-1])
+    if any(p != plans[0] for p in plans):
+        raise RuntimeError(f"the counter runs tuned different Legendre variants: {plans}")
+    plan = plans[0]
+    # forward FP64 kernels of the bench workload (names as rocprofv3 prints them)
+    classes = {f"void k_synthesis<0, double, {plan['syn_lat_tiles']}, {plan['syn_depth']}>": "synthesis",
+               f"void k_analysis_swe<0, double, {plan['ana_depth']}>": "analysis",
                "void k_grid_swe<": "grid", "void k_update<": "update"}
 
     def per_kernel(path, counter):
@@ -291,6 +315,7 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json):
     f_scale = copy_bytes / (max(cf) * 1024.0)
     w_scale = copy_bytes / (max(cw) * 1024.0)
     out["fetch_scale"], out["write_scale"] = f_scale, w_scale
+    out["legendre_plan"] = plan
     for name, vals in fetch.items():
         cls = next((c for key, c in classes.items() if name.startswith(key)), None)
         if cls is None:
@@ -336,11 +361,18 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a reference kernel of known "
                          "traffic for scaling hardware byte counters)")
-    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB", "OUT"))
+    ap.add_argument("--plan", default=None, metavar="TILES,DEPTH,ANA_DEPTH,INTERLEAVE",
+                    help="set these Legendre launch variants instead of running the autotuner "
+                         "(profiling runs that must launch the same kernels)")
+    ap.add_argument("--summarize-pmc", nargs=6,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB", "OUT", "FETCH_LOG", "WRITE_LOG"))
     args = ap.parse_args()
+    global FORCED_PLAN
+    if args.plan:
+        FORCED_PLAN = tuple(int(v) for v in args.plan.split(","))
     if args.summarize_pmc:
-        f, w, mib, outp = args.summarize_pmc
-        summarize_pmc(f, w, float(mib), outp)
+        f, w, mib, outp, flog, wlog = args.summarize_pmc
+        summarize_pmc(f, w, float(mib), outp, [flog, wlog])
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the step on a single MI355X "
@@ -355,7 +387,7 @@ def main():
     kernels = r64["kernels"]
     dom = max(r64["kernel_ms"], key=lambda k: r64["kernel_ms"][k])
     d = kernels[dom]
-    tr = traffic_for(dom)
+    tr = traffic_for(dom, r64["plan"])
     roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
                 "frac": d["frac"], "traffic": tr, "kernel": dom, "avg_launch_us": d["avg_us"],
                 "timed_over": "eager steps with per-launch HIP events on the library's stream"}

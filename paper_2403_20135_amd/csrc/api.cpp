@@ -595,36 +595,49 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         if (e == hipSuccess) e = hipGetLastError();
         return e;
     };
+    // a candidate replaces the current variant only when it is at least 3 % faster (timing noise
+    // alone does not flip the choice)
+    constexpr float kMargin = 0.97f;
     const LegPlan saved = c->lplan;
     const LegPlan syn_cands[5] = {{1, 8, 4, 1}, {1, 4, 4, 1}, {2, 4, 4, 1}, {2, 2, 4, 1}, {4, 2, 4, 1}};
     const LegPlan ana_cands[4] = {{1, 8, 4, 1}, {1, 8, 4, 0}, {1, 8, 2, 1}, {1, 8, 2, 0}};
-    LegPlan best = saved;
-    float best_syn = 0.f, best_ana = 0.f;
+    float syn_ms[5] = {0.f}, ana_ms[4] = {0.f};
     hipError_t err = hipSuccess;
     for (int k = 0; k < 5 && err == hipSuccess; ++k) {
         c->lplan = syn_cands[k];
-        float ms = 0.f;
         err = time_it([&] {
             launch_synthesis_swe(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
                                  c->cml, S, c->four, c->g, c->st);
-        }, ms);
-        if (err == hipSuccess && (k == 0 || ms < best_syn)) {
-            best_syn = ms;
-            best.syn_tiles = syn_cands[k].syn_tiles;
-            best.syn_depth = syn_cands[k].syn_depth;
-        }
+        }, syn_ms[k]);
     }
     for (int k = 0; k < 4 && err == hipSuccess; ++k) {
         c->lplan = ana_cands[k];
-        float ms = 0.f;
         err = time_it([&] {
             launch_analysis_swe(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
                                 c->E, c->g, c->st);
-        }, ms);
-        if (err == hipSuccess && (k == 0 || ms < best_ana)) {
-            best_ana = ms;
-            best.ana_depth = ana_cands[k].ana_depth;
-            best.ana_interleave = ana_cands[k].ana_interleave;
+        }, ana_ms[k]);
+    }
+    LegPlan best = saved;
+    if (err == hipSuccess) {
+        int cur = 0, fast = 0;
+        for (int k = 0; k < 5; ++k) {
+            if (syn_cands[k].syn_tiles == saved.syn_tiles && syn_cands[k].syn_depth == saved.syn_depth) cur = k;
+            if (syn_ms[k] < syn_ms[fast]) fast = k;
+        }
+        if (syn_ms[fast] < kMargin * syn_ms[cur]) {
+            best.syn_tiles = syn_cands[fast].syn_tiles;
+            best.syn_depth = syn_cands[fast].syn_depth;
+        }
+        cur = 0;
+        fast = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (ana_cands[k].ana_depth == saved.ana_depth && ana_cands[k].ana_interleave == saved.ana_interleave)
+                cur = k;
+            if (ana_ms[k] < ana_ms[fast]) fast = k;
+        }
+        if (ana_ms[fast] < kMargin * ana_ms[cur]) {
+            best.ana_depth = ana_cands[fast].ana_depth;
+            best.ana_interleave = ana_cands[fast].ana_interleave;
         }
     }
     (void)hipEventDestroy(e0);

@@ -77,7 +77,7 @@ __device__ inline int2 xcd_task_group(int ntasks, int ngroups, int interleave) {
 // (2, 4), (2, 2), (4, 2)), analysis table stages per wave (4 or 2) and state-group order.  The
 // defaults are the variants measured fastest for one T255 member.
 struct LegPlan {
-    int syn_tiles = 2, syn_depth = 4, ana_depth = 2, ana_interleave = 1;
+    int syn_tiles = 2, syn_depth = 2, ana_depth = 2, ana_interleave = 1;
 };
 
 // Synthesis input ("coefficient-major", written by the update/prep kernels): for table row

@@ -467,9 +467,9 @@ __device__ __forceinline__ void stage_inputs(double2* buf, const double2* __rest
 // signals is transformed by one wave; only the hand-offs between phases are workgroup barriers.
 // LDS holds four signals (three workgroups fit a CU), and every thread loads the first twiddles
 // of its butterflies once, ahead of their use: the fifth product E waits in registers while A..D are
-// transformed and unpacked, then reuses buffer 0 and is transformed by the whole workgroup, so an
-// analysis row (14 values and 2 zeros, one 128-byte line) is written in two parts from the same
-// workgroup.
+// transformed, then reuses buffer 0 (A's contributions to the rows wait in registers) and is
+// transformed by the whole workgroup; each analysis row (14 values and 2 zeros, one 128-byte
+// line) is then written whole by one thread.
 // ---------------------------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
@@ -525,16 +525,36 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
     const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
     const double we = wt * invN;
     const double2 z2 = make_double2(0.0, 0.0);
-    // -i m X g = (m g X.y, -m g X.x); i m X g = (-m g X.y, m g X.x)
-    // parity 0 (n-m even): Pbar pairs with symmetric, H with antisymmetric sums; parity 1 the reverse
-    for (int m = threadIdx.x; m <= T; m += kGridBlock) {
+    // Analysis rows (per m and parity, 7 complex columns + pad):
+    //   parity 0: -i m g As, i m g Bs, w E_s, -i m g Cs, g Ba, g Aa, g Da, 0
+    //   parity 1: -i m g Aa, i m g Ba, w E_a, -i m g Ca, g Bs, g As, g Ds, 0
+    // (-i m X g = (m g X.y, -m g X.x); s / a: north + / - south; Pbar pairs with symmetric sums
+    // for even n - m, H with antisymmetric ones, and the reverse for odd.)  Buffer 0 (A) is
+    // needed for E, so A's four values of the rows of this thread's first MP orders wait in
+    // registers and those rows are written whole once E is transformed; rows of higher orders
+    // (grids with T + 1 > nlon / 3) are written in two parts.
+    constexpr int MP = (N + 3 * kGridBlock - 1) / (3 * kGridBlock);
+    double2 areg[MP][4];
+#pragma unroll
+    for (int mp = 0; mp < MP; ++mp) {
+        const int m = threadIdx.x + mp * kGridBlock;
+        if (m > T) continue;
+        double2 AN, AS;
+        unpack_pair(buf, m, N, AN, AS);
+        const double mg = (double)m * gg;
+        const double2 As = cadd(AN, AS), Aa = csub(AN, AS);
+        areg[mp][0] = make_double2(mg * As.y, -mg * As.x);
+        areg[mp][1] = make_double2(gg * Aa.x, gg * Aa.y);
+        areg[mp][2] = make_double2(mg * Aa.y, -mg * Aa.x);
+        areg[mp][3] = make_double2(gg * As.x, gg * As.y);
+    }
+    for (int m = threadIdx.x + MP * kGridBlock; m <= T; m += kGridBlock) {
         double2 AN, AS, BN, BS, CN, CS, DN, DS;
         unpack_pair(buf, m, N, AN, AS);
         unpack_pair(buf + N, m, N, BN, BS);
         unpack_pair(buf + 2 * N, m, N, CN, CS);
         unpack_pair(buf + 3 * N, m, N, DN, DS);
         const double mg = (double)m * gg;
-        // symmetric (north + south) and antisymmetric (north - south) parts
         const double2 As = cadd(AN, AS), Aa = csub(AN, AS);
         const double2 Bs = cadd(BN, BS), Ba = csub(BN, BS);
         const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
@@ -557,7 +577,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
         o1[7] = z2;
     }
     __syncthreads();
-    // E: into buffer 0, forward transform, its slot of every row
+    // E: into buffer 0 and transformed by the whole workgroup
 #pragma unroll
     for (int kk = 0; kk < KP; ++kk) {
         const int k = threadIdx.x + kk * kGridBlock;
@@ -565,7 +585,40 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
     }
     __syncthreads();
     fft_block<N, false>(buf, twb);
-    for (int m = threadIdx.x; m <= T; m += kGridBlock) {
+#pragma unroll
+    for (int mp = 0; mp < MP; ++mp) {
+        const int m = threadIdx.x + mp * kGridBlock;
+        if (m > T) continue;
+        double2 BN, BS, CN, CS, DN, DS, EN, ES;
+        unpack_pair(buf + N, m, N, BN, BS);
+        unpack_pair(buf + 2 * N, m, N, CN, CS);
+        unpack_pair(buf + 3 * N, m, N, DN, DS);
+        unpack_pair(buf, m, N, EN, ES);
+        const double mg = (double)m * gg;
+        const double2 Bs = cadd(BN, BS), Ba = csub(BN, BS);
+        const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
+        const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
+        const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
+        double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
+        double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
+        o0[0] = areg[mp][0];
+        o0[1] = make_double2(-mg * Bs.y, mg * Bs.x);
+        o0[2] = make_double2(we * Es.x, we * Es.y);
+        o0[3] = make_double2(mg * Cs.y, -mg * Cs.x);
+        o0[4] = make_double2(gg * Ba.x, gg * Ba.y);
+        o0[5] = areg[mp][1];
+        o0[6] = make_double2(gg * Da.x, gg * Da.y);
+        o0[7] = z2;
+        o1[0] = areg[mp][2];
+        o1[1] = make_double2(-mg * Ba.y, mg * Ba.x);
+        o1[2] = make_double2(we * Ea.x, we * Ea.y);
+        o1[3] = make_double2(mg * Ca.y, -mg * Ca.x);
+        o1[4] = make_double2(gg * Bs.x, gg * Bs.y);
+        o1[5] = areg[mp][3];
+        o1[6] = make_double2(gg * Ds.x, gg * Ds.y);
+        o1[7] = z2;
+    }
+    for (int m = threadIdx.x + MP * kGridBlock; m <= T; m += kGridBlock) {
         double2 EN, ES;
         unpack_pair(buf, m, N, EN, ES);
         const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);

@@ -19,9 +19,9 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import quadrature
 from oracle.sdc import Oracle
 
+from conditioning import oracle_one_ulp
 from test_gpu_parity import _dev, _host, _sdc, _states, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -42,19 +42,9 @@ def _oracle_fp32_tables():
     return o
 
 
-def _grid_one_ulp(seed):
-    """Gauss nodes moved by one ulp each (seeded directions, mirror-symmetric), weights recomputed."""
-    mu, _ = quadrature.gauss_legendre(NLAT)
-    h = NLAT // 2
-    s = np.random.default_rng(seed).choice([-1.0, 1.0], size=h)
-    mun = np.nextafter(mu[:h], mu[:h] + s)
-    mu2 = np.concatenate([mun, -mun[::-1]])
-    return mu2, quadrature.gauss_weights(NLAT, mu2)
-
-
 @pytest.fixture(scope="module")
 def oracles():
-    return _oracle_on(), _oracle_on(_grid_one_ulp(1)), _oracle_fp32_tables()
+    return _oracle_on(), oracle_one_ulp(T, NLAT, NLON), _oracle_fp32_tables()
 
 
 def _per_field(a, b):

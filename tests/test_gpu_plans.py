@@ -15,7 +15,7 @@ from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-DEFAULT = dict(syn_lat_tiles=2, syn_depth=4, ana_depth=2, ana_interleave=1)
+DEFAULT = dict(syn_lat_tiles=2, syn_depth=2, ana_depth=2, ana_interleave=1)
 VARIANTS = [(1, 8, 4, 1), (1, 4, 4, 1), (2, 4, 4, 1), (2, 2, 4, 1), (4, 2, 4, 1), (1, 8, 2, 1),
             (1, 8, 4, 0), (2, 4, 2, 0)]
 

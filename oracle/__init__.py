@@ -16,8 +16,10 @@ Every routine is written from the paper (Freese, Goetschel, Lunet, Ruprecht, Sch
 * swe.py        -- the split right-hand side of the shallow-water equations of Section 3.2:
   f_I = L_g (implicit) and f_E = L_c + N_a + N_r (explicit), and the solver for
   u - alpha f_I(u) = beta (Section 4.2, required routines).
-* sdc.py        -- the diagonal IMEX SDC step (Algorithm 2 with the node update of Section 4.2),
-  the sequential IMEX SDC step (Algorithm 1) and the grid loss used for gradients.
+* sdc.py        -- the diagonal IMEX SDC step (Algorithm 2 with the node update of Section 4.2)
+  and the grid loss used for gradients.
+* imex2.py      -- IMEX-o2, the reference integrator of Section 3.2 (Strang splitting:
+  Crank-Nicolson for L_g, Heun for the rest).
 
 Floating point is FP64 throughout.  Parity status of each function is listed in its module
 header; every function is pinned by a CPU test against a value fixed by the paper or by

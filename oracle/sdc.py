@@ -25,6 +25,7 @@ import numpy as np
 import torch
 
 from . import quadrature
+from .imex2 import imex2_step
 from .sht import CT, DT, Sphere, to_complex, to_real
 from .swe import SWE
 
@@ -85,6 +86,16 @@ class Oracle:
         u = to_complex(torch.as_tensor(np.asarray(state), dtype=DT))
         for _ in range(steps):
             u = self.step_c(u, dt, M, K)
+        return to_real(u).numpy()
+
+    def imex2_c(self, u, dt: float):
+        return imex2_step(u, dt, self.swe.f_explicit, self.swe.f_implicit, self.swe.solve)
+
+    def imex2(self, state, dt: float, steps: int = 1):
+        """IMEX-o2 steps (the paper's reference integrator) on a real state [3, ncoef, 2]."""
+        u = to_complex(torch.as_tensor(np.asarray(state), dtype=DT))
+        for _ in range(steps):
+            u = self.imex2_c(u, dt)
         return to_real(u).numpy()
 
     def f_explicit(self, state):

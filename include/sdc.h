@@ -116,6 +116,18 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K);
  * recent graphs.  The state must stay allocated while a graph for it is cached. */
 int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K);
 
+/* One step of IMEX-o2, the paper's reference integrator (Section 3.2): a Strang splitting with
+ * Crank-Nicolson half steps for f_I = L_g around one Heun (explicit second-order Runge-Kutta)
+ * step for f_E (the paper leaves the order open; the Crank-Nicolson part takes the half steps):
+ *   u* = C(dt/2) u_n,  k1 = f_E(u*),  k2 = f_E(u* + dt k1),  u_{n+1} = C(dt/2)(u* + dt/2 (k1 + k2)),
+ *   C(h) u = (I - h/2 L_g)^{-1} (I + h/2 L_g) u, closed form per coefficient.
+ * In place on state [batch][3][ncoef], all members; dt > 0 and finite.  Two f_E evaluations per
+ * step, in the handle's precision mode.  The first call on a handle allocates three states per
+ * member of workspace; later calls allocate nothing.  Non-finite results are reported by sdc_sync.
+ * imex2_step_graph: the same step as a cached hipGraph (as sdc_step_graph, keyed by state and dt). */
+int imex2_step(sdc_handle h, double* state, double dt);
+int imex2_step_graph(sdc_handle h, double* state, double dt);
+
 /* Adjoint of one step: lam_n = (d u_{n+1} / d u_n)^T lam_np1 for the step taken from state_n
  * with the same dt, M, K (the step is recomputed internally from state_n, keeping the grid fields
  * of every stage; then the sweep runs in reverse with Q^T, the transposed per-degree solve and

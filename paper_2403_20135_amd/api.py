@@ -80,6 +80,18 @@ class SDC:
         check(self.lib.sdc_step_graph(self.h, _ptr(state), float(dt), M or self.M, K or self.K))
         return state
 
+    def imex2_step(self, state, dt: float):
+        """One IMEX-o2 step (the paper's reference integrator) in place."""
+        self._check(state, self.state_shape, "state")
+        check(self.lib.imex2_step(self.h, _ptr(state), float(dt)))
+        return state
+
+    def imex2_step_graph(self, state, dt: float):
+        """One IMEX-o2 step in place as a replayed hipGraph."""
+        self._check(state, self.state_shape, "state")
+        check(self.lib.imex2_step_graph(self.h, _ptr(state), float(dt)))
+        return state
+
     def step_adjoint(self, state_n, lam_np1, lam_n, dt: float, M: Optional[int] = None,
                      K: Optional[int] = None):
         self._check(state_n, self.state_shape, "state_n")

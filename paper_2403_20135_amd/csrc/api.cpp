@@ -166,6 +166,7 @@ struct sdc_ctx {
     double *ua = nullptr, *ub = nullptr, *E = nullptr, *E0 = nullptr;
     // captured steps: (state, dt, M, K) -> executable graph, replayed on st
     struct GraphEntry {
+        int kind;                     // 0: dSDC step, 1: IMEX-o2 step
         const double* state;
         double dt;
         int M, K;
@@ -182,6 +183,8 @@ struct sdc_ctx {
     double* adj_ebar = nullptr;       // tendency adjoints [B][M][3][ncoef]
     double* adj_un = nullptr;         // u_n adjoint [B][3][ncoef]
     double* adj_x = nullptr;          // copy of u_n for the recomputation
+    // IMEX-o2 workspaces (allocated by the first imex2_step call): u*, k1, k2 per member
+    double *i2_ustar = nullptr, *i2_k1 = nullptr, *i2_k2 = nullptr;
     double* cml = nullptr;            // synthesis input, coefficient-major
     double* G = nullptr;              // analysis input (also the scalar analysis input)
     double2* four = nullptr;
@@ -727,23 +730,62 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
     run_update(c, a);
 }
 
-}  // namespace
-
-extern "C" {
-
-int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
-    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
-    enqueue_step(h, state, dt, M, K);
-    HIP_TRY(hipGetLastError());
+int alloc_imex2(sdc_ctx* c) {
+    if (c->i2_ustar) return SDC_OK;
+    const size_t n = (size_t)c->cfg.batch * 3 * c->g.ncoef * 2;
+    int rc;
+    if ((rc = c->alloc(c->i2_ustar, n))) return rc;
+    if ((rc = c->alloc(c->i2_k1, n))) return rc;
+    if ((rc = c->alloc(c->i2_k2, n))) return rc;
     return SDC_OK;
 }
 
-int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K) {
-    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
-    sdc_ctx* c = h;
+// One IMEX-o2 step for all members (workspaces allocated, arguments checked).
+void enqueue_imex2(sdc_ctx* c, double* state, double dt) {
+    const int B = c->cfg.batch;
+    Imex2Args a{};
+    a.n_of = c->n_of;
+    a.m_of = c->m_of;
+    a.rowoff = c->rowoff;
+    a.inv_lap = c->inv_lap;
+    a.cml = c->cml;
+    a.flag = c->flag;
+    a.dt = dt;
+    a.phibar = c->phibar;
+    a.inv_a2 = c->inv_a2;
+    a.batch = B;
+    a.ncoef = c->g.ncoef;
+    a.T = c->g.T;
+    auto phase = [&](int ph, const double* in, double* out) {
+        a.phase = ph;
+        a.in = in;
+        a.out = out;
+        a.k1 = c->i2_k1;
+        a.k2 = c->i2_k2;
+        const long t = c->begin(SDC_KERNEL_UPDATE);
+        launch_imex2(a, c->st);
+        c->end(SDC_KERNEL_UPDATE, t);
+    };
+    phase(kImex2First, state, c->i2_ustar);          // u* = C(dt/2) u_n
+    run_explicit_cml(c, B, c->i2_k1);               // k1 = f_E(u*)
+    phase(kImex2Predict, c->i2_ustar, nullptr);      // synthesis input u* + dt k1
+    run_explicit_cml(c, B, c->i2_k2);               // k2 = f_E(u* + dt k1)
+    phase(kImex2Last, c->i2_ustar, state);           // u_{n+1}
+}
+
+int check_imex2_args(sdc_handle h, const double* state, double dt) {
+    if (int rc = check_handle(h)) return rc;
+    if (!state) return fail(SDC_EINVAL, "state is NULL");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(SDC_EINVAL, "dt must be positive and finite");
+    return alloc_imex2(h);
+}
+
+// Replays the cached graph of (kind, state, dt, M, K), capturing it first if needed.
+template <class Enqueue>
+int graph_launch(sdc_ctx* c, int kind, double* state, double dt, int M, int K, Enqueue&& enqueue) {
     sdc_ctx::GraphEntry* hit = nullptr;
     for (auto& ge : c->graphs)
-        if (ge.state == state && ge.dt == dt && ge.M == M && ge.K == K) hit = &ge;
+        if (ge.kind == kind && ge.state == state && ge.dt == dt && ge.M == M && ge.K == K) hit = &ge;
     if (!hit) {
         if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
         hipStream_t user = c->st;
@@ -753,7 +795,7 @@ int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K) {
         hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
         hipGraph_t graph = nullptr;
         if (e == hipSuccess) {
-            enqueue_step(c, state, dt, M, K);
+            enqueue();
             e = hipStreamEndCapture(c->cap, &graph);
         }
         c->st = user;
@@ -770,11 +812,39 @@ int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K) {
             (void)hipGraphDestroy(c->graphs.front().graph);
             c->graphs.erase(c->graphs.begin());
         }
-        c->graphs.push_back({state, dt, M, K, graph, exec});
+        c->graphs.push_back({kind, state, dt, M, K, graph, exec});
         hit = &c->graphs.back();
     }
     HIP_TRY(hipGraphLaunch(hit->exec, c->st));
     return SDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
+    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    enqueue_step(h, state, dt, M, K);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K) {
+    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    return graph_launch(h, 0, state, dt, M, K, [&] { enqueue_step(h, state, dt, M, K); });
+}
+
+int imex2_step(sdc_handle h, double* state, double dt) {
+    if (int rc = check_imex2_args(h, state, dt)) return rc;
+    enqueue_imex2(h, state, dt);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int imex2_step_graph(sdc_handle h, double* state, double dt) {
+    if (int rc = check_imex2_args(h, state, dt)) return rc;
+    return graph_launch(h, 1, state, dt, 0, 0, [&] { enqueue_imex2(h, state, dt); });
 }
 
 int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1, double* lam_n,

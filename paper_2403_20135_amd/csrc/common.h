@@ -189,6 +189,26 @@ struct UpdateArgs {
     int M, sweep, last_only, batch, ncoef, T;
 };
 void launch_update(const UpdateArgs& a, hipStream_t st);
+// imex2.hip: the coefficient-wise phases of an IMEX-o2 step for `batch` states [b][3][ncoef]
+//   kImex2First:   out = C(dt/2) in (u*), and its synthesis layout in cml
+//   kImex2Predict: synthesis layout of in + dt k1 (in = u*)
+//   kImex2Last:    out = C(dt/2)(in + dt/2 (k1 + k2)), flag set on a non-finite value
+constexpr int kImex2First = 0, kImex2Predict = 1, kImex2Last = 2;
+struct Imex2Args {
+    const double* in;
+    const double* k1;
+    const double* k2;
+    double* out;
+    double* cml;
+    const int* n_of;
+    const int* m_of;
+    const int* rowoff;
+    const double* inv_lap;
+    int* flag;
+    double dt, phibar, inv_a2;
+    int phase, batch, ncoef, T;
+};
+void launch_imex2(const Imex2Args& a, hipStream_t st);
 // Synthesis layout of `batch` states [b][3][ncoef] (the first f_E of a step, eval_explicit).
 void launch_prep_cml(const double* state, int nstates, double* cml, const int* n_of,
                      const int* m_of, const int* rowoff, const double* inv_lap, int ncoef, int T,

@@ -1,0 +1,95 @@
+"""GPU parity of the IMEX-o2 reference integrator (Section 3.2) against the oracle, through the
+C ABI.  Bars as for the dSDC step: 1e-11 relative L2 per field for the FP64 path at T <= 127, the
+oracle's one-ulp spread at T255 (three times, at least 1e-11), 2 (T+1) u_32 per f_E evaluation on
+the state change for the FP32 mode."""
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2403_20135_amd import _lib
+
+from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, _torch, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("T,nlat,nlon,dt,steps,batch", [
+    (31, 48, 96, 600.0, 10, 1),
+    (63, 96, 192, 300.0, 4, 2),
+    (21, 34, 64, 900.0, 5, 3),          # ragged latitude tile
+])
+def test_imex2_matches_oracle(T, nlat, nlon, dt, steps, batch):
+    sdc = _sdc(T, nlat, nlon, 2, 2, batch)
+    o = _oracle(T, nlat, nlon)
+    u0 = _states(T, batch, 401)
+    x = _dev(u0)
+    for _ in range(steps):
+        sdc.imex2_step(x, dt)
+    sdc.sync()
+    ref = np.stack([o.imex2(u0[b], dt, steps=steps) for b in range(batch)])
+    err = rel_l2(_host(x), ref, T)
+    print(f"[gpu] IMEX-o2 T{T} x{batch}, {steps} steps: rel L2 {err:.3e}", flush=True)
+    assert err <= 1e-11
+
+
+def test_imex2_graph_replays_match_eager():
+    torch = _torch()
+    T, nlat, nlon, dt = 31, 48, 96, 600.0
+    sdc = _sdc(T, nlat, nlon, 2, 2, 2)
+    u0 = _states(T, 2, 402)
+    xe, xg = _dev(u0), _dev(u0)
+    for k in range(4):
+        sdc.imex2_step(xe, dt)
+        sdc.imex2_step_graph(xg, dt)
+        sdc.sync()
+        torch.cuda.synchronize()
+        assert np.array_equal(_host(xe), _host(xg)), k
+        other = _dev(u0)                 # eager work between replays
+        sdc.step(other, dt)
+        sdc.sync()
+
+
+def test_imex2_t255_full_size():
+    from conditioning import oracle_one_ulp
+    wl = W.WORKLOADS["t255_m4k4"]
+    mb = wl.members[0]
+    sdc = _sdc(mb.T, mb.nlat, mb.nlon, wl.M, wl.K)
+    o = _oracle(mb.T, mb.nlat, mb.nlon)
+    u0 = W.initial_state(wl)
+    x = _dev(u0[None])
+    for _ in range(2):
+        sdc.imex2_step_graph(x, mb.dt)
+    sdc.sync()
+    ref = o.imex2(u0, mb.dt, steps=2)
+    alt = oracle_one_ulp(mb.T, mb.nlat, mb.nlon).imex2(u0, mb.dt, steps=2)
+    got = _host(x)[0]
+    for k, name in enumerate(("Phi'", "zeta", "delta")):
+        err = rel_l2(got[None, k], ref[None, k], mb.T)
+        spread = rel_l2(alt[None, k], ref[None, k], mb.T)
+        print(f"[gpu] IMEX-o2 T255 2 steps {name}: rel L2 {err:.3e} (oracle 1-ulp spread {spread:.2e})",
+              flush=True)
+        assert err <= max(1e-11, 3 * spread)
+
+
+def test_imex2_fp32_mode():
+    T, nlat, nlon, dt, steps = 31, 48, 96, 600.0, 10
+    sdc = _sdc(T, nlat, nlon, 2, 2, 1, precision="fp32")
+    o = _oracle(T, nlat, nlon)
+    u0 = _states(T, 1, 403)
+    x = _dev(u0)
+    for _ in range(steps):
+        sdc.imex2_step(x, dt)
+    sdc.sync()
+    ref = o.imex2(u0[0], dt, steps=steps)[None]
+    err = rel_l2(_host(x) - u0, ref - u0, T)
+    print(f"[gpu] IMEX-o2 FP32 {steps} steps: rel L2 of the state change {err:.3e}", flush=True)
+    assert err <= 2 * (T + 1) * 2.0 ** -24 * 2 * steps
+
+
+def test_imex2_argument_errors():
+    sdc = _sdc(21, 34, 64, 2, 2, 1)
+    x = _dev(_states(21, 1, 404))
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(_lib.SDCError) as ei:
+            sdc.imex2_step(x, bad)
+        assert ei.value.code == _lib.SDC_EINVAL

@@ -2,7 +2,8 @@
 """Benchmark: dSDC steps/s of the T255, M=4, K=4 shallow-water workload on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload t255_m4k4] [--no-cpu-baseline]
-                    [--no-fp32] [--no-adjoint] [--plan TILES,DEPTH,ANA_DEPTH,INTERLEAVE]
+                    [--no-fp32] [--no-adjoint] [--no-work-precision]
+                    [--plan TILES,DEPTH,ANA_DEPTH,INTERLEAVE]
     python bench.py --summarize-pmc FETCH.csv WRITE.csv COPY_MIB OUT.json FETCH.log WRITE.log
                                                                             (counter summary)
 
@@ -18,7 +19,9 @@ on MFMA), whose error is compared with the plain path's at equal step size again
 path at dt/8 ("equal error": E_fp32 <= 1.1 E_fp64, E = max over output times of the relative
 L2 error of vorticity).  Two further workloads are reported beside the headline: the 32-member
 ensemble of mixed truncations (one graph launch per step) and T511 (FP64 and FP32, forward and
-forward+adjoint).  The CPU baseline is the FP64 oracle timed on the host cores on a bounded
+forward+adjoint), and a work-precision comparison of dSDC with the paper's reference integrator
+IMEX-o2 over one simulated day (errors against IMEX-o2 at dt = 1.5 s, wall time per run, dSDC's
+speedup at equal error).  The CPU baseline is the FP64 oracle timed on the host cores on a bounded
 sample.
 
 Rooflines: the Legendre kernels are priced at min(MFMA peak, AI x HBM peak) with AI = useful
@@ -260,6 +263,73 @@ def measure_mixed(steps=20, warmup=3):
             "launch": "one hipGraph per step (members as parallel branches)"}
 
 
+def work_precision(wl, t_end=86400.0, out_every=21600.0):
+    """Work against precision over one simulated day (the comparison of Section 5: dSDC against
+    the IMEX-o2 reference integrator, both on this GPU): absolute L-infinity-in-time, L2-in-space
+    error of vorticity at the output times against IMEX-o2 at dt = 1.5 s, and the wall time of each
+    run (graph replays, output copies on the device).  The absolute L2 norm is the area-weighted
+    RMS over the sphere, sqrt(1/2 sum_m s_m |c|^2) by Parseval."""
+    import numpy as np
+    import torch
+    from paper_2403_20135_amd.api import SDC
+    mb = wl.members[0]
+    _, m = W.degree_order_arrays(mb.T)
+    sm = torch.tensor(np.where(m == 0, 1.0, 2.0)[:, None], dtype=torch.float64, device="cuda")
+    sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, 1, "fp64", W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
+    plan = sdc.autotune(10)
+    x0 = torch.tensor(W.initial_state(wl)[None], dtype=torch.float64, device="cuda")
+    nout = int(round(t_end / out_every))
+
+    def run(method, dt):
+        n = int(round(t_end / dt))
+        per = int(round(out_every / dt))
+        assert n * dt == t_end and per * dt == out_every
+        x = x0.clone()
+        outs = torch.empty((nout,) + tuple(x[0, 1].shape), dtype=torch.float64, device="cuda")
+        stepf = (lambda: sdc.step_graph(x, dt)) if method == "dSDC" else (lambda: sdc.imex2_step_graph(x, dt))
+        stepf()                                        # capture (untimed): restart from x0
+        x.copy_(x0)
+        sdc.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, n + 1):
+            stepf()
+            if k % per == 0:
+                outs[k // per - 1].copy_(x[0, 1])
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        sdc.sync()
+        return n, secs, outs
+
+    _, _, ref = run("IMEX-o2", 1.5)
+    rows = []
+    for method, dts in (("dSDC", (450.0, 360.0, 240.0, 180.0, 120.0, 60.0)),
+                        ("IMEX-o2", (60.0, 30.0, 15.0, 7.5, 3.75))):
+        for dt in dts:
+            n, secs, outs = run(method, dt)
+            d = outs - ref
+            err = float(torch.sqrt(0.5 * (sm * d * d).sum(dim=(-2, -1))).max())
+            rows.append({"method": method, "dt": dt, "steps": n, "seconds": round(secs, 5),
+                         "error": err})
+    sdc.close()
+    # speedup of dSDC at equal error: IMEX-o2 time interpolated (log-log) at each dSDC error
+    imex = sorted([(r["error"], r["seconds"]) for r in rows if r["method"] == "IMEX-o2"])
+    speed = []
+    for r in rows:
+        if r["method"] != "dSDC":
+            continue
+        for (e0, t0), (e1, t1) in zip(imex, imex[1:]):
+            if e0 <= r["error"] <= e1 and e0 > 0:
+                f = math.log(r["error"] / e0) / math.log(e1 / e0)
+                t_imex = math.exp(math.log(t0) + f * (math.log(t1) - math.log(t0)))
+                speed.append({"dt_dSDC": r["dt"], "error": r["error"],
+                              "speedup_vs_IMEX_o2": round(t_imex / r["seconds"], 3)})
+    return {"workload": wl.name, "t_end_s": t_end, "output_every_s": out_every, "M": wl.M, "K": wl.K,
+            "precision": "fp64", "reference": "IMEX-o2 at dt = 1.5 s",
+            "error": "max over output times of the area-weighted RMS of the vorticity difference [1/s]",
+            "legendre_plan": plan, "rows": rows, "speedup_at_equal_error": speed}
+
+
 def traffic_for(kernel, plan):
     """Measured HBM bytes per launch of `kernel` from the committed counter summary, or None when
     the summary is missing, was taken from other kernel sources or (for the Legendre classes)
@@ -356,6 +426,8 @@ def main():
     ap.add_argument("--workload", default="t255_m4k4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="measure the plain FP64 path only")
+    ap.add_argument("--no-work-precision", action="store_true",
+                    help="skip the dSDC / IMEX-o2 work-precision comparison")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the forward+adjoint region (counter runs of the forward kernels)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -427,6 +499,8 @@ def main():
             "kernels": r32["kernels"],
             "legendre_plan": r32["plan"],
         }
+    if not args.no_fp32 and not args.no_work_precision and args.workload == "t255_m4k4":
+        result["work_precision"] = work_precision(wl)
     if not args.no_fp32 and args.workload == "t255_m4k4":
         result["mixed32_m4k3"] = measure_mixed()
         big = W.WORKLOADS["t511_m4k4"]

@@ -78,7 +78,10 @@ typedef struct {
     int M;                    /* largest number of collocation nodes used by sdc_step, 1..8 */
     int K;                    /* largest number of sweeps used by sdc_step, 1..16 */
     int nodes;                /* collocation nodes: 0 = Radau-right (tau_M = 1), the only choice */
-    int qdelta;               /* diagonal coefficients: 0 = MIN-SR-FLEX, the only choice */
+    int qdelta;               /* diagonal coefficients of the implicit sweeps (Section 4.2):
+                                 0 = MIN-SR-FLEX, tau_m / min(s, M) in sweep s (the paper's choice);
+                                 1 = MIN-SR-NS, tau_m / M in every sweep (a variant of the family:
+                                 Q - Q_Delta is nilpotent) */
     int precision;            /* an sdc_precision value */
     int batch;                /* ensemble members sharing this truncation, >= 1 */
 } sdc_config;

@@ -88,3 +88,13 @@ def min_sr_flex(tau: np.ndarray, sweep: int) -> np.ndarray:
     """Diagonal of Q_Delta in sweep `sweep` (1-based): tau_m / min(sweep, M)."""
     M = len(tau)
     return tau / float(min(sweep, M))
+
+
+def min_sr_ns(tau: np.ndarray, sweep: int) -> np.ndarray:
+    """MIN-SR-NS, the sweep-independent diagonal of the same family (a variant beside the paper's
+    MIN-SR-FLEX; the sweep argument is ignored): tau_m / M, for which Q - Q_Delta is nilpotent
+    (the non-stiff limit of the iteration matrix vanishes after M sweeps)."""
+    return tau / float(len(tau))
+
+
+QDELTA = {"flex": min_sr_flex, "ns": min_sr_ns}

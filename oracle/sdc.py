@@ -31,8 +31,10 @@ from .swe import SWE
 
 
 def dsdc_step(u_n, dt: float, tau: np.ndarray, Q: np.ndarray, K: int,
-              f_explicit: Callable, f_implicit: Callable, solve: Callable):
-    """One dSDC step u_n -> u_{n+1} for any state tensor u_n (node axis added in front)."""
+              f_explicit: Callable, f_implicit: Callable, solve: Callable,
+              qdelta: Callable = quadrature.min_sr_flex):
+    """One dSDC step u_n -> u_{n+1} for any state tensor u_n (node axis added in front);
+    qdelta(tau, s) is the diagonal of Q_Delta in sweep s (MIN-SR-FLEX unless given)."""
     M = len(tau)
     E0 = f_explicit(u_n)
     I0 = f_implicit(u_n)
@@ -52,12 +54,12 @@ def dsdc_step(u_n, dt: float, tau: np.ndarray, Q: np.ndarray, K: int,
 
     all_m = list(range(M))
     for s in range(1, K):
-        alpha = dt * quadrature.min_sr_flex(tau, s)
+        alpha = dt * qdelta(tau, s)
         beta = rhs(all_m, alpha)
         U = torch.stack([solve(float(alpha[m]), beta[m]) for m in all_m])
         E = torch.stack([f_explicit(U[m]) for m in all_m])
         I = torch.stack([f_implicit(U[m]) for m in all_m])
-    alpha_last = dt * quadrature.min_sr_flex(tau, K)[M - 1]
+    alpha_last = dt * qdelta(tau, K)[M - 1]
     beta = rhs([M - 1], np.array([alpha_last]))
     return solve(float(alpha_last), beta[0])
 
@@ -66,8 +68,9 @@ class Oracle:
     """Sphere + shallow-water right-hand side + collocation coefficients for one truncation."""
 
     def __init__(self, T: int, nlat: int, nlon: int, radius: float, gravity: float,
-                 omega: float, mean_depth: float, grid=None):
+                 omega: float, mean_depth: float, grid=None, qdelta: str = "flex"):
         self.sphere = Sphere(T, nlat, nlon, radius, grid)
+        self.qdelta = quadrature.QDELTA[qdelta]
         self.swe = SWE(self.sphere, gravity, omega, mean_depth)
         self.gravity = gravity
         self.mean_depth = mean_depth
@@ -79,7 +82,8 @@ class Oracle:
     # complex-state API
     def step_c(self, u, dt: float, M: int, K: int):
         tau, Q = self.coefficients(M)
-        return dsdc_step(u, dt, tau, Q, K, self.swe.f_explicit, self.swe.f_implicit, self.swe.solve)
+        return dsdc_step(u, dt, tau, Q, K, self.swe.f_explicit, self.swe.f_implicit, self.swe.solve,
+                         self.qdelta)
 
     # real-state API: [3, ncoef, 2] float64 arrays / tensors (the device layout)
     def step(self, state, dt: float, M: int, K: int, steps: int = 1):

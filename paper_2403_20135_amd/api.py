@@ -24,14 +24,16 @@ class SDC:
 
     def __init__(self, T: int, nlat: int, nlon: int, M: int, K: int, batch: int = 1,
                  precision: str = "fp64", radius: float = 6.371e6, gravity: float = 9.81,
-                 omega: float = 7.292e-5, mean_depth: float = 1.0e4, stream: Optional[int] = None):
+                 omega: float = 7.292e-5, mean_depth: float = 1.0e4, stream: Optional[int] = None,
+                 qdelta: str = "flex"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the dSDC library needs a GPU (no CPU fallback)")
         lib = _lib.load()
         self._torch = torch
         self.cfg = _lib.SdcConfig(T=T, nlat=nlat, nlon=nlon, radius=radius, gravity=gravity,
-                                  omega=omega, mean_depth=mean_depth, M=M, K=K, nodes=0, qdelta=0,
+                                  omega=omega, mean_depth=mean_depth, M=M, K=K, nodes=0,
+                                  qdelta=_lib.QDELTAS[qdelta],
                                   precision=_lib.PRECISIONS[precision], batch=batch)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream

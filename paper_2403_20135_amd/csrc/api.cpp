@@ -277,7 +277,8 @@ int validate_config(const sdc_config* c) {
     if (c->M < 1 || c->M > kMaxNodes) return fail(SDC_EINVAL, "M=%d out of range 1..%d", c->M, kMaxNodes);
     if (c->K < 1 || c->K > kMaxSweeps) return fail(SDC_EINVAL, "K=%d out of range 1..%d", c->K, kMaxSweeps);
     if (c->nodes != 0) return fail(SDC_EINVAL, "nodes=%d: only Radau-right (0) is defined", c->nodes);
-    if (c->qdelta != 0) return fail(SDC_EINVAL, "qdelta=%d: only MIN-SR-FLEX (0) is defined", c->qdelta);
+    if (c->qdelta != 0 && c->qdelta != 1)
+        return fail(SDC_EINVAL, "qdelta=%d: MIN-SR-FLEX (0) or MIN-SR-NS (1)", c->qdelta);
     if (c->precision < SDC_FP64 || c->precision > SDC_BF16X3_MFMA)
         return fail(SDC_EINVAL, "precision=%d unknown", c->precision);
     if (c->batch < 1 || c->batch > 4096) return fail(SDC_EINVAL, "batch=%d out of range 1..4096", c->batch);
@@ -673,6 +674,10 @@ int check_step_args(sdc_handle h, const double* state, double dt, int M, int K) 
     return SDC_OK;
 }
 
+// The update kernels form the diagonal coefficient of sweep s as tau_m / min(s, M)
+// (MIN-SR-FLEX); MIN-SR-NS uses tau_m / M in every sweep, i.e. the kernels' s = M.
+int qd_sweep(const sdc_ctx* c, int s, int M) { return c->cfg.qdelta == 1 ? M : s; }
+
 // Algorithm 2 for all members of the handle, enqueued on c->st (arguments already checked).
 void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
     const int B = c->cfg.batch;
@@ -707,7 +712,7 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
         a.uout = bufs[cur];
         a.out_node = fs;
         a.out_member = (long long)M * fs;
-        a.sweep = s;
+        a.sweep = qd_sweep(c, s, M);
         a.last_only = 0;
         a.cml = c->cml;
         run_update(c, a);
@@ -725,7 +730,7 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
     a.out_node = 0;
     a.out_member = fs;
     a.cml = nullptr;
-    a.sweep = K;
+    a.sweep = qd_sweep(c, K, M);
     a.last_only = 1;
     run_update(c, a);
 }
@@ -894,7 +899,7 @@ int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1,
         a.out_node = fs;
         a.out_member = (long long)M * fs;
         a.cml = c->cml;
-        a.sweep = s;
+        a.sweep = qd_sweep(c, s, M);
         a.last_only = 0;
         launch_update(a, c->st);
         run_explicit_cml(c, B * M, c->E, save_at(s));
@@ -924,7 +929,7 @@ int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1,
     b.ubar_member = fs;
     b.ubar_prev = c->adj_ubar;
     b.ebar_prev = c->adj_ebar;
-    b.sweep = K;
+    b.sweep = qd_sweep(c, K, M);
     b.last = 1;
     b.first_stage = K == 1;
     b.init_un = 1;
@@ -934,7 +939,7 @@ int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1,
         b.ubar = c->adj_ubar;
         b.ubar_node = fs;
         b.ubar_member = (long long)M * fs;
-        b.sweep = s;
+        b.sweep = qd_sweep(c, s, M);
         b.last = 0;
         b.first_stage = s == 1;
         b.init_un = 0;

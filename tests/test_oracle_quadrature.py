@@ -104,3 +104,15 @@ def test_min_sr_flex_values():
     np.testing.assert_allclose(q.min_sr_flex(tau, 3), tau / 3)
     np.testing.assert_allclose(q.min_sr_flex(tau, 9), tau / 4)   # beyond M: reuse s = M
     assert math.isclose(q.min_sr_flex(tau, 2)[-1], 0.5)
+
+
+@pytest.mark.parametrize("M", [2, 3, 4, 5, 6])
+def test_min_sr_ns_makes_q_minus_qdelta_nilpotent(M):
+    """MIN-SR-NS: (Q - diag(tau / M))^M = 0 (the non-stiff limit of the sweep iteration matrix
+    vanishes after M sweeps), and no smaller power does for M >= 2."""
+    tau = q.radau_right_nodes(M)
+    Q = q.collocation_matrix(tau)
+    A = Q - np.diag(q.min_sr_ns(tau, 1))
+    assert np.abs(np.linalg.matrix_power(A, M)).max() < 1e-13
+    assert np.abs(np.linalg.matrix_power(A, M - 1)).max() > 1e-6
+    np.testing.assert_array_equal(q.min_sr_ns(tau, 1), q.min_sr_ns(tau, 7))

@@ -48,10 +48,12 @@ def test_single_sweep_is_imex_euler(M):
         assert torch.max(torch.abs(r[f])).item() <= 1e-13 * scale
 
 
+@pytest.mark.parametrize("qd", ["flex", "ns"])
 @pytest.mark.parametrize("M,K", [(2, 2), (3, 3), (4, 4), (3, 5)])
-def test_linear_mode_against_stage_matrices(M, K):
+def test_linear_mode_against_stage_matrices(M, K, qd):
     """With f_E = 0 one (n,m) mode evolves by the product of the sweep matrices built from
     Q, QDelta and the 3x3 gravity-wave operator (Kronecker form of the node update)."""
+    qfun = q.QDELTA[qd]
     T = 7
     o = _oracle(T, 12, 24)
     n, m = 5, 2
@@ -64,17 +66,17 @@ def test_linear_mode_against_stage_matrices(M, K):
     tau = q.radau_right_nodes(M)
     Q = q.collocation_matrix(tau)
     out = dsdc_step(torch.tensor(st), dt, tau, Q, K,
-                    lambda u: torch.zeros_like(u), o.swe.f_implicit, o.swe.solve).numpy()
+                    lambda u: torch.zeros_like(u), o.swe.f_implicit, o.swe.solve, qfun).numpy()
     # brute force with Kronecker products
     I3 = np.eye(3)
     X = np.kron(np.ones(M), u_mode)
     one_un = np.kron(np.ones(M), u_mode)
     for s in range(1, K):
-        a = dt * q.min_sr_flex(tau, s)
+        a = dt * qfun(tau, s)
         D = np.eye(3 * M) - np.kron(np.diag(a), L)
         R = one_un + (dt * np.kron(Q, L) - np.kron(np.diag(a), L)) @ X
         X = np.linalg.solve(D, R)
-    aM = dt * q.min_sr_flex(tau, K)[-1]
+    aM = dt * qfun(tau, K)[-1]
     rhs = u_mode + dt * np.kron(Q[-1], L) @ X - aM * L @ X[3 * (M - 1):]
     ref = np.linalg.solve(I3 - aM * L, rhs)
     got = out[:, W.coef_index(T, m, n)]

@@ -13,9 +13,13 @@ MIN-SR-FLEX: q^D_{m,m} = tau_m / s in sweep s = 1..K (readings: the sweep index 
 coefficient is the 1-based sweep count; the initial guess is the state at the start of the
 step; f_I of a new iterate is evaluated, not recovered from the solve).
 
+`imex_sdc_step` is the sequential IMEX SDC of Algorithm 1 (the method dSDC parallelises).
+
 Pins: tests/test_oracle_sdc.py (steady balanced flow, IMEX Euler special case, brute-force
 linear stage matrices, order of accuracy, collocation limit against the Pade approximant,
-operation count 1 + (K-1) M of f_E per step, performance-model speedup 3.25 of Section 4.7).
+operation count 1 + (K-1) M of f_E per step, performance-model speedup 3.25 of Section 4.7;
+for Algorithm 1: IMEX Euler at M = K = 1, block lower-triangular stage matrices, collocation
+limit, order K).
 """
 from __future__ import annotations
 
@@ -64,6 +68,35 @@ def dsdc_step(u_n, dt: float, tau: np.ndarray, Q: np.ndarray, K: int,
     return solve(float(alpha_last), beta[0])
 
 
+def imex_sdc_step(u_n, dt: float, tau: np.ndarray, Q: np.ndarray, K: int,
+                  f_explicit: Callable, f_implicit: Callable, solve: Callable):
+    """One sequential IMEX SDC step (Algorithm 1 with the node update of Section 4.1): K sweeps,
+    each updating the nodes one after another; node m of sweep k+1 uses the new values of nodes
+    j < m through forward-Euler differences of f_E (weights dtau_{j+1}) and backward-Euler
+    differences of f_I (weights dtau_j, j <= m; the j = m term is the implicit solve), with
+    dtau_1 = tau_1 and dtau_j = tau_j - tau_{j-1}.  The initial guess is u_n at every node;
+    f_E of the final iterate is not evaluated."""
+    M = len(tau)
+    dtau = np.diff(np.concatenate([[0.0], tau]))
+    E0, I0 = f_explicit(u_n), f_implicit(u_n)
+    U, E, I = [u_n] * M, [E0] * M, [I0] * M
+    for k in range(K):
+        Un, En, In = [], [], []
+        for m in range(M):
+            beta = u_n + dt * sum(Q[m, j] * (I[j] + E[j]) for j in range(M))
+            for j in range(m):
+                beta = beta + dt * dtau[j + 1] * (En[j] - E[j]) + dt * dtau[j] * (In[j] - I[j])
+            beta = beta - dt * dtau[m] * I[m]
+            um = solve(float(dt * dtau[m]), beta)
+            Un.append(um)
+            if k == K - 1 and m == M - 1:
+                break
+            En.append(f_explicit(um))
+            In.append(f_implicit(um))
+        U, E, I = Un, En, In
+    return U[M - 1]
+
+
 class Oracle:
     """Sphere + shallow-water right-hand side + collocation coefficients for one truncation."""
 
@@ -84,6 +117,17 @@ class Oracle:
         tau, Q = self.coefficients(M)
         return dsdc_step(u, dt, tau, Q, K, self.swe.f_explicit, self.swe.f_implicit, self.swe.solve,
                          self.qdelta)
+
+    def seq_step_c(self, u, dt: float, M: int, K: int):
+        tau, Q = self.coefficients(M)
+        return imex_sdc_step(u, dt, tau, Q, K, self.swe.f_explicit, self.swe.f_implicit, self.swe.solve)
+
+    def seq_step(self, state, dt: float, M: int, K: int, steps: int = 1):
+        """Sequential IMEX SDC steps (Algorithm 1) on a real state [3, ncoef, 2]."""
+        u = to_complex(torch.as_tensor(np.asarray(state), dtype=DT))
+        for _ in range(steps):
+            u = self.seq_step_c(u, dt, M, K)
+        return to_real(u).numpy()
 
     # real-state API: [3, ncoef, 2] float64 arrays / tensors (the device layout)
     def step(self, state, dt: float, M: int, K: int, steps: int = 1):

@@ -162,3 +162,109 @@ def test_operation_counts_reproduce_performance_model():
         c_seq = 1.0 + node_updates * (1.0 + r)
         c_par = 1.0 + sweeps * (1.0 + r)
         assert round(c_seq / c_par, digits) == S_printed
+
+
+# ---------------------------------------------------------------- sequential IMEX SDC (Algorithm 1)
+from oracle.sdc import imex_sdc_step  # noqa: E402
+
+
+def _seq_matrices(tau):
+    """Lower-triangular sweep matrices of Algorithm 1: implicit (backward Euler) Q_I[m][j] =
+    dtau_j for j <= m, explicit (forward Euler) Q_E[m][j] = dtau_{j+1} for j < m (0-based)."""
+    M = len(tau)
+    dtau = np.diff(np.concatenate([[0.0], tau]))
+    QI = np.zeros((M, M))
+    QE = np.zeros((M, M))
+    for m in range(M):
+        for j in range(m + 1):
+            QI[m, j] = dtau[j]
+        for j in range(m):
+            QE[m, j] = dtau[j + 1]
+    return QI, QE
+
+
+def test_seq_single_node_single_sweep_is_imex_euler():
+    o = _oracle()
+    st = W.initial_state(W.WORKLOADS["t31_m3k2"])
+    dt = 600.0
+    u0 = to_complex(torch.tensor(st))
+    tau, Q = o.coefficients(1)
+    u1 = imex_sdc_step(u0, dt, tau, Q, 1, o.swe.f_explicit, o.swe.f_implicit, o.swe.solve)
+    fi1, fe0 = dt * o.swe.f_implicit(u1), dt * o.swe.f_explicit(u0)
+    r = u1 - fi1 - u0 - fe0
+    for f in range(3):
+        scale = max(torch.max(torch.abs(x[f])).item() for x in (u0, u1, fi1, fe0))
+        assert torch.max(torch.abs(r[f])).item() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("M,K", [(2, 2), (3, 3), (4, 2), (3, 6)])
+def test_seq_scalar_against_preconditioned_iteration(M, K):
+    """u' = lI u + lE u: K sweeps of Algorithm 1 equal K steps of the matrix iteration
+    (I - dt lI Q_I - dt lE Q_E) X+ = u_n + dt (lI (Q - Q_I) + lE (Q - Q_E)) X from X = u_n."""
+    lI, lE, dt = -2.0 + 0.5j, 0.3j, 0.7
+    tau = q.radau_right_nodes(M)
+    Q = q.collocation_matrix(tau)
+    QI, QE = _seq_matrices(tau)
+    u0 = 1.0 + 0.25j
+    out = imex_sdc_step(u0, dt, tau, Q, K, lambda u: lE * u, lambda u: lI * u,
+                        lambda a, b: b / (1.0 - a * lI))
+    X = np.full(M, u0, dtype=complex)
+    A = np.eye(M) - dt * lI * QI - dt * lE * QE
+    B = dt * (lI * (Q - QI) + lE * (Q - QE))
+    for _ in range(K):
+        X = np.linalg.solve(A, u0 + B @ X)
+    assert abs(out - X[-1]) <= 1e-14 * abs(X[-1])
+
+
+@pytest.mark.parametrize("M", [2, 3, 4])
+def test_seq_collocation_limit_is_radau_iia(M):
+    lI, lE, dt = -1.0, 0.6j, 1.0
+    tau = q.radau_right_nodes(M)
+    Q = q.collocation_matrix(tau)
+    out = imex_sdc_step(1.0 + 0.0j, dt, tau, Q, 40, lambda u: lE * u, lambda u: lI * u,
+                        lambda a, b: b / (1.0 - a * lI))
+    assert abs(out - _pade(M - 1, M, (lI + lE) * dt)) < 1e-12
+
+
+def test_seq_linear_mode_against_stage_matrices():
+    """f_E = 0, one (n, m) mode of the gravity-wave operator: Kronecker form with Q_I."""
+    T, M, K = 7, 3, 3
+    o = _oracle(T, 12, 24)
+    n, m = 5, 2
+    c = n * (n + 1) / W.RADIUS ** 2
+    L = np.array([[0.0, 0.0, -W.PHI_BAR], [0.0, 0.0, 0.0], [c, 0.0, 0.0]])
+    u_mode = np.array([3.0 + 1.0j, 2e-6 - 1e-6j, 1e-6 + 4e-7j])
+    st = np.zeros((3, W.ncoef(T)), dtype=complex)
+    st[:, W.coef_index(T, m, n)] = u_mode
+    dt = 700.0
+    tau = q.radau_right_nodes(M)
+    Q = q.collocation_matrix(tau)
+    QI, _ = _seq_matrices(tau)
+    out = imex_sdc_step(torch.tensor(st), dt, tau, Q, K, lambda u: torch.zeros_like(u),
+                        o.swe.f_implicit, o.swe.solve).numpy()
+    X = np.kron(np.ones(M), u_mode)
+    A = np.eye(3 * M) - dt * np.kron(QI, L)
+    B = dt * np.kron(Q - QI, L)
+    for _ in range(K):
+        X = np.linalg.solve(A, np.kron(np.ones(M), u_mode) + B @ X)
+    np.testing.assert_allclose(out[:, W.coef_index(T, m, n)], X[3 * (M - 1):], rtol=1e-12, atol=0)
+
+
+def test_seq_order_of_accuracy():
+    """Order K (K <= 2M - 1) on the smooth nonlinear flow of test_order_of_accuracy."""
+    T, nlat, nlon = 15, 24, 48
+    o = _oracle(T, nlat, nlon)
+    st = W.random_state(T, 0) + W.balanced_jet(T, 20.0)
+    Tend = 7200.0
+    u0 = to_complex(torch.tensor(st))
+    for (M, K) in [(3, 2), (3, 3)]:
+        ref = o.step(st, Tend / 128, 4, 4, steps=128)
+        errs = []
+        for div in (16, 32):
+            u = u0
+            for _ in range(div):
+                u = o.seq_step_c(u, Tend / div, M, K)
+            s = to_real(u).numpy()
+            errs.append(np.linalg.norm(s[1] - ref[1]) / np.linalg.norm(ref[1]))
+        slope = math.log(errs[0] / errs[1]) / math.log(2.0)
+        assert slope >= K - 0.3, (M, K, errs, slope)

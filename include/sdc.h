@@ -119,6 +119,17 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K);
  * recent graphs.  The state must stay allocated while a graph for it is cached. */
 int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K);
 
+/* One step of the sequential IMEX SDC of Algorithm 1 (node update of Section 4.1), the method dSDC
+ * parallelises: K sweeps, each updating the M nodes one after another with backward-Euler
+ * differences of f_I (weights dtau_j, dtau_1 = tau_1, dtau_j = tau_j - tau_{j-1}) and forward-Euler
+ * differences of f_E (weights dtau_{j+1}) against the previous sweep; initial guess u_n at every
+ * node; u_{n+1} = u_M^K.  1 + K M - 1 f_E evaluations per step, each over the batch members of one
+ * node (dSDC evaluates all nodes of a sweep at once).  Same arguments, layouts and errors as
+ * sdc_step; qdelta does not apply.  The first call allocates 4 M states per member of workspace.
+ * sdc_step_sequential_graph: the same step as a cached hipGraph. */
+int sdc_step_sequential(sdc_handle h, double* state, double dt, int M, int K);
+int sdc_step_sequential_graph(sdc_handle h, double* state, double dt, int M, int K);
+
 /* One step of IMEX-o2, the paper's reference integrator (Section 3.2): a Strang splitting with
  * Crank-Nicolson half steps for f_I = L_g around one Heun (explicit second-order Runge-Kutta)
  * step for f_E (the paper leaves the order open; the Crank-Nicolson part takes the half steps):

@@ -51,6 +51,8 @@ _SIGS = {
     "sdc_step_graph": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
     "sdc_step_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int]),
     "imex2_step": (c_int, [c_void_p, c_void_p, c_double]),
+    "sdc_step_sequential": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
+    "sdc_step_sequential_graph": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
     "imex2_step_graph": (c_int, [c_void_p, c_void_p, c_double]),
     "sdc_group_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     "sdc_group_step": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_double), c_int, c_int]),

@@ -82,6 +82,17 @@ class SDC:
         check(self.lib.sdc_step_graph(self.h, _ptr(state), float(dt), M or self.M, K or self.K))
         return state
 
+    def step_sequential(self, state, dt: float, M: Optional[int] = None, K: Optional[int] = None):
+        """One sequential IMEX SDC step (Algorithm 1) in place."""
+        self._check(state, self.state_shape, "state")
+        check(self.lib.sdc_step_sequential(self.h, _ptr(state), float(dt), M or self.M, K or self.K))
+        return state
+
+    def step_sequential_graph(self, state, dt: float, M: Optional[int] = None, K: Optional[int] = None):
+        self._check(state, self.state_shape, "state")
+        check(self.lib.sdc_step_sequential_graph(self.h, _ptr(state), float(dt), M or self.M, K or self.K))
+        return state
+
     def imex2_step(self, state, dt: float):
         """One IMEX-o2 step (the paper's reference integrator) in place."""
         self._check(state, self.state_shape, "state")

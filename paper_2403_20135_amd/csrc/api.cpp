@@ -166,7 +166,7 @@ struct sdc_ctx {
     double *ua = nullptr, *ub = nullptr, *E = nullptr, *E0 = nullptr;
     // captured steps: (state, dt, M, K) -> executable graph, replayed on st
     struct GraphEntry {
-        int kind;                     // 0: dSDC step, 1: IMEX-o2 step
+        int kind;                     // 0: dSDC step, 1: IMEX-o2 step, 2: sequential IMEX SDC
         const double* state;
         double dt;
         int M, K;
@@ -185,6 +185,10 @@ struct sdc_ctx {
     double* adj_x = nullptr;          // copy of u_n for the recomputation
     // IMEX-o2 workspaces (allocated by the first imex2_step call): u*, k1, k2 per member
     double *i2_ustar = nullptr, *i2_k1 = nullptr, *i2_k2 = nullptr;
+    // sequential IMEX SDC workspaces (first sdc_step_sequential call): nodes and tendencies of
+    // two sweeps, node-major [M][B][3][ncoef]
+    double* seq_u[2] = {nullptr, nullptr};
+    double* seq_e[2] = {nullptr, nullptr};
     double* cml = nullptr;            // synthesis input, coefficient-major
     double* G = nullptr;              // analysis input (also the scalar analysis input)
     double2* four = nullptr;
@@ -778,6 +782,66 @@ void enqueue_imex2(sdc_ctx* c, double* state, double dt) {
     phase(kImex2Last, c->i2_ustar, state);           // u_{n+1}
 }
 
+int alloc_seq(sdc_ctx* c) {
+    if (c->seq_u[0]) return SDC_OK;
+    const size_t n = (size_t)c->cfg.M * c->cfg.batch * 3 * c->g.ncoef * 2;
+    int rc;
+    for (int k = 0; k < 2; ++k) {
+        if ((rc = c->alloc(c->seq_u[k], n))) return rc;
+        if ((rc = c->alloc(c->seq_e[k], n))) return rc;
+    }
+    return SDC_OK;
+}
+
+// Algorithm 1 for all members: K sweeps of M sequential node updates, each followed by f_E of the
+// new node (all members in one launch), except after the step's last update.
+void enqueue_seq(sdc_ctx* c, double* state, double dt, int M, int K) {
+    const int B = c->cfg.batch;
+    const long long fsz = 3LL * c->g.ncoef * 2;     // doubles per state
+    const long long nsn = (long long)B * fsz;       // node stride of the sweep buffers
+    run_explicit(c, state, B, c->E0);              // E_0 = f_E(u_n)
+    SeqArgs a{};
+    a.un = state;
+    a.uold = state;
+    a.uold_node = 0;
+    a.eold = c->E0;
+    a.eold_node = 0;
+    a.n_of = c->n_of;
+    a.m_of = c->m_of;
+    a.rowoff = c->rowoff;
+    a.inv_lap = c->inv_lap;
+    a.tau = c->tau + M * kMaxNodes;
+    a.Q = c->Q + M * kMaxNodes * kMaxNodes;
+    a.flag = c->flag;
+    a.dt = dt;
+    a.phibar = c->phibar;
+    a.inv_a2 = c->inv_a2;
+    a.M = M;
+    a.batch = B;
+    a.ncoef = c->g.ncoef;
+    a.T = c->g.T;
+    for (int k = 0; k < K; ++k) {
+        double* un = c->seq_u[k & 1];
+        double* en = c->seq_e[k & 1];
+        a.unew = un;
+        a.enew = en;
+        for (int m = 0; m < M; ++m) {
+            const bool last = k == K - 1 && m == M - 1;
+            a.m = m;
+            a.out = last ? state : un + m * nsn;
+            a.cml = last ? nullptr : c->cml;
+            const long t = c->begin(SDC_KERNEL_UPDATE);
+            launch_update_seq(a, c->st);
+            c->end(SDC_KERNEL_UPDATE, t);
+            if (!last) run_explicit_cml(c, B, en + m * nsn);
+        }
+        a.uold = un;
+        a.uold_node = nsn;
+        a.eold = en;
+        a.eold_node = nsn;
+    }
+}
+
 int check_imex2_args(sdc_handle h, const double* state, double dt) {
     if (int rc = check_handle(h)) return rc;
     if (!state) return fail(SDC_EINVAL, "state is NULL");
@@ -838,6 +902,20 @@ int sdc_step(sdc_handle h, double* state, double dt, int M, int K) {
 int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K) {
     if (int rc = check_step_args(h, state, dt, M, K)) return rc;
     return graph_launch(h, 0, state, dt, M, K, [&] { enqueue_step(h, state, dt, M, K); });
+}
+
+int sdc_step_sequential(sdc_handle h, double* state, double dt, int M, int K) {
+    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    if (int rc = alloc_seq(h)) return rc;
+    enqueue_seq(h, state, dt, M, K);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int sdc_step_sequential_graph(sdc_handle h, double* state, double dt, int M, int K) {
+    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    if (int rc = alloc_seq(h)) return rc;
+    return graph_launch(h, 2, state, dt, M, K, [&] { enqueue_seq(h, state, dt, M, K); });
 }
 
 int imex2_step(sdc_handle h, double* state, double dt) {

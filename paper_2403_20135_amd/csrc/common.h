@@ -189,6 +189,27 @@ struct UpdateArgs {
     int M, sweep, last_only, batch, ncoef, T;
 };
 void launch_update(const UpdateArgs& a, hipStream_t st);
+// Sequential IMEX SDC (Algorithm 1): update of node m of a sweep.  Node arrays [node][B][3][ncoef].
+struct SeqArgs {
+    const double* un;          // u_n [B][3][ncoef][2]
+    const double* uold;        // nodes of the previous sweep; node stride uold_node (0: all u_n)
+    const double* eold;        // their explicit tendencies; node stride eold_node (0: all E_0)
+    long long uold_node, eold_node;
+    const double* unew;        // nodes j < m of this sweep (node stride B * 3 * ncoef * 2)
+    const double* enew;
+    double* out;               // u_m of this sweep, or the state on the step's last update
+    double* cml;               // synthesis layout of out (S = B), or null on the last update
+    const int* n_of;
+    const int* m_of;
+    const int* rowoff;
+    const double* inv_lap;
+    const double* tau;         // [M] nodes
+    const double* Q;           // [M][kMaxNodes] collocation matrix rows
+    int* flag;                 // non-finite output of the last update
+    double dt, phibar, inv_a2;
+    int M, m, batch, ncoef, T;
+};
+void launch_update_seq(const SeqArgs& a, hipStream_t st);
 // imex2.hip: the coefficient-wise phases of an IMEX-o2 step for `batch` states [b][3][ncoef]
 //   kImex2First:   out = C(dt/2) in (u*), and its synthesis layout in cml
 //   kImex2Predict: synthesis layout of in + dt k1 (in = u*)

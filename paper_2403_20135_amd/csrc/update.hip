@@ -183,3 +183,89 @@ void launch_solve(double alpha, const double* beta, double* u, const int* n_of, 
     dim3 grid((ncoef + kBlock - 1) / kBlock, batch);
     k_solve<<<grid, kBlock, 0, st>>>(alpha, beta, u, n_of, phibar, inv_a2, ncoef);
 }
+
+// Node update of the sequential IMEX SDC of Algorithm 1 (Section 4.1) for node m of a sweep, one
+// thread per (coefficient, Re/Im part, member):
+//   beta = u_n + dt sum_j q_mj (L_g(u_j^k) + E_j^k)
+//        + dt sum_{j<m} [dtau_{j+1} (E_j^{k+1} - E_j^k) + dtau_j (L_g(u_j^{k+1}) - L_g(u_j^k))]
+//        - dt dtau_m L_g(u_m^k),
+//   u_m^{k+1} = solve(dt dtau_m, beta),  dtau_1 = tau_1, dtau_j = tau_j - tau_{j-1}.
+// Node arrays are node-major [node][member][3][ncoef] so that the f_E launch of one node reads
+// and writes its members contiguously.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_update_seq(SeqArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (t >= 2 * a.ncoef) return;
+    const int idx = t >> 1, c = t & 1;
+    const int n = a.n_of[idx];
+    const double cn = n * (n + 1.0) * a.inv_a2;
+    const size_t fs = (size_t)a.ncoef * 2;
+    const size_t o = (size_t)b * 3 * fs + (size_t)t;           // member b, field 0 of a state
+    const size_t nsn = (size_t)a.batch * 3 * fs;                // node stride of the new sweep
+    const int m = a.m;
+    double sp = 0.0, sz = 0.0, sd = 0.0;                          // the beta terms, per field
+    double Lp_m = 0.0, Ld_m = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const double* uo = a.uold + (size_t)j * a.uold_node + o;
+        const double* eo = a.eold + (size_t)j * a.eold_node + o;
+        const double Lp = -a.phibar * uo[2 * fs], Ld = cn * uo[0];   // L_g(u_j^k)
+        const double Ep = eo[0], Ez = eo[fs], Ed = eo[2 * fs];
+        const double q = a.Q[m * kMaxNodes + j];
+        sp += q * (Lp + Ep);
+        sz += q * Ez;
+        sd += q * (Ld + Ed);
+        if (j < m) {
+            const double dj = a.tau[j] - (j > 0 ? a.tau[j - 1] : 0.0);
+            const double dj1 = a.tau[j + 1] - a.tau[j];
+            const double* un = a.unew + (size_t)j * nsn + o;
+            const double* en = a.enew + (size_t)j * nsn + o;
+            sp += dj1 * (en[0] - Ep) + dj * (-a.phibar * un[2 * fs] - Lp);
+            sz += dj1 * (en[fs] - Ez);
+            sd += dj1 * (en[2 * fs] - Ed) + dj * (cn * un[0] - Ld);
+        }
+        if (j == m) {
+            Lp_m = Lp;
+            Ld_m = Ld;
+        }
+    }
+    const double dm = a.tau[m] - (m > 0 ? a.tau[m - 1] : 0.0);
+    const double alpha = a.dt * dm;
+    const double* un0 = a.un + o;
+    const double bphi = un0[0] + a.dt * sp - alpha * Lp_m;
+    const double bzeta = un0[fs] + a.dt * sz;
+    const double bdiv = un0[2 * fs] + a.dt * sd - alpha * Ld_m;
+    const double phi = (bphi - alpha * a.phibar * bdiv) / (1.0 + alpha * alpha * a.phibar * cn);
+    const double dv = bdiv + alpha * cn * phi;
+    double* out = a.out + o;
+    out[0] = phi;
+    out[fs] = bzeta;
+    out[2 * fs] = dv;
+    if (a.cml) {
+        const int mo = a.m_of[idx], par = (n - mo) & 1, kk = (n - mo) >> 1;
+        const double il = a.inv_lap[n];
+        double* cr = a.cml + (((size_t)a.rowoff[2 * mo + par] + kk) * a.batch + b) * kCmlVals + c;
+        cr[0] = bzeta;
+        cr[2] = phi;
+        cr[4] = il * bzeta;
+        cr[6] = il * dv;
+        if (c == 0) cml_clear_pad(a.cml, a.rowoff[2 * mo + par], kk, npk_of(a.T, mo, par), a.batch, b);
+    } else if (!(isfinite(phi) && isfinite(bzeta) && isfinite(dv))) {
+        a.flag[0] = 1;
+    }
+}
+
+void launch_update_seq(const SeqArgs& a, hipStream_t st) {
+    dim3 grid((2 * a.ncoef + kBlock - 1) / kBlock, a.batch);
+    switch (a.M) {
+    case 1: k_update_seq<1><<<grid, kBlock, 0, st>>>(a); break;
+    case 2: k_update_seq<2><<<grid, kBlock, 0, st>>>(a); break;
+    case 3: k_update_seq<3><<<grid, kBlock, 0, st>>>(a); break;
+    case 4: k_update_seq<4><<<grid, kBlock, 0, st>>>(a); break;
+    case 5: k_update_seq<5><<<grid, kBlock, 0, st>>>(a); break;
+    case 6: k_update_seq<6><<<grid, kBlock, 0, st>>>(a); break;
+    case 7: k_update_seq<7><<<grid, kBlock, 0, st>>>(a); break;
+    default: k_update_seq<8><<<grid, kBlock, 0, st>>>(a); break;
+    }
+}

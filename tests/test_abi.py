@@ -65,6 +65,8 @@ def test_null_arguments():
     assert lib.sht_forward(None, None, None) == _lib.SDC_EINVAL
     assert lib.eval_explicit(None, None, None) == _lib.SDC_EINVAL
     assert lib.imex2_step(None, None, 1.0) == _lib.SDC_EINVAL
+    assert lib.sdc_step_sequential(None, None, 1.0, 1, 1) == _lib.SDC_EINVAL
+    assert lib.sdc_step_sequential_graph(None, None, 1.0, 1, 1) == _lib.SDC_EINVAL
     assert lib.imex2_step_graph(None, None, 1.0) == _lib.SDC_EINVAL
     pl = _lib.SdcPlan(1, 8, 4, 1)
     assert lib.sdc_get_plan(None, ctypes.byref(pl)) == _lib.SDC_EINVAL

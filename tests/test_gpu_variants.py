@@ -1,12 +1,13 @@
-"""GPU parity of the method variants beside the paper's choices, against the oracle through the
-C ABI: MIN-SR-NS diagonal coefficients (tau_m / M in every sweep) for the step and its adjoint."""
+"""GPU parity of the method variants beside the paper's dSDC configuration, against the oracle
+through the C ABI: MIN-SR-NS diagonal coefficients (tau_m / M in every sweep) for the step and its
+adjoint, and the sequential IMEX SDC of Algorithm 1."""
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle.sdc import Oracle
 
-from test_gpu_parity import _dev, _host, _states, rel_l2
+from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, _torch, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -59,3 +60,60 @@ def test_min_sr_ns_adjoint_matches_oracle_vjp():
     err = rel_l2(_host(out), ref, T)
     print(f"[gpu] MIN-SR-NS adjoint: rel L2 {err:.3e}", flush=True)
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("T,nlat,nlon,M,K,dt,steps,batch", [
+    (31, 48, 96, 3, 3, 600.0, 4, 1),
+    (63, 96, 192, 4, 4, 480.0, 2, 2),
+    (21, 34, 64, 2, 5, 900.0, 3, 3),        # ragged latitude tile, K > M
+    (31, 48, 96, 1, 1, 300.0, 2, 1),        # IMEX Euler
+])
+def test_sequential_sdc_matches_oracle(T, nlat, nlon, M, K, dt, steps, batch):
+    sdc = _sdc(T, nlat, nlon, M, K, batch)
+    o = _oracle(T, nlat, nlon)
+    u0 = _states(T, batch, 511)
+    x = _dev(u0)
+    for _ in range(steps):
+        sdc.step_sequential(x, dt)
+    sdc.sync()
+    ref = np.stack([o.seq_step(u0[b], dt, M, K, steps=steps) for b in range(batch)])
+    err = rel_l2(_host(x), ref, T)
+    print(f"[gpu] sequential IMEX SDC T{T} M{M}K{K} x{batch}: rel L2 {err:.3e}", flush=True)
+    assert err <= 1e-11
+
+
+def test_sequential_sdc_graph_matches_eager():
+    torch = _torch()
+    T, nlat, nlon, M, K, dt = 31, 48, 96, 3, 2, 600.0
+    sdc = _sdc(T, nlat, nlon, M, K, 2)
+    u0 = _states(T, 2, 512)
+    xe, xg = _dev(u0), _dev(u0)
+    for k in range(3):
+        sdc.step_sequential(xe, dt)
+        sdc.step_sequential_graph(xg, dt)
+        sdc.sync()
+        torch.cuda.synchronize()
+        assert np.array_equal(_host(xe), _host(xg)), k
+        other = _dev(u0)
+        sdc.step(other, dt)
+        sdc.sync()
+
+
+def test_sequential_sdc_t255_full_size():
+    from conditioning import oracle_one_ulp
+    wl = W.WORKLOADS["t255_m4k4"]
+    mb = wl.members[0]
+    sdc = _sdc(mb.T, mb.nlat, mb.nlon, wl.M, wl.K)
+    u0 = W.initial_state(wl)
+    x = _dev(u0[None])
+    sdc.step_sequential_graph(x, mb.dt)
+    sdc.sync()
+    ref = _oracle(mb.T, mb.nlat, mb.nlon).seq_step(u0, mb.dt, wl.M, wl.K)
+    alt = oracle_one_ulp(mb.T, mb.nlat, mb.nlon).seq_step(u0, mb.dt, wl.M, wl.K)
+    got = _host(x)[0]
+    for k, name in enumerate(("Phi'", "zeta", "delta")):
+        err = rel_l2(got[None, k], ref[None, k], mb.T)
+        spread = rel_l2(alt[None, k], ref[None, k], mb.T)
+        print(f"[gpu] sequential SDC T255 {name}: rel L2 {err:.3e} (oracle 1-ulp spread {spread:.2e})",
+              flush=True)
+        assert err <= max(1e-11, 3 * spread)

@@ -19,8 +19,9 @@ on MFMA), whose error is compared with the plain path's at equal step size again
 path at dt/8 ("equal error": E_fp32 <= 1.1 E_fp64, E = max over output times of the relative
 L2 error of vorticity).  Two further workloads are reported beside the headline: the 32-member
 ensemble of mixed truncations (one graph launch per step) and T511 (FP64 and FP32, forward and
-forward+adjoint), and a work-precision comparison of dSDC with the paper's reference integrator
-IMEX-o2 over one simulated day (errors against IMEX-o2 at dt = 1.5 s, wall time per run, dSDC's
+forward+adjoint), the steps/s of dSDC next to the sequential IMEX SDC it parallelises and to the
+reference integrator IMEX-o2, and a work-precision comparison of dSDC with IMEX-o2 over one
+simulated day (errors against IMEX-o2 at dt = 1.5 s, wall time per run, dSDC's
 speedup at equal error).  The CPU baseline is the FP64 oracle timed on the host cores on a bounded
 sample.
 
@@ -330,6 +331,39 @@ def work_precision(wl, t_end=86400.0, out_every=21600.0):
             "legendre_plan": plan, "rows": rows, "speedup_at_equal_error": speed}
 
 
+def integrators(wl, steps=100, warmup=3):
+    """Steps/s of the three integrators on the headline workload (FP64, graph replays): dSDC
+    (Algorithm 2, the nodes of a sweep batched), the sequential IMEX SDC it parallelises
+    (Algorithm 1, one node at a time) and the reference integrator IMEX-o2."""
+    import torch
+    from paper_2403_20135_amd.api import SDC
+    mb = wl.members[0]
+    sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, 1, "fp64", W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
+    sdc.autotune(10)
+    x0 = torch.tensor(W.initial_state(wl)[None], dtype=torch.float64, device="cuda")
+    out = {}
+    for name, f in (("dSDC", sdc.step_graph), ("sequential_IMEX_SDC", sdc.step_sequential_graph),
+                    ("IMEX_o2", sdc.imex2_step_graph)):
+        x = x0.clone()
+        for _ in range(warmup):
+            f(x, mb.dt)
+        sdc.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f(x, mb.dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sdc.sync()
+        out[name] = {"steps_per_s": round(steps / el, 2), "ms_per_step": round(el / steps * 1e3, 4)}
+    sdc.close()
+    out["f_E_evaluations_per_step"] = {"dSDC": 1 + (wl.K - 1) * wl.M, "sequential_IMEX_SDC": wl.K * wl.M,
+                                       "IMEX_o2": 2}
+    out["dSDC_speedup_vs_sequential"] = round(out["dSDC"]["steps_per_s"] /
+                                              out["sequential_IMEX_SDC"]["steps_per_s"], 3)
+    return out
+
+
 def traffic_for(kernel, plan):
     """Measured HBM bytes per launch of `kernel` from the committed counter summary, or None when
     the summary is missing, was taken from other kernel sources or (for the Legendre classes)
@@ -500,6 +534,7 @@ def main():
             "legendre_plan": r32["plan"],
         }
     if not args.no_fp32 and not args.no_work_precision and args.workload == "t255_m4k4":
+        result["integrators"] = integrators(wl)
         result["work_precision"] = work_precision(wl)
     if not args.no_fp32 and args.workload == "t255_m4k4":
         result["mixed32_m4k3"] = measure_mixed()

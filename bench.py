@@ -72,8 +72,10 @@ def algorithmic_work(T, nlat, M, K, batch, precision):
     with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).  Bytes: both tables (Pbar, H:
     ncoef x nlat/2 entries each) once per launch, plus per state the spectral input (4 complex per
     coefficient) and Fourier output (4 fields x nlat x (T+1) complex) of the synthesis, and the
-    analysis input (7 weighted columns x (T+1) x nlat complex) and spectral output (3 complex).
-    Grid (bytes): reads 4 Fourier fields and writes 5 (minimal), nlat*(T+1) complex each per state.
+    analysis input (7 weighted columns x (T+1) x nlat complex, stored in the table precision:
+    FP32 in the FP32 mode) and spectral output (3 complex).
+    Grid (bytes): reads 4 Fourier fields (FP64) and writes 5 (the minimal output; stored in the
+    table precision), nlat*(T+1) complex each per state.
     Update (bytes): per coefficient and member, reads u_n (3 complex), per node j the Phi', delta
     of u_j (2) and E_j (3), writes the updated nodes (3 each) and their synthesis-layout copy
     (4 each); the last sweep writes node M only; the first f_E of a step converts u_n (3 -> 4).
@@ -84,8 +86,9 @@ def algorithmic_work(T, nlat, M, K, batch, precision):
     launches = K                                 # Legendre launches per step (one per sweep + first)
     tables = 2.0 * ncoef * (nlat // 2) * TABLE_BYTES[precision] * launches
     syn_bytes = tables + states * (4 * 16.0 * ncoef + 4 * 16.0 * nlat * (T + 1))
-    ana_bytes = tables + states * (7 * 16.0 * nlat * (T + 1) + 3 * 16.0 * ncoef)
-    grid_bytes = 9.0 * nlat * (T + 1) * 16 * states
+    col = 2.0 * TABLE_BYTES[precision]          # the analysis columns are stored in the table type
+    ana_bytes = tables + states * (7 * col * nlat * (T + 1) + 3 * 16.0 * ncoef)
+    grid_bytes = (4 * 16.0 + 5 * col) * nlat * (T + 1) * states
     upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + 7)
     return {"synthesis": (6 * transform * states, syn_bytes),
             "analysis": (7 * transform * states, ana_bytes),

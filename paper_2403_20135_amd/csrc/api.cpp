@@ -442,7 +442,7 @@ void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr) {
                          c->cml, S, c->four, c->g, c->st);
     c->end(SDC_KERNEL_SYNTHESIS, t);
     t = c->begin(SDC_KERNEL_GRID);
-    launch_grid_swe(c->four, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, save, c->g, c->st);
+    launch_grid_swe(c->four, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega, save, c->g, c->st);
     c->end(SDC_KERNEL_GRID, t);
     t = c->begin(SDC_KERNEL_ANALYSIS);
     launch_analysis_swe(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
@@ -462,7 +462,7 @@ void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save
     launch_prep_cml_adj(ebar, S, c->cml, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->g.T, c->st);
     launch_synthesis_adj(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
                          c->cml, S, c->adj_four5, c->g, c->st);
-    launch_grid_adj(c->adj_four5, save, c->G, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
+    launch_grid_adj(c->adj_four5, save, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
     launch_analysis_adjoint(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S,
                             c->inv_lap, out_acc, c->g, c->st);
 }

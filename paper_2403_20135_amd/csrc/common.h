@@ -99,11 +99,13 @@ __device__ inline void cml_clear_pad(double* cml, size_t row0, int kk, int np, s
 // four[s][field][lat][m].
 constexpr int kSynFields = 4;
 // Analysis input written by the grid kernel, per (northern latitude jh, m, parity p, state s):
-// 14 doubles = 7 complex columns, Pbar parts (zeta, delta, kinetic energy, Phi') then H parts
+// 14 values = 7 complex columns, Pbar parts (zeta, delta, kinetic energy, Phi') then H parts
 // (zeta, delta, Phi'), already combined into the north +- south sums of parity p and weighted,
-// padded to kAnaStride doubles (one 128-byte line, written whole with zeros in the pad).  The
-// latitude is outermost, so a grid workgroup (one latitude pair, one state) writes whole lines
-// into one contiguous slab and the states of a latitude complete each other's rows:
+// padded to kAnaStride values (written whole with zeros in the pad: one 128-byte line in FP64; in
+// the FP32 precision mode the values are stored rounded to FP32, 64 bytes, since that mode's
+// analysis MFMAs consume them rounded anyway).  The latitude is outermost, so a grid workgroup
+// (one latitude pair, one state) writes whole rows into one contiguous slab and the states of a
+// latitude complete each other's rows:
 //   G[ana_index(T, S, jh, m, p, s) + c]
 constexpr int kAnaVals = 14;
 constexpr int kAnaStride = 16;
@@ -154,10 +156,10 @@ void launch_analysis_scalar(const double* P, const long long* toff, const int4* 
 // grid.hip
 // save (optional): grid values of zeta, Phi', U, V per [state][field][northern latitude][lon]
 // as (north, south) pairs, kept for the adjoint.
-void launch_grid_swe(const double2* four, double* G, const double* mu, const double* w,
+void launch_grid_swe(const double2* four, double* G, bool g32, const double* mu, const double* w,
                      const double2* tw, const FFTPlan& plan, int nstates, double two_omega,
                      double2* save, const Geom& g, hipStream_t st);
-void launch_grid_adj(const double2* four5, const double2* save, double* G, const double* mu,
+void launch_grid_adj(const double2* four5, const double2* save, double* G, bool g32, const double* mu,
                      const double* w, const double2* tw, const FFTPlan& plan, int nstates,
                      double two_omega, const Geom& g, hipStream_t st);
 hipError_t grid_set_lds_limit(int nlon, size_t bytes);

@@ -455,6 +455,21 @@ __device__ __forceinline__ void stage_inputs(double2* buf, const double2* __rest
     }
 }
 
+// One row (16 values) of the analysis input, written as complex pairs: FP64, or FP32 in the FP32
+// mode, whose analysis MFMAs consume the values rounded to FP32 anyway (storing them rounded
+// changes no result and halves the bytes).
+template <typename GT> struct Row;
+template <> struct Row<double> {
+    double2* p;
+    __device__ Row(double* G, size_t off) : p(reinterpret_cast<double2*>(G + off)) {}
+    __device__ void put(int k, double2 v) const { p[k] = v; }
+};
+template <> struct Row<float> {
+    float2* p;
+    __device__ Row(float* G, size_t off) : p(reinterpret_cast<float2*>(G + off)) {}
+    __device__ void put(int k, double2 v) const { p[k] = make_float2((float)v.x, (float)v.y); }
+};
+
 // ---------------------------------------------------------------------------------------------
 // Fused grid step of f_E for one latitude pair of one state:
 //   inverse FFT of zeta, Phi', U, V -> grid products
@@ -471,9 +486,9 @@ __device__ __forceinline__ void stage_inputs(double2* buf, const double2* __rest
 // transformed by the whole workgroup; each analysis row (14 values and 2 zeros, one 128-byte
 // line) is then written whole by one thread.
 // ---------------------------------------------------------------------------------------------
-template <int N>
+template <int N, typename GT>
 __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
-    const double2* __restrict__ four, double* __restrict__ G, const double* __restrict__ mu,
+    const double2* __restrict__ four, GT* __restrict__ G, const double* __restrict__ mu,
     const double* __restrict__ w, const double2* __restrict__ tw, double two_omega,
     int nstates, double2* __restrict__ save, Geom g) {
     extern __shared__ double2 buf[];      // kGridSignals signals x N
@@ -559,22 +574,22 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
         const double2 Bs = cadd(BN, BS), Ba = csub(BN, BS);
         const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
         const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
-        double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
-        double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
-        o0[0] = make_double2(mg * As.y, -mg * As.x);
-        o0[1] = make_double2(-mg * Bs.y, mg * Bs.x);
-        o0[3] = make_double2(mg * Cs.y, -mg * Cs.x);
-        o0[4] = make_double2(gg * Ba.x, gg * Ba.y);
-        o0[5] = make_double2(gg * Aa.x, gg * Aa.y);
-        o0[6] = make_double2(gg * Da.x, gg * Da.y);
-        o0[7] = z2;
-        o1[0] = make_double2(mg * Aa.y, -mg * Aa.x);
-        o1[1] = make_double2(-mg * Ba.y, mg * Ba.x);
-        o1[3] = make_double2(mg * Ca.y, -mg * Ca.x);
-        o1[4] = make_double2(gg * Bs.x, gg * Bs.y);
-        o1[5] = make_double2(gg * As.x, gg * As.y);
-        o1[6] = make_double2(gg * Ds.x, gg * Ds.y);
-        o1[7] = z2;
+        const Row<GT> o0(G, ana_index(T, nstates, jh, m, 0, s));
+        const Row<GT> o1(G, ana_index(T, nstates, jh, m, 1, s));
+        o0.put(0, make_double2(mg * As.y, -mg * As.x));
+        o0.put(1, make_double2(-mg * Bs.y, mg * Bs.x));
+        o0.put(3, make_double2(mg * Cs.y, -mg * Cs.x));
+        o0.put(4, make_double2(gg * Ba.x, gg * Ba.y));
+        o0.put(5, make_double2(gg * Aa.x, gg * Aa.y));
+        o0.put(6, make_double2(gg * Da.x, gg * Da.y));
+        o0.put(7, z2);
+        o1.put(0, make_double2(mg * Aa.y, -mg * Aa.x));
+        o1.put(1, make_double2(-mg * Ba.y, mg * Ba.x));
+        o1.put(3, make_double2(mg * Ca.y, -mg * Ca.x));
+        o1.put(4, make_double2(gg * Bs.x, gg * Bs.y));
+        o1.put(5, make_double2(gg * As.x, gg * As.y));
+        o1.put(6, make_double2(gg * Ds.x, gg * Ds.y));
+        o1.put(7, z2);
     }
     __syncthreads();
     // E: into buffer 0 and transformed by the whole workgroup
@@ -599,43 +614,48 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
         const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
         const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
         const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
-        double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
-        double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
-        o0[0] = areg[mp][0];
-        o0[1] = make_double2(-mg * Bs.y, mg * Bs.x);
-        o0[2] = make_double2(we * Es.x, we * Es.y);
-        o0[3] = make_double2(mg * Cs.y, -mg * Cs.x);
-        o0[4] = make_double2(gg * Ba.x, gg * Ba.y);
-        o0[5] = areg[mp][1];
-        o0[6] = make_double2(gg * Da.x, gg * Da.y);
-        o0[7] = z2;
-        o1[0] = areg[mp][2];
-        o1[1] = make_double2(-mg * Ba.y, mg * Ba.x);
-        o1[2] = make_double2(we * Ea.x, we * Ea.y);
-        o1[3] = make_double2(mg * Ca.y, -mg * Ca.x);
-        o1[4] = make_double2(gg * Bs.x, gg * Bs.y);
-        o1[5] = areg[mp][3];
-        o1[6] = make_double2(gg * Ds.x, gg * Ds.y);
-        o1[7] = z2;
+        const Row<GT> o0(G, ana_index(T, nstates, jh, m, 0, s));
+        const Row<GT> o1(G, ana_index(T, nstates, jh, m, 1, s));
+        o0.put(0, areg[mp][0]);
+        o0.put(1, make_double2(-mg * Bs.y, mg * Bs.x));
+        o0.put(2, make_double2(we * Es.x, we * Es.y));
+        o0.put(3, make_double2(mg * Cs.y, -mg * Cs.x));
+        o0.put(4, make_double2(gg * Ba.x, gg * Ba.y));
+        o0.put(5, areg[mp][1]);
+        o0.put(6, make_double2(gg * Da.x, gg * Da.y));
+        o0.put(7, z2);
+        o1.put(0, areg[mp][2]);
+        o1.put(1, make_double2(-mg * Ba.y, mg * Ba.x));
+        o1.put(2, make_double2(we * Ea.x, we * Ea.y));
+        o1.put(3, make_double2(mg * Ca.y, -mg * Ca.x));
+        o1.put(4, make_double2(gg * Bs.x, gg * Bs.y));
+        o1.put(5, areg[mp][3]);
+        o1.put(6, make_double2(gg * Ds.x, gg * Ds.y));
+        o1.put(7, z2);
     }
     for (int m = threadIdx.x + MP * kGridBlock; m <= T; m += kGridBlock) {
         double2 EN, ES;
         unpack_pair(buf, m, N, EN, ES);
         const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
-        double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
-        double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
-        o0[2] = make_double2(we * Es.x, we * Es.y);
-        o1[2] = make_double2(we * Ea.x, we * Ea.y);
+        const Row<GT> o0(G, ana_index(T, nstates, jh, m, 0, s));
+        const Row<GT> o1(G, ana_index(T, nstates, jh, m, 1, s));
+        o0.put(2, make_double2(we * Es.x, we * Es.y));
+        o1.put(2, make_double2(we * Ea.x, we * Ea.y));
     }
 }
 
-void launch_grid_swe(const double2* four, double* G, const double* mu, const double* w,
+void launch_grid_swe(const double2* four, double* G, bool g32, const double* mu, const double* w,
                      const double2* tw, const FFTPlan& plan, int nstates, double two_omega,
                      double2* save, const Geom& g, hipStream_t st) {
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
     const size_t lds = (size_t)kGridSignals * plan.n * sizeof(double2);
-#define LAUNCH(NN) k_grid_swe<NN><<<nblk, kGridBlock, lds, st>>>(four, G, mu, w, tw, two_omega, nstates, save, g)
+#define LAUNCH(NN)                                                                                    \
+    if (g32)                                                                                          \
+        k_grid_swe<NN, float><<<nblk, kGridBlock, lds, st>>>(four, reinterpret_cast<float*>(G), mu, w, \
+                                                             tw, two_omega, nstates, save, g);        \
+    else                                                                                              \
+        k_grid_swe<NN, double><<<nblk, kGridBlock, lds, st>>>(four, G, mu, w, tw, two_omega, nstates, save, g)
     FFT_DISPATCH(plan.n, LAUNCH)
 #undef LAUNCH
 }
@@ -650,9 +670,9 @@ void launch_grid_swe(const double2* four, double* G, const double* mu, const dou
 // With four LDS signals, E^ is transformed first (by the whole workgroup) and held in registers
 // during the products.
 // ---------------------------------------------------------------------------------------------
-template <int N>
+template <int N, typename GT>
 __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
-    const double2* __restrict__ four5, const double2* __restrict__ save, double* __restrict__ G,
+    const double2* __restrict__ four5, const double2* __restrict__ save, GT* __restrict__ G,
     const double* __restrict__ mu, const double* __restrict__ w, const double2* __restrict__ tw,
     double two_omega, int nstates, Geom g) {
     extern __shared__ double2 buf[];      // kGridSignals signals x N
@@ -723,35 +743,40 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
         const double sm = m == 0 ? 1.0 : 2.0, sa = sm * inva, ms = (double)m * sa;
         const double2 Zs = cadd(ZN, ZS), Za = csub(ZN, ZS), Ps = cadd(PN, PS), Pa = csub(PN, PS);
         const double2 Us = cadd(UN, US), Ua = csub(UN, US), Vs = cadd(VN, VS), Va = csub(VN, VS);
-        double2* o0 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 0, s));
-        double2* o1 = reinterpret_cast<double2*>(G + ana_index(T, nstates, jh, m, 1, s));
+        const Row<GT> o0(G, ana_index(T, nstates, jh, m, 0, s));
+        const Row<GT> o1(G, ana_index(T, nstates, jh, m, 1, s));
         // -i m X (s_m/a) = (m sa X.y, -m sa X.x)
-        o0[0] = make_double2(sm * Zs.x, sm * Zs.y);
-        o0[1] = make_double2(ms * Vs.y, -ms * Vs.x);
-        o0[2] = make_double2(ms * Us.y, -ms * Us.x);
-        o0[3] = make_double2(sm * Ps.x, sm * Ps.y);
-        o0[4] = make_double2(-sa * Ua.x, -sa * Ua.y);
-        o0[5] = make_double2(sa * Va.x, sa * Va.y);
-        o0[6] = z2;
-        o0[7] = z2;
-        o1[0] = make_double2(sm * Za.x, sm * Za.y);
-        o1[1] = make_double2(ms * Va.y, -ms * Va.x);
-        o1[2] = make_double2(ms * Ua.y, -ms * Ua.x);
-        o1[3] = make_double2(sm * Pa.x, sm * Pa.y);
-        o1[4] = make_double2(-sa * Us.x, -sa * Us.y);
-        o1[5] = make_double2(sa * Vs.x, sa * Vs.y);
-        o1[6] = z2;
-        o1[7] = z2;
+        o0.put(0, make_double2(sm * Zs.x, sm * Zs.y));
+        o0.put(1, make_double2(ms * Vs.y, -ms * Vs.x));
+        o0.put(2, make_double2(ms * Us.y, -ms * Us.x));
+        o0.put(3, make_double2(sm * Ps.x, sm * Ps.y));
+        o0.put(4, make_double2(-sa * Ua.x, -sa * Ua.y));
+        o0.put(5, make_double2(sa * Va.x, sa * Va.y));
+        o0.put(6, z2);
+        o0.put(7, z2);
+        o1.put(0, make_double2(sm * Za.x, sm * Za.y));
+        o1.put(1, make_double2(ms * Va.y, -ms * Va.x));
+        o1.put(2, make_double2(ms * Ua.y, -ms * Ua.x));
+        o1.put(3, make_double2(sm * Pa.x, sm * Pa.y));
+        o1.put(4, make_double2(-sa * Us.x, -sa * Us.y));
+        o1.put(5, make_double2(sa * Vs.x, sa * Vs.y));
+        o1.put(6, z2);
+        o1.put(7, z2);
     }
 }
 
-void launch_grid_adj(const double2* four5, const double2* save, double* G, const double* mu,
+void launch_grid_adj(const double2* four5, const double2* save, double* G, bool g32, const double* mu,
                      const double* w, const double2* tw, const FFTPlan& plan, int nstates,
                      double two_omega, const Geom& g, hipStream_t st) {
     const int ntask = g.nh * nstates;
     const int nblk = (ntask + 7) / 8 * 8;
     const size_t lds = (size_t)kGridSignals * plan.n * sizeof(double2);
-#define LAUNCH(NN) k_grid_adj<NN><<<nblk, kGridBlock, lds, st>>>(four5, save, G, mu, w, tw, two_omega, nstates, g)
+#define LAUNCH(NN)                                                                                     \
+    if (g32)                                                                                           \
+        k_grid_adj<NN, float><<<nblk, kGridBlock, lds, st>>>(four5, save, reinterpret_cast<float*>(G), \
+                                                             mu, w, tw, two_omega, nstates, g);        \
+    else                                                                                               \
+        k_grid_adj<NN, double><<<nblk, kGridBlock, lds, st>>>(four5, save, G, mu, w, tw, two_omega, nstates, g)
     FFT_DISPATCH(plan.n, LAUNCH)
 #undef LAUNCH
 }
@@ -835,13 +860,17 @@ void launch_fft_forward_scalar(const double* grid, double2* ana, const double* w
 
 hipError_t grid_set_lds_limit(int n, size_t bytes) {
     hipError_t e = hipSuccess;
-#define SETLDS(NN)                                                                                   \
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_swe<NN>),                          \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                 \
+#define SETLDS1(F)                                                                                   \
     if (e == hipSuccess)                                                                             \
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_adj<NN>),                      \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&F), hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                (int)bytes)
+#define SETLDS(NN)                                                                                   \
+    SETLDS1((k_grid_swe<NN, double>));                                                               \
+    SETLDS1((k_grid_swe<NN, float>));                                                                \
+    SETLDS1((k_grid_adj<NN, double>));                                                               \
+    SETLDS1((k_grid_adj<NN, float>))
     FFT_DISPATCH(n, SETLDS)
 #undef SETLDS
+#undef SETLDS1
     return e;
 }

@@ -16,6 +16,8 @@
 // already holds.
 #include "common.h"
 
+#include <type_traits>
+
 constexpr int kAnaForward = 0, kAnaAdjoint = 1;
 constexpr int kSynForward = 0, kSynAdjoint = 1;
 
@@ -298,11 +300,11 @@ template <typename TT> struct AnaStage {
 template <int MODE, typename TT, int D>
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
-    const int4* __restrict__ tasks, int ntasks, int interleave, const double* __restrict__ G,
+    const int4* __restrict__ tasks, int ntasks, int interleave, const TT* __restrict__ G,
     int nstates, const double* __restrict__ nscale, double* __restrict__ out, Geom g) {
     using MM = Mma<TT>;
     using vec = typename MM::vec;
-    __shared__ __align__(16) double gl[2][kAnaBuf + 2];       // + a dummy slot for idle threads
+    __shared__ __align__(16) double gl[2][kAnaBuf + 4];       // + a dummy slot for idle threads
     const int2 tg = xcd_task_group(ntasks, (nstates + 3) >> 2, interleave);
     if (tg.x >= ntasks) return;
     const int4 task = tasks[tg.x];
@@ -339,36 +341,62 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         offH[t] = sl * kAnaVals + (has_h ? cH : v);
     }
 
-    // cooperative copy of a G block into LDS: thread tid moves chunks tid and tid + 256
-    const size_t jstride = ana_index(g.T, S, 1, 0, 0, 0);           // doubles per latitude
-    const double* gsrc = G + ana_index(g.T, S, 0, m, p, s0);
-    // chunk c: latitude c / 28 of the block, state cw / 7, values 2 (cw % 7), 2 (cw % 7) + 1
-    int clat[2], cw[2], csrc[2], cdst[2];
+    // Cooperative copy of each 16-latitude block of G (16 latitudes x 4 states x 14 values) into
+    // LDS as FP64, all loads of a block issued before the previous block is consumed.  FP64 input:
+    // 448 chunks of two values, thread tid moving chunks tid and tid + 256.  FP32 input (the FP32
+    // mode stores the columns already rounded, which is what its MFMAs consume): 256 chunks of
+    // four values, one per thread (a state's fourth chunk holds values 12, 13 and the row's two
+    // pad zeros, which go to the dummy slot).  Idle threads write the dummy slot.
+    constexpr bool g64 = sizeof(TT) == 8;
+    constexpr int NC = g64 ? 2 : 1;                                  // chunks per thread
+    const size_t jstride = ana_index(g.T, S, 1, 0, 0, 0);           // values per latitude
+    const TT* gsrc = G + ana_index(g.T, S, 0, m, p, s0);
+    int clat[NC], csrc[NC], cdst[NC], cdst2[NC];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int c = tid + kBlock * k;
-        clat[k] = c / (2 * kAnaVals);
-        cw[k] = c % (2 * kAnaVals);
-        const bool ok = c < kAnaChunks && cw[k] < nsg * (kAnaVals / 2);
-        if (!ok) { clat[k] = 0; cw[k] = 0; }
-        csrc[k] = (cw[k] / (kAnaVals / 2)) * kAnaStride + 2 * (cw[k] % (kAnaVals / 2));
-        cdst[k] = ok ? clat[k] * kAnaLat + 2 * cw[k] : kAnaBuf;   // idle: the dummy slot
+    for (int k = 0; k < NC; ++k) {
+        if constexpr (g64) {
+            // chunk c: latitude c / 14 of the block, state cw / 7, values 2 (cw % 7), 2 (cw % 7) + 1
+            const int c = tid + kBlock * k;
+            int lat = c / (2 * kAnaVals), cw = c % (2 * kAnaVals);
+            const bool ok = c < kAnaChunks && cw < nsg * (kAnaVals / 2);
+            if (!ok) { lat = 0; cw = 0; }
+            clat[k] = lat;
+            csrc[k] = (cw / (kAnaVals / 2)) * kAnaStride + 2 * (cw % (kAnaVals / 2));
+            cdst[k] = ok ? lat * kAnaLat + 2 * cw : kAnaBuf;
+            cdst2[k] = 0;
+        } else {
+            // chunk tid: latitude tid / 16, state (tid / 4) % 4, values 4 (tid % 4) .. + 3
+            const int st = (tid >> 2) & 3, kq = tid & 3;
+            const bool ok = st < nsg;
+            clat[k] = ok ? tid >> 4 : 0;
+            csrc[k] = (ok ? st : 0) * kAnaStride + 4 * kq;
+            cdst[k] = ok ? clat[k] * kAnaLat + st * kAnaVals + 4 * kq : kAnaBuf;
+            cdst2[k] = ok && kq < 3 ? cdst[k] + 2 : kAnaBuf + 2;
+        }
     }
-    auto gload = [&](double2 (&r)[2], int b) {
+    typedef typename std::conditional<g64, double2, float4>::type GV;
+    auto gload = [&](GV (&r)[NC], int b) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < NC; ++k) {
             int jh = 16 * b + clat[k];
             jh = jh < g.nh ? jh : g.nh - 1;
-            r[k] = *(const double2*)(gsrc + (size_t)jh * jstride + csrc[k]);
+            r[k] = *(const GV*)(gsrc + (size_t)jh * jstride + csrc[k]);
         }
     };
     // latitudes past nh are stored as zeros (their table entries are zero as well)
     // (no branches: a load sunk into a branch would wait for every load in flight)
-    auto gstore = [&](const double2 (&r)[2], int b, int buf) {
+    auto gstore = [&](const GV (&r)[NC], int b, int buf) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < NC; ++k) {
             const bool live = 16 * b + clat[k] < g.nh;
-            *(double2*)&gl[buf][cdst[k]] = live ? r[k] : make_double2(0.0, 0.0);
+            if constexpr (g64) {
+                *(double2*)&gl[buf][cdst[k]] = live ? r[k] : make_double2(0.0, 0.0);
+            } else {
+                const double2 lo = make_double2((double)r[k].x, (double)r[k].y);
+                const double2 hi = make_double2((double)r[k].z, (double)r[k].w);
+                *(double2*)&gl[buf][cdst[k]] = live ? lo : make_double2(0.0, 0.0);
+                *(double2*)&gl[buf][cdst2[k]] = live ? hi : make_double2(0.0, 0.0);
+            }
         }
     };
 
@@ -390,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         }
     };
 
-    double2 gr[2];
+    GV gr[NC];
     gload(gr, 0);
     gstore(gr, 0, 0);
     __syncthreads();
@@ -462,8 +490,9 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
 template <int MODE, typename TT>
 static void launch_analysis_variant(const LegPlan& plan, unsigned grid, hipStream_t st, const TT* P,
                                     const TT* H, const long long* toff, const int4* tasks, int nwg,
-                                    const double* G, int nstates, const double* nscale, double* out,
+                                    const void* Gv, int nstates, const double* nscale, double* out,
                                     const Geom& g) {
+    const TT* G = static_cast<const TT*>(Gv);      // the analysis input is stored in the table type
     if (plan.ana_depth == 2)
         k_analysis_swe<MODE, TT, 2><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg, plan.ana_interleave,
                                                              G, nstates, nscale, out, g);

@@ -71,7 +71,8 @@ def algorithmic_work(T, nlat, M, K, batch, precision):
     2*ncoef*nlat flops; synthesis does 6 per state (zeta, Phi', psi and chi with Pbar, psi and chi
     with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).  Bytes: both tables (Pbar, H:
     ncoef x nlat/2 entries each) once per launch, plus per state the spectral input (4 complex per
-    coefficient) and Fourier output (4 fields x nlat x (T+1) complex) of the synthesis, and the
+    coefficient, in the table precision) and Fourier output (4 fields x nlat x (T+1) complex, FP64)
+    of the synthesis, and the
     analysis input (7 weighted columns x (T+1) x nlat complex, stored in the table precision:
     FP32 in the FP32 mode) and spectral output (3 complex).
     Grid (bytes): reads 4 Fourier fields (FP64) and writes 5 (the minimal output; stored in the
@@ -85,8 +86,8 @@ def algorithmic_work(T, nlat, M, K, batch, precision):
     states = batch * (1 + (K - 1) * M)          # states transformed per step
     launches = K                                 # Legendre launches per step (one per sweep + first)
     tables = 2.0 * ncoef * (nlat // 2) * TABLE_BYTES[precision] * launches
-    syn_bytes = tables + states * (4 * 16.0 * ncoef + 4 * 16.0 * nlat * (T + 1))
-    col = 2.0 * TABLE_BYTES[precision]          # the analysis columns are stored in the table type
+    col = 2.0 * TABLE_BYTES[precision]          # coefficient columns are stored in the table type
+    syn_bytes = tables + states * (4 * col * ncoef + 4 * 16.0 * nlat * (T + 1))
     ana_bytes = tables + states * (7 * col * nlat * (T + 1) + 3 * 16.0 * ncoef)
     grid_bytes = (4 * 16.0 + 5 * col) * nlat * (T + 1) * states
     upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + 7)

@@ -29,7 +29,7 @@ __device__ __forceinline__ void st2a(double* p, double2 v) { *(double2*)p = v; }
 // Coefficient-major layout of adjoint tendencies: (zeta_adj, delta_adj, Phi_adj, c_n delta_adj).
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_prep_cml_adj(const double* __restrict__ ebar, int nstates,
-                                                         double* __restrict__ cml,
+                                                         double* __restrict__ cml, int cml32,
                                                          const int* __restrict__ n_of,
                                                          const int* __restrict__ m_of,
                                                          const int* __restrict__ rowoff,
@@ -43,18 +43,27 @@ __global__ __launch_bounds__(kBlock) void k_prep_cml_adj(const double* __restric
     const double* e = ebar + (size_t)s * 3 * fs + (size_t)idx * 2;
     const double2 phi = ld2a(e), zeta = ld2a(e + fs), dv = ld2a(e + 2 * fs);
     const double c = neg_lap[n];
-    double* o = cml + (((size_t)rowoff[2 * mo + par] + kk) * nstates + s) * kCmlVals;
-    st2a(o, zeta);
-    st2a(o + 2, dv);
-    st2a(o + 4, phi);
-    st2a(o + 6, make_double2(c * dv.x, c * dv.y));
-    cml_clear_pad(cml, rowoff[2 * mo + par], kk, npk_of(T, mo, par), nstates, s);
+    const size_t ci = (((size_t)rowoff[2 * mo + par] + kk) * nstates + s) * kCmlVals;
+    if (cml32) {
+        float4* o = reinterpret_cast<float4*>(reinterpret_cast<float*>(cml) + ci);
+        o[0] = make_float4((float)zeta.x, (float)zeta.y, (float)dv.x, (float)dv.y);
+        o[1] = make_float4((float)phi.x, (float)phi.y, (float)(c * dv.x), (float)(c * dv.y));
+    } else {
+        double* o = cml + ci;
+        st2a(o, zeta);
+        st2a(o + 2, dv);
+        st2a(o + 4, phi);
+        st2a(o + 6, make_double2(c * dv.x, c * dv.y));
+    }
+    cml_clear_pad(cml, cml32, rowoff[2 * mo + par], kk, npk_of(T, mo, par), nstates, s);
 }
 
-void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int* n_of, const int* m_of,
+void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, bool cml32, const int* n_of,
+                         const int* m_of,
                          const int* rowoff, const double* neg_lap, int ncoef, int T, hipStream_t st) {
     dim3 grid((ncoef + kBlock - 1) / kBlock, nstates);
-    k_prep_cml_adj<<<grid, kBlock, 0, st>>>(ebar, nstates, cml, n_of, m_of, rowoff, neg_lap, ncoef, T);
+    k_prep_cml_adj<<<grid, kBlock, 0, st>>>(ebar, nstates, cml, cml32 ? 1 : 0, n_of, m_of, rowoff, neg_lap,
+                                            ncoef, T);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -452,14 +452,14 @@ void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr) {
 
 void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2* save = nullptr) {
     const long t = c->begin(SDC_KERNEL_UPDATE);
-    launch_prep_cml(states, S, c->cml, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->g.T, c->st);
+    launch_prep_cml(states, S, c->cml, c->P32 != nullptr, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->g.T, c->st);
     c->end(SDC_KERNEL_UPDATE, t);
     run_explicit_cml(c, S, out, save);
 }
 
 // out_acc += J_E(u)^T ebar for S states whose stage grid fields are in `save`.
 void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save, double* out_acc) {
-    launch_prep_cml_adj(ebar, S, c->cml, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->g.T, c->st);
+    launch_prep_cml_adj(ebar, S, c->cml, c->P32 != nullptr, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->g.T, c->st);
     launch_synthesis_adj(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
                          c->cml, S, c->adj_four5, c->g, c->st);
     launch_grid_adj(c->adj_four5, save, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
@@ -689,6 +689,7 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
     // sweep initialisation: E_0 = f_E(u_n); u_m^0 = u_n and E_m^0 = E_0 through node stride 0
     run_explicit(c, state, B, c->E0);
     UpdateArgs a{};
+    a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
     a.un = state;
     a.tau = c->tau + M * kMaxNodes;
     a.Q = c->Q + M * kMaxNodes * kMaxNodes;
@@ -753,6 +754,7 @@ int alloc_imex2(sdc_ctx* c) {
 void enqueue_imex2(sdc_ctx* c, double* state, double dt) {
     const int B = c->cfg.batch;
     Imex2Args a{};
+    a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
     a.n_of = c->n_of;
     a.m_of = c->m_of;
     a.rowoff = c->rowoff;
@@ -801,6 +803,7 @@ void enqueue_seq(sdc_ctx* c, double* state, double dt, int M, int K) {
     const long long nsn = (long long)B * fsz;       // node stride of the sweep buffers
     run_explicit(c, state, B, c->E0);              // E_0 = f_E(u_n)
     SeqArgs a{};
+    a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
     a.un = state;
     a.uold = state;
     a.uold_node = 0;
@@ -949,6 +952,7 @@ int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1,
     HIP_TRY(hipMemcpyAsync(c->adj_x, state_n, (size_t)B * fs * sizeof(double), hipMemcpyDeviceToDevice, c->st));
     run_explicit(c, c->adj_x, B, c->E0, save_at(0));
     UpdateArgs a{};
+    a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
     a.un = c->adj_x;
     a.tau = c->tau + M * kMaxNodes;
     a.Q = c->Q + M * kMaxNodes * kMaxNodes;

@@ -87,13 +87,29 @@ constexpr int kCmlVals = 8;
 // Rows np..np4-1 of every (m, parity) block are padding; each producer of the layout zeroes them
 // for the states it writes (the thread of the block's last real row does it), so that the
 // synthesis contracts whole 4-row steps without masks.
-__device__ inline void cml_clear_pad(double* cml, size_t row0, int kk, int np, size_t S, size_t s) {
+__device__ inline void cml_clear_pad(double* cml, bool cml32, size_t row0, int kk, int np, size_t S,
+                                     size_t s) {
     if (kk != np - 1) return;
     const int np4 = (np + 3) & ~3;
     for (int r = np; r < np4; ++r) {
-        double2* c = (double2*)(cml + ((row0 + r) * S + s) * kCmlVals);
-        for (int k = 0; k < kCmlVals / 2; ++k) c[k] = make_double2(0.0, 0.0);
+        const size_t i = ((row0 + r) * S + s) * kCmlVals;
+        if (cml32) {
+            float4* c = reinterpret_cast<float4*>(reinterpret_cast<float*>(cml) + i);
+            for (int k = 0; k < kCmlVals / 4; ++k) c[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            double2* c = reinterpret_cast<double2*>(cml + i);
+            for (int k = 0; k < kCmlVals / 2; ++k) c[k] = make_double2(0.0, 0.0);
+        }
     }
+}
+// In the FP32 precision mode the synthesis input is stored in FP32 (cml32): its MFMAs consume the
+// values rounded to FP32 anyway, so storing them rounded changes no result and halves the bytes.
+// Element i of the layout (in values):
+__device__ inline void cml_put(double* cml, bool cml32, size_t i, double v) {
+    if (cml32)
+        reinterpret_cast<float*>(cml)[i] = (float)v;
+    else
+        cml[i] = v;
 }
 // Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V, layout
 // four[s][field][lat][m].
@@ -180,6 +196,7 @@ struct UpdateArgs {
     double* uout;              // [B][M][3][ncoef][2], or the state itself when last_only
     long long out_node, out_member;
     double* cml;               // if not null: the updated nodes also in synthesis layout (S = B*M)
+    int cml32;                 // synthesis layout stored in FP32 (FP32 mode)
     const int* m_of;           // order m of every coefficient
     const int* rowoff;         // table row offset of (m, parity)
     const double* inv_lap;     // -a^2/(n(n+1)), 0 at n = 0
@@ -201,6 +218,7 @@ struct SeqArgs {
     const double* enew;
     double* out;               // u_m of this sweep, or the state on the step's last update
     double* cml;               // synthesis layout of out (S = B), or null on the last update
+    int cml32;
     const int* n_of;
     const int* m_of;
     const int* rowoff;
@@ -223,6 +241,7 @@ struct Imex2Args {
     const double* k2;
     double* out;
     double* cml;
+    int cml32;
     const int* n_of;
     const int* m_of;
     const int* rowoff;
@@ -233,7 +252,7 @@ struct Imex2Args {
 };
 void launch_imex2(const Imex2Args& a, hipStream_t st);
 // Synthesis layout of `batch` states [b][3][ncoef] (the first f_E of a step, eval_explicit).
-void launch_prep_cml(const double* state, int nstates, double* cml, const int* n_of,
+void launch_prep_cml(const double* state, int nstates, double* cml, bool cml32, const int* n_of,
                      const int* m_of, const int* rowoff, const double* inv_lap, int ncoef, int T,
                      hipStream_t st);
 void launch_implicit(const double* u, double* fI, const int* n_of, double phibar, double inv_a2,
@@ -242,7 +261,8 @@ void launch_solve(double alpha, const double* beta, double* u, const int* n_of, 
                   double inv_a2, int batch, int ncoef, hipStream_t st);
 
 // adjoint.hip
-void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, const int* n_of, const int* m_of,
+void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, bool cml32, const int* n_of,
+                         const int* m_of,
                          const int* rowoff, const double* neg_lap, int ncoef, int T, hipStream_t st);
 void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long* toff,
                           const int* rowoff, const int2* tasks, int ntasks, const double* cml,

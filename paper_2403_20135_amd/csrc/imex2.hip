@@ -58,12 +58,12 @@ __global__ __launch_bounds__(kBlock) void k_imex2(Imex2Args a) {
     // synthesis layout of member b's next f_E input: (zeta, Phi', psi, chi) x (Re, Im)
     const int mo = a.m_of[idx], par = (n - mo) & 1, kk = (n - mo) >> 1;
     const double il = a.inv_lap[n];
-    double* cr = a.cml + (((size_t)a.rowoff[2 * mo + par] + kk) * a.batch + b) * kCmlVals + c;
-    cr[0] = zeta;
-    cr[2] = phi;
-    cr[4] = il * zeta;
-    cr[6] = il * dv;
-    if (c == 0) cml_clear_pad(a.cml, a.rowoff[2 * mo + par], kk, npk_of(a.T, mo, par), a.batch, b);
+    const size_t ci = (((size_t)a.rowoff[2 * mo + par] + kk) * a.batch + b) * kCmlVals + c;
+    cml_put(a.cml, a.cml32, ci, zeta);
+    cml_put(a.cml, a.cml32, ci + 2, phi);
+    cml_put(a.cml, a.cml32, ci + 4, il * zeta);
+    cml_put(a.cml, a.cml32, ci + 6, il * dv);
+    if (c == 0) cml_clear_pad(a.cml, a.cml32, a.rowoff[2 * mo + par], kk, npk_of(a.T, mo, par), a.batch, b);
 }
 
 void launch_imex2(const Imex2Args& a, hipStream_t st) {

@@ -28,8 +28,9 @@ __device__ __forceinline__ v4d zero4() { return (v4d){0.0, 0.0, 0.0, 0.0}; }
 
 // Table precision of the SWE kernels: FP64 (v_mfma_f64_16x16x4f64; the accumulator of lane l
 // holds rows 4r + q) or FP32 (v_mfma_f32_16x16x4f32 with FP32 accumulation; rows 4q + r).  Both
-// take A[i][q] and B[q][i] from lane i + 16 q.  Coefficient columns stay FP64 in memory and are
-// rounded to the table precision as they enter the MFMA.
+// take A[i][q] and B[q][i] from lane i + 16 q.  The coefficient columns of both transforms are
+// stored in the table precision by their producers (in the FP32 mode: rounded once, as the MFMA
+// would round them); the analysis copies its columns to LDS as FP64 and rounds them at the MFMA.
 typedef float v4f __attribute__((ext_vector_type(4)));
 template <typename TT> struct Mma;
 template <> struct Mma<double> {
@@ -91,7 +92,7 @@ template <> struct SynTiles<kSynAdjoint> {
 
 template <typename TT, int NT, int JT> struct SynStage {
     TT a[JT][2];             // Pbar, H of each latitude tile
-    double b[NT];            // rounded to TT at the MFMA (a conversion here would wait for the load)
+    TT b[NT];                // coefficient columns (stored in the table type)
 };
 
 constexpr int kSynBlock = 128;                   // two waves: the two parities
@@ -102,7 +103,7 @@ constexpr int kSynBlock = 128;                   // two waves: the two parities
 template <int MODE, typename TT, int JT, int D>
 __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
-    const int* __restrict__ rowoff, const int2* __restrict__ tasks, const double* __restrict__ cml,
+    const int* __restrict__ rowoff, const int2* __restrict__ tasks, const TT* __restrict__ cml,
     int nstates, double* __restrict__ four, Geom g) {
     using TL = SynTiles<MODE>;
     using MM = Mma<TT>;
@@ -122,8 +123,8 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     // 32-bit byte offsets from per-block (uniform) base addresses: one VGPR per address
     unsigned boff[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * 8u;
-    const unsigned rstride = (unsigned)S * kCmlVals * 8u;           // bytes per cml row
+    for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * tsz;
+    const unsigned rstride = (unsigned)S * kCmlVals * tsz;          // bytes per cml row
     const int nst = (npk_of(g.T, m, p) + 3) >> 2;                   // 4-row steps of this parity
     const unsigned tstep = 4u * 16u * tsz, cstep = 4u * rstride;    // bytes per 4-row step
     unsigned tlane[JT];
@@ -136,7 +137,6 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const char* tP = (const char*)(P + toff[2 * m + p]);
     const char* tH = (const char*)(H + toff[2 * m + p]);
     const char* cb = (const char*)(cml + (size_t)rowoff[2 * m + p] * S * kCmlVals);
-    auto ldd = [](const char* base, unsigned off) { return *(const double*)(base + off); };
     auto ldt = [](const char* base, unsigned off) { return *(const TT*)(base + off); };
 
     typename MM::vec acc[JT][NT];
@@ -153,12 +153,12 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
             x.a[u][1] = ldt(tH, ot);
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) x.b[t] = ldd(cb, oc + boff[t]);
+        for (int t = 0; t < NT; ++t) x.b[t] = ldt(cb, oc + boff[t]);
     };
     auto compute = [&](const SynStage<TT, NT, JT>& x) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const TT bt = (TT)x.b[t];
+            const TT bt = x.b[t];
 #pragma unroll
             for (int u = 0; u < JT; ++u) acc[u][t] = MM::mma(x.a[u][TL::is_h(t) ? 1 : 0], bt, acc[u][t]);
         }
@@ -237,7 +237,8 @@ static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t
                                      const TT* H, const long long* toff, const int* rowoff,
                                      const int2* tasks, const double* cml, int nstates,
                                      double* four, const Geom& g) {
-#define SYN(JT, D) k_synthesis<MODE, TT, JT, D><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cml, nstates, four, g)
+    const TT* cmlt = reinterpret_cast<const TT*>(cml);    // stored in the table type
+#define SYN(JT, D) k_synthesis<MODE, TT, JT, D><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cmlt, nstates, four, g)
     if (plan.syn_tiles == 4) SYN(4, 2);
     else if (plan.syn_tiles == 2 && plan.syn_depth == 2) SYN(2, 2);
     else if (plan.syn_tiles == 2) SYN(2, 4);

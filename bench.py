@@ -268,6 +268,25 @@ def measure_mixed(steps=20, warmup=3):
             "launch": "one hipGraph per step (members as parallel branches)"}
 
 
+def speedup_at_equal_error(rows):
+    """dSDC's speedup over IMEX-o2 at equal error: for every dSDC row whose error lies inside the
+    IMEX-o2 errors, the IMEX-o2 time interpolated linearly in (log error, log time) between the
+    two bracketing IMEX-o2 rows, divided by the dSDC time."""
+    imex = sorted([(r["error"], r["seconds"]) for r in rows if r["method"] == "IMEX-o2"])
+    speed = []
+    for r in rows:
+        if r["method"] != "dSDC":
+            continue
+        for (e0, t0), (e1, t1) in zip(imex, imex[1:]):
+            if 0 < e0 <= r["error"] <= e1 and e1 > e0:
+                f = math.log(r["error"] / e0) / math.log(e1 / e0)
+                t_imex = math.exp(math.log(t0) + f * (math.log(t1) - math.log(t0)))
+                speed.append({"dt_dSDC": r["dt"], "error": r["error"],
+                              "speedup_vs_IMEX_o2": round(t_imex / r["seconds"], 3)})
+                break
+    return speed
+
+
 def work_precision(wl, t_end=86400.0, out_every=21600.0):
     """Work against precision over one simulated day (the comparison of Section 5: dSDC against
     the IMEX-o2 reference integrator, both on this GPU): absolute L-infinity-in-time, L2-in-space
@@ -317,18 +336,7 @@ def work_precision(wl, t_end=86400.0, out_every=21600.0):
             rows.append({"method": method, "dt": dt, "steps": n, "seconds": round(secs, 5),
                          "error": err})
     sdc.close()
-    # speedup of dSDC at equal error: IMEX-o2 time interpolated (log-log) at each dSDC error
-    imex = sorted([(r["error"], r["seconds"]) for r in rows if r["method"] == "IMEX-o2"])
-    speed = []
-    for r in rows:
-        if r["method"] != "dSDC":
-            continue
-        for (e0, t0), (e1, t1) in zip(imex, imex[1:]):
-            if e0 <= r["error"] <= e1 and e0 > 0:
-                f = math.log(r["error"] / e0) / math.log(e1 / e0)
-                t_imex = math.exp(math.log(t0) + f * (math.log(t1) - math.log(t0)))
-                speed.append({"dt_dSDC": r["dt"], "error": r["error"],
-                              "speedup_vs_IMEX_o2": round(t_imex / r["seconds"], 3)})
+    speed = speedup_at_equal_error(rows)
     return {"workload": wl.name, "t_end_s": t_end, "output_every_s": out_every, "M": wl.M, "K": wl.K,
             "precision": "fp64", "reference": "IMEX-o2 at dt = 1.5 s",
             "error": "max over output times of the area-weighted RMS of the vorticity difference [1/s]",

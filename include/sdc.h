@@ -204,7 +204,8 @@ int sdc_get_info(sdc_handle h, sdc_info* info);
  * Section 3.2).  Every variant computes the same sums in the same order, so results are bitwise
  * identical; only the speed differs with truncation, batch and precision.
  *   syn_lat_tiles, syn_depth: 16-latitude tiles per synthesis workgroup and operand stages in
- *     flight per wave; the built pairs are (1, 8), (1, 4), (2, 4), (2, 2) (the default), (4, 2).
+ *     flight per wave; the built pairs are (1, 8), (1, 4), (2, 4), (2, 2) (the default), (3, 2),
+ *     (4, 2), (4, 1), (6, 1).
  *   ana_depth: table stages in flight per analysis wave, 2 (default) or 4.
  *   ana_interleave: 1 (default) runs the 4-state groups of one analysis task back to back on one
  *     XCD (shared table tile from its L2), 0 issues group after group. */
@@ -221,7 +222,7 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan);
 
 /* Autotuner: times every built synthesis variant and every analysis variant on the handle's
  * stream, at the launch shape of a step (batch x M states), reps launches each after one warm-up
- * (1 <= reps <= 1000), and switches each kernel to its fastest variant when that is at least 3 %
+ * (1 <= reps <= 1000), and switches each kernel to its fastest variant when that is at least 5 %
  * faster than the current one (the plan is written to *chosen unless NULL).  Blocks
  * until the timing is done.  Overwrites the handle's synthesis and analysis workspaces (states
  * passed to other calls are not touched) and drops cached step graphs.  SDC_EHIP if a launch

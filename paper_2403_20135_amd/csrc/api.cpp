@@ -154,8 +154,10 @@ struct sdc_ctx {
     int* n_of = nullptr;
     int* m_of = nullptr;
     double2* tw = nullptr;
-    int2* syn_tasks_t[3] = {nullptr, nullptr, nullptr};   // the same for 1, 2, 4 latitude tiles
-    int n_syn_t[3] = {0, 0, 0};
+    // the same for 1, 2, 3, 4, 6 latitude tiles per workgroup
+    static constexpr int kTileCounts[5] = {1, 2, 3, 4, 6};
+    int2* syn_tasks_t[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int n_syn_t[5] = {0, 0, 0, 0, 0};
     LegPlan lplan{};                  // Legendre launch variants (defaults or sdc_autotune)
     int4* ana_tasks = nullptr;        // SWE analysis: 4 wave tasks per workgroup (XCD-ordered)
     int n_ana_wg = 0;
@@ -226,7 +228,11 @@ struct sdc_ctx {
         ev_marks[k].push_back({(size_t)start, ev_used - 1});
     }
     // SWE synthesis workgroups (XCD-ordered) for the plan's latitude tiles per workgroup
-    static int tiles_index(int jt) { return jt == 4 ? 2 : (jt == 2 ? 1 : 0); }
+    static int tiles_index(int jt) {
+        for (int k = 0; k < 5; ++k)
+            if (kTileCounts[k] == jt) return k;
+        return 0;
+    }
     const int2* syn_list() const { return syn_tasks_t[tiles_index(lplan.syn_tiles)]; }
     int syn_count() const { return n_syn_t[tiles_index(lplan.syn_tiles)]; }
     void drop_graphs() {
@@ -347,7 +353,7 @@ int setup(sdc_ctx* c) {
     // grouped per block of 8 orders on one XCD (the partial output lines of neighbouring orders
     // meet in that L2) and issued longest first.
     const int ntj = g.nhp / 16, njg = (ntj + 3) / 4;
-    for (int jt_per = 1; jt_per <= 4; jt_per *= 2) {
+    for (int jt_per : sdc_ctx::kTileCounts) {
         std::vector<int2> t;
         std::vector<int> grp;
         std::vector<double> wk;
@@ -562,10 +568,11 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
     if (int rc = check_handle(h)) return rc;
     if (!plan) return fail(SDC_EINVAL, "plan is NULL");
     const int jt = plan->syn_lat_tiles, d = plan->syn_depth;
-    const bool syn_ok = (jt == 1 && (d == 8 || d == 4)) || (jt == 2 && (d == 4 || d == 2)) || (jt == 4 && d == 2);
+    const bool syn_ok = (jt == 1 && (d == 8 || d == 4)) || (jt == 2 && (d == 4 || d == 2)) ||
+                        (jt == 3 && d == 2) || (jt == 4 && (d == 2 || d == 1)) || (jt == 6 && d == 1);
     if (!syn_ok)
         return fail(SDC_EINVAL, "synthesis variant (%d tiles, depth %d) not built: use (1, 8), (1, 4), (2, 4), "
-                    "(2, 2) or (4, 2)", jt, d);
+                    "(2, 2), (3, 2), (4, 2), (4, 1) or (6, 1)", jt, d);
     if ((plan->ana_depth != 2 && plan->ana_depth != 4) || (plan->ana_interleave != 0 && plan->ana_interleave != 1))
         return fail(SDC_EINVAL, "analysis variant (depth %d, interleave %d) not built: depth 2 or 4, interleave 0 or 1",
                     plan->ana_depth, plan->ana_interleave);
@@ -603,15 +610,17 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         if (e == hipSuccess) e = hipGetLastError();
         return e;
     };
-    // a candidate replaces the current variant only when it is at least 3 % faster (timing noise
-    // alone does not flip the choice)
-    constexpr float kMargin = 0.97f;
+    // a candidate replaces the current variant only when it is at least 5 % faster (timing noise
+    // and near-ties do not flip the choice)
+    constexpr float kMargin = 0.95f;
     const LegPlan saved = c->lplan;
-    const LegPlan syn_cands[5] = {{1, 8, 4, 1}, {1, 4, 4, 1}, {2, 4, 4, 1}, {2, 2, 4, 1}, {4, 2, 4, 1}};
+    constexpr int kSyn = 8;
+    const LegPlan syn_cands[kSyn] = {{1, 8, 4, 1}, {1, 4, 4, 1}, {2, 4, 4, 1}, {2, 2, 4, 1},
+                                     {3, 2, 4, 1}, {4, 2, 4, 1}, {4, 1, 4, 1}, {6, 1, 4, 1}};
     const LegPlan ana_cands[4] = {{1, 8, 4, 1}, {1, 8, 4, 0}, {1, 8, 2, 1}, {1, 8, 2, 0}};
-    float syn_ms[5] = {0.f}, ana_ms[4] = {0.f};
+    float syn_ms[kSyn] = {0.f}, ana_ms[4] = {0.f};
     hipError_t err = hipSuccess;
-    for (int k = 0; k < 5 && err == hipSuccess; ++k) {
+    for (int k = 0; k < kSyn && err == hipSuccess; ++k) {
         c->lplan = syn_cands[k];
         err = time_it([&] {
             launch_synthesis_swe(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
@@ -628,7 +637,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
     LegPlan best = saved;
     if (err == hipSuccess) {
         int cur = 0, fast = 0;
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < kSyn; ++k) {
             if (syn_cands[k].syn_tiles == saved.syn_tiles && syn_cands[k].syn_depth == saved.syn_depth) cur = k;
             if (syn_ms[k] < syn_ms[fast]) fast = k;
         }

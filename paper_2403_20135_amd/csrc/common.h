@@ -74,7 +74,8 @@ __device__ inline int2 xcd_task_group(int ntasks, int ngroups, int interleave) {
 
 // Launch variants of the Legendre kernels, chosen per handle (defaults or timed at run time):
 // synthesis latitude tiles per workgroup and operand stages in flight per wave ((1, 8), (1, 4),
-// (2, 4), (2, 2), (4, 2)), analysis table stages per wave (4 or 2) and state-group order.  The
+// (2, 4), (2, 2), (3, 2), (4, 2), (4, 1), (6, 1)), analysis table stages per wave (4 or 2) and
+// state-group order.  The
 // defaults are the variants measured fastest for one T255 member.
 struct LegPlan {
     int syn_tiles = 2, syn_depth = 2, ana_depth = 2, ana_interleave = 1;

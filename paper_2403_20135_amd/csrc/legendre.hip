@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
 }
 
 // Synthesis variants (latitude tiles per workgroup, stages in flight): (1, 8), (1, 4), (2, 4),
-// (2, 2), (4, 2).
+// (2, 2), (3, 2), (4, 2), (4, 1), (6, 1).
 template <int MODE, typename TT>
 static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t st, const TT* P,
                                      const TT* H, const long long* toff, const int* rowoff,
@@ -239,7 +239,10 @@ static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t
                                      double* four, const Geom& g) {
     const TT* cmlt = reinterpret_cast<const TT*>(cml);    // stored in the table type
 #define SYN(JT, D) k_synthesis<MODE, TT, JT, D><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cmlt, nstates, four, g)
-    if (plan.syn_tiles == 4) SYN(4, 2);
+    if (plan.syn_tiles == 6) SYN(6, 1);
+    else if (plan.syn_tiles == 4 && plan.syn_depth == 1) SYN(4, 1);
+    else if (plan.syn_tiles == 4) SYN(4, 2);
+    else if (plan.syn_tiles == 3) SYN(3, 2);
     else if (plan.syn_tiles == 2 && plan.syn_depth == 2) SYN(2, 2);
     else if (plan.syn_tiles == 2) SYN(2, 4);
     else if (plan.syn_depth == 4) SYN(1, 4);

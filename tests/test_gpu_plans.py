@@ -2,8 +2,8 @@
 
 Every variant forms the same sums in the same order, so f_E, a step and an adjoint step must agree
 bitwise with the default variants; the grids include an odd number of 16-latitude tiles (T63:
-three tiles, so two- and four-tile synthesis tasks have tiles past the end) and batched node
-states.
+three tiles, so two-, four- and six-tile synthesis tasks have tiles past the end) and batched
+node states.
 """
 import numpy as np
 import pytest
@@ -16,8 +16,8 @@ from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, rel_l2
 pytestmark = pytest.mark.gpu
 
 DEFAULT = dict(syn_lat_tiles=2, syn_depth=2, ana_depth=2, ana_interleave=1)
-VARIANTS = [(1, 8, 4, 1), (1, 4, 4, 1), (2, 4, 4, 1), (2, 2, 4, 1), (4, 2, 4, 1), (1, 8, 2, 1),
-            (1, 8, 4, 0), (2, 4, 2, 0)]
+VARIANTS = [(1, 8, 4, 1), (1, 4, 4, 1), (2, 4, 4, 1), (2, 2, 4, 1), (3, 2, 4, 1), (4, 2, 4, 1),
+            (4, 1, 4, 1), (6, 1, 4, 1), (1, 8, 2, 1), (1, 8, 4, 0), (2, 4, 2, 0)]
 
 
 def _outputs(sdc, x, lam, dt):
@@ -51,7 +51,8 @@ def test_variants_agree_bitwise(T, nlat, nlon, batch, prec):
 
 def test_set_plan_rejects_variants_not_built():
     sdc = _sdc(21, 34, 64, 2, 2, 1)
-    for bad in [(2, 8, 4, 1), (4, 4, 4, 1), (3, 4, 4, 1), (1, 6, 4, 1), (1, 8, 3, 1), (1, 8, 4, 2)]:
+    for bad in [(2, 8, 4, 1), (4, 4, 4, 1), (3, 4, 4, 1), (5, 2, 4, 1), (6, 2, 4, 1), (1, 6, 4, 1),
+                (1, 8, 3, 1), (1, 8, 4, 2)]:
         with pytest.raises(_lib.SDCError) as ei:
             sdc.set_plan(*bad)
         assert ei.value.code == _lib.SDC_EINVAL
@@ -68,7 +69,8 @@ def test_autotune_keeps_results_and_graphs():
     chosen = sdc.autotune(5)
     print(f"[gpu] autotune T{T} x4: {chosen}", flush=True)
     assert chosen == sdc.plan()
-    assert (chosen["syn_lat_tiles"], chosen["syn_depth"]) in [(1, 8), (1, 4), (2, 4), (2, 2), (4, 2)]
+    assert (chosen["syn_lat_tiles"], chosen["syn_depth"]) in [(1, 8), (1, 4), (2, 4), (2, 2), (3, 2),
+                                                                (4, 2), (4, 1), (6, 1)]
     assert chosen["ana_depth"] in (2, 4) and chosen["ana_interleave"] in (0, 1)
     for _ in range(2):
         sdc.step_graph(x, dt)             # recaptured with the chosen variants

@@ -13,7 +13,9 @@ K steps (after W warm-up steps and one graph capture) on synthetic seeded fields
 torch.cuda.synchronize(); each step is one replay of the step's captured hipGraph.  A second
 region of K eager steps brackets every launch with HIP events on the library's stream; the
 dominant kernel class (largest summed time) is reported against its roofline.  A third region
-times K forward steps with one checkpoint each followed by K adjoint steps (forward+adjoint).
+times K forward steps with one checkpoint each followed by K adjoint steps (forward+adjoint, each
+adjoint step recomputing its forward stages), and a fourth the same with every step's stages
+taped in HBM (forward+adjoint taped: no recomputation).
 The same three regions are measured for the FP32 precision mode (Legendre contractions in FP32
 on MFMA), whose error is compared with the plain path's at equal step size against the FP64
 path at dt/8 ("equal error": E_fp32 <= 1.1 E_fp64, E = max over output times of the relative
@@ -190,6 +192,23 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
         raise RuntimeError(f"non-finite state or adjoint ({precision})")
     out["fwd_adj_steps_per_s"] = steps / elapsed_fa
     out["fwd_adj_ms_per_step"] = elapsed_fa / steps * 1e3
+    # forward + adjoint with every step's stages taped in HBM (no recomputation in the adjoint)
+    tapes = [sdc.new_tape() for _ in range(steps)]
+    lam.fill_(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sdc.step_taped(x, mb.dt, tapes[k])
+    for k in range(steps - 1, -1, -1):
+        sdc.step_adjoint_taped(tapes[k], lam, lam, mb.dt)
+    torch.cuda.synchronize()
+    elapsed_ft = time.perf_counter() - t0
+    sdc.sync()
+    if not bool(torch.isfinite(lam).all()):
+        raise RuntimeError(f"non-finite taped adjoint ({precision})")
+    out["fwd_adj_taped_steps_per_s"] = steps / elapsed_ft
+    out["tape_bytes_per_step"] = tapes[0].numel()
+    del tapes
     sdc.close()
     return out
 
@@ -527,6 +546,9 @@ def main():
         "eager_ms_per_step": round(r64["eager_ms_per_step"], 4),
         "fwd_adj_steps_per_s": round(r64["fwd_adj_steps_per_s"], 3) if "fwd_adj_steps_per_s" in r64 else None,
         "fwd_adj_ms_per_step": round(r64["fwd_adj_ms_per_step"], 4) if "fwd_adj_ms_per_step" in r64 else None,
+        "fwd_adj_taped_steps_per_s": (round(r64["fwd_adj_taped_steps_per_s"], 3)
+                                      if "fwd_adj_taped_steps_per_s" in r64 else None),
+        "tape_bytes_per_step": r64.get("tape_bytes_per_step"),
         "roofline": roofline,
         "kernels": kernels,
         "legendre_plan": r64["plan"],
@@ -539,6 +561,7 @@ def main():
             "dtype": "f32 Legendre contractions (FP32 MFMA, FP32 accumulation); f64 elsewhere",
             "ms_per_step": round(r32["ms_per_step"], 4),
             "fwd_adj_steps_per_s": round(r32["fwd_adj_steps_per_s"], 3),
+            "fwd_adj_taped_steps_per_s": round(r32["fwd_adj_taped_steps_per_s"], 3),
             "speedup_vs_fp64": round(r32["steps_per_s"] / r64["steps_per_s"], 4),
             "fwd_adj_speedup_vs_fp64": round(r32["fwd_adj_steps_per_s"] / r64["fwd_adj_steps_per_s"], 4),
             "equal_error": ee,
@@ -556,6 +579,7 @@ def main():
             "config": {"T": 511, "nlat": 768, "nlon": 1536, "M": 4, "K": 4, "dt": 60.0, "steps": 20},
             **{p: {"steps_per_s": round(r["steps_per_s"], 3),
                    "fwd_adj_steps_per_s": round(r["fwd_adj_steps_per_s"], 3),
+                   "fwd_adj_taped_steps_per_s": round(r["fwd_adj_taped_steps_per_s"], 3),
                    "legendre_plan": r["plan"]} for p, r in r511.items()}}
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")

@@ -152,6 +152,19 @@ int imex2_step_graph(sdc_handle h, double* state, double dt);
 int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1, double* lam_n,
                      double dt, int M, int K);
 
+/* Taped adjoint (no recomputation; for callers that keep every step's stages, e.g. a whole
+ * trajectory in HBM): sdc_step_taped is sdc_step that also writes the grid fields of every f_E
+ * evaluation of the step (zeta, Phi', U, V at every grid point of the 1 + (K-1) M stage states of
+ * each member) into `tape`, a caller-owned device buffer of sdc_tape_size(h, M, K) bytes;
+ * sdc_step_adjoint_taped then computes the same lam_n as sdc_step_adjoint for that step from the
+ * tape, skipping the forward recomputation.  The tape must come from a taped step of the same
+ * handle with the same dt, M, K and stay unchanged until the adjoint call has run (stream order).
+ * lam_n may alias lam_np1.  sdc_tape_size: SDC_EINVAL for M, K outside the configured ranges. */
+int sdc_tape_size(sdc_handle h, int M, int K, long long* bytes);
+int sdc_step_taped(sdc_handle h, double* state, double dt, int M, int K, void* tape);
+int sdc_step_adjoint_taped(sdc_handle h, const void* tape, const double* lam_np1, double* lam_n,
+                           double dt, int M, int K);
+
 /* Scalar spherical-harmonic analysis of `batch` grid fields: grid [batch][nlat][nlon] ->
  * spec [batch][ncoef] (Gauss quadrature of the longitude Fourier coefficients truncated to
  * m <= T).  Exact inverse of sht_inverse on band-limited fields. */

@@ -51,6 +51,9 @@ _SIGS = {
     "sdc_step_graph": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
     "sdc_step_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int]),
     "imex2_step": (c_int, [c_void_p, c_void_p, c_double]),
+    "sdc_tape_size": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_ll)]),
+    "sdc_step_taped": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int, c_void_p]),
+    "sdc_step_adjoint_taped": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int]),
     "sdc_step_sequential": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
     "sdc_step_sequential_graph": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
     "imex2_step_graph": (c_int, [c_void_p, c_void_p, c_double]),

@@ -93,6 +93,35 @@ class SDC:
         check(self.lib.sdc_step_sequential_graph(self.h, _ptr(state), float(dt), M or self.M, K or self.K))
         return state
 
+    def tape_size(self, M: Optional[int] = None, K: Optional[int] = None) -> int:
+        """Bytes of the tape of one step (sdc_step_taped)."""
+        n = ctypes.c_longlong()
+        check(self.lib.sdc_tape_size(self.h, M or self.M, K or self.K, ctypes.byref(n)))
+        return n.value
+
+    def new_tape(self, M: Optional[int] = None, K: Optional[int] = None):
+        """A device buffer for one step's tape (uint8 tensor)."""
+        return self._torch.empty(self.tape_size(M, K), dtype=self._torch.uint8, device="cuda")
+
+    def step_taped(self, state, dt: float, tape, M: Optional[int] = None, K: Optional[int] = None):
+        """One dSDC step in place that also records its stages in `tape`."""
+        self._check(state, self.state_shape, "state")
+        if tape.numel() * tape.element_size() < self.tape_size(M, K):
+            raise ValueError("tape too small")
+        check(self.lib.sdc_step_taped(self.h, _ptr(state), float(dt), M or self.M, K or self.K, _ptr(tape)))
+        return state
+
+    def step_adjoint_taped(self, tape, lam_np1, lam_n, dt: float, M: Optional[int] = None,
+                           K: Optional[int] = None):
+        """Adjoint of a taped step from its tape (no recomputation)."""
+        self._check(lam_np1, self.state_shape, "lam_np1")
+        self._check(lam_n, self.state_shape, "lam_n")
+        if tape.numel() * tape.element_size() < self.tape_size(M, K):
+            raise ValueError("tape too small")
+        check(self.lib.sdc_step_adjoint_taped(self.h, _ptr(tape), _ptr(lam_np1), _ptr(lam_n), float(dt),
+                                              M or self.M, K or self.K))
+        return lam_n
+
     def imex2_step(self, state, dt: float):
         """One IMEX-o2 step (the paper's reference integrator) in place."""
         self._check(state, self.state_shape, "state")

@@ -477,22 +477,30 @@ size_t stage_states(const sdc_ctx* c, int s, int M) {     // states stored befor
     return s == 0 ? 0 : (size_t)c->cfg.batch + (size_t)(s - 1) * c->cfg.batch * M;
 }
 
-int alloc_adjoint(sdc_ctx* c) {
-    if (c->adj_ready) return SDC_OK;
+// Adjoint workspaces (first adjoint call); the stage grid fields of the recomputing adjoint only
+// when `with_save` (the taped adjoint reads them from the caller's tape).
+int alloc_adjoint(sdc_ctx* c, bool with_save) {
     const Geom& g = c->g;
     const size_t B = c->cfg.batch;
-    const size_t nst = B + (size_t)(c->cfg.K > 1 ? c->cfg.K - 1 : 0) * B * c->cfg.M;
     const size_t st_d = (size_t)3 * g.ncoef * 2;
     int rc;
-    if ((rc = c->alloc(c->adj_save, nst * kSynFields * g.nh * g.nlon))) return rc;
-    if ((rc = c->alloc(c->adj_four5, (size_t)c->smax * 5 * g.nlat * g.ms))) return rc;
-    if ((rc = c->alloc(c->adj_ubar, st_d * c->smax))) return rc;
-    if ((rc = c->alloc(c->adj_ebar, st_d * c->smax))) return rc;
-    if ((rc = c->alloc(c->adj_un, st_d * B))) return rc;
-    if ((rc = c->alloc(c->adj_x, st_d * B))) return rc;
-    c->adj_ready = true;
+    if (!c->adj_ready) {
+        if ((rc = c->alloc(c->adj_four5, (size_t)c->smax * 5 * g.nlat * g.ms))) return rc;
+        if ((rc = c->alloc(c->adj_ubar, st_d * c->smax))) return rc;
+        if ((rc = c->alloc(c->adj_ebar, st_d * c->smax))) return rc;
+        if ((rc = c->alloc(c->adj_un, st_d * B))) return rc;
+        if ((rc = c->alloc(c->adj_x, st_d * B))) return rc;
+        c->adj_ready = true;
+    }
+    if (with_save && !c->adj_save) {
+        const size_t nst = B + (size_t)(c->cfg.K > 1 ? c->cfg.K - 1 : 0) * B * c->cfg.M;
+        if ((rc = c->alloc(c->adj_save, nst * kSynFields * g.nh * g.nlon))) return rc;
+    }
     return SDC_OK;
 }
+
+// Stage grid fields per state in a tape: zeta, Phi', U, V as (north, south) pairs.
+size_t tape_per_state(const sdc_ctx* c) { return (size_t)kSynFields * c->g.nh * c->g.nlon; }
 
 void run_update(sdc_ctx* c, const UpdateArgs& a) {
     const long t = c->begin(SDC_KERNEL_UPDATE);
@@ -692,11 +700,18 @@ int check_step_args(sdc_handle h, const double* state, double dt, int M, int K) 
 int qd_sweep(const sdc_ctx* c, int s, int M) { return c->cfg.qdelta == 1 ? M : s; }
 
 // Algorithm 2 for all members of the handle, enqueued on c->st (arguments already checked).
-void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
+// With `tape`, the grid fields of every f_E evaluation are kept there (stage s at
+// tape + stage_states(s) * tape_per_state); without `last_update` the final last-node update is
+// skipped (the adjoint's recomputation needs only the stages).
+void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K, double2* tape = nullptr,
+                  bool last_update = true) {
     const int B = c->cfg.batch;
     const long long fs = 3LL * c->g.ncoef * 2;
+    auto tape_at = [&](int s) -> double2* {
+        return tape ? tape + stage_states(c, s, M) * tape_per_state(c) : nullptr;
+    };
     // sweep initialisation: E_0 = f_E(u_n); u_m^0 = u_n and E_m^0 = E_0 through node stride 0
-    run_explicit(c, state, B, c->E0);
+    run_explicit(c, state, B, c->E0, tape_at(0));
     UpdateArgs a{};
     a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
     a.un = state;
@@ -730,7 +745,7 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
         a.last_only = 0;
         a.cml = c->cml;
         run_update(c, a);
-        run_explicit_cml(c, B * M, c->E);
+        run_explicit_cml(c, B * M, c->E, tape_at(s));
         a.uprev = bufs[cur];
         a.uprev_node = fs;
         a.uprev_member = (long long)M * fs;
@@ -739,6 +754,7 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K) {
         a.E_member = (long long)M * fs;
         cur ^= 1;
     }
+    if (!last_update) return;
     // last sweep: node M only, written into the state
     a.uout = state;
     a.out_node = 0;
@@ -861,6 +877,59 @@ int check_imex2_args(sdc_handle h, const double* state, double dt) {
     return alloc_imex2(h);
 }
 
+int check_adjoint_args(sdc_handle h, const double* state_n, const double* lam_np1, const double* lam_n,
+                       double dt, int M, int K) {
+    if (int rc = check_handle(h)) return rc;
+    if (!state_n || !lam_np1 || !lam_n) return fail(SDC_EINVAL, "state_n/lam_np1/lam_n is NULL");
+    if (M < 1 || M > h->cfg.M) return fail(SDC_EINVAL, "M=%d out of range 1..%d", M, h->cfg.M);
+    if (K < 1 || K > h->cfg.K) return fail(SDC_EINVAL, "K=%d out of range 1..%d", K, h->cfg.K);
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(SDC_EINVAL, "dt must be positive and finite");
+    return SDC_OK;
+}
+
+// The reversed sweep of the adjoint step, reading the stage grid fields from `tape`: last-node
+// update, then sweeps K-1..1, then the initial f_E.
+void enqueue_adjoint_reverse(sdc_ctx* c, const double2* tape, const double* lam_np1, double* lam_n,
+                             double dt, int M, int K) {
+    const int B = c->cfg.batch;
+    const long long fs = 3LL * c->g.ncoef * 2;
+    auto save_at = [&](int s) { return tape + stage_states(c, s, M) * tape_per_state(c); };
+    AdjUpdateArgs b{};
+    b.tau = c->tau + M * kMaxNodes;
+    b.Q = c->Q + M * kMaxNodes * kMaxNodes;
+    b.n_of = c->n_of;
+    b.dt = dt;
+    b.phibar = c->phibar;
+    b.inv_a2 = c->inv_a2;
+    b.M = M;
+    b.batch = B;
+    b.ncoef = c->g.ncoef;
+    b.ubar_n = c->adj_un;
+    b.ubar = lam_np1;
+    b.ubar_node = 0;
+    b.ubar_member = fs;
+    b.ubar_prev = c->adj_ubar;
+    b.ebar_prev = c->adj_ebar;
+    b.sweep = qd_sweep(c, K, M);
+    b.last = 1;
+    b.first_stage = K == 1;
+    b.init_un = 1;
+    launch_update_adj(b, c->st);
+    for (int s = K - 1; s >= 1; --s) {
+        run_explicit_adj(c, c->adj_ebar, B * M, save_at(s), c->adj_ubar);
+        b.ubar = c->adj_ubar;
+        b.ubar_node = fs;
+        b.ubar_member = (long long)M * fs;
+        b.sweep = qd_sweep(c, s, M);
+        b.last = 0;
+        b.first_stage = s == 1;
+        b.init_un = 0;
+        launch_update_adj(b, c->st);
+    }
+    run_explicit_adj(c, c->adj_ebar, B, save_at(0), c->adj_un);
+    launch_finish_adj(c->adj_un, lam_n, c->m_of, c->g.ncoef, B, c->st);
+}
+
 // Replays the cached graph of (kind, state, dt, M, K), capturing it first if needed.
 template <class Enqueue>
 int graph_launch(sdc_ctx* c, int kind, double* state, double dt, int M, int K, Enqueue&& enqueue) {
@@ -944,100 +1013,43 @@ int imex2_step_graph(sdc_handle h, double* state, double dt) {
 
 int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1, double* lam_n,
                      double dt, int M, int K) {
-    if (int rc = check_handle(h)) return rc;
-    if (!state_n || !lam_np1 || !lam_n) return fail(SDC_EINVAL, "state_n/lam_np1/lam_n is NULL");
+    if (int rc = check_adjoint_args(h, state_n, lam_np1, lam_n, dt, M, K)) return rc;
     if (lam_n == state_n) return fail(SDC_EINVAL, "lam_n must not alias state_n");
+    sdc_ctx* c = h;
+    if (int rc = alloc_adjoint(c, true)) return rc;
+    // 1. recompute the forward stages, keeping the grid fields of every f_E evaluation
+    HIP_TRY(hipMemcpyAsync(c->adj_x, state_n, (size_t)c->cfg.batch * 3 * c->g.ncoef * 2 * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->st));
+    enqueue_step(c, c->adj_x, dt, M, K, c->adj_save, false);
+    // 2. the reversed sweep
+    enqueue_adjoint_reverse(c, c->adj_save, lam_np1, lam_n, dt, M, K);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
+
+int sdc_tape_size(sdc_handle h, int M, int K, long long* bytes) {
+    if (int rc = check_handle(h)) return rc;
+    if (!bytes) return fail(SDC_EINVAL, "bytes is NULL");
     if (M < 1 || M > h->cfg.M) return fail(SDC_EINVAL, "M=%d out of range 1..%d", M, h->cfg.M);
     if (K < 1 || K > h->cfg.K) return fail(SDC_EINVAL, "K=%d out of range 1..%d", K, h->cfg.K);
-    if (!(dt > 0) || !std::isfinite(dt)) return fail(SDC_EINVAL, "dt must be positive and finite");
-    sdc_ctx* c = h;
-    if (int rc = alloc_adjoint(c)) return rc;
-    const int B = c->cfg.batch;
-    const long long fs = 3LL * c->g.ncoef * 2;
-    const size_t save_per_state = (size_t)kSynFields * c->g.nh * c->g.nlon;
-    auto save_at = [&](int s) { return c->adj_save + stage_states(c, s, M) * save_per_state; };
+    *bytes = (long long)(stage_states(h, K, M) * tape_per_state(h) * sizeof(double2));
+    return SDC_OK;
+}
 
-    // 1. recompute the forward stages, keeping the grid fields of every f_E evaluation
-    HIP_TRY(hipMemcpyAsync(c->adj_x, state_n, (size_t)B * fs * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-    run_explicit(c, c->adj_x, B, c->E0, save_at(0));
-    UpdateArgs a{};
-    a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
-    a.un = c->adj_x;
-    a.tau = c->tau + M * kMaxNodes;
-    a.Q = c->Q + M * kMaxNodes * kMaxNodes;
-    a.n_of = c->n_of;
-    a.m_of = c->m_of;
-    a.rowoff = c->rowoff;
-    a.inv_lap = c->inv_lap;
-    a.flag = c->flag;
-    a.dt = dt;
-    a.phibar = c->phibar;
-    a.inv_a2 = c->inv_a2;
-    a.M = M;
-    a.batch = B;
-    a.ncoef = c->g.ncoef;
-    a.T = c->g.T;
-    a.uprev = c->adj_x;
-    a.uprev_node = 0;
-    a.uprev_member = fs;
-    a.E = c->E0;
-    a.E_node = 0;
-    a.E_member = fs;
-    double* bufs[2] = {c->ua, c->ub};
-    int cur = 0;
-    for (int s = 1; s < K; ++s) {
-        a.uout = bufs[cur];
-        a.out_node = fs;
-        a.out_member = (long long)M * fs;
-        a.cml = c->cml;
-        a.sweep = qd_sweep(c, s, M);
-        a.last_only = 0;
-        launch_update(a, c->st);
-        run_explicit_cml(c, B * M, c->E, save_at(s));
-        a.uprev = bufs[cur];
-        a.uprev_node = fs;
-        a.uprev_member = (long long)M * fs;
-        a.E = c->E;
-        a.E_node = fs;
-        a.E_member = (long long)M * fs;
-        cur ^= 1;
-    }
+int sdc_step_taped(sdc_handle h, double* state, double dt, int M, int K, void* tape) {
+    if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    if (!tape) return fail(SDC_EINVAL, "tape is NULL");
+    enqueue_step(h, state, dt, M, K, static_cast<double2*>(tape), true);
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
+}
 
-    // 2. reversed sweep: last-node update, then sweeps K-1..1, then the initial f_E
-    AdjUpdateArgs b{};
-    b.tau = a.tau;
-    b.Q = a.Q;
-    b.n_of = c->n_of;
-    b.dt = dt;
-    b.phibar = c->phibar;
-    b.inv_a2 = c->inv_a2;
-    b.M = M;
-    b.batch = B;
-    b.ncoef = c->g.ncoef;
-    b.ubar_n = c->adj_un;
-    b.ubar = lam_np1;
-    b.ubar_node = 0;
-    b.ubar_member = fs;
-    b.ubar_prev = c->adj_ubar;
-    b.ebar_prev = c->adj_ebar;
-    b.sweep = qd_sweep(c, K, M);
-    b.last = 1;
-    b.first_stage = K == 1;
-    b.init_un = 1;
-    launch_update_adj(b, c->st);
-    for (int s = K - 1; s >= 1; --s) {
-        run_explicit_adj(c, c->adj_ebar, B * M, save_at(s), c->adj_ubar);
-        b.ubar = c->adj_ubar;
-        b.ubar_node = fs;
-        b.ubar_member = (long long)M * fs;
-        b.sweep = qd_sweep(c, s, M);
-        b.last = 0;
-        b.first_stage = s == 1;
-        b.init_un = 0;
-        launch_update_adj(b, c->st);
-    }
-    run_explicit_adj(c, c->adj_ebar, B, save_at(0), c->adj_un);
-    launch_finish_adj(c->adj_un, lam_n, c->m_of, c->g.ncoef, B, c->st);
+int sdc_step_adjoint_taped(sdc_handle h, const void* tape, const double* lam_np1, double* lam_n,
+                           double dt, int M, int K) {
+    if (!tape) return fail(SDC_EINVAL, "tape is NULL");
+    if (int rc = check_adjoint_args(h, static_cast<const double*>(tape), lam_np1, lam_n, dt, M, K)) return rc;
+    if (int rc = alloc_adjoint(h, false)) return rc;
+    enqueue_adjoint_reverse(h, static_cast<const double2*>(tape), lam_np1, lam_n, dt, M, K);
     HIP_TRY(hipGetLastError());
     return SDC_OK;
 }

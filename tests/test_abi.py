@@ -65,6 +65,9 @@ def test_null_arguments():
     assert lib.sht_forward(None, None, None) == _lib.SDC_EINVAL
     assert lib.eval_explicit(None, None, None) == _lib.SDC_EINVAL
     assert lib.imex2_step(None, None, 1.0) == _lib.SDC_EINVAL
+    assert lib.sdc_tape_size(None, 1, 1, ctypes.byref(ctypes.c_longlong())) == _lib.SDC_EINVAL
+    assert lib.sdc_step_taped(None, None, 1.0, 1, 1, None) == _lib.SDC_EINVAL
+    assert lib.sdc_step_adjoint_taped(None, None, None, None, 1.0, 1, 1) == _lib.SDC_EINVAL
     assert lib.sdc_step_sequential(None, None, 1.0, 1, 1) == _lib.SDC_EINVAL
     assert lib.sdc_step_sequential_graph(None, None, 1.0, 1, 1) == _lib.SDC_EINVAL
     assert lib.imex2_step_graph(None, None, 1.0) == _lib.SDC_EINVAL

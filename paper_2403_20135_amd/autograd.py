@@ -3,7 +3,9 @@
 `sdc_step(x, sdc, dt, M, K)` returns the state after one dSDC step; its backward calls
 sdc_step_adjoint, which recomputes the node stages of that step from the saved input.  A loop of
 steps therefore keeps one checkpoint per step (the step's input state) and recomputes each step's
-stages during the backward pass.  `sht_inverse(spec, sdc)` is the scalar synthesis with its
+stages during the backward pass.  With taped=True the forward keeps the step's stage grid fields
+in a device tape (sdc_tape_size bytes per step) and the backward reads them instead of
+recomputing (same gradient, bitwise).  `sht_inverse(spec, sdc)` is the scalar synthesis with its
 transpose as backward.  Gradients follow the real inner product over (Re, Im) of every stored
 coefficient; the imaginary parts of m = 0 entries of state gradients are zero.
 """
@@ -14,20 +16,28 @@ import torch
 
 class _SDCStep(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x, sdc, dt, M, K):
+    def forward(ctx, x, sdc, dt, M, K, taped):
         y = x.detach().clone().contiguous()
-        sdc.step(y, dt, M, K)
-        ctx.save_for_backward(x.detach())
-        ctx.sdc, ctx.dt, ctx.M, ctx.K = sdc, dt, M, K
+        if taped:
+            tape = sdc.new_tape(M, K)
+            sdc.step_taped(y, dt, tape, M, K)
+            ctx.save_for_backward(tape)
+        else:
+            sdc.step(y, dt, M, K)
+            ctx.save_for_backward(x.detach())
+        ctx.sdc, ctx.dt, ctx.M, ctx.K, ctx.taped = sdc, dt, M, K, taped
         return y
 
     @staticmethod
     def backward(ctx, gy):
-        (x,) = ctx.saved_tensors
+        (saved,) = ctx.saved_tensors
         lam = gy.detach().contiguous().clone()
         out = torch.empty_like(lam)
-        ctx.sdc.step_adjoint(x.contiguous(), lam, out, ctx.dt, ctx.M, ctx.K)
-        return out, None, None, None, None
+        if ctx.taped:
+            ctx.sdc.step_adjoint_taped(saved, lam, out, ctx.dt, ctx.M, ctx.K)
+        else:
+            ctx.sdc.step_adjoint(saved.contiguous(), lam, out, ctx.dt, ctx.M, ctx.K)
+        return out, None, None, None, None, None
 
 
 class _SHTInverse(torch.autograd.Function):
@@ -45,8 +55,8 @@ class _SHTInverse(torch.autograd.Function):
         return spec, None
 
 
-def sdc_step(x, sdc, dt: float, M: int = None, K: int = None):
-    return _SDCStep.apply(x, sdc, float(dt), M or sdc.M, K or sdc.K)
+def sdc_step(x, sdc, dt: float, M: int = None, K: int = None, taped: bool = False):
+    return _SDCStep.apply(x, sdc, float(dt), M or sdc.M, K or sdc.K, bool(taped))
 
 
 def sht_inverse(spec, sdc):

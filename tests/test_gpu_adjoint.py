@@ -89,13 +89,13 @@ def test_sht_inverse_adjoint_matches_oracle():
     assert rel_l2(_host(spec), ref, T) <= 1e-13
 
 
-def _loss_grad_gpu(sdc, x0, tgt, dt, steps):
+def _loss_grad_gpu(sdc, x0, tgt, dt, steps, taped=False):
     torch = _torch()
     from paper_2403_20135_amd.autograd import height_loss, sdc_step
     x = _dev(x0).requires_grad_(True)
     y = x
     for _ in range(steps):
-        y = sdc_step(y, sdc, dt)
+        y = sdc_step(y, sdc, dt, taped=taped)
     L = height_loss(y, _dev(tgt), sdc, W.GRAVITY)
     L.backward()
     torch.cuda.synchronize()
@@ -123,6 +123,8 @@ def test_adjoint_workload_gradient_t127():
     tgt = W.loss_target_phi(mb.T)[None]
     L, g = _loss_grad_gpu(sdc, x0, tgt, mb.dt, wl.steps)
     print(f"[gpu] T127 loss {L:.6e}", flush=True)
+    Lt, gt = _loss_grad_gpu(sdc, x0, tgt, mb.dt, wl.steps, taped=True)   # stages taped in HBM
+    assert Lt == L and np.array_equal(gt, g)
     o = _oracle(mb.T, mb.nlat, mb.nlon)
     Lo, go = o.loss_and_grad(x0[0], tgt[0], mb.dt, wl.M, wl.K, wl.steps)
     assert abs(L - Lo) <= 1e-11 * abs(Lo)

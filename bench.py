@@ -58,9 +58,12 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_t255_m4k4.json")
 
 
 def source_hash() -> str:
-    """Hash of the HIP sources: a counter summary is valid only for the kernels it measured."""
+    """Hash of the device sources (the .hip kernels and the header they share): a counter summary
+    is valid only for the kernels it measured.  The Legendre launch variants, the only host-side
+    choice that changes what those kernels do per launch, are checked separately (the plan)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2403_20135_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_2403_20135_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode() + f.read())
     return h.hexdigest()[:16]

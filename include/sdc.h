@@ -155,7 +155,8 @@ int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1,
 /* Taped adjoint (no recomputation; for callers that keep every step's stages, e.g. a whole
  * trajectory in HBM): sdc_step_taped is sdc_step that also writes the grid fields of every f_E
  * evaluation of the step (zeta, Phi', U, V at every grid point of the 1 + (K-1) M stage states of
- * each member) into `tape`, a caller-owned device buffer of sdc_tape_size(h, M, K) bytes;
+ * each member) into `tape`, a caller-owned, 16-byte aligned device buffer of sdc_tape_size(h, M, K)
+ * bytes;
  * sdc_step_adjoint_taped then computes the same lam_n as sdc_step_adjoint for that step from the
  * tape, skipping the forward recomputation.  The tape must come from a taped step of the same
  * handle with the same dt, M, K and stay unchanged until the adjoint call has run (stream order).

@@ -1,6 +1,7 @@
 // C ABI of the dSDC library: argument validation, device memory, setup and the orchestration of
 // Algorithm 2 (diagonal IMEX SDC step) on one HIP stream.
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
@@ -1039,6 +1040,7 @@ int sdc_tape_size(sdc_handle h, int M, int K, long long* bytes) {
 int sdc_step_taped(sdc_handle h, double* state, double dt, int M, int K, void* tape) {
     if (int rc = check_step_args(h, state, dt, M, K)) return rc;
     if (!tape) return fail(SDC_EINVAL, "tape is NULL");
+    if (reinterpret_cast<uintptr_t>(tape) % 16) return fail(SDC_EINVAL, "tape must be 16-byte aligned");
     enqueue_step(h, state, dt, M, K, static_cast<double2*>(tape), true);
     HIP_TRY(hipGetLastError());
     return SDC_OK;
@@ -1047,6 +1049,7 @@ int sdc_step_taped(sdc_handle h, double* state, double dt, int M, int K, void* t
 int sdc_step_adjoint_taped(sdc_handle h, const void* tape, const double* lam_np1, double* lam_n,
                            double dt, int M, int K) {
     if (!tape) return fail(SDC_EINVAL, "tape is NULL");
+    if (reinterpret_cast<uintptr_t>(tape) % 16) return fail(SDC_EINVAL, "tape must be 16-byte aligned");
     if (int rc = check_adjoint_args(h, static_cast<const double*>(tape), lam_np1, lam_n, dt, M, K)) return rc;
     if (int rc = alloc_adjoint(h, false)) return rc;
     enqueue_adjoint_reverse(h, static_cast<const double2*>(tape), lam_np1, lam_n, dt, M, K);

@@ -225,13 +225,18 @@ int sdc_get_info(sdc_handle h, sdc_info* info);
  *     XCD (shared table tile from its L2), 0 issues group after group. */
 typedef struct {
     int syn_lat_tiles, syn_depth, ana_depth, ana_interleave;
+    int fuse_update;   /* 1 (default): for M in {1, 2, 4} the node update of the next sweep runs in
+                          the analysis kernel's epilogue, from tendencies that never leave its
+                          workgroups (same arithmetic, bitwise the same states); 0: separate
+                          update kernel.  Not changed by the autotuner. */
 } sdc_plan;
 
 /* The handle's current variants. */
 int sdc_get_plan(sdc_handle h, sdc_plan* plan);
 
 /* Select variants; SDC_EINVAL for a combination that is not built (the handle keeps its plan).
- * Graphs cached by sdc_step_graph are dropped and recaptured on their next call. */
+ * fuse_update must be 0 or 1.  Graphs cached by sdc_step_graph are dropped and recaptured on
+ * their next call. */
 int sdc_set_plan(sdc_handle h, const sdc_plan* plan);
 
 /* Autotuner: times every built synthesis variant and every analysis variant on the handle's

@@ -202,8 +202,9 @@ class SDC:
         check(self.lib.sdc_get_plan(self.h, ctypes.byref(pl)))
         return {k: getattr(pl, k) for k, _ in pl._fields_}
 
-    def set_plan(self, syn_lat_tiles: int, syn_depth: int, ana_depth: int, ana_interleave: int):
-        pl = _lib.SdcPlan(syn_lat_tiles, syn_depth, ana_depth, ana_interleave)
+    def set_plan(self, syn_lat_tiles: int, syn_depth: int, ana_depth: int, ana_interleave: int,
+                 fuse_update: int = 1):
+        pl = _lib.SdcPlan(syn_lat_tiles, syn_depth, ana_depth, ana_interleave, fuse_update)
         check(self.lib.sdc_set_plan(self.h, ctypes.byref(pl)))
 
     def autotune(self, reps: int = 10) -> dict:

@@ -443,7 +443,8 @@ int setup(sdc_ctx* c) {
 
 // f_E of S states whose synthesis input is already in c->cml (written by the update kernel or
 // by launch_prep_cml).
-void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr) {
+void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr,
+                      const UpdateArgs* fuse = nullptr, int fuse_mode = 0) {
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
     launch_synthesis_swe(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
                          c->cml, S, c->four, c->g, c->st);
@@ -453,15 +454,16 @@ void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr) {
     c->end(SDC_KERNEL_GRID, t);
     t = c->begin(SDC_KERNEL_ANALYSIS);
     launch_analysis_swe(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
-                        out, c->g, c->st);
+                        out, c->g, c->st, fuse, fuse_mode);
     c->end(SDC_KERNEL_ANALYSIS, t);
 }
 
-void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2* save = nullptr) {
+void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2* save = nullptr,
+                  const UpdateArgs* fuse = nullptr, int fuse_mode = 0) {
     const long t = c->begin(SDC_KERNEL_UPDATE);
     launch_prep_cml(states, S, c->cml, c->P32 != nullptr, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->g.T, c->st);
     c->end(SDC_KERNEL_UPDATE, t);
-    run_explicit_cml(c, S, out, save);
+    run_explicit_cml(c, S, out, save, fuse, fuse_mode);
 }
 
 // out_acc += J_E(u)^T ebar for S states whose stage grid fields are in `save`.
@@ -570,12 +572,15 @@ int sdc_get_plan(sdc_handle h, sdc_plan* plan) {
     plan->syn_depth = h->lplan.syn_depth;
     plan->ana_depth = h->lplan.ana_depth;
     plan->ana_interleave = h->lplan.ana_interleave;
+    plan->fuse_update = h->lplan.fuse_update;
     return SDC_OK;
 }
 
 int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
     if (int rc = check_handle(h)) return rc;
     if (!plan) return fail(SDC_EINVAL, "plan is NULL");
+    if (plan->fuse_update != 0 && plan->fuse_update != 1)
+        return fail(SDC_EINVAL, "fuse_update=%d: 0 or 1", plan->fuse_update);
     const int jt = plan->syn_lat_tiles, d = plan->syn_depth;
     const bool syn_ok = (jt == 1 && (d == 8 || d == 4)) || (jt == 2 && (d == 4 || d == 2)) ||
                         (jt == 3 && d == 2) || (jt == 4 && (d == 2 || d == 1)) || (jt == 6 && d == 1);
@@ -589,6 +594,7 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
     h->lplan.syn_depth = plan->syn_depth;
     h->lplan.ana_depth = plan->ana_depth;
     h->lplan.ana_interleave = plan->ana_interleave;
+    h->lplan.fuse_update = plan->fuse_update;
     h->drop_graphs();                 // recaptured with the new variants on their next replay
     return SDC_OK;
 }
@@ -679,6 +685,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         chosen->syn_depth = best.syn_depth;
         chosen->ana_depth = best.ana_depth;
         chosen->ana_interleave = best.ana_interleave;
+        chosen->fuse_update = best.fuse_update;
     }
     return SDC_OK;
 }
@@ -711,8 +718,6 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K, double2* t
     auto tape_at = [&](int s) -> double2* {
         return tape ? tape + stage_states(c, s, M) * tape_per_state(c) : nullptr;
     };
-    // sweep initialisation: E_0 = f_E(u_n); u_m^0 = u_n and E_m^0 = E_0 through node stride 0
-    run_explicit(c, state, B, c->E0, tape_at(0));
     UpdateArgs a{};
     a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
     a.un = state;
@@ -738,6 +743,40 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K, double2* t
     a.E_member = fs;
     double* bufs[2] = {c->ua, c->ub};
     int cur = 0;
+    if (c->lplan.fuse_update && (M == 1 || M == 2 || M == 4)) {
+        // The node update of sweep s + 1 runs inside the analysis of the f_E of sweep s (the
+        // tendencies stay in the analysis workgroups): sweep s < K updates every node into
+        // bufs[cur] and the synthesis input, sweep K node M into the state.
+        auto set_update = [&](int s) {
+            if (s < K) {
+                a.uout = bufs[cur];
+                a.out_node = fs;
+                a.out_member = (long long)M * fs;
+                a.cml = c->cml;
+                a.last_only = 0;
+            } else {
+                a.uout = state;
+                a.out_node = 0;
+                a.out_member = fs;
+                a.cml = nullptr;
+                a.last_only = 1;
+            }
+            a.sweep = qd_sweep(c, s, M);
+        };
+        set_update(1);
+        run_explicit(c, state, B, c->E0, tape_at(0), (K > 1 || last_update) ? &a : nullptr, 1);
+        for (int s = 1; s < K; ++s) {
+            a.uprev = bufs[cur];
+            a.uprev_node = fs;
+            a.uprev_member = (long long)M * fs;
+            cur ^= 1;
+            set_update(s + 1);
+            run_explicit_cml(c, B * M, c->E, tape_at(s), (s + 1 < K || last_update) ? &a : nullptr, 2);
+        }
+        return;
+    }
+    // sweep initialisation: E_0 = f_E(u_n); u_m^0 = u_n and E_m^0 = E_0 through node stride 0
+    run_explicit(c, state, B, c->E0, tape_at(0));
     for (int s = 1; s < K; ++s) {
         a.uout = bufs[cur];
         a.out_node = fs;

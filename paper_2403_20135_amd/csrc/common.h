@@ -79,6 +79,7 @@ __device__ inline int2 xcd_task_group(int ntasks, int ngroups, int interleave) {
 // defaults are the variants measured fastest for one T255 member.
 struct LegPlan {
     int syn_tiles = 2, syn_depth = 2, ana_depth = 2, ana_interleave = 1;
+    int fuse_update = 1;       // node updates inside the analysis (M in {1, 2, 4})
 };
 
 // Synthesis input ("coefficient-major", written by the update/prep kernels): for table row
@@ -155,9 +156,14 @@ void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long
                           const int* rowoff, const int2* tasks, int ntasks, const double* cml,
                           int nstates, double2* four, const Geom& g, hipStream_t st);
 // Analysis tasks: (m, p, first row, valid) per workgroup, XCD-ordered.
+// With fuse != null the tendencies are not written: the kernel applies the node update `*fuse`
+// to them (fuse_mode 1: the states are members, as in the step's first f_E; 2: the states are
+// (member, node) pairs of M in {1, 2, 4} nodes per member).
+struct UpdateArgs;
 void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
                          const int4* tasks, int nwg, const double* G, int nstates,
-                         const double* neg_lap, double* out, const Geom& g, hipStream_t st);
+                         const double* neg_lap, double* out, const Geom& g, hipStream_t st,
+                         const UpdateArgs* fuse = nullptr, int fuse_mode = 0);
 void launch_synthesis_scalar(const double* P, const long long* toff, const int2* tasks, int ntasks,
                              const double* spec, int nfields, double2* four, const Geom& g,
                              hipStream_t st);

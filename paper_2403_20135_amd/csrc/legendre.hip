@@ -14,7 +14,7 @@
 // keep several 4-row (synthesis) or 16-latitude (analysis) operand stages in flight in registers,
 // and place the columns of their tiles so that every output is formed from values the lane
 // already holds.
-#include "common.h"
+#include "node_update.h"
 
 #include <type_traits>
 
@@ -305,7 +305,8 @@ template <int MODE, typename TT, int D>
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int4* __restrict__ tasks, int ntasks, int interleave, const TT* __restrict__ G,
-    int nstates, const double* __restrict__ nscale, double* __restrict__ out, Geom g) {
+    int nstates, const double* __restrict__ nscale, double* __restrict__ out, Geom g,
+    UpdateArgs fu, int fuse) {
     using MM = Mma<TT>;
     using vec = typename MM::vec;
     __shared__ __align__(16) double gl[2][kAnaBuf + 4];       // + a dummy slot for idle threads
@@ -460,10 +461,57 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
             gstore(gr, b + 1, (b + 1) & 1);
             __syncthreads();
         }
-        return;
+        if (!fuse) return;                                   // uniform
     }
 
     const int cb = coef_offset(g.T, m) - m;
+    if constexpr (MODE == kAnaForward) {
+        if (fuse) {
+            // Fused node update of the next sweep (the tendencies never leave the workgroup): the
+            // tendencies of this block's rows go to LDS as [row][state][field][part], then every
+            // (row, part, member) of the block is updated from them (node_update_part, the same
+            // arithmetic as the update kernel).  fuse = 1: the states are members (the step's
+            // first f_E, E_j = E_0 for every node); fuse = 2: state b M + j is node j of member b
+            // and a group of four states holds 4 / M whole members.
+            double* eb = reinterpret_cast<double*>(gl);          // 64 x 4 x 3 x 2 doubles
+            const int kk0 = task.z;
+            if (active) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int sl = 2 * t + (i >> 3);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double val = has_h ? (double)accP[t][r] + (double)accH[t][r] : (double)accP[t][r];
+                        const double right = __shfl_down(val, 2, 64);
+                        const int kk = kt + MM::row(r, q);
+                        if (kk >= np || sl >= nsg || kind == 2) continue;
+                        const int n = m + p + 2 * kk;
+                        const int field = kind == 0 ? 1 : (kind == 1 ? 2 : 0);
+                        const double res = kind == 1 ? val + nscale[n] * right : val;
+                        eb[(((kk - kk0) * 4 + sl) * 3 + field) * 2 + re] = res;
+                    }
+                }
+            }
+            __syncthreads();
+            const int Mn = fu.M;
+            const int nmem = fuse == 1 ? nsg : nsg / Mn;
+            const int bfirst = fuse == 1 ? s0 : s0 / Mn;
+            for (int it = tid; it < 128 * nmem; it += kBlock) {
+                const int row = (it >> 1) & 63, c = it & 1, k = it >> 7;
+                const int kk = kk0 + row;
+                if (kk >= np) continue;
+                const int idx = cb + m + p + 2 * kk;
+                auto ep = [&](int j, int f) {
+                    const int sl = fuse == 1 ? k : k * Mn + j;
+                    return eb[((row * 4 + sl) * 3 + f) * 2 + c];
+                };
+                if (Mn == 1) node_update_part<1>(fu, idx, c, bfirst + k, ep);
+                else if (Mn == 2) node_update_part<2>(fu, idx, c, bfirst + k, ep);
+                else node_update_part<4>(fu, idx, c, bfirst + k, ep);
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int s = s0 + 2 * t + (i >> 3);
@@ -495,26 +543,30 @@ template <int MODE, typename TT>
 static void launch_analysis_variant(const LegPlan& plan, unsigned grid, hipStream_t st, const TT* P,
                                     const TT* H, const long long* toff, const int4* tasks, int nwg,
                                     const void* Gv, int nstates, const double* nscale, double* out,
-                                    const Geom& g) {
+                                    const Geom& g, const UpdateArgs& fu, int fuse) {
     const TT* G = static_cast<const TT*>(Gv);      // the analysis input is stored in the table type
     if (plan.ana_depth == 2)
         k_analysis_swe<MODE, TT, 2><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg, plan.ana_interleave,
-                                                             G, nstates, nscale, out, g);
+                                                             G, nstates, nscale, out, g, fu, fuse);
     else
         k_analysis_swe<MODE, TT, 4><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg, plan.ana_interleave,
-                                                             G, nstates, nscale, out, g);
+                                                             G, nstates, nscale, out, g, fu, fuse);
 }
 
 void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
                          const int4* tasks, int nwg, const double* G, int nstates,
-                         const double* neg_lap, double* out, const Geom& g, hipStream_t st) {
+                         const double* neg_lap, double* out, const Geom& g, hipStream_t st,
+                         const UpdateArgs* fuse, int fuse_mode) {
     const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
+    const UpdateArgs none{};
+    const UpdateArgs& fu = fuse ? *fuse : none;
+    const int mode = fuse ? fuse_mode : 0;
     if (tb.P32)
         launch_analysis_variant<kAnaForward, float>(plan, grid, st, tb.P32, tb.H32, toff, tasks, nwg, G,
-                                                    nstates, neg_lap, out, g);
+                                                    nstates, neg_lap, out, g, fu, mode);
     else
         launch_analysis_variant<kAnaForward, double>(plan, grid, st, tb.P, tb.H, toff, tasks, nwg, G,
-                                                     nstates, neg_lap, out, g);
+                                                     nstates, neg_lap, out, g, fu, mode);
 }
 
 void launch_analysis_adjoint(const Tables& tb, const LegPlan& plan, const long long* toff,
@@ -523,10 +575,10 @@ void launch_analysis_adjoint(const Tables& tb, const LegPlan& plan, const long l
     const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
     if (tb.P32)
         launch_analysis_variant<kAnaAdjoint, float>(plan, grid, st, tb.P32, tb.H32, toff, tasks, nwg, G,
-                                                    nstates, inv_lap, out_acc, g);
+                                                    nstates, inv_lap, out_acc, g, UpdateArgs{}, 0);
     else
         launch_analysis_variant<kAnaAdjoint, double>(plan, grid, st, tb.P, tb.H, toff, tasks, nwg, G,
-                                                     nstates, inv_lap, out_acc, g);
+                                                     nstates, inv_lap, out_acc, g, UpdateArgs{}, 0);
 }
 
 // FP32 copies of the FP64 tables (same layout), for the FP32 precision mode.

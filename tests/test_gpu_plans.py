@@ -11,11 +11,11 @@ import pytest
 import workloads as W
 from paper_2403_20135_amd import _lib
 
-from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, rel_l2
+from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, _torch, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-DEFAULT = dict(syn_lat_tiles=2, syn_depth=2, ana_depth=2, ana_interleave=1)
+DEFAULT = dict(syn_lat_tiles=2, syn_depth=2, ana_depth=2, ana_interleave=1, fuse_update=1)
 VARIANTS = [(1, 8, 4, 1), (1, 4, 4, 1), (2, 4, 4, 1), (2, 2, 4, 1), (3, 2, 4, 1), (4, 2, 4, 1),
             (4, 1, 4, 1), (6, 1, 4, 1), (1, 8, 2, 1), (1, 8, 4, 0), (2, 4, 2, 0)]
 
@@ -52,7 +52,7 @@ def test_variants_agree_bitwise(T, nlat, nlon, batch, prec):
 def test_set_plan_rejects_variants_not_built():
     sdc = _sdc(21, 34, 64, 2, 2, 1)
     for bad in [(2, 8, 4, 1), (4, 4, 4, 1), (3, 4, 4, 1), (5, 2, 4, 1), (6, 2, 4, 1), (1, 6, 4, 1),
-                (1, 8, 3, 1), (1, 8, 4, 2)]:
+                (1, 8, 3, 1), (1, 8, 4, 2), (2, 2, 2, 1, 2)]:
         with pytest.raises(_lib.SDCError) as ei:
             sdc.set_plan(*bad)
         assert ei.value.code == _lib.SDC_EINVAL
@@ -81,3 +81,43 @@ def test_autotune_keeps_results_and_graphs():
     assert err <= 1e-11
     with pytest.raises(_lib.SDCError):
         sdc.autotune(0)
+
+
+@pytest.mark.parametrize("T,nlat,nlon,M,K,batch,prec,qd", [
+    (31, 48, 96, 4, 3, 2, "fp64", "flex"),
+    (21, 34, 64, 2, 4, 3, "fp64", "ns"),      # ragged tile, K > M, MIN-SR-NS, odd member count
+    (31, 48, 96, 1, 2, 5, "fp32", "flex"),    # one node: every state of a group is a member
+    (63, 96, 192, 4, 1, 1, "fp64", "flex"),   # one sweep: the first f_E's analysis writes the state
+    (31, 48, 96, 3, 3, 2, "fp64", "flex"),    # M = 3: the separate update kernel either way
+])
+def test_fused_update_is_bitwise_the_separate_one(T, nlat, nlon, M, K, batch, prec, qd):
+    """The node update inside the analysis epilogue gives bitwise the same steps (eager and graph),
+    taped steps and adjoints (whose recomputation uses the fused forward) as the update kernel."""
+    from paper_2403_20135_amd.api import SDC
+    torch = _torch()
+    sdc = SDC(T, nlat, nlon, M, K, batch, prec, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, qdelta=qd)
+    x0 = _states(T, batch, 701)
+    lam = np.stack([W.random_state(T, 702 + b) for b in range(batch)])
+    lam[..., :T + 1, 1] = 0.0
+    dt = 600.0
+    res = {}
+    for fuse in (1, 0):
+        sdc.set_plan(2, 2, 2, 1, fuse)
+        x, xg = _dev(x0), _dev(x0)
+        for _ in range(3):
+            sdc.step(x, dt)
+            sdc.step_graph(xg, dt)
+        tape = sdc.new_tape()
+        xt = _dev(x0)
+        sdc.step_taped(xt, dt, tape)
+        ga, gb = _dev(np.zeros_like(x0)), _dev(np.zeros_like(x0))
+        sdc.step_adjoint(_dev(x0), _dev(lam), ga, dt)
+        sdc.step_adjoint_taped(tape, _dev(lam), gb, dt)
+        sdc.sync()
+        torch.cuda.synchronize()
+        res[fuse] = [_host(v) for v in (x, xg, xt, ga, gb)]
+    for name, a, b in zip(("step", "graph step", "taped step", "adjoint", "taped adjoint"), res[1], res[0]):
+        print(f"[gpu] fused update T{T} M{M}K{K} x{batch} {prec} {name}: max |diff| {np.max(np.abs(a - b)):.3e}",
+              flush=True)
+        assert np.array_equal(a, b), name
+    assert np.array_equal(res[1][0], res[1][1])

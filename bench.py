@@ -69,7 +69,7 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_work(T, nlat, M, K, batch, precision):
+def algorithmic_work(T, nlat, M, K, batch, precision, fused=False):
     """Algorithmic work of every kernel class over one step: {class: (flops, bytes)}.
 
     Legendre: one scalar-equivalent complex transform with equatorial symmetry costs
@@ -85,6 +85,9 @@ def algorithmic_work(T, nlat, M, K, batch, precision):
     Update (bytes): per coefficient and member, reads u_n (3 complex), per node j the Phi', delta
     of u_j (2) and E_j (3), writes the updated nodes (3 each) and their synthesis-layout copy
     (4 each); the last sweep writes node M only; the first f_E of a step converts u_n (3 -> 4).
+    fused (the node update inside the analysis epilogue, M in {1, 2, 4}): the tendencies never
+    reach HBM, so the analysis loses its spectral output and gains the update's other bytes, and
+    the update class keeps only the conversion of u_n.
     """
     ncoef = (T + 1) * (T + 2) // 2
     transform = 2.0 * ncoef * nlat
@@ -96,6 +99,10 @@ def algorithmic_work(T, nlat, M, K, batch, precision):
     ana_bytes = tables + states * (7 * col * nlat * (T + 1) + 3 * 16.0 * ncoef)
     grid_bytes = (4 * 16.0 + 5 * col) * nlat * (T + 1) * states
     upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + 7)
+    if fused:
+        ana_bytes += batch * ncoef * 16.0 * ((K - 1) * (3 + 9 * M) + (3 + 2 * M + 3)) \
+            - states * 3 * 16.0 * ncoef
+        upd_bytes = batch * ncoef * 16.0 * 7
     return {"synthesis": (6 * transform * states, syn_bytes),
             "analysis": (7 * transform * states, ana_bytes),
             "grid": (0.0, grid_bytes), "update": (0.0, upd_bytes)}
@@ -165,10 +172,11 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
         sdc.sync()
         kt = sdc.timing_read()
         sdc.timing(False)
-        work = algorithmic_work(mb.T, mb.nlat, wl.M, wl.K, batch, precision)
+        fused = bool(plan["fuse_update"]) and wl.M in (1, 2, 4)
+        work = algorithmic_work(mb.T, mb.nlat, wl.M, wl.K, batch, precision, fused)
         out["kernels"] = {name: roofline_entry(work[name][0] * steps, work[name][1] * steps, ms / 1e3,
                                                launches, precision)
-                          for name, (ms, launches) in kt.items()}
+                          for name, (ms, launches) in kt.items() if launches > 0}
         out["kernel_ms"] = {name: ms for name, (ms, _) in kt.items()}
 
     if not with_adjoint:

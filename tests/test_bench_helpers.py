@@ -24,6 +24,13 @@ def test_algorithmic_work_counts():
     w4 = bench.algorithmic_work(T, nlat, M, K, 4, "fp64")
     assert w4["synthesis"][0] == pytest.approx(4 * w["synthesis"][0])
     assert w4["synthesis"][1] < 4 * w["synthesis"][1]
+    # fused update: the tendencies (written by the analysis, read M times per sweep by the update)
+    # leave the count; every other byte moves from the update class to the analysis
+    wf = bench.algorithmic_work(T, nlat, M, K, 1, "fp64", fused=True)
+    e_bytes = 16.0 * ncoef * (3 * states + 3 * M * K)
+    assert wf["analysis"][1] + wf["update"][1] == pytest.approx(w["analysis"][1] + w["update"][1] - e_bytes)
+    assert wf["update"][1] == pytest.approx(7 * 16.0 * ncoef)
+    assert wf["synthesis"] == w["synthesis"] and wf["grid"] == w["grid"]
 
 
 def test_roofline_entry_picks_the_smaller_ceiling():

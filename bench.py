@@ -69,7 +69,7 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_work(T, nlat, M, K, batch, precision, fused=False):
+def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=False):
     """Algorithmic work of every kernel class over one step: {class: (flops, bytes)}.
 
     Legendre: one scalar-equivalent complex transform with equatorial symmetry costs
@@ -88,6 +88,9 @@ def algorithmic_work(T, nlat, M, K, batch, precision, fused=False):
     fused (the node update inside the analysis epilogue, M in {1, 2, 4}): the tendencies never
     reach HBM, so the analysis loses its spectral output and gains the update's other bytes, and
     the update class keeps only the conversion of u_n.
+    syn_recur (the synthesis regenerates its tables): the synthesis reads the recurrence
+    coefficients (4 FP64 per (m, n), n < T + 16) and the sectoral values (FP64 per m and northern
+    latitude) instead of the tables.
     """
     ncoef = (T + 1) * (T + 2) // 2
     transform = 2.0 * ncoef * nlat
@@ -95,7 +98,11 @@ def algorithmic_work(T, nlat, M, K, batch, precision, fused=False):
     launches = K                                 # Legendre launches per step (one per sweep + first)
     tables = 2.0 * ncoef * (nlat // 2) * TABLE_BYTES[precision] * launches
     col = 2.0 * TABLE_BYTES[precision]          # coefficient columns are stored in the table type
-    syn_bytes = tables + states * (4 * col * ncoef + 4 * 16.0 * nlat * (T + 1))
+    syn_tables = tables
+    if syn_recur:
+        nhp = (nlat // 2 + 15) // 16 * 16
+        syn_tables = (32.0 * (T + 1) * (T + 16) + 8.0 * (T + 1) * nhp) * launches
+    syn_bytes = syn_tables + states * (4 * col * ncoef + 4 * 16.0 * nlat * (T + 1))
     ana_bytes = tables + states * (7 * col * nlat * (T + 1) + 3 * 16.0 * ncoef)
     grid_bytes = (4 * 16.0 + 5 * col) * nlat * (T + 1) * states
     upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + 7)
@@ -173,7 +180,8 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
         kt = sdc.timing_read()
         sdc.timing(False)
         fused = bool(plan["fuse_update"]) and wl.M in (1, 2, 4)
-        work = algorithmic_work(mb.T, mb.nlat, wl.M, wl.K, batch, precision, fused)
+        work = algorithmic_work(mb.T, mb.nlat, wl.M, wl.K, batch, precision, fused,
+                                bool(plan["syn_recur"]))
         out["kernels"] = {name: roofline_entry(work[name][0] * steps, work[name][1] * steps, ms / 1e3,
                                                launches, precision)
                           for name, (ms, launches) in kt.items() if launches > 0}
@@ -440,7 +448,8 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
         raise RuntimeError(f"the counter runs tuned different Legendre variants: {plans}")
     plan = plans[0]
     # forward FP64 kernels of the bench workload (names as rocprofv3 prints them)
-    classes = {f"void k_synthesis<0, double, {plan['syn_lat_tiles']}, {plan['syn_depth']}>": "synthesis",
+    rec = "true" if plan.get("syn_recur") else "false"
+    classes = {f"void k_synthesis<0, double, {plan['syn_lat_tiles']}, {plan['syn_depth']}, {rec}>": "synthesis",
                f"void k_analysis_swe<0, double, {plan['ana_depth']}>": "analysis",
                "void k_grid_swe<": "grid", "void k_update<": "update"}
 

@@ -229,13 +229,20 @@ typedef struct {
                           the analysis kernel's epilogue, from tendencies that never leave its
                           workgroups (same arithmetic, bitwise the same states); 0: separate
                           update kernel.  Not changed by the autotuner. */
+    int syn_recur;     /* 1: the synthesis regenerates Pbar_n^m and H_n^m in registers by the
+                          upward three-term recurrence in n (Section 3.2 transforms; coefficients
+                          and sectoral values precomputed at init, the same evaluation as the
+                          stored tables, so the same results bit for bit) and reads only the
+                          coefficient columns from HBM; 0: it reads the stored tables.  Built
+                          for syn_lat_tiles 1, 2 and 4 (with their depths).  Chosen by the
+                          autotuner with the synthesis shape. */
 } sdc_plan;
 
 /* The handle's current variants. */
 int sdc_get_plan(sdc_handle h, sdc_plan* plan);
 
 /* Select variants; SDC_EINVAL for a combination that is not built (the handle keeps its plan).
- * fuse_update must be 0 or 1.  Graphs cached by sdc_step_graph are dropped and recaptured on
+ * fuse_update and syn_recur must be 0 or 1.  Graphs cached by sdc_step_graph are dropped and recaptured on
  * their next call. */
 int sdc_set_plan(sdc_handle h, const sdc_plan* plan);
 

@@ -148,6 +148,7 @@ struct sdc_ctx {
     std::vector<void*> allocs;
     long long bytes = 0, table_bytes = 0;
     double *mu = nullptr, *w = nullptr, *P = nullptr, *H = nullptr, *tau = nullptr, *Q = nullptr;
+    double *rc = nullptr, *sect = nullptr;  // Legendre recurrence coefficients, sectoral values
     float *P32 = nullptr, *H32 = nullptr;   // FP32 copies of the tables (precision SDC_FP32_MFMA)
     double *inv_lap = nullptr, *neg_lap = nullptr;
     long long* toff = nullptr;
@@ -248,7 +249,7 @@ struct sdc_ctx {
         for (auto& v : ev_marks) v.clear();
     }
 
-    Tables tables() const { return Tables{P, H, P32, H32}; }
+    Tables tables() const { return Tables{P, H, P32, H32, rc, sect, mu}; }
 
     template <typename T>
     int alloc(T*& p, size_t count, bool table = false) {
@@ -338,6 +339,8 @@ int setup(sdc_ctx* c) {
     if ((rc = c->alloc(c->w, g.nlat))) return rc;
     if ((rc = c->alloc(c->P, tot, true))) return rc;
     if ((rc = c->alloc(c->H, tot, true))) return rc;
+    if ((rc = c->alloc(c->rc, (size_t)4 * (g.T + 1) * (g.T + kRecPad)))) return rc;
+    if ((rc = c->alloc(c->sect, (size_t)(g.T + 1) * g.nhp))) return rc;
     if ((rc = c->alloc(c->toff, c->h_toff.size()))) return rc;
     if ((rc = c->alloc(c->rowoff, h_rowoff.size()))) return rc;
     if ((rc = c->alloc(c->n_of, g.ncoef))) return rc;
@@ -424,7 +427,8 @@ int setup(sdc_ctx* c) {
 
     // FP64 setup kernels
     launch_gauss(c->mu, c->w, g.nlat, c->st);
-    launch_legendre_tables(c->mu, c->P, c->H, c->toff, g, c->st);
+    launch_rec_coefs(c->rc, g, c->st);
+    launch_legendre_tables(c->mu, c->rc, c->P, c->H, c->sect, c->toff, g, c->st);
     if (cf.precision == SDC_FP32_MFMA) {
         // FP32 copies of the FP64 tables for the Legendre contractions
         if ((rc = c->alloc(c->P32, tot, true))) return rc;
@@ -573,6 +577,7 @@ int sdc_get_plan(sdc_handle h, sdc_plan* plan) {
     plan->ana_depth = h->lplan.ana_depth;
     plan->ana_interleave = h->lplan.ana_interleave;
     plan->fuse_update = h->lplan.fuse_update;
+    plan->syn_recur = h->lplan.syn_recur;
     return SDC_OK;
 }
 
@@ -581,12 +586,16 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
     if (!plan) return fail(SDC_EINVAL, "plan is NULL");
     if (plan->fuse_update != 0 && plan->fuse_update != 1)
         return fail(SDC_EINVAL, "fuse_update=%d: 0 or 1", plan->fuse_update);
+    if (plan->syn_recur != 0 && plan->syn_recur != 1)
+        return fail(SDC_EINVAL, "syn_recur=%d: 0 or 1", plan->syn_recur);
     const int jt = plan->syn_lat_tiles, d = plan->syn_depth;
     const bool syn_ok = (jt == 1 && (d == 8 || d == 4)) || (jt == 2 && (d == 4 || d == 2)) ||
                         (jt == 3 && d == 2) || (jt == 4 && (d == 2 || d == 1)) || (jt == 6 && d == 1);
     if (!syn_ok)
         return fail(SDC_EINVAL, "synthesis variant (%d tiles, depth %d) not built: use (1, 8), (1, 4), (2, 4), "
                     "(2, 2), (3, 2), (4, 2), (4, 1) or (6, 1)", jt, d);
+    if (plan->syn_recur && (jt == 3 || jt == 6))
+        return fail(SDC_EINVAL, "the regenerating synthesis (syn_recur) is built for 1, 2 or 4 latitude tiles");
     if ((plan->ana_depth != 2 && plan->ana_depth != 4) || (plan->ana_interleave != 0 && plan->ana_interleave != 1))
         return fail(SDC_EINVAL, "analysis variant (depth %d, interleave %d) not built: depth 2 or 4, interleave 0 or 1",
                     plan->ana_depth, plan->ana_interleave);
@@ -595,6 +604,7 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
     h->lplan.ana_depth = plan->ana_depth;
     h->lplan.ana_interleave = plan->ana_interleave;
     h->lplan.fuse_update = plan->fuse_update;
+    h->lplan.syn_recur = plan->syn_recur;
     h->drop_graphs();                 // recaptured with the new variants on their next replay
     return SDC_OK;
 }
@@ -629,10 +639,24 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
     // and near-ties do not flip the choice)
     constexpr float kMargin = 0.95f;
     const LegPlan saved = c->lplan;
-    constexpr int kSyn = 8;
-    const LegPlan syn_cands[kSyn] = {{1, 8, 4, 1}, {1, 4, 4, 1}, {2, 4, 4, 1}, {2, 2, 4, 1},
-                                     {3, 2, 4, 1}, {4, 2, 4, 1}, {4, 1, 4, 1}, {6, 1, 4, 1}};
-    const LegPlan ana_cands[4] = {{1, 8, 4, 1}, {1, 8, 4, 0}, {1, 8, 2, 1}, {1, 8, 2, 0}};
+    // synthesis: every (tiles, depth, regenerate) variant built
+    constexpr int kSyn = 14;
+    const int shapes[kSyn][3] = {{1, 8, 0}, {1, 4, 0}, {2, 4, 0}, {2, 2, 0}, {3, 2, 0},
+                                 {4, 2, 0}, {4, 1, 0}, {6, 1, 0}, {1, 8, 1}, {1, 4, 1},
+                                 {2, 4, 1}, {2, 2, 1}, {4, 2, 1}, {4, 1, 1}};
+    LegPlan syn_cands[kSyn];
+    for (int k = 0; k < kSyn; ++k) {
+        syn_cands[k] = saved;
+        syn_cands[k].syn_tiles = shapes[k][0];
+        syn_cands[k].syn_depth = shapes[k][1];
+        syn_cands[k].syn_recur = shapes[k][2];
+    }
+    LegPlan ana_cands[4];
+    for (int k = 0; k < 4; ++k) {
+        ana_cands[k] = saved;
+        ana_cands[k].ana_depth = k < 2 ? 4 : 2;
+        ana_cands[k].ana_interleave = (k & 1) ? 0 : 1;
+    }
     float syn_ms[kSyn] = {0.f}, ana_ms[4] = {0.f};
     hipError_t err = hipSuccess;
     for (int k = 0; k < kSyn && err == hipSuccess; ++k) {
@@ -653,12 +677,15 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
     if (err == hipSuccess) {
         int cur = 0, fast = 0;
         for (int k = 0; k < kSyn; ++k) {
-            if (syn_cands[k].syn_tiles == saved.syn_tiles && syn_cands[k].syn_depth == saved.syn_depth) cur = k;
+            if (syn_cands[k].syn_tiles == saved.syn_tiles && syn_cands[k].syn_depth == saved.syn_depth &&
+                syn_cands[k].syn_recur == saved.syn_recur)
+                cur = k;
             if (syn_ms[k] < syn_ms[fast]) fast = k;
         }
         if (syn_ms[fast] < kMargin * syn_ms[cur]) {
             best.syn_tiles = syn_cands[fast].syn_tiles;
             best.syn_depth = syn_cands[fast].syn_depth;
+            best.syn_recur = syn_cands[fast].syn_recur;
         }
         cur = 0;
         fast = 0;
@@ -686,6 +713,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         chosen->ana_depth = best.ana_depth;
         chosen->ana_interleave = best.ana_interleave;
         chosen->fuse_update = best.fuse_update;
+        chosen->syn_recur = best.syn_recur;
     }
     return SDC_OK;
 }

@@ -80,7 +80,28 @@ __device__ inline int2 xcd_task_group(int ntasks, int ngroups, int interleave) {
 struct LegPlan {
     int syn_tiles = 2, syn_depth = 2, ana_depth = 2, ana_interleave = 1;
     int fuse_update = 1;       // node updates inside the analysis (M in {1, 2, 4})
+    int syn_recur = 0;         // synthesis regenerates Pbar, H in registers instead of reading them
 };
+
+// Upward recurrence of the orthonormal associated Legendre functions in n at fixed m and mu (the
+// three-term relation with eps_n = sqrt((n^2 - m^2) / (4 n^2 - 1))):
+//   Pbar_{n+1} = a_n mu Pbar_n - b_n Pbar_{n-1},   a_n = 1 / eps_{n+1},  b_n = eps_n / eps_{n+1},
+//   H_n = c_n Pbar_{n-1} - d_n Pbar_{n+1},          c_n = (n + 1) eps_n,  d_n = n eps_{n+1},
+// started from Pbar_{m-1} = 0 and the sectoral Pbar_m^m.  The table generator and the synthesis
+// that regenerates the tables evaluate it with these two functions and the same stored
+// coefficients, so both produce the same values bit for bit.
+// Coefficients: rc[4 rec_index(T, m, n) + {0, 1, 2, 3}] = (a_n, b_n, c_n, d_n) for
+// n = m .. T + kRecPad - 1 (rows past T feed the padding rows of the last 4-row steps).
+constexpr int kRecPad = 16;
+__host__ __device__ inline size_t rec_index(int T, int m, int n) {
+    return (size_t)m * (T + kRecPad) + (n - m);
+}
+__device__ __forceinline__ double leg_next(double mu, double p, double pm1, double a, double b) {
+    return fma(a * mu, p, -(b * pm1));
+}
+__device__ __forceinline__ double leg_h(double pm1, double pp1, double c, double d) {
+    return fma(c, pm1, -(d * pp1));
+}
 
 // Synthesis input ("coefficient-major", written by the update/prep kernels): for table row
 // (m, p, kk) and state s, 8 doubles (zeta, Phi', psi, chi) x (Re, Im) with psi, chi the inverse
@@ -136,8 +157,11 @@ __host__ __device__ inline size_t ana_index(int T, int S, int jh, int m, int p, 
 // ---------------------------------------------------------------------------------------------
 // setup.hip
 void launch_gauss(double* mu, double* w, int nlat, hipStream_t st);
-void launch_legendre_tables(const double* mu, double* P, double* H, const long long* toff,
-                            const Geom& g, hipStream_t st);
+// Recurrence coefficients (rec_index layout), then the tables and the sectoral values
+// sect[m * nhp + jh] = Pbar_m^m(mu_jh) (zero on the padding latitudes jh >= nh).
+void launch_rec_coefs(double* rc, const Geom& g, hipStream_t st);
+void launch_legendre_tables(const double* mu, const double* rc, double* P, double* H, double* sect,
+                            const long long* toff, const Geom& g, hipStream_t st);
 void launch_collocation(double* tau, double* Q, int Mmax, hipStream_t st);
 void launch_degree_tables(int* n_of, int* m_of, double* inv_lap, double* neg_lap, int T,
                           double radius, hipStream_t st);
@@ -150,6 +174,9 @@ struct Tables {
     const double* H;
     const float* P32;
     const float* H32;
+    const double* rc;        // recurrence coefficients and sectoral values for the synthesis
+    const double* sect;      // that regenerates the tables (LegPlan::syn_recur)
+    const double* mu;
 };
 // Synthesis tasks: (m, latitude tile) per workgroup, XCD-ordered; x < 0 = pad.
 void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,

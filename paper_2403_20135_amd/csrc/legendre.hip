@@ -100,11 +100,54 @@ constexpr int kSynBlock = 128;                   // two waves: the two parities
 // JT latitude tiles per workgroup share every coefficient column they load; D operand stages are
 // in flight per wave.  Task (m, jt0) covers tiles jt0 .. jt0 + JT - 1 (tiles past the last one
 // re-read it and store nothing).
-template <int MODE, typename TT, int JT, int D>
+//
+// REC (JT = 1, 2 or 4 latitude tiles per wave): the table operands are not read but regenerated
+// in registers by the upward recurrence in n (leg_next / leg_h with the stored coefficients, the
+// same evaluation as the table generator, hence the same values bit for bit), so only the
+// coefficient columns stream from HBM.  Lane (i, q) of wave p runs the recurrence for latitude i
+// of tile q % JT through all degrees (both parities: each value needs the two before it; the
+// coefficients are wave-uniform scalar loads, issued a step ahead) and forms Pbar_n, H_n of the
+// step's four rows n = m + p + 2 (4 j + k) in registers k = 0..3.  The MFMA slot of lane (i, q)
+// for tile u takes row q of tile u, i.e. register q of lane (i, u): a 4 x 4 transpose between
+// registers and lane groups, done by one row-pair swap (v_permlane32_swap) and one row swap
+// (v_permlane16_swap); with JT < 4 the lane groups past JT repeat the first ones.
+__device__ __forceinline__ void swap_rows32(unsigned& a, unsigned& b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);   // rows 2,3 of a <-> rows 0,1 of b
+    a = r[0];
+    b = r[1];
+}
+__device__ __forceinline__ void swap_rows16(unsigned& a, unsigned& b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);   // odd rows of a <-> even rows of b
+    a = r[0];
+    b = r[1];
+}
+// v[u] at lane group q becomes v[q] at lane group u (rows are 16-lane groups)
+__device__ __forceinline__ void transpose_rows4(double (&v)[4]) {
+    unsigned lo[4], hi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lo[k] = (unsigned)__double_as_longlong(v[k]);
+        hi[k] = (unsigned)((unsigned long long)__double_as_longlong(v[k]) >> 32);
+    }
+    swap_rows32(lo[0], lo[2]);
+    swap_rows32(lo[1], lo[3]);
+    swap_rows32(hi[0], hi[2]);
+    swap_rows32(hi[1], hi[3]);
+    swap_rows16(lo[0], lo[1]);
+    swap_rows16(lo[2], lo[3]);
+    swap_rows16(hi[0], hi[1]);
+    swap_rows16(hi[2], hi[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        v[k] = __longlong_as_double((long long)(((unsigned long long)hi[k] << 32) | lo[k]));
+}
+
+template <int MODE, typename TT, int JT, int D, bool REC>
 __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int* __restrict__ rowoff, const int2* __restrict__ tasks, const TT* __restrict__ cml,
-    int nstates, double* __restrict__ four, Geom g) {
+    int nstates, double* __restrict__ four, Geom g, const double* __restrict__ rc,
+    const double* __restrict__ sect, const double* __restrict__ mu) {
     using TL = SynTiles<MODE>;
     using MM = Mma<TT>;
     constexpr int NT = TL::NT;
@@ -117,6 +160,33 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // parity of this wave
     const int m = task.x, jt0 = task.y, ntj = g.nhp >> 4;
     const int lane = threadIdx.x & 63, i = lane & 15, q = lane >> 4, v = i & 3;
+    // REC state of this lane's latitude (tile q): mu, Pbar_{n-1}, Pbar_n at the step's first row
+    // n = m + p + 8 j, and the coefficients of that row
+    static_assert(!REC || JT == 1 || JT == 2 || JT == 4, "regenerating synthesis: 1, 2 or 4 tiles");
+    double rx = 0.0, rpm1 = 0.0, rp0 = 0.0;
+    const double* rcrow = rc + 4 * rec_index(g.T, m, m + p);
+    double rcs[24];                                          // the next step's coefficients
+    auto load_coefs = [&]() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int e = 0; e < 6; ++e) rcs[6 * k + e] = rcrow[8 * k + e];   // wave-uniform
+        rcrow += 32;
+    };
+    if constexpr (REC) {
+        load_coefs();
+        const int tq = jt0 + q % JT;
+        const int jh = (tq < ntj ? tq : ntj - 1) * 16 + i;
+        rx = jh < g.nh ? mu[jh] : 0.0;
+        const double pmm = sect[(size_t)m * g.nhp + jh];
+        if (p == 0) {
+            rp0 = pmm;
+        } else {                                             // one degree up: Pbar_m, Pbar_{m+1}
+            const double* c0 = rc + 4 * rec_index(g.T, m, m);
+            rpm1 = pmm;
+            rp0 = leg_next(rx, pmm, 0.0, c0[0], c0[1]);
+        }
+    }
     const int S = nstates;
     const int s = blockIdx.y * 4 + (i >> 2);
     const int sc = s < S ? s : S - 1;
@@ -146,21 +216,53 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
         for (int t = 0; t < NT; ++t) acc[u][t] = MM::zero();
     auto load = [&](SynStage<TT, NT, JT>& x, int j) {
         const unsigned oc = clane + (unsigned)j * cstep;
+        if constexpr (!REC) {
 #pragma unroll
-        for (int u = 0; u < JT; ++u) {
-            const unsigned ot = tlane[u] + (unsigned)j * tstep;
-            x.a[u][0] = ldt(tP, ot);
-            x.a[u][1] = ldt(tH, ot);
+            for (int u = 0; u < JT; ++u) {
+                const unsigned ot = tlane[u] + (unsigned)j * tstep;
+                x.a[u][0] = ldt(tP, ot);
+                x.a[u][1] = ldt(tH, ot);
+            }
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) x.b[t] = ldt(cb, oc + boff[t]);
     };
-    auto compute = [&](const SynStage<TT, NT, JT>& x) {
+    auto mma_all = [&](const TT (&a)[JT][2], const TT (&b)[NT]) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const TT bt = x.b[t];
 #pragma unroll
-            for (int u = 0; u < JT; ++u) acc[u][t] = MM::mma(x.a[u][TL::is_h(t) ? 1 : 0], bt, acc[u][t]);
+            for (int u = 0; u < JT; ++u) acc[u][t] = MM::mma(a[u][TL::is_h(t) ? 1 : 0], b[t], acc[u][t]);
+        }
+    };
+    // REC: the eight degrees of the next step (row k of the step is degree 2k), then the transpose
+    // (the following step's coefficients are requested as soon as these are used)
+    auto generate = [&](TT (&a)[JT][2]) {
+        double vp[4], vh[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double* ck = rcs + 6 * k;
+            const double p1 = leg_next(rx, rp0, rpm1, ck[0], ck[1]);
+            vp[k] = rp0;
+            vh[k] = leg_h(rpm1, p1, ck[2], ck[3]);
+            rpm1 = p1;
+            rp0 = leg_next(rx, p1, vp[k], ck[4], ck[5]);
+        }
+        load_coefs();
+        transpose_rows4(vp);
+        transpose_rows4(vh);
+#pragma unroll
+        for (int u = 0; u < JT; ++u) {
+            a[u][0] = (TT)vp[u];
+            a[u][1] = (TT)vh[u];
+        }
+    };
+    auto compute = [&](const SynStage<TT, NT, JT>& x) {
+        if constexpr (REC) {
+            TT ga[JT][2];
+            generate(ga);
+            mma_all(ga, x.b);
+        } else {
+            mma_all(x.a, x.b);
         }
     };
     // Loads past the chain's end re-read its last step (cache hits, results unused): a
@@ -231,15 +333,28 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
 }
 
 // Synthesis variants (latitude tiles per workgroup, stages in flight): (1, 8), (1, 4), (2, 4),
-// (2, 2), (3, 2), (4, 2), (4, 1), (6, 1).
+// (2, 2), (3, 2), (4, 2), (4, 1), (6, 1) reading the tables; all but (3, 2) and (6, 1) also
+// regenerating them.
 template <int MODE, typename TT>
-static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t st, const TT* P,
-                                     const TT* H, const long long* toff, const int* rowoff,
-                                     const int2* tasks, const double* cml, int nstates,
-                                     double* four, const Geom& g) {
+static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t st,
+                                     const Tables& tb, const TT* P, const TT* H,
+                                     const long long* toff, const int* rowoff, const int2* tasks,
+                                     const double* cml, int nstates, double* four, const Geom& g) {
     const TT* cmlt = reinterpret_cast<const TT*>(cml);    // stored in the table type
-#define SYN(JT, D) k_synthesis<MODE, TT, JT, D><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cmlt, nstates, four, g)
-    if (plan.syn_tiles == 6) SYN(6, 1);
+#define SYN(JT, D)                                                                                  \
+    k_synthesis<MODE, TT, JT, D, false><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cmlt, \
+                                                                   nstates, four, g, tb.rc, tb.sect, tb.mu)
+#define SYN_REC(JT, D)                                                                              \
+    k_synthesis<MODE, TT, JT, D, true><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cmlt, \
+                                                                  nstates, four, g, tb.rc, tb.sect, tb.mu)
+    if (plan.syn_recur) {
+        if (plan.syn_tiles == 4 && plan.syn_depth == 1) SYN_REC(4, 1);
+        else if (plan.syn_tiles == 4) SYN_REC(4, 2);
+        else if (plan.syn_tiles == 2 && plan.syn_depth == 2) SYN_REC(2, 2);
+        else if (plan.syn_tiles == 2) SYN_REC(2, 4);
+        else if (plan.syn_depth == 4) SYN_REC(1, 4);
+        else SYN_REC(1, 8);
+    } else if (plan.syn_tiles == 6) SYN(6, 1);
     else if (plan.syn_tiles == 4 && plan.syn_depth == 1) SYN(4, 1);
     else if (plan.syn_tiles == 4) SYN(4, 2);
     else if (plan.syn_tiles == 3) SYN(3, 2);
@@ -248,6 +363,7 @@ static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t
     else if (plan.syn_depth == 4) SYN(1, 4);
     else SYN(1, 8);
 #undef SYN
+#undef SYN_REC
 }
 
 void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
@@ -255,10 +371,10 @@ void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long
                           int nstates, double2* four, const Geom& g, hipStream_t st) {
     const dim3 grid(ntasks, (nstates + 3) / 4);
     if (tb.P32)
-        launch_synthesis_variant<kSynForward, float>(plan, grid, st, tb.P32, tb.H32, toff, rowoff,
+        launch_synthesis_variant<kSynForward, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, rowoff,
                                                      tasks, cml, nstates, (double*)four, g);
     else
-        launch_synthesis_variant<kSynForward, double>(plan, grid, st, tb.P, tb.H, toff, rowoff,
+        launch_synthesis_variant<kSynForward, double>(plan, grid, st, tb, tb.P, tb.H, toff, rowoff,
                                                       tasks, cml, nstates, (double*)four, g);
 }
 
@@ -267,10 +383,10 @@ void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long
                           int nstates, double2* four5, const Geom& g, hipStream_t st) {
     const dim3 grid(ntasks, (nstates + 3) / 4);
     if (tb.P32)
-        launch_synthesis_variant<kSynAdjoint, float>(plan, grid, st, tb.P32, tb.H32, toff, rowoff,
+        launch_synthesis_variant<kSynAdjoint, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, rowoff,
                                                      tasks, cml, nstates, (double*)four5, g);
     else
-        launch_synthesis_variant<kSynAdjoint, double>(plan, grid, st, tb.P, tb.H, toff, rowoff,
+        launch_synthesis_variant<kSynAdjoint, double>(plan, grid, st, tb, tb.P, tb.H, toff, rowoff,
                                                       tasks, cml, nstates, (double*)four5, g);
 }
 

@@ -50,11 +50,31 @@ __device__ inline double eps_nm(int n, int m) {
     return sqrt((nn * nn - mm * mm) / (4.0 * nn * nn - 1.0));
 }
 
-// One thread per (m, northern latitude): upward recurrence in n from Pbar_m^m, writing Pbar and
-// H for n = m..T into the parity-split packed layout (row n goes to parity (n-m)&1, row (n-m)>>1;
-// tile-major, tab_index).
-__global__ void k_legendre(const double* __restrict__ mu, double* __restrict__ P,
-                           double* __restrict__ H, const long long* __restrict__ toff, Geom g) {
+// One thread per (m, n): the recurrence coefficients of Pbar_n^m and H_n^m (rec_index layout).
+__global__ void k_rec_coefs(double* __restrict__ rc, Geom g) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    const int n = m + k;
+    if (m > g.T || n >= g.T + kRecPad) return;
+    const double e_n = eps_nm(n, m), e_n1 = eps_nm(n + 1, m);
+    double* c = rc + 4 * rec_index(g.T, m, n);
+    c[0] = 1.0 / e_n1;
+    c[1] = e_n / e_n1;
+    c[2] = (n + 1) * e_n;
+    c[3] = n * e_n1;
+}
+
+void launch_rec_coefs(double* rc, const Geom& g, hipStream_t st) {
+    dim3 grid((g.T + kRecPad + 63) / 64, g.T + 1);
+    k_rec_coefs<<<grid, 64, 0, st>>>(rc, g);
+}
+
+// One thread per (m, northern latitude): Pbar_m^m by its product formula, then the upward
+// recurrence in n (leg_next / leg_h), writing Pbar and H for n = m..T into the parity-split
+// packed layout (row n goes to parity (n-m)&1, row (n-m)>>1; tile-major, tab_index).
+__global__ void k_legendre(const double* __restrict__ mu, const double* __restrict__ rc,
+                           double* __restrict__ P, double* __restrict__ H,
+                           double* __restrict__ sect, const long long* __restrict__ toff, Geom g) {
     const int jh = blockIdx.x * blockDim.x + threadIdx.x;
     const int m = blockIdx.y;
     if (jh >= g.nh || m > g.T) return;
@@ -62,29 +82,24 @@ __global__ void k_legendre(const double* __restrict__ mu, double* __restrict__ P
     const double s = sqrt((1.0 - x) * (1.0 + x));
     double pmm = 0.70710678118654752440;   // Pbar_0^0 = 1/sqrt(2)
     for (int k = 1; k <= m; ++k) pmm *= sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
-    // p_prev = Pbar_{n-1}, p_cur = Pbar_n, p_next = Pbar_{n+1}
-    double p_prev = 0.0, p_cur = pmm;
-    double p_next = sqrt(2.0 * m + 3.0) * x * pmm;
+    sect[(size_t)m * g.nhp + jh] = pmm;
+    double pm1 = 0.0, p0 = pmm;            // Pbar_{n-1}, Pbar_n
     for (int n = m; n <= g.T; ++n) {
-        const double e_n = eps_nm(n, m), e_n1 = eps_nm(n + 1, m);
-        const double h = (n + 1) * e_n * p_prev - n * e_n1 * p_next;
+        const double* c = rc + 4 * rec_index(g.T, m, n);
+        const double p1 = leg_next(x, p0, pm1, c[0], c[1]);
         const int par = (n - m) & 1, kk = (n - m) >> 1;
         const long long idx = toff[2 * m + par] + tab_index((npk_of(g.T, m, par) + 3) & ~3, kk, jh);
-        P[idx] = p_cur;
-        H[idx] = h;
-        // advance: Pbar_{n+2} = (x Pbar_{n+1} - eps_{n+1} Pbar_n) / eps_{n+2}
-        const double e_n2 = eps_nm(n + 2, m);
-        const double p_nn = (x * p_next - e_n1 * p_cur) / e_n2;
-        p_prev = p_cur;
-        p_cur = p_next;
-        p_next = p_nn;
+        P[idx] = p0;
+        H[idx] = leg_h(pm1, p1, c[2], c[3]);
+        pm1 = p0;
+        p0 = p1;
     }
 }
 
-void launch_legendre_tables(const double* mu, double* P, double* H, const long long* toff,
-                            const Geom& g, hipStream_t st) {
+void launch_legendre_tables(const double* mu, const double* rc, double* P, double* H, double* sect,
+                            const long long* toff, const Geom& g, hipStream_t st) {
     dim3 grid((g.nh + 63) / 64, g.T + 1);
-    k_legendre<<<grid, 64, 0, st>>>(mu, P, H, toff, g);
+    k_legendre<<<grid, 64, 0, st>>>(mu, rc, P, H, sect, toff, g);
 }
 
 // Radau-right nodes for every node count Mc = 1..Mmax: the roots of P_Mc(x) - P_{Mc-1}(x) on

@@ -31,6 +31,11 @@ def test_algorithmic_work_counts():
     assert wf["analysis"][1] + wf["update"][1] == pytest.approx(w["analysis"][1] + w["update"][1] - e_bytes)
     assert wf["update"][1] == pytest.approx(7 * 16.0 * ncoef)
     assert wf["synthesis"] == w["synthesis"] and wf["grid"] == w["grid"]
+    # regenerated synthesis tables: same flops, the table bytes replaced by the small recurrence data
+    wr = bench.algorithmic_work(T, nlat, M, K, 1, "fp64", syn_recur=True)
+    assert wr["synthesis"][0] == w["synthesis"][0]
+    assert w["synthesis"][1] - wr["synthesis"][1] > 0.9 * tables
+    assert wr["analysis"] == w["analysis"]
 
 
 def test_roofline_entry_picks_the_smaller_ceiling():
@@ -53,7 +58,8 @@ def _csv(path, counter, rows):
 
 
 def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
-    plan = {"syn_lat_tiles": 2, "syn_depth": 2, "ana_depth": 2, "ana_interleave": 1}
+    plan = {"syn_lat_tiles": 2, "syn_depth": 2, "ana_depth": 2, "ana_interleave": 1, "fuse_update": 1,
+            "syn_recur": 1}
     logs = []
     for name in ("f.log", "w.log"):
         p = tmp_path / name
@@ -62,15 +68,16 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     copy_kib = 256 * 1024 / 2.0                                   # counter reads half the bytes
     _csv(tmp_path / "f.csv", "FETCH_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", copy_kib),
-        ("void k_synthesis<0, double, 2, 2>(double const*)", 1000.0),
-        ("void k_synthesis<0, double, 2, 2>(double const*)", 3000.0),
-        ("void k_synthesis<0, double, 1, 8>(double const*)", 99999.0),   # an autotuner trial
+        ("void k_synthesis<0, double, 2, 2, true>(double const*)", 1000.0),
+        ("void k_synthesis<0, double, 2, 2, true>(double const*)", 3000.0),
+        ("void k_synthesis<0, double, 1, 8, true>(double const*)", 99999.0),   # an autotuner trial
+        ("void k_synthesis<0, double, 2, 2, false>(double const*)", 77777.0),  # table-reading trial
         ("void k_analysis_swe<0, double, 2>(double const*)", 500.0),
         ("void k_grid_swe<768, double>(x)", 10.0),
         ("void k_update<4>(UpdateArgs)", 20.0)])
     _csv(tmp_path / "w.csv", "WRITE_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", 256 * 1024.0),
-        ("void k_synthesis<0, double, 2, 2>(double const*)", 100.0),
+        ("void k_synthesis<0, double, 2, 2, true>(double const*)", 100.0),
         ("void k_analysis_swe<0, double, 2>(double const*)", 50.0),
         ("void k_grid_swe<768, double>(x)", 40.0),
         ("void k_update<4>(UpdateArgs)", 30.0)])
@@ -79,7 +86,7 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     t = json.loads(out.read_text())
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
     syn = t["kernels"]["synthesis"]
-    assert syn["kernel_name"] == "void k_synthesis<0, double, 2, 2>"
+    assert syn["kernel_name"] == "void k_synthesis<0, double, 2, 2, true>"
     assert syn["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
     assert syn["write_bytes_per_launch"] == pytest.approx(100.0 * 1024)
     assert set(t["kernels"]) == {"synthesis", "analysis", "grid", "update"}

@@ -236,13 +236,17 @@ typedef struct {
                           coefficient columns from HBM; 0: it reads the stored tables.  Built
                           for syn_lat_tiles 1, 2 and 4 (with their depths).  Chosen by the
                           autotuner with the synthesis shape. */
+    int ana_recur;     /* 1: the analysis reads two stored Pbar values per latitude and four
+                          rows and regenerates the table entries of those rows by the same
+                          recurrence (a quarter of the table bytes; the same results bit for
+                          bit); 0: it streams the tables.  Chosen by the autotuner. */
 } sdc_plan;
 
 /* The handle's current variants. */
 int sdc_get_plan(sdc_handle h, sdc_plan* plan);
 
 /* Select variants; SDC_EINVAL for a combination that is not built (the handle keeps its plan).
- * fuse_update and syn_recur must be 0 or 1.  Graphs cached by sdc_step_graph are dropped and recaptured on
+ * fuse_update, syn_recur and ana_recur must be 0 or 1.  Graphs cached by sdc_step_graph are dropped and recaptured on
  * their next call. */
 int sdc_set_plan(sdc_handle h, const sdc_plan* plan);
 

@@ -578,6 +578,7 @@ int sdc_get_plan(sdc_handle h, sdc_plan* plan) {
     plan->ana_interleave = h->lplan.ana_interleave;
     plan->fuse_update = h->lplan.fuse_update;
     plan->syn_recur = h->lplan.syn_recur;
+    plan->ana_recur = h->lplan.ana_recur;
     return SDC_OK;
 }
 
@@ -588,6 +589,8 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
         return fail(SDC_EINVAL, "fuse_update=%d: 0 or 1", plan->fuse_update);
     if (plan->syn_recur != 0 && plan->syn_recur != 1)
         return fail(SDC_EINVAL, "syn_recur=%d: 0 or 1", plan->syn_recur);
+    if (plan->ana_recur != 0 && plan->ana_recur != 1)
+        return fail(SDC_EINVAL, "ana_recur=%d: 0 or 1", plan->ana_recur);
     const int jt = plan->syn_lat_tiles, d = plan->syn_depth;
     const bool syn_ok = (jt == 1 && (d == 8 || d == 4)) || (jt == 2 && (d == 4 || d == 2)) ||
                         (jt == 3 && d == 2) || (jt == 4 && (d == 2 || d == 1)) || (jt == 6 && d == 1);
@@ -605,6 +608,7 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
     h->lplan.ana_interleave = plan->ana_interleave;
     h->lplan.fuse_update = plan->fuse_update;
     h->lplan.syn_recur = plan->syn_recur;
+    h->lplan.ana_recur = plan->ana_recur;
     h->drop_graphs();                 // recaptured with the new variants on their next replay
     return SDC_OK;
 }
@@ -651,13 +655,15 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         syn_cands[k].syn_depth = shapes[k][1];
         syn_cands[k].syn_recur = shapes[k][2];
     }
-    LegPlan ana_cands[4];
-    for (int k = 0; k < 4; ++k) {
+    constexpr int kAna = 8;                 // depth 4 / 2 x interleave 1 / 0 x read / regenerate
+    LegPlan ana_cands[kAna];
+    for (int k = 0; k < kAna; ++k) {
         ana_cands[k] = saved;
-        ana_cands[k].ana_depth = k < 2 ? 4 : 2;
+        ana_cands[k].ana_depth = (k & 2) ? 2 : 4;
         ana_cands[k].ana_interleave = (k & 1) ? 0 : 1;
+        ana_cands[k].ana_recur = k >> 2;
     }
-    float syn_ms[kSyn] = {0.f}, ana_ms[4] = {0.f};
+    float syn_ms[kSyn] = {0.f}, ana_ms[kAna] = {0.f};
     hipError_t err = hipSuccess;
     for (int k = 0; k < kSyn && err == hipSuccess; ++k) {
         c->lplan = syn_cands[k];
@@ -666,7 +672,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
                                  c->cml, S, c->four, c->g, c->st);
         }, syn_ms[k]);
     }
-    for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+    for (int k = 0; k < kAna && err == hipSuccess; ++k) {
         c->lplan = ana_cands[k];
         err = time_it([&] {
             launch_analysis_swe(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
@@ -689,14 +695,16 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         }
         cur = 0;
         fast = 0;
-        for (int k = 0; k < 4; ++k) {
-            if (ana_cands[k].ana_depth == saved.ana_depth && ana_cands[k].ana_interleave == saved.ana_interleave)
+        for (int k = 0; k < kAna; ++k) {
+            if (ana_cands[k].ana_depth == saved.ana_depth && ana_cands[k].ana_interleave == saved.ana_interleave &&
+                ana_cands[k].ana_recur == saved.ana_recur)
                 cur = k;
             if (ana_ms[k] < ana_ms[fast]) fast = k;
         }
         if (ana_ms[fast] < kMargin * ana_ms[cur]) {
             best.ana_depth = ana_cands[fast].ana_depth;
             best.ana_interleave = ana_cands[fast].ana_interleave;
+            best.ana_recur = ana_cands[fast].ana_recur;
         }
     }
     (void)hipEventDestroy(e0);
@@ -714,6 +722,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         chosen->ana_interleave = best.ana_interleave;
         chosen->fuse_update = best.fuse_update;
         chosen->syn_recur = best.syn_recur;
+        chosen->ana_recur = best.ana_recur;
     }
     return SDC_OK;
 }

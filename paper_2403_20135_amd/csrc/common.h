@@ -81,6 +81,7 @@ struct LegPlan {
     int syn_tiles = 2, syn_depth = 2, ana_depth = 2, ana_interleave = 1;
     int fuse_update = 1;       // node updates inside the analysis (M in {1, 2, 4})
     int syn_recur = 0;         // synthesis regenerates Pbar, H in registers instead of reading them
+    int ana_recur = 0;         // analysis regenerates them from a quarter of the stored entries
 };
 
 // Upward recurrence of the orthonormal associated Legendre functions in n at fixed m and mu (the

@@ -413,19 +413,36 @@ constexpr int kAnaLat = 4 * kAnaVals + 2;       // LDS doubles per latitude (pad
 constexpr int kAnaBuf = 16 * kAnaLat;           // doubles per LDS block buffer
 constexpr int kAnaChunks = 16 * 2 * kAnaVals;   // double2 chunks per block (16 lat x 4 states x 7)
 
-template <typename TT> struct AnaStage {
+template <typename TT, bool REC> struct AnaStage {
     typename Mma<TT>::vec aP, aH;   // table rows, 4 consecutive latitudes per lane group
 };
+// REC: the table entries of a block are regenerated from two stored values per lane
+template <typename TT> struct AnaStage<TT, true> {
+    double pm1, p0, mu;             // Pbar_{n0-1}, Pbar_{n0} and mu of the lane's latitude
+};
 
-template <int MODE, typename TT, int D>
+// REC (restarting recurrence): instead of streaming a wave's 16 table rows for each block, lane
+// (i, q) reads Pbar_{n0-1} and Pbar_{n0} of latitude i of the block at the first of its four rows
+// kt + 4q (n0 = m + p + 2 (kt + 4 q)), continues the upward recurrence over the next eight
+// degrees with leg_next / leg_h (the table generator's own evaluation, so the values are the
+// table entries bit for bit) and so forms Pbar, H of rows kt + 4q .. kt + 4q + 3; a wave-private
+// LDS transpose then hands lane (i, q) row i at the four latitudes 4q .. 4q + 3 its MFMA steps
+// take.  A quarter of the table bytes is read; the coefficients of the lane's eight degrees stay
+// in registers for the whole contraction.
+constexpr int kAnaTrRow = 18;                   // LDS doubles per transpose row (16 + pad)
+constexpr int kAnaTr = 2 * 16 * kAnaTrRow;      // doubles per wave: (Pbar, H) x 16 rows
+
+template <int MODE, typename TT, int D, bool REC>
 __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int4* __restrict__ tasks, int ntasks, int interleave, const TT* __restrict__ G,
     int nstates, const double* __restrict__ nscale, double* __restrict__ out, Geom g,
-    UpdateArgs fu, int fuse) {
+    UpdateArgs fu, int fuse, const double* __restrict__ P64, const double* __restrict__ rc,
+    const double* __restrict__ mu) {
     using MM = Mma<TT>;
     using vec = typename MM::vec;
     __shared__ __align__(16) double gl[2][kAnaBuf + 4];       // + a dummy slot for idle threads
+    __shared__ __align__(16) double tr[REC ? 4 * kAnaTr : 2];  // REC transposes, one area per wave
     const int2 tg = xcd_task_group(ntasks, (nstates + 3) >> 2, interleave);
     if (tg.x >= ntasks) return;
     const int4 task = tasks[tg.x];
@@ -522,20 +539,84 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     };
 
     vec accP[2] = {MM::zero(), MM::zero()}, accH[2] = {MM::zero(), MM::zero()};
-    auto load = [&](AnaStage<TT>& x, int b) {
-        x.aP = *(const vec*)(Pr + b * bstride);
-        x.aH = *(const vec*)(Hr + b * bstride);
+    // REC: restart rows and recurrence coefficients of this lane group's four rows (rows past the
+    // order's end restart at a stored row; their outputs are dropped)
+    const double* rP0 = P64;
+    const double* rPm = P64;
+    size_t rPm_tile = 0;                                     // doubles per latitude tile
+    bool rzero = false;
+    double ca[8], cbb[8], cc[4], cd[4];
+    if constexpr (REC) {
+        const int kq = kt + 4 * q < np4 ? kt + 4 * q : np4 - 1;
+        const int n0 = m + p + 2 * kq;
+        rP0 = P64 + toff[2 * m + p] + tab_index(np4, kq, i);
+        // Pbar_{n0-1}: parity 1, row kq - 1 (p = 0) or parity 0, row kq (p = 1); zero at n0 = m
+        const int po = 1 - p;
+        const int npo4 = (npk_of(g.T, m, po) + 3) & ~3;
+        int ko = p == 0 ? kq - 1 : kq;
+        rzero = ko < 0 || npo4 == 0;
+        ko = ko < 0 ? 0 : (ko < npo4 ? ko : npo4 - 1);
+        rPm = npo4 > 0 ? P64 + toff[2 * m + po] + tab_index(npo4, ko, i) : rP0;
+        rPm_tile = (size_t)npo4 * 16;
+        const double* c0 = rc + 4 * rec_index(g.T, m, n0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            ca[k] = c0[4 * k];
+            cbb[k] = c0[4 * k + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            cc[k] = c0[8 * k + 2];
+            cd[k] = c0[8 * k + 3];
+        }
+    }
+    double* trw = tr + (REC ? wave * kAnaTr : 0);
+    auto load = [&](AnaStage<TT, REC>& x, int b) {
+        if constexpr (REC) {
+            const int jh = 16 * b + i;
+            x.p0 = rP0[(size_t)b * bstride];
+            x.pm1 = rzero ? 0.0 : rPm[(size_t)b * rPm_tile];
+            x.mu = jh < g.nh ? mu[jh] : 0.0;
+        } else {
+            x.aP = *(const vec*)(Pr + b * bstride);
+            x.aH = *(const vec*)(Hr + b * bstride);
+        }
     };
     // k-step qq of a block contracts latitude 4 q + qq of the block (lane group q)
-    auto compute = [&](const AnaStage<TT>& x, const double* lb) {
+    auto contract = [&](const vec& aP, const vec& aH, const double* lb) {
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             const double* lq = lb + (4 * q + qq) * kAnaLat;
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                accP[t] = MM::mma(x.aP[qq], (TT)lq[offP[t]], accP[t]);
-                accH[t] = MM::mma(x.aH[qq], (TT)lq[offH[t]], accH[t]);   // dropped for kinds without H
+                accP[t] = MM::mma(aP[qq], (TT)lq[offP[t]], accP[t]);
+                accH[t] = MM::mma(aH[qq], (TT)lq[offH[t]], accH[t]);   // dropped for kinds without H
             }
+        }
+    };
+    auto compute = [&](const AnaStage<TT, REC>& x, const double* lb) {
+        if constexpr (REC) {
+            double pm1 = x.pm1, p0 = x.p0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double p1 = leg_next(x.mu, p0, pm1, ca[2 * k], cbb[2 * k]);
+                trw[(4 * q + k) * kAnaTrRow + i] = p0;
+                trw[(16 + 4 * q + k) * kAnaTrRow + i] = leg_h(pm1, p1, cc[k], cd[k]);
+                pm1 = p1;
+                p0 = leg_next(x.mu, p1, p0, ca[2 * k + 1], cbb[2 * k + 1]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double2* rp = reinterpret_cast<const double2*>(trw + i * kAnaTrRow + 4 * q);
+            const double2* rh = reinterpret_cast<const double2*>(trw + (16 + i) * kAnaTrRow + 4 * q);
+            const double2 p01 = rp[0], p23 = rp[1], h01 = rh[0], h23 = rh[1];
+            vec aP, aH;
+            aP[0] = (TT)p01.x; aP[1] = (TT)p01.y; aP[2] = (TT)p23.x; aP[3] = (TT)p23.y;
+            aH[0] = (TT)h01.x; aH[1] = (TT)h01.y; aH[2] = (TT)h23.x; aH[3] = (TT)h23.y;
+            contract(aP, aH, lb);
+        } else {
+            contract(x.aP, x.aH, lb);
         }
     };
 
@@ -544,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     gstore(gr, 0, 0);
     __syncthreads();
     if (active) {
-        AnaStage<TT> st[D];
+        AnaStage<TT, REC> st[D];
 #pragma unroll
         for (int u = 0; u < D; ++u) load(st[u], u < nb ? u : nb - 1);
         int b0 = 0;
@@ -656,17 +737,26 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
 // Analysis variants: D = 4 or 2 table stages in flight per wave; state groups interleaved per
 // XCD or group-major.
 template <int MODE, typename TT>
-static void launch_analysis_variant(const LegPlan& plan, unsigned grid, hipStream_t st, const TT* P,
-                                    const TT* H, const long long* toff, const int4* tasks, int nwg,
+static void launch_analysis_variant(const LegPlan& plan, unsigned grid, hipStream_t st,
+                                    const Tables& tb, const TT* P, const TT* H,
+                                    const long long* toff, const int4* tasks, int nwg,
                                     const void* Gv, int nstates, const double* nscale, double* out,
                                     const Geom& g, const UpdateArgs& fu, int fuse) {
     const TT* G = static_cast<const TT*>(Gv);      // the analysis input is stored in the table type
-    if (plan.ana_depth == 2)
-        k_analysis_swe<MODE, TT, 2><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg, plan.ana_interleave,
-                                                             G, nstates, nscale, out, g, fu, fuse);
-    else
-        k_analysis_swe<MODE, TT, 4><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg, plan.ana_interleave,
-                                                             G, nstates, nscale, out, g, fu, fuse);
+#define ANA(D, REC)                                                                                 \
+    k_analysis_swe<MODE, TT, D, REC><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg,               \
+                                                              plan.ana_interleave, G, nstates,      \
+                                                              nscale, out, g, fu, fuse, tb.P,       \
+                                                              tb.rc, tb.mu)
+    if (plan.ana_recur) {
+        if (plan.ana_depth == 2) ANA(2, true);
+        else ANA(4, true);
+    } else if (plan.ana_depth == 2) {
+        ANA(2, false);
+    } else {
+        ANA(4, false);
+    }
+#undef ANA
 }
 
 void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
@@ -678,10 +768,10 @@ void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long*
     const UpdateArgs& fu = fuse ? *fuse : none;
     const int mode = fuse ? fuse_mode : 0;
     if (tb.P32)
-        launch_analysis_variant<kAnaForward, float>(plan, grid, st, tb.P32, tb.H32, toff, tasks, nwg, G,
+        launch_analysis_variant<kAnaForward, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, tasks, nwg, G,
                                                     nstates, neg_lap, out, g, fu, mode);
     else
-        launch_analysis_variant<kAnaForward, double>(plan, grid, st, tb.P, tb.H, toff, tasks, nwg, G,
+        launch_analysis_variant<kAnaForward, double>(plan, grid, st, tb, tb.P, tb.H, toff, tasks, nwg, G,
                                                      nstates, neg_lap, out, g, fu, mode);
 }
 
@@ -690,10 +780,10 @@ void launch_analysis_adjoint(const Tables& tb, const LegPlan& plan, const long l
                              const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st) {
     const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
     if (tb.P32)
-        launch_analysis_variant<kAnaAdjoint, float>(plan, grid, st, tb.P32, tb.H32, toff, tasks, nwg, G,
+        launch_analysis_variant<kAnaAdjoint, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, tasks, nwg, G,
                                                     nstates, inv_lap, out_acc, g, UpdateArgs{}, 0);
     else
-        launch_analysis_variant<kAnaAdjoint, double>(plan, grid, st, tb.P, tb.H, toff, tasks, nwg, G,
+        launch_analysis_variant<kAnaAdjoint, double>(plan, grid, st, tb, tb.P, tb.H, toff, tasks, nwg, G,
                                                      nstates, inv_lap, out_acc, g, UpdateArgs{}, 0);
 }
 

@@ -15,13 +15,15 @@ from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, _torch, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-DEFAULT = dict(syn_lat_tiles=2, syn_depth=2, ana_depth=2, ana_interleave=1, fuse_update=1, syn_recur=0)
+DEFAULT = dict(syn_lat_tiles=2, syn_depth=2, ana_depth=2, ana_interleave=1, fuse_update=1, syn_recur=0,
+               ana_recur=0)
 # (syn_lat_tiles, syn_depth, ana_depth, ana_interleave[, fuse_update, syn_recur]); syn_recur = 1
 # regenerates the tables in the synthesis by the recurrence that wrote them
 VARIANTS = [(1, 8, 4, 1), (1, 4, 4, 1), (2, 4, 4, 1), (2, 2, 4, 1), (3, 2, 4, 1), (4, 2, 4, 1),
             (4, 1, 4, 1), (6, 1, 4, 1), (1, 8, 2, 1), (1, 8, 4, 0), (2, 4, 2, 0),
             (4, 2, 2, 1, 1, 1), (4, 1, 2, 1, 1, 1), (4, 2, 4, 0, 0, 1), (2, 2, 2, 1, 1, 1),
-            (2, 4, 2, 1, 1, 1), (1, 4, 2, 1, 1, 1), (1, 8, 4, 1, 1, 1)]
+            (2, 4, 2, 1, 1, 1), (1, 4, 2, 1, 1, 1), (1, 8, 4, 1, 1, 1), (2, 2, 2, 1, 1, 0, 1),
+            (2, 2, 4, 0, 1, 0, 1), (4, 2, 2, 1, 1, 1, 1), (2, 2, 2, 1, 0, 0, 1)]
 
 
 def _outputs(sdc, x, lam, dt):
@@ -57,7 +59,7 @@ def test_set_plan_rejects_variants_not_built():
     sdc = _sdc(21, 34, 64, 2, 2, 1)
     for bad in [(2, 8, 4, 1), (4, 4, 4, 1), (3, 4, 4, 1), (5, 2, 4, 1), (6, 2, 4, 1), (1, 6, 4, 1),
                 (1, 8, 3, 1), (1, 8, 4, 2), (2, 2, 2, 1, 2), (2, 2, 2, 1, 1, 2), (3, 2, 2, 1, 1, 1),
-                (6, 1, 2, 1, 1, 1)]:
+                (6, 1, 2, 1, 1, 1), (2, 2, 2, 1, 1, 0, 2)]:
         with pytest.raises(_lib.SDCError) as ei:
             sdc.set_plan(*bad)
         assert ei.value.code == _lib.SDC_EINVAL
@@ -76,7 +78,7 @@ def test_autotune_keeps_results_and_graphs():
     assert chosen == sdc.plan()
     assert (chosen["syn_lat_tiles"], chosen["syn_depth"]) in [(1, 8), (1, 4), (2, 4), (2, 2), (3, 2),
                                                                 (4, 2), (4, 1), (6, 1)]
-    assert chosen["syn_recur"] in (0, 1) and chosen["fuse_update"] == 1
+    assert chosen["syn_recur"] in (0, 1) and chosen["ana_recur"] in (0, 1) and chosen["fuse_update"] == 1
     assert chosen["ana_depth"] in (2, 4) and chosen["ana_interleave"] in (0, 1)
     for _ in range(2):
         sdc.step_graph(x, dt)             # recaptured with the chosen variants

@@ -450,7 +450,8 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     # forward FP64 kernels of the bench workload (names as rocprofv3 prints them)
     rec = "true" if plan.get("syn_recur") else "false"
     classes = {f"void k_synthesis<0, double, {plan['syn_lat_tiles']}, {plan['syn_depth']}, {rec}>": "synthesis",
-               f"void k_analysis_swe<0, double, {plan['ana_depth']}>": "analysis",
+               f"void k_analysis_swe<0, double, {plan['ana_depth']}, "
+               f"{'true' if plan.get('ana_recur') else 'false'}>": "analysis",
                "void k_grid_swe<": "grid", "void k_update<": "update"}
 
     def per_kernel(path, counter):

@@ -59,7 +59,7 @@ def _csv(path, counter, rows):
 
 def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     plan = {"syn_lat_tiles": 2, "syn_depth": 2, "ana_depth": 2, "ana_interleave": 1, "fuse_update": 1,
-            "syn_recur": 1}
+            "syn_recur": 1, "ana_recur": 0}
     logs = []
     for name in ("f.log", "w.log"):
         p = tmp_path / name
@@ -72,13 +72,14 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
         ("void k_synthesis<0, double, 2, 2, true>(double const*)", 3000.0),
         ("void k_synthesis<0, double, 1, 8, true>(double const*)", 99999.0),   # an autotuner trial
         ("void k_synthesis<0, double, 2, 2, false>(double const*)", 77777.0),  # table-reading trial
-        ("void k_analysis_swe<0, double, 2>(double const*)", 500.0),
+        ("void k_analysis_swe<0, double, 2, false>(double const*)", 500.0),
+        ("void k_analysis_swe<0, double, 2, true>(double const*)", 88888.0),     # regenerating trial
         ("void k_grid_swe<768, double>(x)", 10.0),
         ("void k_update<4>(UpdateArgs)", 20.0)])
     _csv(tmp_path / "w.csv", "WRITE_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", 256 * 1024.0),
         ("void k_synthesis<0, double, 2, 2, true>(double const*)", 100.0),
-        ("void k_analysis_swe<0, double, 2>(double const*)", 50.0),
+        ("void k_analysis_swe<0, double, 2, false>(double const*)", 50.0),
         ("void k_grid_swe<768, double>(x)", 40.0),
         ("void k_update<4>(UpdateArgs)", 30.0)])
     out = tmp_path / "t.json"
@@ -90,6 +91,7 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     assert syn["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
     assert syn["write_bytes_per_launch"] == pytest.approx(100.0 * 1024)
     assert set(t["kernels"]) == {"synthesis", "analysis", "grid", "update"}
+    assert t["kernels"]["analysis"]["fetch_bytes_per_launch"] == pytest.approx(500.0 * 1024 * 2.0)
     assert t["legendre_plan"] == plan
 
 

@@ -97,4 +97,11 @@ def min_sr_ns(tau: np.ndarray, sweep: int) -> np.ndarray:
     return tau / float(len(tau))
 
 
-QDELTA = {"flex": min_sr_flex, "ns": min_sr_ns}
+def ie_par(tau: np.ndarray, sweep: int) -> np.ndarray:
+    """Parallel implicit Euler: q_mm = tau_m in every sweep (the sweep argument is ignored), i.e.
+    each node's implicit correction is an implicit Euler step from t_n to its own node; one of
+    the nonzero diagonals the node update of Section 4.2 admits, and MIN-SR-FLEX's first sweep."""
+    return np.array(tau, dtype=float)
+
+
+QDELTA = {"flex": min_sr_flex, "ns": min_sr_ns, "iepar": ie_par}

@@ -116,3 +116,15 @@ def test_min_sr_ns_makes_q_minus_qdelta_nilpotent(M):
     assert np.abs(np.linalg.matrix_power(A, M)).max() < 1e-13
     assert np.abs(np.linalg.matrix_power(A, M - 1)).max() > 1e-6
     np.testing.assert_array_equal(q.min_sr_ns(tau, 1), q.min_sr_ns(tau, 7))
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 5])
+def test_parallel_implicit_euler_diagonal(M):
+    """q_mm = tau_m (implicit Euler from t_n to each node) in every sweep; it is MIN-SR-FLEX's
+    first sweep, and for M = 1 (tau = 1) all three diagonals coincide with the implicit Euler step."""
+    tau = q.radau_right_nodes(M)
+    for s in (1, 2, 7):
+        np.testing.assert_array_equal(q.ie_par(tau, s), tau)
+    np.testing.assert_array_equal(q.ie_par(tau, 3), q.min_sr_flex(tau, 1))
+    if M == 1:
+        assert q.ie_par(tau, 5)[0] == q.min_sr_ns(tau, 5)[0] == q.min_sr_flex(tau, 5)[0] == 1.0

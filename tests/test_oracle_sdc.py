@@ -48,7 +48,7 @@ def test_single_sweep_is_imex_euler(M):
         assert torch.max(torch.abs(r[f])).item() <= 1e-13 * scale
 
 
-@pytest.mark.parametrize("qd", ["flex", "ns"])
+@pytest.mark.parametrize("qd", ["flex", "ns", "iepar"])
 @pytest.mark.parametrize("M,K", [(2, 2), (3, 3), (4, 4), (3, 5)])
 def test_linear_mode_against_stage_matrices(M, K, qd):
     """With f_E = 0 one (n,m) mode evolves by the product of the sweep matrices built from

@@ -81,7 +81,9 @@ typedef struct {
     int qdelta;               /* diagonal coefficients of the implicit sweeps (Section 4.2):
                                  0 = MIN-SR-FLEX, tau_m / min(s, M) in sweep s (the paper's choice);
                                  1 = MIN-SR-NS, tau_m / M in every sweep (a variant of the family:
-                                 Q - Q_Delta is nilpotent) */
+                                 Q - Q_Delta is nilpotent);
+                                 2 = parallel implicit Euler, tau_m in every sweep (another of the
+                                 nonzero diagonals the node update admits) */
     int precision;            /* an sdc_precision value */
     int batch;                /* ensemble members sharing this truncation, >= 1 */
 } sdc_config;

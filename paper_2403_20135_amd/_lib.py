@@ -11,7 +11,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "sdc.h")
 
 SDC_OK, SDC_EINVAL, SDC_ENOMEM, SDC_EHIP, SDC_ENONFINITE, SDC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-QDELTAS = {"flex": 0, "ns": 1}
+QDELTAS = {"flex": 0, "ns": 1, "iepar": 2}
 KERNEL_CLASSES = {"synthesis": 0, "grid": 1, "analysis": 2, "update": 3}
 _NAMES = {0: "SDC_OK", -1: "SDC_EINVAL", -2: "SDC_ENOMEM", -3: "SDC_EHIP", -4: "SDC_ENONFINITE",
           -5: "SDC_EUNSUPPORTED"}

@@ -289,8 +289,9 @@ int validate_config(const sdc_config* c) {
     if (c->M < 1 || c->M > kMaxNodes) return fail(SDC_EINVAL, "M=%d out of range 1..%d", c->M, kMaxNodes);
     if (c->K < 1 || c->K > kMaxSweeps) return fail(SDC_EINVAL, "K=%d out of range 1..%d", c->K, kMaxSweeps);
     if (c->nodes != 0) return fail(SDC_EINVAL, "nodes=%d: only Radau-right (0) is defined", c->nodes);
-    if (c->qdelta != 0 && c->qdelta != 1)
-        return fail(SDC_EINVAL, "qdelta=%d: MIN-SR-FLEX (0) or MIN-SR-NS (1)", c->qdelta);
+    if (c->qdelta < 0 || c->qdelta > 2)
+        return fail(SDC_EINVAL, "qdelta=%d: MIN-SR-FLEX (0), MIN-SR-NS (1) or parallel implicit Euler (2)",
+                    c->qdelta);
     if (c->precision < SDC_FP64 || c->precision > SDC_BF16X3_MFMA)
         return fail(SDC_EINVAL, "precision=%d unknown", c->precision);
     if (c->batch < 1 || c->batch > 4096) return fail(SDC_EINVAL, "batch=%d out of range 1..4096", c->batch);
@@ -742,7 +743,9 @@ int check_step_args(sdc_handle h, const double* state, double dt, int M, int K) 
 
 // The update kernels form the diagonal coefficient of sweep s as tau_m / min(s, M)
 // (MIN-SR-FLEX); MIN-SR-NS uses tau_m / M in every sweep, i.e. the kernels' s = M.
-int qd_sweep(const sdc_ctx* c, int s, int M) { return c->cfg.qdelta == 1 ? M : s; }
+// The kernels take q_mm = tau_m / min(sweep, M): MIN-SR-FLEX passes the sweep, MIN-SR-NS M and
+// parallel implicit Euler 1.
+int qd_sweep(const sdc_ctx* c, int s, int M) { return c->cfg.qdelta == 1 ? M : (c->cfg.qdelta == 2 ? 1 : s); }
 
 // Algorithm 2 for all members of the handle, enqueued on c->st (arguments already checked).
 // With `tape`, the grid fields of every f_E evaluation are kept there (stage s at

@@ -35,7 +35,7 @@ def test_every_declared_function_is_exported():
     (dict(M=9), _lib.SDC_EINVAL),
     (dict(K=0), _lib.SDC_EINVAL),
     (dict(nodes=1), _lib.SDC_EINVAL),
-    (dict(qdelta=2), _lib.SDC_EINVAL),
+    (dict(qdelta=3), _lib.SDC_EINVAL),
     (dict(precision=7), _lib.SDC_EINVAL),
     (dict(batch=0), _lib.SDC_EINVAL),
     (dict(radius=-1.0), _lib.SDC_EINVAL),

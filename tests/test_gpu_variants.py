@@ -1,6 +1,6 @@
 """GPU parity of the method variants beside the paper's dSDC configuration, against the oracle
-through the C ABI: MIN-SR-NS diagonal coefficients (tau_m / M in every sweep) for the step and its
-adjoint, and the sequential IMEX SDC of Algorithm 1."""
+through the C ABI: MIN-SR-NS diagonal coefficients (tau_m / M in every sweep) and parallel implicit
+Euler (tau_m) for the step and its adjoint, and the sequential IMEX SDC of Algorithm 1."""
 import numpy as np
 import pytest
 
@@ -12,15 +12,15 @@ from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, _torch, rel_l2
 pytestmark = pytest.mark.gpu
 
 
-def _sdc_ns(T, nlat, nlon, M, K, batch):
+def _sdc_ns(T, nlat, nlon, M, K, batch, qd="ns"):
     from paper_2403_20135_amd.api import SDC
-    print(f"\n[gpu] SDC(T={T}, {nlat}x{nlon}, M={M}, K={K}, batch={batch}, MIN-SR-NS)", flush=True)
+    print(f"\n[gpu] SDC(T={T}, {nlat}x{nlon}, M={M}, K={K}, batch={batch}, qdelta {qd})", flush=True)
     return SDC(T, nlat, nlon, M, K, batch, "fp64", W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH,
-               qdelta="ns")
+               qdelta=qd)
 
 
-def _oracle_ns(T, nlat, nlon):
-    return Oracle(T, nlat, nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, qdelta="ns")
+def _oracle_ns(T, nlat, nlon, qd="ns"):
+    return Oracle(T, nlat, nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, qdelta=qd)
 
 
 @pytest.mark.parametrize("T,nlat,nlon,M,K,dt,steps,batch", [
@@ -45,6 +45,38 @@ def test_min_sr_ns_step_matches_oracle(T, nlat, nlon, M, K, dt, steps, batch):
           flush=True)
     assert err <= 1e-11
     assert rel_l2(flex, ref, T) > 1e-9
+
+
+@pytest.mark.parametrize("T,nlat,nlon,M,K,dt,steps,batch", [
+    (31, 48, 96, 3, 3, 300.0, 4, 1),
+    (63, 96, 192, 4, 4, 240.0, 2, 2),
+])
+def test_parallel_implicit_euler_step_and_adjoint_match_oracle(T, nlat, nlon, M, K, dt, steps, batch):
+    """Parallel implicit Euler diagonal (q_mm = tau_m in every sweep): steps against the oracle,
+    the adjoint against the oracle's VJP."""
+    sdc = _sdc_ns(T, nlat, nlon, M, K, batch, "iepar")
+    o = _oracle_ns(T, nlat, nlon, "iepar")
+    u0 = _states(T, batch, 521)
+    x = _dev(u0)
+    for _ in range(steps):
+        sdc.step(x, dt)
+    sdc.sync()
+    ref = np.stack([o.step(u0[b], dt, M, K, steps=steps) for b in range(batch)])
+    err = rel_l2(_host(x), ref, T)
+    flex = np.stack([Oracle(T, nlat, nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
+                     .step(u0[b], dt, M, K, steps=steps) for b in range(batch)])
+    print(f"[gpu] IE-par T{T} M{M}K{K}: rel L2 {err:.3e} (FLEX differs by {rel_l2(flex, ref, T):.2e})",
+          flush=True)
+    assert err <= 1e-11
+    assert rel_l2(flex, ref, T) > 1e-9
+    lam = np.stack([W.random_state(T, 522 + b) for b in range(batch)])
+    lam[..., :T + 1, 1] = 0.0
+    out = _dev(np.zeros_like(u0))
+    sdc.step_adjoint(_dev(u0), _dev(lam), out, dt)
+    vref = np.stack([o.step_vjp(u0[b], lam[b], dt, M, K) for b in range(batch)])
+    verr = rel_l2(_host(out), vref, T)
+    print(f"[gpu] IE-par adjoint: rel L2 {verr:.3e}", flush=True)
+    assert verr <= 1e-10
 
 
 def test_min_sr_ns_adjoint_matches_oracle_vjp():

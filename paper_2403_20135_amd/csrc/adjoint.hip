@@ -20,7 +20,7 @@
 //   zeta_adj += -a^2/(n(n+1)) psi_adj, delta_adj += -a^2/(n(n+1)) chi_adj.
 // The node update and solve are per-coefficient linear maps with constant real coefficients; their
 // transposes are written out in k_update_adj.
-#include "common.h"
+#include "adj_update.h"
 
 __device__ __forceinline__ double2 ld2a(const double* p) { return *(const double2*)p; }
 __device__ __forceinline__ void st2a(double* p, double2 v) { *(double2*)p = v; }
@@ -66,101 +66,18 @@ void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, bool cml3
                                             ncoef, T);
 }
 
-// ---------------------------------------------------------------------------------------------
-// Node-update adjoint, one thread per (coefficient, member).  Per node m of sweep s:
-//   beta_adj_m = A_{m,s}^T ubar_m,  A = (I - alpha L)^{-1},  A^T(a, b, d) = ((a + alpha c d)/D, b,
-//   (d - alpha Phi_bar a)/D), D = 1 + alpha^2 Phi_bar c;  L^T(a, b, d) = (c d, 0, -Phi_bar a).
-//   u_n_adj += beta_adj_m
-//   E_adj_j (previous sweep) = dt sum_m q_mj beta_adj_m
-//   u_adj_j (previous sweep) = dt sum_m q_mj L^T beta_adj_m - alpha_{j,s} L^T beta_adj_j
-// For the last sweep only node M carries ubar (= the incoming adjoint state).  When the previous
-// sweep is the initial one (all nodes equal u_n, all tendencies E_0) the node sums are folded
-// into u_n_adj and E_0_adj.
-// ---------------------------------------------------------------------------------------------
-
+// Node-update adjoint (adj_update_part), one thread per (coefficient, Re/Im part, member): every
+// map here has real coefficients.
 template <int M>
 __global__ __launch_bounds__(64) void k_update_adj(AdjUpdateArgs a) {
-    // one thread per (coefficient, Re/Im part): every map here has real coefficients
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (t >= 2 * a.ncoef) return;
-    const int idx = t >> 1;
-    const int n = a.n_of[idx];
-    const double c = n * (n + 1.0) * a.inv_a2;
-    const size_t o = (size_t)t;
     const size_t fs = (size_t)a.ncoef * 2;
-    const int sdiv = a.sweep < M ? a.sweep : M;
-    double bp[M], bz[M], bd[M];                               // beta_adj per node
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        if (a.last && m != M - 1) {
-            bp[m] = bz[m] = bd[m] = 0.0;
-            continue;
-        }
-        const double* u = a.ubar + (size_t)b * a.ubar_member + (size_t)(a.last ? 0 : m) * a.ubar_node + o;
-        const double up = u[0], uz = u[fs], ud = u[2 * fs];
-        const double alpha = a.dt * a.tau[m] / sdiv;
-        const double den = 1.0 / (1.0 + alpha * alpha * a.phibar * c);
-        bp[m] = (up + alpha * c * ud) * den;
-        bz[m] = uz;
-        bd[m] = (ud - alpha * a.phibar * up) * den;
-    }
-    double sp = 0.0, sz = 0.0, sd = 0.0;                      // u_n adjoint contributions
-    double ep0 = 0.0, ez0 = 0.0, ed0 = 0.0;                   // E_0 adjoint when first_stage
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        sp += bp[m];
-        sz += bz[m];
-        sd += bd[m];
-    }
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        double qp = 0.0, qz = 0.0, qd = 0.0;                  // sum_m q_mj beta_adj_m
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const double qmj = a.Q[m * kMaxNodes + j];
-            qp += qmj * bp[m];
-            qz += qmj * bz[m];
-            qd += qmj * bd[m];
-        }
-        const double aj = a.dt * a.tau[j] / sdiv;
-        // E_adj_j = dt * qsum;  u_adj_j = dt L^T qsum - alpha_j L^T beta_adj_j
-        const double ep = a.dt * qp, ez = a.dt * qz, ed = a.dt * qd;
-        const double wp = c * (ed - aj * bd[j]);
-        const double wd = -a.phibar * (ep - aj * bp[j]);
-        if (a.first_stage) {
-            ep0 += ep;
-            ez0 += ez;
-            ed0 += ed;
-            sp += wp;
-            sd += wd;
-        } else {
-            double* e = a.ebar_prev + ((size_t)b * M + j) * 3 * fs + o;
-            e[0] = ep;
-            e[fs] = ez;
-            e[2 * fs] = ed;
-            double* u = a.ubar_prev + ((size_t)b * M + j) * 3 * fs + o;
-            u[0] = wp;
-            u[fs] = 0.0;
-            u[2 * fs] = wd;
-        }
-    }
-    if (a.first_stage) {
-        double* e = a.ebar_prev + (size_t)b * 3 * fs + o;
-        e[0] = ep0;
-        e[fs] = ez0;
-        e[2 * fs] = ed0;
-    }
-    double* un = a.ubar_n + (size_t)b * 3 * fs + o;
-    if (a.init_un) {
-        un[0] = sp;
-        un[fs] = sz;
-        un[2 * fs] = sd;
-    } else {
-        un[0] += sp;
-        un[fs] += sz;
-        un[2 * fs] += sd;
-    }
+    const double* u = a.ubar + (size_t)b * a.ubar_member + (size_t)t;
+    adj_update_part<M>(a, t, b, [&](int m, int f) {
+        return u[(size_t)(a.last ? 0 : m) * a.ubar_node + f * fs];
+    });
 }
 
 void launch_update_adj(const AdjUpdateArgs& a, hipStream_t st) {

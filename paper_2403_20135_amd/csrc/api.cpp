@@ -472,13 +472,19 @@ void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2*
 }
 
 // out_acc += J_E(u)^T ebar for S states whose stage grid fields are in `save`.
-void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save, double* out_acc) {
-    launch_prep_cml_adj(ebar, S, c->cml, c->P32 != nullptr, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef, c->g.T, c->st);
+// Transposed tendency of S states: ebar -> synthesis-adjoint layout (skipped when an earlier fused
+// epilogue wrote that layout already), then synthesis^T, products'^T, analysis^T accumulated into
+// out_acc (or, with fuse, consumed by the analysis epilogue).
+void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save, double* out_acc,
+                      const AdjFuse* fuse = nullptr, bool cml_ready = false) {
+    if (!cml_ready)
+        launch_prep_cml_adj(ebar, S, c->cml, c->P32 != nullptr, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef,
+                            c->g.T, c->st);
     launch_synthesis_adj(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
                          c->cml, S, c->adj_four5, c->g, c->st);
     launch_grid_adj(c->adj_four5, save, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
     launch_analysis_adjoint(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S,
-                            c->inv_lap, out_acc, c->g, c->st);
+                            c->inv_lap, out_acc, c->g, c->st, fuse);
 }
 
 size_t stage_states(const sdc_ctx* c, int s, int M) {     // states stored before stage s
@@ -995,6 +1001,37 @@ void enqueue_adjoint_reverse(sdc_ctx* c, const double2* tape, const double* lam_
     b.first_stage = K == 1;
     b.init_un = 1;
     launch_update_adj(b, c->st);
+    if (c->lplan.fuse_update && (M == 1 || M == 2 || M == 4)) {
+        // The adjoint update of sweep s runs in the epilogue of the transposed analysis that
+        // completes its node adjoints and writes the next transposed tendency's input directly;
+        // the first stage's epilogue writes lam_n.
+        AdjFuse af{};
+        af.m_of = c->m_of;
+        af.a = b;
+        af.a.cml = c->cml;
+        af.a.cml32 = c->P32 != nullptr ? 1 : 0;
+        af.a.T = c->g.T;
+        af.a.m_of = c->m_of;
+        af.a.rowoff = c->rowoff;
+        af.a.neg_lap = c->neg_lap;
+        af.a.ubar = c->adj_ubar;
+        af.a.ubar_node = fs;
+        af.a.ubar_member = (long long)M * fs;
+        af.a.last = 0;
+        af.a.init_un = 0;
+        af.mode = 1;
+        for (int s = K - 1; s >= 1; --s) {
+            af.a.sweep = qd_sweep(c, s, M);
+            af.a.first_stage = s == 1;
+            run_explicit_adj(c, c->adj_ebar, B * M, save_at(s), c->adj_ubar, &af, s < K - 1);
+        }
+        AdjFuse fin{};
+        fin.mode = 2;
+        fin.lam_out = lam_n;
+        fin.m_of = c->m_of;
+        run_explicit_adj(c, c->adj_ebar, B, save_at(0), c->adj_un, &fin, K > 1);
+        return;
+    }
     for (int s = K - 1; s >= 1; --s) {
         run_explicit_adj(c, c->adj_ebar, B * M, save_at(s), c->adj_ubar);
         b.ubar = c->adj_ubar;

@@ -195,9 +195,13 @@ void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long*
 void launch_synthesis_scalar(const double* P, const long long* toff, const int2* tasks, int ntasks,
                              const double* spec, int nfields, double2* four, const Geom& g,
                              hipStream_t st);
+// With fuse != null the accumulated adjoints are not stored: the kernel's epilogue applies
+// *fuse (the adjoint node update of the group's members, or the final copy to lam_out).
+struct AdjFuse;
 void launch_analysis_adjoint(const Tables& tb, const LegPlan& plan, const long long* toff,
                              const int4* tasks, int nwg, const double* G, int nstates,
-                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st);
+                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st,
+                             const AdjFuse* fuse = nullptr);
 void launch_round_tables(const double* P, const double* H, float* P32, float* H32, long long n,
                          hipStream_t st);
 void launch_analysis_scalar(const double* P, const long long* toff, const int4* tasks, int ntasks,
@@ -313,6 +317,23 @@ struct AdjUpdateArgs {
     const int* n_of;
     double dt, phibar, inv_a2;
     int M, sweep, last, first_stage, init_un, batch, ncoef;
+    // when cml is set the E adjoints are written in the synthesis-adjoint input layout instead
+    // of ebar_prev (the transposed analysis' fused epilogue)
+    double* cml;
+    int cml32, T;
+    const int* m_of;
+    const int* rowoff;
+    const double* neg_lap;
+};
+// Fused epilogue of the transposed analysis: mode 1 applies the adjoint node update `a` to the
+// accumulated adjoints of the group's members (states b M + j); mode 2 (the step's first stage,
+// states = members) writes the finished u_n adjoint to lam_out with the m = 0 imaginary parts
+// set to zero.
+struct AdjFuse {
+    AdjUpdateArgs a;
+    double* lam_out;
+    const int* m_of;
+    int mode;
 };
 
 void launch_update_adj(const AdjUpdateArgs& a, hipStream_t st);

@@ -14,6 +14,7 @@
 // keep several 4-row (synthesis) or 16-latitude (analysis) operand stages in flight in registers,
 // and place the columns of their tiles so that every output is formed from values the lane
 // already holds.
+#include "adj_update.h"
 #include "node_update.h"
 
 #include <type_traits>
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     const int4* __restrict__ tasks, int ntasks, int interleave, const TT* __restrict__ G,
     int nstates, const double* __restrict__ nscale, double* __restrict__ out, Geom g,
     UpdateArgs fu, int fuse, const double* __restrict__ P64, const double* __restrict__ rc,
-    const double* __restrict__ mu) {
+    const double* __restrict__ mu, AdjFuse af) {
     using MM = Mma<TT>;
     using vec = typename MM::vec;
     __shared__ __align__(16) double gl[2][kAnaBuf + 4];       // + a dummy slot for idle threads
@@ -658,10 +659,68 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
             gstore(gr, b + 1, (b + 1) & 1);
             __syncthreads();
         }
-        if (!fuse) return;                                   // uniform
+        if (!fuse && !(MODE == kAnaAdjoint && af.mode)) return;   // uniform
     }
 
     const int cb = coef_offset(g.T, m) - m;
+    if constexpr (MODE == kAnaAdjoint) {
+        if (af.mode) {
+            // Fused epilogue of the transposed tendency: the accumulated adjoints of this block's
+            // rows (earlier contributions + this one, the sum the unfused kernel stores) go to LDS
+            // as [row][state][field][part]; then mode 1 applies the adjoint node update to every
+            // (row, part, member) of the block (adj_update_part, the same arithmetic as the
+            // adjoint update kernel; a group of four states holds 4 / M whole members), and mode
+            // 2 writes the finished u_n adjoint of every member to lam_out.
+            double* eb = reinterpret_cast<double*>(gl);          // 64 x 4 x 3 x 2 doubles
+            const int kk0 = task.z;
+            if (active) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int sl = 2 * t + (i >> 3);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double val = has_h ? (double)accP[t][r] + (double)accH[t][r] : (double)accP[t][r];
+                        const double right = __shfl_down(val, 2, 64);
+                        const int kk = kt + MM::row(r, q);
+                        if (kk >= np || sl >= nsg || kind == 1) continue;
+                        const int n = m + p + 2 * kk;
+                        const int field = kind == 0 ? 1 : (kind == 2 ? 2 : 0);
+                        const double res = kind == 0 ? val + nscale[n] * right : (kind == 2 ? nscale[n] * val : val);
+                        const double tot = out[((size_t)((s0 + sl) * 3 + field) * g.ncoef + cb + n) * 2 + re] + res;
+                        eb[(((kk - kk0) * 4 + sl) * 3 + field) * 2 + re] = tot;
+                    }
+                }
+            }
+            __syncthreads();
+            if (af.mode == 1) {
+                const int Mn = af.a.M;
+                const int nmem = nsg / Mn, bfirst = s0 / Mn;
+                for (int it = tid; it < 128 * nmem; it += kBlock) {
+                    const int row = (it >> 1) & 63, c = it & 1, k = it >> 7;
+                    const int kk = kk0 + row;
+                    if (kk >= np) continue;
+                    const int t2 = 2 * (cb + m + p + 2 * kk) + c;
+                    auto ub = [&](int j, int f) { return eb[((row * 4 + k * Mn + j) * 3 + f) * 2 + c]; };
+                    if (Mn == 1) adj_update_part<1>(af.a, t2, bfirst + k, ub);
+                    else if (Mn == 2) adj_update_part<2>(af.a, t2, bfirst + k, ub);
+                    else adj_update_part<4>(af.a, t2, bfirst + k, ub);
+                }
+            } else {
+                for (int it = tid; it < 128 * nsg; it += kBlock) {
+                    const int row = (it >> 1) & 63, c = it & 1, k = it >> 7;
+                    const int kk = kk0 + row;
+                    if (kk >= np) continue;
+                    const int idx = cb + m + p + 2 * kk;
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        const double v = eb[((row * 4 + k) * 3 + f) * 2 + c];
+                        af.lam_out[((size_t)((s0 + k) * 3 + f) * g.ncoef + idx) * 2 + c] = (m == 0 && c == 1) ? 0.0 : v;
+                    }
+                }
+            }
+            return;
+        }
+    }
     if constexpr (MODE == kAnaForward) {
         if (fuse) {
             // Fused node update of the next sweep (the tendencies never leave the workgroup): the
@@ -741,13 +800,13 @@ static void launch_analysis_variant(const LegPlan& plan, unsigned grid, hipStrea
                                     const Tables& tb, const TT* P, const TT* H,
                                     const long long* toff, const int4* tasks, int nwg,
                                     const void* Gv, int nstates, const double* nscale, double* out,
-                                    const Geom& g, const UpdateArgs& fu, int fuse) {
+                                    const Geom& g, const UpdateArgs& fu, int fuse, const AdjFuse& af) {
     const TT* G = static_cast<const TT*>(Gv);      // the analysis input is stored in the table type
 #define ANA(D, REC)                                                                                 \
     k_analysis_swe<MODE, TT, D, REC><<<grid, kBlock, 0, st>>>(P, H, toff, tasks, nwg,               \
                                                               plan.ana_interleave, G, nstates,      \
                                                               nscale, out, g, fu, fuse, tb.P,       \
-                                                              tb.rc, tb.mu)
+                                                              tb.rc, tb.mu, af)
     if (plan.ana_recur) {
         if (plan.ana_depth == 2) ANA(2, true);
         else ANA(4, true);
@@ -767,24 +826,28 @@ void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long*
     const UpdateArgs none{};
     const UpdateArgs& fu = fuse ? *fuse : none;
     const int mode = fuse ? fuse_mode : 0;
+    const AdjFuse noadj{};
     if (tb.P32)
         launch_analysis_variant<kAnaForward, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, tasks, nwg, G,
-                                                    nstates, neg_lap, out, g, fu, mode);
+                                                    nstates, neg_lap, out, g, fu, mode, noadj);
     else
         launch_analysis_variant<kAnaForward, double>(plan, grid, st, tb, tb.P, tb.H, toff, tasks, nwg, G,
-                                                     nstates, neg_lap, out, g, fu, mode);
+                                                     nstates, neg_lap, out, g, fu, mode, noadj);
 }
 
 void launch_analysis_adjoint(const Tables& tb, const LegPlan& plan, const long long* toff,
                              const int4* tasks, int nwg, const double* G, int nstates,
-                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st) {
+                             const double* inv_lap, double* out_acc, const Geom& g, hipStream_t st,
+                             const AdjFuse* fuse) {
     const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
+    const AdjFuse none{};
+    const AdjFuse& af = fuse ? *fuse : none;
     if (tb.P32)
         launch_analysis_variant<kAnaAdjoint, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, tasks, nwg, G,
-                                                    nstates, inv_lap, out_acc, g, UpdateArgs{}, 0);
+                                                    nstates, inv_lap, out_acc, g, UpdateArgs{}, 0, af);
     else
         launch_analysis_variant<kAnaAdjoint, double>(plan, grid, st, tb, tb.P, tb.H, toff, tasks, nwg, G,
-                                                     nstates, inv_lap, out_acc, g, UpdateArgs{}, 0);
+                                                     nstates, inv_lap, out_acc, g, UpdateArgs{}, 0, af);
 }
 
 // FP32 copies of the FP64 tables (same layout), for the FP32 precision mode.

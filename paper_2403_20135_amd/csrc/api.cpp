@@ -1000,20 +1000,20 @@ void enqueue_adjoint_reverse(sdc_ctx* c, const double2* tape, const double* lam_
     b.last = 1;
     b.first_stage = K == 1;
     b.init_un = 1;
-    launch_update_adj(b, c->st);
     if (c->lplan.fuse_update && (M == 1 || M == 2 || M == 4)) {
         // The adjoint update of sweep s runs in the epilogue of the transposed analysis that
-        // completes its node adjoints and writes the next transposed tendency's input directly;
-        // the first stage's epilogue writes lam_n.
+        // completes its node adjoints, and every update writes the next transposed tendency's
+        // input directly; the first stage's epilogue writes lam_n.
+        b.cml = c->cml;
+        b.cml32 = c->P32 != nullptr ? 1 : 0;
+        b.T = c->g.T;
+        b.m_of = c->m_of;
+        b.rowoff = c->rowoff;
+        b.neg_lap = c->neg_lap;
+        launch_update_adj(b, c->st);
         AdjFuse af{};
         af.m_of = c->m_of;
         af.a = b;
-        af.a.cml = c->cml;
-        af.a.cml32 = c->P32 != nullptr ? 1 : 0;
-        af.a.T = c->g.T;
-        af.a.m_of = c->m_of;
-        af.a.rowoff = c->rowoff;
-        af.a.neg_lap = c->neg_lap;
         af.a.ubar = c->adj_ubar;
         af.a.ubar_node = fs;
         af.a.ubar_member = (long long)M * fs;
@@ -1023,15 +1023,16 @@ void enqueue_adjoint_reverse(sdc_ctx* c, const double2* tape, const double* lam_
         for (int s = K - 1; s >= 1; --s) {
             af.a.sweep = qd_sweep(c, s, M);
             af.a.first_stage = s == 1;
-            run_explicit_adj(c, c->adj_ebar, B * M, save_at(s), c->adj_ubar, &af, s < K - 1);
+            run_explicit_adj(c, c->adj_ebar, B * M, save_at(s), c->adj_ubar, &af, true);
         }
         AdjFuse fin{};
         fin.mode = 2;
         fin.lam_out = lam_n;
         fin.m_of = c->m_of;
-        run_explicit_adj(c, c->adj_ebar, B, save_at(0), c->adj_un, &fin, K > 1);
+        run_explicit_adj(c, c->adj_ebar, B, save_at(0), c->adj_un, &fin, true);
         return;
     }
+    launch_update_adj(b, c->st);
     for (int s = K - 1; s >= 1; --s) {
         run_explicit_adj(c, c->adj_ebar, B * M, save_at(s), c->adj_ubar);
         b.ubar = c->adj_ubar;

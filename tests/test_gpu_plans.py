@@ -38,7 +38,7 @@ def _outputs(sdc, x, lam, dt):
 
 
 @pytest.mark.parametrize("T,nlat,nlon,batch,prec", [(63, 96, 192, 2, "fp64"), (31, 48, 96, 3, "fp32"),
-                                                    (21, 34, 64, 1, "fp64")])
+                                                    (21, 34, 64, 1, "fp64"), (10, 12, 24, 2, "fp64")])
 def test_variants_agree_bitwise(T, nlat, nlon, batch, prec):
     sdc = _sdc(T, nlat, nlon, 3, 3, batch, precision=prec)
     x = _states(T, batch, 301)
@@ -99,8 +99,9 @@ def test_autotune_keeps_results_and_graphs():
     (31, 48, 96, 3, 3, 2, "fp64", "flex"),    # M = 3: the separate update kernel either way
 ])
 def test_fused_update_is_bitwise_the_separate_one(T, nlat, nlon, M, K, batch, prec, qd):
-    """The node update inside the analysis epilogue gives bitwise the same steps (eager and graph),
-    taped steps and adjoints (whose recomputation uses the fused forward) as the update kernel."""
+    """The node updates inside the analysis epilogues (forward and adjoint) give bitwise the same
+    steps (eager and graph), taped steps and adjoints as the separate update kernels, also with
+    both Legendre kernels regenerating their tables."""
     from paper_2403_20135_amd.api import SDC
     torch = _torch()
     sdc = SDC(T, nlat, nlon, M, K, batch, prec, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, qdelta=qd)
@@ -109,8 +110,10 @@ def test_fused_update_is_bitwise_the_separate_one(T, nlat, nlon, M, K, batch, pr
     lam[..., :T + 1, 1] = 0.0
     dt = 600.0
     res = {}
-    for fuse in (1, 0):
-        sdc.set_plan(2, 2, 2, 1, fuse)
+    # plans: separate update kernels (the reference), fused updates, fused updates with both
+    # Legendre kernels regenerating their tables
+    for key, plan in ((0, (2, 2, 2, 1, 0)), (1, (2, 2, 2, 1, 1)), (2, (4, 2, 2, 1, 1, 1, 1))):
+        sdc.set_plan(*plan)
         x, xg = _dev(x0), _dev(x0)
         for _ in range(3):
             sdc.step(x, dt)
@@ -123,9 +126,10 @@ def test_fused_update_is_bitwise_the_separate_one(T, nlat, nlon, M, K, batch, pr
         sdc.step_adjoint_taped(tape, _dev(lam), gb, dt)
         sdc.sync()
         torch.cuda.synchronize()
-        res[fuse] = [_host(v) for v in (x, xg, xt, ga, gb)]
-    for name, a, b in zip(("step", "graph step", "taped step", "adjoint", "taped adjoint"), res[1], res[0]):
-        print(f"[gpu] fused update T{T} M{M}K{K} x{batch} {prec} {name}: max |diff| {np.max(np.abs(a - b)):.3e}",
-              flush=True)
-        assert np.array_equal(a, b), name
+        res[key] = [_host(v) for v in (x, xg, xt, ga, gb)]
+    for key in (1, 2):
+        for name, a, b in zip(("step", "graph step", "taped step", "adjoint", "taped adjoint"), res[key], res[0]):
+            print(f"[gpu] {'fused' if key == 1 else 'fused+regenerated'} T{T} M{M}K{K} x{batch} {prec} {name}: "
+                  f"max |diff| {np.max(np.abs(a - b)):.3e}", flush=True)
+            assert np.array_equal(a, b), (key, name)
     assert np.array_equal(res[1][0], res[1][1])

@@ -425,7 +425,11 @@ def traffic_for(kernel, plan):
         return None
     if t.get("source_sha") != source_hash() or kernel not in t.get("kernels", {}):
         return None
-    if kernel in ("synthesis", "analysis") and t.get("legendre_plan") != plan:
+    # the plan fields that change what each Legendre kernel does per launch
+    fields = {"synthesis": ("syn_lat_tiles", "syn_depth", "syn_recur"),
+              "analysis": ("ana_depth", "ana_interleave", "ana_recur", "fuse_update")}.get(kernel, ())
+    profiled = t.get("legendre_plan") or {}
+    if any(profiled.get(f) != plan.get(f) for f in fields):
         return None
     k = t["kernels"][kernel]
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]

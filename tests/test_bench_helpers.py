@@ -119,8 +119,10 @@ def test_traffic_is_reported_only_for_the_profiled_sources_and_plan(tmp_path, mo
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.traffic_for("analysis", plan) == 3.0
     other = dict(plan, syn_depth=4)
-    assert bench.traffic_for("analysis", other) is None            # another Legendre variant
+    assert bench.traffic_for("synthesis", other) is None           # another synthesis variant
+    assert bench.traffic_for("analysis", other) == 3.0             # the analysis is unchanged
     assert bench.traffic_for("grid", other) == 3.0                 # grid does not depend on it
+    assert bench.traffic_for("analysis", dict(plan, ana_depth=4)) is None
     t["source_sha"] = "0" * 16
     f.write_text(json.dumps(t))
     assert bench.traffic_for("grid", plan) is None                 # other kernel sources

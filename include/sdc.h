@@ -217,8 +217,9 @@ int sdc_timing_read(sdc_handle h, int kernel_class, double* total_ms, long long*
 int sdc_get_info(sdc_handle h, sdc_info* info);
 
 /* Launch variants of the two Legendre kernels (the Legendre parts of the spectral transforms of
- * Section 3.2).  Every variant computes the same sums in the same order, so results are bitwise
- * identical; only the speed differs with truncation, batch and precision.
+ * Section 3.2).  Every variant computes the same sums in the same order from the same table
+ * values (streamed or regenerated), so results are bitwise identical; only the speed differs
+ * with truncation, batch and precision.
  *   syn_lat_tiles, syn_depth: 16-latitude tiles per synthesis workgroup and operand stages in
  *     flight per wave; the built pairs are (1, 8), (1, 4), (2, 4), (2, 2) (the default), (3, 2),
  *     (4, 2), (4, 1), (6, 1).
@@ -248,8 +249,8 @@ typedef struct {
 int sdc_get_plan(sdc_handle h, sdc_plan* plan);
 
 /* Select variants; SDC_EINVAL for a combination that is not built (the handle keeps its plan).
- * fuse_update, syn_recur and ana_recur must be 0 or 1.  Graphs cached by sdc_step_graph are dropped and recaptured on
- * their next call. */
+ * fuse_update, syn_recur and ana_recur must be 0 or 1.  Graphs cached by sdc_step_graph are
+ * dropped and recaptured on their next call. */
 int sdc_set_plan(sdc_handle h, const sdc_plan* plan);
 
 /* Autotuner: times every built synthesis variant and every analysis variant on the handle's

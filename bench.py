@@ -537,8 +537,8 @@ def main():
         summarize_pmc(f, w, float(mib), outp, [flog, wlog])
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the step on a single MI355X "
-              "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the step on a single MI355X "
+              "(sharding across GPUs is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -62,7 +62,7 @@ typedef enum {
                                  spectral / Fourier columns rounded to FP32 as they enter the MFMA,
                                  FP32 accumulation; every other step of sdc_step stays FP64 */
     SDC_BF16X3_MFMA = 2       /* operands split into three BF16 terms each, BF16 MFMA products,
-                                 FP32 accumulation: sdc_init returns SDC_EUNSUPPORTED in this build
+                                 FP32 accumulation: not implemented, sdc_init returns SDC_EUNSUPPORTED
                                  (one member at T255 is table-bandwidth-bound, where three BF16
                                  terms move more bytes than one FP32 value) */
 } sdc_precision;

@@ -300,7 +300,7 @@ int validate_config(const sdc_config* c) {
     if (!make_fft_plan(c->nlon, pl) || !fft_length_supported(c->nlon))
         return fail(SDC_EUNSUPPORTED, "nlon=%d is not one of 16..2048 = 2^p or 24..1536 = 3*2^p", c->nlon);
     if (c->precision == SDC_BF16X3_MFMA)
-        return fail(SDC_EUNSUPPORTED, "precision=%d (BF16x3) is not available in this build", c->precision);
+        return fail(SDC_EUNSUPPORTED, "precision=%d (BF16x3) is not implemented by this library", c->precision);
     return SDC_OK;
 }
 

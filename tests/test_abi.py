@@ -42,7 +42,7 @@ def test_every_declared_function_is_exported():
     (dict(mean_depth=0.0), _lib.SDC_EINVAL),
     (dict(nlon=100), _lib.SDC_EUNSUPPORTED),            # not 2^p or 3*2^p
     (dict(nlon=4096, T=31), _lib.SDC_EUNSUPPORTED),
-    (dict(precision=2), _lib.SDC_EUNSUPPORTED),         # BF16x3 not in this build
+    (dict(precision=2), _lib.SDC_EUNSUPPORTED),         # BF16x3 not implemented
 ])
 def test_init_rejects_invalid_config_on_host(kw, code):
     lib = _lib.load()

@@ -621,10 +621,16 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         }
     };
 
-    GV gr[NC];
-    gload(gr, 0);
-    gstore(gr, 0, 0);
+    // The columns of block b + 2 are requested while block b is contracted, into the register set
+    // that held block b (staged already); block b + 1, requested an iteration earlier, is staged
+    // into LDS after the contraction.  Two register sets alternate with the block's parity (D is
+    // even, so the set of block b0 + u is u & 1).
+    GV gr[2][NC];
+    gload(gr[0], 0);
+    gload(gr[1], nb > 1 ? 1 : 0);
+    gstore(gr[0], 0, 0);
     __syncthreads();
+    static_assert(D % 2 == 0, "the column register sets alternate with the block parity");
     if (active) {
         AnaStage<TT, REC> st[D];
 #pragma unroll
@@ -634,11 +640,11 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
 #pragma unroll
             for (int u = 0; u < D; ++u) {
                 const int b = b0 + u;
-                gload(gr, b + 1 < nb ? b + 1 : nb - 1);
+                gload(gr[u & 1], b + 2 < nb ? b + 2 : nb - 1);
                 compute(st[u], gl[b & 1]);
                 const int bn = b + D;
                 load(st[u], bn < nb ? bn : nb - 1);          // past the end: re-read, unused
-                gstore(gr, b + 1, (b + 1) & 1);
+                gstore(gr[(u + 1) & 1], b + 1, (b + 1) & 1);
                 __syncthreads();
             }
         }
@@ -646,18 +652,23 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         for (int u = 0; u < D; ++u) {
             const int b = b0 + u;
             if (b < nb) {                                    // uniform
-                gload(gr, b + 1 < nb ? b + 1 : nb - 1);
+                gload(gr[u & 1], b + 2 < nb ? b + 2 : nb - 1);
                 compute(st[u], gl[b & 1]);
-                gstore(gr, b + 1, (b + 1) & 1);
+                gstore(gr[(u + 1) & 1], b + 1, (b + 1) & 1);
                 __syncthreads();
             }
         }
     } else {
         // rows past the order's end: this wave only helps move the columns
-        for (int b = 0; b < nb; ++b) {
-            gload(gr, b + 1 < nb ? b + 1 : nb - 1);
-            gstore(gr, b + 1, (b + 1) & 1);
+        for (int b = 0; b < nb; b += 2) {
+            gload(gr[0], b + 2 < nb ? b + 2 : nb - 1);
+            gstore(gr[1], b + 1, (b + 1) & 1);
             __syncthreads();
+            if (b + 1 < nb) {                                // uniform
+                gload(gr[1], b + 3 < nb ? b + 3 : nb - 1);
+                gstore(gr[0], b + 2, (b + 2) & 1);
+                __syncthreads();
+            }
         }
         if (!fuse && !(MODE == kAnaAdjoint && af.mode)) return;   // uniform
     }

@@ -82,12 +82,14 @@ def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=Fal
     FP32 in the FP32 mode) and spectral output (3 complex).
     Grid (bytes): reads 4 Fourier fields (FP64) and writes 5 (the minimal output; stored in the
     table precision), nlat*(T+1) complex each per state.
+    The streaming synthesis of a step's first f_E reads u_n in the state layout (3 complex per
+    coefficient); the regenerating one takes it converted (3 -> 4 complex, an update-class launch).
     Update (bytes): per coefficient and member, reads u_n (3 complex), per node j the Phi', delta
     of u_j (2) and E_j (3), writes the updated nodes (3 each) and their synthesis-layout copy
-    (4 each); the last sweep writes node M only; the first f_E of a step converts u_n (3 -> 4).
+    (4 each); the last sweep writes node M only.
     fused (the node update inside the analysis epilogue, M in {1, 2, 4}): the tendencies never
     reach HBM, so the analysis loses its spectral output and gains the update's other bytes, and
-    the update class keeps only the conversion of u_n.
+    the update class keeps only that conversion.
     syn_recur (the synthesis regenerates its tables): the synthesis reads the recurrence
     coefficients (4 FP64 per (m, n), n < T + 16) and the sectoral values (FP64 per m and northern
     latitude) instead of the tables.
@@ -102,14 +104,17 @@ def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=Fal
     if syn_recur:
         nhp = (nlat // 2 + 15) // 16 * 16
         syn_tables = (32.0 * (T + 1) * (T + 16) + 8.0 * (T + 1) * nhp) * launches
-    syn_bytes = syn_tables + states * (4 * col * ncoef + 4 * 16.0 * nlat * (T + 1))
+    first_in = 4 * col if syn_recur else 3 * 16.0          # u_n converted, or read in place
+    syn_bytes = syn_tables + (states - batch) * 4 * col * ncoef + batch * first_in * ncoef \
+        + states * 4 * 16.0 * nlat * (T + 1)
     ana_bytes = tables + states * (7 * col * nlat * (T + 1) + 3 * 16.0 * ncoef)
     grid_bytes = (4 * 16.0 + 5 * col) * nlat * (T + 1) * states
-    upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + 7)
+    conv = 7.0 if syn_recur else 0.0                         # u_n -> synthesis layout (3 -> 4)
+    upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + conv)
     if fused:
         ana_bytes += batch * ncoef * 16.0 * ((K - 1) * (3 + 9 * M) + (3 + 2 * M + 3)) \
             - states * 3 * 16.0 * ncoef
-        upd_bytes = batch * ncoef * 16.0 * 7
+        upd_bytes = batch * ncoef * 16.0 * conv
     return {"synthesis": (6 * transform * states, syn_bytes),
             "analysis": (7 * transform * states, ana_bytes),
             "grid": (0.0, grid_bytes), "update": (0.0, upd_bytes)}

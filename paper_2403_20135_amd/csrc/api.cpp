@@ -249,7 +249,7 @@ struct sdc_ctx {
         for (auto& v : ev_marks) v.clear();
     }
 
-    Tables tables() const { return Tables{P, H, P32, H32, rc, sect, mu}; }
+    Tables tables() const { return Tables{P, H, P32, H32, rc, sect, mu, inv_lap}; }
 
     template <typename T>
     int alloc(T*& p, size_t count, bool table = false) {
@@ -446,13 +446,13 @@ int setup(sdc_ctx* c) {
     return SDC_OK;
 }
 
-// f_E of S states whose synthesis input is already in c->cml (written by the update kernel or
-// by launch_prep_cml).
+// f_E of S states whose synthesis input is already in c->cml (written by the update kernels), or,
+// with states != null, read by the synthesis from the state layout.
 void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr,
-                      const UpdateArgs* fuse = nullptr, int fuse_mode = 0) {
+                      const UpdateArgs* fuse = nullptr, int fuse_mode = 0, const double* states = nullptr) {
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
     launch_synthesis_swe(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
-                         c->cml, S, c->four, c->g, c->st);
+                         c->cml, S, c->four, c->g, c->st, states);
     c->end(SDC_KERNEL_SYNTHESIS, t);
     t = c->begin(SDC_KERNEL_GRID);
     launch_grid_swe(c->four, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega, save, c->g, c->st);
@@ -463,8 +463,14 @@ void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr,
     c->end(SDC_KERNEL_ANALYSIS, t);
 }
 
+// f_E of S states in the state layout: a streaming synthesis reads them directly; the regenerating
+// synthesis (no state-input form) takes them converted to the synthesis layout.
 void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2* save = nullptr,
                   const UpdateArgs* fuse = nullptr, int fuse_mode = 0) {
+    if (!c->lplan.syn_recur) {
+        run_explicit_cml(c, S, out, save, fuse, fuse_mode, states);
+        return;
+    }
     const long t = c->begin(SDC_KERNEL_UPDATE);
     launch_prep_cml(states, S, c->cml, c->P32 != nullptr, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->g.T, c->st);
     c->end(SDC_KERNEL_UPDATE, t);

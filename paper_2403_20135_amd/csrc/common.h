@@ -178,11 +178,15 @@ struct Tables {
     const double* rc;        // recurrence coefficients and sectoral values for the synthesis
     const double* sect;      // that regenerates the tables (LegPlan::syn_recur)
     const double* mu;
+    const double* inv_lap;   // -a^2 / (n (n + 1)) per degree (state-input synthesis)
 };
 // Synthesis tasks: (m, latitude tile) per workgroup, XCD-ordered; x < 0 = pad.
+// state_in != null: the input columns are read from nstates states in the state layout (the
+// forward synthesis of a step's first f_E) instead of cml.
 void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
                           const int* rowoff, const int2* tasks, int ntasks, const double* cml,
-                          int nstates, double2* four, const Geom& g, hipStream_t st);
+                          int nstates, double2* four, const Geom& g, hipStream_t st,
+                          const double* state_in = nullptr);
 // Analysis tasks: (m, p, first row, valid) per workgroup, XCD-ordered.
 // With fuse != null the tendencies are not written: the kernel applies the node update `*fuse`
 // to them (fuse_mode 1: the states are members, as in the step's first f_E; 2: the states are

@@ -143,12 +143,19 @@ __device__ __forceinline__ void transpose_rows4(double (&v)[4]) {
         v[k] = __longlong_as_double((long long)(((unsigned long long)hi[k] << 32) | lo[k]));
 }
 
-template <int MODE, typename TT, int JT, int D, bool REC>
+//
+// SIN (forward, streamed tables): the input columns are read from the state layout itself
+// ([state][Phi', zeta, delta][ncoef] complex) instead of the synthesis layout: value v is zeta
+// (v < 2), Phi' (v < 4) or inv_lap[n] times zeta or delta (v >= 4), part v & 1, formed with the
+// same products and roundings as the conversion kernel, so a step's first f_E needs no
+// conversion launch and gives the same results bit for bit.
+template <int MODE, typename TT, int JT, int D, bool REC, bool SIN = false>
 __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int* __restrict__ rowoff, const int2* __restrict__ tasks, const TT* __restrict__ cml,
     int nstates, double* __restrict__ four, Geom g, const double* __restrict__ rc,
-    const double* __restrict__ sect, const double* __restrict__ mu) {
+    const double* __restrict__ sect, const double* __restrict__ mu,
+    const double* __restrict__ sin_state, const double* __restrict__ inv_lap) {
     using TL = SynTiles<MODE>;
     using MM = Mma<TT>;
     constexpr int NT = TL::NT;
@@ -195,6 +202,21 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     unsigned boff[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * tsz;
+    static_assert(!SIN || (MODE == kSynForward && !REC), "state input: forward, streamed tables");
+    size_t soff[NT];
+    bool sscale[NT];
+    const int npk = npk_of(g.T, m, p);
+    if constexpr (SIN) {
+        const size_t fsd = (size_t)g.ncoef * 2;
+        const size_t c0 = (size_t)coef_offset(g.T, m) * 2;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int vv = TL::col(t, v);
+            const int field = vv < 2 ? 1 : (vv < 4 ? 0 : (vv < 6 ? 1 : 2));
+            soff[t] = ((size_t)sc * 3 + field) * fsd + c0 + (vv & 1);
+            sscale[t] = vv >= 4;
+        }
+    }
     const unsigned rstride = (unsigned)S * kCmlVals * tsz;          // bytes per cml row
     const int nst = (npk_of(g.T, m, p) + 3) >> 2;                   // 4-row steps of this parity
     const unsigned tstep = 4u * 16u * tsz, cstep = 4u * rstride;    // bytes per 4-row step
@@ -225,8 +247,21 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
                 x.a[u][1] = ldt(tH, ot);
             }
         }
+        if constexpr (SIN) {
+            // rows past the order's end read its last row and contribute zero
+            const int kk = 4 * j + q;
+            const int dn = p + 2 * (kk < npk ? kk : npk - 1);          // n - m
+            const double il = inv_lap[m + dn];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) x.b[t] = ldt(cb, oc + boff[t]);
+            for (int t = 0; t < NT; ++t) {
+                const double val = sin_state[soff[t] + 2 * (size_t)dn];
+                const double w = sscale[t] ? il * val : val;
+                x.b[t] = kk < npk ? (TT)w : (TT)0;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) x.b[t] = ldt(cb, oc + boff[t]);
+        }
     };
     auto mma_all = [&](const TT (&a)[JT][2], const TT (&b)[NT]) {
 #pragma unroll
@@ -340,14 +375,29 @@ template <int MODE, typename TT>
 static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t st,
                                      const Tables& tb, const TT* P, const TT* H,
                                      const long long* toff, const int* rowoff, const int2* tasks,
-                                     const double* cml, int nstates, double* four, const Geom& g) {
+                                     const double* cml, int nstates, double* four, const Geom& g,
+                                     const double* state_in) {
     const TT* cmlt = reinterpret_cast<const TT*>(cml);    // stored in the table type
-#define SYN(JT, D)                                                                                  \
-    k_synthesis<MODE, TT, JT, D, false><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cmlt, \
-                                                                   nstates, four, g, tb.rc, tb.sect, tb.mu)
-#define SYN_REC(JT, D)                                                                              \
-    k_synthesis<MODE, TT, JT, D, true><<<grid, kSynBlock, 0, st>>>(P, H, toff, rowoff, tasks, cmlt, \
-                                                                  nstates, four, g, tb.rc, tb.sect, tb.mu)
+#define SYN_ARGS P, H, toff, rowoff, tasks, cmlt, nstates, four, g, tb.rc, tb.sect, tb.mu, state_in, tb.inv_lap
+#define SYN(JT, D) k_synthesis<MODE, TT, JT, D, false><<<grid, kSynBlock, 0, st>>>(SYN_ARGS)
+#define SYN_REC(JT, D) k_synthesis<MODE, TT, JT, D, true><<<grid, kSynBlock, 0, st>>>(SYN_ARGS)
+#define SYN_SIN(JT, D) k_synthesis<MODE, TT, JT, D, false, true><<<grid, kSynBlock, 0, st>>>(SYN_ARGS)
+    if constexpr (MODE == kSynForward) {
+        if (state_in) {
+            // the state-input variants stream the tables, at the plan's shape (the task list
+            // follows the shape; every regenerating shape is also built streaming)
+            const int jt = plan.syn_tiles, d = plan.syn_depth;
+            if (jt == 6) SYN_SIN(6, 1);
+            else if (jt == 4 && d == 1) SYN_SIN(4, 1);
+            else if (jt == 4) SYN_SIN(4, 2);
+            else if (jt == 3) SYN_SIN(3, 2);
+            else if (jt == 2 && d == 2) SYN_SIN(2, 2);
+            else if (jt == 2) SYN_SIN(2, 4);
+            else if (d == 4) SYN_SIN(1, 4);
+            else SYN_SIN(1, 8);
+            return;
+        }
+    }
     if (plan.syn_recur) {
         if (plan.syn_tiles == 4 && plan.syn_depth == 1) SYN_REC(4, 1);
         else if (plan.syn_tiles == 4) SYN_REC(4, 2);
@@ -365,18 +415,21 @@ static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t
     else SYN(1, 8);
 #undef SYN
 #undef SYN_REC
+#undef SYN_SIN
+#undef SYN_ARGS
 }
 
 void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long* toff,
                           const int* rowoff, const int2* tasks, int ntasks, const double* cml,
-                          int nstates, double2* four, const Geom& g, hipStream_t st) {
+                          int nstates, double2* four, const Geom& g, hipStream_t st,
+                          const double* state_in) {
     const dim3 grid(ntasks, (nstates + 3) / 4);
     if (tb.P32)
         launch_synthesis_variant<kSynForward, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, rowoff,
-                                                     tasks, cml, nstates, (double*)four, g);
+                                                     tasks, cml, nstates, (double*)four, g, state_in);
     else
         launch_synthesis_variant<kSynForward, double>(plan, grid, st, tb, tb.P, tb.H, toff, rowoff,
-                                                      tasks, cml, nstates, (double*)four, g);
+                                                      tasks, cml, nstates, (double*)four, g, state_in);
 }
 
 void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long* toff,
@@ -385,10 +438,10 @@ void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long
     const dim3 grid(ntasks, (nstates + 3) / 4);
     if (tb.P32)
         launch_synthesis_variant<kSynAdjoint, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, rowoff,
-                                                     tasks, cml, nstates, (double*)four5, g);
+                                                     tasks, cml, nstates, (double*)four5, g, nullptr);
     else
         launch_synthesis_variant<kSynAdjoint, double>(plan, grid, st, tb, tb.P, tb.H, toff, rowoff,
-                                                      tasks, cml, nstates, (double*)four5, g);
+                                                      tasks, cml, nstates, (double*)four5, g, nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------

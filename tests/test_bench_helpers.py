@@ -29,7 +29,9 @@ def test_algorithmic_work_counts():
     wf = bench.algorithmic_work(T, nlat, M, K, 1, "fp64", fused=True)
     e_bytes = 16.0 * ncoef * (3 * states + 3 * M * K)
     assert wf["analysis"][1] + wf["update"][1] == pytest.approx(w["analysis"][1] + w["update"][1] - e_bytes)
-    assert wf["update"][1] == pytest.approx(7 * 16.0 * ncoef)
+    assert wf["update"][1] == 0.0                                 # no update-class launch left
+    assert bench.algorithmic_work(T, nlat, M, K, 1, "fp64", True, True)["update"][1] == \
+        pytest.approx(7 * 16.0 * ncoef)                           # u_n conversion (regenerating)
     assert wf["synthesis"] == w["synthesis"] and wf["grid"] == w["grid"]
     # regenerated synthesis tables: same flops, the table bytes replaced by the small recurrence data
     wr = bench.algorithmic_work(T, nlat, M, K, 1, "fp64", syn_recur=True)

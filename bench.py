@@ -458,7 +458,8 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     plan = plans[0]
     # forward FP64 kernels of the bench workload (names as rocprofv3 prints them)
     rec = "true" if plan.get("syn_recur") else "false"
-    classes = {f"void k_synthesis<0, double, {plan['syn_lat_tiles']}, {plan['syn_depth']}, {rec}>": "synthesis",
+    # every synthesis launch of the step (the first one reads the state in place: a second flag)
+    classes = {f"void k_synthesis<0, double, {plan['syn_lat_tiles']}, {plan['syn_depth']}, {rec},": "synthesis",
                f"void k_analysis_swe<0, double, {plan['ana_depth']}, "
                f"{'true' if plan.get('ana_recur') else 'false'}>": "analysis",
                "void k_grid_swe<": "grid", "void k_update<": "update"}
@@ -481,16 +482,22 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     w_scale = copy_bytes / (max(cw) * 1024.0)
     out["fetch_scale"], out["write_scale"] = f_scale, w_scale
     out["legendre_plan"] = plan
+    acc = {}                        # per class: every dispatch of every kernel of the class
     for name, vals in fetch.items():
         cls = next((c for key, c in classes.items() if name.startswith(key)), None)
         if cls is None:
             continue
-        wv = write.get(name, [0.0])
-        out["kernels"].setdefault(cls, {
-            "kernel_name": name.split("(")[0],
-            "dispatches": len(vals),
-            "fetch_bytes_per_launch": sum(vals) / len(vals) * 1024.0 * f_scale,
-            "write_bytes_per_launch": sum(wv) / len(wv) * 1024.0 * w_scale})
+        a = acc.setdefault(cls, {"names": set(), "fetch": [], "write": []})
+        a["names"].add(name.split("(")[0])
+        a["fetch"] += vals
+        a["write"] += write.get(name, [])
+    for cls, a in acc.items():
+        wv = a["write"] or [0.0]
+        out["kernels"][cls] = {
+            "kernel_name": " + ".join(sorted(a["names"])),
+            "dispatches": len(a["fetch"]),
+            "fetch_bytes_per_launch": sum(a["fetch"]) / len(a["fetch"]) * 1024.0 * f_scale,
+            "write_bytes_per_launch": sum(wv) / len(wv) * 1024.0 * w_scale}
     with open(out_json, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))

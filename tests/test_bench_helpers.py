@@ -70,17 +70,19 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     copy_kib = 256 * 1024 / 2.0                                   # counter reads half the bytes
     _csv(tmp_path / "f.csv", "FETCH_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", copy_kib),
-        ("void k_synthesis<0, double, 2, 2, true>(double const*)", 1000.0),
-        ("void k_synthesis<0, double, 2, 2, true>(double const*)", 3000.0),
-        ("void k_synthesis<0, double, 1, 8, true>(double const*)", 99999.0),   # an autotuner trial
-        ("void k_synthesis<0, double, 2, 2, false>(double const*)", 77777.0),  # table-reading trial
+        ("void k_synthesis<0, double, 2, 2, true, false>(double const*)", 1000.0),
+        ("void k_synthesis<0, double, 2, 2, true, false>(double const*)", 3000.0),
+        ("void k_synthesis<0, double, 2, 2, true, true>(double const*)", 2000.0),    # first launch
+        ("void k_synthesis<0, double, 1, 8, true, false>(double const*)", 99999.0),   # an autotuner trial
+        ("void k_synthesis<0, double, 2, 2, false, false>(double const*)", 77777.0),  # table-reading trial
         ("void k_analysis_swe<0, double, 2, false>(double const*)", 500.0),
         ("void k_analysis_swe<0, double, 2, true>(double const*)", 88888.0),     # regenerating trial
         ("void k_grid_swe<768, double>(x)", 10.0),
         ("void k_update<4>(UpdateArgs)", 20.0)])
     _csv(tmp_path / "w.csv", "WRITE_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", 256 * 1024.0),
-        ("void k_synthesis<0, double, 2, 2, true>(double const*)", 100.0),
+        ("void k_synthesis<0, double, 2, 2, true, false>(double const*)", 100.0),
+        ("void k_synthesis<0, double, 2, 2, true, true>(double const*)", 100.0),
         ("void k_analysis_swe<0, double, 2, false>(double const*)", 50.0),
         ("void k_grid_swe<768, double>(x)", 40.0),
         ("void k_update<4>(UpdateArgs)", 30.0)])
@@ -89,7 +91,9 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     t = json.loads(out.read_text())
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
     syn = t["kernels"]["synthesis"]
-    assert syn["kernel_name"] == "void k_synthesis<0, double, 2, 2, true>"
+    assert syn["kernel_name"] == ("void k_synthesis<0, double, 2, 2, true, false> + "
+                                  "void k_synthesis<0, double, 2, 2, true, true>")
+    assert syn["dispatches"] == 3
     assert syn["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
     assert syn["write_bytes_per_launch"] == pytest.approx(100.0 * 1024)
     assert set(t["kernels"]) == {"synthesis", "analysis", "grid", "update"}

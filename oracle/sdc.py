@@ -9,9 +9,11 @@ solved with the routine for u - alpha f_I(u) = beta, alpha = dt q^D_{m,m}.  The 
 sweeps update every node from the previous sweep's values (the loop the paper runs in
 parallel); the K-th sweep updates only the last node, whose value is the new state
 (tau_M = 1 for Radau-right nodes).  f_E and f_I are not evaluated at that final iterate.
-MIN-SR-FLEX: q^D_{m,m} = tau_m / s in sweep s = 1..K (readings: the sweep index in the
-coefficient is the 1-based sweep count; the initial guess is the state at the start of the
-step; f_I of a new iterate is evaluated, not recovered from the solve).
+MIN-SR-FLEX: q^D_{m,m} = tau_m / min(s, M) in sweep s = 1..K (readings: the sweep index in
+the coefficient is the 1-based sweep count; the paper defines the coefficients for sweeps 1..M
+only, and sweeps beyond M -- K > M, used by tests only -- keep tau_m / M; the initial guess is
+the state at the start of the step; f_I of a new iterate is evaluated, not recovered from the
+solve).
 
 `imex_sdc_step` is the sequential IMEX SDC of Algorithm 1 (the method dSDC parallelises).
 

@@ -22,8 +22,11 @@ paper does for its spectral code:
       delta = beta_delta + alpha n(n+1)/a^2 Phi'.
 
 States are complex tensors [..., 3, ncoef] in the field order (Phi', zeta, delta).
-Pins: tests/test_oracle_swe.py (steady balanced zonal flow, mass conservation, solid-body
-advection, solve residual).
+Pins: tests/test_oracle_swe.py (steady balanced zonal flow, mass conservation, solve residual;
+non-zonal flow: the Rossby-Haurwitz single-degree wave, solid-body advection of Phi', the
+Coriolis linear part with its n +- 1 couplings, and the cross terms of a perturbation with
+solid-body rotation -- each of these closed forms derived from the equations above, and each
+shown to fail for planted sign slips).
 """
 from __future__ import annotations
 

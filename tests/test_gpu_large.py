@@ -5,9 +5,10 @@ adjoint step against central differences of the GPU step (dot-product test).
 Tolerance at T511.  Gauss nodes computed by two correct FP64 Newton iterations may differ by one
 ulp; near the poles that moves the weights by ~1e-11 relative and the tables by ~1e-12, and the
 divergence tendency (which carries n(n+1)/a^2 times the kinetic energy) amplifies it further.  The
-FP64 bar is therefore the larger of the plain-path target (1e-12 for f_E, 1e-11 for a step) and
-three times the oracle's own spread: the oracle evaluated on nodes moved by one ulp (weights
-recomputed by its own formula), per field.
+FP64 bar of a single f_E evaluation is therefore the larger of 1e-12 and three times the oracle's
+own spread: the oracle evaluated on nodes moved by one ulp (weights recomputed by its own formula),
+per field.  A whole step is held to the plain-path target 1e-11 (the spread is printed beside
+it).
 
 The FP32 bar 2 (T+1) u_32 holds for an output as well conditioned as Phi' (a plain divergence of
 fluxes).  The divergence tendency is a curl plus a Laplacian of the kinetic energy, whose factor
@@ -83,7 +84,7 @@ def test_t511_step_fp64(oracles):
     spread = _per_field(o1.step(x0[0], DT, M, K)[None], ref)
     err = _per_field(_host(x), ref)
     for k, name in enumerate(("Phi'", "zeta", "delta")):
-        tol = max(1e-11, 3 * spread[k])
+        tol = 1e-11
         print(f"[gpu] T511 step {name}: rel L2 {err[k]:.3e} (oracle 1-ulp spread {spread[k]:.2e}, "
               f"tol {tol:.2e})", flush=True)
         assert err[k] <= tol

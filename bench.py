@@ -70,49 +70,46 @@ def source_hash() -> str:
 
 
 def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=False):
-    """Algorithmic work of every kernel class over one step: {class: (flops, bytes)}.
+    """Algorithmic work of every kernel class over one step: {class: (flops, bytes)}.  Bytes are
+    the minimum each class must move, independent of the layouts the kernels use.
 
     Legendre: one scalar-equivalent complex transform with equatorial symmetry costs
     2*ncoef*nlat flops; synthesis does 6 per state (zeta, Phi', psi and chi with Pbar, psi and chi
     with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).  Bytes: both tables (Pbar, H:
-    ncoef x nlat/2 entries each) once per launch, plus per state the spectral input (4 complex per
-    coefficient, in the table precision) and Fourier output (4 fields x nlat x (T+1) complex, FP64)
-    of the synthesis, and the
-    analysis input (7 weighted columns x (T+1) x nlat complex, stored in the table precision:
-    FP32 in the FP32 mode) and spectral output (3 complex).
-    Grid (bytes): reads 4 Fourier fields (FP64) and writes 5 (the minimal output; stored in the
-    table precision), nlat*(T+1) complex each per state.
-    The streaming synthesis of a step's first f_E reads u_n in the state layout (3 complex per
-    coefficient); the regenerating one takes it converted (3 -> 4 complex, an update-class launch).
-    Update (bytes): per coefficient and member, reads u_n (3 complex), per node j the Phi', delta
-    of u_j (2) and E_j (3), writes the updated nodes (3 each) and their synthesis-layout copy
-    (4 each); the last sweep writes node M only.
-    fused (the node update inside the analysis epilogue, M in {1, 2, 4}): the tendencies never
-    reach HBM, so the analysis loses its spectral output and gains the update's other bytes, and
-    the update class keeps only that conversion.
+    ncoef x nlat/2 entries each) once per launch; per state the synthesis reads the state
+    (3 complex per coefficient, at the column precision: the FP32 mode rounds the columns to
+    FP32) and writes 4 Fourier fields (nlat x (T+1) complex FP64); the analysis reads 5 Fourier
+    fields (A..E, nlat x (T+1) complex at the column precision) and writes 3 complex per
+    coefficient.  Grid: reads 4 Fourier fields (FP64), writes 5 (column precision).
+    Update (separate kernel): per coefficient and member, each full sweep reads u_n (3 complex)
+    and per node j the Phi', delta of u_j (2) and E_j (3), and writes node m (3); the last sweep
+    writes node M only.
+    fused (the node update in the analysis epilogue, M in {1, 2, 4}): the tendencies never reach
+    HBM, so the analysis loses its spectral output and gains per coefficient and member
+    (K-1)(3 + 5M) + (6 + 2M) complex (u_n, Phi' and delta of the nodes, the new nodes).
     syn_recur (the synthesis regenerates its tables): the synthesis reads the recurrence
     coefficients (4 FP64 per (m, n), n < T + 16) and the sectoral values (FP64 per m and northern
-    latitude) instead of the tables.
+    latitude) instead of the tables; u_n is first converted to the synthesis layout (3 complex in,
+    4 out, an update-class launch).
     """
     ncoef = (T + 1) * (T + 2) // 2
     transform = 2.0 * ncoef * nlat
     states = batch * (1 + (K - 1) * M)          # states transformed per step
     launches = K                                 # Legendre launches per step (one per sweep + first)
     tables = 2.0 * ncoef * (nlat // 2) * TABLE_BYTES[precision] * launches
-    col = 2.0 * TABLE_BYTES[precision]          # coefficient columns are stored in the table type
+    col = 2.0 * TABLE_BYTES[precision]          # one complex value at the column precision
+    four = nlat * (T + 1)                        # Fourier coefficients of one field
     syn_tables = tables
     if syn_recur:
         nhp = (nlat // 2 + 15) // 16 * 16
         syn_tables = (32.0 * (T + 1) * (T + 16) + 8.0 * (T + 1) * nhp) * launches
-    first_in = 4 * col if syn_recur else 3 * 16.0          # u_n converted, or read in place
-    syn_bytes = syn_tables + (states - batch) * 4 * col * ncoef + batch * first_in * ncoef \
-        + states * 4 * 16.0 * nlat * (T + 1)
-    ana_bytes = tables + states * (7 * col * nlat * (T + 1) + 3 * 16.0 * ncoef)
-    grid_bytes = (4 * 16.0 + 5 * col) * nlat * (T + 1) * states
+    syn_bytes = syn_tables + states * (3 * col * ncoef + 4 * 16.0 * four)
+    ana_bytes = tables + states * (5 * col * four + 3 * 16.0 * ncoef)
+    grid_bytes = (4 * 16.0 + 5 * col) * four * states
     conv = 7.0 if syn_recur else 0.0                         # u_n -> synthesis layout (3 -> 4)
-    upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 12 * M) + (3 + 5 * M + 3) + conv)
+    upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 8 * M) + (6 + 5 * M) + conv)
     if fused:
-        ana_bytes += batch * ncoef * 16.0 * ((K - 1) * (3 + 9 * M) + (3 + 2 * M + 3)) \
+        ana_bytes += batch * ncoef * 16.0 * ((K - 1) * (3 + 5 * M) + (6 + 2 * M)) \
             - states * 3 * 16.0 * ncoef
         upd_bytes = batch * ncoef * 16.0 * conv
     return {"synthesis": (6 * transform * states, syn_bytes),
@@ -462,7 +459,9 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     classes = {f"void k_synthesis<0, double, {plan['syn_lat_tiles']}, {plan['syn_depth']}, {rec},": "synthesis",
                f"void k_analysis_swe<0, double, {plan['ana_depth']}, "
                f"{'true' if plan.get('ana_recur') else 'false'}>": "analysis",
-               "void k_grid_swe<": "grid", "void k_update<": "update"}
+               "void k_grid_swe<": "grid", "void k_update<": "update",
+               # the conversion of u_n to the synthesis layout (regenerating plans only)
+               "k_prep_cml(": "update", "void k_prep_cml(": "update"}
 
     def per_kernel(path, counter):
         acc = {}
@@ -503,21 +502,157 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     print(json.dumps(out))
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def sphere_rel_l2(got, ref, T):
+    """Relative L2 (sphere norm, sqrt(sum_m s_m |c|^2) by Parseval) per field (Phi', zeta, delta),
+    maximised over members; got, ref [members][3][ncoef][2]."""
+    import numpy as np
+    _, m = W.degree_order_arrays(T)
+    s = np.where(m == 0, 1.0, 2.0)[:, None]
+    got = np.asarray(got).reshape(-1, 3, len(m), 2)
+    ref = np.asarray(ref).reshape(-1, 3, len(m), 2)
+    out = {}
+    for f, name in enumerate(("phi", "zeta", "delta")):
+        worst = 0.0
+        for a, b in zip(got[:, f], ref[:, f]):
+            num, den = float(np.sum(s * (a - b) ** 2)), float(np.sum(s * b ** 2))
+            worst = max(worst, math.sqrt(num / den) if den > 0 else math.sqrt(num))
+        out[name] = worst
+    out["max"] = max(out.values())
+    return out
+
+
 def cpu_baseline(wl, state0, budget_s=15.0):
+    """The CPU-baseline leg: the FP64 oracle timed on the host cores (all threads torch uses over
+    n steps, n sized to about budget_s, then one step on one thread), and, untimed, the oracle's
+    references for the error of every GPU result the line reports: the headline state after 1 and
+    1 + n steps from state0, the VJP of one headline step, one member of each truncation of the
+    mixed ensemble after 2 steps, and one T511 step."""
     import torch
     from oracle.sdc import Oracle
     mb = wl.members[0]
     o = Oracle(mb.T, mb.nlat, mb.nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
     t0 = time.perf_counter()
-    x = o.step(state0, mb.dt, wl.M, wl.K, steps=1)
+    x1 = o.step(state0, mb.dt, wl.M, wl.K, steps=1)
     t1 = time.perf_counter() - t0
     n = max(1, min(20, int(budget_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
-    o.step(x, mb.dt, wl.M, wl.K, steps=n)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+    xn = o.step(x1, mb.dt, wl.M, wl.K, steps=n)
+    dt_all = time.perf_counter() - t0
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.step(x1, mb.dt, wl.M, wl.K, steps=1)
+        dt_one = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(threads)
+    base = {"value": n / dt_all, "unit": "steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} dSDC steps of {wl.name} (T{mb.T} {mb.nlat}x{mb.nlon}, M={wl.M}, K={wl.K}) "
-                      f"after 1 untimed step, torch-CPU float64 oracle"}
+                      f"after 1 untimed step, torch-CPU float64 oracle, {threads} threads",
+            "single_thread": {"value": 1.0 / dt_one, "unit": "steps/s", "cores": 1,
+                              "sample": "1 step of the same workload on one thread"},
+            "host": host_cpu()}
+    refs = {"after": {1: x1, 1 + n: xn}}
+    if wl.name != "t255_m4k4":
+        return base, refs
+    lam = W.random_state(mb.T, 255)
+    lam[:, :mb.T + 1, 1] = 0.0                       # m = 0 imaginary parts are held at 0
+    refs["lam"] = lam
+    refs["vjp"] = o.step_vjp(state0, lam, mb.dt, wl.M, wl.K)
+    mix = W.WORKLOADS["mixed32_m4k3"]
+    refs["mixed"] = {}
+    for k, m0 in enumerate(mix.members):
+        if any(m0.T == mm.T for mm in mix.members[:k]):
+            continue                                 # the first member of each truncation
+        om = Oracle(m0.T, m0.nlat, m0.nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
+        refs["mixed"][k] = om.step(W.initial_state(mix, member=k), m0.dt, mix.M, mix.K, steps=2)
+    big = W.WORKLOADS["t511_m4k4"]
+    bm = big.members[0]
+    ob = Oracle(bm.T, bm.nlat, bm.nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
+    refs["t511"] = ob.step(W.initial_state(big), bm.dt, big.M, big.K, steps=1)
+    return base, refs
+
+
+def oracle_errors(wl, refs):
+    """Error against the FP64 oracle (references from the CPU-baseline leg) of every result the
+    line reports: the headline step in FP64 and FP32 after 1 and 1 + n steps, one adjoint step of
+    each precision, the first member of each truncation of the mixed ensemble after 2 group steps,
+    and one T511 step in FP64 and FP32.  Relative L2 per field (sphere norm), max over members."""
+    import numpy as np
+    import torch
+    from paper_2403_20135_amd.api import SDC, SDCGroup
+    mb = wl.members[0]
+    x0 = W.initial_state(wl)[None]
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    out = {"metric": "relative L2 per field (sphere norm) against the FP64 oracle, max over members"}
+    for prec in ("fp64", "fp32"):
+        sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, 1, prec, W.RADIUS, W.GRAVITY, W.OMEGA,
+                  W.MEAN_DEPTH)
+        sdc.autotune(5)
+        x = dev(x0)
+        done, res = 0, {}
+        for k in sorted(refs["after"]):
+            while done < k:
+                sdc.step_graph(x, mb.dt)
+                done += 1
+            sdc.sync()
+            res[f"after_{k}_steps"] = sphere_rel_l2(x.cpu().numpy(), refs["after"][k][None], mb.T)
+        g = torch.zeros_like(x)
+        sdc.step_adjoint(dev(x0), dev(refs["lam"][None]), g, mb.dt)
+        sdc.sync()
+        res["adjoint_step"] = sphere_rel_l2(g.cpu().numpy(), refs["vjp"][None], mb.T)
+        sdc.close()
+        out[f"{wl.name}_{prec}"] = res
+
+    mix = W.WORKLOADS["mixed32_m4k3"]
+    groups = {}
+    for k, m in enumerate(mix.members):
+        groups.setdefault(m.T, []).append(k)
+    handles, xs, dts = [], [], []
+    for T, ks in sorted(groups.items()):
+        m0 = mix.members[ks[0]]
+        handles.append(SDC(T, m0.nlat, m0.nlon, mix.M, mix.K, len(ks), "fp64", W.RADIUS,
+                           W.GRAVITY, W.OMEGA, W.MEAN_DEPTH))
+        xs.append(dev(np.stack([W.initial_state(mix, member=k) for k in ks])))
+        dts.append(m0.dt)
+    grp = SDCGroup(handles)
+    for _ in range(2):
+        grp.step(xs, dts, mix.M, mix.K)
+    grp.sync()
+    mres = {}
+    for (T, ks), x in zip(sorted(groups.items()), xs):
+        mres[f"member_{ks[0]}_T{T}"] = sphere_rel_l2(x[0].cpu().numpy()[None], refs["mixed"][ks[0]][None], T)
+    grp.close()
+    for h in handles:
+        h.close()
+    out["mixed32_m4k3_fp64_2_steps"] = mres
+
+    big = W.WORKLOADS["t511_m4k4"]
+    bm = big.members[0]
+    for prec in ("fp64", "fp32"):
+        sdc = SDC(bm.T, bm.nlat, bm.nlon, big.M, big.K, 1, prec, W.RADIUS, W.GRAVITY, W.OMEGA,
+                  W.MEAN_DEPTH)
+        sdc.autotune(3)
+        x = dev(W.initial_state(big)[None])
+        sdc.step(x, bm.dt)
+        sdc.sync()
+        out[f"t511_m4k4_{prec}_1_step"] = sphere_rel_l2(x.cpu().numpy(), refs["t511"][None], bm.T)
+        sdc.close()
+    return out
 
 
 def main():
@@ -626,7 +761,10 @@ def main():
         torch.cuda.synchronize()
         result["calibration_copy_bytes"] = 2 * src.numel() * 8      # read + write
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(wl, W.initial_state(wl))
+        base, refs = cpu_baseline(wl, W.initial_state(wl))
+        result["cpu_baseline"] = base
+        if "vjp" in refs:
+            result["err_vs_oracle"] = oracle_errors(wl, refs)
     print(json.dumps(result))
 
 

@@ -33,6 +33,13 @@ def test_algorithmic_work_counts():
     assert bench.algorithmic_work(T, nlat, M, K, 1, "fp64", True, True)["update"][1] == \
         pytest.approx(7 * 16.0 * ncoef)                           # u_n conversion (regenerating)
     assert wf["synthesis"] == w["synthesis"] and wf["grid"] == w["grid"]
+    # the dominant kernel of the headline step by hand, per launch (4 launches, 13/4 states each):
+    # both tables once, 5 Fourier fields per state, the node update's state I/O
+    # (K-1)(3+5M) + (6+2M) complex per coefficient spread over the launches
+    per_launch = (2 * ncoef * (nlat // 2) * 8 + 13 / 4 * 5 * 16 * nlat * (T + 1)
+                  + 16 * ncoef * ((K - 1) * (3 + 5 * M) + (6 + 2 * M)) / 4)
+    assert wf["analysis"][1] / K == pytest.approx(per_launch)
+    assert per_launch == pytest.approx(137.537024e6)
     # regenerated synthesis tables: same flops, the table bytes replaced by the small recurrence data
     wr = bench.algorithmic_work(T, nlat, M, K, 1, "fp64", syn_recur=True)
     assert wr["synthesis"][0] == w["synthesis"][0]
@@ -61,7 +68,7 @@ def _csv(path, counter, rows):
 
 def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     plan = {"syn_lat_tiles": 2, "syn_depth": 2, "ana_depth": 2, "ana_interleave": 1, "fuse_update": 1,
-            "syn_recur": 1, "ana_recur": 0}
+            "syn_recur": 0, "ana_recur": 0}
     logs = []
     for name in ("f.log", "w.log"):
         p = tmp_path / name
@@ -70,19 +77,19 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     copy_kib = 256 * 1024 / 2.0                                   # counter reads half the bytes
     _csv(tmp_path / "f.csv", "FETCH_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", copy_kib),
-        ("void k_synthesis<0, double, 2, 2, true, false>(double const*)", 1000.0),
-        ("void k_synthesis<0, double, 2, 2, true, false>(double const*)", 3000.0),
-        ("void k_synthesis<0, double, 2, 2, true, true>(double const*)", 2000.0),    # first launch
-        ("void k_synthesis<0, double, 1, 8, true, false>(double const*)", 99999.0),   # an autotuner trial
-        ("void k_synthesis<0, double, 2, 2, false, false>(double const*)", 77777.0),  # table-reading trial
+        ("void k_synthesis<0, double, 2, 2, false, false>(double const*)", 1000.0),
+        ("void k_synthesis<0, double, 2, 2, false, false>(double const*)", 3000.0),
+        ("void k_synthesis<0, double, 2, 2, false, true>(double const*)", 2000.0),   # first launch
+        ("void k_synthesis<0, double, 1, 8, false, false>(double const*)", 99999.0),  # an autotuner trial
+        ("void k_synthesis<0, double, 2, 2, true, false>(double const*)", 77777.0),   # regenerating trial
         ("void k_analysis_swe<0, double, 2, false>(double const*)", 500.0),
         ("void k_analysis_swe<0, double, 2, true>(double const*)", 88888.0),     # regenerating trial
         ("void k_grid_swe<768, double>(x)", 10.0),
         ("void k_update<4>(UpdateArgs)", 20.0)])
     _csv(tmp_path / "w.csv", "WRITE_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", 256 * 1024.0),
-        ("void k_synthesis<0, double, 2, 2, true, false>(double const*)", 100.0),
-        ("void k_synthesis<0, double, 2, 2, true, true>(double const*)", 100.0),
+        ("void k_synthesis<0, double, 2, 2, false, false>(double const*)", 100.0),
+        ("void k_synthesis<0, double, 2, 2, false, true>(double const*)", 100.0),
         ("void k_analysis_swe<0, double, 2, false>(double const*)", 50.0),
         ("void k_grid_swe<768, double>(x)", 40.0),
         ("void k_update<4>(UpdateArgs)", 30.0)])
@@ -91,14 +98,46 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     t = json.loads(out.read_text())
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
     syn = t["kernels"]["synthesis"]
-    assert syn["kernel_name"] == ("void k_synthesis<0, double, 2, 2, true, false> + "
-                                  "void k_synthesis<0, double, 2, 2, true, true>")
+    assert syn["kernel_name"] == ("void k_synthesis<0, double, 2, 2, false, false> + "
+                                  "void k_synthesis<0, double, 2, 2, false, true>")
     assert syn["dispatches"] == 3
     assert syn["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
     assert syn["write_bytes_per_launch"] == pytest.approx(100.0 * 1024)
     assert set(t["kernels"]) == {"synthesis", "analysis", "grid", "update"}
     assert t["kernels"]["analysis"]["fetch_bytes_per_launch"] == pytest.approx(500.0 * 1024 * 2.0)
     assert t["legendre_plan"] == plan
+
+
+def test_summarize_pmc_regenerating_plan_counts_the_conversion_as_update(tmp_path):
+    plan = {"syn_lat_tiles": 4, "syn_depth": 2, "ana_depth": 2, "ana_interleave": 1, "fuse_update": 1,
+            "syn_recur": 1, "ana_recur": 1}
+    logs = []
+    for name in ("f.log", "w.log"):
+        p = tmp_path / name
+        p.write_text(json.dumps({"metric": "m", "legendre_plan": plan}) + "\n")
+        logs.append(str(p))
+    _csv(tmp_path / "f.csv", "FETCH_SIZE", [
+        ("__amd_rocclr_copyBuffer(...)", 256 * 1024.0),
+        ("void k_synthesis<0, double, 4, 2, true, false>(double const*)", 1000.0),
+        ("void k_synthesis<0, double, 4, 2, false, false>(double const*)", 55555.0),  # streaming trial
+        ("void k_analysis_swe<0, double, 2, true>(double const*)", 400.0),
+        ("void k_analysis_swe<0, double, 2, false>(double const*)", 66666.0),     # streaming trial
+        ("k_prep_cml(double const*, int, double*, bool)", 30.0),
+        ("k_prep_cml_adj(double const*, int, double*, bool)", 44444.0)])          # adjoint: not counted
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", [
+        ("__amd_rocclr_copyBuffer(...)", 256 * 1024.0),
+        ("void k_synthesis<0, double, 4, 2, true, false>(double const*)", 10.0),
+        ("void k_analysis_swe<0, double, 2, true>(double const*)", 20.0),
+        ("k_prep_cml(double const*, int, double*, bool)", 40.0)])
+    out = tmp_path / "t.json"
+    bench.summarize_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 256, str(out), logs)
+    t = json.loads(out.read_text())
+    assert t["kernels"]["synthesis"]["fetch_bytes_per_launch"] == pytest.approx(1000.0 * 1024)
+    assert t["kernels"]["analysis"]["fetch_bytes_per_launch"] == pytest.approx(400.0 * 1024)
+    upd = t["kernels"]["update"]
+    assert upd["dispatches"] == 1 and upd["kernel_name"] == "k_prep_cml"
+    assert upd["fetch_bytes_per_launch"] == pytest.approx(30.0 * 1024)
+    assert upd["write_bytes_per_launch"] == pytest.approx(40.0 * 1024)
 
 
 def test_summarize_pmc_rejects_runs_with_different_variants(tmp_path):

@@ -31,8 +31,9 @@
  * Execution: every call is enqueued on the HIP stream given to sdc_init and returns without
  * waiting for the GPU.  Argument errors are detected on the host before anything is enqueued
  * and returned synchronously (nothing is modified then).  Device-side conditions (non-finite
- * values produced by sdc_step) are reported by the next sdc_sync.  No call allocates device
- * memory except sdc_init; sdc_free releases everything the handle owns.  A handle must be used
+ * values produced by sdc_step) are reported by the next sdc_sync.  Device memory is allocated
+ * by sdc_init and, once per handle, by the first call of an entry point that says so (adjoint,
+ * comparison integrators); sdc_free releases everything the handle owns.  A handle must be used
  * from one host thread at a time; different handles are independent.  No C++ exception crosses
  * this interface.
  * ---------------------------------------------------------------------------------------------
@@ -143,6 +144,18 @@ int sdc_step_sequential_graph(sdc_handle h, double* state, double dt, int M, int
  * imex2_step_graph: the same step as a cached hipGraph (as sdc_step_graph, keyed by state and dt). */
 int imex2_step(sdc_handle h, double* state, double dt);
 int imex2_step_graph(sdc_handle h, double* state, double dt);
+
+/* For callers that cannot allocate device memory during the call (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same IMEX-o2 step as imex2_step, the
+ * same kernels and bitwise the same result, with u*, k1 and k2 held in a fixed device array of the
+ * library (64 MiB per device, reserved from library load until the process ends) instead of
+ * handle workspaces allocated by the first imex2_step.  It allocates nothing and records no timing
+ * events.  Needs 3 * batch * 3 * ncoef * 16 bytes (T255 with one member: 4.7 MB); SDC_EINVAL when
+ * that exceeds 64 MiB (nothing enqueued), SDC_EHIP if the array's device address could not be
+ * resolved at sdc_init.  Every handle on one device shares that device's array, and every value in
+ * it is written before it is read within one call: calls that overlap on one device (other
+ * streams or host threads) race and must be ordered by the caller. */
+int imex2_step_noalloc(sdc_handle h, double* state, double dt);
 
 /* Adjoint of one step: lam_n = (d u_{n+1} / d u_n)^T lam_np1 for the step taken from state_n
  * with the same dt, M, K (the step is recomputed internally from state_n, keeping the grid fields

@@ -58,6 +58,7 @@ _SIGS = {
     "sdc_step_sequential": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
     "sdc_step_sequential_graph": (c_int, [c_void_p, c_void_p, c_double, c_int, c_int]),
     "imex2_step_graph": (c_int, [c_void_p, c_void_p, c_double]),
+    "imex2_step_noalloc": (c_int, [c_void_p, c_void_p, c_double]),
     "sdc_group_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     "sdc_group_step": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_double), c_int, c_int]),
     "sdc_group_sync": (c_int, [c_void_p]),

@@ -134,6 +134,12 @@ class SDC:
         check(self.lib.imex2_step_graph(self.h, _ptr(state), float(dt)))
         return state
 
+    def imex2_step_noalloc(self, state, dt: float):
+        """One IMEX-o2 step in place with the library's fixed device scratch (no allocation)."""
+        self._check(state, self.state_shape, "state")
+        check(self.lib.imex2_step_noalloc(self.h, _ptr(state), float(dt)))
+        return state
+
     def step_adjoint(self, state_n, lam_np1, lam_n, dt: float, M: Optional[int] = None,
                      K: Optional[int] = None):
         self._check(state_n, self.state_shape, "state_n")

@@ -6,10 +6,20 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "common.h"
+
+// Device scratch of the allocation-free IMEX-o2 step (imex2_step_noalloc): the intermediate state
+// u* and the two tendencies k1, k2 of every member, kScratchBytes at most.  Each device that loads
+// the library holds its own copy until the process ends; in host code the array's name is only a
+// stand-in, so kernels get its device address (resolved once per device by hipGetSymbolAddress
+// in sdc_init, with that device current) and never the name itself.
+static constexpr size_t kScratchBytes = size_t(64) << 20;
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
 
 namespace {
 
@@ -30,6 +40,31 @@ int fail(int code, const char* fmt, ...) {
         hipError_t e_ = (expr);                                                          \
         if (e_ != hipSuccess) return fail(SDC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on the first call per device);
+// nullptr with *err set when it cannot be resolved.
+double* scratch_address(int dev, hipError_t* err) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    if (!g_scratch_done[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_err[dev] = e;
+        g_scratch_ptr[dev] = e == hipSuccess ? static_cast<double*>(p) : nullptr;
+        if (e != hipSuccess) (void)hipGetLastError();
+        g_scratch_done[dev] = true;
+    }
+    *err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
 
 // FFT plan for nlon = 2^p or 3*2^p: an optional radix-3 stage, then the power of two split into
 // radices 16, 8, 4, 2.  A pass advances fchunk of a workgroup's up to 5 signals together, every
@@ -189,6 +224,10 @@ struct sdc_ctx {
     double* adj_x = nullptr;          // copy of u_n for the recomputation
     // IMEX-o2 workspaces (allocated by the first imex2_step call): u*, k1, k2 per member
     double *i2_ustar = nullptr, *i2_k1 = nullptr, *i2_k2 = nullptr;
+    // device address of the library's scratch array on this handle's device (imex2_step_noalloc)
+    int dev = -1;
+    double* scratch_dev = nullptr;
+    hipError_t scratch_err = hipSuccess;
     // sequential IMEX SDC workspaces (first sdc_step_sequential call): nodes and tendencies of
     // two sweeps, node-major [M][B][3][ncoef]
     double* seq_u[2] = {nullptr, nullptr};
@@ -555,6 +594,13 @@ int sdc_init(const sdc_config* cfg, void* hip_stream, sdc_handle* out) {
         delete c;
         return rc;
     }
+    // the scratch array's address on this device (the device current at init owns the handle)
+    if (hipGetDevice(&c->dev) == hipSuccess) {
+        c->scratch_dev = scratch_address(c->dev, &c->scratch_err);
+    } else {
+        (void)hipGetLastError();
+        c->scratch_err = hipErrorInvalidDevice;
+    }
     *out = c;
     return SDC_OK;
 }
@@ -868,7 +914,7 @@ int alloc_imex2(sdc_ctx* c) {
 }
 
 // One IMEX-o2 step for all members (workspaces allocated, arguments checked).
-void enqueue_imex2(sdc_ctx* c, double* state, double dt) {
+void enqueue_imex2(sdc_ctx* c, double* state, double dt, double* ustar, double* k1, double* k2) {
     const int B = c->cfg.batch;
     Imex2Args a{};
     a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
@@ -888,17 +934,17 @@ void enqueue_imex2(sdc_ctx* c, double* state, double dt) {
         a.phase = ph;
         a.in = in;
         a.out = out;
-        a.k1 = c->i2_k1;
-        a.k2 = c->i2_k2;
+        a.k1 = k1;
+        a.k2 = k2;
         const long t = c->begin(SDC_KERNEL_UPDATE);
         launch_imex2(a, c->st);
         c->end(SDC_KERNEL_UPDATE, t);
     };
-    phase(kImex2First, state, c->i2_ustar);          // u* = C(dt/2) u_n
-    run_explicit_cml(c, B, c->i2_k1);               // k1 = f_E(u*)
-    phase(kImex2Predict, c->i2_ustar, nullptr);      // synthesis input u* + dt k1
-    run_explicit_cml(c, B, c->i2_k2);               // k2 = f_E(u* + dt k1)
-    phase(kImex2Last, c->i2_ustar, state);           // u_{n+1}
+    phase(kImex2First, state, ustar);               // u* = C(dt/2) u_n
+    run_explicit_cml(c, B, k1);                     // k1 = f_E(u*)
+    phase(kImex2Predict, ustar, nullptr);           // synthesis input u* + dt k1
+    run_explicit_cml(c, B, k2);                     // k2 = f_E(u* + dt k1)
+    phase(kImex2Last, ustar, state);                // u_{n+1}
 }
 
 int alloc_seq(sdc_ctx* c) {
@@ -962,10 +1008,15 @@ void enqueue_seq(sdc_ctx* c, double* state, double dt, int M, int K) {
     }
 }
 
-int check_imex2_args(sdc_handle h, const double* state, double dt) {
+int check_imex2_state(sdc_handle h, const double* state, double dt) {
     if (int rc = check_handle(h)) return rc;
     if (!state) return fail(SDC_EINVAL, "state is NULL");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(SDC_EINVAL, "dt must be positive and finite");
+    return SDC_OK;
+}
+
+int check_imex2_args(sdc_handle h, const double* state, double dt) {
+    if (int rc = check_imex2_state(h, state, dt)) return rc;
     return alloc_imex2(h);
 }
 
@@ -1125,14 +1176,35 @@ int sdc_step_sequential_graph(sdc_handle h, double* state, double dt, int M, int
 
 int imex2_step(sdc_handle h, double* state, double dt) {
     if (int rc = check_imex2_args(h, state, dt)) return rc;
-    enqueue_imex2(h, state, dt);
+    enqueue_imex2(h, state, dt, h->i2_ustar, h->i2_k1, h->i2_k2);
     HIP_TRY(hipGetLastError());
     return SDC_OK;
 }
 
 int imex2_step_graph(sdc_handle h, double* state, double dt) {
     if (int rc = check_imex2_args(h, state, dt)) return rc;
-    return graph_launch(h, 1, state, dt, 0, 0, [&] { enqueue_imex2(h, state, dt); });
+    return graph_launch(h, 1, state, dt, 0, 0,
+                        [&] { enqueue_imex2(h, state, dt, h->i2_ustar, h->i2_k1, h->i2_k2); });
+}
+
+int imex2_step_noalloc(sdc_handle h, double* state, double dt) {
+    if (int rc = check_imex2_state(h, state, dt)) return rc;
+    const size_t per = (size_t)h->cfg.batch * 3 * h->g.ncoef * 2;        // doubles of one state set
+    const size_t need = 3 * per * sizeof(double);
+    if (need > kScratchBytes)
+        return fail(SDC_EINVAL, "imex2_step_noalloc needs %zu bytes of device scratch (u*, k1, k2 of %d "
+                    "members), more than its fixed %zu bytes; use imex2_step", need, h->cfg.batch,
+                    kScratchBytes);
+    if (!h->scratch_dev)
+        return fail(SDC_EHIP, "device scratch of device %d unavailable: %s", h->dev,
+                    hipGetErrorString(h->scratch_err));
+    // no event pool growth either: timing events are not recorded by this call
+    const bool timing = h->timing;
+    h->timing = false;
+    enqueue_imex2(h, state, dt, h->scratch_dev, h->scratch_dev + per, h->scratch_dev + 2 * per);
+    h->timing = timing;
+    HIP_TRY(hipGetLastError());
+    return SDC_OK;
 }
 
 int sdc_step_adjoint(sdc_handle h, const double* state_n, const double* lam_np1, double* lam_n,

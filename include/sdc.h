@@ -256,6 +256,14 @@ typedef struct {
                           rows and regenerates the table entries of those rows by the same
                           recurrence (a quarter of the table bytes; the same results bit for
                           bit); 0: it streams the tables.  Chosen by the autotuner. */
+    int node_launch;   /* 0 (default): the f_E evaluations of the M nodes of a sweep (Algorithm 2's
+                          parallel loop over m, Section 4.2) are one launch per kernel class; 1: one
+                          launch set per node, one node after another, after a separate node-update
+                          kernel -- the sequential counterpart of the time-parallel loop, bitwise
+                          the same states, for measuring the speedup of evaluating the nodes
+                          together (Section 4.7).  Handles of one member only (SDC_EINVAL
+                          otherwise).  Applies to sdc_step, sdc_step_graph, sdc_step_taped and the
+                          recomputation of sdc_step_adjoint.  Not changed by the autotuner. */
 } sdc_plan;
 
 /* The handle's current variants. */

@@ -36,7 +36,7 @@ class SdcInfo(ctypes.Structure):
 class SdcPlan(ctypes.Structure):
     _fields_ = [("syn_lat_tiles", c_int), ("syn_depth", c_int), ("ana_depth", c_int),
                 ("ana_interleave", c_int), ("fuse_update", c_int),
-                ("syn_recur", c_int), ("ana_recur", c_int)]
+                ("syn_recur", c_int), ("ana_recur", c_int), ("node_launch", c_int)]
 
 
 class SDCError(RuntimeError):

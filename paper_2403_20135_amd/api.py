@@ -209,11 +209,11 @@ class SDC:
         return {k: getattr(pl, k) for k, _ in pl._fields_}
 
     def set_plan(self, syn_lat_tiles: int, syn_depth: int, ana_depth: int, ana_interleave: int,
-                 fuse_update: int = 1, syn_recur: int = 0, ana_recur: int = 0):
-        """Select the Legendre launch variants (see sdc_plan in include/sdc.h); every variant
-        gives bitwise the same results."""
+                 fuse_update: int = 1, syn_recur: int = 0, ana_recur: int = 0, node_launch: int = 0):
+        """Select the launch variants (see sdc_plan in include/sdc.h); every variant gives bitwise
+        the same results."""
         pl = _lib.SdcPlan(syn_lat_tiles, syn_depth, ana_depth, ana_interleave, fuse_update, syn_recur,
-                          ana_recur)
+                          ana_recur, node_launch)
         check(self.lib.sdc_set_plan(self.h, ctypes.byref(pl)))
 
     def autotune(self, reps: int = 10) -> dict:

@@ -638,6 +638,7 @@ int sdc_get_plan(sdc_handle h, sdc_plan* plan) {
     plan->fuse_update = h->lplan.fuse_update;
     plan->syn_recur = h->lplan.syn_recur;
     plan->ana_recur = h->lplan.ana_recur;
+    plan->node_launch = h->lplan.node_launch;
     return SDC_OK;
 }
 
@@ -650,6 +651,10 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
         return fail(SDC_EINVAL, "syn_recur=%d: 0 or 1", plan->syn_recur);
     if (plan->ana_recur != 0 && plan->ana_recur != 1)
         return fail(SDC_EINVAL, "ana_recur=%d: 0 or 1", plan->ana_recur);
+    if (plan->node_launch != 0 && plan->node_launch != 1)
+        return fail(SDC_EINVAL, "node_launch=%d: 0 or 1", plan->node_launch);
+    if (plan->node_launch && h->cfg.batch != 1)
+        return fail(SDC_EINVAL, "node_launch=1 is defined for handles of one member (batch=%d)", h->cfg.batch);
     const int jt = plan->syn_lat_tiles, d = plan->syn_depth;
     const bool syn_ok = (jt == 1 && (d == 8 || d == 4)) || (jt == 2 && (d == 4 || d == 2)) ||
                         (jt == 3 && d == 2) || (jt == 4 && (d == 2 || d == 1)) || (jt == 6 && d == 1);
@@ -668,6 +673,7 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
     h->lplan.fuse_update = plan->fuse_update;
     h->lplan.syn_recur = plan->syn_recur;
     h->lplan.ana_recur = plan->ana_recur;
+    h->lplan.node_launch = plan->node_launch;
     h->drop_graphs();                 // recaptured with the new variants on their next replay
     return SDC_OK;
 }
@@ -782,6 +788,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         chosen->fuse_update = best.fuse_update;
         chosen->syn_recur = best.syn_recur;
         chosen->ana_recur = best.ana_recur;
+        chosen->node_launch = best.node_launch;
     }
     return SDC_OK;
 }
@@ -841,6 +848,42 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K, double2* t
     a.E_member = fs;
     double* bufs[2] = {c->ua, c->ub};
     int cur = 0;
+    if (c->lplan.node_launch) {
+        // The same sweeps with the f_E of the nodes evaluated one node per launch (one member:
+        // node j of a sweep is state j of the stage), after a separate update of all nodes: the
+        // node loop run sequentially, as a code without the batched nodes would.  Every state's
+        // transforms are independent of the others in a launch, so the result is bitwise the
+        // batched step's.
+        run_explicit(c, state, B, c->E0, tape_at(0));
+        for (int s = 1; s < K; ++s) {
+            a.uout = bufs[cur];
+            a.out_node = fs;
+            a.out_member = (long long)M * fs;
+            a.sweep = qd_sweep(c, s, M);
+            a.last_only = 0;
+            a.cml = nullptr;
+            run_update(c, a);
+            for (int j = 0; j < M; ++j)
+                run_explicit(c, bufs[cur] + j * fs, 1, c->E + j * fs,
+                             tape ? tape_at(s) + (size_t)j * tape_per_state(c) : nullptr);
+            a.uprev = bufs[cur];
+            a.uprev_node = fs;
+            a.uprev_member = (long long)M * fs;
+            a.E = c->E;
+            a.E_node = fs;
+            a.E_member = (long long)M * fs;
+            cur ^= 1;
+        }
+        if (!last_update) return;
+        a.uout = state;
+        a.out_node = 0;
+        a.out_member = fs;
+        a.cml = nullptr;
+        a.sweep = qd_sweep(c, K, M);
+        a.last_only = 1;
+        run_update(c, a);
+        return;
+    }
     if (c->lplan.fuse_update && (M == 1 || M == 2 || M == 4)) {
         // The node update of sweep s + 1 runs inside the analysis of the f_E of sweep s (the
         // tendencies stay in the analysis workgroups): sweep s < K updates every node into

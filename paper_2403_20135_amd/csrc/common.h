@@ -82,6 +82,7 @@ struct LegPlan {
     int fuse_update = 1;       // node updates inside the analysis (M in {1, 2, 4})
     int syn_recur = 0;         // synthesis regenerates Pbar, H in registers instead of reading them
     int ana_recur = 0;         // analysis regenerates them from a quarter of the stored entries
+    int node_launch = 0;       // 1: the f_E of the nodes of a sweep one node per launch (batch 1)
 };
 
 // Upward recurrence of the orthonormal associated Legendre functions in n at fixed m and mu (the
@@ -138,9 +139,27 @@ __device__ inline void cml_put(double* cml, bool cml32, size_t i, double v) {
 // Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V, layout
 // four[s][field][lat][m].
 constexpr int kSynFields = 4;
-// Analysis input written by the grid kernel, per (northern latitude jh, m, parity p, state s):
-// 14 values = 7 complex columns, Pbar parts (zeta, delta, kinetic energy, Phi') then H parts
-// (zeta, delta, Phi'), already combined into the north +- south sums of parity p and weighted,
+// Analysis input of the forward tendency, written by the grid kernel, per (northern latitude jh,
+// m, state s): 10 complex values, the north + south ("s") and north - south ("a") sums of the
+// Fourier coefficients of the five grid products, weighted as g A, g B, g C, g D
+// (g = w / (a (1 - mu^2) nlon)) and w E / nlon, in the order
+//   Cs, Es, Da, As, Bs, Aa, Ba, Ca, Ea, Ds
+// so that the seven columns of each parity of n - m are one contiguous window: values 0..6 for
+// even n - m (Pbar pairs with the symmetric sums, H with the antisymmetric ones), values 3..9 for
+// odd.  The factors -i m (A, C) and +i m (B) of the Pbar columns are applied to the contraction's
+// results.  Stored rounded to FP32 in the FP32 precision mode (what its MFMAs consume).  The
+// latitude is outermost and the states of a latitude are adjacent, so the grid workgroups of one
+// latitude pair write one contiguous slab:
+//   G[fwd_index(T, S, jh, m, s) + 2 v + part]
+constexpr int kFwdVals = 10;
+enum FwdVal { kCs = 0, kEs, kDa, kAs, kBs, kAa, kBa, kCa, kEa, kDs };
+__host__ __device__ inline size_t fwd_index(int T, int S, int jh, int m, int s) {
+    return (((size_t)jh * (T + 1) + m) * S + s) * (2 * kFwdVals);
+}
+// Transposed synthesis of the adjoint, written by the adjoint grid kernel, per (northern latitude
+// jh, m, parity p, state s):
+// 14 values = 7 complex columns (Pbar parts then H parts), already combined into the north +-
+// south sums of parity p and weighted,
 // padded to kAnaStride values (written whole with zeros in the pad: one 128-byte line in FP64; in
 // the FP32 precision mode the values are stored rounded to FP32, 64 bytes, since that mode's
 // analysis MFMAs consume them rounded anyway).  The latitude is outermost, so a grid workgroup

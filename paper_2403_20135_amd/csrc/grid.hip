@@ -15,6 +15,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 // multiply by -i (forward) or +i (inverse)
 __device__ __forceinline__ double2 cmul_mi(double2 a, bool inv) {
     return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
@@ -474,17 +475,17 @@ template <> struct Row<float> {
 // Fused grid step of f_E for one latitude pair of one state:
 //   inverse FFT of zeta, Phi', U, V -> grid products
 //   A = (zeta+f) U, B = (zeta+f) V, C = Phi' U, D = Phi' V, E = (U^2+V^2)/(2(1-mu^2))
-//   -> forward FFT -> weighted analysis columns (north +- south sums per parity):
-//   Pbar columns: -i m A g, i m B g, E w, -i m C g;  H columns: B g, A g, D g
-//   with g = w / (a (1-mu^2)), Fourier coefficients normalised by 1/nlon.
+//   -> forward FFT -> analysis input: the north + south and north - south sums of g A, g B,
+//   g C, g D and w E (g = w / (a (1-mu^2)), Fourier coefficients normalised by 1/nlon), one line
+//   of 10 complex values per (latitude pair, m, state) (fwd_index).
 // Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of (latitude, state) tasks,
 // states fastest, so the rows of the analysis input meet in one L2.  Each of the first eight
 // signals is transformed by one wave; only the hand-offs between phases are workgroup barriers.
 // LDS holds four signals (three workgroups fit a CU), and every thread loads the first twiddles
 // of its butterflies once, ahead of their use: the fifth product E waits in registers while A..D are
 // transformed, then reuses buffer 0 (A's contributions to the rows wait in registers) and is
-// transformed by the whole workgroup; each analysis row (14 values and 2 zeros, one 128-byte
-// line) is then written whole by one thread.
+// transformed by the whole workgroup; each analysis-input line (10 complex values) is then
+// written whole by one thread.
 // ---------------------------------------------------------------------------------------------
 template <int N, typename GT>
 __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
@@ -539,29 +540,20 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
     const double wt = w[jN];
     const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
     const double we = wt * invN;
-    const double2 z2 = make_double2(0.0, 0.0);
-    // Analysis rows (per m and parity, 7 complex columns + pad):
-    //   parity 0: -i m g As, i m g Bs, w E_s, -i m g Cs, g Ba, g Aa, g Da, 0
-    //   parity 1: -i m g Aa, i m g Ba, w E_a, -i m g Ca, g Bs, g As, g Ds, 0
-    // (-i m X g = (m g X.y, -m g X.x); s / a: north + / - south; Pbar pairs with symmetric sums
-    // for even n - m, H with antisymmetric ones, and the reverse for odd.)  Buffer 0 (A) is
-    // needed for E, so A's four values of the rows of this thread's first MP orders wait in
-    // registers and those rows are written whole once E is transformed; rows of higher orders
-    // (grids with T + 1 > nlon / 3) are written in two parts.
+    // Analysis input lines (fwd_index): the weighted north +- south sums of A..E.  Buffer 0 (A) is
+    // needed for E, so A's two values of this thread's first MP orders wait in registers and those
+    // lines are written whole once E is transformed; lines of higher orders (grids with
+    // T + 1 > nlon / 3) are written in two parts.
     constexpr int MP = (N + 3 * kGridBlock - 1) / (3 * kGridBlock);
-    double2 areg[MP][4];
+    double2 areg[MP][2];
 #pragma unroll
     for (int mp = 0; mp < MP; ++mp) {
         const int m = threadIdx.x + mp * kGridBlock;
         if (m > T) continue;
         double2 AN, AS;
         unpack_pair(buf, m, N, AN, AS);
-        const double mg = (double)m * gg;
-        const double2 As = cadd(AN, AS), Aa = csub(AN, AS);
-        areg[mp][0] = make_double2(mg * As.y, -mg * As.x);
-        areg[mp][1] = make_double2(gg * Aa.x, gg * Aa.y);
-        areg[mp][2] = make_double2(mg * Aa.y, -mg * Aa.x);
-        areg[mp][3] = make_double2(gg * As.x, gg * As.y);
+        areg[mp][0] = cscale(gg, cadd(AN, AS));
+        areg[mp][1] = cscale(gg, csub(AN, AS));
     }
     for (int m = threadIdx.x + MP * kGridBlock; m <= T; m += kGridBlock) {
         double2 AN, AS, BN, BS, CN, CS, DN, DS;
@@ -569,27 +561,15 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
         unpack_pair(buf + N, m, N, BN, BS);
         unpack_pair(buf + 2 * N, m, N, CN, CS);
         unpack_pair(buf + 3 * N, m, N, DN, DS);
-        const double mg = (double)m * gg;
-        const double2 As = cadd(AN, AS), Aa = csub(AN, AS);
-        const double2 Bs = cadd(BN, BS), Ba = csub(BN, BS);
-        const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
-        const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
-        const Row<GT> o0(G, ana_index(T, nstates, jh, m, 0, s));
-        const Row<GT> o1(G, ana_index(T, nstates, jh, m, 1, s));
-        o0.put(0, make_double2(mg * As.y, -mg * As.x));
-        o0.put(1, make_double2(-mg * Bs.y, mg * Bs.x));
-        o0.put(3, make_double2(mg * Cs.y, -mg * Cs.x));
-        o0.put(4, make_double2(gg * Ba.x, gg * Ba.y));
-        o0.put(5, make_double2(gg * Aa.x, gg * Aa.y));
-        o0.put(6, make_double2(gg * Da.x, gg * Da.y));
-        o0.put(7, z2);
-        o1.put(0, make_double2(mg * Aa.y, -mg * Aa.x));
-        o1.put(1, make_double2(-mg * Ba.y, mg * Ba.x));
-        o1.put(3, make_double2(mg * Ca.y, -mg * Ca.x));
-        o1.put(4, make_double2(gg * Bs.x, gg * Bs.y));
-        o1.put(5, make_double2(gg * As.x, gg * As.y));
-        o1.put(6, make_double2(gg * Ds.x, gg * Ds.y));
-        o1.put(7, z2);
+        const Row<GT> o(G, fwd_index(T, nstates, jh, m, s));
+        o.put(kCs, cscale(gg, cadd(CN, CS)));
+        o.put(kDa, cscale(gg, csub(DN, DS)));
+        o.put(kAs, cscale(gg, cadd(AN, AS)));
+        o.put(kBs, cscale(gg, cadd(BN, BS)));
+        o.put(kAa, cscale(gg, csub(AN, AS)));
+        o.put(kBa, cscale(gg, csub(BN, BS)));
+        o.put(kCa, cscale(gg, csub(CN, CS)));
+        o.put(kDs, cscale(gg, cadd(DN, DS)));
     }
     __syncthreads();
     // E: into buffer 0 and transformed by the whole workgroup
@@ -609,38 +589,24 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
         unpack_pair(buf + 2 * N, m, N, CN, CS);
         unpack_pair(buf + 3 * N, m, N, DN, DS);
         unpack_pair(buf, m, N, EN, ES);
-        const double mg = (double)m * gg;
-        const double2 Bs = cadd(BN, BS), Ba = csub(BN, BS);
-        const double2 Cs = cadd(CN, CS), Ca = csub(CN, CS);
-        const double2 Ds = cadd(DN, DS), Da = csub(DN, DS);
-        const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
-        const Row<GT> o0(G, ana_index(T, nstates, jh, m, 0, s));
-        const Row<GT> o1(G, ana_index(T, nstates, jh, m, 1, s));
-        o0.put(0, areg[mp][0]);
-        o0.put(1, make_double2(-mg * Bs.y, mg * Bs.x));
-        o0.put(2, make_double2(we * Es.x, we * Es.y));
-        o0.put(3, make_double2(mg * Cs.y, -mg * Cs.x));
-        o0.put(4, make_double2(gg * Ba.x, gg * Ba.y));
-        o0.put(5, areg[mp][1]);
-        o0.put(6, make_double2(gg * Da.x, gg * Da.y));
-        o0.put(7, z2);
-        o1.put(0, areg[mp][2]);
-        o1.put(1, make_double2(-mg * Ba.y, mg * Ba.x));
-        o1.put(2, make_double2(we * Ea.x, we * Ea.y));
-        o1.put(3, make_double2(mg * Ca.y, -mg * Ca.x));
-        o1.put(4, make_double2(gg * Bs.x, gg * Bs.y));
-        o1.put(5, areg[mp][3]);
-        o1.put(6, make_double2(gg * Ds.x, gg * Ds.y));
-        o1.put(7, z2);
+        const Row<GT> o(G, fwd_index(T, nstates, jh, m, s));
+        o.put(kCs, cscale(gg, cadd(CN, CS)));
+        o.put(kEs, cscale(we, cadd(EN, ES)));
+        o.put(kDa, cscale(gg, csub(DN, DS)));
+        o.put(kAs, areg[mp][0]);
+        o.put(kBs, cscale(gg, cadd(BN, BS)));
+        o.put(kAa, areg[mp][1]);
+        o.put(kBa, cscale(gg, csub(BN, BS)));
+        o.put(kCa, cscale(gg, csub(CN, CS)));
+        o.put(kEa, cscale(we, csub(EN, ES)));
+        o.put(kDs, cscale(gg, cadd(DN, DS)));
     }
     for (int m = threadIdx.x + MP * kGridBlock; m <= T; m += kGridBlock) {
         double2 EN, ES;
         unpack_pair(buf, m, N, EN, ES);
-        const double2 Es = cadd(EN, ES), Ea = csub(EN, ES);
-        const Row<GT> o0(G, ana_index(T, nstates, jh, m, 0, s));
-        const Row<GT> o1(G, ana_index(T, nstates, jh, m, 1, s));
-        o0.put(2, make_double2(we * Es.x, we * Es.y));
-        o1.put(2, make_double2(we * Ea.x, we * Ea.y));
+        const Row<GT> o(G, fwd_index(T, nstates, jh, m, s));
+        o.put(kEs, cscale(we, cadd(EN, ES)));
+        o.put(kEa, cscale(we, csub(EN, ES)));
     }
 }
 

@@ -445,10 +445,13 @@ void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long
 }
 
 // ---------------------------------------------------------------------------------------------
-// Analysis for the shallow-water explicit tendency (MODE = kAnaForward).  Input: per (m, parity
-// p, latitude, state) the seven weighted Fourier columns of the grid kernel.  Output per state:
-//   d zeta/dt = Pbar.col0 + H.col4, d delta/dt = Pbar.col1 + H.col5 + n(n+1)/a^2 Pbar.col2,
-//   d Phi'/dt = Pbar.col3 + H.col6.
+// Analysis for the shallow-water explicit tendency (MODE = kAnaForward).  Input: per (latitude,
+// m, state) the weighted north +- south sums of the products A..E (fwd_index); the workgroup of
+// parity p reads its window of seven (col0..col6 = g A, g B, w E, g C with the sums Pbar pairs
+// with, then g B, g A, g D with the others).  Output per state:
+//   d zeta/dt = -i m Pbar.col0 + H.col4,
+//   d delta/dt = i m Pbar.col1 + H.col5 + n(n+1)/a^2 Pbar.col2,
+//   d Phi'/dt = -i m Pbar.col3 + H.col6.
 // Transposed synthesis of the adjoint (MODE = kAnaAdjoint), accumulated into the output:
 //   zeta_adj += Pbar.col0 + (-a^2/(n(n+1))) (Pbar.col1 + H.col4'),
 //   delta_adj += (-a^2/(n(n+1))) (Pbar.col2 + H.col5'),  Phi'_adj += Pbar.col3
@@ -539,14 +542,31 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
     // mode stores the columns already rounded, which is what its MFMAs consume): 256 chunks of
     // four values, one per thread (a state's fourth chunk holds values 12, 13 and the row's two
     // pad zeros, which go to the dummy slot).  Idle threads write the dummy slot.
+    // Forward input (fwd_index lines of 10 complex values, FP64 or FP32): 448 chunks of one complex
+    // value, the seven of this parity's window per (latitude, state), two per thread, each stored
+    // into its column's LDS slot.
     constexpr bool g64 = sizeof(TT) == 8;
-    constexpr int NC = g64 ? 2 : 1;                                  // chunks per thread
-    const size_t jstride = ana_index(g.T, S, 1, 0, 0, 0);           // values per latitude
-    const TT* gsrc = G + ana_index(g.T, S, 0, m, p, s0);
+    constexpr bool fwd = MODE == kAnaForward;
+    constexpr int NC = (g64 || fwd) ? 2 : 1;                         // chunks per thread
+    const size_t jstride = fwd ? fwd_index(g.T, S, 1, 0, 0) : ana_index(g.T, S, 1, 0, 0, 0);
+    const TT* gsrc = G + (fwd ? fwd_index(g.T, S, 0, m, s0) : ana_index(g.T, S, 0, m, p, s0));
     int clat[NC], csrc[NC], cdst[NC], cdst2[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        if constexpr (g64) {
+        if constexpr (fwd) {
+            // chunk c: latitude c / 28 of the block, state cw / 7, window value cw % 7; the window
+            // of parity p starts at value 3 p, and value v of it is column fwd_col[p][v]
+            constexpr int fwd_col[2][7] = {{3, 2, 6, 0, 1, 5, 4}, {5, 4, 0, 1, 3, 2, 6}};
+            const int c = tid + kBlock * k;
+            int lat = c / (2 * kAnaVals), cw = c % (2 * kAnaVals);
+            const bool ok = c < kAnaChunks && cw < nsg * (kAnaVals / 2);
+            if (!ok) { lat = 0; cw = 0; }
+            const int st = cw / (kAnaVals / 2), kv = cw % (kAnaVals / 2);
+            clat[k] = lat;
+            csrc[k] = st * 2 * kFwdVals + 2 * (3 * p + kv);
+            cdst[k] = ok ? lat * kAnaLat + st * kAnaVals + 2 * fwd_col[p][kv] : kAnaBuf;
+            cdst2[k] = 0;
+        } else if constexpr (g64) {
             // chunk c: latitude c / 14 of the block, state cw / 7, values 2 (cw % 7), 2 (cw % 7) + 1
             const int c = tid + kBlock * k;
             int lat = c / (2 * kAnaVals), cw = c % (2 * kAnaVals);
@@ -566,7 +586,8 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
             cdst2[k] = ok && kq < 3 ? cdst[k] + 2 : kAnaBuf + 2;
         }
     }
-    typedef typename std::conditional<g64, double2, float4>::type GV;
+    typedef typename std::conditional<g64, double2,
+                                      typename std::conditional<fwd, float2, float4>::type>::type GV;
     auto gload = [&](GV (&r)[NC], int b) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
@@ -583,6 +604,9 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
             const bool live = 16 * b + clat[k] < g.nh;
             if constexpr (g64) {
                 *(double2*)&gl[buf][cdst[k]] = live ? r[k] : make_double2(0.0, 0.0);
+            } else if constexpr (fwd) {
+                const double2 v2 = make_double2((double)r[k].x, (double)r[k].y);
+                *(double2*)&gl[buf][cdst[k]] = live ? v2 : make_double2(0.0, 0.0);
             } else {
                 const double2 lo = make_double2((double)r[k].x, (double)r[k].y);
                 const double2 hi = make_double2((double)r[k].z, (double)r[k].w);
@@ -726,6 +750,25 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         if (!fuse && !(MODE == kAnaAdjoint && af.mode)) return;   // uniform
     }
 
+    // The Pbar columns of the forward input carry no factor i m: the Pbar parts of zeta_t
+    // (-i m A), Phi'_t (-i m C) and delta_t (+i m B) are rotated here, each lane taking the other
+    // part of its complex value from its partner lane i ^ 1.
+    double pv[2][4];
+    {
+        const double rot = (re == 0 ? 1.0 : -1.0) * (kind == 1 ? -1.0 : 1.0) * (double)m;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double x = (double)accP[t][r];
+                if constexpr (MODE == kAnaForward) {
+                    const double y = __shfl_xor(x, 1, 64);
+                    pv[t][r] = kind == 2 ? x : rot * y;
+                } else {
+                    pv[t][r] = x;
+                }
+            }
+    }
     const int cb = coef_offset(g.T, m) - m;
     if constexpr (MODE == kAnaAdjoint) {
         if (af.mode) {
@@ -801,7 +844,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
                     const int sl = 2 * t + (i >> 3);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const double val = has_h ? (double)accP[t][r] + (double)accH[t][r] : (double)accP[t][r];
+                        const double val = has_h ? pv[t][r] + (double)accH[t][r] : pv[t][r];
                         const double right = __shfl_down(val, 2, 64);
                         const int kk = kt + MM::row(r, q);
                         if (kk >= np || sl >= nsg || kind == 2) continue;
@@ -837,7 +880,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
         const int s = s0 + 2 * t + (i >> 3);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double val = has_h ? (double)accP[t][r] + (double)accH[t][r] : (double)accP[t][r];
+            const double val = has_h ? pv[t][r] + (double)accH[t][r] : pv[t][r];
             const double right = __shfl_down(val, 2, 64);    // the kind one to the right
             const int kk = kt + MM::row(r, q);
             if (kk >= np || s >= S) continue;

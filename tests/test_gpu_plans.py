@@ -16,7 +16,7 @@ from test_gpu_parity import _dev, _host, _oracle, _sdc, _states, _torch, rel_l2
 pytestmark = pytest.mark.gpu
 
 DEFAULT = dict(syn_lat_tiles=2, syn_depth=2, ana_depth=2, ana_interleave=1, fuse_update=1, syn_recur=0,
-               ana_recur=0)
+               ana_recur=0, node_launch=0)
 # (syn_lat_tiles, syn_depth, ana_depth, ana_interleave[, fuse_update, syn_recur]); syn_recur = 1
 # regenerates the tables in the synthesis by the recurrence that wrote them
 VARIANTS = [(1, 8, 4, 1), (1, 4, 4, 1), (2, 4, 4, 1), (2, 2, 4, 1), (3, 2, 4, 1), (4, 2, 4, 1),
@@ -133,3 +133,50 @@ def test_fused_update_is_bitwise_the_separate_one(T, nlat, nlon, M, K, batch, pr
                   f"max |diff| {np.max(np.abs(a - b)):.3e}", flush=True)
             assert np.array_equal(a, b), (key, name)
     assert np.array_equal(res[1][0], res[1][1])
+
+
+@pytest.mark.parametrize("T,nlat,nlon,M,K,prec", [(63, 96, 192, 4, 4, "fp64"), (31, 48, 96, 3, 3, "fp32"),
+                                                  (21, 34, 64, 2, 4, "fp64")])
+def test_node_launch_agrees_bitwise(T, nlat, nlon, M, K, prec):
+    """One node per launch (the sequential counterpart of the batched nodes): the same step, taped
+    step and adjoint step bit for bit, eager and as a graph, with the fused update of the batched
+    plan as the reference."""
+    sdc = _sdc(T, nlat, nlon, M, K, 1, precision=prec)
+    x = _states(T, 1, 311)
+    lam = W.random_state(T, 312)[None]
+    lam[..., :T + 1, 1] = 0.0
+    dt = 480.0
+    ref = _outputs(sdc, x, lam, dt)
+    tape_ref = sdc.new_tape()
+    u = _dev(x)
+    sdc.step_taped(u, dt, tape_ref)
+    sdc.set_plan(**dict(DEFAULT, node_launch=1))
+    assert sdc.plan()["node_launch"] == 1
+    got = _outputs(sdc, x, lam, dt)
+    for name, a, b in zip(("f_E", "step", "adjoint"), got, ref):
+        print(f"[gpu] T{T} M={M} K={K} {prec} node_launch {name}: max |diff| {np.max(np.abs(a - b)):.3e}",
+              flush=True)
+        assert np.array_equal(a, b), name
+    ug = _dev(x)
+    for _ in range(2):
+        sdc.step_graph(ug, dt)
+    ue = _dev(x)
+    for _ in range(2):
+        sdc.step(ue, dt)
+    tape = sdc.new_tape()
+    ut = _dev(x)
+    sdc.step_taped(ut, dt, tape)
+    sdc.sync()
+    assert np.array_equal(_host(ug), _host(ue))
+    assert np.array_equal(_host(ut), ref[1])
+    assert np.array_equal(_host(tape), _host(tape_ref))       # the same stage fields, same places
+    sdc.close()
+
+
+def test_node_launch_needs_one_member():
+    sdc = _sdc(21, 34, 64, 2, 2, 2)
+    with pytest.raises(_lib.SDCError) as e:
+        sdc.set_plan(**dict(DEFAULT, node_launch=1))
+    assert e.value.code == _lib.SDC_EINVAL
+    assert sdc.plan() == DEFAULT
+    sdc.close()

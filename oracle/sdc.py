@@ -33,7 +33,7 @@ import torch
 from . import quadrature
 from .imex2 import imex2_step
 from .sht import CT, DT, Sphere, to_complex, to_real
-from .swe import SWE
+from .swe import SWE, SWECoriolisImplicit
 
 
 def dsdc_step(u_n, dt: float, tau: np.ndarray, Q: np.ndarray, K: int,
@@ -103,10 +103,14 @@ class Oracle:
     """Sphere + shallow-water right-hand side + collocation coefficients for one truncation."""
 
     def __init__(self, T: int, nlat: int, nlon: int, radius: float, gravity: float,
-                 omega: float, mean_depth: float, grid=None, qdelta: str = "flex"):
+                 omega: float, mean_depth: float, grid=None, qdelta: str = "flex",
+                 coriolis_implicit: bool = False):
+        """coriolis_implicit: the split with the linear Coriolis term on the implicit side
+        (SWECoriolisImplicit) instead of the paper's spectral-code split."""
         self.sphere = Sphere(T, nlat, nlon, radius, grid)
         self.qdelta = quadrature.QDELTA[qdelta]
-        self.swe = SWE(self.sphere, gravity, omega, mean_depth)
+        cls = SWECoriolisImplicit if coriolis_implicit else SWE
+        self.swe = cls(self.sphere, gravity, omega, mean_depth)
         self.gravity = gravity
         self.mean_depth = mean_depth
 

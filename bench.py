@@ -69,14 +69,15 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=False):
+def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=False, ana_recur=False,
+                     syn_recur1=None, ana_recur1=None):
     """Algorithmic work of every kernel class over one step: {class: (flops, bytes)}.  Bytes are
     the minimum each class must move, independent of the layouts the kernels use.
 
     Legendre: one scalar-equivalent complex transform with equatorial symmetry costs
     2*ncoef*nlat flops; synthesis does 6 per state (zeta, Phi', psi and chi with Pbar, psi and chi
-    with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).  Bytes: both tables (Pbar, H:
-    ncoef x nlat/2 entries each) once per launch; per state the synthesis reads the state
+    with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).  Bytes per launch: both tables
+    (Pbar, H: ncoef x nlat/2 entries each) once; per state the synthesis reads the state
     (3 complex per coefficient, at the column precision: the FP32 mode rounds the columns to
     FP32) and writes 4 Fourier fields (nlat x (T+1) complex FP64); the analysis reads 5 Fourier
     fields (A..E, nlat x (T+1) complex at the column precision) and writes 3 complex per
@@ -87,31 +88,32 @@ def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=Fal
     fused (the node update in the analysis epilogue, M in {1, 2, 4}): the tendencies never reach
     HBM, so the analysis loses its spectral output and gains per coefficient and member
     (K-1)(3 + 5M) + (6 + 2M) complex (u_n, Phi' and delta of the nodes, the new nodes).
-    syn_recur (the synthesis regenerates its tables): the synthesis reads the recurrence
-    coefficients (4 FP64 per (m, n), n < T + 16) and the sectoral values (FP64 per m and northern
-    latitude) instead of the tables; u_n is first converted to the synthesis layout (3 complex in,
-    4 out, an update-class launch).
+    syn_recur (the synthesis regenerates its tables): it reads the recurrence coefficients
+    (4 FP64 per (m, n), n < T + 16) and the sectoral values (FP64 per m and northern latitude)
+    instead of the tables.  ana_recur (the analysis restarts the recurrence): a quarter of the
+    table bytes.  syn_recur1 / ana_recur1: the same for the step's first launch (one state per
+    member), whose plan may differ (default: the node launches').
     """
+    syn_recur1 = syn_recur if syn_recur1 is None else syn_recur1
+    ana_recur1 = ana_recur if ana_recur1 is None else ana_recur1
     ncoef = (T + 1) * (T + 2) // 2
     transform = 2.0 * ncoef * nlat
     states = batch * (1 + (K - 1) * M)          # states transformed per step
-    launches = K                                 # Legendre launches per step (one per sweep + first)
-    tables = 2.0 * ncoef * (nlat // 2) * TABLE_BYTES[precision] * launches
+    tables = 2.0 * ncoef * (nlat // 2) * TABLE_BYTES[precision]   # per launch
+    nhp = (nlat // 2 + 15) // 16 * 16
+    rec_data = 32.0 * (T + 1) * (T + 16) + 8.0 * (T + 1) * nhp
     col = 2.0 * TABLE_BYTES[precision]          # one complex value at the column precision
     four = nlat * (T + 1)                        # Fourier coefficients of one field
-    syn_tables = tables
-    if syn_recur:
-        nhp = (nlat // 2 + 15) // 16 * 16
-        syn_tables = (32.0 * (T + 1) * (T + 16) + 8.0 * (T + 1) * nhp) * launches
-    syn_bytes = syn_tables + states * (3 * col * ncoef + 4 * 16.0 * four)
-    ana_bytes = tables + states * (5 * col * four + 3 * 16.0 * ncoef)
+    syn_tab = (rec_data if syn_recur1 else tables) + (K - 1) * (rec_data if syn_recur else tables)
+    ana_tab = (tables / 4 if ana_recur1 else tables) + (K - 1) * (tables / 4 if ana_recur else tables)
+    syn_bytes = syn_tab + states * (3 * col * ncoef + 4 * 16.0 * four)
+    ana_bytes = ana_tab + states * (5 * col * four + 3 * 16.0 * ncoef)
     grid_bytes = (4 * 16.0 + 5 * col) * four * states
-    conv = 7.0 if syn_recur else 0.0                         # u_n -> synthesis layout (3 -> 4)
-    upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 8 * M) + (6 + 5 * M) + conv)
+    upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 8 * M) + (6 + 5 * M))
     if fused:
         ana_bytes += batch * ncoef * 16.0 * ((K - 1) * (3 + 5 * M) + (6 + 2 * M)) \
             - states * 3 * 16.0 * ncoef
-        upd_bytes = batch * ncoef * 16.0 * conv
+        upd_bytes = 0.0
     return {"synthesis": (6 * transform * states, syn_bytes),
             "analysis": (7 * transform * states, ana_bytes),
             "grid": (0.0, grid_bytes), "update": (0.0, upd_bytes)}
@@ -137,6 +139,7 @@ def roofline_entry(flops, nbytes, secs, launches, precision):
 
 
 FORCED_PLAN = None          # --plan: Legendre variants set instead of tuned
+FORCED_PLAN1 = None         # --plan1: those of the launches over one state per member
 
 
 def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
@@ -150,6 +153,8 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
     x = torch.tensor(W.initial_state(wl)[None], dtype=torch.float64, device="cuda")
     if FORCED_PLAN is not None:                       # fixed variants (profiling runs)
         sdc.set_plan(*FORCED_PLAN)
+        if FORCED_PLAN1 is not None:
+            sdc.set_plan_for(1, *FORCED_PLAN1)
         plan = sdc.plan()
     else:
         plan = sdc.autotune(10)                       # Legendre launch variants (untimed setup)
@@ -167,7 +172,8 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     sdc.sync()
-    out = {"steps_per_s": steps / elapsed, "ms_per_step": elapsed / steps * 1e3, "plan": plan}
+    out = {"steps_per_s": steps / elapsed, "ms_per_step": elapsed / steps * 1e3, "plan": plan,
+           "plan1": sdc.plan_for(1)}
 
     if with_kernels:
         # per-kernel HIP events (on the library's stream) over K eager steps of the same kernels
@@ -183,7 +189,8 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
         sdc.timing(False)
         fused = bool(plan["fuse_update"]) and wl.M in (1, 2, 4)
         work = algorithmic_work(mb.T, mb.nlat, wl.M, wl.K, batch, precision, fused,
-                                bool(plan["syn_recur"]))
+                                bool(plan["syn_recur"]), bool(plan["ana_recur"]),
+                                bool(out["plan1"]["syn_recur"]), bool(out["plan1"]["ana_recur"]))
         out["kernels"] = {name: roofline_entry(work[name][0] * steps, work[name][1] * steps, ms / 1e3,
                                                launches, precision)
                           for name, (ms, launches) in kt.items() if launches > 0}
@@ -424,6 +431,24 @@ def integrators(wl, steps=100, warmup=3):
     sdc.sync()
     out["dSDC_one_node_per_launch"] = {"steps_per_s": round(steps / el, 2), "ms_per_step": round(el / steps * 1e3, 4)}
     sdc.close()
+    # the variant with the linear Coriolis term implicit (f_I = L_g + L_c: two tridiagonal chain
+    # solves per order in every node update)
+    sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, 1, "fp64", W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH,
+              implicit_coriolis=True)
+    sdc.autotune(10)
+    x = x0.clone()
+    for _ in range(warmup):
+        sdc.step_graph(x, mb.dt)
+    sdc.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sdc.step_graph(x, mb.dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sdc.sync()
+    out["dSDC_implicit_coriolis"] = {"steps_per_s": round(steps / el, 2), "ms_per_step": round(el / steps * 1e3, 4)}
+    sdc.close()
     out["f_E_evaluations_per_step"] = {"dSDC": 1 + (wl.K - 1) * wl.M, "sequential_IMEX_SDC": wl.K * wl.M,
                                        "IMEX_o2": 2}
     out["dSDC_speedup_vs_sequential"] = round(out["dSDC"]["steps_per_s"] /
@@ -440,7 +465,7 @@ def integrators(wl, steps=100, warmup=3):
     return out
 
 
-def traffic_for(kernel, plan):
+def traffic_for(kernel, plan, plan1=None):
     """Measured HBM bytes per launch of `kernel` from the committed counter summary, or None when
     the summary is missing, was taken from other kernel sources or (for the Legendre classes)
     from other launch variants than `plan`."""
@@ -457,6 +482,10 @@ def traffic_for(kernel, plan):
     profiled = t.get("legendre_plan") or {}
     if any(profiled.get(f) != plan.get(f) for f in fields):
         return None
+    if plan1 is not None and kernel in ("synthesis", "analysis"):
+        profiled1 = t.get("legendre_plan_one_state") or profiled
+        if any(profiled1.get(f) != plan1.get(f) for f in fields):
+            return None
     k = t["kernels"][kernel]
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
@@ -470,22 +499,23 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     import csv
     plans = []
     for log in bench_logs:
-        found = [json.loads(line)["legendre_plan"] for line in open(log) if line.startswith('{"metric"')]
+        found = [json.loads(line) for line in open(log) if line.startswith('{"metric"')]
         if not found:
             raise RuntimeError(f"no bench result line in {log}")
-        plans.append(found[-1])
+        plans.append((found[-1]["legendre_plan"], found[-1].get("legendre_plan_one_state")))
     if any(p != plans[0] for p in plans):
         raise RuntimeError(f"the counter runs tuned different Legendre variants: {plans}")
-    plan = plans[0]
-    # forward FP64 kernels of the bench workload (names as rocprofv3 prints them)
-    rec = "true" if plan.get("syn_recur") else "false"
-    # every synthesis launch of the step (the first one reads the state in place: a second flag)
-    classes = {f"void k_synthesis<0, double, {plan['syn_lat_tiles']}, {plan['syn_depth']}, {rec},": "synthesis",
-               f"void k_analysis_swe<0, double, {plan['ana_depth']}, "
-               f"{'true' if plan.get('ana_recur') else 'false'}>": "analysis",
-               "void k_grid_swe<": "grid", "void k_update<": "update",
-               # the conversion of u_n to the synthesis layout (regenerating plans only)
-               "k_prep_cml(": "update", "void k_prep_cml(": "update"}
+    plan, plan1 = plans[0]
+    # forward FP64 kernels of the bench workload (names as rocprofv3 prints them): the variants of
+    # both launch shapes (the first f_E's synthesis reads the state in place: a second flag)
+    classes = {}
+    for pl, first in ((plan, "false"), (plan1 or plan, "true")):
+        rec = "true" if pl.get("syn_recur") else "false"
+        classes[f"void k_synthesis<0, double, {pl['syn_lat_tiles']}, {pl['syn_depth']}, {rec}, {first}>"] = \
+            "synthesis"
+        classes[f"void k_analysis_swe<0, double, {pl['ana_depth']}, "
+                f"{'true' if pl.get('ana_recur') else 'false'}>"] = "analysis"
+    classes.update({"void k_grid_swe<": "grid", "void k_update<": "update"})
 
     def per_kernel(path, counter):
         acc = {}
@@ -505,6 +535,7 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     w_scale = copy_bytes / (max(cw) * 1024.0)
     out["fetch_scale"], out["write_scale"] = f_scale, w_scale
     out["legendre_plan"] = plan
+    out["legendre_plan_one_state"] = plan1
     acc = {}                        # per class: every dispatch of every kernel of the class
     for name, vals in fetch.items():
         cls = next((c for key, c in classes.items() if name.startswith(key)), None)
@@ -608,6 +639,8 @@ def cpu_baseline(wl, state0, budget_s=15.0):
     bm = big.members[0]
     ob = Oracle(bm.T, bm.nlat, bm.nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH)
     refs["t511"] = ob.step(W.initial_state(big), bm.dt, big.M, big.K, steps=1)
+    oc = Oracle(mb.T, mb.nlat, mb.nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, coriolis_implicit=True)
+    refs["implicit_coriolis"] = oc.step(state0, mb.dt, wl.M, wl.K, steps=1)
     return base, refs
 
 
@@ -676,6 +709,14 @@ def oracle_errors(wl, refs):
         sdc.sync()
         out[f"t511_m4k4_{prec}_1_step"] = sphere_rel_l2(x.cpu().numpy(), refs["t511"][None], bm.T)
         sdc.close()
+    sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, 1, "fp64", W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH,
+              implicit_coriolis=True)
+    x = dev(x0)
+    sdc.step(x, mb.dt)
+    sdc.sync()
+    out[f"{wl.name}_implicit_coriolis_fp64_1_step"] = sphere_rel_l2(x.cpu().numpy(), refs["implicit_coriolis"][None],
+                                                                    mb.T)
+    sdc.close()
     return out
 
 
@@ -694,15 +735,18 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a reference kernel of known "
                          "traffic for scaling hardware byte counters)")
-    ap.add_argument("--plan", default=None, metavar="TILES,DEPTH,ANA_DEPTH,INTERLEAVE",
+    ap.add_argument("--plan", default=None, metavar="TILES,DEPTH,ANA_DEPTH,INTERLEAVE[,FUSE,SREC,AREC]",
                     help="set these Legendre launch variants instead of running the autotuner "
                          "(profiling runs that must launch the same kernels)")
+    ap.add_argument("--plan1", default=None, metavar="TILES,DEPTH,ANA_DEPTH,INTERLEAVE[,FUSE,SREC,AREC]",
+                    help="with --plan: the variants of the launches over one state per member")
     ap.add_argument("--summarize-pmc", nargs=6,
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB", "OUT", "FETCH_LOG", "WRITE_LOG"))
     args = ap.parse_args()
-    global FORCED_PLAN
+    global FORCED_PLAN, FORCED_PLAN1
     if args.plan:
         FORCED_PLAN = tuple(int(v) for v in args.plan.split(","))
+        FORCED_PLAN1 = tuple(int(v) for v in args.plan1.split(",")) if args.plan1 else None
     if args.summarize_pmc:
         f, w, mib, outp, flog, wlog = args.summarize_pmc
         summarize_pmc(f, w, float(mib), outp, [flog, wlog])
@@ -720,7 +764,7 @@ def main():
     kernels = r64["kernels"]
     dom = max(r64["kernel_ms"], key=lambda k: r64["kernel_ms"][k])
     d = kernels[dom]
-    tr = traffic_for(dom, r64["plan"])
+    tr = traffic_for(dom, r64["plan"], r64["plan1"])
     roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
                 "frac": d["frac"], "traffic": tr, "kernel": dom, "avg_launch_us": d["avg_us"],
                 "timed_over": "eager steps with per-launch HIP events on the library's stream"}
@@ -748,6 +792,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "legendre_plan": r64["plan"],
+        "legendre_plan_one_state": r64["plan1"],
     }
     if not args.no_fp32:
         r32 = measure(wl, "fp32", args.steps, args.warmup)
@@ -763,6 +808,7 @@ def main():
             "equal_error": ee,
             "kernels": r32["kernels"],
             "legendre_plan": r32["plan"],
+            "legendre_plan_one_state": r32["plan1"],
         }
     if not args.no_fp32 and not args.no_work_precision and args.workload == "t255_m4k4":
         result["integrators"] = integrators(wl)
@@ -776,7 +822,8 @@ def main():
             **{p: {"steps_per_s": round(r["steps_per_s"], 3),
                    "fwd_adj_steps_per_s": round(r["fwd_adj_steps_per_s"], 3),
                    "fwd_adj_taped_steps_per_s": round(r["fwd_adj_taped_steps_per_s"], 3),
-                   "legendre_plan": r["plan"]} for p, r in r511.items()}}
+                   "legendre_plan": r["plan"], "legendre_plan_one_state": r["plan1"]}
+                for p, r in r511.items()}}
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

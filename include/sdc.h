@@ -87,6 +87,15 @@ typedef struct {
                                  nonzero diagonals the node update admits) */
     int precision;            /* an sdc_precision value */
     int batch;                /* ensemble members sharing this truncation, >= 1 */
+    int implicit_coriolis;    /* which terms are implicit (the change of split the paper's outlook
+                                 names, Section 6): 0 = the paper's spectral split, f_I = L_g,
+                                 f_E = L_c + N_a + N_r; 1 = the linear Coriolis term implicit too,
+                                 f_I = L_g + L_c, f_E = N_a + N_r, the solve of u - alpha f_I(u) =
+                                 beta then coupling the degrees n +- 1 of each order (two complex
+                                 tridiagonal chains per order m).  With 1, sdc_step[_graph],
+                                 eval_explicit, eval_implicit and imex_solve follow the new split;
+                                 the adjoint, taped, sequential, IMEX-o2, group and one-node-per-
+                                 launch paths return SDC_EUNSUPPORTED. */
 } sdc_config;
 
 typedef struct sdc_ctx* sdc_handle;
@@ -195,14 +204,17 @@ int sht_inverse(sdc_handle h, const double* spec, double* grid);
 int sht_inverse_adjoint(sdc_handle h, const double* grid, double* spec);
 
 /* The solver of Section 4.2: u with u - alpha f_I(u) = beta, for states [batch][3][ncoef];
- * closed form per coefficient.  u may alias beta.  alpha >= 0 and finite. */
+ * closed form per coefficient (with implicit_coriolis: the two tridiagonal chains per order).
+ * u may alias beta.  alpha >= 0 and finite. */
 int imex_solve(sdc_handle h, double alpha, const double* beta, double* u);
 
 /* f_E(u) = L_c + N_a + N_r (Coriolis and nonlinear terms, Sections 3.2 and 4.4) for states
- * [batch][3][ncoef] by a transform round trip; fE must not alias u. */
+ * [batch][3][ncoef] by a transform round trip; fE must not alias u.  With implicit_coriolis,
+ * N_a + N_r only (the products with the relative vorticity instead of the absolute one). */
 int eval_explicit(sdc_handle h, const double* u, double* fE);
 
-/* f_I(u) = L_g(u) (gravity-wave part, Section 3.2) for states [batch][3][ncoef]; fI may alias u. */
+/* f_I(u) = L_g(u) (gravity-wave part, Section 3.2) for states [batch][3][ncoef]; fI may alias u.
+ * With implicit_coriolis, L_g(u) + L_c(u), and fI must not alias u (SDC_EINVAL). */
 int eval_implicit(sdc_handle h, const double* u, double* fI);
 
 /* Wait for all work enqueued by this handle; returns SDC_ENONFINITE if any sdc_step since the
@@ -266,18 +278,31 @@ typedef struct {
                           recomputation of sdc_step_adjoint.  Not changed by the autotuner. */
 } sdc_plan;
 
-/* The handle's current variants. */
+/* The handle's current variants (of the launches over the node states of a sweep). */
 int sdc_get_plan(sdc_handle h, sdc_plan* plan);
 
-/* Select variants; SDC_EINVAL for a combination that is not built (the handle keeps its plan).
- * fuse_update, syn_recur and ana_recur must be 0 or 1.  Graphs cached by sdc_step_graph are
- * dropped and recaptured on their next call. */
+/* Select variants for every launch; SDC_EINVAL for a combination that is not built (the handle
+ * keeps its plan).  fuse_update, syn_recur, ana_recur and node_launch must be 0 or 1.  Graphs
+ * cached by sdc_step_graph are dropped and recaptured on their next call. */
 int sdc_set_plan(sdc_handle h, const sdc_plan* plan);
 
+/* Variants per launch shape.  A handle with M > 1 keeps two Legendre plans: one for the launches
+ * over states = M states per member (the node states of a sweep, Algorithm 2's batched loop over
+ * m) and one for the launches over states = 1 state per member (a step's first f_E, eval_explicit,
+ * the f_E of the comparison integrators, the adjoint's first stage), which read the Legendre
+ * tables for a quarter of the states and may prefer the variants that regenerate them.  All
+ * variants give bitwise the same results.  fuse_update and node_launch belong to the step: set by
+ * either call, reported by both.  states must be 1 or the configured M (SDC_EINVAL otherwise);
+ * with M = 1 both name the same plan.  sdc_autotune chooses both plans. */
+int sdc_get_plan_for(sdc_handle h, int states, sdc_plan* plan);
+int sdc_set_plan_for(sdc_handle h, int states, const sdc_plan* plan);
+
 /* Autotuner: times every built synthesis variant and every analysis variant on the handle's
- * stream, at the launch shape of a step (batch x M states), reps launches each after one warm-up
- * (1 <= reps <= 1000), and switches each kernel to its fastest variant when that is at least 5 %
- * faster than the current one (the plan is written to *chosen unless NULL).  Blocks
+ * stream, at both launch shapes of a step (batch x M states, and batch states with the synthesis
+ * reading the states in place), reps launches each after one warm-up (1 <= reps <= 1000), and
+ * switches each kernel of each shape to its fastest variant when that is at least 5 % faster
+ * than the current one (the plan of the M-state launches is written to *chosen unless NULL; see
+ * sdc_get_plan_for for the other).  Blocks
  * until the timing is done.  Overwrites the handle's synthesis and analysis workspaces (states
  * passed to other calls are not touched) and drops cached step graphs.  SDC_EHIP if a launch
  * fails (the previous plan is kept). */

@@ -24,7 +24,7 @@ class SdcConfig(ctypes.Structure):
     _fields_ = [("T", c_int), ("nlat", c_int), ("nlon", c_int),
                 ("radius", c_double), ("gravity", c_double), ("omega", c_double), ("mean_depth", c_double),
                 ("M", c_int), ("K", c_int), ("nodes", c_int), ("qdelta", c_int), ("precision", c_int),
-                ("batch", c_int)]
+                ("batch", c_int), ("implicit_coriolis", c_int)]
 
 
 class SdcInfo(ctypes.Structure):
@@ -73,6 +73,8 @@ _SIGS = {
     "sdc_get_info": (c_int, [c_void_p, ctypes.POINTER(SdcInfo)]),
     "sdc_get_plan": (c_int, [c_void_p, ctypes.POINTER(SdcPlan)]),
     "sdc_set_plan": (c_int, [c_void_p, ctypes.POINTER(SdcPlan)]),
+    "sdc_get_plan_for": (c_int, [c_void_p, c_int, ctypes.POINTER(SdcPlan)]),
+    "sdc_set_plan_for": (c_int, [c_void_p, c_int, ctypes.POINTER(SdcPlan)]),
     "sdc_autotune": (c_int, [c_void_p, c_int, ctypes.POINTER(SdcPlan)]),
     "sdc_copy_grid": (c_int, [c_void_p, P_DOUBLE, P_DOUBLE]),
     "sdc_copy_coefficients": (c_int, [c_void_p, c_int, P_DOUBLE, P_DOUBLE]),

@@ -25,7 +25,7 @@ class SDC:
     def __init__(self, T: int, nlat: int, nlon: int, M: int, K: int, batch: int = 1,
                  precision: str = "fp64", radius: float = 6.371e6, gravity: float = 9.81,
                  omega: float = 7.292e-5, mean_depth: float = 1.0e4, stream: Optional[int] = None,
-                 qdelta: str = "flex"):
+                 qdelta: str = "flex", implicit_coriolis: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the dSDC library needs a GPU (no CPU fallback)")
@@ -34,7 +34,8 @@ class SDC:
         self.cfg = _lib.SdcConfig(T=T, nlat=nlat, nlon=nlon, radius=radius, gravity=gravity,
                                   omega=omega, mean_depth=mean_depth, M=M, K=K, nodes=0,
                                   qdelta=_lib.QDELTAS[qdelta],
-                                  precision=_lib.PRECISIONS[precision], batch=batch)
+                                  precision=_lib.PRECISIONS[precision], batch=batch,
+                                  implicit_coriolis=int(bool(implicit_coriolis)))
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
@@ -215,6 +216,20 @@ class SDC:
         pl = _lib.SdcPlan(syn_lat_tiles, syn_depth, ana_depth, ana_interleave, fuse_update, syn_recur,
                           ana_recur, node_launch)
         check(self.lib.sdc_set_plan(self.h, ctypes.byref(pl)))
+
+    def plan_for(self, states: int) -> dict:
+        """The launch variants of the launches over `states` states per member (1 or M)."""
+        pl = _lib.SdcPlan()
+        check(self.lib.sdc_get_plan_for(self.h, int(states), ctypes.byref(pl)))
+        return {k: getattr(pl, k) for k, _ in pl._fields_}
+
+    def set_plan_for(self, states: int, syn_lat_tiles: int, syn_depth: int, ana_depth: int,
+                     ana_interleave: int, fuse_update: int = 1, syn_recur: int = 0, ana_recur: int = 0,
+                     node_launch: int = 0):
+        """Select the variants of the launches over `states` states per member (1 or M)."""
+        pl = _lib.SdcPlan(syn_lat_tiles, syn_depth, ana_depth, ana_interleave, fuse_update, syn_recur,
+                          ana_recur, node_launch)
+        check(self.lib.sdc_set_plan_for(self.h, int(states), ctypes.byref(pl)))
 
     def autotune(self, reps: int = 10) -> dict:
         """Time every built variant at this handle's step shape and keep the fastest."""

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsdc_mi355x.so")
-SOURCES = ["api.cpp", "setup.hip", "legendre.hip", "grid.hip", "update.hip", "adjoint.hip", "imex2.hip"]
+SOURCES = ["api.cpp", "setup.hip", "legendre.hip", "grid.hip", "update.hip", "adjoint.hip", "imex2.hip",
+           "coriolis.hip"]
 ARCH = "gfx950"
 
 

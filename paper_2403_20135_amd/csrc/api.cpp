@@ -180,6 +180,9 @@ struct sdc_ctx {
     Geom g{};
     FFTPlan plan{};
     double phibar = 0, inv_a2 = 0, two_omega = 0;
+    double two_omega_explicit = 0;    // f in the explicit products (0 when L_c is implicit)
+    double2* lc = nullptr;            // implicit_coriolis: (e-_k, e+_k) per coefficient
+    double2* lc_scratch = nullptr;    // implicit_coriolis: elimination coefficients of the chains
     std::vector<void*> allocs;
     long long bytes = 0, table_bytes = 0;
     double *mu = nullptr, *w = nullptr, *P = nullptr, *H = nullptr, *tau = nullptr, *Q = nullptr;
@@ -195,7 +198,12 @@ struct sdc_ctx {
     static constexpr int kTileCounts[5] = {1, 2, 3, 4, 6};
     int2* syn_tasks_t[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int n_syn_t[5] = {0, 0, 0, 0, 0};
-    LegPlan lplan{};                  // Legendre launch variants (defaults or sdc_autotune)
+    // Legendre launch variants (defaults or sdc_autotune), per launch shape: lplan for launches
+    // over the node states of a sweep (batch x M states), lplan1 for launches over one state per
+    // member (a step's first f_E, eval_explicit, the comparison integrators, the adjoint's first
+    // stage).  fuse_update and node_launch belong to the step and are read from lplan only.
+    LegPlan lplan{};
+    LegPlan lplan1{};
     int4* ana_tasks = nullptr;        // SWE analysis: 4 wave tasks per workgroup (XCD-ordered)
     int n_ana_wg = 0;
     int2* ssyn_tasks = nullptr;       // scalar synthesis (m, latitude group)
@@ -274,8 +282,9 @@ struct sdc_ctx {
             if (kTileCounts[k] == jt) return k;
         return 0;
     }
-    const int2* syn_list() const { return syn_tasks_t[tiles_index(lplan.syn_tiles)]; }
-    int syn_count() const { return n_syn_t[tiles_index(lplan.syn_tiles)]; }
+    const LegPlan& plan_for(int S) const { return (cfg.M > 1 && S <= cfg.batch) ? lplan1 : lplan; }
+    const int2* syn_list(const LegPlan& lp) const { return syn_tasks_t[tiles_index(lp.syn_tiles)]; }
+    int syn_count(const LegPlan& lp) const { return n_syn_t[tiles_index(lp.syn_tiles)]; }
     void drop_graphs() {
         for (auto& ge : graphs) {
             (void)hipGraphExecDestroy(ge.exec);
@@ -334,6 +343,8 @@ int validate_config(const sdc_config* c) {
     if (c->precision < SDC_FP64 || c->precision > SDC_BF16X3_MFMA)
         return fail(SDC_EINVAL, "precision=%d unknown", c->precision);
     if (c->batch < 1 || c->batch > 4096) return fail(SDC_EINVAL, "batch=%d out of range 1..4096", c->batch);
+    if (c->implicit_coriolis != 0 && c->implicit_coriolis != 1)
+        return fail(SDC_EINVAL, "implicit_coriolis=%d: 0 or 1", c->implicit_coriolis);
     if (c->nlon > 2048) return fail(SDC_EUNSUPPORTED, "nlon=%d > 2048 is not supported", c->nlon);
     FFTPlan pl;
     if (!make_fft_plan(c->nlon, pl) || !fft_length_supported(c->nlon))
@@ -358,6 +369,7 @@ int setup(sdc_ctx* c) {
     c->phibar = cf.gravity * cf.mean_depth;
     c->inv_a2 = 1.0 / (cf.radius * cf.radius);
     c->two_omega = 2.0 * cf.omega;
+    c->two_omega_explicit = cf.implicit_coriolis ? 0.0 : c->two_omega;
     c->smax = cf.batch * cf.M;
     int rc;
 
@@ -477,6 +489,11 @@ int setup(sdc_ctx* c) {
     }
     launch_collocation(c->tau, c->Q, cf.M, c->st);
     launch_degree_tables(c->n_of, c->m_of, c->inv_lap, c->neg_lap, g.T, g.radius, c->st);
+    if (cf.implicit_coriolis) {
+        if ((rc = c->alloc(c->lc, g.ncoef))) return rc;
+        if ((rc = c->alloc(c->lc_scratch, (size_t)c->smax * 2 * 3 * g.ncoef))) return rc;
+        launch_lc_coefs(c->lc, c->n_of, c->m_of, g.ncoef, c->st);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->st));
 
@@ -489,31 +506,25 @@ int setup(sdc_ctx* c) {
 // with states != null, read by the synthesis from the state layout.
 void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr,
                       const UpdateArgs* fuse = nullptr, int fuse_mode = 0, const double* states = nullptr) {
+    const LegPlan& lp = c->plan_for(S);
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
-    launch_synthesis_swe(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
+    launch_synthesis_swe(c->tables(), lp, c->toff, c->rowoff, c->syn_list(lp), c->syn_count(lp),
                          c->cml, S, c->four, c->g, c->st, states);
     c->end(SDC_KERNEL_SYNTHESIS, t);
     t = c->begin(SDC_KERNEL_GRID);
-    launch_grid_swe(c->four, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega, save, c->g, c->st);
+    launch_grid_swe(c->four, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega_explicit, save,
+                    c->g, c->st);
     c->end(SDC_KERNEL_GRID, t);
     t = c->begin(SDC_KERNEL_ANALYSIS);
-    launch_analysis_swe(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
+    launch_analysis_swe(c->tables(), lp, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
                         out, c->g, c->st, fuse, fuse_mode);
     c->end(SDC_KERNEL_ANALYSIS, t);
 }
 
-// f_E of S states in the state layout: a streaming synthesis reads them directly; the regenerating
-// synthesis (no state-input form) takes them converted to the synthesis layout.
+// f_E of S states in the state layout (every synthesis variant reads them in place).
 void run_explicit(sdc_ctx* c, const double* states, int S, double* out, double2* save = nullptr,
                   const UpdateArgs* fuse = nullptr, int fuse_mode = 0) {
-    if (!c->lplan.syn_recur) {
-        run_explicit_cml(c, S, out, save, fuse, fuse_mode, states);
-        return;
-    }
-    const long t = c->begin(SDC_KERNEL_UPDATE);
-    launch_prep_cml(states, S, c->cml, c->P32 != nullptr, c->n_of, c->m_of, c->rowoff, c->inv_lap, c->g.ncoef, c->g.T, c->st);
-    c->end(SDC_KERNEL_UPDATE, t);
-    run_explicit_cml(c, S, out, save, fuse, fuse_mode);
+    run_explicit_cml(c, S, out, save, fuse, fuse_mode, states);
 }
 
 // out_acc += J_E(u)^T ebar for S states whose stage grid fields are in `save`.
@@ -525,10 +536,11 @@ void run_explicit_adj(sdc_ctx* c, const double* ebar, int S, const double2* save
     if (!cml_ready)
         launch_prep_cml_adj(ebar, S, c->cml, c->P32 != nullptr, c->n_of, c->m_of, c->rowoff, c->neg_lap, c->g.ncoef,
                             c->g.T, c->st);
-    launch_synthesis_adj(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
+    const LegPlan& lp = c->plan_for(S);
+    launch_synthesis_adj(c->tables(), lp, c->toff, c->rowoff, c->syn_list(lp), c->syn_count(lp),
                          c->cml, S, c->adj_four5, c->g, c->st);
     launch_grid_adj(c->adj_four5, save, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega, c->g, c->st);
-    launch_analysis_adjoint(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S,
+    launch_analysis_adjoint(c->tables(), lp, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S,
                             c->inv_lap, out_acc, c->g, c->st, fuse);
 }
 
@@ -628,22 +640,22 @@ int sdc_get_info(sdc_handle h, sdc_info* info) {
     return SDC_OK;
 }
 
-int sdc_get_plan(sdc_handle h, sdc_plan* plan) {
-    if (int rc = check_handle(h)) return rc;
-    if (!plan) return fail(SDC_EINVAL, "plan is NULL");
-    plan->syn_lat_tiles = h->lplan.syn_tiles;
-    plan->syn_depth = h->lplan.syn_depth;
-    plan->ana_depth = h->lplan.ana_depth;
-    plan->ana_interleave = h->lplan.ana_interleave;
-    plan->fuse_update = h->lplan.fuse_update;
-    plan->syn_recur = h->lplan.syn_recur;
-    plan->ana_recur = h->lplan.ana_recur;
-    plan->node_launch = h->lplan.node_launch;
-    return SDC_OK;
+}  // extern "C"
+
+namespace {
+
+void plan_out(const LegPlan& lp, const LegPlan& step, sdc_plan* plan) {
+    plan->syn_lat_tiles = lp.syn_tiles;
+    plan->syn_depth = lp.syn_depth;
+    plan->ana_depth = lp.ana_depth;
+    plan->ana_interleave = lp.ana_interleave;
+    plan->syn_recur = lp.syn_recur;
+    plan->ana_recur = lp.ana_recur;
+    plan->fuse_update = step.fuse_update;
+    plan->node_launch = step.node_launch;
 }
 
-int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
-    if (int rc = check_handle(h)) return rc;
+int check_plan(sdc_handle h, const sdc_plan* plan) {
     if (!plan) return fail(SDC_EINVAL, "plan is NULL");
     if (plan->fuse_update != 0 && plan->fuse_update != 1)
         return fail(SDC_EINVAL, "fuse_update=%d: 0 or 1", plan->fuse_update);
@@ -655,6 +667,8 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
         return fail(SDC_EINVAL, "node_launch=%d: 0 or 1", plan->node_launch);
     if (plan->node_launch && h->cfg.batch != 1)
         return fail(SDC_EINVAL, "node_launch=1 is defined for handles of one member (batch=%d)", h->cfg.batch);
+    if (plan->node_launch && h->cfg.implicit_coriolis)
+        return fail(SDC_EUNSUPPORTED, "node_launch=1 is built for the split with f_I = L_g");
     const int jt = plan->syn_lat_tiles, d = plan->syn_depth;
     const bool syn_ok = (jt == 1 && (d == 8 || d == 4)) || (jt == 2 && (d == 4 || d == 2)) ||
                         (jt == 3 && d == 2) || (jt == 4 && (d == 2 || d == 1)) || (jt == 6 && d == 1);
@@ -666,15 +680,73 @@ int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
     if ((plan->ana_depth != 2 && plan->ana_depth != 4) || (plan->ana_interleave != 0 && plan->ana_interleave != 1))
         return fail(SDC_EINVAL, "analysis variant (depth %d, interleave %d) not built: depth 2 or 4, interleave 0 or 1",
                     plan->ana_depth, plan->ana_interleave);
-    h->lplan.syn_tiles = plan->syn_lat_tiles;
-    h->lplan.syn_depth = plan->syn_depth;
-    h->lplan.ana_depth = plan->ana_depth;
-    h->lplan.ana_interleave = plan->ana_interleave;
-    h->lplan.fuse_update = plan->fuse_update;
-    h->lplan.syn_recur = plan->syn_recur;
-    h->lplan.ana_recur = plan->ana_recur;
-    h->lplan.node_launch = plan->node_launch;
+    return SDC_OK;
+}
+
+void plan_in(const sdc_plan* plan, LegPlan& lp) {
+    lp.syn_tiles = plan->syn_lat_tiles;
+    lp.syn_depth = plan->syn_depth;
+    lp.ana_depth = plan->ana_depth;
+    lp.ana_interleave = plan->ana_interleave;
+    lp.syn_recur = plan->syn_recur;
+    lp.ana_recur = plan->ana_recur;
+    lp.fuse_update = plan->fuse_update;
+    lp.node_launch = plan->node_launch;
+}
+
+// the plan of launches over `states` states per member: 1 or the configured M
+LegPlan* plan_of(sdc_handle h, int states) {
+    if (states == h->cfg.M) return &h->lplan;
+    if (states == 1) return &h->lplan1;
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdc_get_plan(sdc_handle h, sdc_plan* plan) {
+    if (int rc = check_handle(h)) return rc;
+    if (!plan) return fail(SDC_EINVAL, "plan is NULL");
+    plan_out(h->lplan, h->lplan, plan);
+    return SDC_OK;
+}
+
+int sdc_set_plan(sdc_handle h, const sdc_plan* plan) {
+    if (int rc = check_handle(h)) return rc;
+    if (int rc = check_plan(h, plan)) return rc;
+    plan_in(plan, h->lplan);
+    plan_in(plan, h->lplan1);
     h->drop_graphs();                 // recaptured with the new variants on their next replay
+    return SDC_OK;
+}
+
+int sdc_get_plan_for(sdc_handle h, int states, sdc_plan* plan) {
+    if (int rc = check_handle(h)) return rc;
+    if (!plan) return fail(SDC_EINVAL, "plan is NULL");
+    const LegPlan* lp = plan_of(h, states);
+    if (!lp) return fail(SDC_EINVAL, "states=%d: 1 or the configured M=%d", states, h->cfg.M);
+    plan_out(h->cfg.M > 1 ? *lp : h->lplan, h->lplan, plan);
+    return SDC_OK;
+}
+
+int sdc_set_plan_for(sdc_handle h, int states, const sdc_plan* plan) {
+    if (int rc = check_handle(h)) return rc;
+    if (int rc = check_plan(h, plan)) return rc;
+    LegPlan* lp = plan_of(h, states);
+    if (!lp) return fail(SDC_EINVAL, "states=%d: 1 or the configured M=%d", states, h->cfg.M);
+    if (h->cfg.M == 1) {              // one launch shape: both plans are the same
+        plan_in(plan, h->lplan);
+        plan_in(plan, h->lplan1);
+    } else {
+        plan_in(plan, *lp);
+        // the step's fields live in lplan
+        h->lplan.fuse_update = plan->fuse_update;
+        h->lplan.node_launch = plan->node_launch;
+        h->lplan1.fuse_update = plan->fuse_update;
+        h->lplan1.node_launch = plan->node_launch;
+    }
+    h->drop_graphs();
     return SDC_OK;
 }
 
@@ -707,89 +779,90 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
     // a candidate replaces the current variant only when it is at least 5 % faster (timing noise
     // and near-ties do not flip the choice)
     constexpr float kMargin = 0.95f;
-    const LegPlan saved = c->lplan;
-    // synthesis: every (tiles, depth, regenerate) variant built
     constexpr int kSyn = 14;
     const int shapes[kSyn][3] = {{1, 8, 0}, {1, 4, 0}, {2, 4, 0}, {2, 2, 0}, {3, 2, 0},
                                  {4, 2, 0}, {4, 1, 0}, {6, 1, 0}, {1, 8, 1}, {1, 4, 1},
                                  {2, 4, 1}, {2, 2, 1}, {4, 2, 1}, {4, 1, 1}};
-    LegPlan syn_cands[kSyn];
-    for (int k = 0; k < kSyn; ++k) {
-        syn_cands[k] = saved;
-        syn_cands[k].syn_tiles = shapes[k][0];
-        syn_cands[k].syn_depth = shapes[k][1];
-        syn_cands[k].syn_recur = shapes[k][2];
-    }
     constexpr int kAna = 8;                 // depth 4 / 2 x interleave 1 / 0 x read / regenerate
-    LegPlan ana_cands[kAna];
-    for (int k = 0; k < kAna; ++k) {
-        ana_cands[k] = saved;
-        ana_cands[k].ana_depth = (k & 2) ? 2 : 4;
-        ana_cands[k].ana_interleave = (k & 1) ? 0 : 1;
-        ana_cands[k].ana_recur = k >> 2;
-    }
-    float syn_ms[kSyn] = {0.f}, ana_ms[kAna] = {0.f};
     hipError_t err = hipSuccess;
-    for (int k = 0; k < kSyn && err == hipSuccess; ++k) {
-        c->lplan = syn_cands[k];
-        err = time_it([&] {
-            launch_synthesis_swe(c->tables(), c->lplan, c->toff, c->rowoff, c->syn_list(), c->syn_count(),
-                                 c->cml, S, c->four, c->g, c->st);
-        }, syn_ms[k]);
-    }
-    for (int k = 0; k < kAna && err == hipSuccess; ++k) {
-        c->lplan = ana_cands[k];
-        err = time_it([&] {
-            launch_analysis_swe(c->tables(), c->lplan, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
-                                c->E, c->g, c->st);
-        }, ana_ms[k]);
-    }
-    LegPlan best = saved;
-    if (err == hipSuccess) {
-        int cur = 0, fast = 0;
+    // Times every synthesis and analysis variant at S states and returns `cur` with the fastest
+    // of each (the synthesis of one state per member reads the states in place, as a step's
+    // first f_E does).
+    auto tune = [&](const LegPlan& cur, int S, const double* state_in) {
+        LegPlan syn_cands[kSyn], ana_cands[kAna];
         for (int k = 0; k < kSyn; ++k) {
-            if (syn_cands[k].syn_tiles == saved.syn_tiles && syn_cands[k].syn_depth == saved.syn_depth &&
-                syn_cands[k].syn_recur == saved.syn_recur)
-                cur = k;
+            syn_cands[k] = cur;
+            syn_cands[k].syn_tiles = shapes[k][0];
+            syn_cands[k].syn_depth = shapes[k][1];
+            syn_cands[k].syn_recur = shapes[k][2];
+        }
+        for (int k = 0; k < kAna; ++k) {
+            ana_cands[k] = cur;
+            ana_cands[k].ana_depth = (k & 2) ? 2 : 4;
+            ana_cands[k].ana_interleave = (k & 1) ? 0 : 1;
+            ana_cands[k].ana_recur = k >> 2;
+        }
+        float syn_ms[kSyn] = {0.f}, ana_ms[kAna] = {0.f};
+        for (int k = 0; k < kSyn && err == hipSuccess; ++k) {
+            const LegPlan& lp = syn_cands[k];
+            err = time_it([&] {
+                launch_synthesis_swe(c->tables(), lp, c->toff, c->rowoff, c->syn_list(lp), c->syn_count(lp),
+                                     c->cml, S, c->four, c->g, c->st, state_in);
+            }, syn_ms[k]);
+        }
+        for (int k = 0; k < kAna && err == hipSuccess; ++k) {
+            const LegPlan& lp = ana_cands[k];
+            err = time_it([&] {
+                launch_analysis_swe(c->tables(), lp, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
+                                    c->E, c->g, c->st);
+            }, ana_ms[k]);
+        }
+        LegPlan best = cur;
+        if (err != hipSuccess) return best;
+        int now = 0, fast = 0;
+        for (int k = 0; k < kSyn; ++k) {
+            if (syn_cands[k].syn_tiles == cur.syn_tiles && syn_cands[k].syn_depth == cur.syn_depth &&
+                syn_cands[k].syn_recur == cur.syn_recur)
+                now = k;
             if (syn_ms[k] < syn_ms[fast]) fast = k;
         }
-        if (syn_ms[fast] < kMargin * syn_ms[cur]) {
+        if (syn_ms[fast] < kMargin * syn_ms[now]) {
             best.syn_tiles = syn_cands[fast].syn_tiles;
             best.syn_depth = syn_cands[fast].syn_depth;
             best.syn_recur = syn_cands[fast].syn_recur;
         }
-        cur = 0;
+        now = 0;
         fast = 0;
         for (int k = 0; k < kAna; ++k) {
-            if (ana_cands[k].ana_depth == saved.ana_depth && ana_cands[k].ana_interleave == saved.ana_interleave &&
-                ana_cands[k].ana_recur == saved.ana_recur)
-                cur = k;
+            if (ana_cands[k].ana_depth == cur.ana_depth && ana_cands[k].ana_interleave == cur.ana_interleave &&
+                ana_cands[k].ana_recur == cur.ana_recur)
+                now = k;
             if (ana_ms[k] < ana_ms[fast]) fast = k;
         }
-        if (ana_ms[fast] < kMargin * ana_ms[cur]) {
+        if (ana_ms[fast] < kMargin * ana_ms[now]) {
             best.ana_depth = ana_cands[fast].ana_depth;
             best.ana_interleave = ana_cands[fast].ana_interleave;
             best.ana_recur = ana_cands[fast].ana_recur;
         }
-    }
+        return best;
+    };
+    const LegPlan saved = c->lplan, saved1 = c->lplan1;
+    LegPlan best = tune(saved, S, nullptr);
+    // launches over one state per member (handles with more than one node): their own variants
+    LegPlan best1 = c->cfg.M > 1 ? tune(saved1, c->cfg.batch, c->ua) : best;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) {
         c->lplan = saved;
+        c->lplan1 = saved1;
         return fail(SDC_EHIP, "autotune launch failed: %s", hipGetErrorString(err));
     }
     c->lplan = best;
+    c->lplan1 = best1;
+    c->lplan1.fuse_update = best.fuse_update;
+    c->lplan1.node_launch = best.node_launch;
     c->drop_graphs();
-    if (chosen) {
-        chosen->syn_lat_tiles = best.syn_tiles;
-        chosen->syn_depth = best.syn_depth;
-        chosen->ana_depth = best.ana_depth;
-        chosen->ana_interleave = best.ana_interleave;
-        chosen->fuse_update = best.fuse_update;
-        chosen->syn_recur = best.syn_recur;
-        chosen->ana_recur = best.ana_recur;
-        chosen->node_launch = best.node_launch;
-    }
+    if (chosen) plan_out(best, best, chosen);
     return SDC_OK;
 }
 
@@ -848,6 +921,67 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K, double2* t
     a.E_member = fs;
     double* bufs[2] = {c->ua, c->ub};
     int cur = 0;
+    if (c->cfg.implicit_coriolis) {
+        // f_I = L_g + L_c: every node update is a pair of tridiagonal chain solves per order
+        // (the sweeps of Algorithm 2 are unchanged; f_E is N_a + N_r)
+        LcArgs l{};
+        l.mode = 0;
+        l.un = state;
+        l.uprev = state;
+        l.uprev_node = 0;
+        l.uprev_member = fs;
+        l.E = c->E0;
+        l.E_node = 0;
+        l.E_member = fs;
+        l.cml32 = c->P32 != nullptr ? 1 : 0;
+        l.tau = c->tau + M * kMaxNodes;
+        l.Q = c->Q + M * kMaxNodes * kMaxNodes;
+        l.rowoff = c->rowoff;
+        l.inv_lap = c->inv_lap;
+        l.lc = c->lc;
+        l.scratch = c->lc_scratch;
+        l.flag = c->flag;
+        l.dt = dt;
+        l.phibar = c->phibar;
+        l.inv_a2 = c->inv_a2;
+        l.two_omega = c->two_omega;
+        l.M = M;
+        l.batch = B;
+        l.ncoef = c->g.ncoef;
+        l.T = c->g.T;
+        auto solve = [&] {
+            const long t = c->begin(SDC_KERNEL_UPDATE);
+            launch_solve_lc(l, c->st);
+            c->end(SDC_KERNEL_UPDATE, t);
+        };
+        run_explicit(c, state, B, c->E0, tape_at(0));
+        for (int s = 1; s < K; ++s) {
+            l.uout = bufs[cur];
+            l.out_node = fs;
+            l.out_member = (long long)M * fs;
+            l.cml = c->cml;
+            l.sweep = qd_sweep(c, s, M);
+            l.last_only = 0;
+            solve();
+            run_explicit_cml(c, B * M, c->E, tape_at(s));
+            l.uprev = bufs[cur];
+            l.uprev_node = fs;
+            l.uprev_member = (long long)M * fs;
+            l.E = c->E;
+            l.E_node = fs;
+            l.E_member = (long long)M * fs;
+            cur ^= 1;
+        }
+        if (!last_update) return;
+        l.uout = state;
+        l.out_node = 0;
+        l.out_member = fs;
+        l.cml = nullptr;
+        l.sweep = qd_sweep(c, K, M);
+        l.last_only = 1;
+        solve();
+        return;
+    }
     if (c->lplan.node_launch) {
         // The same sweeps with the f_E of the nodes evaluated one node per launch (one member:
         // node j of a sweep is state j of the stage), after a separate update of all nodes: the
@@ -1051,8 +1185,17 @@ void enqueue_seq(sdc_ctx* c, double* state, double dt, int M, int K) {
     }
 }
 
+// Paths built for the paper's split only (f_I = L_g): the adjoint, the sequential SDC and IMEX-o2
+// with their closed-form gravity-wave solves.
+int paper_split_only(sdc_handle h, const char* what) {
+    if (h->cfg.implicit_coriolis)
+        return fail(SDC_EUNSUPPORTED, "%s is built for the split with f_I = L_g (implicit_coriolis = 0)", what);
+    return SDC_OK;
+}
+
 int check_imex2_state(sdc_handle h, const double* state, double dt) {
     if (int rc = check_handle(h)) return rc;
+    if (int rc = paper_split_only(h, "IMEX-o2")) return rc;
     if (!state) return fail(SDC_EINVAL, "state is NULL");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(SDC_EINVAL, "dt must be positive and finite");
     return SDC_OK;
@@ -1066,6 +1209,7 @@ int check_imex2_args(sdc_handle h, const double* state, double dt) {
 int check_adjoint_args(sdc_handle h, const double* state_n, const double* lam_np1, const double* lam_n,
                        double dt, int M, int K) {
     if (int rc = check_handle(h)) return rc;
+    if (int rc = paper_split_only(h, "the adjoint step")) return rc;
     if (!state_n || !lam_np1 || !lam_n) return fail(SDC_EINVAL, "state_n/lam_np1/lam_n is NULL");
     if (M < 1 || M > h->cfg.M) return fail(SDC_EINVAL, "M=%d out of range 1..%d", M, h->cfg.M);
     if (K < 1 || K > h->cfg.K) return fail(SDC_EINVAL, "K=%d out of range 1..%d", K, h->cfg.K);
@@ -1205,6 +1349,7 @@ int sdc_step_graph(sdc_handle h, double* state, double dt, int M, int K) {
 
 int sdc_step_sequential(sdc_handle h, double* state, double dt, int M, int K) {
     if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    if (int rc = paper_split_only(h, "the sequential IMEX SDC step")) return rc;
     if (int rc = alloc_seq(h)) return rc;
     enqueue_seq(h, state, dt, M, K);
     HIP_TRY(hipGetLastError());
@@ -1213,6 +1358,7 @@ int sdc_step_sequential(sdc_handle h, double* state, double dt, int M, int K) {
 
 int sdc_step_sequential_graph(sdc_handle h, double* state, double dt, int M, int K) {
     if (int rc = check_step_args(h, state, dt, M, K)) return rc;
+    if (int rc = paper_split_only(h, "the sequential IMEX SDC step")) return rc;
     if (int rc = alloc_seq(h)) return rc;
     return graph_launch(h, 2, state, dt, M, K, [&] { enqueue_seq(h, state, dt, M, K); });
 }
@@ -1331,7 +1477,33 @@ int imex_solve(sdc_handle h, double alpha, const double* beta, double* u) {
     if (int rc = check_handle(h)) return rc;
     if (!beta || !u) return fail(SDC_EINVAL, "beta/u is NULL");
     if (!(alpha >= 0) || !std::isfinite(alpha)) return fail(SDC_EINVAL, "alpha must be >= 0 and finite");
-    launch_solve(alpha, beta, u, h->n_of, h->phibar, h->inv_a2, h->cfg.batch, h->g.ncoef, h->st);
+    if (h->cfg.implicit_coriolis) {
+        LcArgs l{};
+        l.mode = 1;
+        l.beta = beta;
+        l.alpha = alpha;
+        l.uout = u;
+        l.out_member = 3LL * h->g.ncoef * 2;
+        l.lc = h->lc;
+        l.scratch = h->lc_scratch;
+        l.rowoff = h->rowoff;
+        l.inv_lap = h->inv_lap;
+        l.flag = h->flag;
+        l.tau = h->tau + kMaxNodes;       // unused by the plain solve (valid addresses only)
+        l.Q = h->Q + kMaxNodes * kMaxNodes;
+        l.cml = nullptr;
+        l.phibar = h->phibar;
+        l.inv_a2 = h->inv_a2;
+        l.two_omega = h->two_omega;
+        l.M = 1;
+        l.batch = h->cfg.batch;
+        l.ncoef = h->g.ncoef;
+        l.T = h->g.T;
+        l.sweep = 1;
+        launch_solve_lc(l, h->st);
+    } else {
+        launch_solve(alpha, beta, u, h->n_of, h->phibar, h->inv_a2, h->cfg.batch, h->g.ncoef, h->st);
+    }
     HIP_TRY(hipGetLastError());
     return SDC_OK;
 }
@@ -1348,7 +1520,16 @@ int eval_explicit(sdc_handle h, const double* u, double* fE) {
 int eval_implicit(sdc_handle h, const double* u, double* fI) {
     if (int rc = check_handle(h)) return rc;
     if (!u || !fI) return fail(SDC_EINVAL, "u/fI is NULL");
-    launch_implicit(u, fI, h->n_of, h->phibar, h->inv_a2, h->cfg.batch, h->g.ncoef, h->st);
+    if (h->cfg.implicit_coriolis) {
+        const size_t nb = (size_t)h->cfg.batch * 3 * h->g.ncoef * 2 * sizeof(double);
+        const char *pu = (const char*)u, *pf = (const char*)fI;
+        if (pu < pf + nb && pf < pu + nb)
+            return fail(SDC_EINVAL, "with implicit_coriolis fI must not overlap u (L_c reads neighbouring degrees)");
+        launch_implicit_lc(u, fI, h->n_of, h->m_of, h->lc, h->phibar, h->inv_a2, h->two_omega, h->g.T,
+                           h->cfg.batch, h->g.ncoef, h->st);
+    } else {
+        launch_implicit(u, fI, h->n_of, h->phibar, h->inv_a2, h->cfg.batch, h->g.ncoef, h->st);
+    }
     HIP_TRY(hipGetLastError());
     return SDC_OK;
 }

@@ -313,14 +313,40 @@ struct Imex2Args {
     int phase, batch, ncoef, T;
 };
 void launch_imex2(const Imex2Args& a, hipStream_t st);
-// Synthesis layout of `batch` states [b][3][ncoef] (the first f_E of a step, eval_explicit).
-void launch_prep_cml(const double* state, int nstates, double* cml, bool cml32, const int* n_of,
-                     const int* m_of, const int* rowoff, const double* inv_lap, int ncoef, int T,
-                     hipStream_t st);
 void launch_implicit(const double* u, double* fI, const int* n_of, double phibar, double inv_a2,
                      int batch, int ncoef, hipStream_t st);
 void launch_solve(double alpha, const double* beta, double* u, const int* n_of, double phibar,
                   double inv_a2, int batch, int ncoef, hipStream_t st);
+
+// coriolis.hip: the split with the linear Coriolis term implicit (f_I = L_g + L_c)
+struct LcArgs {
+    int mode;                    // 0: node update of a sweep, 1: u = solve(alpha, beta)
+    const double* un;            // mode 0: [B][3][ncoef]
+    const double* uprev;         // mode 0: node iterates of the previous sweep (strides as UpdateArgs)
+    long long uprev_node, uprev_member;
+    const double* E;             // mode 0: f_E = N_a + N_r of the previous sweep's nodes
+    long long E_node, E_member;
+    double* uout;                // output states (mode 0: nodes, or the state when last_only)
+    long long out_node, out_member;
+    double* cml;                 // synthesis layout of the new nodes (or nullptr)
+    int cml32;
+    const double* beta;          // mode 1: [B][3][ncoef] (u may alias it)
+    double alpha;                // mode 1
+    const double* tau;
+    const double* Q;
+    const int* rowoff;
+    const double* inv_lap;
+    const double2* lc;           // (e-_k, e+_k) per coefficient
+    double2* scratch;            // 3 complex per (output state, chain, coefficient)
+    int* flag;
+    double dt, phibar, inv_a2, two_omega;
+    int M, batch, ncoef, T, sweep, last_only;
+};
+void launch_lc_coefs(double2* lc, const int* n_of, const int* m_of, int ncoef, hipStream_t st);
+void launch_solve_lc(const LcArgs& a, hipStream_t st);
+void launch_implicit_lc(const double* u, double* fI, const int* n_of, const int* m_of, const double2* lc,
+                        double phibar, double inv_a2, double two_omega, int T, int batch, int ncoef,
+                        hipStream_t st);
 
 // adjoint.hip
 void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, bool cml32, const int* n_of,

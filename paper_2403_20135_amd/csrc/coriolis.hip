@@ -1,0 +1,245 @@
+// The split with the linear Coriolis term on the implicit side (the change of implicit and
+// explicit terms the paper's outlook names, Section 6): f_I = L_g + L_c, f_E = N_a + N_r.
+//
+// L_c(u) = (0, -div(f U, f V), curl(f U, f V)), f = 2 Omega mu, in spectral space couples degree
+// k of order m with k - 1 and k + 1 (mu P and (1 - mu^2) dP/dmu of orthonormal functions are
+// combinations of the neighbouring degrees), per coefficient:
+//   d zeta_k  = i b_k zeta_k - 2 Omega (e-_k delta_{k-1} + e+_k delta_{k+1})
+//   d delta_k = i b_k delta_k + 2 Omega (e-_k zeta_{k-1} + e+_k zeta_{k+1})
+// with b_k = 2 Omega m / (k (k + 1)) (0 at k = 0), e-_k = eps_k (k + 1) / k (0 at k = 0),
+// e+_k = eps_{k+1} k / (k + 1), eps_k = sqrt((k^2 - m^2) / (4 k^2 - 1)), and degrees outside
+// m..T dropped (the truncation).  Together with L_g (d Phi' = -Phi_bar delta, d delta = c_k Phi',
+// c_k = k (k + 1) / a^2) the solve of u - alpha f_I(u) = beta splits, per order m, into two
+// independent chains over k = m..T: chain c holds zeta at the degrees with k - m = c (mod 2) and
+// delta and Phi' at the others, Phi' eliminated (Phi'_k = beta_Phi,k - alpha Phi_bar delta_k).
+// Each chain is a complex tridiagonal system, diagonally dominant for the step sizes of the
+// shallow-water configurations (off-diagonals 2 Omega alpha e <~ 0.1, diagonals of modulus >= 1),
+// solved by forward elimination and back substitution without pivoting.  One thread carries one
+// chain of one order of one output state; the elimination's coefficients go to a scratch buffer.
+#include "common.h"
+
+// (e-_k, e+_k) per coefficient of the m-major triangular layout
+__global__ __launch_bounds__(kBlock) void k_lc_coefs(double2* __restrict__ lc, const int* __restrict__ n_of,
+                                                     const int* __restrict__ m_of, int ncoef) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ncoef) return;
+    const double k = n_of[idx], m = m_of[idx];
+    auto eps = [&](double n) { return n > m ? sqrt((n * n - m * m) / (4.0 * n * n - 1.0)) : 0.0; };
+    const double em = k > 0.0 ? eps(k) * (k + 1.0) / k : 0.0;
+    const double ep = eps(k + 1.0) * k / (k + 1.0);
+    lc[idx] = make_double2(em, ep);
+}
+
+void launch_lc_coefs(double2* lc, const int* n_of, const int* m_of, int ncoef, hipStream_t st) {
+    k_lc_coefs<<<(ncoef + kBlock - 1) / kBlock, kBlock, 0, st>>>(lc, n_of, m_of, ncoef);
+}
+
+namespace {
+
+__device__ __forceinline__ double2 ld(const double* p) { return *(const double2*)p; }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 rmul(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 imul(double s, double2 a) { return make_double2(-s * a.y, s * a.x); }  // i s a
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cinv(double2 a) {
+    const double r = 1.0 / (a.x * a.x + a.y * a.y);
+    return make_double2(a.x * r, -a.y * r);
+}
+
+// f_I = L_g + L_c of the state u ([3][ncoef] complex) at degree k of order m (coefficient idx,
+// first coefficient of the order at idx0); fields (Phi', zeta, delta).
+struct FI {
+    double2 phi, zeta, div;
+};
+__device__ __forceinline__ FI f_implicit_at(const double* __restrict__ u, size_t fs, int idx, int k, int m,
+                                            int T, double2 e, double two_omega, double phibar, double cn) {
+    const double2 z = ld(u + fs + 2 * (size_t)idx), d = ld(u + 2 * fs + 2 * (size_t)idx);
+    const double2 p = ld(u + 2 * (size_t)idx);
+    double2 zm = make_double2(0.0, 0.0), zp = zm, dm = zm, dp = zm;
+    if (k > m) {
+        zm = ld(u + fs + 2 * (size_t)(idx - 1));
+        dm = ld(u + 2 * fs + 2 * (size_t)(idx - 1));
+    }
+    if (k < T) {
+        zp = ld(u + fs + 2 * (size_t)(idx + 1));
+        dp = ld(u + 2 * fs + 2 * (size_t)(idx + 1));
+    }
+    const double b = k > 0 ? two_omega * m / (k * (k + 1.0)) : 0.0;
+    FI r;
+    r.phi = rmul(-phibar, d);
+    r.zeta = csub(imul(b, z), rmul(two_omega, cadd(rmul(e.x, dm), rmul(e.y, dp))));
+    r.div = cadd(cadd(imul(b, d), rmul(cn, p)), rmul(two_omega, cadd(rmul(e.x, zm), rmul(e.y, zp))));
+    return r;
+}
+
+}  // namespace
+
+// The chain solve.  mode 0: node update of a dSDC sweep (Section 4.2, with f_I = L_g + L_c) for
+// output node i of member b; mode 1: u = solve(alpha, beta) of member b.
+__global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
+    const int nodes = a.mode == 0 ? (a.last_only ? 1 : a.M) : 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per_m = 2 * nodes * a.batch;
+    if (t >= (a.T + 1) * per_m) return;
+    const int m = t / per_m;
+    int r = t - m * per_m;
+    const int c = r / (nodes * a.batch);
+    r -= c * nodes * a.batch;
+    const int i = a.mode == 0 ? (a.last_only ? a.M - 1 : r / a.batch) : 0;   // output node
+    const int b = r % a.batch;
+    const int T = a.T;
+    const size_t fs = (size_t)a.ncoef * 2;
+    const int idx0 = coef_offset(T, m);
+    const int J = T + 1 - m;
+    const int sdiv = a.sweep < a.M ? a.sweep : a.M;
+    const double alpha = a.mode == 0 ? a.dt * a.tau[i] / sdiv : a.alpha;
+    const double two_omega = a.two_omega;
+    // scratch: 3 complex per (output state, chain, coefficient)
+    const int ostate = a.mode == 0 ? (a.last_only ? b : b * a.M + i) : b;
+    double2* sc = a.scratch + ((size_t)ostate * 2 + c) * a.ncoef * 3;
+    const double* Qi = a.Q + i * kMaxNodes;
+    // right-hand side (beta) at degree k
+    auto rhs = [&](int k, int idx, double cn, double2 e, bool zeta_pos) {
+        FI bt;
+        if (a.mode == 1) {
+            // only the fields this chain owns at this degree: u may alias beta
+            const double* be = a.beta + (size_t)b * 3 * fs;
+            const double2 z0 = make_double2(0.0, 0.0);
+            bt.phi = zeta_pos ? z0 : ld(be + 2 * (size_t)idx);
+            bt.zeta = zeta_pos ? ld(be + fs + 2 * (size_t)idx) : z0;
+            bt.div = zeta_pos ? z0 : ld(be + 2 * fs + 2 * (size_t)idx);
+            return bt;
+        }
+        const double* un = a.un + (size_t)b * 3 * fs;
+        bt.phi = ld(un + 2 * (size_t)idx);
+        bt.zeta = ld(un + fs + 2 * (size_t)idx);
+        bt.div = ld(un + 2 * fs + 2 * (size_t)idx);
+        FI own{};
+        for (int j = 0; j < a.M; ++j) {
+            const double* uj = a.uprev + (size_t)b * a.uprev_member + (size_t)j * a.uprev_node;
+            const double* ej = a.E + (size_t)b * a.E_member + (size_t)j * a.E_node;
+            const FI fi = f_implicit_at(uj, fs, idx, k, m, T, e, two_omega, a.phibar, cn);
+            if (j == i) own = fi;
+            const double q = a.dt * Qi[j];
+            bt.phi = cadd(bt.phi, rmul(q, cadd(fi.phi, ld(ej + 2 * (size_t)idx))));
+            bt.zeta = cadd(bt.zeta, rmul(q, cadd(fi.zeta, ld(ej + fs + 2 * (size_t)idx))));
+            bt.div = cadd(bt.div, rmul(q, cadd(fi.div, ld(ej + 2 * fs + 2 * (size_t)idx))));
+        }
+        bt.phi = csub(bt.phi, rmul(alpha, own.phi));
+        bt.zeta = csub(bt.zeta, rmul(alpha, own.zeta));
+        bt.div = csub(bt.div, rmul(alpha, own.div));
+        return bt;
+    };
+    // forward elimination
+    double2 cp = make_double2(0.0, 0.0), dp = cp;
+    for (int j = 0; j < J; ++j) {
+        const int k = m + j, idx = idx0 + j;
+        const double cn = k * (k + 1.0) * a.inv_a2;
+        const double2 e = a.lc[idx];
+        const bool zeta_pos = ((j & 1) == c);
+        const FI bt = rhs(k, idx, cn, e, zeta_pos);
+        const double bk = k > 0 ? two_omega * m / (k * (k + 1.0)) : 0.0;
+        double2 D;
+        double Lo, Up;
+        double2 rr;
+        if (zeta_pos) {
+            D = make_double2(1.0, -alpha * bk);
+            Lo = two_omega * alpha * e.x;
+            Up = two_omega * alpha * e.y;
+            rr = bt.zeta;
+        } else {
+            D = make_double2(1.0 + alpha * alpha * a.phibar * cn, -alpha * bk);
+            Lo = -two_omega * alpha * e.x;
+            Up = -two_omega * alpha * e.y;
+            rr = cadd(bt.div, rmul(alpha * cn, bt.phi));
+        }
+        if (j == J - 1) Up = 0.0;                       // degree T + 1 is truncated
+        const double2 den = j == 0 ? D : csub(D, rmul(Lo, cp));
+        const double2 inv = cinv(den);
+        cp = rmul(Up, inv);
+        dp = cmul(csub(rr, rmul(Lo, dp)), inv);
+        sc[3 * (size_t)idx] = cp;
+        sc[3 * (size_t)idx + 1] = dp;
+        sc[3 * (size_t)idx + 2] = bt.phi;
+    }
+    // back substitution and output
+    double* out = a.uout + (size_t)b * a.out_member + (size_t)(a.mode == 0 && !a.last_only ? i : 0) * a.out_node;
+    const size_t S = (size_t)a.batch * a.M;
+    const size_t cs = (size_t)b * a.M + i;                // synthesis-layout state of this node
+    bool bad = false;
+    double2 x = make_double2(0.0, 0.0);
+    for (int j = J - 1; j >= 0; --j) {
+        const int k = m + j, idx = idx0 + j;
+        const double2 cpj = sc[3 * (size_t)idx], dpj = sc[3 * (size_t)idx + 1];
+        x = csub(dpj, cmul(cpj, x));
+        const bool zeta_pos = ((j & 1) == c);
+        const int par = j & 1, kk = j >> 1;
+        const double il = a.cml ? a.inv_lap[k] : 0.0;      // only the synthesis layout needs it
+        const size_t ci = a.cml ? (((size_t)a.rowoff[2 * m + par] + kk) * S + cs) * kCmlVals : 0;
+        const double2 xv = x;
+        if (zeta_pos) {
+            *(double2*)(out + fs + 2 * (size_t)idx) = xv;
+            if (a.cml) {
+                cml_put(a.cml, a.cml32, ci, xv.x);
+                cml_put(a.cml, a.cml32, ci + 1, xv.y);
+                cml_put(a.cml, a.cml32, ci + 4, il * xv.x);
+                cml_put(a.cml, a.cml32, ci + 5, il * xv.y);
+            }
+            bad = bad || !(isfinite(xv.x) && isfinite(xv.y));
+        } else {
+            const double2 bphi = sc[3 * (size_t)idx + 2];
+            const double2 phi = csub(bphi, rmul(alpha * a.phibar, xv));
+            *(double2*)(out + 2 * fs + 2 * (size_t)idx) = xv;
+            *(double2*)(out + 2 * (size_t)idx) = phi;
+            if (a.cml) {
+                cml_put(a.cml, a.cml32, ci + 2, phi.x);
+                cml_put(a.cml, a.cml32, ci + 3, phi.y);
+                cml_put(a.cml, a.cml32, ci + 6, il * xv.x);
+                cml_put(a.cml, a.cml32, ci + 7, il * xv.y);
+            }
+            bad = bad || !(isfinite(xv.x) && isfinite(xv.y) && isfinite(phi.x) && isfinite(phi.y));
+        }
+    }
+    // padding rows of the synthesis layout: chain c clears those of parity c
+    if (a.cml) {
+        const int np = npk_of(T, m, c);
+        if (np > 0) cml_clear_pad(a.cml, a.cml32, a.rowoff[2 * m + c], np - 1, np, S, cs);
+    }
+    if (a.last_only && bad) a.flag[0] = 1;
+}
+
+void launch_solve_lc(const LcArgs& a, hipStream_t st) {
+    const int nodes = a.mode == 0 ? (a.last_only ? 1 : a.M) : 1;
+    const int n = (a.T + 1) * 2 * nodes * a.batch;
+    k_solve_lc<<<(n + 63) / 64, 64, 0, st>>>(a);
+}
+
+// f_I = L_g + L_c of `batch` states; fI must not alias u (the neighbours are read).
+__global__ __launch_bounds__(kBlock) void k_implicit_lc(const double* __restrict__ u, double* __restrict__ fI,
+                                                        const int* __restrict__ n_of,
+                                                        const int* __restrict__ m_of,
+                                                        const double2* __restrict__ lc, double phibar,
+                                                        double inv_a2, double two_omega, int T, int ncoef) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= ncoef) return;
+    const size_t fs = (size_t)ncoef * 2;
+    const int k = n_of[idx], m = m_of[idx];
+    const double cn = k * (k + 1.0) * inv_a2;
+    const double* us = u + (size_t)b * 3 * fs;
+    const FI r = f_implicit_at(us, fs, idx, k, m, T, lc[idx], two_omega, phibar, cn);
+    double* o = fI + (size_t)b * 3 * fs + 2 * (size_t)idx;
+    *(double2*)o = r.phi;
+    *(double2*)(o + fs) = r.zeta;
+    *(double2*)(o + 2 * fs) = r.div;
+}
+
+void launch_implicit_lc(const double* u, double* fI, const int* n_of, const int* m_of, const double2* lc,
+                        double phibar, double inv_a2, double two_omega, int T, int batch, int ncoef,
+                        hipStream_t st) {
+    dim3 grid((ncoef + kBlock - 1) / kBlock, batch);
+    k_implicit_lc<<<grid, kBlock, 0, st>>>(u, fI, n_of, m_of, lc, phibar, inv_a2, two_omega, T, ncoef);
+}

@@ -144,7 +144,7 @@ __device__ __forceinline__ void transpose_rows4(double (&v)[4]) {
 }
 
 //
-// SIN (forward, streamed tables): the input columns are read from the state layout itself
+// SIN (forward): the input columns are read from the state layout itself
 // ([state][Phi', zeta, delta][ncoef] complex) instead of the synthesis layout: value v is zeta
 // (v < 2), Phi' (v < 4) or inv_lap[n] times zeta or delta (v >= 4), part v & 1, formed with the
 // same products and roundings as the conversion kernel, so a step's first f_E needs no
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     unsigned boff[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * tsz;
-    static_assert(!SIN || (MODE == kSynForward && !REC), "state input: forward, streamed tables");
+    static_assert(!SIN || MODE == kSynForward, "state input: forward synthesis");
     size_t soff[NT];
     bool sscale[NT];
     const int npk = npk_of(g.T, m, p);
@@ -382,11 +382,20 @@ static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t
 #define SYN(JT, D) k_synthesis<MODE, TT, JT, D, false><<<grid, kSynBlock, 0, st>>>(SYN_ARGS)
 #define SYN_REC(JT, D) k_synthesis<MODE, TT, JT, D, true><<<grid, kSynBlock, 0, st>>>(SYN_ARGS)
 #define SYN_SIN(JT, D) k_synthesis<MODE, TT, JT, D, false, true><<<grid, kSynBlock, 0, st>>>(SYN_ARGS)
+#define SYN_SIN_REC(JT, D) k_synthesis<MODE, TT, JT, D, true, true><<<grid, kSynBlock, 0, st>>>(SYN_ARGS)
     if constexpr (MODE == kSynForward) {
         if (state_in) {
-            // the state-input variants stream the tables, at the plan's shape (the task list
-            // follows the shape; every regenerating shape is also built streaming)
+            // the state-input variants, at the plan's shape (the task list follows the shape)
             const int jt = plan.syn_tiles, d = plan.syn_depth;
+            if (plan.syn_recur) {
+                if (jt == 4 && d == 1) SYN_SIN_REC(4, 1);
+                else if (jt == 4) SYN_SIN_REC(4, 2);
+                else if (jt == 2 && d == 2) SYN_SIN_REC(2, 2);
+                else if (jt == 2) SYN_SIN_REC(2, 4);
+                else if (d == 4) SYN_SIN_REC(1, 4);
+                else SYN_SIN_REC(1, 8);
+                return;
+            }
             if (jt == 6) SYN_SIN(6, 1);
             else if (jt == 4 && d == 1) SYN_SIN(4, 1);
             else if (jt == 4) SYN_SIN(4, 2);
@@ -416,6 +425,7 @@ static void launch_synthesis_variant(const LegPlan& plan, dim3 grid, hipStream_t
 #undef SYN
 #undef SYN_REC
 #undef SYN_SIN
+#undef SYN_SIN_REC
 #undef SYN_ARGS
 }
 

@@ -46,45 +46,6 @@ void launch_update(const UpdateArgs& a, hipStream_t st) {
     }
 }
 
-// Synthesis layout of states [s][3][ncoef]: one thread per (coefficient, state).
-__global__ __launch_bounds__(kBlock) void k_prep_cml(const double* __restrict__ state, int nstates,
-                                                     double* __restrict__ cml, int cml32,
-                                                     const int* __restrict__ n_of,
-                                                     const int* __restrict__ m_of,
-                                                     const int* __restrict__ rowoff,
-                                                     const double* __restrict__ inv_lap, int ncoef,
-                                                     int T) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
-    if (idx >= ncoef) return;
-    const int n = n_of[idx], mo = m_of[idx], par = (n - mo) & 1, kk = (n - mo) >> 1;
-    const size_t fs = (size_t)ncoef * 2;
-    const double* u = state + (size_t)s * 3 * fs + (size_t)idx * 2;
-    const double2 phi = ld2(u), zeta = ld2(u + fs), dv = ld2(u + 2 * fs);
-    const double il = inv_lap[n];
-    const size_t ci = (((size_t)rowoff[2 * mo + par] + kk) * nstates + s) * kCmlVals;
-    if (cml32) {
-        float4* c = reinterpret_cast<float4*>(reinterpret_cast<float*>(cml) + ci);
-        c[0] = make_float4((float)zeta.x, (float)zeta.y, (float)phi.x, (float)phi.y);
-        c[1] = make_float4((float)(il * zeta.x), (float)(il * zeta.y), (float)(il * dv.x), (float)(il * dv.y));
-    } else {
-        double* c = cml + ci;
-        st2(c, zeta);
-        st2(c + 2, phi);
-        st2(c + 4, make_double2(il * zeta.x, il * zeta.y));
-        st2(c + 6, make_double2(il * dv.x, il * dv.y));
-    }
-    cml_clear_pad(cml, cml32, rowoff[2 * mo + par], kk, npk_of(T, mo, par), nstates, s);
-}
-
-void launch_prep_cml(const double* state, int nstates, double* cml, bool cml32, const int* n_of,
-                     const int* m_of, const int* rowoff, const double* inv_lap, int ncoef, int T,
-                     hipStream_t st) {
-    dim3 grid((ncoef + kBlock - 1) / kBlock, nstates);
-    k_prep_cml<<<grid, kBlock, 0, st>>>(state, nstates, cml, cml32 ? 1 : 0, n_of, m_of, rowoff, inv_lap,
-                                        ncoef, T);
-}
-
 __global__ __launch_bounds__(kBlock) void k_implicit(const double* __restrict__ u, double* __restrict__ fI,
                                                      const int* __restrict__ n_of, double phibar,
                                                      double inv_a2, int ncoef) {

@@ -19,5 +19,6 @@ def grid_one_ulp(nlat, seed):
     return mu2, quadrature.gauss_weights(nlat, mu2)
 
 
-def oracle_one_ulp(T, nlat, nlon, seed=1):
-    return Oracle(T, nlat, nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, grid_one_ulp(nlat, seed))
+def oracle_one_ulp(T, nlat, nlon, seed=1, coriolis_implicit=False):
+    return Oracle(T, nlat, nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, grid_one_ulp(nlat, seed),
+                  coriolis_implicit=coriolis_implicit)

@@ -30,8 +30,7 @@ def test_algorithmic_work_counts():
     e_bytes = 16.0 * ncoef * (3 * states + 3 * M * K)
     assert wf["analysis"][1] + wf["update"][1] == pytest.approx(w["analysis"][1] + w["update"][1] - e_bytes)
     assert wf["update"][1] == 0.0                                 # no update-class launch left
-    assert bench.algorithmic_work(T, nlat, M, K, 1, "fp64", True, True)["update"][1] == \
-        pytest.approx(7 * 16.0 * ncoef)                           # u_n conversion (regenerating)
+    assert bench.algorithmic_work(T, nlat, M, K, 1, "fp64", True, True)["update"][1] == 0.0
     assert wf["synthesis"] == w["synthesis"] and wf["grid"] == w["grid"]
     # the dominant kernel of the headline step by hand, per launch (4 launches, 13/4 states each):
     # both tables once, 5 Fourier fields per state, the node update's state I/O
@@ -45,6 +44,16 @@ def test_algorithmic_work_counts():
     assert wr["synthesis"][0] == w["synthesis"][0]
     assert w["synthesis"][1] - wr["synthesis"][1] > 0.9 * tables
     assert wr["analysis"] == w["analysis"]
+    # restarting analysis: a quarter of the table bytes per launch
+    wa = bench.algorithmic_work(T, nlat, M, K, 1, "fp64", ana_recur=True)
+    assert w["analysis"][1] - wa["analysis"][1] == pytest.approx(0.75 * tables)
+    # the first launch's own plan: only its launch changes
+    w1 = bench.algorithmic_work(T, nlat, M, K, 1, "fp64", syn_recur1=True, ana_recur1=True)
+    per = tables / K
+    nhp = (nlat // 2 + 15) // 16 * 16
+    rec = 32.0 * (T + 1) * (T + 16) + 8.0 * (T + 1) * nhp
+    assert w["synthesis"][1] - w1["synthesis"][1] == pytest.approx(per - rec)
+    assert w["analysis"][1] - w1["analysis"][1] == pytest.approx(0.75 * per)
 
 
 def test_roofline_entry_picks_the_smaller_ceiling():
@@ -108,36 +117,40 @@ def test_summarize_pmc_scales_by_the_copy_and_uses_the_tuned_variant(tmp_path):
     assert t["legendre_plan"] == plan
 
 
-def test_summarize_pmc_regenerating_plan_counts_the_conversion_as_update(tmp_path):
-    plan = {"syn_lat_tiles": 4, "syn_depth": 2, "ana_depth": 2, "ana_interleave": 1, "fuse_update": 1,
-            "syn_recur": 1, "ana_recur": 1}
+def test_summarize_pmc_counts_both_launch_shapes(tmp_path):
+    """Streamed tables for the node launches, regenerating variants for the first f_E (one state
+    per member): both kernels of each class are averaged, autotuner trials of other variants and
+    adjoint kernels are not."""
+    plan = {"syn_lat_tiles": 2, "syn_depth": 2, "ana_depth": 2, "ana_interleave": 1, "fuse_update": 1,
+            "syn_recur": 0, "ana_recur": 0}
+    plan1 = dict(plan, syn_lat_tiles=4, syn_recur=1, ana_recur=1)
     logs = []
     for name in ("f.log", "w.log"):
         p = tmp_path / name
-        p.write_text(json.dumps({"metric": "m", "legendre_plan": plan}) + "\n")
+        p.write_text(json.dumps({"metric": "m", "legendre_plan": plan,
+                                 "legendre_plan_one_state": plan1}) + "\n")
         logs.append(str(p))
     _csv(tmp_path / "f.csv", "FETCH_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", 256 * 1024.0),
-        ("void k_synthesis<0, double, 4, 2, true, false>(double const*)", 1000.0),
-        ("void k_synthesis<0, double, 4, 2, false, false>(double const*)", 55555.0),  # streaming trial
-        ("void k_analysis_swe<0, double, 2, true>(double const*)", 400.0),
-        ("void k_analysis_swe<0, double, 2, false>(double const*)", 66666.0),     # streaming trial
-        ("k_prep_cml(double const*, int, double*, bool)", 30.0),
-        ("k_prep_cml_adj(double const*, int, double*, bool)", 44444.0)])          # adjoint: not counted
+        ("void k_synthesis<0, double, 2, 2, false, false>(double const*)", 1000.0),
+        ("void k_synthesis<0, double, 4, 2, true, true>(double const*)", 200.0),     # first launch
+        ("void k_synthesis<0, double, 4, 2, true, false>(double const*)", 55555.0),  # trial
+        ("void k_analysis_swe<0, double, 2, false>(double const*)", 400.0),
+        ("void k_analysis_swe<0, double, 2, true>(double const*)", 100.0),           # first launch
+        ("void k_analysis_swe<0, double, 4, true>(double const*)", 66666.0),         # trial
+        ("k_prep_cml_adj(double const*, int, double*, bool)", 44444.0)])             # adjoint
     _csv(tmp_path / "w.csv", "WRITE_SIZE", [
         ("__amd_rocclr_copyBuffer(...)", 256 * 1024.0),
-        ("void k_synthesis<0, double, 4, 2, true, false>(double const*)", 10.0),
-        ("void k_analysis_swe<0, double, 2, true>(double const*)", 20.0),
-        ("k_prep_cml(double const*, int, double*, bool)", 40.0)])
+        ("void k_synthesis<0, double, 2, 2, false, false>(double const*)", 10.0),
+        ("void k_analysis_swe<0, double, 2, false>(double const*)", 20.0)])
     out = tmp_path / "t.json"
     bench.summarize_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 256, str(out), logs)
     t = json.loads(out.read_text())
-    assert t["kernels"]["synthesis"]["fetch_bytes_per_launch"] == pytest.approx(1000.0 * 1024)
-    assert t["kernels"]["analysis"]["fetch_bytes_per_launch"] == pytest.approx(400.0 * 1024)
-    upd = t["kernels"]["update"]
-    assert upd["dispatches"] == 1 and upd["kernel_name"] == "k_prep_cml"
-    assert upd["fetch_bytes_per_launch"] == pytest.approx(30.0 * 1024)
-    assert upd["write_bytes_per_launch"] == pytest.approx(40.0 * 1024)
+    assert t["kernels"]["synthesis"]["dispatches"] == 2
+    assert t["kernels"]["synthesis"]["fetch_bytes_per_launch"] == pytest.approx(600.0 * 1024)
+    assert t["kernels"]["analysis"]["fetch_bytes_per_launch"] == pytest.approx(250.0 * 1024)
+    assert "update" not in t["kernels"]
+    assert t["legendre_plan_one_state"] == plan1
 
 
 def test_summarize_pmc_rejects_runs_with_different_variants(tmp_path):
@@ -168,6 +181,8 @@ def test_traffic_is_reported_only_for_the_profiled_sources_and_plan(tmp_path, mo
     assert bench.traffic_for("analysis", other) == 3.0             # the analysis is unchanged
     assert bench.traffic_for("grid", other) == 3.0                 # grid does not depend on it
     assert bench.traffic_for("analysis", dict(plan, ana_depth=4)) is None
+    assert bench.traffic_for("analysis", plan, plan) == 3.0          # no separate one-state plan
+    assert bench.traffic_for("analysis", plan, dict(plan, ana_recur=1)) is None
     t["source_sha"] = "0" * 16
     f.write_text(json.dumps(t))
     assert bench.traffic_for("grid", plan) is None                 # other kernel sources

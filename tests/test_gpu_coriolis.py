@@ -1,0 +1,166 @@
+"""GPU parity of the split with the linear Coriolis term on the implicit side (f_I = L_g + L_c,
+f_E = N_a + N_r; the change of implicit terms the paper's outlook names) against the oracle's
+SWECoriolisImplicit, through the C ABI.
+
+Bars (relative L2 per field, the sphere norm, as for the paper's split), from the oracle's own
+conditioning where that is worse than the plain targets: f_I (closed-form couplings on the GPU,
+the transform route in the oracle) <= max(1e-13, 3 x the oracle's spread) and f_E <=
+max(1e-12, 3 x the oracle's spread), the spread being how far the oracle moves between its two
+routes of L_c (transform round trip, per-order matrices) and when its Gauss nodes move by one ulp
+(weights recomputed).  Without the Coriolis term the divergence tendency N is a near-cancellation
+of the curl of the relative-vorticity flux and the kinetic-energy Laplacian (one-ulp spread
+1e-12 at T31, 4.6e-12 at T63), and the transform route of L_c rounds relative to the Coriolis
+terms of the rotational wind, which largely cancel in the vorticity tendency (routes' spread 3e-13
+at T63, while the closed form agrees with a long-double evaluation to 1e-16).  The chain solve
+<= 1e-13 (max norm) against the oracle's dense per-order solve;
+whole steps <= 1e-11 relative L2 per field, as for the paper's split; the FP32 mode (FP32
+Legendre contractions only) 2 (T+1) u_32 per f_E on the state change.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.sdc import Oracle
+from paper_2403_20135_amd import _lib
+
+from conditioning import oracle_one_ulp
+from test_gpu_parity import _dev, _host, _states, _torch, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _pair(T, nlat, nlon, M=3, K=3, batch=1, precision="fp64", qdelta="flex"):
+    from paper_2403_20135_amd.api import SDC
+    _torch()
+    print(f"\n[gpu] implicit Coriolis SDC(T={T}, {nlat}x{nlon}, M={M}, K={K}, batch={batch}, {precision})",
+          flush=True)
+    sdc = SDC(T, nlat, nlon, M, K, batch, precision, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH,
+              qdelta=qdelta, implicit_coriolis=True)
+    o = Oracle(T, nlat, nlon, W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH, qdelta=qdelta,
+               coriolis_implicit=True)
+    return sdc, o
+
+
+def _relmax(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("T,nlat,nlon", [(31, 48, 96), (21, 34, 64), (63, 96, 192)])
+def test_implicit_explicit_and_solve_match_oracle(T, nlat, nlon):
+    batch = 2
+    sdc, o = _pair(T, nlat, nlon, batch=batch)
+    # random n^-3 fields without the jet: the oracle's transform route rounds relative to its
+    # largest operands, and a strong zonal jet (whose own Coriolis term vanishes in the vorticity
+    # tendency) would set the scale of the reference's rounding, not of the result
+    x = _states(T, batch, 901, jet=False)
+    fi, fe = _dev(np.zeros_like(x)), _dev(np.zeros_like(x))
+    sdc.eval_implicit(_dev(x), fi)
+    sdc.eval_explicit(_dev(x), fe)
+    fi_h, fe_h = _host(fi), _host(fe)
+    ri = np.stack([o.f_implicit(x[b]) for b in range(batch)])
+    re_ = np.stack([o.f_explicit(x[b]) for b in range(batch)])
+    # the oracle's second route: the per-order matrices of L_g + L_c
+    sp = o.sphere
+    rb = np.zeros_like(ri)
+    for m, A in enumerate(o.swe.blocks()):
+        L = T + 1 - m
+        sl = slice(sp.off[m], sp.off[m + 1])
+        for b in range(batch):
+            u = x[b, :, sl, 0] + 1j * x[b, :, sl, 1]
+            y = (A.numpy() @ u.reshape(3 * L)).reshape(3, L)
+            rb[b, :, sl, 0], rb[b, :, sl, 1] = y.real, y.imag
+    o1 = oracle_one_ulp(T, nlat, nlon, coriolis_implicit=True)
+    ri1 = np.stack([o1.f_implicit(x[b]) for b in range(batch)])
+    re1 = np.stack([o1.f_explicit(x[b]) for b in range(batch)])
+    for f in range(3):
+        ei, ee = rel_l2(fi_h[:, f], ri[:, f], T), rel_l2(fe_h[:, f], re_[:, f], T)
+        si = max(rel_l2(rb[:, f], ri[:, f], T), rel_l2(ri1[:, f], ri[:, f], T))
+        se = rel_l2(re1[:, f], re_[:, f], T)
+        print(f"[gpu] T{T} field {f}: f_I rel L2 {ei:.3e} (oracle spread {si:.2e}), "
+              f"f_E rel L2 {ee:.3e} (oracle spread {se:.2e})", flush=True)
+        assert ei <= max(1e-13, 3 * si)
+        assert ee <= max(1e-12, 3 * se)
+    for alpha in (60.0, 450.0):
+        u = _dev(x)
+        sdc.imex_solve(alpha, u, u)                      # u aliases beta
+        uh = _host(u)
+        ref = np.stack([o.solve(alpha, x[b]) for b in range(batch)])
+        err = max(_relmax(uh[b, f], ref[b, f]) for b in range(batch) for f in range(3))
+        print(f"[gpu] T{T} chain solve alpha={alpha}: rel max {err:.3e}", flush=True)
+        assert err <= 1e-13
+    sdc.close()
+
+
+@pytest.mark.parametrize("T,nlat,nlon,M,K,dt,steps,batch", [
+    (31, 48, 96, 3, 2, 600.0, 5, 1),
+    (63, 96, 192, 4, 4, 480.0, 2, 2),
+    (21, 34, 64, 2, 4, 900.0, 3, 1),       # ragged latitude tile, K > M
+    (31, 48, 96, 1, 1, 300.0, 3, 1),       # IMEX Euler with L_c implicit
+    (127, 192, 384, 3, 3, 240.0, 2, 1),    # the T127 jet workload's shape
+    (255, 384, 768, 4, 4, 120.0, 1, 1),    # the headline shape
+])
+def test_step_matches_oracle(T, nlat, nlon, M, K, dt, steps, batch):
+    sdc, o = _pair(T, nlat, nlon, M, K, batch)
+    x0 = _states(T, batch, 911)
+    x = _dev(x0)
+    for _ in range(steps):
+        sdc.step(x, dt)
+    sdc.sync()
+    got = _host(x)
+    ref = np.stack([o.step(x0[b], dt, M, K, steps=steps) for b in range(batch)])
+    err = max(rel_l2(got[:, f], ref[:, f], T) for f in range(3))
+    print(f"[gpu] implicit Coriolis T{T} M={M} K={K} x{batch}, {steps} steps: rel L2 {err:.3e}", flush=True)
+    assert err <= 1e-11
+    sdc.close()
+
+
+def test_step_fp32_graph_and_jet():
+    T, nlat, nlon, M, K, dt = 31, 48, 96, 3, 3, 600.0
+    sdc, o = _pair(T, nlat, nlon, M, K, 1)
+    s32, _ = _pair(T, nlat, nlon, M, K, 1, precision="fp32")
+    x0 = _states(T, 1, 921)
+    xe, xg, x32 = _dev(x0), _dev(x0), _dev(x0)
+    for _ in range(3):
+        sdc.step(xe, dt)
+        sdc.step_graph(xg, dt)
+        s32.step(x32, dt)
+    sdc.sync()
+    s32.sync()
+    assert np.array_equal(_host(xe), _host(xg))
+    ref = o.step(x0[0], dt, M, K, steps=3)[None]
+    err_d = rel_l2(_host(x32) - x0, ref - x0, T)
+    bar = 2 * (T + 1) * U32 * 3
+    print(f"[gpu] implicit Coriolis FP32 3 steps: state change rel L2 {err_d:.3e} (bar {bar:.2e})", flush=True)
+    assert err_d <= bar
+    # the balanced jet stays a fixed point
+    jet = W.balanced_jet(T, 20.0)[None]
+    xj = _dev(jet)
+    sdc.step(xj, dt)
+    sdc.sync()
+    jh = _host(xj)
+    for f in range(3):
+        scale = np.max(np.abs(jet[0, W.FIELD_ZETA if f == W.FIELD_DIV else f]))
+        assert np.max(np.abs(jh[0, f] - jet[0, f])) <= 1e-13 * scale, f
+    sdc.close()
+    s32.close()
+
+
+def test_unsupported_paths_and_argument_errors():
+    T, nlat, nlon = 21, 34, 64
+    sdc, _ = _pair(T, nlat, nlon, 2, 2, 1)
+    x = _dev(_states(T, 1, 931))
+    y = _dev(np.zeros_like(_host(x)))
+    for call in (lambda: sdc.imex2_step(x, 600.0), lambda: sdc.imex2_step_noalloc(x, 600.0),
+                 lambda: sdc.step_sequential(x, 600.0), lambda: sdc.step_adjoint(x, x, y, 600.0)):
+        with pytest.raises(_lib.SDCError) as e:
+            call()
+        assert e.value.code == _lib.SDC_EUNSUPPORTED
+    with pytest.raises(_lib.SDCError) as e:
+        sdc.eval_implicit(x, x)
+    assert e.value.code == _lib.SDC_EINVAL
+    with pytest.raises(_lib.SDCError) as e:
+        sdc.set_plan(2, 2, 2, 1, 1, 0, 0, 1)
+    assert e.value.code == _lib.SDC_EUNSUPPORTED
+    sdc.close()

@@ -55,6 +55,42 @@ def test_variants_agree_bitwise(T, nlat, nlon, batch, prec):
             assert np.array_equal(a, b), (v, name)
 
 
+SPLIT = [((2, 2, 2, 1), (4, 2, 2, 1, 1, 1, 1)), ((2, 2, 2, 1), (1, 8, 4, 0, 1, 1, 0)),
+         ((4, 2, 2, 1, 1, 1, 1), (2, 2, 4, 1)), ((6, 1, 4, 0), (2, 4, 2, 1, 1, 1, 1))]
+
+
+@pytest.mark.parametrize("T,nlat,nlon,batch,prec", [(63, 96, 192, 2, "fp64"), (31, 48, 96, 3, "fp32")])
+def test_split_plans_agree_bitwise(T, nlat, nlon, batch, prec):
+    """Different variants for the launches over one state per member (the first f_E, eval_explicit,
+    the adjoint's first stage; the first synthesis reading the states in place, also when it
+    regenerates its tables) and over the node states: the same f_E, step, graph step and adjoint
+    bit for bit."""
+    sdc = _sdc(T, nlat, nlon, 3, 3, batch, precision=prec)
+    x = _states(T, batch, 321)
+    lam = np.stack([W.random_state(T, 322 + b) for b in range(batch)])
+    lam[..., :T + 1, 1] = 0.0
+    dt = 600.0
+    ref = _outputs(sdc, x, lam, dt)
+    for main, one in SPLIT:
+        sdc.set_plan(*main)
+        sdc.set_plan_for(1, *one)
+        assert sdc.plan_for(3) == sdc.plan()
+        p1 = sdc.plan_for(1)
+        assert (p1["syn_lat_tiles"], p1["syn_depth"], p1["ana_depth"], p1["ana_interleave"]) == one[:4]
+        got = _outputs(sdc, x, lam, dt)
+        xg = _dev(x)
+        sdc.step_graph(xg, dt)
+        sdc.sync()
+        for name, a, b in zip(("f_E", "step", "adjoint", "graph step"), got + (_host(xg),), ref + (ref[1],)):
+            print(f"[gpu] T{T} {prec} split {main} / {one} {name}: max |diff| {np.max(np.abs(a - b)):.3e}",
+                  flush=True)
+            assert np.array_equal(a, b), (main, one, name)
+    with pytest.raises(_lib.SDCError) as ei:
+        sdc.set_plan_for(2, *DEFAULT.values())
+    assert ei.value.code == _lib.SDC_EINVAL
+    sdc.close()
+
+
 def test_set_plan_rejects_variants_not_built():
     sdc = _sdc(21, 34, 64, 2, 2, 1)
     for bad in [(2, 8, 4, 1), (4, 4, 4, 1), (3, 4, 4, 1), (5, 2, 4, 1), (6, 2, 4, 1), (1, 6, 4, 1),
@@ -74,8 +110,12 @@ def test_autotune_keeps_results_and_graphs():
     x = _dev(x0)
     sdc.step_graph(x, dt)                 # a cached graph from before tuning
     chosen = sdc.autotune(5)
-    print(f"[gpu] autotune T{T} x4: {chosen}", flush=True)
+    one = sdc.plan_for(1)
+    print(f"[gpu] autotune T{T} x4: {chosen}; one state per member: {one}", flush=True)
     assert chosen == sdc.plan()
+    assert (one["syn_lat_tiles"], one["syn_depth"]) in [(1, 8), (1, 4), (2, 4), (2, 2), (3, 2),
+                                                        (4, 2), (4, 1), (6, 1)]
+    assert one["fuse_update"] == chosen["fuse_update"] and one["node_launch"] == 0
     assert (chosen["syn_lat_tiles"], chosen["syn_depth"]) in [(1, 8), (1, 4), (2, 4), (2, 2), (3, 2),
                                                                 (4, 2), (4, 1), (6, 1)]
     assert chosen["syn_recur"] in (0, 1) and chosen["ana_recur"] in (0, 1) and chosen["fuse_update"] == 1

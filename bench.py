@@ -294,25 +294,30 @@ def measure_mixed(steps=20, warmup=3):
                                dtype=torch.float64, device="cuda"))
         dts.append(mb.dt)
     grp = SDCGroup(handles)
-    for _ in range(warmup):
-        grp.step(xs, dts, wl.M, wl.K)
-    grp.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        grp.step(xs, dts, wl.M, wl.K)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    grp.sync()
+    res = {}
+    for mode in (1, 0):
+        grp.set_mode(mode)
+        for _ in range(warmup):
+            grp.step(xs, dts, wl.M, wl.K)
+        grp.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            grp.step(xs, dts, wl.M, wl.K)
+        torch.cuda.synchronize()
+        res[mode] = time.perf_counter() - t0
+        grp.sync()
     if not all(bool(torch.isfinite(x).all()) for x in xs):
         raise RuntimeError("non-finite ensemble state")
     grp.close()
     for h in handles:
         h.close()
+    el = res[1]
     return {"workload": wl.name, "members": len(wl.members), "steps": steps,
             "steps_per_s": round(steps / el, 3), "member_steps_per_s": round(len(wl.members) * steps / el, 1),
             "ms_per_step": round(el / steps * 1e3, 4), "precision": "fp64",
-            "launch": "one hipGraph per step (members as parallel branches)"}
+            "launch": "one hipGraph per step; every phase one launch over all 32 members (mode 1)",
+            "member_steps_per_s_graph_branches": round(len(wl.members) * steps / res[0], 1)}
 
 
 def speedup_at_equal_error(rows):

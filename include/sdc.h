@@ -317,14 +317,28 @@ int sdc_copy_legendre(sdc_handle h, int m, double* Pbar, double* H);
 
 /* Ensembles of different truncations (one handle per truncation, each with its own members):
  * sdc_group_step advances every member of every handle by one dSDC step (Algorithm 2) as ONE graph
- * launch on the group's stream; the handles' steps are parallel branches of the graph.  states[i]
- * and dts[i] belong to members[i]; M and K are common (<= every handle's configured M, K).  The
- * graph is captured on the first call and whenever states, dts, M or K change.  The member handles
- * must outlive the group and must not be used on other streams while a group step is in flight.
- * sdc_group_sync waits for the group's stream and returns the first deferred error of a member. */
+ * launch on the group's stream.  states[i] and dts[i] belong to members[i]; M and K are common
+ * (<= every handle's configured M, K).  The graph is captured on the first call and whenever
+ * states, dts, M or K change.  The member handles must outlive the group and must not be used on
+ * other streams while a group step is in flight.  sdc_group_sync waits for the group's stream and
+ * returns the first deferred error of a member.  sdc_group_create reserves a small device buffer
+ * for the merged launches' arguments (released by sdc_group_free).
+ * Modes (sdc_group_set_mode / sdc_group_get_mode):
+ *   1: every phase of the step (each sweep's synthesis, grid step, analysis with its fused node
+ *      update, or separate update) is ONE kernel launch over all members of all truncations --
+ *      the batched loop over nodes of Algorithm 2 (Section 4.2) extended over the ensemble: each
+ *      handle's workgroups form one range of the launch, with the Legendre variants of the handle
+ *      with the most work (every variant gives the same results).  Needs members of one precision,
+ *      the paper's split, one node per launch off, the same kind of node update (fused or not)
+ *      and nlon in {96, 192, 384, 768}; sdc_group_step returns SDC_EUNSUPPORTED otherwise.
+ *   0: each handle's own launches as a parallel branch of the graph.
+ * A new group starts in mode 1 when its members allow it, else in mode 0.  Both modes give
+ * bitwise the same states. */
 typedef struct sdc_group_s* sdc_group;
 int sdc_group_create(const sdc_handle* members, int n, void* hip_stream, sdc_group* out);
 int sdc_group_step(sdc_group g, double* const* states, const double* dts, int M, int K);
+int sdc_group_set_mode(sdc_group g, int mode);
+int sdc_group_get_mode(sdc_group g, int* mode);
 int sdc_group_sync(sdc_group g);
 int sdc_group_free(sdc_group g);
 

@@ -62,6 +62,8 @@ _SIGS = {
     "sdc_group_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     "sdc_group_step": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_double), c_int, c_int]),
     "sdc_group_sync": (c_int, [c_void_p]),
+    "sdc_group_set_mode": (c_int, [c_void_p, c_int]),
+    "sdc_group_get_mode": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
     "sdc_group_free": (c_int, [c_void_p]),
     "sht_forward": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sht_inverse": (c_int, [c_void_p, c_void_p, c_void_p]),

@@ -289,6 +289,16 @@ class SDCGroup:
         check(self.lib.sdc_group_create(arr, len(self.members), ctypes.c_void_p(stream), ctypes.byref(g)))
         self.g = g
 
+    @property
+    def mode(self) -> int:
+        """1: one launch per kernel class and phase over all members; 0: one graph branch each."""
+        v = ctypes.c_int()
+        check(self.lib.sdc_group_get_mode(self.g, ctypes.byref(v)))
+        return v.value
+
+    def set_mode(self, mode: int):
+        check(self.lib.sdc_group_set_mode(self.g, int(mode)))
+
     def step(self, states, dts, M: int, K: int):
         if len(states) != len(self.members) or len(dts) != len(self.members):
             raise ValueError("one state tensor and one dt per member handle")

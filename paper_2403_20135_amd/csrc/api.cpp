@@ -174,7 +174,21 @@ std::vector<Task> xcd_order(const std::vector<Task>& tasks, const std::vector<in
 
 }  // namespace
 
+// One launch group of a step as enqueue_step issues it, recorded instead of launched when a
+// group merges its members' launches: an f_E evaluation (synthesis, grid, analysis with an
+// optional fused node update) or a separate node-update launch.
+struct StepOp {
+    int kind;                         // 0: f_E of S states, 1: node update
+    int S;
+    const double* states;             // f_E: the states read in place (or nullptr: synthesis layout)
+    double* out;
+    double2* save;
+    UpdateArgs upd;                   // f_E: the fused update (fuse_mode > 0); kind 1: the update
+    int fuse_mode;
+};
+
 struct sdc_ctx {
+    std::vector<StepOp>* rec = nullptr;   // when set, f_E and update launches are recorded here
     sdc_config cfg{};
     hipStream_t st = nullptr;
     Geom g{};
@@ -506,6 +520,10 @@ int setup(sdc_ctx* c) {
 // with states != null, read by the synthesis from the state layout.
 void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr,
                       const UpdateArgs* fuse = nullptr, int fuse_mode = 0, const double* states = nullptr) {
+    if (c->rec) {
+        c->rec->push_back(StepOp{0, S, states, out, save, fuse ? *fuse : UpdateArgs{}, fuse ? fuse_mode : 0});
+        return;
+    }
     const LegPlan& lp = c->plan_for(S);
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
     launch_synthesis_swe(c->tables(), lp, c->toff, c->rowoff, c->syn_list(lp), c->syn_count(lp),
@@ -574,6 +592,10 @@ int alloc_adjoint(sdc_ctx* c, bool with_save) {
 size_t tape_per_state(const sdc_ctx* c) { return (size_t)kSynFields * c->g.nh * c->g.nlon; }
 
 void run_update(sdc_ctx* c, const UpdateArgs& a) {
+    if (c->rec) {
+        c->rec->push_back(StepOp{1, 0, nullptr, nullptr, nullptr, a, 0});
+        return;
+    }
     const long t = c->begin(SDC_KERNEL_UPDATE);
     launch_update(a, c->st);
     c->end(SDC_KERNEL_UPDATE, t);
@@ -1625,6 +1647,9 @@ int sdc_copy_legendre(sdc_handle h, int m, double* Pbar, double* H) {
 // ---------------------------------------------------------------------------------------------
 struct sdc_group_s {
     std::vector<sdc_handle> members;
+    int mode = 0;                     // 1: one launch per kernel class and phase over all members
+    void* desc = nullptr;             // device copies of the merged launches' per-member arguments
+    size_t desc_bytes = 0;
     hipStream_t st = nullptr;
     hipStream_t cap = nullptr;
     std::vector<hipStream_t> branch;
@@ -1636,6 +1661,7 @@ struct sdc_group_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~sdc_group_s() {
+        if (desc) (void)hipFree(desc);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (hipEvent_t e : join) (void)hipEventDestroy(e);
@@ -1644,6 +1670,194 @@ struct sdc_group_s {
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
+
+}  // extern "C"
+
+namespace {
+
+// Whether the members can share one launch per kernel class and phase: the same precision, the
+// same kind of node update (fused or separate), the paper's split, one launch per sweep, and FFT
+// lengths the multi-handle grid kernel is built for.  msg receives the reason otherwise.
+bool group_mergeable(const sdc_group_s* g, int M, std::string* msg) {
+    const sdc_ctx* c0 = g->members[0];
+    const bool fused0 = c0->lplan.fuse_update && (M == 1 || M == 2 || M == 4);
+    for (const sdc_ctx* c : g->members) {
+        if (c->cfg.precision != c0->cfg.precision) { *msg = "members of different precision"; return false; }
+        if (c->cfg.implicit_coriolis) { *msg = "a member with implicit_coriolis"; return false; }
+        if (c->lplan.node_launch) { *msg = "a member with node_launch"; return false; }
+        if ((c->lplan.fuse_update && (M == 1 || M == 2 || M == 4)) != fused0) {
+            *msg = "members with and without the fused node update";
+            return false;
+        }
+        if (!grid_multi_supported(c->cfg.nlon)) {
+            *msg = "a member's nlon is not one of 96, 192, 384, 768";
+            return false;
+        }
+    }
+    return true;
+}
+
+// Bytes of device descriptors one merged step needs at most (K f_E and K + 1 update launches).
+size_t group_desc_bytes(const sdc_group_s* g) {
+    int kmax = kMaxSweeps;
+    for (const sdc_ctx* c : g->members) kmax = std::min(kmax, c->cfg.K);
+    const size_t per_op = sizeof(SynArgs) + sizeof(GridArgs) + sizeof(AnaArgs) + sizeof(UpdArgsM);
+    return (size_t)(2 * kmax + 2) * (g->members.size() * per_op + 4 * 16) + 256;   // + 16-byte alignment
+}
+
+// Records every member's step, builds one descriptor list per launch (workgroup ranges of the
+// members back to back, each starting at a multiple of 8), copies them to the device and captures
+// one launch per kernel class and phase on g->cap.
+int group_capture_merged(sdc_group_s* g, double* const* states, const double* dts, int M, int K,
+                         hipGraph_t* graph) {
+    const size_t n = g->members.size();
+    std::vector<std::vector<StepOp>> ops(n);
+    for (size_t h = 0; h < n; ++h) {
+        sdc_ctx* c = g->members[h];
+        c->rec = &ops[h];
+        enqueue_step(c, states[h], dts[h], M, K);
+        c->rec = nullptr;
+    }
+    for (size_t h = 1; h < n; ++h) {
+        if (ops[h].size() != ops[0].size()) return fail(SDC_EUNSUPPORTED, "members record different steps");
+        for (size_t i = 0; i < ops[0].size(); ++i)
+            if (ops[h][i].kind != ops[0][i].kind || ops[h][i].fuse_mode != ops[0][i].fuse_mode ||
+                (ops[h][i].states == nullptr) != (ops[0][i].states == nullptr))
+                return fail(SDC_EUNSUPPORTED, "members record different steps");
+    }
+    // the variants of the member with the most work serve every member (all variants give the
+    // same results)
+    size_t lead = 0;
+    for (size_t h = 1; h < n; ++h)
+        if ((double)g->members[h]->g.ncoef * g->members[h]->cfg.batch >
+            (double)g->members[lead]->g.ncoef * g->members[lead]->cfg.batch)
+            lead = h;
+    const sdc_ctx* cl = g->members[lead];
+    const bool fp32 = cl->P32 != nullptr;
+    int nlon_max = 0;
+    for (const sdc_ctx* c : g->members) nlon_max = std::max(nlon_max, c->cfg.nlon);
+    // host image of the descriptors
+    std::vector<char> img;
+    auto put = [&](const void* p, size_t nb) {
+        const size_t off = (img.size() + 15) / 16 * 16;
+        img.resize(off + nb);
+        std::memcpy(img.data() + off, p, nb);
+        return off;
+    };
+    struct Launch {
+        int kind;
+        LegPlan plan;
+        bool state_in;
+        size_t syn, grid, ana, upd;
+        int syn_blocks, grid_blocks, ana_blocks, upd_blocks;
+    };
+    std::vector<Launch> launches;
+    for (size_t i = 0; i < ops[0].size(); ++i) {
+        Launch L{};
+        L.kind = ops[0][i].kind;
+        if (L.kind == 0) {
+            const LegPlan lp = cl->plan_for(ops[lead][i].S);
+            L.plan = lp;
+            L.state_in = ops[0][i].states != nullptr;
+            std::vector<SynArgs> sy(n);
+            std::vector<GridArgs> gr(n);
+            std::vector<AnaArgs> an(n);
+            int fs = 0, fg = 0, fa = 0;
+            for (size_t h = 0; h < n; ++h) {
+                sdc_ctx* c = g->members[h];
+                const StepOp& op = ops[h][i];
+                sy[h] = make_syn_args(c->tables(), c->toff, c->rowoff, c->syn_list(lp), c->syn_count(lp), c->cml,
+                                      op.S, reinterpret_cast<double*>(c->four), c->g, op.states);
+                sy[h].first = fs;
+                fs += (sy[h].blocks + 7) / 8 * 8;
+                gr[h] = make_grid_args(c->four, c->G, c->mu, c->w, c->tw, op.S, c->two_omega_explicit, op.save,
+                                       c->g);
+                gr[h].first = fg;
+                fg += (gr[h].blocks + 7) / 8 * 8;
+                an[h] = make_ana_args(c->tables(), lp, c->toff, c->ana_tasks, c->n_ana_wg, c->G, op.S, c->neg_lap,
+                                      op.out, c->g, op.fuse_mode ? &op.upd : nullptr, op.fuse_mode);
+                an[h].first = fa;
+                fa += (an[h].blocks + 7) / 8 * 8;
+            }
+            L.syn = put(sy.data(), n * sizeof(SynArgs));
+            L.grid = put(gr.data(), n * sizeof(GridArgs));
+            L.ana = put(an.data(), n * sizeof(AnaArgs));
+            L.syn_blocks = fs;
+            L.grid_blocks = fg;
+            L.ana_blocks = fa;
+        } else {
+            std::vector<UpdArgsM> up(n);
+            int fu = 0;
+            for (size_t h = 0; h < n; ++h) {
+                const StepOp& op = ops[h][i];
+                up[h].a = op.upd;
+                up[h].gx = (2 * op.upd.ncoef + 63) / 64;
+                up[h].blocks = up[h].gx * op.upd.batch;
+                up[h].first = fu;
+                fu += (up[h].blocks + 7) / 8 * 8;
+            }
+            L.upd = put(up.data(), n * sizeof(UpdArgsM));
+            L.upd_blocks = fu;
+        }
+        launches.push_back(L);
+    }
+    if (img.size() > g->desc_bytes) return fail(SDC_EINVAL, "merged step needs more descriptor space than reserved");
+    HIP_TRY(hipStreamSynchronize(g->st));            // a replay of the previous graph may read them
+    HIP_TRY(hipMemcpy(g->desc, img.data(), img.size(), hipMemcpyHostToDevice));
+    const char* d = static_cast<const char*>(g->desc);
+    HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+    for (const Launch& L : launches) {
+        if (L.kind == 0) {
+            launch_synthesis_multi(L.plan, fp32, L.state_in, reinterpret_cast<const SynArgs*>(d + L.syn), (int)n,
+                                   L.syn_blocks, g->cap);
+            launch_grid_multi(fp32, nlon_max, reinterpret_cast<const GridArgs*>(d + L.grid), (int)n, L.grid_blocks,
+                              g->cap);
+            launch_analysis_multi(L.plan, fp32, reinterpret_cast<const AnaArgs*>(d + L.ana), (int)n, L.ana_blocks,
+                                  g->cap);
+        } else {
+            launch_update_multi(M, reinterpret_cast<const UpdArgsM*>(d + L.upd), (int)n, L.upd_blocks, g->cap);
+        }
+    }
+    const hipError_t e = hipStreamEndCapture(g->cap, graph);
+    if (e != hipSuccess) return fail(SDC_EHIP, "group step capture failed: %s", hipGetErrorString(e));
+    (void)K;
+    return SDC_OK;
+}
+
+// One graph branch per member, each with the member's own launches.
+int group_capture_branches(sdc_group_s* g, double* const* states, const double* dts, int M, int K,
+                           hipGraph_t* graph) {
+    const size_t n = g->members.size();
+    hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipEventRecord(g->fork, g->cap);
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+        sdc_ctx* c = g->members[i];
+        e = hipStreamWaitEvent(g->branch[i], g->fork, 0);
+        if (e != hipSuccess) break;
+        const hipStream_t saved = c->st;
+        const bool saved_timing = c->timing;
+        c->st = g->branch[i];
+        c->timing = false;
+        enqueue_step(c, states[i], dts[i], M, K);
+        c->st = saved;
+        c->timing = saved_timing;
+        e = hipEventRecord(g->join[i], g->branch[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(g->cap, g->join[i], 0);
+    }
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(g->cap, &gr);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail(SDC_EHIP, "group step capture failed: %s", hipGetErrorString(e));
+    }
+    *graph = gr;
+    return SDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int sdc_group_create(const sdc_handle* members, int n, void* hip_stream, sdc_group* out) {
     if (!out) return fail(SDC_EINVAL, "out is NULL");
@@ -1672,7 +1886,35 @@ int sdc_group_create(const sdc_handle* members, int n, void* hip_stream, sdc_gro
         delete g;
         return fail(SDC_EHIP, "group stream/event creation failed: %s", hipGetErrorString(e));
     }
+    g->desc_bytes = group_desc_bytes(g);
+    if (hipMalloc(&g->desc, g->desc_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        g->desc = nullptr;
+        delete g;
+        return fail(SDC_ENOMEM, "group descriptor allocation failed");
+    }
+    std::string why;
+    g->mode = group_mergeable(g, g->members[0]->cfg.M, &why) ? 1 : 0;
     *out = g;
+    return SDC_OK;
+}
+
+int sdc_group_set_mode(sdc_group g, int mode) {
+    if (!g) return fail(SDC_EINVAL, "group is NULL");
+    if (mode != 0 && mode != 1) return fail(SDC_EINVAL, "mode=%d: 0 or 1", mode);
+    if (mode != g->mode && g->exec) {              // recaptured on the next step
+        (void)hipGraphExecDestroy(g->exec);
+        (void)hipGraphDestroy(g->graph);
+        g->exec = nullptr;
+        g->graph = nullptr;
+    }
+    g->mode = mode;
+    return SDC_OK;
+}
+
+int sdc_group_get_mode(sdc_group g, int* mode) {
+    if (!g || !mode) return fail(SDC_EINVAL, "group/mode is NULL");
+    *mode = g->mode;
     return SDC_OK;
 }
 
@@ -1698,33 +1940,17 @@ int sdc_group_step(sdc_group g, double* const* states, const double* dts, int M,
             g->exec = nullptr;
             g->graph = nullptr;
         }
-        std::vector<hipStream_t> saved(n);
-        std::vector<bool> saved_timing(n);
-        hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) e = hipEventRecord(g->fork, g->cap);
-        for (size_t i = 0; i < n && e == hipSuccess; ++i) {
-            sdc_ctx* c = g->members[i];
-            e = hipStreamWaitEvent(g->branch[i], g->fork, 0);
-            if (e != hipSuccess) break;
-            saved[i] = c->st;
-            saved_timing[i] = c->timing;
-            c->st = g->branch[i];
-            c->timing = false;
-            enqueue_step(c, states[i], dts[i], M, K);
-            c->st = saved[i];
-            c->timing = saved_timing[i];
-            e = hipEventRecord(g->join[i], g->branch[i]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(g->cap, g->join[i], 0);
-        }
         hipGraph_t graph = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(g->cap, &graph);
-        if (e == hipSuccess) e = e2;
-        if (e != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return fail(SDC_EHIP, "group step capture failed: %s", hipGetErrorString(e));
+        if (g->mode == 1) {
+            std::string why;
+            if (!group_mergeable(g, M, &why))
+                return fail(SDC_EUNSUPPORTED, "one launch per phase over the members: %s (use mode 0)", why.c_str());
+            if (int rc = group_capture_merged(g, states, dts, M, K, &graph)) return rc;
+        } else if (int rc = group_capture_branches(g, states, dts, M, K, &graph)) {
+            return rc;
         }
         hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             (void)hipGraphDestroy(graph);
             return fail(SDC_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));

@@ -62,8 +62,7 @@ __host__ __device__ inline size_t tab_index(int np4, int kk, int jh) {
 __host__ inline unsigned xcd_grid(int ntasks, int ngroups) {
     return (unsigned)((ntasks + 7) / 8) * 8u * (unsigned)ngroups;
 }
-__device__ inline int2 xcd_task_group(int ntasks, int ngroups, int interleave) {
-    const int w = blockIdx.x;
+__device__ inline int2 xcd_task_group(int w, int ntasks, int ngroups, int interleave) {
     if (!interleave) {
         const int npad = (ntasks + 7) / 8 * 8;
         return make_int2(w % npad, w / npad);
@@ -347,6 +346,77 @@ void launch_solve_lc(const LcArgs& a, hipStream_t st);
 void launch_implicit_lc(const double* u, double* fI, const int* n_of, const int* m_of, const double2* lc,
                         double phibar, double inv_a2, double two_omega, int T, int batch, int ncoef,
                         hipStream_t st);
+
+// Launches over several handles (members of different truncations) at once, one workgroup range
+// per handle: the arguments of each handle's launch, the first workgroup of its range (a multiple
+// of 8: XCD order kept) and its workgroup count.
+struct SynArgs {
+    const void* P;
+    const void* H;
+    const long long* toff;
+    const int* rowoff;
+    const int2* tasks;
+    const void* cml;             // in the table type
+    int nstates;
+    double* four;
+    Geom g;
+    const double* rc;
+    const double* sect;
+    const double* mu;
+    const double* sin_state;
+    const double* inv_lap;
+    int gx;                      // workgroups per state group (the task list's length)
+    int first, blocks;
+};
+SynArgs make_syn_args(const Tables& tb, const long long* toff, const int* rowoff, const int2* tasks,
+                      int ntasks, const double* cml, int nstates, double* four, const Geom& g,
+                      const double* state_in);
+void launch_synthesis_multi(const LegPlan& plan, bool fp32, bool state_in, const SynArgs* list, int n,
+                            int blocks, hipStream_t st);
+struct AnaArgs {
+    const void* P;
+    const void* H;
+    const long long* toff;
+    const int4* tasks;
+    int ntasks, interleave;
+    const void* G;               // in the table type
+    int nstates;
+    const double* nscale;
+    double* out;
+    Geom g;
+    UpdateArgs fu;
+    int fuse;
+    const double* P64;
+    const double* rc;
+    const double* mu;
+    int first, blocks;
+};
+AnaArgs make_ana_args(const Tables& tb, const LegPlan& plan, const long long* toff, const int4* tasks,
+                      int nwg, const double* G, int nstates, const double* neg_lap, double* out,
+                      const Geom& g, const UpdateArgs* fuse, int fuse_mode);
+void launch_analysis_multi(const LegPlan& plan, bool fp32, const AnaArgs* list, int n, int blocks,
+                           hipStream_t st);
+struct GridArgs {
+    const double2* four;
+    double* G;                   // in the table type
+    const double* mu;
+    const double* w;
+    const double2* tw;
+    double two_omega;
+    int nstates;
+    double2* save;
+    Geom g;
+    int first, blocks;
+};
+GridArgs make_grid_args(const double2* four, double* G, const double* mu, const double* w, const double2* tw,
+                        int nstates, double two_omega, double2* save, const Geom& g);
+bool grid_multi_supported(int nlon);
+void launch_grid_multi(bool g32, int nlon_max, const GridArgs* list, int n, int blocks, hipStream_t st);
+struct UpdArgsM {
+    UpdateArgs a;
+    int gx, first, blocks;
+};
+void launch_update_multi(int M, const UpdArgsM* list, int n, int blocks, hipStream_t st);
 
 // adjoint.hip
 void launch_prep_cml_adj(const double* ebar, int nstates, double* cml, bool cml32, const int* n_of,

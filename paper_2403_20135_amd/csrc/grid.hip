@@ -488,15 +488,15 @@ template <> struct Row<float> {
 // written whole by one thread.
 // ---------------------------------------------------------------------------------------------
 template <int N, typename GT>
-__global__ __launch_bounds__(kGridBlock) void k_grid_swe(
+__device__ __forceinline__ void grid_swe_body(
     const double2* __restrict__ four, GT* __restrict__ G, const double* __restrict__ mu,
     const double* __restrict__ w, const double2* __restrict__ tw, double two_omega,
-    int nstates, double2* __restrict__ save, Geom g) {
+    int nstates, double2* __restrict__ save, const Geom& g, int bx) {
     extern __shared__ double2 buf[];      // kGridSignals signals x N
     constexpr int KP = (N + kGridBlock - 1) / kGridBlock;
     const int ntask = g.nh * nstates;
     const int per = (ntask + 7) / 8;
-    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int t = (bx & 7) * per + (bx >> 3);
     if (t >= ntask) return;                // uniform per workgroup, before any barrier
     const int jh = t / nstates, s = t % nstates;
     const int T = g.T;
@@ -608,6 +608,58 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_swe(
         o.put(kEs, cscale(we, cadd(EN, ES)));
         o.put(kEa, cscale(we, csub(EN, ES)));
     }
+}
+
+template <int N, typename GT>
+__global__ __launch_bounds__(kGridBlock) void k_grid_swe(
+    const double2* __restrict__ four, GT* __restrict__ G, const double* __restrict__ mu,
+    const double* __restrict__ w, const double2* __restrict__ tw, double two_omega,
+    int nstates, double2* __restrict__ save, Geom g) {
+    grid_swe_body<N, GT>(four, G, mu, w, tw, two_omega, nstates, save, g, blockIdx.x);
+}
+
+// One grid launch over several handles (workgroup ranges as k_synthesis_multi); each workgroup
+// runs the FFT length of its handle, one of the lengths 3 * 2^p up to 768 (the dynamic LDS of
+// the launch is the largest handle's).
+template <typename GT>
+__global__ __launch_bounds__(kGridBlock) void k_grid_multi(const GridArgs* __restrict__ list, int n) {
+    const int b = blockIdx.x;
+    int h = 0;
+    while (h + 1 < n && b >= list[h + 1].first) ++h;
+    const GridArgs& a = list[h];
+    const int bx = b - a.first;
+    if (bx >= a.blocks) return;                              // padding to the next range (uniform)
+    GT* G = reinterpret_cast<GT*>(a.G);
+    switch (a.g.nlon) {
+    case 96: grid_swe_body<96, GT>(a.four, G, a.mu, a.w, a.tw, a.two_omega, a.nstates, a.save, a.g, bx); break;
+    case 192: grid_swe_body<192, GT>(a.four, G, a.mu, a.w, a.tw, a.two_omega, a.nstates, a.save, a.g, bx); break;
+    case 384: grid_swe_body<384, GT>(a.four, G, a.mu, a.w, a.tw, a.two_omega, a.nstates, a.save, a.g, bx); break;
+    default: grid_swe_body<768, GT>(a.four, G, a.mu, a.w, a.tw, a.two_omega, a.nstates, a.save, a.g, bx); break;
+    }
+}
+
+bool grid_multi_supported(int nlon) { return nlon == 96 || nlon == 192 || nlon == 384 || nlon == 768; }
+
+GridArgs make_grid_args(const double2* four, double* G, const double* mu, const double* w, const double2* tw,
+                        int nstates, double two_omega, double2* save, const Geom& g) {
+    GridArgs a{};
+    a.four = four;
+    a.G = G;
+    a.mu = mu;
+    a.w = w;
+    a.tw = tw;
+    a.two_omega = two_omega;
+    a.nstates = nstates;
+    a.save = save;
+    a.g = g;
+    a.blocks = (g.nh * nstates + 7) / 8 * 8;
+    return a;
+}
+
+void launch_grid_multi(bool g32, int nlon_max, const GridArgs* list, int n, int blocks, hipStream_t st) {
+    const size_t lds = (size_t)kGridSignals * nlon_max * sizeof(double2);
+    if (g32) k_grid_multi<float><<<blocks, kGridBlock, lds, st>>>(list, n);
+    else k_grid_multi<double><<<blocks, kGridBlock, lds, st>>>(list, n);
 }
 
 void launch_grid_swe(const double2* four, double* G, bool g32, const double* mu, const double* w,

@@ -149,21 +149,23 @@ __device__ __forceinline__ void transpose_rows4(double (&v)[4]) {
 // (v < 2), Phi' (v < 4) or inv_lap[n] times zeta or delta (v >= 4), part v & 1, formed with the
 // same products and roundings as the conversion kernel, so a step's first f_E needs no
 // conversion launch and gives the same results bit for bit.
-template <int MODE, typename TT, int JT, int D, bool REC, bool SIN = false>
-__global__ __launch_bounds__(kSynBlock) void k_synthesis(
+// The body of one workgroup (task bx of the task list, state group by); the kernels below run it
+// for one handle's launch or for one workgroup of a launch over several handles.
+template <int MODE, typename TT, int JT, int D, bool REC, bool SIN>
+__device__ __forceinline__ void synthesis_body(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int* __restrict__ rowoff, const int2* __restrict__ tasks, const TT* __restrict__ cml,
-    int nstates, double* __restrict__ four, Geom g, const double* __restrict__ rc,
+    int nstates, double* __restrict__ four, const Geom& g, const double* __restrict__ rc,
     const double* __restrict__ sect, const double* __restrict__ mu,
-    const double* __restrict__ sin_state, const double* __restrict__ inv_lap) {
+    const double* __restrict__ sin_state, const double* __restrict__ inv_lap, int bx, int by) {
     using TL = SynTiles<MODE>;
     using MM = Mma<TT>;
     constexpr int NT = TL::NT;
     constexpr unsigned tsz = sizeof(TT);
     __shared__ double part[2][NT][4][64];
-    // state groups on blockIdx.y: the groups of one task run far apart in time (sharing a
-    // table tile between co-scheduled groups through L2 measured slower)
-    const int2 task = tasks[blockIdx.x];
+    // state groups on by (the second grid dimension): the groups of one task run far apart in
+    // time (sharing a table tile between co-scheduled groups through L2 measured slower)
+    const int2 task = tasks[bx];
     if (task.x < 0) return;                                  // padding workgroup (uniform)
     const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // parity of this wave
     const int m = task.x, jt0 = task.y, ntj = g.nhp >> 4;
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
         }
     }
     const int S = nstates;
-    const int s = blockIdx.y * 4 + (i >> 2);
+    const int s = by * 4 + (i >> 2);
     const int sc = s < S ? s : S - 1;
     // 32-bit byte offsets from per-block (uniform) base addresses: one VGPR per address
     unsigned boff[NT];
@@ -368,6 +370,34 @@ __global__ __launch_bounds__(kSynBlock) void k_synthesis(
     }
 }
 
+template <int MODE, typename TT, int JT, int D, bool REC, bool SIN = false>
+__global__ __launch_bounds__(kSynBlock) void k_synthesis(
+    const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
+    const int* __restrict__ rowoff, const int2* __restrict__ tasks, const TT* __restrict__ cml,
+    int nstates, double* __restrict__ four, Geom g, const double* __restrict__ rc,
+    const double* __restrict__ sect, const double* __restrict__ mu,
+    const double* __restrict__ sin_state, const double* __restrict__ inv_lap) {
+    synthesis_body<MODE, TT, JT, D, REC, SIN>(P, H, toff, rowoff, tasks, cml, nstates, four, g, rc, sect, mu,
+                                             sin_state, inv_lap, blockIdx.x, blockIdx.y);
+}
+
+// One launch over the synthesis of several handles (members of different truncations): workgroup
+// b belongs to the handle h with first[h] <= b < first[h + 1] (first[h] a multiple of 8, so every
+// handle keeps its XCD-ordered task list) and runs that handle's task (b - first[h]) mod gx.
+template <int MODE, typename TT, int JT, int D, bool REC, bool SIN = false>
+__global__ __launch_bounds__(kSynBlock) void k_synthesis_multi(const SynArgs* __restrict__ list, int n) {
+    const int b = blockIdx.x;
+    int h = 0;
+    while (h + 1 < n && b >= list[h + 1].first) ++h;
+    const SynArgs& a = list[h];
+    const int local = b - a.first;
+    if (local >= a.blocks) return;                           // padding to the next range (uniform)
+    synthesis_body<MODE, TT, JT, D, REC, SIN>(
+        static_cast<const TT*>(a.P), static_cast<const TT*>(a.H), a.toff, a.rowoff, a.tasks,
+        static_cast<const TT*>(a.cml), a.nstates, a.four, a.g, a.rc, a.sect, a.mu, a.sin_state, a.inv_lap,
+        local % a.gx, local / a.gx);
+}
+
 // Synthesis variants (latitude tiles per workgroup, stages in flight): (1, 8), (1, 4), (2, 4),
 // (2, 2), (3, 2), (4, 2), (4, 1), (6, 1) reading the tables; all but (3, 2) and (6, 1) also
 // regenerating them.
@@ -442,6 +472,62 @@ void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long
                                                       tasks, cml, nstates, (double*)four, g, state_in);
 }
 
+SynArgs make_syn_args(const Tables& tb, const long long* toff, const int* rowoff, const int2* tasks,
+                      int ntasks, const double* cml, int nstates, double* four, const Geom& g,
+                      const double* state_in) {
+    SynArgs a{};
+    a.P = tb.P32 ? (const void*)tb.P32 : (const void*)tb.P;
+    a.H = tb.P32 ? (const void*)tb.H32 : (const void*)tb.H;
+    a.toff = toff;
+    a.rowoff = rowoff;
+    a.tasks = tasks;
+    a.cml = cml;
+    a.nstates = nstates;
+    a.four = four;
+    a.g = g;
+    a.rc = tb.rc;
+    a.sect = tb.sect;
+    a.mu = tb.mu;
+    a.sin_state = state_in;
+    a.inv_lap = tb.inv_lap;
+    a.gx = ntasks;
+    a.blocks = ntasks * ((nstates + 3) / 4);
+    return a;
+}
+
+void launch_synthesis_multi(const LegPlan& plan, bool fp32, bool state_in, const SynArgs* list, int n,
+                            int blocks, hipStream_t st) {
+#define SYNM(TT, JT, D, REC, SIN) k_synthesis_multi<kSynForward, TT, JT, D, REC, SIN><<<blocks, kSynBlock, 0, st>>>(list, n)
+#define SYNM_PLAN(TT, SIN)                                                                        \
+    do {                                                                                          \
+        const int jt = plan.syn_tiles, d = plan.syn_depth;                                        \
+        if (plan.syn_recur) {                                                                     \
+            if (jt == 4 && d == 1) SYNM(TT, 4, 1, true, SIN);                                     \
+            else if (jt == 4) SYNM(TT, 4, 2, true, SIN);                                          \
+            else if (jt == 2 && d == 2) SYNM(TT, 2, 2, true, SIN);                                \
+            else if (jt == 2) SYNM(TT, 2, 4, true, SIN);                                          \
+            else if (d == 4) SYNM(TT, 1, 4, true, SIN);                                           \
+            else SYNM(TT, 1, 8, true, SIN);                                                       \
+        } else if (jt == 6) SYNM(TT, 6, 1, false, SIN);                                           \
+        else if (jt == 4 && d == 1) SYNM(TT, 4, 1, false, SIN);                                   \
+        else if (jt == 4) SYNM(TT, 4, 2, false, SIN);                                             \
+        else if (jt == 3) SYNM(TT, 3, 2, false, SIN);                                             \
+        else if (jt == 2 && d == 2) SYNM(TT, 2, 2, false, SIN);                                   \
+        else if (jt == 2) SYNM(TT, 2, 4, false, SIN);                                             \
+        else if (d == 4) SYNM(TT, 1, 4, false, SIN);                                              \
+        else SYNM(TT, 1, 8, false, SIN);                                                          \
+    } while (0)
+    if (fp32) {
+        if (state_in) SYNM_PLAN(float, true);
+        else SYNM_PLAN(float, false);
+    } else {
+        if (state_in) SYNM_PLAN(double, true);
+        else SYNM_PLAN(double, false);
+    }
+#undef SYNM_PLAN
+#undef SYNM
+}
+
 void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long* toff,
                           const int* rowoff, const int2* tasks, int ntasks, const double* cml,
                           int nstates, double2* four5, const Geom& g, hipStream_t st) {
@@ -499,18 +585,20 @@ template <typename TT> struct AnaStage<TT, true> {
 constexpr int kAnaTrRow = 18;                   // LDS doubles per transpose row (16 + pad)
 constexpr int kAnaTr = 2 * 16 * kAnaTrRow;      // doubles per wave: (Pbar, H) x 16 rows
 
+// The body of workgroup w of one handle's analysis launch (the kernels below run it for one
+// handle's launch or for one workgroup of a launch over several handles).
 template <int MODE, typename TT, int D, bool REC>
-__global__ __launch_bounds__(kBlock) void k_analysis_swe(
+__device__ __forceinline__ void analysis_body(
     const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
     const int4* __restrict__ tasks, int ntasks, int interleave, const TT* __restrict__ G,
-    int nstates, const double* __restrict__ nscale, double* __restrict__ out, Geom g,
-    UpdateArgs fu, int fuse, const double* __restrict__ P64, const double* __restrict__ rc,
-    const double* __restrict__ mu, AdjFuse af) {
+    int nstates, const double* __restrict__ nscale, double* __restrict__ out, const Geom& g,
+    const UpdateArgs& fu, int fuse, const double* __restrict__ P64, const double* __restrict__ rc,
+    const double* __restrict__ mu, const AdjFuse& af, int w) {
     using MM = Mma<TT>;
     using vec = typename MM::vec;
     __shared__ __align__(16) double gl[2][kAnaBuf + 4];       // + a dummy slot for idle threads
     __shared__ __align__(16) double tr[REC ? 4 * kAnaTr : 2];  // REC transposes, one area per wave
-    const int2 tg = xcd_task_group(ntasks, (nstates + 3) >> 2, interleave);
+    const int2 tg = xcd_task_group(w, ntasks, (nstates + 3) >> 2, interleave);
     if (tg.x >= ntasks) return;
     const int4 task = tasks[tg.x];
     if (task.w == 0) return;                                 // padding workgroup (uniform)
@@ -908,6 +996,76 @@ __global__ __launch_bounds__(kBlock) void k_analysis_swe(
             }
         }
     }
+}
+
+template <int MODE, typename TT, int D, bool REC>
+__global__ __launch_bounds__(kBlock) void k_analysis_swe(
+    const TT* __restrict__ P, const TT* __restrict__ H, const long long* __restrict__ toff,
+    const int4* __restrict__ tasks, int ntasks, int interleave, const TT* __restrict__ G,
+    int nstates, const double* __restrict__ nscale, double* __restrict__ out, Geom g,
+    UpdateArgs fu, int fuse, const double* __restrict__ P64, const double* __restrict__ rc,
+    const double* __restrict__ mu, AdjFuse af) {
+    analysis_body<MODE, TT, D, REC>(P, H, toff, tasks, ntasks, interleave, G, nstates, nscale, out, g, fu,
+                                    fuse, P64, rc, mu, af, blockIdx.x);
+}
+
+// One forward analysis launch over several handles (workgroup ranges as k_synthesis_multi).
+template <typename TT, int D, bool REC>
+__global__ __launch_bounds__(kBlock) void k_analysis_multi(const AnaArgs* __restrict__ list, int n) {
+    const int b = blockIdx.x;
+    int h = 0;
+    while (h + 1 < n && b >= list[h + 1].first) ++h;
+    const AnaArgs& a = list[h];
+    if (b - a.first >= a.blocks) return;                     // padding to the next range (uniform)
+    const AdjFuse none{};
+    analysis_body<kAnaForward, TT, D, REC>(
+        static_cast<const TT*>(a.P), static_cast<const TT*>(a.H), a.toff, a.tasks, a.ntasks, a.interleave,
+        static_cast<const TT*>(a.G), a.nstates, a.nscale, a.out, a.g, a.fu, a.fuse, a.P64, a.rc, a.mu, none,
+        b - a.first);
+}
+
+AnaArgs make_ana_args(const Tables& tb, const LegPlan& plan, const long long* toff, const int4* tasks,
+                      int nwg, const double* G, int nstates, const double* neg_lap, double* out,
+                      const Geom& g, const UpdateArgs* fuse, int fuse_mode) {
+    AnaArgs a{};
+    a.P = tb.P32 ? (const void*)tb.P32 : (const void*)tb.P;
+    a.H = tb.P32 ? (const void*)tb.H32 : (const void*)tb.H;
+    a.toff = toff;
+    a.tasks = tasks;
+    a.ntasks = nwg;
+    a.interleave = plan.ana_interleave;
+    a.G = G;
+    a.nstates = nstates;
+    a.nscale = neg_lap;
+    a.out = out;
+    a.g = g;
+    if (fuse) a.fu = *fuse;
+    a.fuse = fuse ? fuse_mode : 0;
+    a.P64 = tb.P;
+    a.rc = tb.rc;
+    a.mu = tb.mu;
+    a.blocks = (int)xcd_grid(nwg, (nstates + 3) / 4);
+    return a;
+}
+
+void launch_analysis_multi(const LegPlan& plan, bool fp32, const AnaArgs* list, int n, int blocks,
+                           hipStream_t st) {
+#define ANAM(TT, D, REC) k_analysis_multi<TT, D, REC><<<blocks, kBlock, 0, st>>>(list, n)
+#define ANAM_PLAN(TT)                                                                             \
+    do {                                                                                          \
+        if (plan.ana_recur) {                                                                     \
+            if (plan.ana_depth == 2) ANAM(TT, 2, true);                                           \
+            else ANAM(TT, 4, true);                                                               \
+        } else if (plan.ana_depth == 2) {                                                         \
+            ANAM(TT, 2, false);                                                                   \
+        } else {                                                                                  \
+            ANAM(TT, 4, false);                                                                   \
+        }                                                                                         \
+    } while (0)
+    if (fp32) ANAM_PLAN(float);
+    else ANAM_PLAN(double);
+#undef ANAM_PLAN
+#undef ANAM
 }
 
 // Analysis variants: D = 4 or 2 table stages in flight per wave; state groups interleaved per

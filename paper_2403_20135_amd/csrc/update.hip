@@ -20,9 +20,9 @@ __device__ __forceinline__ void st2(double* p, double2 v) { *(double2*)p = v; }
 // parts are independent (twice the waves of a thread per coefficient for the same bytes).  The node
 // count is a template parameter so that the per-node arrays live in registers.
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
+__device__ __forceinline__ void update_body(const UpdateArgs& a, int bx, int by) {
+    const int t = bx * blockDim.x + threadIdx.x;
+    const int b = by;
     if (t >= 2 * a.ncoef) return;
     const size_t fs = (size_t)a.ncoef * 2;
     const double* e = a.E + (size_t)b * a.E_member + (size_t)t;
@@ -30,9 +30,39 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
                         [&](int j, int f) { return e[(size_t)j * a.E_node + f * fs]; });
 }
 
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a) {
+    update_body<M>(a, blockIdx.x, blockIdx.y);
+}
+
+// One update launch over several handles (workgroup ranges as the multi-handle Legendre kernels).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_update_multi(const UpdArgsM* __restrict__ list, int n) {
+    const int b = blockIdx.x;
+    int h = 0;
+    while (h + 1 < n && b >= list[h + 1].first) ++h;
+    const UpdArgsM& u = list[h];
+    const int local = b - u.first;
+    if (local >= u.blocks) return;                           // padding to the next range (uniform)
+    update_body<M>(u.a, local % u.gx, local / u.gx);
+}
+
+constexpr int kUpd = 64;           // small workgroups: the (coefficient, part) threads over all CUs
+
+void launch_update_multi(int M, const UpdArgsM* list, int n, int blocks, hipStream_t st) {
+    switch (M) {
+    case 1: k_update_multi<1><<<blocks, kUpd, 0, st>>>(list, n); break;
+    case 2: k_update_multi<2><<<blocks, kUpd, 0, st>>>(list, n); break;
+    case 3: k_update_multi<3><<<blocks, kUpd, 0, st>>>(list, n); break;
+    case 4: k_update_multi<4><<<blocks, kUpd, 0, st>>>(list, n); break;
+    case 5: k_update_multi<5><<<blocks, kUpd, 0, st>>>(list, n); break;
+    case 6: k_update_multi<6><<<blocks, kUpd, 0, st>>>(list, n); break;
+    case 7: k_update_multi<7><<<blocks, kUpd, 0, st>>>(list, n); break;
+    default: k_update_multi<8><<<blocks, kUpd, 0, st>>>(list, n); break;
+    }
+}
+
 void launch_update(const UpdateArgs& a, hipStream_t st) {
-    // small workgroups: spread the (coefficient, part) threads over all CUs
-    constexpr int kUpd = 64;
     dim3 grid((2 * a.ncoef + kUpd - 1) / kUpd, a.batch);
     switch (a.M) {
     case 1: k_update<1><<<grid, kUpd, 0, st>>>(a); break;

@@ -81,3 +81,95 @@ def test_mixed32_workload_one_graph_per_step():
             err = rel_l2(got[i], ref, T)
             print(f"[gpu] mixed32 T{T} member {i}: rel L2 {err:.3e}", flush=True)
             assert err <= 1e-11
+
+
+def _mixed32_handles(precision="fp64"):
+    from paper_2403_20135_amd.api import SDC, SDCGroup
+    wl = W.WORKLOADS["mixed32_m4k3"]
+    groups = {}
+    for k, mb in enumerate(wl.members):
+        groups.setdefault(mb.T, []).append((k, mb))
+    handles, u0, dts, cfgs = [], [], [], []
+    for T, lst in sorted(groups.items()):
+        mb = lst[0][1]
+        handles.append(SDC(T, mb.nlat, mb.nlon, wl.M, wl.K, len(lst), precision, W.RADIUS, W.GRAVITY,
+                           W.OMEGA, W.MEAN_DEPTH))
+        u0.append(np.stack([W.initial_state(wl, member=k) for k, _ in lst]))
+        dts.append(mb.dt)
+        cfgs.append((T, mb.nlat, mb.nlon, len(lst)))
+    return wl, handles, SDCGroup(handles), u0, dts, cfgs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mixed32_one_launch_per_phase_is_bitwise_the_branches(precision):
+    """Mode 1 (one synthesis, grid and analysis launch per sweep over all 32 members of three
+    truncations) against mode 0 (one graph branch per truncation): the same states bit for bit,
+    over graph replays."""
+    wl, handles, grp, u0, dts, _ = _mixed32_handles(precision)
+    assert grp.mode == 1
+    x1 = [_dev(u) for u in u0]
+    for _ in range(3):
+        grp.step(x1, dts, wl.M, wl.K)
+    grp.sync()
+    grp.set_mode(0)
+    assert grp.mode == 0
+    x0 = [_dev(u) for u in u0]
+    for _ in range(3):
+        grp.step(x0, dts, wl.M, wl.K)
+    grp.sync()
+    for a, b in zip(x1, x0):
+        ha, hb = _host(a), _host(b)
+        print(f"[gpu] mixed32 {precision} merged vs branches: max |diff| {np.max(np.abs(ha - hb)):.3e}", flush=True)
+        assert np.array_equal(ha, hb)
+
+
+def test_mixed32_one_launch_per_phase_matches_oracle():
+    """The 32-member ensemble in mode 1 over 6 steps; the first and last member of every truncation
+    against the oracle, <= 1e-11 relative L2."""
+    wl, handles, grp, u0, dts, cfgs = _mixed32_handles()
+    xs = [_dev(u) for u in u0]
+    steps = 6
+    for _ in range(steps):
+        grp.step(xs, dts, wl.M, wl.K)
+    grp.sync()
+    for g, (T, nlat, nlon, b) in enumerate(cfgs):
+        got = _host(xs[g])
+        o = _oracle(T, nlat, nlon)
+        for i in sorted({0, b - 1}):
+            ref = o.step(u0[g][i], dts[g], wl.M, wl.K, steps=steps)
+            err = rel_l2(got[i], ref, T)
+            print(f"[gpu] mixed32 one launch per phase, T{T} member {i}, {steps} steps: rel L2 {err:.3e}",
+                  flush=True)
+            assert err <= 1e-11
+
+
+def test_merged_group_with_separate_updates():
+    """M = 3 (the separate node-update kernel, also one launch over the members), T31 x 2 and
+    T63 x 1: mode 1 bitwise mode 0 and against the oracle; a group whose members cannot share
+    launches refuses mode 1."""
+    from paper_2403_20135_amd import _lib
+    configs = [(31, 48, 96, 3, 3, 2), (63, 96, 192, 3, 3, 1)]
+    dts = [600.0, 480.0]
+    handles, grp = _group(configs)
+    assert grp.mode == 1
+    u0 = [_states(c[0], c[5], 60 + k) for k, c in enumerate(configs)]
+    x1 = [_dev(u) for u in u0]
+    for _ in range(2):
+        grp.step(x1, dts, 3, 3)
+    grp.set_mode(0)
+    x0 = [_dev(u) for u in u0]
+    for _ in range(2):
+        grp.step(x0, dts, 3, 3)
+    grp.sync()
+    for k, (T, nlat, nlon, M, K, b) in enumerate(configs):
+        assert np.array_equal(_host(x1[k]), _host(x0[k]))
+        o = _oracle(T, nlat, nlon)
+        ref = np.stack([o.step(u0[k][i], dts[k], M, K, steps=2) for i in range(b)])
+        assert rel_l2(_host(x1[k]), ref, T) <= 1e-11
+    # nlon = 64 is not a length of the merged grid kernel
+    h2, g2 = _group([(21, 34, 64, 3, 3, 1), (31, 48, 96, 3, 3, 1)])
+    assert g2.mode == 0
+    g2.set_mode(1)
+    with pytest.raises(_lib.SDCError) as e:
+        g2.step([_dev(_states(21, 1, 70)), _dev(_states(31, 1, 71))], [900.0, 600.0], 3, 3)
+    assert e.value.code == _lib.SDC_EUNSUPPORTED

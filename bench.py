@@ -294,6 +294,7 @@ def measure_mixed(steps=20, warmup=3):
                                dtype=torch.float64, device="cuda"))
         dts.append(mb.dt)
     grp = SDCGroup(handles)
+    chosen = grp.autotune(xs, dts, wl.M, wl.K, 5)
     res = {}
     for mode in (1, 0):
         grp.set_mode(mode)
@@ -312,12 +313,15 @@ def measure_mixed(steps=20, warmup=3):
     grp.close()
     for h in handles:
         h.close()
-    el = res[1]
+    el = res[chosen]
     return {"workload": wl.name, "members": len(wl.members), "steps": steps,
             "steps_per_s": round(steps / el, 3), "member_steps_per_s": round(len(wl.members) * steps / el, 1),
             "ms_per_step": round(el / steps * 1e3, 4), "precision": "fp64",
-            "launch": "one hipGraph per step; every phase one launch over all 32 members (mode 1)",
-            "member_steps_per_s_graph_branches": round(len(wl.members) * steps / res[0], 1)}
+            "mode_chosen_by_group_autotuner": chosen,
+            "member_steps_per_s_one_launch_per_phase": round(len(wl.members) * steps / res[1], 1),
+            "member_steps_per_s_graph_branches": round(len(wl.members) * steps / res[0], 1),
+            "launch": "one hipGraph per step; mode 1: every phase one launch over all 32 members, "
+                      "mode 0: one graph branch per truncation"}
 
 
 def speedup_at_equal_error(rows):

@@ -35,7 +35,9 @@
  * by sdc_init and, once per handle, by the first call of an entry point that says so (adjoint,
  * comparison integrators); sdc_free releases everything the handle owns.  A handle must be used
  * from one host thread at a time; different handles are independent.  No C++ exception crosses
- * this interface.
+ * this interface.  With the environment variable SDC_ROCTX set (and not "0") when a handle is
+ * created, its step phases are marked by host-side roctx ranges ("sdc.step", "sdc.f_E",
+ * "sdc.f_E+update", "sdc.update") for rocprofv3 --marker-trace.
  * ---------------------------------------------------------------------------------------------
  */
 #ifndef SDC_MI355X_H
@@ -238,6 +240,16 @@ typedef enum {
 int sdc_timing_enable(sdc_handle h, int on);
 int sdc_timing_read(sdc_handle h, int kernel_class, double* total_ms, long long* launches);
 
+/* Read-before-write check (race detection for tests): while on = 1, the step (sdc_step,
+ * sdc_step_graph, sdc_step_taped and the adjoint's recomputation) fills every workspace a launch
+ * writes -- the Fourier fields before the synthesis, the analysis input before the grid step, the
+ * tendencies or the updated node states and their synthesis layout before the analysis or update
+ * that writes them -- with all-ones words (NaN in FP64 and FP32) just before that launch.  A
+ * kernel that reads a value of its own sweep before it is written, padding it does not clear, or
+ * a value left from an earlier sweep then produces NaN instead of the step's result; with correct
+ * kernels the states are bitwise those of on = 0.  Extra fill launches; cached graphs are dropped. */
+int sdc_debug_poison(sdc_handle h, int on);
+
 /* Sizes and device memory of a handle. */
 int sdc_get_info(sdc_handle h, sdc_info* info);
 
@@ -339,6 +351,15 @@ int sdc_group_create(const sdc_handle* members, int n, void* hip_stream, sdc_gro
 int sdc_group_step(sdc_group g, double* const* states, const double* dts, int M, int K);
 int sdc_group_set_mode(sdc_group g, int mode);
 int sdc_group_get_mode(sdc_group g, int* mode);
+
+/* Group autotuner: when the members can share launches, times every built Legendre variant as a
+ * merged launch at the node and one-state shapes (reps launches each) and keeps the fastest for
+ * mode 1, then times reps whole steps of the given states in mode 1 and in mode 0 and keeps the
+ * faster mode (*mode receives it unless NULL); otherwise selects mode 0.  The states are restored
+ * afterwards (a device copy of each is allocated for the duration of the call); the members'
+ * workspaces are overwritten.  Blocks until done.  Same argument rules as sdc_group_step. */
+int sdc_group_autotune(sdc_group g, double* const* states, const double* dts, int M, int K, int reps,
+                       int* mode);
 int sdc_group_sync(sdc_group g);
 int sdc_group_free(sdc_group g);
 

@@ -64,6 +64,8 @@ _SIGS = {
     "sdc_group_sync": (c_int, [c_void_p]),
     "sdc_group_set_mode": (c_int, [c_void_p, c_int]),
     "sdc_group_get_mode": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
+    "sdc_group_autotune": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_double), c_int, c_int,
+                                   c_int, ctypes.POINTER(c_int)]),
     "sdc_group_free": (c_int, [c_void_p]),
     "sht_forward": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sht_inverse": (c_int, [c_void_p, c_void_p, c_void_p]),
@@ -82,6 +84,7 @@ _SIGS = {
     "sdc_copy_coefficients": (c_int, [c_void_p, c_int, P_DOUBLE, P_DOUBLE]),
     "sdc_copy_legendre": (c_int, [c_void_p, c_int, P_DOUBLE, P_DOUBLE]),
     "sdc_timing_enable": (c_int, [c_void_p, c_int]),
+    "sdc_debug_poison": (c_int, [c_void_p, c_int]),
     "sdc_timing_read": (c_int, [c_void_p, c_int, P_DOUBLE, ctypes.POINTER(c_ll)]),
     "sdc_last_error": (ctypes.c_char_p, []),
 }

@@ -189,6 +189,10 @@ class SDC:
     def sync(self):
         check(self.lib.sdc_sync(self.h))
 
+    def debug_poison(self, on: bool):
+        """NaN-fill every step workspace before the launch that writes it (read-before-write check)."""
+        check(self.lib.sdc_debug_poison(self.h, int(bool(on))))
+
     def timing(self, on: bool):
         """Enable/disable per-kernel HIP-event timing on this handle's stream (clears figures)."""
         check(self.lib.sdc_timing_enable(self.h, 1 if on else 0))
@@ -308,6 +312,19 @@ class SDCGroup:
         dd = (ctypes.c_double * len(dts))(*[float(d) for d in dts])
         check(self.lib.sdc_group_step(self.g, ptrs, dd, int(M), int(K)))
         return states
+
+    def autotune(self, states, dts, M: int, K: int, reps: int = 5) -> int:
+        """Tune the merged launches' variants, time both modes on these states (restored) and keep
+        the faster; returns the mode."""
+        if len(states) != len(self.members) or len(dts) != len(self.members):
+            raise ValueError("one state tensor and one dt per member handle")
+        for m, s in zip(self.members, states):
+            m._check(s, m.state_shape, "state")
+        ptrs = (ctypes.c_void_p * len(states))(*[s.data_ptr() for s in states])
+        dd = (ctypes.c_double * len(dts))(*[float(d) for d in dts])
+        mode = ctypes.c_int()
+        check(self.lib.sdc_group_autotune(self.g, ptrs, dd, int(M), int(K), int(reps), ctypes.byref(mode)))
+        return mode.value
 
     def sync(self):
         check(self.lib.sdc_group_sync(self.g))

@@ -5,10 +5,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <roctracer/roctx.h>
 
 #include "common.h"
 
@@ -189,6 +192,9 @@ struct StepOp {
 
 struct sdc_ctx {
     std::vector<StepOp>* rec = nullptr;   // when set, f_E and update launches are recorded here
+    bool roctx = false;                   // SDC_ROCTX set at sdc_init: roctx ranges around the phases
+    bool debug_poison = false;            // sdc_debug_poison: NaN-fill workspaces before their writers
+    bool poison_now = false;              // inside enqueue_step with debug_poison on
     sdc_config cfg{};
     hipStream_t st = nullptr;
     Geom g{};
@@ -197,6 +203,7 @@ struct sdc_ctx {
     double two_omega_explicit = 0;    // f in the explicit products (0 when L_c is implicit)
     double2* lc = nullptr;            // implicit_coriolis: (e-_k, e+_k) per coefficient
     double2* lc_scratch = nullptr;    // implicit_coriolis: elimination coefficients of the chains
+    double* lc_beta = nullptr;        // implicit_coriolis: right-hand sides of the node updates
     std::vector<void*> allocs;
     long long bytes = 0, table_bytes = 0;
     double *mu = nullptr, *w = nullptr, *P = nullptr, *H = nullptr, *tau = nullptr, *Q = nullptr;
@@ -506,6 +513,7 @@ int setup(sdc_ctx* c) {
     if (cf.implicit_coriolis) {
         if ((rc = c->alloc(c->lc, g.ncoef))) return rc;
         if ((rc = c->alloc(c->lc_scratch, (size_t)c->smax * 2 * 3 * g.ncoef))) return rc;
+        if ((rc = c->alloc(c->lc_beta, (size_t)c->smax * 3 * g.ncoef * 2))) return rc;
         launch_lc_coefs(c->lc, c->n_of, c->m_of, g.ncoef, c->st);
     }
     HIP_TRY(hipGetLastError());
@@ -516,6 +524,18 @@ int setup(sdc_ctx* c) {
     return SDC_OK;
 }
 
+// Host-side roctx range (rocprofv3 --marker-trace) around the enqueue of one phase when the
+// handle was created with SDC_ROCTX set; under graph capture it marks the capture.
+struct PhaseRange {
+    bool on;
+    PhaseRange(const sdc_ctx* c, const char* name) : on(c->roctx && !c->rec) {
+        if (on) roctxRangePushA(name);
+    }
+    ~PhaseRange() {
+        if (on) roctxRangePop();
+    }
+};
+
 // f_E of S states whose synthesis input is already in c->cml (written by the update kernels), or,
 // with states != null, read by the synthesis from the state layout.
 void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr,
@@ -524,15 +544,29 @@ void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr,
         c->rec->push_back(StepOp{0, S, states, out, save, fuse ? *fuse : UpdateArgs{}, fuse ? fuse_mode : 0});
         return;
     }
+    const PhaseRange range(c, fuse ? "sdc.f_E+update" : "sdc.f_E");
     const LegPlan& lp = c->plan_for(S);
+    const size_t tb = c->P32 ? sizeof(float) : sizeof(double);
+    if (c->poison_now)
+        launch_poison(c->four, (size_t)S * kSynFields * c->g.nlat * c->g.ms * sizeof(double2), c->st);
     long t = c->begin(SDC_KERNEL_SYNTHESIS);
     launch_synthesis_swe(c->tables(), lp, c->toff, c->rowoff, c->syn_list(lp), c->syn_count(lp),
                          c->cml, S, c->four, c->g, c->st, states);
     c->end(SDC_KERNEL_SYNTHESIS, t);
+    if (c->poison_now)
+        launch_poison(c->G, (size_t)c->g.nh * (c->g.T + 1) * S * 2 * kFwdVals * tb, c->st);
     t = c->begin(SDC_KERNEL_GRID);
     launch_grid_swe(c->four, c->G, c->P32 != nullptr, c->mu, c->w, c->tw, c->plan, S, c->two_omega_explicit, save,
                     c->g, c->st);
     c->end(SDC_KERNEL_GRID, t);
+    if (c->poison_now) {
+        const size_t st_b = (size_t)3 * c->g.ncoef * 2 * sizeof(double);
+        if (!fuse) launch_poison(out, (size_t)S * st_b, c->st);          // the tendencies
+        if (fuse && !fuse->last_only) {                                   // the updated nodes
+            launch_poison(fuse->uout, (size_t)fuse->batch * fuse->M * st_b, c->st);
+            launch_poison(fuse->cml, (size_t)c->g.nrows * fuse->batch * fuse->M * kCmlVals * tb, c->st);
+        }
+    }
     t = c->begin(SDC_KERNEL_ANALYSIS);
     launch_analysis_swe(c->tables(), lp, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
                         out, c->g, c->st, fuse, fuse_mode);
@@ -596,6 +630,14 @@ void run_update(sdc_ctx* c, const UpdateArgs& a) {
         c->rec->push_back(StepOp{1, 0, nullptr, nullptr, nullptr, a, 0});
         return;
     }
+    const PhaseRange range(c, "sdc.update");
+    if (c->poison_now && !a.last_only) {
+        const size_t st_b = (size_t)3 * c->g.ncoef * 2 * sizeof(double);
+        launch_poison(a.uout, (size_t)a.batch * a.M * st_b, c->st);
+        if (a.cml)
+            launch_poison(a.cml, (size_t)c->g.nrows * a.batch * a.M * kCmlVals *
+                                     (c->P32 ? sizeof(float) : sizeof(double)), c->st);
+    }
     const long t = c->begin(SDC_KERNEL_UPDATE);
     launch_update(a, c->st);
     c->end(SDC_KERNEL_UPDATE, t);
@@ -628,6 +670,7 @@ int sdc_init(const sdc_config* cfg, void* hip_stream, sdc_handle* out) {
         delete c;
         return rc;
     }
+    if (const char* e = std::getenv("SDC_ROCTX")) c->roctx = e[0] != '\0' && std::strcmp(e, "0") != 0;
     // the scratch array's address on this device (the device current at init owns the handle)
     if (hipGetDevice(&c->dev) == hipSuccess) {
         c->scratch_dev = scratch_address(c->dev, &c->scratch_err);
@@ -911,8 +954,19 @@ int qd_sweep(const sdc_ctx* c, int s, int M) { return c->cfg.qdelta == 1 ? M : (
 // With `tape`, the grid fields of every f_E evaluation are kept there (stage s at
 // tape + stage_states(s) * tape_per_state); without `last_update` the final last-node update is
 // skipped (the adjoint's recomputation needs only the stages).
+void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, double2* tape,
+                       bool last_update);
+
 void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K, double2* tape = nullptr,
                   bool last_update = true) {
+    c->poison_now = c->debug_poison && !c->rec;
+    const PhaseRange range(c, "sdc.step");
+    enqueue_step_impl(c, state, dt, M, K, tape, last_update);
+    c->poison_now = false;
+}
+
+void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, double2* tape,
+                       bool last_update) {
     const int B = c->cfg.batch;
     const long long fs = 3LL * c->g.ncoef * 2;
     auto tape_at = [&](int s) -> double2* {
@@ -962,6 +1016,9 @@ void enqueue_step(sdc_ctx* c, double* state, double dt, int M, int K, double2* t
         l.inv_lap = c->inv_lap;
         l.lc = c->lc;
         l.scratch = c->lc_scratch;
+        l.beta_ws = c->lc_beta;
+        l.n_of = c->n_of;
+        l.m_of = c->m_of;
         l.flag = c->flag;
         l.dt = dt;
         l.phibar = c->phibar;
@@ -1556,6 +1613,14 @@ int eval_implicit(sdc_handle h, const double* u, double* fI) {
     return SDC_OK;
 }
 
+int sdc_debug_poison(sdc_handle h, int on) {
+    if (int rc = check_handle(h)) return rc;
+    if (on != 0 && on != 1) return fail(SDC_EINVAL, "on=%d: 0 or 1", on);
+    h->debug_poison = on != 0;
+    h->drop_graphs();
+    return SDC_OK;
+}
+
 int sdc_timing_enable(sdc_handle h, int on) {
     if (int rc = check_handle(h)) return rc;
     HIP_TRY(hipStreamSynchronize(h->st));
@@ -1648,6 +1713,8 @@ int sdc_copy_legendre(sdc_handle h, int m, double* Pbar, double* H) {
 struct sdc_group_s {
     std::vector<sdc_handle> members;
     int mode = 0;                     // 1: one launch per kernel class and phase over all members
+    bool tuned = false;               // plan / plan1 timed by sdc_group_autotune for mode 1
+    LegPlan plan{}, plan1{};          // Legendre variants of the merged node / one-state launches
     void* desc = nullptr;             // device copies of the merged launches' per-member arguments
     size_t desc_bytes = 0;
     hipStream_t st = nullptr;
@@ -1756,7 +1823,7 @@ int group_capture_merged(sdc_group_s* g, double* const* states, const double* dt
         Launch L{};
         L.kind = ops[0][i].kind;
         if (L.kind == 0) {
-            const LegPlan lp = cl->plan_for(ops[lead][i].S);
+            const LegPlan lp = g->tuned ? (ops[0][i].states ? g->plan1 : g->plan) : cl->plan_for(ops[lead][i].S);
             L.plan = lp;
             L.state_in = ops[0][i].states != nullptr;
             std::vector<SynArgs> sy(n);
@@ -1855,6 +1922,107 @@ int group_capture_branches(sdc_group_s* g, double* const* states, const double* 
     return SDC_OK;
 }
 
+// Times one merged synthesis and one merged analysis launch of every built Legendre variant at the
+// node shape (batch x M states per member, synthesis layout input) and at the one-state shape
+// (the states read in place), and keeps the fastest of each in g->plan / g->plan1.
+int group_tune_legendre(sdc_group_s* g, int M, int reps) {
+    const size_t n = g->members.size();
+    const bool fp32 = g->members[0]->P32 != nullptr;
+    for (sdc_ctx* c : g->members) {         // finite operands in the workspaces
+        HIP_TRY(hipMemsetAsync(c->cml, 0, (size_t)c->g.nrows * c->smax * kCmlVals * sizeof(double), g->st));
+        HIP_TRY(hipMemsetAsync(c->G, 0, (size_t)(c->g.T + 1) * 2 * c->g.nhp * c->smax * kAnaStride * sizeof(double),
+                               g->st));
+    }
+    HIP_TRY(hipStreamSynchronize(g->st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SDC_EHIP, "hipEventCreate failed");
+    }
+    hipError_t err = hipSuccess;
+    auto time_it = [&](auto&& launch) {
+        float ms = 0.f;
+        launch();
+        hipError_t e = hipEventRecord(e0, g->st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, g->st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) err = e;
+        return ms;
+    };
+    constexpr int kSyn = 14;
+    const int shapes[kSyn][3] = {{1, 8, 0}, {1, 4, 0}, {2, 4, 0}, {2, 2, 0}, {3, 2, 0},
+                                 {4, 2, 0}, {4, 1, 0}, {6, 1, 0}, {1, 8, 1}, {1, 4, 1},
+                                 {2, 4, 1}, {2, 2, 1}, {4, 2, 1}, {4, 1, 1}};
+    for (int one = 0; one < 2 && err == hipSuccess; ++one) {
+        LegPlan best = g->members[0]->lplan;
+        float best_ms = 1e30f;
+        for (int k = 0; k < kSyn && err == hipSuccess; ++k) {
+            LegPlan lp = best;
+            lp.syn_tiles = shapes[k][0];
+            lp.syn_depth = shapes[k][1];
+            lp.syn_recur = shapes[k][2];
+            std::vector<SynArgs> sy(n);
+            int fs = 0;
+            for (size_t h = 0; h < n; ++h) {
+                sdc_ctx* c = g->members[h];
+                const int S = one ? c->cfg.batch : c->cfg.batch * M;
+                sy[h] = make_syn_args(c->tables(), c->toff, c->rowoff, c->syn_list(lp), c->syn_count(lp), c->cml, S,
+                                      reinterpret_cast<double*>(c->four), c->g, one ? c->ua : nullptr);
+                sy[h].first = fs;
+                fs += (sy[h].blocks + 7) / 8 * 8;
+            }
+            err = hipMemcpy(g->desc, sy.data(), n * sizeof(SynArgs), hipMemcpyHostToDevice);
+            if (err != hipSuccess) break;
+            const float ms = time_it([&] {
+                launch_synthesis_multi(lp, fp32, one != 0, static_cast<const SynArgs*>(g->desc), (int)n, fs, g->st);
+            });
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.syn_tiles = lp.syn_tiles;
+                best.syn_depth = lp.syn_depth;
+                best.syn_recur = lp.syn_recur;
+            }
+        }
+        best_ms = 1e30f;
+        LegPlan ana_best = best;
+        for (int k = 0; k < 8 && err == hipSuccess; ++k) {
+            LegPlan lp = best;
+            lp.ana_depth = (k & 2) ? 2 : 4;
+            lp.ana_interleave = (k & 1) ? 0 : 1;
+            lp.ana_recur = k >> 2;
+            std::vector<AnaArgs> an(n);
+            int fa = 0;
+            for (size_t h = 0; h < n; ++h) {
+                sdc_ctx* c = g->members[h];
+                const int S = one ? c->cfg.batch : c->cfg.batch * M;
+                an[h] = make_ana_args(c->tables(), lp, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap, c->E,
+                                      c->g, nullptr, 0);
+                an[h].first = fa;
+                fa += (an[h].blocks + 7) / 8 * 8;
+            }
+            err = hipMemcpy(g->desc, an.data(), n * sizeof(AnaArgs), hipMemcpyHostToDevice);
+            if (err != hipSuccess) break;
+            const float ms = time_it([&] {
+                launch_analysis_multi(lp, fp32, static_cast<const AnaArgs*>(g->desc), (int)n, fa, g->st);
+            });
+            if (ms < best_ms) {
+                best_ms = ms;
+                ana_best = lp;
+            }
+        }
+        (one ? g->plan1 : g->plan) = ana_best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(SDC_EHIP, "group autotune launch failed: %s", hipGetErrorString(err));
+    g->tuned = true;
+    return SDC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1915,6 +2083,68 @@ int sdc_group_set_mode(sdc_group g, int mode) {
 int sdc_group_get_mode(sdc_group g, int* mode) {
     if (!g || !mode) return fail(SDC_EINVAL, "group/mode is NULL");
     *mode = g->mode;
+    return SDC_OK;
+}
+
+int sdc_group_autotune(sdc_group g, double* const* states, const double* dts, int M, int K, int reps, int* mode) {
+    if (!g) return fail(SDC_EINVAL, "group is NULL");
+    if (!states || !dts) return fail(SDC_EINVAL, "states/dts is NULL");
+    if (reps < 1 || reps > 1000) return fail(SDC_EINVAL, "reps = %d outside [1, 1000]", reps);
+    const size_t n = g->members.size();
+    for (size_t i = 0; i < n; ++i)
+        if (int rc = check_step_args(g->members[i], states[i], dts[i], M, K)) return rc;
+    std::string why;
+    if (!group_mergeable(g, M, &why)) {
+        if (g->mode != 0) (void)sdc_group_set_mode(g, 0);
+        if (mode) *mode = 0;
+        return SDC_OK;
+    }
+    if (g->exec) {                          // its descriptors are overwritten by the timing below
+        (void)hipStreamSynchronize(g->st);
+        (void)hipGraphExecDestroy(g->exec);
+        (void)hipGraphDestroy(g->graph);
+        g->exec = nullptr;
+        g->graph = nullptr;
+    }
+    if (int rc = group_tune_legendre(g, M, reps)) return rc;
+    // whole steps in both modes, on copies of the states (restored afterwards)
+    std::vector<void*> saved(n, nullptr);
+    std::vector<size_t> nb(n);
+    int rc = SDC_OK;
+    for (size_t i = 0; i < n && rc == SDC_OK; ++i) {
+        nb[i] = (size_t)g->members[i]->cfg.batch * 3 * g->members[i]->g.ncoef * 2 * sizeof(double);
+        if (hipMalloc(&saved[i], nb[i]) != hipSuccess) {
+            (void)hipGetLastError();
+            saved[i] = nullptr;
+            rc = fail(SDC_ENOMEM, "group autotune: state copy allocation failed");
+        } else if (hipMemcpyAsync(saved[i], states[i], nb[i], hipMemcpyDeviceToDevice, g->st) != hipSuccess) {
+            rc = fail(SDC_EHIP, "group autotune: state copy failed");
+        }
+    }
+    float ms[2] = {0.f, 0.f};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == SDC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(SDC_EHIP, "hipEventCreate failed");
+    for (int md = 1; md >= 0 && rc == SDC_OK; --md) {
+        (void)sdc_group_set_mode(g, md);
+        if ((rc = sdc_group_step(g, states, dts, M, K))) break;          // capture + warm-up
+        if (hipEventRecord(e0, g->st) != hipSuccess) rc = fail(SDC_EHIP, "event record failed");
+        for (int r = 0; r < reps && rc == SDC_OK; ++r) rc = sdc_group_step(g, states, dts, M, K);
+        if (rc == SDC_OK && (hipEventRecord(e1, g->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms[md], e0, e1) != hipSuccess))
+            rc = fail(SDC_EHIP, "group autotune timing failed");
+    }
+    for (size_t i = 0; i < n; ++i)
+        if (saved[i]) {
+            (void)hipMemcpyAsync(states[i], saved[i], nb[i], hipMemcpyDeviceToDevice, g->st);
+            (void)hipStreamSynchronize(g->st);
+            (void)hipFree(saved[i]);
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    (void)sdc_group_set_mode(g, ms[1] <= ms[0] ? 1 : 0);
+    if (mode) *mode = g->mode;
     return SDC_OK;
 }
 

@@ -269,6 +269,8 @@ struct UpdateArgs {
     int M, sweep, last_only, batch, ncoef, T;
 };
 void launch_update(const UpdateArgs& a, hipStream_t st);
+// Fills bytes (a multiple of 4) with all-ones words: NaN in FP64 and FP32 (read-before-write checks).
+void launch_poison(void* p, size_t bytes, hipStream_t st);
 // Sequential IMEX SDC (Algorithm 1): update of node m of a sweep.  Node arrays [node][B][3][ncoef].
 struct SeqArgs {
     const double* un;          // u_n [B][3][ncoef][2]
@@ -331,6 +333,9 @@ struct LcArgs {
     int cml32;
     const double* beta;          // mode 1: [B][3][ncoef] (u may alias it)
     double alpha;                // mode 1
+    double* beta_ws;             // mode 0: right-hand sides [output state][3][ncoef] (workspace)
+    const int* n_of;             // mode 0: degree and order of every coefficient
+    const int* m_of;
     const double* tau;
     const double* Q;
     const int* rowoff;

@@ -77,8 +77,49 @@ __device__ __forceinline__ FI f_implicit_at(const double* __restrict__ u, size_t
 
 }  // namespace
 
-// The chain solve.  mode 0: node update of a dSDC sweep (Section 4.2, with f_I = L_g + L_c) for
-// output node i of member b; mode 1: u = solve(alpha, beta) of member b.
+// Right-hand sides of the node update (Section 4.2, with f_I = L_g + L_c) for every coefficient,
+// output node and member, fully parallel: beta_i = u_n + dt sum_j Q[i][j] (f_I(u_j) + E_j) -
+// alpha_i f_I(u_i), written to the workspace the chain solve reads ([output state][3][ncoef]).
+__global__ __launch_bounds__(kBlock) void k_lc_rhs(LcArgs a) {
+    const int nodes = a.last_only ? 1 : a.M;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;                       // output node (fastest) and member
+    if (idx >= a.ncoef) return;
+    const int i = a.last_only ? a.M - 1 : r % nodes;
+    const int b = r / nodes;
+    const int T = a.T;
+    const size_t fs = (size_t)a.ncoef * 2;
+    const int k = a.n_of[idx], m = a.m_of[idx];
+    const double cn = k * (k + 1.0) * a.inv_a2;
+    const double2 e = a.lc[idx];
+    const int sdiv = a.sweep < a.M ? a.sweep : a.M;
+    const double alpha = a.dt * a.tau[i] / sdiv;
+    const double* Qi = a.Q + i * kMaxNodes;
+    const double* un = a.un + (size_t)b * 3 * fs;
+    double2 bphi = ld(un + 2 * (size_t)idx), bzeta = ld(un + fs + 2 * (size_t)idx),
+            bdiv = ld(un + 2 * fs + 2 * (size_t)idx);
+    FI own{};
+    for (int j = 0; j < a.M; ++j) {
+        const double* uj = a.uprev + (size_t)b * a.uprev_member + (size_t)j * a.uprev_node;
+        const double* ej = a.E + (size_t)b * a.E_member + (size_t)j * a.E_node;
+        const FI fi = f_implicit_at(uj, fs, idx, k, m, T, e, a.two_omega, a.phibar, cn);
+        if (j == i) own = fi;
+        const double q = a.dt * Qi[j];
+        bphi = cadd(bphi, rmul(q, cadd(fi.phi, ld(ej + 2 * (size_t)idx))));
+        bzeta = cadd(bzeta, rmul(q, cadd(fi.zeta, ld(ej + fs + 2 * (size_t)idx))));
+        bdiv = cadd(bdiv, rmul(q, cadd(fi.div, ld(ej + 2 * fs + 2 * (size_t)idx))));
+    }
+    const int ostate = a.last_only ? b : b * a.M + i;
+    double* out = a.beta_ws + (size_t)ostate * 3 * fs + 2 * (size_t)idx;
+    *(double2*)out = csub(bphi, rmul(alpha, own.phi));
+    *(double2*)(out + fs) = csub(bzeta, rmul(alpha, own.zeta));
+    *(double2*)(out + 2 * fs) = csub(bdiv, rmul(alpha, own.div));
+}
+
+// The chain solve of u - alpha f_I(u) = beta for one chain of one order of one output state:
+// mode 0, beta from k_lc_rhs (node update of a sweep, output node i of member b); mode 1, beta
+// given (imex_solve, member b; u may alias beta).  The elimination and the back substitution are
+// the only serial dependences; the loads they need are issued several degrees ahead.
 __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
     const int nodes = a.mode == 0 ? (a.last_only ? 1 : a.M) : 1;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -97,64 +138,53 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
     const int sdiv = a.sweep < a.M ? a.sweep : a.M;
     const double alpha = a.mode == 0 ? a.dt * a.tau[i] / sdiv : a.alpha;
     const double two_omega = a.two_omega;
-    // scratch: 3 complex per (output state, chain, coefficient)
     const int ostate = a.mode == 0 ? (a.last_only ? b : b * a.M + i) : b;
-    double2* sc = a.scratch + ((size_t)ostate * 2 + c) * a.ncoef * 3;
-    const double* Qi = a.Q + i * kMaxNodes;
-    // right-hand side (beta) at degree k
-    auto rhs = [&](int k, int idx, double cn, double2 e, bool zeta_pos) {
-        FI bt;
-        if (a.mode == 1) {
-            // only the fields this chain owns at this degree: u may alias beta
-            const double* be = a.beta + (size_t)b * 3 * fs;
-            const double2 z0 = make_double2(0.0, 0.0);
-            bt.phi = zeta_pos ? z0 : ld(be + 2 * (size_t)idx);
-            bt.zeta = zeta_pos ? ld(be + fs + 2 * (size_t)idx) : z0;
-            bt.div = zeta_pos ? z0 : ld(be + 2 * fs + 2 * (size_t)idx);
-            return bt;
-        }
-        const double* un = a.un + (size_t)b * 3 * fs;
-        bt.phi = ld(un + 2 * (size_t)idx);
-        bt.zeta = ld(un + fs + 2 * (size_t)idx);
-        bt.div = ld(un + 2 * fs + 2 * (size_t)idx);
-        FI own{};
-        for (int j = 0; j < a.M; ++j) {
-            const double* uj = a.uprev + (size_t)b * a.uprev_member + (size_t)j * a.uprev_node;
-            const double* ej = a.E + (size_t)b * a.E_member + (size_t)j * a.E_node;
-            const FI fi = f_implicit_at(uj, fs, idx, k, m, T, e, two_omega, a.phibar, cn);
-            if (j == i) own = fi;
-            const double q = a.dt * Qi[j];
-            bt.phi = cadd(bt.phi, rmul(q, cadd(fi.phi, ld(ej + 2 * (size_t)idx))));
-            bt.zeta = cadd(bt.zeta, rmul(q, cadd(fi.zeta, ld(ej + fs + 2 * (size_t)idx))));
-            bt.div = cadd(bt.div, rmul(q, cadd(fi.div, ld(ej + 2 * fs + 2 * (size_t)idx))));
-        }
-        bt.phi = csub(bt.phi, rmul(alpha, own.phi));
-        bt.zeta = csub(bt.zeta, rmul(alpha, own.zeta));
-        bt.div = csub(bt.div, rmul(alpha, own.div));
-        return bt;
+    // scratch: 3 complex per (output state, chain, coefficient)
+    double2* __restrict__ sc = a.scratch + ((size_t)ostate * 2 + c) * a.ncoef * 3;
+    const double* __restrict__ be = (a.mode == 0 ? a.beta_ws + (size_t)ostate * 3 * fs
+                                                 : a.beta + (size_t)b * 3 * fs);
+    const double2* __restrict__ lc = a.lc;
+    // the right-hand side this chain needs at position j: zeta at its zeta degrees, the combination
+    // beta_delta + alpha c_k beta_Phi (Phi' eliminated) and beta_Phi at its delta degrees
+    struct Pos {
+        double2 r, bphi, e;
     };
-    // forward elimination
+    auto fetch = [&](int j) {
+        Pos p;
+        const int idx = idx0 + j;
+        p.e = lc[idx];
+        if (((j & 1) == c)) {
+            p.r = ld(be + fs + 2 * (size_t)idx);
+            p.bphi = make_double2(0.0, 0.0);
+        } else {
+            p.bphi = ld(be + 2 * (size_t)idx);
+            p.r = ld(be + 2 * fs + 2 * (size_t)idx);          // beta_delta (combined below)
+        }
+        return p;
+    };
+    // The loads of a chain are independent of its elimination: they are requested kQ positions
+    // ahead (two alternating register sets of kQ), so their latency overlaps kQ eliminations.
+    constexpr int kQ = 8;
     double2 cp = make_double2(0.0, 0.0), dp = cp;
-    for (int j = 0; j < J; ++j) {
+    Pos q0[kQ], q1[kQ];
+#pragma unroll
+    for (int u = 0; u < kQ; ++u) q0[u] = fetch(u < J ? u : J - 1);
+    auto eliminate = [&](const Pos& cur, int j) {
         const int k = m + j, idx = idx0 + j;
         const double cn = k * (k + 1.0) * a.inv_a2;
-        const double2 e = a.lc[idx];
-        const bool zeta_pos = ((j & 1) == c);
-        const FI bt = rhs(k, idx, cn, e, zeta_pos);
         const double bk = k > 0 ? two_omega * m / (k * (k + 1.0)) : 0.0;
-        double2 D;
+        double2 D, rr;
         double Lo, Up;
-        double2 rr;
-        if (zeta_pos) {
+        if ((j & 1) == c) {
             D = make_double2(1.0, -alpha * bk);
-            Lo = two_omega * alpha * e.x;
-            Up = two_omega * alpha * e.y;
-            rr = bt.zeta;
+            Lo = two_omega * alpha * cur.e.x;
+            Up = two_omega * alpha * cur.e.y;
+            rr = cur.r;
         } else {
             D = make_double2(1.0 + alpha * alpha * a.phibar * cn, -alpha * bk);
-            Lo = -two_omega * alpha * e.x;
-            Up = -two_omega * alpha * e.y;
-            rr = cadd(bt.div, rmul(alpha * cn, bt.phi));
+            Lo = -two_omega * alpha * cur.e.x;
+            Up = -two_omega * alpha * cur.e.y;
+            rr = cadd(cur.r, rmul(alpha * cn, cur.bphi));
         }
         if (j == J - 1) Up = 0.0;                       // degree T + 1 is truncated
         const double2 den = j == 0 ? D : csub(D, rmul(Lo, cp));
@@ -163,18 +193,43 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
         dp = cmul(csub(rr, rmul(Lo, dp)), inv);
         sc[3 * (size_t)idx] = cp;
         sc[3 * (size_t)idx + 1] = dp;
-        sc[3 * (size_t)idx + 2] = bt.phi;
+        sc[3 * (size_t)idx + 2] = cur.bphi;
+    };
+    for (int j0 = 0; j0 < J; j0 += 2 * kQ) {
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) {                 // next set while this one is eliminated
+            const int jn = j0 + kQ + u;
+            q1[u] = fetch(jn < J ? jn : J - 1);
+        }
+#pragma unroll
+        for (int u = 0; u < kQ; ++u)
+            if (j0 + u < J) eliminate(q0[u], j0 + u);
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) {
+            const int jn = j0 + 2 * kQ + u;
+            q0[u] = fetch(jn < J ? jn : J - 1);
+        }
+#pragma unroll
+        for (int u = 0; u < kQ; ++u)
+            if (j0 + kQ + u < J) eliminate(q1[u], j0 + kQ + u);
     }
     // back substitution and output
-    double* out = a.uout + (size_t)b * a.out_member + (size_t)(a.mode == 0 && !a.last_only ? i : 0) * a.out_node;
+    double* __restrict__ out =
+        a.uout + (size_t)b * a.out_member + (size_t)(a.mode == 0 && !a.last_only ? i : 0) * a.out_node;
     const size_t S = (size_t)a.batch * a.M;
     const size_t cs = (size_t)b * a.M + i;                // synthesis-layout state of this node
     bool bad = false;
     double2 x = make_double2(0.0, 0.0);
-    for (int j = J - 1; j >= 0; --j) {
+    struct Back {
+        double2 cp, dp, bphi;
+    };
+    auto fetch_back = [&](int j) {
+        const size_t idx = (size_t)(idx0 + (j >= 0 ? j : 0));
+        return Back{sc[3 * idx], sc[3 * idx + 1], sc[3 * idx + 2]};
+    };
+    auto substitute = [&](const Back& bb, int j) {
         const int k = m + j, idx = idx0 + j;
-        const double2 cpj = sc[3 * (size_t)idx], dpj = sc[3 * (size_t)idx + 1];
-        x = csub(dpj, cmul(cpj, x));
+        x = csub(bb.dp, cmul(bb.cp, x));
         const bool zeta_pos = ((j & 1) == c);
         const int par = j & 1, kk = j >> 1;
         const double il = a.cml ? a.inv_lap[k] : 0.0;      // only the synthesis layout needs it
@@ -190,8 +245,7 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
             }
             bad = bad || !(isfinite(xv.x) && isfinite(xv.y));
         } else {
-            const double2 bphi = sc[3 * (size_t)idx + 2];
-            const double2 phi = csub(bphi, rmul(alpha * a.phibar, xv));
+            const double2 phi = csub(bb.bphi, rmul(alpha * a.phibar, xv));
             *(double2*)(out + 2 * fs + 2 * (size_t)idx) = xv;
             *(double2*)(out + 2 * (size_t)idx) = phi;
             if (a.cml) {
@@ -202,6 +256,21 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
             }
             bad = bad || !(isfinite(xv.x) && isfinite(xv.y) && isfinite(phi.x) && isfinite(phi.y));
         }
+    };
+    Back b0[kQ], b1[kQ];
+#pragma unroll
+    for (int u = 0; u < kQ; ++u) b0[u] = fetch_back(J - 1 - u);
+    for (int j0 = J - 1; j0 >= 0; j0 -= 2 * kQ) {
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) b1[u] = fetch_back(j0 - kQ - u);
+#pragma unroll
+        for (int u = 0; u < kQ; ++u)
+            if (j0 - u >= 0) substitute(b0[u], j0 - u);
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) b0[u] = fetch_back(j0 - 2 * kQ - u);
+#pragma unroll
+        for (int u = 0; u < kQ; ++u)
+            if (j0 - kQ - u >= 0) substitute(b1[u], j0 - kQ - u);
     }
     // padding rows of the synthesis layout: chain c clears those of parity c
     if (a.cml) {
@@ -213,6 +282,10 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
 
 void launch_solve_lc(const LcArgs& a, hipStream_t st) {
     const int nodes = a.mode == 0 ? (a.last_only ? 1 : a.M) : 1;
+    if (a.mode == 0) {
+        dim3 grid((a.ncoef + kBlock - 1) / kBlock, nodes * a.batch);
+        k_lc_rhs<<<grid, kBlock, 0, st>>>(a);
+    }
     const int n = (a.T + 1) * 2 * nodes * a.batch;
     k_solve_lc<<<(n + 63) / 64, 64, 0, st>>>(a);
 }

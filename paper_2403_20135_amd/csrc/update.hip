@@ -208,3 +208,16 @@ void launch_update_seq(const SeqArgs& a, hipStream_t st) {
     default: k_update_seq<8><<<grid, kBlock, 0, st>>>(a); break;
     }
 }
+
+// NaN fill (all bits set: NaN in FP64 and FP32) of n 32-bit words, for read-before-write checks.
+__global__ __launch_bounds__(kBlock) void k_poison(unsigned* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        p[i] = 0xFFFFFFFFu;
+}
+
+void launch_poison(void* p, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 4;
+    if (n == 0) return;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+    k_poison<<<blocks, kBlock, 0, st>>>(static_cast<unsigned*>(p), n);
+}

@@ -124,10 +124,16 @@ def test_mixed32_one_launch_per_phase_is_bitwise_the_branches(precision):
 
 
 def test_mixed32_one_launch_per_phase_matches_oracle():
-    """The 32-member ensemble in mode 1 over 6 steps; the first and last member of every truncation
-    against the oracle, <= 1e-11 relative L2."""
+    """The 32-member ensemble in mode 1 over 6 steps, with the merged launches' variants chosen by
+    the group autotuner (which restores the states it times on); the first and last member of
+    every truncation against the oracle, <= 1e-11 relative L2."""
     wl, handles, grp, u0, dts, cfgs = _mixed32_handles()
     xs = [_dev(u) for u in u0]
+    mode = grp.autotune(xs, dts, wl.M, wl.K, 2)
+    print(f"[gpu] mixed32 group autotune chose mode {mode}", flush=True)
+    for x, u in zip(xs, u0):
+        assert np.array_equal(_host(x), u)              # states restored
+    grp.set_mode(1)
     steps = 6
     for _ in range(steps):
         grp.step(xs, dts, wl.M, wl.K)

@@ -566,6 +566,91 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
     print(json.dumps(out))
 
 
+MFMA_PEAK_TFLOPS = {"F64": 78.6, "F32": 157.3, "BF16": 2500.0}
+
+
+def _kernel_key(name):
+    """A kernel's template name as rocprofv3 prints it, without the argument list."""
+    return name.split("(")[0].strip()
+
+
+def read_kernel_stats(stats_csv):
+    """Per kernel: calls and average duration [us] from a rocprofv3 --stats kernel summary."""
+    import csv
+    out = {}
+    for r in csv.DictReader(open(stats_csv)):
+        out[_kernel_key(r["Name"])] = {"calls": int(r["Calls"]), "avg_us": float(r["AverageNs"]) / 1e3,
+                                       "min_us": float(r["MinNs"]) / 1e3, "max_us": float(r["MaxNs"]) / 1e3,
+                                       "pct": float(r["Percentage"])}
+    return out
+
+
+def summarize_trace(stats_csv, out_md, title, command):
+    """Markdown table of a rocprofv3 --kernel-trace --stats summary (kernels above 0.5 % of the
+    GPU time)."""
+    st = read_kernel_stats(stats_csv)
+    lines = [f"# {title}", "", "Command (run from /tmp with TMPDIR=/tmp, repository at /root/repo):", "",
+             "```", command, "```", "",
+             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for k, v in sorted(st.items(), key=lambda kv: -kv[1]["pct"]):
+        if v["pct"] < 0.5:
+            continue
+        lines.append(f"| `{k}` | {v['calls']} | {v['avg_us']:.1f} | {v['min_us']:.1f} | {v['max_us']:.1f} | "
+                     f"{v['pct']:.1f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_mfma(counter_csv, stats_csv, out_md, title, command):
+    """MFMA evidence of the Legendre kernels from one rocprofv3 --pmc pass (SQ_INSTS_VALU_MFMA_*,
+    SQ_INSTS_VALU_MFMA_MOPS_* in units of 512 flops, SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE)
+    and the kernel-trace durations of the same command without counters.  Per kernel: MFMA
+    instructions and issued MFMA flops per dispatch, the issued rate over the traced average
+    duration against the peak of the instruction's type, and the MFMA-busy share of the SIMD
+    cycles, SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 32 CUs x 4 SIMDs x 8 XCDs):
+    GRBM_GUI_ACTIVE adds up the busy cycles of the 8 XCDs (a 35.8 us dispatch reads 7.6e5)."""
+    import csv
+    st = read_kernel_stats(stats_csv)
+    acc = {}
+    for r in csv.DictReader(open(counter_csv)):
+        k = _kernel_key(r["Kernel_Name"])
+        if not (k.startswith("void k_synthesis") or k.startswith("void k_analysis")):
+            continue
+        a = acc.setdefault(k, {"ids": set()})
+        a["ids"].add(r["Dispatch_Id"])
+        a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    lines = [f"# {title}", "", "Commands (run from /tmp with TMPDIR=/tmp, repository at /root/repo):", "",
+             "```", command, "```", "",
+             "Issued flops = SQ_INSTS_VALU_MFMA_MOPS_{F64,F32} x 512 per dispatch (padding columns and "
+             "rows included); rate = issued flops / the traced average duration; busy = "
+             "SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 256 CUs x 4 SIMDs), GRBM_GUI_ACTIVE being the "
+             "sum over the 8 XCDs. The useful (algorithmic) flops of the same launches are in the "
+             "bench line's kernels entries (tflops).", "",
+             "| kernel | dispatches | MFMA instr / dispatch | issued GFLOP / dispatch | avg us (trace) | "
+             "issued TFLOP/s | of MFMA peak | MFMA busy |", "|---|---|---|---|---|---|---|---|"]
+    summary = {}
+    for k, a in sorted(acc.items()):
+        n = len(a["ids"])
+        typ = "F64" if a.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) > 0 else "F32"
+        mops = a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{typ}", 0.0) / n
+        instr = a.get(f"SQ_INSTS_VALU_MFMA_{typ}", 0.0) / n
+        flop = mops * 512.0
+        busy = a.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / n
+        gui = a.get("GRBM_GUI_ACTIVE", 0.0) / n
+        util = busy / (gui / 8 * 256 * 4) if gui > 0 else float("nan")
+        t = st.get(k, {}).get("avg_us")
+        rate = flop / (t * 1e-6) / 1e12 if t else float("nan")
+        frac = rate / MFMA_PEAK_TFLOPS[typ]
+        summary[k] = {"dispatches": n, "type": typ, "mfma_instr": instr, "issued_flop": flop, "avg_us": t,
+                      "issued_tflops": rate, "of_peak": frac, "mfma_busy": util}
+        lines.append(f"| `{k}` | {n} | {instr:.0f} | {flop / 1e9:.3f} | "
+                     f"{t if t is not None else float('nan'):.1f} | {rate:.1f} | {frac:.3f} ({typ} "
+                     f"{MFMA_PEAK_TFLOPS[typ]}) | {util:.3f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return summary
+
+
 def host_cpu():
     """Model name and logical CPU count of the host the oracle runs on."""
     model = None
@@ -749,6 +834,12 @@ def main():
                          "(profiling runs that must launch the same kernels)")
     ap.add_argument("--plan1", default=None, metavar="TILES,DEPTH,ANA_DEPTH,INTERLEAVE[,FUSE,SREC,AREC]",
                     help="with --plan: the variants of the launches over one state per member")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="measure the FP64 and FP32 steps only (no integrators, work-precision "
+                         "study, equal-error check, ensemble or T511 runs): counter runs")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "OUT_MD", "TITLE", "COMMAND"))
+    ap.add_argument("--summarize-mfma", nargs=5,
+                    metavar=("COUNTER_CSV", "STATS_CSV", "OUT_MD", "TITLE", "COMMAND"))
     ap.add_argument("--summarize-pmc", nargs=6,
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB", "OUT", "FETCH_LOG", "WRITE_LOG"))
     args = ap.parse_args()
@@ -756,6 +847,12 @@ def main():
     if args.plan:
         FORCED_PLAN = tuple(int(v) for v in args.plan.split(","))
         FORCED_PLAN1 = tuple(int(v) for v in args.plan1.split(",")) if args.plan1 else None
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_mfma:
+        summarize_mfma(*args.summarize_mfma)
+        return
     if args.summarize_pmc:
         f, w, mib, outp, flog, wlog = args.summarize_pmc
         summarize_pmc(f, w, float(mib), outp, [flog, wlog])
@@ -805,7 +902,7 @@ def main():
     }
     if not args.no_fp32:
         r32 = measure(wl, "fp32", args.steps, args.warmup)
-        ee = equal_error(wl)
+        ee = None if args.no_extras else equal_error(wl)
         result["fp32"] = {
             "value": round(r32["steps_per_s"], 3), "unit": "steps/s",
             "dtype": "f32 Legendre contractions (FP32 MFMA, FP32 accumulation); f64 elsewhere",
@@ -819,10 +916,10 @@ def main():
             "legendre_plan": r32["plan"],
             "legendre_plan_one_state": r32["plan1"],
         }
-    if not args.no_fp32 and not args.no_work_precision and args.workload == "t255_m4k4":
+    if not args.no_fp32 and not args.no_work_precision and not args.no_extras and args.workload == "t255_m4k4":
         result["integrators"] = integrators(wl)
         result["work_precision"] = work_precision(wl)
-    if not args.no_fp32 and args.workload == "t255_m4k4":
+    if not args.no_fp32 and not args.no_extras and args.workload == "t255_m4k4":
         result["mixed32_m4k3"] = measure_mixed()
         big = W.WORKLOADS["t511_m4k4"]
         r511 = {p: measure(big, p, 20, 3, with_kernels=False) for p in ("fp64", "fp32")}

@@ -52,8 +52,11 @@ import workloads as W  # noqa: E402
 
 METRIC = "SDC steps/s (fwd, fwd+adjoint) at T255 M=4 vs plain FP64 GPU at equal error"
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-TABLE_BYTES = {"fp64": 8, "fp32": 4}
+# MFMA ceilings of the algorithmic contraction flops: FP64 and FP32 MFMA peaks; BF16x3 forms each
+# product from 8 BF16 slot products (16x16x32 for one 16x16x4 step), so its ceiling is the BF16
+# MFMA peak over 8
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 8}
+TABLE_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_t255_m4k4.json")
 
 
@@ -242,8 +245,8 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
 
 
 def equal_error(wl, steps=40, every=10):
-    """E_fp64, E_fp32 against the FP64 path at dt/8: max over output times of the relative L2
-    error (sphere norm) of vorticity."""
+    """E_fp64, E_fp32, E_bf16x3 against the FP64 path at dt/8: max over output times of the
+    relative L2 error (sphere norm) of vorticity."""
     import numpy as np
     import torch
     from paper_2403_20135_amd.api import SDC
@@ -270,7 +273,9 @@ def equal_error(wl, steps=40, every=10):
         return max(math.sqrt(np.sum(sm * (a - r) ** 2) / np.sum(sm * r ** 2)) for a, r in zip(h, ref))
 
     e64, e32 = err(history("fp64", mb.dt, steps, every)), err(history("fp32", mb.dt, steps, every))
+    e3 = err(history("bf16x3", mb.dt, steps, every))
     return {"E_fp64": e64, "E_fp32": e32, "ratio": e32 / e64, "equal": bool(e32 <= 1.1 * e64),
+            "E_bf16x3": e3, "ratio_bf16x3": e3 / e64, "equal_bf16x3": bool(e3 <= 1.1 * e64),
             "quantity": f"max over t = {every}..{steps} steps (every {every}) of rel. L2 of zeta",
             "reference": f"FP64 GPU path at dt/8 ({8 * steps} steps of {mb.dt / 8} s)"}
 
@@ -750,7 +755,7 @@ def oracle_errors(wl, refs):
     x0 = W.initial_state(wl)[None]
     dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
     out = {"metric": "relative L2 per field (sphere norm) against the FP64 oracle, max over members"}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         sdc = SDC(mb.T, mb.nlat, mb.nlon, wl.M, wl.K, 1, prec, W.RADIUS, W.GRAVITY, W.OMEGA,
                   W.MEAN_DEPTH)
         sdc.autotune(5)
@@ -915,6 +920,21 @@ def main():
             "kernels": r32["kernels"],
             "legendre_plan": r32["plan"],
             "legendre_plan_one_state": r32["plan1"],
+        }
+    if not args.no_fp32:
+        r3 = measure(wl, "bf16x3", args.steps, args.warmup)
+        result["bf16x3"] = {
+            "value": round(r3["steps_per_s"], 3), "unit": "steps/s",
+            "dtype": "bf16x3 Legendre contractions (FP32 operands split into three BF16 terms, BF16 MFMA "
+                     "products, FP32 accumulation); f64 elsewhere",
+            "ms_per_step": round(r3["ms_per_step"], 4),
+            "fwd_adj_steps_per_s": round(r3["fwd_adj_steps_per_s"], 3),
+            "fwd_adj_taped_steps_per_s": round(r3["fwd_adj_taped_steps_per_s"], 3),
+            "speedup_vs_fp64": round(r3["steps_per_s"] / r64["steps_per_s"], 4),
+            "fwd_adj_speedup_vs_fp64": round(r3["fwd_adj_steps_per_s"] / r64["fwd_adj_steps_per_s"], 4),
+            "kernels": r3["kernels"],
+            "legendre_plan": r3["plan"],
+            "legendre_plan_one_state": r3["plan1"],
         }
     if not args.no_fp32 and not args.no_work_precision and not args.no_extras and args.workload == "t255_m4k4":
         result["integrators"] = integrators(wl)

@@ -64,10 +64,12 @@ typedef enum {
     SDC_FP32_MFMA = 1,        /* FP32 MFMA (16x16x4) on FP32-rounded copies of the FP64 tables, the
                                  spectral / Fourier columns rounded to FP32 as they enter the MFMA,
                                  FP32 accumulation; every other step of sdc_step stays FP64 */
-    SDC_BF16X3_MFMA = 2       /* operands split into three BF16 terms each, BF16 MFMA products,
-                                 FP32 accumulation: not implemented, sdc_init returns SDC_EUNSUPPORTED
-                                 (one member at T255 is table-bandwidth-bound, where three BF16
-                                 terms move more bytes than one FP32 value) */
+    SDC_BF16X3_MFMA = 2       /* the FP32 mode's operands (FP32 tables and columns), each split
+                                 exactly into three BF16 terms on chip; every MFMA product is the
+                                 sum of the 8 cross terms but the smallest (a2 b2, below 2^-32 |ab|)
+                                 on BF16 MFMA (16x16x32), accumulated in FP32; every other step of
+                                 sdc_step stays FP64 (Section 3.2's transforms; the compensated
+                                 precision mode of the contractions) */
 } sdc_precision;
 
 typedef struct {

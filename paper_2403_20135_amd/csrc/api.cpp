@@ -208,7 +208,7 @@ struct sdc_ctx {
     long long bytes = 0, table_bytes = 0;
     double *mu = nullptr, *w = nullptr, *P = nullptr, *H = nullptr, *tau = nullptr, *Q = nullptr;
     double *rc = nullptr, *sect = nullptr;  // Legendre recurrence coefficients, sectoral values
-    float *P32 = nullptr, *H32 = nullptr;   // FP32 copies of the tables (precision SDC_FP32_MFMA)
+    float *P32 = nullptr, *H32 = nullptr;   // FP32 copies of the tables (FP32 and BF16x3 modes)
     double *inv_lap = nullptr, *neg_lap = nullptr;
     long long* toff = nullptr;
     int* rowoff = nullptr;
@@ -318,7 +318,13 @@ struct sdc_ctx {
         for (auto& v : ev_marks) v.clear();
     }
 
-    Tables tables() const { return Tables{P, H, P32, H32, rc, sect, mu, inv_lap}; }
+    Tables tables() const {
+        return Tables{P, H, P32, H32, cfg.precision == SDC_BF16X3_MFMA ? 1 : 0, rc, sect, mu, inv_lap};
+    }
+    // the Legendre operand type of the handle's kernels (kTabF64, kTabF32, kTabBf3)
+    int table_type() const {
+        return cfg.precision == SDC_BF16X3_MFMA ? kTabBf3 : (cfg.precision == SDC_FP32_MFMA ? kTabF32 : kTabF64);
+    }
 
     template <typename T>
     int alloc(T*& p, size_t count, bool table = false) {
@@ -370,8 +376,6 @@ int validate_config(const sdc_config* c) {
     FFTPlan pl;
     if (!make_fft_plan(c->nlon, pl) || !fft_length_supported(c->nlon))
         return fail(SDC_EUNSUPPORTED, "nlon=%d is not one of 16..2048 = 2^p or 24..1536 = 3*2^p", c->nlon);
-    if (c->precision == SDC_BF16X3_MFMA)
-        return fail(SDC_EUNSUPPORTED, "precision=%d (BF16x3) is not implemented by this library", c->precision);
     return SDC_OK;
 }
 
@@ -502,8 +506,8 @@ int setup(sdc_ctx* c) {
     launch_gauss(c->mu, c->w, g.nlat, c->st);
     launch_rec_coefs(c->rc, g, c->st);
     launch_legendre_tables(c->mu, c->rc, c->P, c->H, c->sect, c->toff, g, c->st);
-    if (cf.precision == SDC_FP32_MFMA) {
-        // FP32 copies of the FP64 tables for the Legendre contractions
+    if (cf.precision != SDC_FP64) {
+        // FP32 copies of the FP64 tables for the Legendre contractions (FP32 and BF16x3 modes)
         if ((rc = c->alloc(c->P32, tot, true))) return rc;
         if ((rc = c->alloc(c->H32, tot, true))) return rc;
         launch_round_tables(c->P, c->H, c->P32, c->H32, tot, c->st);
@@ -1801,6 +1805,7 @@ int group_capture_merged(sdc_group_s* g, double* const* states, const double* dt
             lead = h;
     const sdc_ctx* cl = g->members[lead];
     const bool fp32 = cl->P32 != nullptr;
+    const int tt = cl->table_type();
     int nlon_max = 0;
     for (const sdc_ctx* c : g->members) nlon_max = std::max(nlon_max, c->cfg.nlon);
     // host image of the descriptors
@@ -1875,11 +1880,11 @@ int group_capture_merged(sdc_group_s* g, double* const* states, const double* dt
     HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
     for (const Launch& L : launches) {
         if (L.kind == 0) {
-            launch_synthesis_multi(L.plan, fp32, L.state_in, reinterpret_cast<const SynArgs*>(d + L.syn), (int)n,
+            launch_synthesis_multi(L.plan, tt, L.state_in, reinterpret_cast<const SynArgs*>(d + L.syn), (int)n,
                                    L.syn_blocks, g->cap);
             launch_grid_multi(fp32, nlon_max, reinterpret_cast<const GridArgs*>(d + L.grid), (int)n, L.grid_blocks,
                               g->cap);
-            launch_analysis_multi(L.plan, fp32, reinterpret_cast<const AnaArgs*>(d + L.ana), (int)n, L.ana_blocks,
+            launch_analysis_multi(L.plan, tt, reinterpret_cast<const AnaArgs*>(d + L.ana), (int)n, L.ana_blocks,
                                   g->cap);
         } else {
             launch_update_multi(M, reinterpret_cast<const UpdArgsM*>(d + L.upd), (int)n, L.upd_blocks, g->cap);
@@ -1927,7 +1932,7 @@ int group_capture_branches(sdc_group_s* g, double* const* states, const double* 
 // (the states read in place), and keeps the fastest of each in g->plan / g->plan1.
 int group_tune_legendre(sdc_group_s* g, int M, int reps) {
     const size_t n = g->members.size();
-    const bool fp32 = g->members[0]->P32 != nullptr;
+    const int tt = g->members[0]->table_type();
     for (sdc_ctx* c : g->members) {         // finite operands in the workspaces
         HIP_TRY(hipMemsetAsync(c->cml, 0, (size_t)c->g.nrows * c->smax * kCmlVals * sizeof(double), g->st));
         HIP_TRY(hipMemsetAsync(c->G, 0, (size_t)(c->g.T + 1) * 2 * c->g.nhp * c->smax * kAnaStride * sizeof(double),
@@ -1978,7 +1983,7 @@ int group_tune_legendre(sdc_group_s* g, int M, int reps) {
             err = hipMemcpy(g->desc, sy.data(), n * sizeof(SynArgs), hipMemcpyHostToDevice);
             if (err != hipSuccess) break;
             const float ms = time_it([&] {
-                launch_synthesis_multi(lp, fp32, one != 0, static_cast<const SynArgs*>(g->desc), (int)n, fs, g->st);
+                launch_synthesis_multi(lp, tt, one != 0, static_cast<const SynArgs*>(g->desc), (int)n, fs, g->st);
             });
             if (ms < best_ms) {
                 best_ms = ms;
@@ -2007,7 +2012,7 @@ int group_tune_legendre(sdc_group_s* g, int M, int reps) {
             err = hipMemcpy(g->desc, an.data(), n * sizeof(AnaArgs), hipMemcpyHostToDevice);
             if (err != hipSuccess) break;
             const float ms = time_it([&] {
-                launch_analysis_multi(lp, fp32, static_cast<const AnaArgs*>(g->desc), (int)n, fa, g->st);
+                launch_analysis_multi(lp, tt, static_cast<const AnaArgs*>(g->desc), (int)n, fa, g->st);
             });
             if (ms < best_ms) {
                 best_ms = ms;

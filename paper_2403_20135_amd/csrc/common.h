@@ -187,12 +187,15 @@ void launch_degree_tables(int* n_of, int* m_of, double* inv_lap, double* neg_lap
 
 // legendre.hip
 // The Legendre tables of the SWE kernels: FP64, and FP32 copies when the handle computes its
-// Legendre contractions in FP32 (P32 != nullptr selects them).
+// Legendre contractions in FP32 or in BF16x3 (P32 != nullptr selects them; bf3 the BF16x3
+// products on the FP32 values).
+enum TableType { kTabF64 = 0, kTabF32 = 1, kTabBf3 = 2 };
 struct Tables {
     const double* P;
     const double* H;
     const float* P32;
     const float* H32;
+    int bf3;
     const double* rc;        // recurrence coefficients and sectoral values for the synthesis
     const double* sect;      // that regenerates the tables (LegPlan::syn_recur)
     const double* mu;
@@ -376,7 +379,7 @@ struct SynArgs {
 SynArgs make_syn_args(const Tables& tb, const long long* toff, const int* rowoff, const int2* tasks,
                       int ntasks, const double* cml, int nstates, double* four, const Geom& g,
                       const double* state_in);
-void launch_synthesis_multi(const LegPlan& plan, bool fp32, bool state_in, const SynArgs* list, int n,
+void launch_synthesis_multi(const LegPlan& plan, int tt, bool state_in, const SynArgs* list, int n,
                             int blocks, hipStream_t st);
 struct AnaArgs {
     const void* P;
@@ -399,7 +402,7 @@ struct AnaArgs {
 AnaArgs make_ana_args(const Tables& tb, const LegPlan& plan, const long long* toff, const int4* tasks,
                       int nwg, const double* G, int nstates, const double* neg_lap, double* out,
                       const Geom& g, const UpdateArgs* fuse, int fuse_mode);
-void launch_analysis_multi(const LegPlan& plan, bool fp32, const AnaArgs* list, int n, int blocks,
+void launch_analysis_multi(const LegPlan& plan, int tt, const AnaArgs* list, int n, int blocks,
                            hipStream_t st);
 struct GridArgs {
     const double2* four;

@@ -51,6 +51,51 @@ template <> struct Mma<float> {
     __device__ static constexpr int row(int r, int q) { return 4 * q + r; }
 };
 
+// BF16x3 mode: the tables and columns are the FP32 values of the FP32 mode (same storage), and
+// each MFMA product a b is formed on the BF16 matrix cores from an exact three-term split
+// x = x0 + x1 + x2 of both operands into BF16 values (x0 = x truncated to 8 significant bits,
+// x1 = the remainder truncated likewise, x2 = what is left, at most 8 significant bits, so the
+// sum is exact).  One v_mfma_f32_16x16x32_bf16 replaces one 16x16x4 FP32 step: the 8 BF16 slots
+// of lane (i, q) hold the split terms of the lane's single operand A[i][q] (resp. B[q][i]),
+// paired slot by slot so that the slot products are the 8 cross terms a_r b_s with r + s <= 3
+// (every one but a2 b2, below 2^-32 |a b|); both operands map (lane group, slot) to the same
+// k, so the instruction's sum over its 32 k is the 4-term contraction of the FP32 step with
+// the compensated products, accumulated in FP32.
+struct Bf3 {
+    float v;
+    Bf3() = default;
+    __device__ Bf3(double x) : v((float)x) {}
+    __device__ operator float() const { return v; }
+};
+static_assert(sizeof(Bf3) == sizeof(float), "BF16x3 operands are stored as FP32");
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+// high halves (the BF16 values) of x, of r1 = x - x0 and of r2 = r1 - x1
+__device__ __forceinline__ void split3(float x, unsigned& h0, unsigned& h1, unsigned& h2) {
+    const unsigned u0 = __float_as_uint(x);
+    const float r1 = x - __uint_as_float(u0 & 0xffff0000u);          // exact
+    const unsigned u1 = __float_as_uint(r1);
+    const float r2 = r1 - __uint_as_float(u1 & 0xffff0000u);         // exact, <= 8 bits
+    h0 = u0 >> 16;
+    h1 = u1 >> 16;
+    h2 = __float_as_uint(r2) >> 16;
+}
+template <> struct Mma<Bf3> {
+    typedef v4f vec;
+    __device__ static vec zero() { return (v4f){0.0f, 0.0f, 0.0f, 0.0f}; }
+    __device__ static vec mma(float a, float b, vec c) {
+        unsigned a0, a1, a2, b0, b1, b2;
+        split3(a, a0, a1, a2);
+        split3(b, b0, b1, b2);
+        // slots (low half first): A a0 a0 a1 a0 a1 a2 a1 a2, B b0 b1 b0 b2 b1 b0 b2 b1
+        const v4u A = (v4u){a0 | (a0 << 16), a1 | (a0 << 16), a1 | (a2 << 16), a1 | (a2 << 16)};
+        const v4u B = (v4u){b0 | (b1 << 16), b0 | (b2 << 16), b1 | (b0 << 16), b2 | (b1 << 16)};
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, A),
+                                                        __builtin_bit_cast(v8bf, B), c, 0, 0, 0);
+    }
+    __device__ static constexpr int row(int r, int q) { return 4 * q + r; }
+};
+
 // ---------------------------------------------------------------------------------------------
 // Synthesis (forward SWE and the transposed analysis of the adjoint).
 //
@@ -464,7 +509,11 @@ void launch_synthesis_swe(const Tables& tb, const LegPlan& plan, const long long
                           int nstates, double2* four, const Geom& g, hipStream_t st,
                           const double* state_in) {
     const dim3 grid(ntasks, (nstates + 3) / 4);
-    if (tb.P32)
+    if (tb.P32 && tb.bf3)
+        launch_synthesis_variant<kSynForward, Bf3>(plan, grid, st, tb, reinterpret_cast<const Bf3*>(tb.P32),
+                                                   reinterpret_cast<const Bf3*>(tb.H32), toff, rowoff,
+                                                   tasks, cml, nstates, (double*)four, g, state_in);
+    else if (tb.P32)
         launch_synthesis_variant<kSynForward, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, rowoff,
                                                      tasks, cml, nstates, (double*)four, g, state_in);
     else
@@ -495,7 +544,7 @@ SynArgs make_syn_args(const Tables& tb, const long long* toff, const int* rowoff
     return a;
 }
 
-void launch_synthesis_multi(const LegPlan& plan, bool fp32, bool state_in, const SynArgs* list, int n,
+void launch_synthesis_multi(const LegPlan& plan, int tt, bool state_in, const SynArgs* list, int n,
                             int blocks, hipStream_t st) {
 #define SYNM(TT, JT, D, REC, SIN) k_synthesis_multi<kSynForward, TT, JT, D, REC, SIN><<<blocks, kSynBlock, 0, st>>>(list, n)
 #define SYNM_PLAN(TT, SIN)                                                                        \
@@ -517,7 +566,10 @@ void launch_synthesis_multi(const LegPlan& plan, bool fp32, bool state_in, const
         else if (d == 4) SYNM(TT, 1, 4, false, SIN);                                              \
         else SYNM(TT, 1, 8, false, SIN);                                                          \
     } while (0)
-    if (fp32) {
+    if (tt == kTabBf3) {
+        if (state_in) SYNM_PLAN(Bf3, true);
+        else SYNM_PLAN(Bf3, false);
+    } else if (tt == kTabF32) {
         if (state_in) SYNM_PLAN(float, true);
         else SYNM_PLAN(float, false);
     } else {
@@ -532,7 +584,11 @@ void launch_synthesis_adj(const Tables& tb, const LegPlan& plan, const long long
                           const int* rowoff, const int2* tasks, int ntasks, const double* cml,
                           int nstates, double2* four5, const Geom& g, hipStream_t st) {
     const dim3 grid(ntasks, (nstates + 3) / 4);
-    if (tb.P32)
+    if (tb.P32 && tb.bf3)
+        launch_synthesis_variant<kSynAdjoint, Bf3>(plan, grid, st, tb, reinterpret_cast<const Bf3*>(tb.P32),
+                                                   reinterpret_cast<const Bf3*>(tb.H32), toff, rowoff,
+                                                   tasks, cml, nstates, (double*)four5, g, nullptr);
+    else if (tb.P32)
         launch_synthesis_variant<kSynAdjoint, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, rowoff,
                                                      tasks, cml, nstates, (double*)four5, g, nullptr);
     else
@@ -1048,7 +1104,7 @@ AnaArgs make_ana_args(const Tables& tb, const LegPlan& plan, const long long* to
     return a;
 }
 
-void launch_analysis_multi(const LegPlan& plan, bool fp32, const AnaArgs* list, int n, int blocks,
+void launch_analysis_multi(const LegPlan& plan, int tt, const AnaArgs* list, int n, int blocks,
                            hipStream_t st) {
 #define ANAM(TT, D, REC) k_analysis_multi<TT, D, REC><<<blocks, kBlock, 0, st>>>(list, n)
 #define ANAM_PLAN(TT)                                                                             \
@@ -1062,7 +1118,8 @@ void launch_analysis_multi(const LegPlan& plan, bool fp32, const AnaArgs* list, 
             ANAM(TT, 4, false);                                                                   \
         }                                                                                         \
     } while (0)
-    if (fp32) ANAM_PLAN(float);
+    if (tt == kTabBf3) ANAM_PLAN(Bf3);
+    else if (tt == kTabF32) ANAM_PLAN(float);
     else ANAM_PLAN(double);
 #undef ANAM_PLAN
 #undef ANAM
@@ -1102,7 +1159,11 @@ void launch_analysis_swe(const Tables& tb, const LegPlan& plan, const long long*
     const UpdateArgs& fu = fuse ? *fuse : none;
     const int mode = fuse ? fuse_mode : 0;
     const AdjFuse noadj{};
-    if (tb.P32)
+    if (tb.P32 && tb.bf3)
+        launch_analysis_variant<kAnaForward, Bf3>(plan, grid, st, tb, reinterpret_cast<const Bf3*>(tb.P32),
+                                                  reinterpret_cast<const Bf3*>(tb.H32), toff, tasks, nwg, G,
+                                                  nstates, neg_lap, out, g, fu, mode, noadj);
+    else if (tb.P32)
         launch_analysis_variant<kAnaForward, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, tasks, nwg, G,
                                                     nstates, neg_lap, out, g, fu, mode, noadj);
     else
@@ -1117,7 +1178,11 @@ void launch_analysis_adjoint(const Tables& tb, const LegPlan& plan, const long l
     const unsigned grid = xcd_grid(nwg, (nstates + 3) / 4);
     const AdjFuse none{};
     const AdjFuse& af = fuse ? *fuse : none;
-    if (tb.P32)
+    if (tb.P32 && tb.bf3)
+        launch_analysis_variant<kAnaAdjoint, Bf3>(plan, grid, st, tb, reinterpret_cast<const Bf3*>(tb.P32),
+                                                  reinterpret_cast<const Bf3*>(tb.H32), toff, tasks, nwg, G,
+                                                  nstates, inv_lap, out_acc, g, UpdateArgs{}, 0, af);
+    else if (tb.P32)
         launch_analysis_variant<kAnaAdjoint, float>(plan, grid, st, tb, tb.P32, tb.H32, toff, tasks, nwg, G,
                                                     nstates, inv_lap, out_acc, g, UpdateArgs{}, 0, af);
     else

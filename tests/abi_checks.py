@@ -33,7 +33,7 @@ INVALID_CONFIGS = [
     (dict(implicit_coriolis=2), _lib.SDC_EINVAL),
     (dict(nlon=100), _lib.SDC_EUNSUPPORTED),            # not 2^p or 3*2^p
     (dict(nlon=4096, T=31), _lib.SDC_EUNSUPPORTED),
-    (dict(precision=2), _lib.SDC_EUNSUPPORTED),         # BF16x3 not implemented
+    (dict(precision=-1), _lib.SDC_EINVAL),
 ]
 
 

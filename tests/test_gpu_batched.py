@@ -100,7 +100,7 @@ def _mixed32_handles(precision="fp64"):
     return wl, handles, SDCGroup(handles), u0, dts, cfgs
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_mixed32_one_launch_per_phase_is_bitwise_the_branches(precision):
     """Mode 1 (one synthesis, grid and analysis launch per sweep over all 32 members of three
     truncations) against mode 0 (one graph branch per truncation): the same states bit for bit,

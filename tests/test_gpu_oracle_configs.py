@@ -73,7 +73,7 @@ def test_t255_headline_adjoint_vs_oracle_vjp(t255):
     x = W.initial_state(W.WORKLOADS["t255_m4k4"])[None]
     lam = _lam(T, 255)
     ref = o.step_vjp(x[0], lam[0], dt, M, K)[None]
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         sdc = _sdc(T, mb.nlat, mb.nlon, M, K, 1, precision=prec)
         print(f"[gpu] T255 {prec} autotuned plan {sdc.autotune(5)}", flush=True)
         g = _dev(np.zeros_like(x))
@@ -98,12 +98,12 @@ def test_t255_headline_adjoint_vs_oracle_vjp(t255):
         sdc.close()
 
 
-def test_t255_fp32_steps_vs_oracle(t255):
+def test_t255_reduced_precision_steps_vs_oracle(t255):
     mb, o = t255
     T, M, K, dt, steps = mb.T, 4, 4, mb.dt, 3
     x0 = W.initial_state(W.WORKLOADS["t255_m4k4"])[None]
     ref = o.step(x0[0], dt, M, K, steps=steps)[None]
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         sdc = _sdc(T, mb.nlat, mb.nlon, M, K, 1, precision=prec)
         sdc.autotune(5)
         x = _dev(x0)
@@ -122,7 +122,7 @@ def test_t255_fp32_steps_vs_oracle(t255):
         sdc.close()
 
 
-def test_t127_jet_full_run_fp64_and_fp32():
+def test_t127_jet_full_run_fp64_fp32_bf16x3():
     wl = W.WORKLOADS["t127_m3k3_jet"]
     mb = wl.members[0]
     T = mb.T
@@ -134,7 +134,7 @@ def test_t127_jet_full_run_fp64_and_fp32():
     for k in range(0, wl.steps, every):
         u = o.step(u, mb.dt, wl.M, wl.K, steps=every)
         refs.append(u[None].copy())
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         sdc = _sdc(T, mb.nlat, mb.nlon, wl.M, wl.K, 1, precision=prec)
         x = _dev(x0)
         worst, worst_d = 0.0, 0.0
@@ -145,7 +145,7 @@ def test_t127_jet_full_run_fp64_and_fp32():
             e = max(rel_l2(got[:, k], ref[:, k], T) for k in range(3))
             ed = rel_l2(got - x0, ref - x0, T)
             worst, worst_d = max(worst, e), max(worst_d, ed)
-            if prec == "fp32":
+            if prec != "fp64":
                 assert ed <= 2 * (T + 1) * U32 * (i + 1) * every
         sdc.sync()
         print(f"[gpu] T127 jet {wl.steps} steps {prec}: max over output times of the rel L2 vs the "
@@ -155,7 +155,8 @@ def test_t127_jet_full_run_fp64_and_fp32():
         sdc.close()
 
 
-def test_t127_fp32_adjoint_vs_oracle_vjp():
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_t127_reduced_precision_adjoint_vs_oracle_vjp(prec):
     wl = W.WORKLOADS["t127_adjoint"]
     mb = wl.members[0]
     T = mb.T
@@ -163,12 +164,12 @@ def test_t127_fp32_adjoint_vs_oracle_vjp():
     x = W.initial_state(wl)[None]
     lam = _lam(T, 127)
     ref = o.step_vjp(x[0], lam[0], mb.dt, wl.M, wl.K)[None]
-    sdc = _sdc(T, mb.nlat, mb.nlon, wl.M, wl.K, 1, precision="fp32")
+    sdc = _sdc(T, mb.nlat, mb.nlon, wl.M, wl.K, 1, precision=prec)
     g = _dev(np.zeros_like(x))
     sdc.step_adjoint(_dev(x), _dev(lam), g, mb.dt)
     got = _host(g)
     err_fe = rel_l2(got - lam, ref - lam, T)
-    print(f"[gpu] T127 M=K=3 fp32 adjoint vs oracle VJP: f_E part rel L2 {err_fe:.3e} "
+    print(f"[gpu] T127 M=K=3 {prec} adjoint vs oracle VJP: f_E part rel L2 {err_fe:.3e} "
           f"(bar {2 * (T + 1) * U32 * wl.M * wl.K:.2e})", flush=True)
     assert err_fe <= 2 * (T + 1) * U32 * wl.M * wl.K
     sdc.close()

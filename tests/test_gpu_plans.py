@@ -38,7 +38,8 @@ def _outputs(sdc, x, lam, dt):
 
 
 @pytest.mark.parametrize("T,nlat,nlon,batch,prec", [(63, 96, 192, 2, "fp64"), (31, 48, 96, 3, "fp32"),
-                                                    (21, 34, 64, 1, "fp64"), (10, 12, 24, 2, "fp64")])
+                                                    (21, 34, 64, 1, "fp64"), (10, 12, 24, 2, "fp64"),
+                                                    (31, 48, 96, 2, "bf16x3")])
 def test_variants_agree_bitwise(T, nlat, nlon, batch, prec):
     sdc = _sdc(T, nlat, nlon, 3, 3, batch, precision=prec)
     x = _states(T, batch, 301)
@@ -59,7 +60,8 @@ SPLIT = [((2, 2, 2, 1), (4, 2, 2, 1, 1, 1, 1)), ((2, 2, 2, 1), (1, 8, 4, 0, 1, 1
          ((4, 2, 2, 1, 1, 1, 1), (2, 2, 4, 1)), ((6, 1, 4, 0), (2, 4, 2, 1, 1, 1, 1))]
 
 
-@pytest.mark.parametrize("T,nlat,nlon,batch,prec", [(63, 96, 192, 2, "fp64"), (31, 48, 96, 3, "fp32")])
+@pytest.mark.parametrize("T,nlat,nlon,batch,prec", [(63, 96, 192, 2, "fp64"), (31, 48, 96, 3, "fp32"),
+                                                    (21, 34, 64, 2, "bf16x3")])
 def test_split_plans_agree_bitwise(T, nlat, nlon, batch, prec):
     """Different variants for the launches over one state per member (the first f_E, eval_explicit,
     the adjoint's first stage; the first synthesis reading the states in place, also when it

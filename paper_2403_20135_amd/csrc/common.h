@@ -142,16 +142,17 @@ constexpr int kSynFields = 4;
 // m, state s): 10 complex values, the north + south ("s") and north - south ("a") sums of the
 // Fourier coefficients of the five grid products, weighted as g A, g B, g C, g D
 // (g = w / (a (1 - mu^2) nlon)) and w E / nlon, in the order
-//   Cs, Es, Da, As, Bs, Aa, Ba, Ca, Ea, Ds
+//   Es, Cs, Da, As, Bs, Aa, Ba, Ca, Ds, Ea
 // so that the seven columns of each parity of n - m are one contiguous window: values 0..6 for
 // even n - m (Pbar pairs with the symmetric sums, H with the antisymmetric ones), values 3..9 for
-// odd.  The factors -i m (A, C) and +i m (B) of the Pbar columns are applied to the contraction's
-// results.  Stored rounded to FP32 in the FP32 precision mode (what its MFMAs consume).  The
+// odd; the eight values of A..D (1..8) are contiguous as well, stored before E is transformed.
+// The factors -i m (A, C) and +i m (B) of the Pbar columns are applied to the contraction's
+// results.  Stored rounded to FP32 in the FP32 and BF16x3 modes (what their MFMAs consume).  The
 // latitude is outermost and the states of a latitude are adjacent, so the grid workgroups of one
 // latitude pair write one contiguous slab:
 //   G[fwd_index(T, S, jh, m, s) + 2 v + part]
 constexpr int kFwdVals = 10;
-enum FwdVal { kCs = 0, kEs, kDa, kAs, kBs, kAa, kBa, kCa, kEa, kDs };
+enum FwdVal { kEs = 0, kCs, kDa, kAs, kBs, kAa, kBa, kCa, kDs, kEa };
 __host__ __device__ inline size_t fwd_index(int T, int S, int jh, int m, int s) {
     return (((size_t)jh * (T + 1) + m) * S + s) * (2 * kFwdVals);
 }

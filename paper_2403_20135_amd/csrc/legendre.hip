@@ -710,7 +710,7 @@ __device__ __forceinline__ void analysis_body(
         if constexpr (fwd) {
             // chunk c: latitude c / 28 of the block, state cw / 7, window value cw % 7; the window
             // of parity p starts at value 3 p, and value v of it is column fwd_col[p][v]
-            constexpr int fwd_col[2][7] = {{3, 2, 6, 0, 1, 5, 4}, {5, 4, 0, 1, 3, 2, 6}};
+            constexpr int fwd_col[2][7] = {{2, 3, 6, 0, 1, 5, 4}, {5, 4, 0, 1, 3, 6, 2}};
             const int c = tid + kBlock * k;
             int lat = c / (2 * kAnaVals), cw = c % (2 * kAnaVals);
             const bool ok = c < kAnaChunks && cw < nsg * (kAnaVals / 2);

@@ -80,17 +80,24 @@ __device__ __forceinline__ void split3(float x, unsigned& h0, unsigned& h1, unsi
     h1 = u1 >> 16;
     h2 = __float_as_uint(r2) >> 16;
 }
+// slots (low half first): A a0 a0 a1 a0 a1 a2 a1 a2, B b0 b1 b0 b2 b1 b0 b2 b1
+__device__ __forceinline__ v4u bf3_a(float a) {
+    unsigned a0, a1, a2;
+    split3(a, a0, a1, a2);
+    return (v4u){a0 | (a0 << 16), a1 | (a0 << 16), a1 | (a2 << 16), a1 | (a2 << 16)};
+}
+__device__ __forceinline__ v4u bf3_b(float b) {
+    unsigned b0, b1, b2;
+    split3(b, b0, b1, b2);
+    return (v4u){b0 | (b1 << 16), b0 | (b2 << 16), b1 | (b0 << 16), b2 | (b1 << 16)};
+}
 template <> struct Mma<Bf3> {
     typedef v4f vec;
     __device__ static vec zero() { return (v4f){0.0f, 0.0f, 0.0f, 0.0f}; }
-    __device__ static vec mma(float a, float b, vec c) {
-        unsigned a0, a1, a2, b0, b1, b2;
-        split3(a, a0, a1, a2);
-        split3(b, b0, b1, b2);
-        // slots (low half first): A a0 a0 a1 a0 a1 a2 a1 a2, B b0 b1 b0 b2 b1 b0 b2 b1
-        const v4u A = (v4u){a0 | (a0 << 16), a1 | (a0 << 16), a1 | (a2 << 16), a1 | (a2 << 16)};
-        const v4u B = (v4u){b0 | (b1 << 16), b0 | (b2 << 16), b1 | (b0 << 16), b2 | (b1 << 16)};
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, A),
+    __device__ static vec mma(float a, float b, vec c) { return mma_pre(a, bf3_b(b), c); }
+    // with the B operand's slots already formed (the analysis stages them once per workgroup)
+    __device__ static vec mma_pre(float a, v4u B, vec c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, bf3_a(a)),
                                                         __builtin_bit_cast(v8bf, B), c, 0, 0, 0);
     }
     __device__ static constexpr int row(int r, int q) { return 4 * q + r; }
@@ -652,7 +659,10 @@ __device__ __forceinline__ void analysis_body(
     const double* __restrict__ mu, const AdjFuse& af, int w) {
     using MM = Mma<TT>;
     using vec = typename MM::vec;
-    __shared__ __align__(16) double gl[2][kAnaBuf + 4];       // + a dummy slot for idle threads
+    // BF16x3: each column value is staged as its 8 BF16 B-operand slots (16 bytes), formed once
+    // per workgroup instead of once per wave and k-step
+    constexpr bool bf3 = std::is_same<TT, Bf3>::value;
+    __shared__ __align__(16) double gl[2][(kAnaBuf + 4) * (bf3 ? 2 : 1)];   // + a dummy slot for idle threads
     __shared__ __align__(16) double tr[REC ? 4 * kAnaTr : 2];  // REC transposes, one area per wave
     const int2 tg = xcd_task_group(w, ntasks, (nstates + 3) >> 2, interleave);
     if (tg.x >= ntasks) return;
@@ -756,7 +766,19 @@ __device__ __forceinline__ void analysis_body(
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const bool live = 16 * b + clat[k] < g.nh;
-            if constexpr (g64) {
+            if constexpr (bf3) {
+                v4u* gv = reinterpret_cast<v4u*>(gl[buf]);
+                const v4u z = (v4u){0u, 0u, 0u, 0u};
+                if constexpr (fwd) {
+                    gv[cdst[k]] = live ? bf3_b(r[k].x) : z;
+                    gv[cdst[k] + 1] = live ? bf3_b(r[k].y) : z;
+                } else {
+                    gv[cdst[k]] = live ? bf3_b(r[k].x) : z;
+                    gv[cdst[k] + 1] = live ? bf3_b(r[k].y) : z;
+                    gv[cdst2[k]] = live ? bf3_b(r[k].z) : z;
+                    gv[cdst2[k] + 1] = live ? bf3_b(r[k].w) : z;
+                }
+            } else if constexpr (g64) {
                 *(double2*)&gl[buf][cdst[k]] = live ? r[k] : make_double2(0.0, 0.0);
             } else if constexpr (fwd) {
                 const double2 v2 = make_double2((double)r[k].x, (double)r[k].y);
@@ -818,11 +840,20 @@ __device__ __forceinline__ void analysis_body(
     auto contract = [&](const vec& aP, const vec& aH, const double* lb) {
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
-            const double* lq = lb + (4 * q + qq) * kAnaLat;
+            if constexpr (bf3) {
+                const v4u* lq = reinterpret_cast<const v4u*>(lb) + (4 * q + qq) * kAnaLat;
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                accP[t] = MM::mma(aP[qq], (TT)lq[offP[t]], accP[t]);
-                accH[t] = MM::mma(aH[qq], (TT)lq[offH[t]], accH[t]);   // dropped for kinds without H
+                for (int t = 0; t < 2; ++t) {
+                    accP[t] = MM::mma_pre(aP[qq], lq[offP[t]], accP[t]);
+                    accH[t] = MM::mma_pre(aH[qq], lq[offH[t]], accH[t]);
+                }
+            } else {
+                const double* lq = lb + (4 * q + qq) * kAnaLat;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    accP[t] = MM::mma(aP[qq], (TT)lq[offP[t]], accP[t]);
+                    accH[t] = MM::mma(aH[qq], (TT)lq[offH[t]], accH[t]);   // dropped for kinds without H
+                }
             }
         }
     };

@@ -633,7 +633,7 @@ def summarize_mfma(counter_csv, stats_csv, out_md, title, command):
         a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     lines = [f"# {title}", "", "Commands (run from /tmp with TMPDIR=/tmp, repository at /root/repo):", "",
              "```", command, "```", "",
-             "Issued flops = SQ_INSTS_VALU_MFMA_MOPS_{F64,F32} x 512 per dispatch (padding columns and "
+             "Issued flops = SQ_INSTS_VALU_MFMA_MOPS_{F64,F32,BF16} x 512 per dispatch (padding columns and "
              "rows included); rate = issued flops / the traced average duration; busy = "
              "SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 256 CUs x 4 SIMDs), GRBM_GUI_ACTIVE being the "
              "sum over the 8 XCDs. The useful (algorithmic) flops of the same launches are in the "
@@ -643,7 +643,7 @@ def summarize_mfma(counter_csv, stats_csv, out_md, title, command):
     summary = {}
     for k, a in sorted(acc.items()):
         n = len(a["ids"])
-        typ = "F64" if a.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) > 0 else "F32"
+        typ = next((t for t in ("F64", "F32", "BF16") if a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{t}", 0.0) > 0), "F32")
         mops = a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{typ}", 0.0) / n
         instr = a.get(f"SQ_INSTS_VALU_MFMA_{typ}", 0.0) / n
         flop = mops * 512.0
@@ -658,6 +658,53 @@ def summarize_mfma(counter_csv, stats_csv, out_md, title, command):
         lines.append(f"| `{k}` | {n} | {instr:.0f} | {flop / 1e9:.3f} | "
                      f"{t if t is not None else float('nan'):.1f} | {rate:.1f} | {frac:.3f} ({typ} "
                      f"{MFMA_PEAK_TFLOPS[typ]}) | {util:.3f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return summary
+
+
+def summarize_counters(counter_csv, stats_csv, out_md, title, command, prefixes):
+    """Per-dispatch averages of every counter of one rocprofv3 --pmc pass for the kernels whose
+    template names start with one of the comma-separated prefixes, with the traced average
+    duration and derived shares: VALU instructions per wave, SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES
+    (the share of a wave's life issuing VALU), SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES and
+    SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE."""
+    import csv
+    st = read_kernel_stats(stats_csv)
+    pre = [p.strip() for p in prefixes.split(",")]
+    acc = {}
+    for r in csv.DictReader(open(counter_csv)):
+        k = _kernel_key(r["Kernel_Name"])
+        if not any(k.startswith(p) for p in pre):
+            continue
+        grid = int(r["Grid_Size"])
+        a = acc.setdefault((k, grid), {"ids": set()})
+        a["ids"].add(r["Dispatch_Id"])
+        a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    counters = sorted({c for a in acc.values() for c in a if c != "ids"})
+    lines = [f"# {title}", "", "Commands (run from /tmp with TMPDIR=/tmp, repository at /root/repo):", "",
+             "```", command, "```", "",
+             "Per dispatch (mean over the dispatches of one kernel and grid size); avg us from the "
+             "kernel trace of the same kernel over all its grid sizes.", "",
+             "| kernel | grid (threads) | dispatches | avg us | " + " | ".join(counters)
+             + " | VALU / wave | VALU-issue share | wait share | LDS conflict share |",
+             "|" + "---|" * (len(counters) + 8)]
+    summary = {}
+    for (k, grid), a in sorted(acc.items()):
+        n = len(a["ids"])
+        v = {c: a.get(c, 0.0) / n for c in counters}
+        waves = v.get("SQ_WAVES", 0.0)
+        cyc = v.get("SQ_WAVE_CYCLES", 0.0)
+        d = {"valu_per_wave": v.get("SQ_INSTS_VALU", 0.0) / waves if waves else float("nan"),
+             "valu_issue_share": v.get("SQ_ACTIVE_INST_VALU", 0.0) / cyc if cyc else float("nan"),
+             "wait_share": v.get("SQ_WAIT_INST_ANY", 0.0) / cyc if cyc else float("nan"),
+             "lds_conflict_share": (v.get("SQ_LDS_BANK_CONFLICT", 0.0) / v["SQ_LDS_IDX_ACTIVE"]
+                                    if v.get("SQ_LDS_IDX_ACTIVE") else float("nan"))}
+        t = st.get(k, {}).get("avg_us", float("nan"))
+        summary[f"{k} [{grid}]"] = {"dispatches": n, "avg_us": t, **v, **d}
+        lines.append(f"| `{k}` | {grid} | {n} | {t:.1f} | " + " | ".join(f"{v[c]:.4g}" for c in counters)
+                     + f" | {d['valu_per_wave']:.0f} | {d['valu_issue_share']:.3f} | {d['wait_share']:.3f} | "
+                       f"{d['lds_conflict_share']:.3f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
     return summary
@@ -852,6 +899,8 @@ def main():
     ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "OUT_MD", "TITLE", "COMMAND"))
     ap.add_argument("--summarize-mfma", nargs=5,
                     metavar=("COUNTER_CSV", "STATS_CSV", "OUT_MD", "TITLE", "COMMAND"))
+    ap.add_argument("--summarize-counters", nargs=6,
+                    metavar=("COUNTER_CSV", "STATS_CSV", "OUT_MD", "TITLE", "COMMAND", "KERNEL_PREFIXES"))
     ap.add_argument("--summarize-pmc", nargs=6,
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB", "OUT", "FETCH_LOG", "WRITE_LOG"))
     args = ap.parse_args()
@@ -864,6 +913,9 @@ def main():
         return
     if args.summarize_mfma:
         summarize_mfma(*args.summarize_mfma)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
         return
     if args.summarize_pmc:
         f, w, mib, outp, flog, wlog = args.summarize_pmc

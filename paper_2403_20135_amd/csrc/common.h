@@ -145,7 +145,7 @@ constexpr int kSynFields = 4;
 //   Es, Cs, Da, As, Bs, Aa, Ba, Ca, Ds, Ea
 // so that the seven columns of each parity of n - m are one contiguous window: values 0..6 for
 // even n - m (Pbar pairs with the symmetric sums, H with the antisymmetric ones), values 3..9 for
-// odd; the eight values of A..D (1..8) are contiguous as well, stored before E is transformed.
+// odd.
 // The factors -i m (A, C) and +i m (B) of the Pbar columns are applied to the contraction's
 // results.  Stored rounded to FP32 in the FP32 and BF16x3 modes (what their MFMAs consume).  The
 // latitude is outermost and the states of a latitude are adjacent, so the grid workgroups of one

@@ -288,50 +288,6 @@ __device__ __forceinline__ void fft_wave(double2* buf, const WaveTw<N>& w, int l
     fft_wave_stages<N, 0, 1, INV>(buf, w, lane);
 }
 
-// Inverse transform of the packed spectrum of one latitude pair (pack_pair of the Fourier rows xn
-// and ys) by the calling wave, its first stage reading the spectrum from global memory: the loads
-// of the stage's butterflies are issued together, inputs past the truncation (T < k < N - T) are
-// zero and not loaded, and the first stage needs no twiddles, so the spectrum never passes
-// through LDS before the first butterflies.
-template <int N>
-__device__ __forceinline__ void fft_wave_spectrum(double2* buf, const WaveTw<N>& w, int lane,
-                                                  const double2* __restrict__ xn,
-                                                  const double2* __restrict__ ys, int T) {
-    constexpr int R = fft_radix(N, 0), nb = N / R;
-    constexpr int MAXT = (nb + 63) / 64;
-    double2 v[MAXT][R];
-#pragma unroll
-    for (int tt = 0; tt < MAXT; ++tt) {
-        const int j = lane + 64 * tt;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int k = j + r * nb;
-            double2 z = make_double2(0.0, 0.0);
-            if (j < nb) {
-                if (k <= T) {
-                    const double2 X = xn[k], Y = ys[k];
-                    z = k == 0 ? make_double2(X.x, Y.x) : make_double2(X.x - Y.y, X.y + Y.x);
-                } else if (k >= N - T) {
-                    const double2 X = xn[N - k], Y = ys[N - k];
-                    z = make_double2(X.x + Y.y, -X.y + Y.x);
-                }
-            }
-            v[tt][r] = z;
-        }
-    }
-#pragma unroll
-    for (int tt = 0; tt < MAXT; ++tt) {
-        const int j = lane + 64 * tt;
-        if (j < nb) {
-            dft_small<R>(v[tt], true);
-#pragma unroll
-            for (int r = 0; r < R; ++r) buf[j * R + r] = v[tt][r];
-        }
-    }
-    wave_lds_sync();
-    fft_wave_stages<N, 1, R, true>(buf, w, lane);
-}
-
 constexpr int kGridBlock = 256;               // four waves: one per LDS signal
 constexpr int kGridSignals = 4;                 // LDS signal buffers of the grid kernels
 
@@ -527,8 +483,9 @@ template <> struct Row<float> {
 // signals is transformed by one wave; only the hand-offs between phases are workgroup barriers.
 // LDS holds four signals (three workgroups fit a CU), and every thread loads the first twiddles
 // of its butterflies once, ahead of their use: the fifth product E waits in registers while A..D are
-// transformed and their values stored, then reuses buffer 0 and is transformed by the whole
-// workgroup.
+// transformed, then reuses buffer 0 (A's contributions to the lines wait in registers) and is
+// transformed by the whole workgroup; each analysis-input line (10 complex values) is then
+// written whole by one thread.
 // ---------------------------------------------------------------------------------------------
 template <int N, typename GT>
 __device__ __forceinline__ void grid_swe_body(
@@ -549,9 +506,9 @@ __device__ __forceinline__ void grid_swe_body(
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WaveTw<N> twl;
     wave_tw_load<N, 0, 1>(twl, tw, lane);
-    if (wave < kSynFields)
-        fft_wave_spectrum<N>(buf + wave * N, twl, lane, fs + wave * fstride + (size_t)jN * g.ms,
-                             fs + wave * fstride + (size_t)jS * g.ms, T);
+    stage_inputs<N, kSynFields>(buf, fs, fstride, jN, jS, T, g.ms);
+    __syncthreads();
+    if (wave < kSynFields) fft_wave<N, true>(buf + wave * N, twl, lane);
     __syncthreads();
     if (save) {      // grid values of zeta, Phi', U, V (north, south) for the adjoint
         for (int f = 0; f < kSynFields; ++f)
@@ -583,10 +540,23 @@ __device__ __forceinline__ void grid_swe_body(
     const double wt = w[jN];
     const double gg = wt / (g.radius * (1.0 - x) * (1.0 + x)) * invN;
     const double we = wt * invN;
-    // Analysis input lines (fwd_index): the weighted north +- south sums of A..E.  The eight A..D
-    // values of every line (contiguous, values 1..8) are stored before E is transformed, so that
-    // those stores drain while the workgroup transforms E; E's two values (0 and 9) follow.
-    for (int m = threadIdx.x; m <= T; m += kGridBlock) {
+    // Analysis input lines (fwd_index): the weighted north +- south sums of A..E, each line
+    // written whole by one thread in its value order once E is transformed (a line left half
+    // written while E is transformed can leave L2 partial and cost a read-back).  Buffer 0 (A) is
+    // needed for E, so A's two values of this thread's first MP orders wait in registers; lines of
+    // higher orders (grids with T + 1 > nlon / 3) are written in two parts.
+    constexpr int MP = (N + 3 * kGridBlock - 1) / (3 * kGridBlock);
+    double2 areg[MP][2];
+#pragma unroll
+    for (int mp = 0; mp < MP; ++mp) {
+        const int m = threadIdx.x + mp * kGridBlock;
+        if (m > T) continue;
+        double2 AN, AS;
+        unpack_pair(buf, m, N, AN, AS);
+        areg[mp][0] = cscale(gg, cadd(AN, AS));
+        areg[mp][1] = cscale(gg, csub(AN, AS));
+    }
+    for (int m = threadIdx.x + MP * kGridBlock; m <= T; m += kGridBlock) {
         double2 AN, AS, BN, BS, CN, CS, DN, DS;
         unpack_pair(buf, m, N, AN, AS);
         unpack_pair(buf + N, m, N, BN, BS);
@@ -611,7 +581,28 @@ __device__ __forceinline__ void grid_swe_body(
     }
     __syncthreads();
     fft_block<N, false>(buf, twb);
-    for (int m = threadIdx.x; m <= T; m += kGridBlock) {
+#pragma unroll
+    for (int mp = 0; mp < MP; ++mp) {
+        const int m = threadIdx.x + mp * kGridBlock;
+        if (m > T) continue;
+        double2 BN, BS, CN, CS, DN, DS, EN, ES;
+        unpack_pair(buf + N, m, N, BN, BS);
+        unpack_pair(buf + 2 * N, m, N, CN, CS);
+        unpack_pair(buf + 3 * N, m, N, DN, DS);
+        unpack_pair(buf, m, N, EN, ES);
+        const Row<GT> o(G, fwd_index(T, nstates, jh, m, s));
+        o.put(kEs, cscale(we, cadd(EN, ES)));
+        o.put(kCs, cscale(gg, cadd(CN, CS)));
+        o.put(kDa, cscale(gg, csub(DN, DS)));
+        o.put(kAs, areg[mp][0]);
+        o.put(kBs, cscale(gg, cadd(BN, BS)));
+        o.put(kAa, areg[mp][1]);
+        o.put(kBa, cscale(gg, csub(BN, BS)));
+        o.put(kCa, cscale(gg, csub(CN, CS)));
+        o.put(kDs, cscale(gg, cadd(DN, DS)));
+        o.put(kEa, cscale(we, csub(EN, ES)));
+    }
+    for (int m = threadIdx.x + MP * kGridBlock; m <= T; m += kGridBlock) {
         double2 EN, ES;
         unpack_pair(buf, m, N, EN, ES);
         const Row<GT> o(G, fwd_index(T, nstates, jh, m, s));
@@ -731,9 +722,9 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(
         ereg[kk] = buf[k < N ? k : 0];
     }
     __syncthreads();
-    if (wave < 4)
-        fft_wave_spectrum<N>(buf + wave * N, twl, lane, fs + wave * fstride + (size_t)jN * g.ms,
-                             fs + wave * fstride + (size_t)jS * g.ms, T);
+    stage_inputs<N, 4>(buf, fs, fstride, jN, jS, T, g.ms);
+    __syncthreads();
+    if (wave < 4) fft_wave<N, true>(buf + wave * N, twl, lane);
     __syncthreads();
     const double x = mu[jN];
     const double fN = two_omega * x, fS = -fN;

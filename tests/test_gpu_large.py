@@ -139,3 +139,44 @@ def test_t511_regenerated_tables_are_bitwise_the_streamed_ones():
                   f"{np.max(np.abs(u - v)):.3e}", flush=True)
             assert np.array_equal(u, v), (prec, name)
         sdc.close()
+
+
+def test_t511_full_run_properties():
+    """The T511 workload over its full 200 steps (the oracle's T511 step takes too long for that
+    many), FP64 and FP32, eager and graph-replayed, by what holds at any length: every value
+    finite, the global mean of Phi' (the (0,0) coefficient: the tendencies of both sides vanish
+    there) unchanged to rounding, the FP32 run within 2 (T+1) u_32 per step of the FP64 run on the
+    state change, and the balanced jet still a fixed point after 200 steps."""
+    wl = W.WORKLOADS["t511_m4k4"]
+    x0 = W.initial_state(wl)[None]
+    steps = wl.steps
+    out = {}
+    for prec in ("fp64", "fp32"):
+        sdc = _sdc(T, NLAT, NLON, M, K, 1, precision=prec)
+        x = _dev(x0)
+        for _ in range(steps):
+            sdc.step_graph(x, DT)
+        sdc.sync()
+        out[prec] = _host(x)
+        sdc.close()
+    x64, x32 = out["fp64"], out["fp32"]
+    assert np.all(np.isfinite(x64)) and np.all(np.isfinite(x32))
+    phi_scale = float(np.max(np.abs(x0[0, W.FIELD_PHI])))
+    d00 = abs(x64[0, W.FIELD_PHI, 0, 0] - x0[0, W.FIELD_PHI, 0, 0])
+    e32 = rel_l2(x32 - x0, x64 - x0, T)
+    sdc = _sdc(T, NLAT, NLON, M, K, 1)
+    jet = W.balanced_jet(T, 20.0)[None]
+    xj = _dev(jet)
+    for _ in range(steps):
+        sdc.step_graph(xj, DT)
+    sdc.sync()
+    jh = _host(xj)
+    e_jet = max(float(np.max(np.abs(jh[0, f] - jet[0, f])) /
+                      np.max(np.abs(jet[0, W.FIELD_ZETA if f == W.FIELD_DIV else f]))) for f in range(3))
+    sdc.close()
+    bar32 = 2 * (T + 1) * 2.0 ** -24 * steps
+    print(f"[gpu] T511 {steps} steps: |dPhi'_00| {d00:.2e} (Phi' scale {phi_scale:.2e}), FP32 vs FP64 on the "
+          f"state change {e32:.3e} (bar {bar32:.2e}), jet after {steps} steps {e_jet:.3e}", flush=True)
+    assert d00 <= 1e-13 * phi_scale
+    assert e32 <= bar32
+    assert e_jet <= 1e-11

@@ -392,6 +392,16 @@ def work_precision(wl, t_end=86400.0, out_every=21600.0):
         sdc.sync()
         return n, secs, outs
 
+    # dSDC against itself at a small step: the observed order per halving of dt shows where the
+    # asymptotic order K begins (stiff gravity waves: omega dt < 1 below ~80 s at T255)
+    _, _, ref_self = run("dSDC", 3.75)
+    conv = []
+    for dt in (480.0, 240.0, 120.0, 60.0, 30.0, 15.0):
+        _, _, outs = run("dSDC", dt)
+        d = outs - ref_self
+        conv.append({"dt": dt, "error": float(torch.sqrt(0.5 * (sm * d * d).sum(dim=(-2, -1))).max())})
+    for a, b in zip(conv, conv[1:]):
+        b["order_vs_previous"] = round(math.log(a["error"] / b["error"]) / math.log(a["dt"] / b["dt"]), 2)
     _, _, ref = run("IMEX-o2", 1.5)
     rows = []
     for method, dts in (("dSDC", (450.0, 360.0, 240.0, 180.0, 120.0, 60.0)),
@@ -408,7 +418,8 @@ def work_precision(wl, t_end=86400.0, out_every=21600.0):
             "t_end_s": t_end, "output_every_s": out_every, "M": wl.M, "K": wl.K,
             "precision": "fp64", "reference": "IMEX-o2 at dt = 1.5 s",
             "error": "max over output times of the area-weighted RMS of the vorticity difference [1/s]",
-            "legendre_plan": plan, "rows": rows, "speedup_at_equal_error": speed}
+            "legendre_plan": plan, "rows": rows, "speedup_at_equal_error": speed,
+            "dSDC_self_convergence": {"reference": "dSDC at dt = 3.75 s", "rows": conv}}
 
 
 def integrators(wl, steps=100, warmup=3):

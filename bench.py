@@ -884,6 +884,24 @@ def oracle_errors(wl, refs):
     return out
 
 
+# The paper's own single-node CPU results, context only (other hardware, the Galewsky workload,
+# unstated precision): SWEET on one JUSUF node (Section 5.3; s/DoF/step converted to steps/s at the
+# stated DoF counts) and ICON-O on one JUWELS node (Section 5.2); the model speedup of Section 4.7.
+PAPER_CONTEXT = {
+    "note": "CPU results of the paper, not targets: Galewsky test case, dSDC M=4 K=4 MIN-SR-FLEX",
+    "SWEET_JUSUF": {
+        "node": "2x AMD EPYC 7742 (128 cores, 2.25 GHz)",
+        "dofs_256^2_(~T255)": {"dSDC_PinT_best_steps_per_s": 16.3, "dSDC_space_only_best": 12.2,
+                                "dSDC_1_thread": 1.15, "IMEX_o2_best": 99.1, "PinT_speedup_4_threads": 2.60},
+        "dofs_512^2_(~T511)": {"dSDC_PinT_best_steps_per_s": 4.0, "dSDC_space_only_best": 4.13,
+                                "dSDC_1_thread": 0.189, "IMEX_o2_best": 34.9, "PinT_speedup_4_threads": 2.90},
+    },
+    "ICON-O_JUWELS": {"node": "2x Intel Xeon Platinum 8168 (48 cores, 2.7 GHz)",
+                      "PinT_speedup_4_threads": 3.37, "model_S": 3.39},
+    "model_S_SWEET": 3.25,
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -974,6 +992,7 @@ def main():
         "kernels": kernels,
         "legendre_plan": r64["plan"],
         "legendre_plan_one_state": r64["plan1"],
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_fp32:
         r32 = measure(wl, "fp32", args.steps, args.warmup)

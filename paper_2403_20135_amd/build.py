@@ -71,8 +71,8 @@ def build_host_sanitized() -> str:
     preloads the sanitizer runtime (sanitizer_runtime())."""
     out_dir = os.path.join(BUILD, "asan")
     os.makedirs(out_dir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+
+    def one(src):
         if src == "api.cpp":
             obj = os.path.join(out_dir, "api.o")
             cmd = [hipcc(), "-x", "hip", *compile_flags(), "-O1", "-g", *HOST_SANITIZE, "-c",
@@ -80,11 +80,12 @@ def build_host_sanitized() -> str:
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
                 raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
-        else:
-            obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-            if not os.path.exists(obj):
-                _compile(src, [])
-        objs.append(obj)
+            return obj
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        return obj if os.path.exists(obj) else _compile(src, [])
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(one, SOURCES))
     lib = os.path.join(out_dir, "libsdc_asan.so")
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *HOST_SANITIZE, "-o", lib, *objs, *LINK_LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -810,9 +810,9 @@ def cpu_baseline(wl, state0, budget_s=15.0):
 
 def oracle_errors(wl, refs):
     """Error against the FP64 oracle (references from the CPU-baseline leg) of every result the
-    line reports: the headline step in FP64 and FP32 after 1 and 1 + n steps, one adjoint step of
+    line reports: the headline step in FP64, FP32 and BF16x3 after 1 and 1 + n steps, one adjoint step of
     each precision, the first member of each truncation of the mixed ensemble after 2 group steps,
-    and one T511 step in FP64 and FP32.  Relative L2 per field (sphere norm), max over members."""
+    and one T511 step in FP64, FP32 and BF16x3.  Relative L2 per field (sphere norm), max over members."""
     import numpy as np
     import torch
     from paper_2403_20135_amd.api import SDC, SDCGroup
@@ -864,7 +864,7 @@ def oracle_errors(wl, refs):
 
     big = W.WORKLOADS["t511_m4k4"]
     bm = big.members[0]
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         sdc = SDC(bm.T, bm.nlat, bm.nlon, big.M, big.K, 1, prec, W.RADIUS, W.GRAVITY, W.OMEGA,
                   W.MEAN_DEPTH)
         sdc.autotune(3)
@@ -1031,7 +1031,7 @@ def main():
     if not args.no_fp32 and not args.no_extras and args.workload == "t255_m4k4":
         result["mixed32_m4k3"] = measure_mixed()
         big = W.WORKLOADS["t511_m4k4"]
-        r511 = {p: measure(big, p, 20, 3, with_kernels=False) for p in ("fp64", "fp32")}
+        r511 = {p: measure(big, p, 20, 3, with_kernels=False) for p in ("fp64", "fp32", "bf16x3")}
         result["t511_m4k4"] = {
             "config": {"T": 511, "nlat": 768, "nlon": 1536, "M": 4, "K": 4, "dt": 60.0, "steps": 20},
             **{p: {"steps_per_s": round(r["steps_per_s"], 3),

@@ -52,14 +52,14 @@ def _per_field(a, b):
     return [rel_l2(a[..., k, :, :], b[..., k, :, :], T) for k in range(3)]
 
 
-def test_t511_explicit_tendency_fp64_and_fp32(oracles):
+def test_t511_explicit_tendency_fp64_fp32_bf16x3(oracles):
     o, o1, o32 = oracles
     x = _states(T, 1, 511)
     ref = o.f_explicit(x[0])[None]
     spread = _per_field(o1.f_explicit(x[0])[None], ref)
     eps = _per_field(o32.f_explicit(x[0])[None], ref)
     tol32 = [2 * (T + 1) * 2.0 ** -24 * max(1.0, e / eps[0]) for e in eps]
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):     # BF16x3: the FP32 mode's operands and bar
         sdc = _sdc(T, NLAT, NLON, M, K, 1, precision=prec)
         f = _dev(np.zeros_like(x))
         sdc.eval_explicit(_dev(x), f)
@@ -120,7 +120,7 @@ def test_t511_regenerated_tables_are_bitwise_the_streamed_ones():
     x = _states(T, 1, 512)
     lam = W.random_state(T, 513)[None]
     lam[..., :T + 1, 1] = 0.0
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         sdc = _sdc(T, NLAT, NLON, M, K, 1, precision=prec)
         res = {}
         for plan in ((2, 2, 2, 1, 1, 0, 0), (4, 2, 2, 1, 1, 1, 1)):
@@ -143,15 +143,15 @@ def test_t511_regenerated_tables_are_bitwise_the_streamed_ones():
 
 def test_t511_full_run_properties():
     """The T511 workload over its full 200 steps (the oracle's T511 step takes too long for that
-    many), FP64 and FP32, eager and graph-replayed, by what holds at any length: every value
-    finite, the global mean of Phi' (the (0,0) coefficient: the tendencies of both sides vanish
-    there) unchanged to rounding, the FP32 run within 2 (T+1) u_32 per step of the FP64 run on the
-    state change, and the balanced jet still a fixed point after 200 steps."""
+    many), FP64, FP32 and BF16x3, graph-replayed, by what holds at any length: every value finite,
+    the global mean of Phi' (the (0,0) coefficient: the tendencies of both sides vanish there)
+    unchanged to rounding, the FP32 and BF16x3 runs within 2 (T+1) u_32 per step of the FP64 run on
+    the state change, and the balanced jet still a fixed point after 200 steps."""
     wl = W.WORKLOADS["t511_m4k4"]
     x0 = W.initial_state(wl)[None]
     steps = wl.steps
     out = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         sdc = _sdc(T, NLAT, NLON, M, K, 1, precision=prec)
         x = _dev(x0)
         for _ in range(steps):
@@ -159,11 +159,12 @@ def test_t511_full_run_properties():
         sdc.sync()
         out[prec] = _host(x)
         sdc.close()
-    x64, x32 = out["fp64"], out["fp32"]
-    assert np.all(np.isfinite(x64)) and np.all(np.isfinite(x32))
+    x64, x32, x3 = out["fp64"], out["fp32"], out["bf16x3"]
+    assert np.all(np.isfinite(x64)) and np.all(np.isfinite(x32)) and np.all(np.isfinite(x3))
     phi_scale = float(np.max(np.abs(x0[0, W.FIELD_PHI])))
     d00 = abs(x64[0, W.FIELD_PHI, 0, 0] - x0[0, W.FIELD_PHI, 0, 0])
     e32 = rel_l2(x32 - x0, x64 - x0, T)
+    e3 = rel_l2(x3 - x0, x64 - x0, T)
     sdc = _sdc(T, NLAT, NLON, M, K, 1)
     jet = W.balanced_jet(T, 20.0)[None]
     xj = _dev(jet)
@@ -176,7 +177,9 @@ def test_t511_full_run_properties():
     sdc.close()
     bar32 = 2 * (T + 1) * 2.0 ** -24 * steps
     print(f"[gpu] T511 {steps} steps: |dPhi'_00| {d00:.2e} (Phi' scale {phi_scale:.2e}), FP32 vs FP64 on the "
-          f"state change {e32:.3e} (bar {bar32:.2e}), jet after {steps} steps {e_jet:.3e}", flush=True)
+          f"state change {e32:.3e}, BF16x3 {e3:.3e} (bar {bar32:.2e}), jet after {steps} steps {e_jet:.3e}",
+          flush=True)
     assert d00 <= 1e-13 * phi_scale
     assert e32 <= bar32
+    assert e3 <= bar32
     assert e_jet <= 1e-11

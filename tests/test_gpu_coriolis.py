@@ -13,8 +13,8 @@ of the curl of the relative-vorticity flux and the kinetic-energy Laplacian (one
 terms of the rotational wind, which largely cancel in the vorticity tendency (routes' spread 3e-13
 at T63, while the closed form agrees with a long-double evaluation to 1e-16).  The chain solve
 <= 1e-13 (max norm) against the oracle's dense per-order solve;
-whole steps <= 1e-11 relative L2 per field, as for the paper's split; the FP32 mode (FP32
-Legendre contractions only) 2 (T+1) u_32 per f_E on the state change.
+whole steps <= 1e-11 relative L2 per field, as for the paper's split; the FP32 and BF16x3 modes (reduced
+precision in the Legendre contractions only) 2 (T+1) u_32 per f_E on the state change.
 """
 import numpy as np
 import pytest
@@ -116,10 +116,11 @@ def test_step_matches_oracle(T, nlat, nlon, M, K, dt, steps, batch):
     sdc.close()
 
 
-def test_step_fp32_graph_and_jet():
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_step_reduced_precision_graph_and_jet(prec):
     T, nlat, nlon, M, K, dt = 31, 48, 96, 3, 3, 600.0
     sdc, o = _pair(T, nlat, nlon, M, K, 1)
-    s32, _ = _pair(T, nlat, nlon, M, K, 1, precision="fp32")
+    s32, _ = _pair(T, nlat, nlon, M, K, 1, precision=prec)
     x0 = _states(T, 1, 921)
     xe, xg, x32 = _dev(x0), _dev(x0), _dev(x0)
     for _ in range(3):
@@ -132,7 +133,7 @@ def test_step_fp32_graph_and_jet():
     ref = o.step(x0[0], dt, M, K, steps=3)[None]
     err_d = rel_l2(_host(x32) - x0, ref - x0, T)
     bar = 2 * (T + 1) * U32 * 3
-    print(f"[gpu] implicit Coriolis FP32 3 steps: state change rel L2 {err_d:.3e} (bar {bar:.2e})", flush=True)
+    print(f"[gpu] implicit Coriolis {prec} 3 steps: state change rel L2 {err_d:.3e} (bar {bar:.2e})", flush=True)
     assert err_d <= bar
     # the balanced jet stays a fixed point
     jet = W.balanced_jet(T, 20.0)[None]

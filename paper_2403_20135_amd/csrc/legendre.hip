@@ -252,10 +252,18 @@ __device__ __forceinline__ void synthesis_body(
     const int S = nstates;
     const int s = by * 4 + (i >> 2);
     const int sc = s < S ? s : S - 1;
+    // One or two states (a step's first f_E of one or two members): tiles 0 and 1 (both Pbar)
+    // share one MFMA, lane group i >> 2 = 2 t + s holding tile t's values of state s, and tile 1's
+    // products move back to lane groups 0 and 1 (the states' own lanes) after the contraction.
+    // Every product is formed from the same operands as with separate tiles.
+    const bool fold = MODE == kSynForward && S <= 2;                // uniform
+    const int gs = (i >> 2) & 1, fs = gs < S ? gs : S - 1;          // fold: state of lane group
+    auto colv = [&](int t) { return fold && t == 0 ? TL::col(i >> 3, v) : TL::col(t, v); };
+    const int scol = fold ? fs : sc;                                // state of this lane's columns
     // 32-bit byte offsets from per-block (uniform) base addresses: one VGPR per address
     unsigned boff[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(sc * kCmlVals + TL::col(t, v)) * tsz;
+    for (int t = 0; t < NT; ++t) boff[t] = (unsigned)(scol * kCmlVals + colv(t)) * tsz;
     static_assert(!SIN || MODE == kSynForward, "state input: forward synthesis");
     size_t soff[NT];
     bool sscale[NT];
@@ -265,9 +273,9 @@ __device__ __forceinline__ void synthesis_body(
         const size_t c0 = (size_t)coef_offset(g.T, m) * 2;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int vv = TL::col(t, v);
+            const int vv = colv(t);
             const int field = vv < 2 ? 1 : (vv < 4 ? 0 : (vv < 6 ? 1 : 2));
-            soff[t] = ((size_t)sc * 3 + field) * fsd + c0 + (vv & 1);
+            soff[t] = ((size_t)scol * 3 + field) * fsd + c0 + (vv & 1);
             sscale[t] = vv >= 4;
         }
     }
@@ -291,7 +299,9 @@ __device__ __forceinline__ void synthesis_body(
     for (int u = 0; u < JT; ++u)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[u][t] = MM::zero();
-    auto load = [&](SynStage<TT, NT, JT>& x, int j) {
+    // FOLD: tile 1 is neither loaded nor contracted (its values ride in tile 0's columns)
+    auto skip = [](auto fd, int t) { return decltype(fd)::value && MODE == kSynForward && t == 1; };
+    auto load = [&](auto fd, SynStage<TT, NT, JT>& x, int j) {
         const unsigned oc = clane + (unsigned)j * cstep;
         if constexpr (!REC) {
 #pragma unroll
@@ -308,18 +318,21 @@ __device__ __forceinline__ void synthesis_body(
             const double il = inv_lap[m + dn];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
+                if (skip(fd, t)) continue;
                 const double val = sin_state[soff[t] + 2 * (size_t)dn];
                 const double w = sscale[t] ? il * val : val;
                 x.b[t] = kk < npk ? (TT)w : (TT)0;
             }
         } else {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) x.b[t] = ldt(cb, oc + boff[t]);
+            for (int t = 0; t < NT; ++t)
+                if (!skip(fd, t)) x.b[t] = ldt(cb, oc + boff[t]);
         }
     };
-    auto mma_all = [&](const TT (&a)[JT][2], const TT (&b)[NT]) {
+    auto mma_all = [&](auto fd, const TT (&a)[JT][2], const TT (&b)[NT]) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
+            if (skip(fd, t)) continue;
 #pragma unroll
             for (int u = 0; u < JT; ++u) acc[u][t] = MM::mma(a[u][TL::is_h(t) ? 1 : 0], b[t], acc[u][t]);
         }
@@ -346,33 +359,44 @@ __device__ __forceinline__ void synthesis_body(
             a[u][1] = (TT)vh[u];
         }
     };
-    auto compute = [&](const SynStage<TT, NT, JT>& x) {
+    auto compute = [&](auto fd, const SynStage<TT, NT, JT>& x) {
         if constexpr (REC) {
             TT ga[JT][2];
             generate(ga);
-            mma_all(ga, x.b);
+            mma_all(fd, ga, x.b);
         } else {
-            mma_all(x.a, x.b);
+            mma_all(fd, x.a, x.b);
         }
     };
     // Loads past the chain's end re-read its last step (cache hits, results unused): a
     // branch-free loop body lets every stage wait for its own loads only.
-    if (nst > 0) {
+    auto pipeline = [&](auto fd) {
         SynStage<TT, NT, JT> st[D];
 #pragma unroll
-        for (int u = 0; u < D; ++u) load(st[u], u < nst ? u : nst - 1);
+        for (int u = 0; u < D; ++u) load(fd, st[u], u < nst ? u : nst - 1);
         int j0 = 0;
         for (; j0 + D <= nst; j0 += D) {
 #pragma unroll
             for (int u = 0; u < D; ++u) {
-                compute(st[u]);
+                compute(fd, st[u]);
                 const int jn = j0 + u + D;
-                load(st[u], jn < nst ? jn : nst - 1);
+                load(fd, st[u], jn < nst ? jn : nst - 1);
             }
         }
 #pragma unroll
         for (int u = 0; u < D; ++u)
-            if (u < nst - j0) compute(st[u]);
+            if (u < nst - j0) compute(fd, st[u]);
+    };
+    if (nst > 0) {
+        if (fold) pipeline(std::true_type{});
+        else pipeline(std::false_type{});
+    }
+    if (fold) {
+        // tile 1's products from lane groups 2, 3 to lane groups 0, 1 (the lanes of the states)
+#pragma unroll
+        for (int u = 0; u < JT; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[u][1][r] = __shfl_down(acc[u][0][r], 8, 64);
     }
 
     // wave 0: north = even + odd; wave 1: south = even - odd (Pbar tiles), odd - even (H tiles);
@@ -836,26 +860,34 @@ __device__ __forceinline__ void analysis_body(
             x.aH = *(const vec*)(Hr + b * bstride);
         }
     };
-    // k-step qq of a block contracts latitude 4 q + qq of the block (lane group q)
-    auto contract = [&](const vec& aP, const vec& aH, const double* lb) {
+    // k-step qq of a block contracts latitude 4 q + qq of the block (lane group q).  A group of
+    // at most two states (a step's first f_E of one member) leaves the second column tile empty:
+    // its products are skipped (NTL = 1), the first tile's are formed exactly as with four states.
+    auto contract = [&](auto ntl, const vec& aP, const vec& aH, const double* lb) {
+        constexpr int NTL = decltype(ntl)::value;
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             if constexpr (bf3) {
                 const v4u* lq = reinterpret_cast<const v4u*>(lb) + (4 * q + qq) * kAnaLat;
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
+                for (int t = 0; t < NTL; ++t) {
                     accP[t] = MM::mma_pre(aP[qq], lq[offP[t]], accP[t]);
                     accH[t] = MM::mma_pre(aH[qq], lq[offH[t]], accH[t]);
                 }
             } else {
                 const double* lq = lb + (4 * q + qq) * kAnaLat;
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
+                for (int t = 0; t < NTL; ++t) {
                     accP[t] = MM::mma(aP[qq], (TT)lq[offP[t]], accP[t]);
                     accH[t] = MM::mma(aH[qq], (TT)lq[offH[t]], accH[t]);   // dropped for kinds without H
                 }
             }
         }
+    };
+    const bool two_tiles = nsg > 2;                          // wave-uniform
+    auto contract_all = [&](const vec& aP, const vec& aH, const double* lb) {
+        if (two_tiles) contract(std::integral_constant<int, 2>{}, aP, aH, lb);
+        else contract(std::integral_constant<int, 1>{}, aP, aH, lb);
     };
     auto compute = [&](const AnaStage<TT, REC>& x, const double* lb) {
         if constexpr (REC) {
@@ -877,9 +909,9 @@ __device__ __forceinline__ void analysis_body(
             vec aP, aH;
             aP[0] = (TT)p01.x; aP[1] = (TT)p01.y; aP[2] = (TT)p23.x; aP[3] = (TT)p23.y;
             aH[0] = (TT)h01.x; aH[1] = (TT)h01.y; aH[2] = (TT)h23.x; aH[3] = (TT)h23.y;
-            contract(aP, aH, lb);
+            contract_all(aP, aH, lb);
         } else {
-            contract(x.aP, x.aH, lb);
+            contract_all(x.aP, x.aH, lb);
         }
     };
 

@@ -222,3 +222,32 @@ def test_node_launch_needs_one_member():
     assert e.value.code == _lib.SDC_EINVAL
     assert sdc.plan() == DEFAULT
     sdc.close()
+
+
+@pytest.mark.parametrize("prec,M", [("fp64", 2), ("fp64", 3), ("fp32", 2), ("bf16x3", 3)])
+def test_member_alone_and_in_a_batch_agree_bitwise(prec, M):
+    """Members evaluated alone or two at a time (the one- and two-state launches: the synthesis
+    forms both Pbar tiles in one product, the analysis contracts one column tile) and inside a
+    batch of three (separate tiles, two column tiles): f_E, a step and an adjoint step bit for
+    bit, for several variants, with the node update fused into the analysis (M = 2) and separate
+    (M = 3)."""
+    T, nlat, nlon, batch, dt = 63, 96, 192, 3, 600.0
+    x = _states(T, batch, 331)
+    lam = np.stack([W.random_state(T, 332 + b) for b in range(batch)])
+    lam[..., :T + 1, 1] = 0.0
+    together = _sdc(T, nlat, nlon, M, 3, batch, precision=prec)
+    alone = _sdc(T, nlat, nlon, M, 3, 1, precision=prec)
+    pair = _sdc(T, nlat, nlon, M, 3, 2, precision=prec)
+    for v in [(2, 2, 2, 1), (1, 4, 4, 0), (6, 1, 2, 1), (4, 2, 2, 1, 1, 1, 1)]:
+        for h in (together, alone, pair):
+            h.set_plan(*v)
+        ref = _outputs(together, x, lam, dt)
+        parts = [(b, b + 1, alone) for b in range(batch)] + [(1, 3, pair)]
+        for b0, b1, h in parts:
+            got = _outputs(h, x[b0:b1], lam[b0:b1], dt)
+            for name, a, r in zip(("f_E", "step", "adjoint"), got, ref):
+                d = np.max(np.abs(a - r[b0:b1]))
+                print(f"[gpu] T{T} {prec} {v} members {b0}..{b1 - 1} {name}: max |diff| {d:.3e}", flush=True)
+                assert np.array_equal(a, r[b0:b1]), (v, b0, name)
+    for h in (together, alone, pair):
+        h.close()

@@ -130,10 +130,15 @@ template <> struct Mma<Bf3> {
 // dropped.
 // ---------------------------------------------------------------------------------------------
 template <int MODE> struct SynTiles;
+// With one or two states a tile's columns are half empty: tile t then also carries the values of
+// tile partner(t) (same table operand) in lane groups 2 and 3, and the partner (rider) is neither
+// loaded nor contracted.
 template <> struct SynTiles<kSynForward> {
     static constexpr int NT = 3, NF = kSynFields;
     __device__ static constexpr bool is_h(int t) { return t == 2; }
     __device__ static int col(int t, int v) { return t == 0 ? v : (t == 1 ? 7 - v : 4 + v); }
+    __device__ static constexpr int partner(int t) { return t == 0 ? 1 : -1; }
+    __device__ static constexpr bool rider(int t) { return t == 1; }
 };
 template <> struct SynTiles<kSynAdjoint> {
     static constexpr int NT = 4, NF = 5;
@@ -141,6 +146,8 @@ template <> struct SynTiles<kSynAdjoint> {
     __device__ static int col(int t, int v) {
         return t == 0 ? (v ^ 1) : (t == 1 ? (v ^ 2) : (t == 2 ? (v < 2 ? 5 - v : 4 + v) : 4 + (v & 1)));
     }
+    __device__ static constexpr int partner(int t) { return t < 2 ? t + 2 : -1; }
+    __device__ static constexpr bool rider(int t) { return t >= 2; }
 };
 
 template <typename TT, int NT, int JT> struct SynStage {
@@ -252,13 +259,16 @@ __device__ __forceinline__ void synthesis_body(
     const int S = nstates;
     const int s = by * 4 + (i >> 2);
     const int sc = s < S ? s : S - 1;
-    // One or two states (a step's first f_E of one or two members): tiles 0 and 1 (both Pbar)
-    // share one MFMA, lane group i >> 2 = 2 t + s holding tile t's values of state s, and tile 1's
-    // products move back to lane groups 0 and 1 (the states' own lanes) after the contraction.
-    // Every product is formed from the same operands as with separate tiles.
-    const bool fold = MODE == kSynForward && S <= 2;                // uniform
+    // One or two states (a step's first f_E of one or two members): a tile and its partner (the
+    // same table operand) share one MFMA, lane group i >> 2 = 2 h + s holding state s's values of
+    // the tile (h = 0) or of the partner (h = 1), and the partner's products move back to lane
+    // groups 0 and 1 (the states' own lanes) after the contraction.  Every product is formed from
+    // the same operands as with separate tiles.
+    const bool fold = S <= 2;                                       // uniform
     const int gs = (i >> 2) & 1, fs = gs < S ? gs : S - 1;          // fold: state of lane group
-    auto colv = [&](int t) { return fold && t == 0 ? TL::col(i >> 3, v) : TL::col(t, v); };
+    auto colv = [&](int t) {
+        return fold && TL::partner(t) >= 0 && (i >> 3) ? TL::col(TL::partner(t), v) : TL::col(t, v);
+    };
     const int scol = fold ? fs : sc;                                // state of this lane's columns
     // 32-bit byte offsets from per-block (uniform) base addresses: one VGPR per address
     unsigned boff[NT];
@@ -299,8 +309,8 @@ __device__ __forceinline__ void synthesis_body(
     for (int u = 0; u < JT; ++u)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[u][t] = MM::zero();
-    // FOLD: tile 1 is neither loaded nor contracted (its values ride in tile 0's columns)
-    auto skip = [](auto fd, int t) { return decltype(fd)::value && MODE == kSynForward && t == 1; };
+    // fold: a rider tile is neither loaded nor contracted (its values ride in its partner's columns)
+    auto skip = [](auto fd, int t) { return decltype(fd)::value && TL::rider(t); };
     auto load = [&](auto fd, SynStage<TT, NT, JT>& x, int j) {
         const unsigned oc = clane + (unsigned)j * cstep;
         if constexpr (!REC) {
@@ -392,11 +402,15 @@ __device__ __forceinline__ void synthesis_body(
         else pipeline(std::false_type{});
     }
     if (fold) {
-        // tile 1's products from lane groups 2, 3 to lane groups 0, 1 (the lanes of the states)
+        // the riders' products from lane groups 2, 3 to lane groups 0, 1 (the lanes of the states)
 #pragma unroll
-        for (int u = 0; u < JT; ++u)
+        for (int t = 0; t < NT; ++t) {
+            if (TL::partner(t) < 0) continue;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[u][1][r] = __shfl_down(acc[u][0][r], 8, 64);
+            for (int u = 0; u < JT; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[u][TL::partner(t)][r] = __shfl_down(acc[u][t][r], 8, 64);
+        }
     }
 
     // wave 0: north = even + odd; wave 1: south = even - odd (Pbar tiles), odd - even (H tiles);
@@ -884,12 +898,7 @@ __device__ __forceinline__ void analysis_body(
             }
         }
     };
-    const bool two_tiles = nsg > 2;                          // wave-uniform
-    auto contract_all = [&](const vec& aP, const vec& aH, const double* lb) {
-        if (two_tiles) contract(std::integral_constant<int, 2>{}, aP, aH, lb);
-        else contract(std::integral_constant<int, 1>{}, aP, aH, lb);
-    };
-    auto compute = [&](const AnaStage<TT, REC>& x, const double* lb) {
+    auto compute = [&](auto ntl, const AnaStage<TT, REC>& x, const double* lb) {
         if constexpr (REC) {
             double pm1 = x.pm1, p0 = x.p0;
 #pragma unroll
@@ -909,9 +918,9 @@ __device__ __forceinline__ void analysis_body(
             vec aP, aH;
             aP[0] = (TT)p01.x; aP[1] = (TT)p01.y; aP[2] = (TT)p23.x; aP[3] = (TT)p23.y;
             aH[0] = (TT)h01.x; aH[1] = (TT)h01.y; aH[2] = (TT)h23.x; aH[3] = (TT)h23.y;
-            contract_all(aP, aH, lb);
+            contract(ntl, aP, aH, lb);
         } else {
-            contract_all(x.aP, x.aH, lb);
+            contract(ntl, x.aP, x.aH, lb);
         }
     };
 
@@ -925,7 +934,8 @@ __device__ __forceinline__ void analysis_body(
     gstore(gr[0], 0, 0);
     __syncthreads();
     static_assert(D % 2 == 0, "the column register sets alternate with the block parity");
-    if (active) {
+    // NTL column tiles contracted: 2, or 1 for a group of at most two states (see contract)
+    auto contract_blocks = [&](auto ntl) {
         AnaStage<TT, REC> st[D];
 #pragma unroll
         for (int u = 0; u < D; ++u) load(st[u], u < nb ? u : nb - 1);
@@ -935,7 +945,7 @@ __device__ __forceinline__ void analysis_body(
             for (int u = 0; u < D; ++u) {
                 const int b = b0 + u;
                 gload(gr[u & 1], b + 2 < nb ? b + 2 : nb - 1);
-                compute(st[u], gl[b & 1]);
+                compute(ntl, st[u], gl[b & 1]);
                 const int bn = b + D;
                 load(st[u], bn < nb ? bn : nb - 1);          // past the end: re-read, unused
                 gstore(gr[(u + 1) & 1], b + 1, (b + 1) & 1);
@@ -947,11 +957,15 @@ __device__ __forceinline__ void analysis_body(
             const int b = b0 + u;
             if (b < nb) {                                    // uniform
                 gload(gr[u & 1], b + 2 < nb ? b + 2 : nb - 1);
-                compute(st[u], gl[b & 1]);
+                compute(ntl, st[u], gl[b & 1]);
                 gstore(gr[(u + 1) & 1], b + 1, (b + 1) & 1);
                 __syncthreads();
             }
         }
+    };
+    if (active) {
+        if (nsg > 2) contract_blocks(std::integral_constant<int, 2>{});
+        else contract_blocks(std::integral_constant<int, 1>{});
     } else {
         // rows past the order's end: this wave only helps move the columns
         for (int b = 0; b < nb; b += 2) {

@@ -135,6 +135,18 @@ __device__ inline void cml_put(double* cml, bool cml32, size_t i, double v) {
     else
         cml[i] = v;
 }
+// Elements i .. i + 3 (i a multiple of 4: 16- or 32-byte aligned) in vector stores.
+__device__ inline void cml_put4(double* cml, bool cml32, size_t i, double v0, double v1, double v2,
+                                double v3) {
+    if (cml32) {
+        *reinterpret_cast<float4*>(reinterpret_cast<float*>(cml) + i) =
+            make_float4((float)v0, (float)v1, (float)v2, (float)v3);
+    } else {
+        double2* p = reinterpret_cast<double2*>(cml + i);
+        p[0] = make_double2(v0, v1);
+        p[1] = make_double2(v2, v3);
+    }
+}
 // Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V, layout
 // four[s][field][lat][m].
 constexpr int kSynFields = 4;

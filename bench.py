@@ -4,7 +4,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload t255_m4k4] [--no-cpu-baseline]
                     [--no-fp32] [--no-adjoint] [--no-work-precision]
                     [--plan TILES,DEPTH,ANA_DEPTH,INTERLEAVE]
-    python bench.py --summarize-pmc FETCH.csv WRITE.csv COPY_MIB OUT.json FETCH.log WRITE.log
+    python bench.py --summarize-pmc FETCH.csv WRITE.csv COPY_MIB OUT.json FETCH.log WRITE.log [COMMAND]
                                                                             (counter summary)
 
 Prints ONE JSON line.  Every handle first runs the library's autotuner (untimed; it picks the
@@ -522,7 +522,7 @@ def traffic_for(kernel, plan, plan1=None):
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
-def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
+def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs, command=None):
     """Counter summary: mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel class, scaled
     so that the device-to-device copy of copy_mib MiB reads and writes exactly that many bytes.
     The Legendre classes take the launch variants the profiled bench runs used (their JSON lines in
@@ -559,6 +559,8 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, out_json, bench_logs):
         return acc
 
     out = {"source_sha": source_hash(), "copy_mib": copy_mib, "kernels": {}}
+    if command:
+        out["commands"] = command
     fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
     copy_bytes = copy_mib * (1 << 20)
     cf = [v for k, vs in fetch.items() if "copyBuffer" in k for v in vs]
@@ -930,8 +932,8 @@ def main():
                     metavar=("COUNTER_CSV", "STATS_CSV", "OUT_MD", "TITLE", "COMMAND"))
     ap.add_argument("--summarize-counters", nargs=6,
                     metavar=("COUNTER_CSV", "STATS_CSV", "OUT_MD", "TITLE", "COMMAND", "KERNEL_PREFIXES"))
-    ap.add_argument("--summarize-pmc", nargs=6,
-                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB", "OUT", "FETCH_LOG", "WRITE_LOG"))
+    ap.add_argument("--summarize-pmc", nargs="+",
+                    metavar="FETCH_CSV WRITE_CSV COPY_MIB OUT FETCH_LOG WRITE_LOG [COMMAND]")
     args = ap.parse_args()
     global FORCED_PLAN, FORCED_PLAN1
     if args.plan:
@@ -947,8 +949,11 @@ def main():
         summarize_counters(*args.summarize_counters)
         return
     if args.summarize_pmc:
-        f, w, mib, outp, flog, wlog = args.summarize_pmc
-        summarize_pmc(f, w, float(mib), outp, [flog, wlog])
+        if len(args.summarize_pmc) not in (6, 7):
+            ap.error("--summarize-pmc takes FETCH_CSV WRITE_CSV COPY_MIB OUT FETCH_LOG WRITE_LOG [COMMAND]")
+        f, w, mib, outp, flog, wlog = args.summarize_pmc[:6]
+        cmd = args.summarize_pmc[6] if len(args.summarize_pmc) == 7 else None
+        summarize_pmc(f, w, float(mib), outp, [flog, wlog], cmd)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs the step on a single MI355X "

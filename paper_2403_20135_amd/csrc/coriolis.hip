@@ -14,8 +14,10 @@
 // delta and Phi' at the others, Phi' eliminated (Phi'_k = beta_Phi,k - alpha Phi_bar delta_k).
 // Each chain is a complex tridiagonal system, diagonally dominant for the step sizes of the
 // shallow-water configurations (off-diagonals 2 Omega alpha e <~ 0.1, diagonals of modulus >= 1),
-// solved by forward elimination and back substitution without pivoting.  One thread carries one
-// chain of one order of one output state; the elimination's coefficients go to a scratch buffer.
+// solved without pivoting: up to T = 511 by one wave per chain (segments per lane, cyclic
+// reduction over the lanes for the segment boundaries; k_solve_lc_wave), beyond that by forward
+// elimination and back substitution with one thread per chain (k_solve_lc), whose elimination
+// coefficients go to a scratch buffer.
 #include "common.h"
 
 // (e-_k, e+_k) per coefficient of the m-major triangular layout
@@ -280,6 +282,232 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
     if (a.last_only && bad) a.flag[0] = 1;
 }
 
+// The same chain solve with one wave per chain (orders up to T = 511): the J = T + 1 - m
+// positions are cut into 64 segments of L consecutive positions (L = 1, 2, 4 or 8, the chain
+// padded with identity rows to 64 L), one segment per lane and held in registers.
+//  1. Each lane eliminates its segment's interior (all positions but the last) with the two
+//     boundary unknowns moved to the right-hand side: x_q = g_q + hl_q X_{p-1} + hr_q X_p, X_p the
+//     last unknown of segment p (three right-hand sides, one Thomas sweep each way).
+//  2. Substituting these into each segment's last equation leaves a tridiagonal system in the 64
+//     X_p (the first interior representation of segment p + 1 comes from the next lane), solved
+//     by parallel cyclic reduction over the lanes: six steps of combining each equation with the
+//     ones h = 1, 2, 4, .., 32 lanes away (shuffles), after which every equation holds one unknown.
+//  3. Every lane forms its interior values from X_{p-1} (the previous lane's) and X_p.
+// The chains are diagonally dominant (see above), for which cyclic reduction and the segment
+// eliminations need no pivoting; the result equals the sequential elimination's up to rounding.
+namespace {
+
+// v of lane - h (lane + h), zero where that lane is outside the wave; every lane must call these
+__device__ __forceinline__ double2 shfl_up2(double2 v, int h, int lane) {
+    const double2 r = make_double2(__shfl_up(v.x, h, 64), __shfl_up(v.y, h, 64));
+    return lane >= h ? r : make_double2(0.0, 0.0);
+}
+__device__ __forceinline__ double2 shfl_down2(double2 v, int h, int lane) {
+    const double2 r = make_double2(__shfl_down(v.x, h, 64), __shfl_down(v.y, h, 64));
+    return lane + h < 64 ? r : make_double2(0.0, 0.0);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) { return cmul(a, cinv(b)); }
+
+struct Row {
+    double2 D, r, bphi;       // diagonal, right-hand side, beta_Phi (delta positions)
+    double lo, up;            // sub- and super-diagonal
+};
+
+template <int L>
+__device__ void solve_chain_wave(const LcArgs& a, int m, int c, int i, int b, double alpha, int lane) {
+    const int T = a.T;
+    const size_t fs = (size_t)a.ncoef * 2;
+    const int idx0 = coef_offset(T, m);
+    const int J = T + 1 - m;
+    const double two_omega = a.two_omega;
+    const int ostate = a.mode == 0 ? (a.last_only ? b : b * a.M + i) : b;
+    const double* __restrict__ be = (a.mode == 0 ? a.beta_ws + (size_t)ostate * 3 * fs
+                                                 : a.beta + (size_t)b * 3 * fs);
+    // the equations of this lane's positions j = lane L + q (identity rows past the chain)
+    Row e[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+        const int j = lane * L + q;
+        Row w;
+        if (j < J) {
+            const int k = m + j, idx = idx0 + j;
+            const double2 ee = a.lc[idx];
+            const double cn = k * (k + 1.0) * a.inv_a2;
+            const double bk = k > 0 ? two_omega * m / (k * (k + 1.0)) : 0.0;
+            if ((j & 1) == c) {
+                w.D = make_double2(1.0, -alpha * bk);
+                w.lo = two_omega * alpha * ee.x;
+                w.up = two_omega * alpha * ee.y;
+                w.r = ld(be + fs + 2 * (size_t)idx);
+                w.bphi = make_double2(0.0, 0.0);
+            } else {
+                w.D = make_double2(1.0 + alpha * alpha * a.phibar * cn, -alpha * bk);
+                w.lo = -two_omega * alpha * ee.x;
+                w.up = -two_omega * alpha * ee.y;
+                w.bphi = ld(be + 2 * (size_t)idx);
+                w.r = cadd(ld(be + 2 * fs + 2 * (size_t)idx), rmul(alpha * cn, w.bphi));
+            }
+            if (j == 0) w.lo = 0.0;                       // degree m - 1 does not exist
+            if (j == J - 1) w.up = 0.0;                   // degree T + 1 is truncated
+        } else {
+            w.D = make_double2(1.0, 0.0);
+            w.lo = 0.0;
+            w.up = 0.0;
+            w.r = make_double2(0.0, 0.0);
+            w.bphi = w.r;
+        }
+        e[q] = w;
+    }
+    // 1. interior q = 0 .. L-2: x_q = g_q + hl_q X_{p-1} + hr_q X_p
+    double2 g[L], hl[L], hr[L];
+    if constexpr (L > 1) {
+        double2 cp[L];
+        double2 dg[L], dl[L], dr[L];
+#pragma unroll
+        for (int q = 0; q < L - 1; ++q) {
+            const double2 rl = q == 0 ? make_double2(-e[0].lo, 0.0) : make_double2(0.0, 0.0);
+            const double2 rrr = q == L - 2 ? make_double2(-e[L - 2].up, 0.0) : make_double2(0.0, 0.0);
+            const double2 den = q == 0 ? e[0].D : csub(e[q].D, rmul(e[q].lo, cp[q - 1]));
+            const double2 inv = cinv(den);
+            cp[q] = q < L - 2 ? rmul(e[q].up, inv) : make_double2(0.0, 0.0);
+            dg[q] = cmul(q == 0 ? e[0].r : csub(e[q].r, rmul(e[q].lo, dg[q - 1])), inv);
+            dl[q] = cmul(q == 0 ? rl : csub(rl, rmul(e[q].lo, dl[q - 1])), inv);
+            dr[q] = cmul(q == 0 ? rrr : csub(rrr, rmul(e[q].lo, dr[q - 1])), inv);
+        }
+        g[L - 2] = dg[L - 2];
+        hl[L - 2] = dl[L - 2];
+        hr[L - 2] = dr[L - 2];
+#pragma unroll
+        for (int q = L - 3; q >= 0; --q) {
+            g[q] = csub(dg[q], cmul(cp[q], g[q + 1]));
+            hl[q] = csub(dl[q], cmul(cp[q], hl[q + 1]));
+            hr[q] = csub(dr[q], cmul(cp[q], hr[q + 1]));
+        }
+    }
+    // 2. the reduced equation of X_p: A X_{p-1} + B X_p + C X_{p+1} = R
+    const Row& last = e[L - 1];
+    double2 A, B, C, R;
+    if constexpr (L > 1) {
+        A = rmul(last.lo, hl[L - 2]);
+        B = cadd(last.D, rmul(last.lo, hr[L - 2]));
+        R = csub(last.r, rmul(last.lo, g[L - 2]));
+    } else {
+        A = make_double2(last.lo, 0.0);
+        B = last.D;
+        R = last.r;
+    }
+    {
+        // x at the next segment's first position: its interior representation (L > 1) or X_{p+1}
+        double2 ng, nl, nr;
+        if constexpr (L > 1) {
+            ng = shfl_down2(g[0], 1, lane);
+            nl = shfl_down2(hl[0], 1, lane);
+            nr = shfl_down2(hr[0], 1, lane);
+        } else {
+            ng = make_double2(0.0, 0.0);
+            nl = ng;
+            nr = make_double2(1.0, 0.0);
+        }
+        B = cadd(B, rmul(last.up, nl));
+        C = rmul(last.up, nr);
+        R = csub(R, rmul(last.up, ng));
+    }
+#pragma unroll
+    for (int h = 1; h < 64; h *= 2) {
+        // every lane shuffles (a lane reading an inactive lane's register gets no defined value);
+        // equations past either end of the chain act as identity rows
+        const double2 Am = shfl_up2(A, h, lane), Cm = shfl_up2(C, h, lane), Rm = shfl_up2(R, h, lane);
+        const double2 Ap = shfl_down2(A, h, lane), Cp = shfl_down2(C, h, lane), Rp = shfl_down2(R, h, lane);
+        const double2 Bm0 = shfl_up2(B, h, lane), Bp0 = shfl_down2(B, h, lane);
+        const double2 Bm = lane >= h ? Bm0 : make_double2(1.0, 0.0);
+        const double2 Bp = lane + h < 64 ? Bp0 : make_double2(1.0, 0.0);
+        const double2 k1 = cdiv(A, Bm), k2 = cdiv(C, Bp);
+        A = make_double2(0.0, 0.0);
+        A = csub(A, cmul(Am, k1));
+        C = csub(make_double2(0.0, 0.0), cmul(Cp, k2));
+        B = csub(csub(B, cmul(Cm, k1)), cmul(Ap, k2));
+        R = csub(csub(R, cmul(Rm, k1)), cmul(Rp, k2));
+    }
+    const double2 X = cdiv(R, B);
+    const double2 Xm = shfl_up2(X, 1, lane);             // X_{p-1} (0 for lane 0: its lo is 0)
+    // 3. values and outputs
+    double* __restrict__ out =
+        a.uout + (size_t)b * a.out_member + (size_t)(a.mode == 0 && !a.last_only ? i : 0) * a.out_node;
+    const size_t S = (size_t)a.batch * a.M;
+    const size_t cs = (size_t)b * a.M + i;                // synthesis-layout state of this node
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+        const int j = lane * L + q;
+        if (j >= J) continue;
+        double2 xv;
+        if constexpr (L > 1) {
+            xv = q == L - 1 ? X : cadd(g[q], cadd(cmul(hl[q], Xm), cmul(hr[q], X)));
+        } else {
+            xv = X;
+        }
+        const int k = m + j, idx = idx0 + j;
+        const bool zeta_pos = ((j & 1) == c);
+        const int par = j & 1, kk = j >> 1;
+        const double il = a.cml ? a.inv_lap[k] : 0.0;
+        const size_t ci = a.cml ? (((size_t)a.rowoff[2 * m + par] + kk) * S + cs) * kCmlVals : 0;
+        if (zeta_pos) {
+            *(double2*)(out + fs + 2 * (size_t)idx) = xv;
+            if (a.cml) {
+                cml_put(a.cml, a.cml32, ci, xv.x);
+                cml_put(a.cml, a.cml32, ci + 1, xv.y);
+                cml_put(a.cml, a.cml32, ci + 4, il * xv.x);
+                cml_put(a.cml, a.cml32, ci + 5, il * xv.y);
+            }
+            bad = bad || !(isfinite(xv.x) && isfinite(xv.y));
+        } else {
+            const double2 phi = csub(e[q].bphi, rmul(alpha * a.phibar, xv));
+            *(double2*)(out + 2 * fs + 2 * (size_t)idx) = xv;
+            *(double2*)(out + 2 * (size_t)idx) = phi;
+            if (a.cml) {
+                cml_put(a.cml, a.cml32, ci + 2, phi.x);
+                cml_put(a.cml, a.cml32, ci + 3, phi.y);
+                cml_put(a.cml, a.cml32, ci + 6, il * xv.x);
+                cml_put(a.cml, a.cml32, ci + 7, il * xv.y);
+            }
+            bad = bad || !(isfinite(xv.x) && isfinite(xv.y) && isfinite(phi.x) && isfinite(phi.y));
+        }
+    }
+    // padding rows of the synthesis layout: chain c clears those of parity c
+    if (a.cml && lane == 0) {
+        const int np = npk_of(T, m, c);
+        if (np > 0) cml_clear_pad(a.cml, a.cml32, a.rowoff[2 * m + c], np - 1, np, S, cs);
+    }
+    if (a.last_only && bad) a.flag[0] = 1;
+}
+
+}  // namespace
+
+constexpr int kLcWaves = 4;                       // chains (waves) per workgroup
+
+// LMAX: the segment length the longest chain (m = 0) needs; shorter chains use shorter segments.
+template <int LMAX>
+__global__ __launch_bounds__(64 * kLcWaves) void k_solve_lc_wave(LcArgs a) {
+    const int nodes = a.mode == 0 ? (a.last_only ? 1 : a.M) : 1;
+    const int t = blockIdx.x * kLcWaves + (threadIdx.x >> 6);          // chain of this wave
+    const int lane = threadIdx.x & 63;
+    const int per_m = 2 * nodes * a.batch;
+    if (t >= (a.T + 1) * per_m) return;                                // uniform per wave
+    const int m = t / per_m;
+    int r = t - m * per_m;
+    const int c = r / (nodes * a.batch);
+    r -= c * nodes * a.batch;
+    const int i = a.mode == 0 ? (a.last_only ? a.M - 1 : r / a.batch) : 0;
+    const int b = r % a.batch;
+    const int sdiv = a.sweep < a.M ? a.sweep : a.M;
+    const double alpha = a.mode == 0 ? a.dt * a.tau[i] / sdiv : a.alpha;
+    const int J = a.T + 1 - m;
+    if (J <= 64 || LMAX == 1) solve_chain_wave<1>(a, m, c, i, b, alpha, lane);
+    else if (J <= 128 || LMAX == 2) solve_chain_wave<LMAX >= 2 ? 2 : 1>(a, m, c, i, b, alpha, lane);
+    else if (J <= 256 || LMAX == 4) solve_chain_wave<LMAX >= 4 ? 4 : 1>(a, m, c, i, b, alpha, lane);
+    else solve_chain_wave<LMAX>(a, m, c, i, b, alpha, lane);
+}
+
 void launch_solve_lc(const LcArgs& a, hipStream_t st) {
     const int nodes = a.mode == 0 ? (a.last_only ? 1 : a.M) : 1;
     if (a.mode == 0) {
@@ -287,7 +515,12 @@ void launch_solve_lc(const LcArgs& a, hipStream_t st) {
         k_lc_rhs<<<grid, kBlock, 0, st>>>(a);
     }
     const int n = (a.T + 1) * 2 * nodes * a.batch;
-    k_solve_lc<<<(n + 63) / 64, 64, 0, st>>>(a);
+    const int wgs = (n + kLcWaves - 1) / kLcWaves;
+    if (a.T + 1 <= 64) k_solve_lc_wave<1><<<wgs, 64 * kLcWaves, 0, st>>>(a);
+    else if (a.T + 1 <= 128) k_solve_lc_wave<2><<<wgs, 64 * kLcWaves, 0, st>>>(a);
+    else if (a.T + 1 <= 256) k_solve_lc_wave<4><<<wgs, 64 * kLcWaves, 0, st>>>(a);
+    else if (a.T + 1 <= 512) k_solve_lc_wave<8><<<wgs, 64 * kLcWaves, 0, st>>>(a);
+    else k_solve_lc<<<(n + 63) / 64, 64, 0, st>>>(a);
 }
 
 // f_I = L_g + L_c of `batch` states; fI must not alias u (the neighbours are read).

@@ -12,7 +12,8 @@ of the curl of the relative-vorticity flux and the kinetic-energy Laplacian (one
 1e-12 at T31, 4.6e-12 at T63), and the transform route of L_c rounds relative to the Coriolis
 terms of the rotational wind, which largely cancel in the vorticity tendency (routes' spread 3e-13
 at T63, while the closed form agrees with a long-double evaluation to 1e-16).  The chain solve
-<= 1e-13 (max norm) against the oracle's dense per-order solve;
+<= 1e-13 (max norm) against the oracle's dense per-order solve, and its residual through the
+closed-form f_I <= 1e-13 at sizes beyond the oracle's reach;
 whole steps <= 1e-11 relative L2 per field, as for the paper's split; the FP32 and BF16x3 modes (reduced
 precision in the Legendre contractions only) 2 (T+1) u_32 per f_E on the state change.
 """
@@ -146,6 +147,33 @@ def test_step_reduced_precision_graph_and_jet(prec):
         assert np.max(np.abs(jh[0, f] - jet[0, f])) <= 1e-13 * scale, f
     sdc.close()
     s32.close()
+
+
+@pytest.mark.parametrize("T,nlat,nlon", [(127, 128, 384), (255, 256, 768), (300, 302, 768), (600, 602, 1536)])
+def test_chain_solve_residual_at_every_segment_length(T, nlat, nlon):
+    """The chain solve through its wave-parallel forms (segments of 2, 4 and 8 positions per lane
+    for T = 127, 255 and 300) and the one-thread-per-chain form beyond T = 511: the residual
+    u - alpha f_I(u) - beta, f_I from eval_implicit (the closed-form couplings, an independent
+    kernel that matches the oracle to an ulp), <= 1e-13 in the max norm relative to the largest of
+    u, alpha f_I(u) and beta per field, with u aliasing beta."""
+    from paper_2403_20135_amd.api import SDC
+    sdc = SDC(T, nlat, nlon, 2, 2, 2, "fp64", W.RADIUS, W.GRAVITY, W.OMEGA, W.MEAN_DEPTH,
+              implicit_coriolis=True)
+    beta = _states(T, 2, 941, jet=False)
+    for alpha in (60.0, 450.0):
+        u = _dev(beta)
+        sdc.imex_solve(alpha, u, u)
+        fi = _dev(np.zeros_like(beta))
+        sdc.eval_implicit(u, fi)
+        uh, afi = _host(u), alpha * _host(fi)
+        res = uh - afi - beta
+        # relative to the largest of the three terms (rounding of u - alpha f_I(u) sets the floor)
+        err = max(float(np.max(np.abs(res[b, f])) /
+                        max(np.max(np.abs(beta[b, f])), np.max(np.abs(afi[b, f])), np.max(np.abs(uh[b, f]))))
+                  for b in range(2) for f in range(3))
+        print(f"[gpu] T{T} chain solve alpha={alpha}: residual rel max {err:.3e}", flush=True)
+        assert err <= 1e-13
+    sdc.close()
 
 
 def test_unsupported_paths_and_argument_errors():

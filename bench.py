@@ -10,7 +10,9 @@
 Prints ONE JSON line.  Every handle first runs the library's autotuner (untimed; it picks the
 Legendre launch variants, reported as `legendre_plan`).  `value` is the plain FP64 path: exactly
 K steps (after W warm-up steps and one graph capture) on synthetic seeded fields already resident in device memory, bracketed by
-torch.cuda.synchronize(); each step is one replay of the step's captured hipGraph.  A second
+torch.cuda.synchronize(); each step is one replay of the step's captured hipGraph (four more
+regions of K replays follow: `steps_per_s_median_of_5` and `steps_per_s_range_of_5` report the
+median and spread of the five, `value` stays the first).  A second
 region of K eager steps brackets every launch with HIP events on the library's stream; the
 dominant kernel class (largest summed time) is reported against its roofline.  A third region
 times K forward steps with one checkpoint each followed by K adjoint steps (forward+adjoint, each
@@ -177,6 +179,17 @@ def measure(wl, precision, steps, warmup, with_kernels=True, with_adjoint=True):
     sdc.sync()
     out = {"steps_per_s": steps / elapsed, "ms_per_step": elapsed / steps * 1e3, "plan": plan,
            "plan1": sdc.plan_for(1)}
+    # four more timed regions of K replays after the contract one (not part of `value`): the
+    # median of five and their spread
+    rates = [steps / elapsed]
+    for _ in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sdc.step_graph(x, mb.dt)
+        torch.cuda.synchronize()
+        rates.append(steps / (time.perf_counter() - t0))
+    out["repeats"] = sorted(rates)
 
     if with_kernels:
         # per-kernel HIP events (on the library's stream) over K eager steps of the same kernels
@@ -987,6 +1000,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "T": mb.T, "nlat": mb.nlat, "nlon": mb.nlon, "M": wl.M,
                    "K": wl.K, "dt": mb.dt, "batch": 1, "precision": "fp64"},
+        "steps_per_s_median_of_5": round(r64["repeats"][2], 3),
+        "steps_per_s_range_of_5": [round(r64["repeats"][0], 3), round(r64["repeats"][-1], 3)],
         "eager_ms_per_step": round(r64["eager_ms_per_step"], 4),
         "fwd_adj_steps_per_s": round(r64["fwd_adj_steps_per_s"], 3) if "fwd_adj_steps_per_s" in r64 else None,
         "fwd_adj_ms_per_step": round(r64["fwd_adj_ms_per_step"], 4) if "fwd_adj_ms_per_step" in r64 else None,

@@ -62,13 +62,19 @@ TABLE_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_t255_m4k4.json")
 
 
+# the sources of the kernels a counter summary covers (synthesis, grid, analysis, node update)
+PROFILED_SOURCES = ("legendre.hip", "grid.hip", "update.hip")
+
+
 def source_hash() -> str:
-    """Hash of the device sources (the .hip kernels and the header they share): a counter summary
-    is valid only for the kernels it measured.  The Legendre launch variants, the only host-side
-    choice that changes what those kernels do per launch, are checked separately (the plan)."""
+    """Hash of the device sources of the profiled kernel classes (their .hip files and every shared
+    header): a counter summary is valid only for the kernels it measured.  The Legendre launch
+    variants, the only host-side choice that changes what those kernels do per launch, are checked
+    separately (the plan)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2403_20135_amd", "csrc")
-    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+    srcs = [os.path.join(csrc, f) for f in PROFILED_SOURCES] + glob.glob(os.path.join(csrc, "*.h"))
+    for p in sorted(srcs):
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode() + f.read())
     return h.hexdigest()[:16]

@@ -566,10 +566,8 @@ void run_explicit_cml(sdc_ctx* c, int S, double* out, double2* save = nullptr,
     if (c->poison_now) {
         const size_t st_b = (size_t)3 * c->g.ncoef * 2 * sizeof(double);
         if (!fuse) launch_poison(out, (size_t)S * st_b, c->st);          // the tendencies
-        if (fuse && !fuse->last_only) {                                   // the updated nodes
+        if (fuse && !fuse->last_only)                                     // the updated nodes
             launch_poison(fuse->uout, (size_t)fuse->batch * fuse->M * st_b, c->st);
-            launch_poison(fuse->cml, (size_t)c->g.nrows * fuse->batch * fuse->M * kCmlVals * tb, c->st);
-        }
     }
     t = c->begin(SDC_KERNEL_ANALYSIS);
     launch_analysis_swe(c->tables(), lp, c->toff, c->ana_tasks, c->n_ana_wg, c->G, S, c->neg_lap,
@@ -638,9 +636,6 @@ void run_update(sdc_ctx* c, const UpdateArgs& a) {
     if (c->poison_now && !a.last_only) {
         const size_t st_b = (size_t)3 * c->g.ncoef * 2 * sizeof(double);
         launch_poison(a.uout, (size_t)a.batch * a.M * st_b, c->st);
-        if (a.cml)
-            launch_poison(a.cml, (size_t)c->g.nrows * a.batch * a.M * kCmlVals *
-                                     (c->P32 ? sizeof(float) : sizeof(double)), c->st);
     }
     const long t = c->begin(SDC_KERNEL_UPDATE);
     launch_update(a, c->st);
@@ -826,6 +821,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
     // the launch shape that dominates a step: every node state of every member at once
     const int S = c->cfg.batch * c->cfg.M;
     // finite operands for every candidate (the buffers are workspaces every step rewrites)
+    HIP_TRY(hipMemsetAsync(c->ua, 0, (size_t)c->smax * 3 * c->g.ncoef * 2 * sizeof(double), c->st));
     HIP_TRY(hipMemsetAsync(c->cml, 0, (size_t)c->g.nrows * c->smax * kCmlVals * sizeof(double), c->st));
     HIP_TRY(hipMemsetAsync(c->G, 0, (size_t)(c->g.T + 1) * 2 * c->g.nhp * c->smax * kAnaStride * sizeof(double),
                            c->st));
@@ -855,8 +851,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
     constexpr int kAna = 8;                 // depth 4 / 2 x interleave 1 / 0 x read / regenerate
     hipError_t err = hipSuccess;
     // Times every synthesis and analysis variant at S states and returns `cur` with the fastest
-    // of each (the synthesis of one state per member reads the states in place, as a step's
-    // first f_E does).
+    // of each (the synthesis reads the states in place, as every f_E of a step does).
     auto tune = [&](const LegPlan& cur, int S, const double* state_in) {
         LegPlan syn_cands[kSyn], ana_cands[kAna];
         for (int k = 0; k < kSyn; ++k) {
@@ -916,7 +911,7 @@ int sdc_autotune(sdc_handle h, int reps, sdc_plan* chosen) {
         return best;
     };
     const LegPlan saved = c->lplan, saved1 = c->lplan1;
-    LegPlan best = tune(saved, S, nullptr);
+    LegPlan best = tune(saved, S, c->ua);
     // launches over one state per member (handles with more than one node): their own variants
     LegPlan best1 = c->cfg.M > 1 ? tune(saved1, c->cfg.batch, c->ua) : best;
     (void)hipEventDestroy(e0);
@@ -977,7 +972,6 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
         return tape ? tape + stage_states(c, s, M) * tape_per_state(c) : nullptr;
     };
     UpdateArgs a{};
-    a.cml32 = c->P32 != nullptr ? 1 : 0;       // synthesis input in the table type
     a.un = state;
     a.tau = c->tau + M * kMaxNodes;
     a.Q = c->Q + M * kMaxNodes * kMaxNodes;
@@ -1013,7 +1007,6 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
         l.E = c->E0;
         l.E_node = 0;
         l.E_member = fs;
-        l.cml32 = c->P32 != nullptr ? 1 : 0;
         l.tau = c->tau + M * kMaxNodes;
         l.Q = c->Q + M * kMaxNodes * kMaxNodes;
         l.rowoff = c->rowoff;
@@ -1042,11 +1035,10 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
             l.uout = bufs[cur];
             l.out_node = fs;
             l.out_member = (long long)M * fs;
-            l.cml = c->cml;
             l.sweep = qd_sweep(c, s, M);
             l.last_only = 0;
             solve();
-            run_explicit_cml(c, B * M, c->E, tape_at(s));
+            run_explicit(c, bufs[cur], B * M, c->E, tape_at(s));
             l.uprev = bufs[cur];
             l.uprev_node = fs;
             l.uprev_member = (long long)M * fs;
@@ -1059,7 +1051,6 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
         l.uout = state;
         l.out_node = 0;
         l.out_member = fs;
-        l.cml = nullptr;
         l.sweep = qd_sweep(c, K, M);
         l.last_only = 1;
         solve();
@@ -1078,7 +1069,6 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
             a.out_member = (long long)M * fs;
             a.sweep = qd_sweep(c, s, M);
             a.last_only = 0;
-            a.cml = nullptr;
             run_update(c, a);
             for (int j = 0; j < M; ++j)
                 run_explicit(c, bufs[cur] + j * fs, 1, c->E + j * fs,
@@ -1095,7 +1085,6 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
         a.uout = state;
         a.out_node = 0;
         a.out_member = fs;
-        a.cml = nullptr;
         a.sweep = qd_sweep(c, K, M);
         a.last_only = 1;
         run_update(c, a);
@@ -1110,13 +1099,11 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
                 a.uout = bufs[cur];
                 a.out_node = fs;
                 a.out_member = (long long)M * fs;
-                a.cml = c->cml;
                 a.last_only = 0;
             } else {
                 a.uout = state;
                 a.out_node = 0;
                 a.out_member = fs;
-                a.cml = nullptr;
                 a.last_only = 1;
             }
             a.sweep = qd_sweep(c, s, M);
@@ -1129,7 +1116,7 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
             a.uprev_member = (long long)M * fs;
             cur ^= 1;
             set_update(s + 1);
-            run_explicit_cml(c, B * M, c->E, tape_at(s), (s + 1 < K || last_update) ? &a : nullptr, 2);
+            run_explicit(c, a.uprev, B * M, c->E, tape_at(s), (s + 1 < K || last_update) ? &a : nullptr, 2);
         }
         return;
     }
@@ -1141,9 +1128,8 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
         a.out_member = (long long)M * fs;
         a.sweep = qd_sweep(c, s, M);
         a.last_only = 0;
-        a.cml = c->cml;
         run_update(c, a);
-        run_explicit_cml(c, B * M, c->E, tape_at(s));
+        run_explicit(c, bufs[cur], B * M, c->E, tape_at(s));
         a.uprev = bufs[cur];
         a.uprev_node = fs;
         a.uprev_member = (long long)M * fs;
@@ -1157,7 +1143,6 @@ void enqueue_step_impl(sdc_ctx* c, double* state, double dt, int M, int K, doubl
     a.uout = state;
     a.out_node = 0;
     a.out_member = fs;
-    a.cml = nullptr;
     a.sweep = qd_sweep(c, K, M);
     a.last_only = 1;
     run_update(c, a);
@@ -1574,7 +1559,6 @@ int imex_solve(sdc_handle h, double alpha, const double* beta, double* u) {
         l.flag = h->flag;
         l.tau = h->tau + kMaxNodes;       // unused by the plain solve (valid addresses only)
         l.Q = h->Q + kMaxNodes * kMaxNodes;
-        l.cml = nullptr;
         l.phibar = h->phibar;
         l.inv_a2 = h->inv_a2;
         l.two_omega = h->two_omega;
@@ -1828,7 +1812,9 @@ int group_capture_merged(sdc_group_s* g, double* const* states, const double* dt
         Launch L{};
         L.kind = ops[0][i].kind;
         if (L.kind == 0) {
-            const LegPlan lp = g->tuned ? (ops[0][i].states ? g->plan1 : g->plan) : cl->plan_for(ops[lead][i].S);
+            // one-state launches (a step's first f_E) and node launches have their own variants
+            const bool one = ops[0][i].S == g->members[0]->cfg.batch;
+            const LegPlan lp = g->tuned ? (one ? g->plan1 : g->plan) : cl->plan_for(ops[lead][i].S);
             L.plan = lp;
             L.state_in = ops[0][i].states != nullptr;
             std::vector<SynArgs> sy(n);
@@ -1928,12 +1914,13 @@ int group_capture_branches(sdc_group_s* g, double* const* states, const double* 
 }
 
 // Times one merged synthesis and one merged analysis launch of every built Legendre variant at the
-// node shape (batch x M states per member, synthesis layout input) and at the one-state shape
-// (the states read in place), and keeps the fastest of each in g->plan / g->plan1.
+// node shape (batch x M states per member) and at the one-state shape, the states read in place
+// as in a step, and keeps the fastest of each in g->plan / g->plan1.
 int group_tune_legendre(sdc_group_s* g, int M, int reps) {
     const size_t n = g->members.size();
     const int tt = g->members[0]->table_type();
     for (sdc_ctx* c : g->members) {         // finite operands in the workspaces
+        HIP_TRY(hipMemsetAsync(c->ua, 0, (size_t)c->smax * 3 * c->g.ncoef * 2 * sizeof(double), g->st));
         HIP_TRY(hipMemsetAsync(c->cml, 0, (size_t)c->g.nrows * c->smax * kCmlVals * sizeof(double), g->st));
         HIP_TRY(hipMemsetAsync(c->G, 0, (size_t)(c->g.T + 1) * 2 * c->g.nhp * c->smax * kAnaStride * sizeof(double),
                                g->st));
@@ -1976,14 +1963,14 @@ int group_tune_legendre(sdc_group_s* g, int M, int reps) {
                 sdc_ctx* c = g->members[h];
                 const int S = one ? c->cfg.batch : c->cfg.batch * M;
                 sy[h] = make_syn_args(c->tables(), c->toff, c->rowoff, c->syn_list(lp), c->syn_count(lp), c->cml, S,
-                                      reinterpret_cast<double*>(c->four), c->g, one ? c->ua : nullptr);
+                                      reinterpret_cast<double*>(c->four), c->g, c->ua);
                 sy[h].first = fs;
                 fs += (sy[h].blocks + 7) / 8 * 8;
             }
             err = hipMemcpy(g->desc, sy.data(), n * sizeof(SynArgs), hipMemcpyHostToDevice);
             if (err != hipSuccess) break;
             const float ms = time_it([&] {
-                launch_synthesis_multi(lp, tt, one != 0, static_cast<const SynArgs*>(g->desc), (int)n, fs, g->st);
+                launch_synthesis_multi(lp, tt, true, static_cast<const SynArgs*>(g->desc), (int)n, fs, g->st);
             });
             if (ms < best_ms) {
                 best_ms = ms;

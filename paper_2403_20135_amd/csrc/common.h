@@ -135,18 +135,6 @@ __device__ inline void cml_put(double* cml, bool cml32, size_t i, double v) {
     else
         cml[i] = v;
 }
-// Elements i .. i + 3 (i a multiple of 4: 16- or 32-byte aligned) in vector stores.
-__device__ inline void cml_put4(double* cml, bool cml32, size_t i, double v0, double v1, double v2,
-                                double v3) {
-    if (cml32) {
-        *reinterpret_cast<float4*>(reinterpret_cast<float*>(cml) + i) =
-            make_float4((float)v0, (float)v1, (float)v2, (float)v3);
-    } else {
-        double2* p = reinterpret_cast<double2*>(cml + i);
-        p[0] = make_double2(v0, v1);
-        p[1] = make_double2(v2, v3);
-    }
-}
 // Fourier fields produced by the synthesis for the grid kernel: zeta, Phi', U, V, layout
 // four[s][field][lat][m].
 constexpr int kSynFields = 4;
@@ -272,8 +260,6 @@ struct UpdateArgs {
     long long E_node, E_member;
     double* uout;              // [B][M][3][ncoef][2], or the state itself when last_only
     long long out_node, out_member;
-    double* cml;               // if not null: the updated nodes also in synthesis layout (S = B*M)
-    int cml32;                 // synthesis layout stored in FP32 (FP32 mode)
     const int* m_of;           // order m of every coefficient
     const int* rowoff;         // table row offset of (m, parity)
     const double* inv_lap;     // -a^2/(n(n+1)), 0 at n = 0
@@ -345,8 +331,6 @@ struct LcArgs {
     long long E_node, E_member;
     double* uout;                // output states (mode 0: nodes, or the state when last_only)
     long long out_node, out_member;
-    double* cml;                 // synthesis layout of the new nodes (or nullptr)
-    int cml32;
     const double* beta;          // mode 1: [B][3][ncoef] (u may alias it)
     double alpha;                // mode 1
     double* beta_ws;             // mode 0: right-hand sides [output state][3][ncoef] (workspace)

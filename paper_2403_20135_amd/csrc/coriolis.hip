@@ -218,8 +218,6 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
     // back substitution and output
     double* __restrict__ out =
         a.uout + (size_t)b * a.out_member + (size_t)(a.mode == 0 && !a.last_only ? i : 0) * a.out_node;
-    const size_t S = (size_t)a.batch * a.M;
-    const size_t cs = (size_t)b * a.M + i;                // synthesis-layout state of this node
     bool bad = false;
     double2 x = make_double2(0.0, 0.0);
     struct Back {
@@ -230,32 +228,17 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
         return Back{sc[3 * idx], sc[3 * idx + 1], sc[3 * idx + 2]};
     };
     auto substitute = [&](const Back& bb, int j) {
-        const int k = m + j, idx = idx0 + j;
+        const int idx = idx0 + j;
         x = csub(bb.dp, cmul(bb.cp, x));
         const bool zeta_pos = ((j & 1) == c);
-        const int par = j & 1, kk = j >> 1;
-        const double il = a.cml ? a.inv_lap[k] : 0.0;      // only the synthesis layout needs it
-        const size_t ci = a.cml ? (((size_t)a.rowoff[2 * m + par] + kk) * S + cs) * kCmlVals : 0;
         const double2 xv = x;
         if (zeta_pos) {
             *(double2*)(out + fs + 2 * (size_t)idx) = xv;
-            if (a.cml) {
-                cml_put(a.cml, a.cml32, ci, xv.x);
-                cml_put(a.cml, a.cml32, ci + 1, xv.y);
-                cml_put(a.cml, a.cml32, ci + 4, il * xv.x);
-                cml_put(a.cml, a.cml32, ci + 5, il * xv.y);
-            }
             bad = bad || !(isfinite(xv.x) && isfinite(xv.y));
         } else {
             const double2 phi = csub(bb.bphi, rmul(alpha * a.phibar, xv));
             *(double2*)(out + 2 * fs + 2 * (size_t)idx) = xv;
             *(double2*)(out + 2 * (size_t)idx) = phi;
-            if (a.cml) {
-                cml_put(a.cml, a.cml32, ci + 2, phi.x);
-                cml_put(a.cml, a.cml32, ci + 3, phi.y);
-                cml_put(a.cml, a.cml32, ci + 6, il * xv.x);
-                cml_put(a.cml, a.cml32, ci + 7, il * xv.y);
-            }
             bad = bad || !(isfinite(xv.x) && isfinite(xv.y) && isfinite(phi.x) && isfinite(phi.y));
         }
     };
@@ -273,11 +256,6 @@ __global__ __launch_bounds__(64) void k_solve_lc(LcArgs a) {
 #pragma unroll
         for (int u = 0; u < kQ; ++u)
             if (j0 - kQ - u >= 0) substitute(b1[u], j0 - kQ - u);
-    }
-    // padding rows of the synthesis layout: chain c clears those of parity c
-    if (a.cml) {
-        const int np = npk_of(T, m, c);
-        if (np > 0) cml_clear_pad(a.cml, a.cml32, a.rowoff[2 * m + c], np - 1, np, S, cs);
     }
     if (a.last_only && bad) a.flag[0] = 1;
 }
@@ -433,8 +411,6 @@ __device__ void solve_chain_wave(const LcArgs& a, int m, int c, int i, int b, do
     // 3. values and outputs
     double* __restrict__ out =
         a.uout + (size_t)b * a.out_member + (size_t)(a.mode == 0 && !a.last_only ? i : 0) * a.out_node;
-    const size_t S = (size_t)a.batch * a.M;
-    const size_t cs = (size_t)b * a.M + i;                // synthesis-layout state of this node
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < L; ++q) {
@@ -446,37 +422,16 @@ __device__ void solve_chain_wave(const LcArgs& a, int m, int c, int i, int b, do
         } else {
             xv = X;
         }
-        const int k = m + j, idx = idx0 + j;
-        const bool zeta_pos = ((j & 1) == c);
-        const int par = j & 1, kk = j >> 1;
-        const double il = a.cml ? a.inv_lap[k] : 0.0;
-        const size_t ci = a.cml ? (((size_t)a.rowoff[2 * m + par] + kk) * S + cs) * kCmlVals : 0;
-        if (zeta_pos) {
+        const int idx = idx0 + j;
+        if ((j & 1) == c) {
             *(double2*)(out + fs + 2 * (size_t)idx) = xv;
-            if (a.cml) {
-                cml_put(a.cml, a.cml32, ci, xv.x);
-                cml_put(a.cml, a.cml32, ci + 1, xv.y);
-                cml_put(a.cml, a.cml32, ci + 4, il * xv.x);
-                cml_put(a.cml, a.cml32, ci + 5, il * xv.y);
-            }
             bad = bad || !(isfinite(xv.x) && isfinite(xv.y));
         } else {
             const double2 phi = csub(e[q].bphi, rmul(alpha * a.phibar, xv));
             *(double2*)(out + 2 * fs + 2 * (size_t)idx) = xv;
             *(double2*)(out + 2 * (size_t)idx) = phi;
-            if (a.cml) {
-                cml_put(a.cml, a.cml32, ci + 2, phi.x);
-                cml_put(a.cml, a.cml32, ci + 3, phi.y);
-                cml_put(a.cml, a.cml32, ci + 6, il * xv.x);
-                cml_put(a.cml, a.cml32, ci + 7, il * xv.y);
-            }
             bad = bad || !(isfinite(xv.x) && isfinite(xv.y) && isfinite(phi.x) && isfinite(phi.y));
         }
-    }
-    // padding rows of the synthesis layout: chain c clears those of parity c
-    if (a.cml && lane == 0) {
-        const int np = npk_of(T, m, c);
-        if (np > 0) cml_clear_pad(a.cml, a.cml32, a.rowoff[2 * m + c], np - 1, np, S, cs);
     }
     if (a.last_only && bad) a.flag[0] = 1;
 }

@@ -54,23 +54,6 @@ __device__ __forceinline__ void node_update_part(const UpdateArgs& a, int idx, i
         out[0] = phi;
         out[fs] = bzeta;
         out[2 * fs] = dv;
-        if (a.cml) {
-            // synthesis layout of node state b*M + m: (zeta, Phi', psi, chi) x (Re, Im).  The Re
-            // and Im threads of a coefficient are adjacent lanes (both active): they swap halves so
-            // that each writes four consecutive values, lane c = 0 (zeta, Phi') x (Re, Im) and
-            // lane c = 1 (psi, chi) x (Re, Im).
-            const int mo = a.m_of[idx], par = (n - mo) & 1, kk = (n - mo) >> 1;
-            const double il = a.inv_lap[n];
-            const size_t S = (size_t)a.batch * M;
-            const size_t c0 = (((size_t)a.rowoff[2 * mo + par] + kk) * S + (size_t)b * M + m) * kCmlVals;
-            const double ps = il * bzeta, ch = il * dv;
-            const double ra = __shfl_xor(c ? bzeta : ps, 1, 64);
-            const double rb = __shfl_xor(c ? phi : ch, 1, 64);
-            cml_put4(a.cml, a.cml32, c0 + 4 * c, c ? ra : bzeta, c ? ps : ra, c ? rb : phi, c ? ch : rb);
-            if (c == 0)
-                cml_clear_pad(a.cml, a.cml32, a.rowoff[2 * mo + par], kk, npk_of(a.T, mo, par), S,
-                              (size_t)b * M + m);
-        }
         if (a.last_only) bad = !(isfinite(phi) && isfinite(bzeta) && isfinite(dv));
     }
     if (bad) a.flag[0] = 1;

@@ -88,9 +88,9 @@ def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=Fal
     Legendre: one scalar-equivalent complex transform with equatorial symmetry costs
     2*ncoef*nlat flops; synthesis does 6 per state (zeta, Phi', psi and chi with Pbar, psi and chi
     with H), analysis 7 (div/curl pairs of (A,B), (C,D), and KE).  Bytes per launch: both tables
-    (Pbar, H: ncoef x nlat/2 entries each) once; per state the synthesis reads the state
-    (3 complex per coefficient, at the column precision: the FP32 mode rounds the columns to
-    FP32) and writes 4 Fourier fields (nlat x (T+1) complex FP64); the analysis reads 5 Fourier
+    (Pbar, H: ncoef x nlat/2 entries each) once; per state the synthesis reads the state in place
+    (3 complex FP64 per coefficient; the FP32 mode rounds them to FP32 in registers) and writes 4
+    Fourier fields (nlat x (T+1) complex FP64); the analysis reads 5 Fourier
     fields (A..E, nlat x (T+1) complex at the column precision) and writes 3 complex per
     coefficient.  Grid: reads 4 Fourier fields (FP64), writes 5 (column precision).
     Update (separate kernel): per coefficient and member, each full sweep reads u_n (3 complex)
@@ -117,7 +117,7 @@ def algorithmic_work(T, nlat, M, K, batch, precision, fused=False, syn_recur=Fal
     four = nlat * (T + 1)                        # Fourier coefficients of one field
     syn_tab = (rec_data if syn_recur1 else tables) + (K - 1) * (rec_data if syn_recur else tables)
     ana_tab = (tables / 4 if ana_recur1 else tables) + (K - 1) * (tables / 4 if ana_recur else tables)
-    syn_bytes = syn_tab + states * (3 * col * ncoef + 4 * 16.0 * four)
+    syn_bytes = syn_tab + states * (3 * 16.0 * ncoef + 4 * 16.0 * four)
     ana_bytes = ana_tab + states * (5 * col * four + 3 * 16.0 * ncoef)
     grid_bytes = (4 * 16.0 + 5 * col) * four * states
     upd_bytes = batch * ncoef * 16.0 * ((K - 1) * (3 + 8 * M) + (6 + 5 * M))

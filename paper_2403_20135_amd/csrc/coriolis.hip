@@ -80,42 +80,61 @@ __device__ __forceinline__ FI f_implicit_at(const double* __restrict__ u, size_t
 }  // namespace
 
 // Right-hand sides of the node update (Section 4.2, with f_I = L_g + L_c) for every coefficient,
-// output node and member, fully parallel: beta_i = u_n + dt sum_j Q[i][j] (f_I(u_j) + E_j) -
-// alpha_i f_I(u_i), written to the workspace the chain solve reads ([output state][3][ncoef]).
+// output node and member: beta_i = u_n + dt sum_j Q[i][j] (f_I(u_j) + E_j) - alpha_i f_I(u_i),
+// written to the workspace the chain solve reads ([output state][3][ncoef]).  One thread per
+// (coefficient, member) forms f_I(u_j) and reads E_j once for all its output nodes (M is a template
+// parameter so that the per-node sums stay in registers); each beta_i is summed over j in order.
+template <int M>
 __global__ __launch_bounds__(kBlock) void k_lc_rhs(LcArgs a) {
-    const int nodes = a.last_only ? 1 : a.M;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;                       // output node (fastest) and member
+    const int b = blockIdx.y;                       // member
     if (idx >= a.ncoef) return;
-    const int i = a.last_only ? a.M - 1 : r % nodes;
-    const int b = r / nodes;
+    const int i0 = a.last_only ? M - 1 : 0;         // output nodes i0 .. M-1
     const int T = a.T;
     const size_t fs = (size_t)a.ncoef * 2;
     const int k = a.n_of[idx], m = a.m_of[idx];
     const double cn = k * (k + 1.0) * a.inv_a2;
     const double2 e = a.lc[idx];
-    const int sdiv = a.sweep < a.M ? a.sweep : a.M;
-    const double alpha = a.dt * a.tau[i] / sdiv;
-    const double* Qi = a.Q + i * kMaxNodes;
+    const int sdiv = a.sweep < M ? a.sweep : M;
     const double* un = a.un + (size_t)b * 3 * fs;
-    double2 bphi = ld(un + 2 * (size_t)idx), bzeta = ld(un + fs + 2 * (size_t)idx),
-            bdiv = ld(un + 2 * fs + 2 * (size_t)idx);
-    FI own{};
-    for (int j = 0; j < a.M; ++j) {
+    const double2 u0p = ld(un + 2 * (size_t)idx), u0z = ld(un + fs + 2 * (size_t)idx),
+                  u0d = ld(un + 2 * fs + 2 * (size_t)idx);
+    double2 bphi[M], bzeta[M], bdiv[M];
+    FI own[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        bphi[i] = u0p;
+        bzeta[i] = u0z;
+        bdiv[i] = u0d;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
         const double* uj = a.uprev + (size_t)b * a.uprev_member + (size_t)j * a.uprev_node;
         const double* ej = a.E + (size_t)b * a.E_member + (size_t)j * a.E_node;
         const FI fi = f_implicit_at(uj, fs, idx, k, m, T, e, a.two_omega, a.phibar, cn);
-        if (j == i) own = fi;
-        const double q = a.dt * Qi[j];
-        bphi = cadd(bphi, rmul(q, cadd(fi.phi, ld(ej + 2 * (size_t)idx))));
-        bzeta = cadd(bzeta, rmul(q, cadd(fi.zeta, ld(ej + fs + 2 * (size_t)idx))));
-        bdiv = cadd(bdiv, rmul(q, cadd(fi.div, ld(ej + 2 * fs + 2 * (size_t)idx))));
+        const double2 sp = cadd(fi.phi, ld(ej + 2 * (size_t)idx));
+        const double2 sz = cadd(fi.zeta, ld(ej + fs + 2 * (size_t)idx));
+        const double2 sd = cadd(fi.div, ld(ej + 2 * fs + 2 * (size_t)idx));
+        own[j] = fi;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            if (i < i0) continue;
+            const double q = a.dt * a.Q[i * kMaxNodes + j];
+            bphi[i] = cadd(bphi[i], rmul(q, sp));
+            bzeta[i] = cadd(bzeta[i], rmul(q, sz));
+            bdiv[i] = cadd(bdiv[i], rmul(q, sd));
+        }
     }
-    const int ostate = a.last_only ? b : b * a.M + i;
-    double* out = a.beta_ws + (size_t)ostate * 3 * fs + 2 * (size_t)idx;
-    *(double2*)out = csub(bphi, rmul(alpha, own.phi));
-    *(double2*)(out + fs) = csub(bzeta, rmul(alpha, own.zeta));
-    *(double2*)(out + 2 * fs) = csub(bdiv, rmul(alpha, own.div));
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        if (i < i0) continue;
+        const double alpha = a.dt * a.tau[i] / sdiv;
+        const int ostate = a.last_only ? b : b * M + i;
+        double* out = a.beta_ws + (size_t)ostate * 3 * fs + 2 * (size_t)idx;
+        *(double2*)out = csub(bphi[i], rmul(alpha, own[i].phi));
+        *(double2*)(out + fs) = csub(bzeta[i], rmul(alpha, own[i].zeta));
+        *(double2*)(out + 2 * fs) = csub(bdiv[i], rmul(alpha, own[i].div));
+    }
 }
 
 // The chain solve of u - alpha f_I(u) = beta for one chain of one order of one output state:
@@ -466,8 +485,17 @@ __global__ __launch_bounds__(64 * kLcWaves) void k_solve_lc_wave(LcArgs a) {
 void launch_solve_lc(const LcArgs& a, hipStream_t st) {
     const int nodes = a.mode == 0 ? (a.last_only ? 1 : a.M) : 1;
     if (a.mode == 0) {
-        dim3 grid((a.ncoef + kBlock - 1) / kBlock, nodes * a.batch);
-        k_lc_rhs<<<grid, kBlock, 0, st>>>(a);
+        dim3 grid((a.ncoef + kBlock - 1) / kBlock, a.batch);
+        switch (a.M) {
+        case 1: k_lc_rhs<1><<<grid, kBlock, 0, st>>>(a); break;
+        case 2: k_lc_rhs<2><<<grid, kBlock, 0, st>>>(a); break;
+        case 3: k_lc_rhs<3><<<grid, kBlock, 0, st>>>(a); break;
+        case 4: k_lc_rhs<4><<<grid, kBlock, 0, st>>>(a); break;
+        case 5: k_lc_rhs<5><<<grid, kBlock, 0, st>>>(a); break;
+        case 6: k_lc_rhs<6><<<grid, kBlock, 0, st>>>(a); break;
+        case 7: k_lc_rhs<7><<<grid, kBlock, 0, st>>>(a); break;
+        default: k_lc_rhs<8><<<grid, kBlock, 0, st>>>(a); break;
+        }
     }
     const int n = (a.T + 1) * 2 * nodes * a.batch;
     const int wgs = (n + kLcWaves - 1) / kLcWaves;

@@ -196,3 +196,38 @@ def test_merged_group_with_separate_updates():
     with pytest.raises(_lib.SDCError) as e:
         g2.step([_dev(_states(21, 1, 70)), _dev(_states(31, 1, 71))], [900.0, 600.0], 3, 3)
     assert e.value.code == _lib.SDC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_merged_group_of_single_members_with_fused_updates(precision):
+    """M = 4 (the node update fused into the analysis, every synthesis reading its states in
+    place) with members of one and two states (the one- and two-state launches form both Pbar
+    tiles in one product): mode 1 bitwise mode 0, after the group autotuner, and FP64 against the
+    oracle (1e-11)."""
+    from paper_2403_20135_amd.api import SDCGroup
+    configs = [(31, 48, 96, 4, 3, 1), (63, 96, 192, 4, 3, 2)]
+    dts = [600.0, 480.0]
+    handles = [_sdc(T, nlat, nlon, M, K, b, precision=precision) for (T, nlat, nlon, M, K, b) in configs]
+    grp = SDCGroup(handles)
+    u0 = [_states(c[0], c[5], 80 + k) for k, c in enumerate(configs)]
+    grp.autotune([_dev(u) for u in u0], dts, 4, 3)
+    res = {}
+    for mode in (1, 0):
+        grp.set_mode(mode)
+        xs = [_dev(u) for u in u0]
+        for _ in range(2):
+            grp.step(xs, dts, 4, 3)
+        grp.sync()
+        res[mode] = [_host(x) for x in xs]
+    for k in range(len(configs)):
+        assert np.array_equal(res[1][k], res[0][k]), k
+    if precision == "fp64":
+        for k, (T, nlat, nlon, M, K, b) in enumerate(configs):
+            o = _oracle(T, nlat, nlon)
+            ref = np.stack([o.step(u0[k][i], dts[k], M, K, steps=2) for i in range(b)])
+            err = rel_l2(res[1][k], ref, T)
+            print(f"[gpu] group member T{T} x{b}: rel L2 vs oracle {err:.3e}", flush=True)
+            assert err <= 1e-11
+    grp.close()
+    for h in handles:
+        h.close()

@@ -100,3 +100,32 @@ def test_maximum_truncation_properties():
     assert e_rh <= 1e-11
     assert e_phi <= 1e-30                     # no Phi': its fluxes vanish exactly
     sdc.close()
+
+
+def test_grid_kernel_high_order_lines():
+    """With T + 1 > nlon / 3 the grid kernel writes the analysis lines of the higher orders in two
+    parts (A..D before E is transformed).  A field band-limited to degree 460 on 900 latitudes has
+    alias-free products at nlon = 1536 and 2048, so f_E at T = 600 (orders >= 512 written in parts
+    at nlon = 1536, whole at 2048) agrees to rounding: <= 1e-10 relative L2 (2e-12 measured; the
+    divergence tendency's cancellation between the vorticity-flux curl and the kinetic-energy
+    Laplacian sets the rounding level, as in the smaller grids), the small values of orders above
+    511 on their own <= 1e-8 (1e-10 measured); a misplaced line value would be O(1)."""
+    T, nlat, L = 600, 900, 460
+    a = _sdc(T, nlat, 1536, 2, 2, 1)
+    b = _sdc(T, nlat, 2048, 2, 2, 1)
+    x = W.random_state(T, 991)[None].copy()
+    n, m = W.degree_order_arrays(T)
+    x[:, :, n > L] = 0.0
+    fa, fb = _dev(np.zeros_like(x)), _dev(np.zeros_like(x))
+    a.eval_explicit(_dev(x), fa)
+    b.eval_explicit(_dev(x), fb)
+    ha, hb = _host(fa), _host(fb)
+    err = rel_l2(ha, hb, T)
+    hi = m >= 512
+    err_hi = float(np.linalg.norm(ha[..., hi, :] - hb[..., hi, :]) / np.linalg.norm(hb[..., hi, :]))
+    print(f"[gpu] T600 f_E nlon 1536 vs 2048: rel L2 {err:.3e}, orders >= 512 {err_hi:.3e}", flush=True)
+    assert np.linalg.norm(hb[..., hi, :]) > 0
+    assert err <= 1e-10
+    assert err_hi <= 1e-8
+    a.close()
+    b.close()
